@@ -1,0 +1,134 @@
+/*
+ * jiffy.h -- C ABI of the MI355X (gfx950) Jiffy LiDAR scan codec.
+ *
+ * The codec is the one of Ford & Ford, "Lossless SIMD Compression of LiDAR
+ * Range and Attribute Scan Sequences" (arXiv 2209.08196): each scan of each
+ * attribute is quantized to a precision (Sec. III-B), its zero samples are
+ * recorded in a bitmask that is compressed on its own (Sec. III-C), a trial
+ * compression of a few scanlines picks intra-scan (I) or predicted-scan (P)
+ * coding (Sec. III-E), and the remaining samples -- minus the previous scan
+ * for a P-scan (Sec. III-D) -- are delta coded along the flattened scan,
+ * ZigZag mapped (Eq. 1) and packed with a patched frame of reference in
+ * frames of 128 values (Sec. II, III-C).  Every step runs in HIP kernels on
+ * the device; the output is a byte stream identical to that of the project's
+ * CPU reference.
+ *
+ * Memory: every d_* pointer is device memory owned by the caller; h_*
+ * pointers are host memory owned by the caller.  The library owns its
+ * workspace (grown on demand per device, kept until process exit) and the
+ * resident state of each jiffy_stream.  Calls enqueue work on `stream` and
+ * synchronize with it once before they return (the byte count, the chosen
+ * modes and the status are host values).  Calls on one device are
+ * serialized by a per-device lock.
+ *
+ * Errors: every entry point returns a jiffy_status and never aborts.
+ */
+#ifndef JIFFY_H
+#define JIFFY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* the HIP runtime's stream handle (identical to its own declaration) */
+typedef struct ihipStream_t* hipStream_t;
+
+#define JIFFY_MAX_ATTRS 8
+
+/* Scan shape and attributes (Sec. III-A: canonical 2-D scans of 1, 2 or 4
+ * byte unsigned samples, zero meaning "no return").  height = scanlines
+ * (rows), width = samples per scanline; samples are row-major.
+ * precision[a] is the quantization step P >= 1 in input units (Sec. III-B);
+ * P = 1 keeps the samples as they are.  It is stored in the stream. */
+typedef struct {
+    uint32_t height, width, n_attrs;        /* n_attrs in 1..8 */
+    uint8_t width_bytes[JIFFY_MAX_ATTRS];   /* 1, 2 or 4 per attribute */
+    uint32_t precision[JIFFY_MAX_ATTRS];    /* P >= 1 */
+} jiffy_layout;
+
+/* Sec. III-E: I-only, P-only, or the per-scan automatic choice. */
+typedef enum { JIFFY_MODE_AUTO = 0, JIFFY_MODE_I_ONLY = 1, JIFFY_MODE_P_ONLY = 2 } jiffy_mode;
+
+typedef struct {
+    uint32_t mode;        /* a jiffy_mode */
+    uint32_t trial_rows;  /* scanlines in the trial compression; 0 = 4 (Sec. IV-E) */
+} jiffy_options;
+
+typedef enum {
+    JIFFY_OK = 0,
+    JIFFY_E_INVALID = -1,   /* bad layout, options, pointer or alignment */
+    JIFFY_E_CAPACITY = -2,  /* output buffer too small; the size needed is returned */
+    JIFFY_E_CORRUPT = -3,   /* malformed stream */
+    JIFFY_E_DEVICE = -4,    /* a HIP runtime error */
+    JIFFY_E_SHAPE = -5      /* planes do not match the stream's layout */
+} jiffy_status;
+
+/* Worst-case size in bytes of the stream jiffy_encode writes for n_scans
+ * scans of this layout; 0 for an invalid layout. */
+size_t jiffy_encode_bound(const jiffy_layout* layout, uint32_t n_scans);
+
+/* Encodes n_scans scans (the whole method of Sec. III).
+ *   d_planes[a]: device pointer to n_scans*height*width samples of attribute a
+ *                ([n_scans][height][width], row-major, width_bytes[a] each,
+ *                aligned to the sample size).
+ *   d_out:       device buffer of out_capacity bytes, 4-byte aligned.
+ *   h_out_len:   host; receives the stream length (on JIFFY_E_CAPACITY the
+ *                length that would be needed; nothing is written then).
+ *   h_modes:     optional host [n_scans][n_attrs]; receives 0 (I) or 1 (P).
+ * Scan 0 is always an I-scan.  Returns a jiffy_status. */
+int jiffy_encode(const jiffy_layout* layout, const jiffy_options* options, uint32_t n_scans,
+                 const void* const* d_planes, void* d_out, size_t out_capacity, size_t* h_out_len,
+                 uint8_t* h_modes, hipStream_t stream);
+
+/* Parses a stream header in host memory.  With a record-length table
+ * (n_scans > 0 in the header) in_len must be the whole stream; a header
+ * without one (records until the end) is walked record by record.
+ * Returns JIFFY_OK or JIFFY_E_CORRUPT. */
+int jiffy_peek(const void* h_in, size_t in_len, jiffy_layout* layout, uint32_t* n_scans);
+
+/* Decodes a whole stream (every step of Sec. III reversed).
+ *   d_in:          device pointer to the stream (in_len bytes, 4-byte aligned).
+ *   d_planes_out:  n_attrs device pointers, each [n_scans][height][width] of
+ *                  the attribute's width, receiving min(q * P, 2^w - 1).
+ * Returns JIFFY_OK or JIFFY_E_CORRUPT (outputs then undefined), or another
+ * jiffy_status. */
+int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hipStream_t stream);
+
+/* A short English description of a status code (static storage). */
+const char* jiffy_status_string(int status);
+
+/* ---- stateful streams (many sensors, one scan per step) ---------------
+ * A jiffy_stream keeps the previous quantized scan and its zero mask
+ * resident in device memory, so that a P-scan (Sec. III-D) can predict from
+ * it.  Its first scan, and the first after jiffy_stream_reset, is an
+ * I-scan. */
+typedef struct jiffy_stream jiffy_stream;
+
+int jiffy_stream_create(const jiffy_layout* layout, const jiffy_options* options, jiffy_stream** out);
+
+/* Encodes one scan of each of n streams in one batch.
+ *   d_planes[i][a]: device pointer to the height*width samples of attribute
+ *                   a of stream i's new scan.
+ *   d_out[i]:       device buffer of caps[i] bytes (4-byte aligned) that
+ *                   receives stream i's n_attrs records (no stream header).
+ *   h_lens[i]:      host; bytes written (or needed, on JIFFY_E_CAPACITY).
+ *   h_modes:        optional host [n][n_attrs] (0 = I, 1 = P).
+ * The records equal those jiffy_encode writes for the same scan sequence.
+ * On any error no stream's state advances.  The same stream may appear at
+ * most once per call. */
+int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
+                            void* const* d_out, const size_t* caps, size_t* h_lens, uint8_t* h_modes,
+                            hipStream_t stream);
+
+/* Drops the resident previous scan; the next scan is an I-scan. */
+int jiffy_stream_reset(jiffy_stream* s);
+
+void jiffy_stream_destroy(jiffy_stream* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JIFFY_H */

@@ -1,0 +1,656 @@
+// C ABI of the Jiffy codec (include/jiffy.h): argument checks, workspace
+// layout, kernel planning, stream headers, resident stream state.
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/jiffy.h"
+#include "jiffy_internal.h"
+
+using namespace jiffy;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t al(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+struct HostBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+hipError_t grow(DevBuf& b, size_t need) {
+    if (need <= b.cap) return hipSuccess;
+    size_t cap = need + need / 4;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, cap);
+    if (e == hipSuccess) b.cap = cap;
+    return e;
+}
+hipError_t grow(HostBuf& b, size_t need) {
+    if (need <= b.cap) return hipSuccess;
+    size_t cap = need + need / 4;
+    if (b.p) {
+        hipError_t e = hipHostFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    hipError_t e = hipHostMalloc(&b.p, cap, hipHostMallocDefault);
+    if (e == hipSuccess) b.cap = cap;
+    return e;
+}
+
+// Per-device workspace.  Calls on one device are serialized by `mu` and
+// synchronize their stream before returning, so the buffers are free again.
+struct DevCtx {
+    std::mutex mu;
+    DevBuf ws;
+    HostBuf up, down;
+};
+DevCtx g_ctx[64];
+
+int current_device(int* dev) {
+    if (hipGetDevice(dev) != hipSuccess || *dev < 0 || *dev >= 64) return JIFFY_E_DEVICE;
+    return JIFFY_OK;
+}
+
+bool layout_ok(const jiffy_layout* L) {
+    if (!L || L->n_attrs < 1 || L->n_attrs > JIFFY_MAX_ATTRS || L->height == 0 || L->width == 0) return false;
+    if ((uint64_t)L->height * L->width >= (1ull << 31)) return false;
+    for (uint32_t a = 0; a < L->n_attrs; ++a) {
+        const uint32_t wb = L->width_bytes[a];
+        if (wb != 1 && wb != 2 && wb != 4) return false;
+        if (L->precision[a] == 0) return false;
+    }
+    return true;
+}
+
+uint32_t header_len(uint32_t A, uint32_t T) { return 20 + 8 * A + 4 * T * A; }
+
+// ---------------------------------------------------------------------------
+// encode planning
+// ---------------------------------------------------------------------------
+struct EncSpec {
+    const void* x;
+    const void* xprev;
+    void* qout;
+    uint64_t* vw_fixed;          // resident valid words (stream state) or null
+    const uint64_t* vwprev_fixed;
+    int prev_item;               // item whose valid words are the previous ones, or -1
+    uint32_t H, W, wb, P, attr, out_id;
+    uint32_t has_prev, prev_quantized, mode_req, trial_rows;
+};
+
+struct OutSpec {
+    uint8_t* base;
+    uint64_t cap;
+    uint32_t first_item, n_items, hdr_len, n_scans;
+    const jiffy_layout* layout;
+};
+
+struct EncResult {
+    std::vector<uint64_t> lens;
+    std::vector<uint8_t> ok;
+    std::vector<uint8_t> modes;
+};
+
+int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs, hipStream_t stream,
+               EncResult& result) {
+    const uint32_t n = (uint32_t)specs.size(), no = (uint32_t)outs.size();
+    // layout of the device workspace: [res][err][outs][items][tile_first][tile_item] then per item
+    uint32_t n_tiles = 0, max_groups = 1;
+    std::vector<uint32_t> tile_first(n);
+    for (uint32_t r = 0; r < n; ++r) {
+        tile_first[r] = n_tiles;
+        const uint32_t npx = specs[r].H * specs[r].W;
+        n_tiles += div_up(npx, kTilePx);
+        const uint32_t groups = div_up(div_up(npx, kFrame), kGroupFrames);
+        if (groups > max_groups) max_groups = groups;
+    }
+    size_t off = 0;
+    const size_t o_res = off; off = al(off + sizeof(EncRes) * n);
+    const size_t o_err = off; off = al(off + sizeof(uint32_t));
+    const size_t o_outs = off; off = al(off + sizeof(EncOut) * no);
+    const size_t o_items = off; off = al(off + sizeof(EncItem) * n);
+    const size_t o_tfirst = off; off = al(off + sizeof(uint32_t) * n);
+    const size_t o_titem = off; off = al(off + sizeof(uint32_t) * n_tiles);
+    const size_t up_end = off;
+    std::vector<size_t> o_vw(n), o_blk(n), o_slots(n), o_frame(n), o_segs(n);
+    for (uint32_t r = 0; r < n; ++r) {
+        const uint32_t npx = specs[r].H * specs[r].W;
+        const uint32_t nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame), nm = div_up(npx, 8);
+        o_vw[r] = off; off = al(off + (specs[r].vw_fixed ? 0 : 8ull * nwords));
+        o_blk[r] = off; off = al(off + 4ull * maxnb * 6);
+        o_slots[r] = off; off = al(off + (size_t)kSlotBytes * maxnb);
+        o_frame[r] = off; off = al(off + frame_bound(nm));
+        o_segs[r] = off; off = al(off + 8ull * (nm / 4 + 4));
+    }
+    if (grow(ctx.ws, off) != hipSuccess) return JIFFY_E_DEVICE;
+    const size_t up_bytes = up_end - o_err;
+    if (grow(ctx.up, up_bytes) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(ctx.down, o_items) != hipSuccess) return JIFFY_E_DEVICE;
+    uint8_t* dev = (uint8_t*)ctx.ws.p;
+    uint8_t* up = (uint8_t*)ctx.up.p;
+    memset(up, 0, up_bytes);
+    auto U = [&](size_t o) { return up + (o - o_err); };
+
+    EncOut* hout = (EncOut*)U(o_outs);
+    for (uint32_t k = 0; k < no; ++k) {
+        EncOut& o = hout[k];
+        o.base = outs[k].base;
+        o.cap = outs[k].cap;
+        o.first_item = outs[k].first_item;
+        o.n_items = outs[k].n_items;
+        o.hdr_len = outs[k].hdr_len;
+        o.n_scans = outs[k].n_scans;
+        const jiffy_layout* L = outs[k].layout;
+        o.n_attrs = L->n_attrs;
+        o.height = L->height;
+        o.width = L->width;
+        for (uint32_t a = 0; a < L->n_attrs; ++a) {
+            o.attr_wb[a] = L->width_bytes[a];
+            o.attr_p[a] = L->precision[a];
+        }
+    }
+    EncItem* hit = (EncItem*)U(o_items);
+    for (uint32_t r = 0; r < n; ++r) {
+        const EncSpec& s = specs[r];
+        EncItem& it = hit[r];
+        const uint32_t npx = s.H * s.W;
+        it.x = s.x;
+        it.xprev = s.xprev;
+        it.qout = s.qout;
+        it.vw = s.vw_fixed ? s.vw_fixed : (uint64_t*)(dev + o_vw[r]);
+        if (s.vwprev_fixed) it.vwprev = s.vwprev_fixed;
+        else if (s.prev_item >= 0) it.vwprev = specs[s.prev_item].vw_fixed ? specs[s.prev_item].vw_fixed
+                                                                         : (uint64_t*)(dev + o_vw[s.prev_item]);
+        else it.vwprev = nullptr;
+        const uint32_t maxnb = div_up(npx, kFrame), nm = div_up(npx, 8);
+        uint32_t* blk = (uint32_t*)(dev + o_blk[r]);
+        it.blkstart = blk;
+        it.blklast = blk + maxnb;
+        it.blkinfo = blk + 2 * maxnb;
+        it.blkoffs = blk + 3 * maxnb;
+        it.slots = dev + o_slots[r];
+        it.frame = dev + o_frame[r];
+        it.seg_cap = nm / 4 + 4;
+        it.segs = (uint32_t*)(dev + o_segs[r]);
+        it.segoff = it.segs + it.seg_cap;
+        it.div = make_divisor(s.P);
+        it.npx = npx;
+        it.nwords = div_up(npx, 64);
+        it.height = s.H;
+        it.width = s.W;
+        it.wb = s.wb;
+        it.bits = 8 * s.wb;
+        it.attr = s.attr;
+        it.out_id = s.out_id;
+        it.has_prev = s.has_prev;
+        it.prev_quantized = s.prev_quantized;
+        it.mode_req = s.mode_req;
+        it.trial_rows = s.trial_rows;
+        it.maxnb = maxnb;
+        it.frame_cap = frame_bound(nm);
+        bool al16 = ((uintptr_t)s.x % 16 == 0) && (!s.xprev || (uintptr_t)s.xprev % 16 == 0) &&
+                    (!s.qout || (uintptr_t)s.qout % 16 == 0);
+        it.aligned16 = al16 ? 1u : 0u;
+    }
+    uint32_t* htf = (uint32_t*)U(o_tfirst);
+    uint32_t* hti = (uint32_t*)U(o_titem);
+    for (uint32_t r = 0; r < n; ++r) {
+        htf[r] = tile_first[r];
+        const uint32_t nt = div_up(specs[r].H * specs[r].W, kTilePx);
+        for (uint32_t k = 0; k < nt; ++k) hti[tile_first[r] + k] = r;
+    }
+    if (hipMemcpyAsync(dev + o_err, up, up_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return JIFFY_E_DEVICE;
+
+    EncPlan plan;
+    plan.items = (const EncItem*)(dev + o_items);
+    plan.res = (EncRes*)(dev + o_res);
+    plan.outs = (EncOut*)(dev + o_outs);
+    plan.err = (uint32_t*)(dev + o_err);
+    plan.tile_item = (const uint32_t*)(dev + o_titem);
+    plan.tile_first = (const uint32_t*)(dev + o_tfirst);
+    plan.n_items = n;
+    plan.n_outs = no;
+    plan.n_tiles = n_tiles;
+    plan.max_groups = max_groups;
+    if (launch_encode(plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipMemcpyAsync(ctx.down.p, dev, o_items, hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+
+    const uint8_t* down = (const uint8_t*)ctx.down.p;
+    const EncRes* dres = (const EncRes*)(down + o_res);
+    const EncOut* douts = (const EncOut*)(down + o_outs);
+    result.lens.resize(no);
+    result.ok.resize(no);
+    result.modes.resize(n);
+    for (uint32_t k = 0; k < no; ++k) {
+        result.lens[k] = douts[k].len;
+        result.ok[k] = (uint8_t)douts[k].ok;
+    }
+    for (uint32_t r = 0; r < n; ++r) result.modes[r] = (uint8_t)dres[r].mode;
+    return JIFFY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// header parsing (host memory)
+// ---------------------------------------------------------------------------
+uint32_t rd32(const uint8_t* p) { return p[0] | (p[1] << 8) | (p[2] << 16) | ((uint32_t)p[3] << 24); }
+uint16_t rd16(const uint8_t* p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+
+int parse_header(const uint8_t* h, size_t len, jiffy_layout* L, uint32_t* T, size_t* hdr) {
+    if (len < 20 || memcmp(h, "JFY1", 4) != 0 || rd16(h + 4) != 1) return JIFFY_E_CORRUPT;
+    const uint32_t A = rd16(h + 6);
+    if (A < 1 || A > JIFFY_MAX_ATTRS || len < 20 + 8ull * A) return JIFFY_E_CORRUPT;
+    memset(L, 0, sizeof *L);
+    L->n_attrs = A;
+    L->height = rd32(h + 8);
+    L->width = rd32(h + 12);
+    *T = rd32(h + 16);
+    for (uint32_t a = 0; a < A; ++a) {
+        const uint8_t* d = h + 20 + 8 * a;
+        if (d[1] || d[2] || d[3]) return JIFFY_E_CORRUPT;
+        L->width_bytes[a] = d[0];
+        L->precision[a] = rd32(d + 4);
+    }
+    if (!layout_ok(L)) return JIFFY_E_CORRUPT;
+    *hdr = 20 + 8 * A;
+    return JIFFY_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* jiffy_status_string(int s) {
+    switch (s) {
+        case JIFFY_OK: return "ok";
+        case JIFFY_E_INVALID: return "invalid argument";
+        case JIFFY_E_CAPACITY: return "output buffer too small";
+        case JIFFY_E_CORRUPT: return "corrupt stream";
+        case JIFFY_E_DEVICE: return "HIP runtime error";
+        case JIFFY_E_SHAPE: return "planes do not match the stream";
+        default: return "unknown status";
+    }
+}
+
+size_t jiffy_encode_bound(const jiffy_layout* L, uint32_t n_scans) {
+    if (!layout_ok(L)) return 0;
+    const size_t npx = (size_t)L->height * L->width;
+    const size_t nm = (npx + 7) / 8, nb = (npx + 127) / 128;
+    size_t total = header_len(L->n_attrs, n_scans);
+    for (uint32_t a = 0; a < L->n_attrs; ++a) {
+        const size_t bits = 8u * L->width_bytes[a];
+        const size_t rec = 12 + frame_bound((uint32_t)nm) + 3 + 4 + 3 * nb + 3 + nb * 16 * bits + 3;
+        total += rec * n_scans;
+    }
+    return total;
+}
+
+int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, const void* const* d_planes,
+                 void* d_out, size_t cap, size_t* h_out_len, uint8_t* h_modes, hipStream_t stream) {
+    if (!layout_ok(L) || !h_out_len || !d_out || (uintptr_t)d_out % 4) return JIFFY_E_INVALID;
+    const uint32_t mode = opt ? opt->mode : 0;
+    const uint32_t K = (opt && opt->trial_rows) ? opt->trial_rows : 4;
+    if (mode > 2) return JIFFY_E_INVALID;
+    const uint32_t A = L->n_attrs;
+    if ((uint64_t)T * A > (1u << 24)) return JIFFY_E_INVALID;
+    if (T && !d_planes) return JIFFY_E_INVALID;
+    for (uint32_t a = 0; T && a < A; ++a)
+        if (!d_planes[a] || (uintptr_t)d_planes[a] % L->width_bytes[a]) return JIFFY_E_INVALID;
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    const size_t npx = (size_t)L->height * L->width;
+    if (T == 0) {
+        // a header with no records
+        const uint32_t hl = header_len(A, 0);
+        *h_out_len = hl;
+        if (cap < hl) return JIFFY_E_CAPACITY;
+        if (grow(ctx.up, hl) != hipSuccess) return JIFFY_E_DEVICE;
+        uint8_t* h = (uint8_t*)ctx.up.p;
+        memset(h, 0, hl);
+        memcpy(h, "JFY1", 4);
+        h[4] = 1;
+        h[6] = (uint8_t)A;
+        memcpy(h + 8, &L->height, 4);
+        memcpy(h + 12, &L->width, 4);
+        for (uint32_t a = 0; a < A; ++a) {
+            h[20 + 8 * a] = L->width_bytes[a];
+            memcpy(h + 24 + 8 * a, &L->precision[a], 4);
+        }
+        if (hipMemcpyAsync(d_out, h, hl, hipMemcpyHostToDevice, stream) != hipSuccess) return JIFFY_E_DEVICE;
+        if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+        return JIFFY_OK;
+    }
+    std::vector<EncSpec> specs((size_t)T * A);
+    for (uint32_t t = 0; t < T; ++t) {
+        for (uint32_t a = 0; a < A; ++a) {
+            EncSpec& s = specs[(size_t)t * A + a];
+            const size_t step = npx * L->width_bytes[a];
+            s.x = (const uint8_t*)d_planes[a] + t * step;
+            s.xprev = t ? (const uint8_t*)d_planes[a] + (t - 1) * step : nullptr;
+            s.qout = nullptr;
+            s.vw_fixed = nullptr;
+            s.vwprev_fixed = nullptr;
+            s.prev_item = t ? (int)((t - 1) * A + a) : -1;
+            s.H = L->height;
+            s.W = L->width;
+            s.wb = L->width_bytes[a];
+            s.P = L->precision[a];
+            s.attr = a;
+            s.out_id = 0;
+            s.has_prev = t ? 1u : 0u;
+            s.prev_quantized = 0;
+            s.mode_req = mode;
+            s.trial_rows = K;
+        }
+    }
+    std::vector<OutSpec> outs(1);
+    outs[0] = OutSpec{(uint8_t*)d_out, cap, 0, T * A, header_len(A, T), T, L};
+    EncResult res;
+    int rc = run_encode(ctx, specs, outs, stream, res);
+    if (rc) return rc;
+    *h_out_len = res.lens[0];
+    if (!res.ok[0]) return JIFFY_E_CAPACITY;
+    if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
+    return JIFFY_OK;
+}
+
+int jiffy_peek(const void* h_in, size_t len, jiffy_layout* L, uint32_t* n_scans) {
+    if (!h_in || !L) return JIFFY_E_INVALID;
+    const uint8_t* h = (const uint8_t*)h_in;
+    uint32_t T;
+    size_t p;
+    int rc = parse_header(h, len, L, &T, &p);
+    if (rc) return rc;
+    if (T) {
+        const size_t nrec = (size_t)T * L->n_attrs;
+        if (len < p + 4 * nrec) return JIFFY_E_CORRUPT;
+        size_t total = p + 4 * nrec;
+        for (size_t r = 0; r < nrec; ++r) total += rd32(h + p + 4 * r);
+        if (total != len) return JIFFY_E_CORRUPT;
+    } else {
+        size_t q = p, nrec = 0;
+        while (q < len) {
+            if (q + 4 > len) return JIFFY_E_CORRUPT;
+            const uint32_t rl = rd32(h + q);
+            if (rl < 12 || rl % 4 || rl > len - q) return JIFFY_E_CORRUPT;
+            q += rl;
+            nrec++;
+        }
+        if (nrec % L->n_attrs) return JIFFY_E_CORRUPT;
+        T = (uint32_t)(nrec / L->n_attrs);
+    }
+    if (n_scans) *n_scans = T;
+    return JIFFY_OK;
+}
+
+int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hipStream_t stream) {
+    if (!d_in || (uintptr_t)d_in % 4) return JIFFY_E_INVALID;
+    if (in_len < 20) return JIFFY_E_CORRUPT;
+    int devid;
+    if (current_device(&devid)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[devid];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    const uint8_t* din = (const uint8_t*)d_in;
+    // header
+    const size_t h0 = in_len < 20 + 8 * JIFFY_MAX_ATTRS ? in_len : 20 + 8 * JIFFY_MAX_ATTRS;
+    if (grow(ctx.down, 4096) != hipSuccess) return JIFFY_E_DEVICE;
+    uint8_t* hb = (uint8_t*)ctx.down.p;
+    if (hipMemcpyAsync(hb, din, h0, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    jiffy_layout L;
+    uint32_t T_hdr;
+    size_t p;
+    int rc = parse_header(hb, h0, &L, &T_hdr, &p);
+    if (rc) return rc;
+    const uint32_t A = L.n_attrs;
+    // record offsets: from the length table, or by walking the records
+    std::vector<uint64_t> roff;
+    std::vector<uint32_t> rlen;
+    if (T_hdr) {
+        const size_t nrec = (size_t)T_hdr * A;
+        if ((uint64_t)T_hdr * A > (1u << 24) || in_len < p + 4 * nrec) return JIFFY_E_CORRUPT;
+        if (grow(ctx.down, 4 * nrec + 64) != hipSuccess) return JIFFY_E_DEVICE;
+        uint8_t* tb = (uint8_t*)ctx.down.p;
+        if (hipMemcpyAsync(tb, din + p, 4 * nrec, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+        if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+        uint64_t q = p + 4 * nrec;
+        roff.resize(nrec);
+        rlen.resize(nrec);
+        for (size_t r = 0; r < nrec; ++r) {
+            const uint32_t rl = rd32(tb + 4 * r);
+            if (rl < 12 || rl % 4) return JIFFY_E_CORRUPT;
+            roff[r] = q;
+            rlen[r] = rl;
+            q += rl;
+        }
+        if (q != in_len) return JIFFY_E_CORRUPT;
+    } else {
+        uint64_t q = p;
+        uint8_t* tb = (uint8_t*)ctx.down.p;
+        while (q < in_len) {
+            if (q + 4 > in_len) return JIFFY_E_CORRUPT;
+            if (hipMemcpyAsync(tb, din + q, 4, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+            if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+            const uint32_t rl = rd32(tb);
+            if (rl < 12 || rl % 4 || rl > in_len - q) return JIFFY_E_CORRUPT;
+            roff.push_back(q);
+            rlen.push_back(rl);
+            q += rl;
+        }
+        if (roff.size() % A) return JIFFY_E_CORRUPT;
+    }
+    const uint32_t T = (uint32_t)(roff.size() / A);
+    if (T == 0) return JIFFY_OK;
+    if (!d_planes_out) return JIFFY_E_INVALID;
+    for (uint32_t a = 0; a < A; ++a)
+        if (!d_planes_out[a] || (uintptr_t)d_planes_out[a] % L.width_bytes[a]) return JIFFY_E_INVALID;
+
+    const uint32_t n = T * A;
+    const uint32_t npx = L.height * L.width, nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame);
+    size_t off = 0;
+    const size_t o_res = off; off = al(off + sizeof(DecRes) * n);
+    const size_t o_err = off; off = al(off + sizeof(uint32_t));
+    const size_t o_items = off; off = al(off + sizeof(DecItem) * n);
+    const size_t up_end = off;
+    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * nwords) + al(4ull * maxnb * 5) + al(4ull * npx);
+    const size_t o_data = off;
+    off += per_item * n;
+    if (grow(ctx.ws, off) != hipSuccess) return JIFFY_E_DEVICE;
+    const size_t up_bytes = up_end - o_err;
+    if (grow(ctx.up, up_bytes) != hipSuccess) return JIFFY_E_DEVICE;
+    uint8_t* dev = (uint8_t*)ctx.ws.p;
+    uint8_t* up = (uint8_t*)ctx.up.p;
+    memset(up, 0, up_bytes);
+    DecItem* hit = (DecItem*)(up + (o_items - o_err));
+    bool need_temporal = T > 1;
+    for (uint32_t t = 0; t < T; ++t) {
+        for (uint32_t a = 0; a < A; ++a) {
+            const uint32_t r = t * A + a;
+            DecItem& it = hit[r];
+            uint8_t* base = dev + o_data + per_item * r;
+            it.rec = din + roff[r];
+            it.rec_len = rlen[r];
+            const size_t step = (size_t)npx * L.width_bytes[a];
+            it.out = (uint8_t*)d_planes_out[a] + t * step;
+            it.cw = (uint64_t*)base; base += al(8ull * nwords);
+            it.vw = (uint64_t*)base; base += al(8ull * nwords);
+            it.wpre = (uint32_t*)base; base += al(4ull * nwords);
+            it.blkinfo = (uint32_t*)base;
+            it.blkoffs = it.blkinfo + maxnb;
+            it.bsum = it.blkinfo + 4 * maxnb;
+            base += al(4ull * maxnb * 5);
+            it.sbuf = (uint32_t*)base;
+            it.npx = npx;
+            it.nwords = nwords;
+            it.wb = L.width_bytes[a];
+            it.bits = 8 * it.wb;
+            it.attr = a;
+            it.t = t;
+            it.P = L.precision[a];
+            it.maxnb = maxnb;
+            it.aligned16 = ((uintptr_t)it.out % 16 == 0) ? 1u : 0u;
+            if (it.P > 1) need_temporal = true;
+        }
+    }
+    if (hipMemcpyAsync(dev + o_err, up, up_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    DecPlan plan;
+    plan.items = (const DecItem*)(dev + o_items);
+    plan.res = (DecRes*)(dev + o_res);
+    plan.err = (uint32_t*)(dev + o_err);
+    plan.n_items = n;
+    plan.n_scans = T;
+    plan.n_attrs = A;
+    plan.nwords = nwords;
+    plan.npx = npx;
+    plan.max_groups = div_up(maxnb, kGroupFrames);
+    plan.n_tiles = div_up(npx, kTilePx);
+    plan.need_temporal = need_temporal ? 1u : 0u;
+    if (launch_decode(plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipMemcpyAsync(ctx.down.p, dev + o_err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    const uint32_t err = *(const uint32_t*)ctx.down.p;
+    return err ? JIFFY_E_CORRUPT : JIFFY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stateful streams
+// ---------------------------------------------------------------------------
+struct jiffy_stream {
+    jiffy_layout layout;
+    jiffy_options opt;
+    int device;
+    void* q[2][JIFFY_MAX_ATTRS];
+    uint64_t* v[2][JIFFY_MAX_ATTRS];
+    int cur;
+    int has_prev;
+};
+
+int jiffy_stream_create(const jiffy_layout* L, const jiffy_options* opt, jiffy_stream** out) {
+    if (!layout_ok(L) || !out) return JIFFY_E_INVALID;
+    if (opt && opt->mode > 2) return JIFFY_E_INVALID;
+    jiffy_stream* s = new (std::nothrow) jiffy_stream();
+    if (!s) return JIFFY_E_INVALID;
+    s->layout = *L;
+    s->opt.mode = opt ? opt->mode : 0;
+    s->opt.trial_rows = (opt && opt->trial_rows) ? opt->trial_rows : 4;
+    if (current_device(&s->device)) { delete s; return JIFFY_E_DEVICE; }
+    const size_t npx = (size_t)L->height * L->width, nwords = (npx + 63) / 64;
+    for (int k = 0; k < 2; ++k) {
+        for (uint32_t a = 0; a < L->n_attrs; ++a) {
+            if (hipMalloc(&s->q[k][a], npx * L->width_bytes[a] + 16) != hipSuccess ||
+                hipMalloc((void**)&s->v[k][a], 8 * nwords) != hipSuccess) {
+                jiffy_stream_destroy(s);
+                return JIFFY_E_DEVICE;
+            }
+        }
+    }
+    s->cur = 0;
+    s->has_prev = 0;
+    *out = s;
+    return JIFFY_OK;
+}
+
+int jiffy_stream_reset(jiffy_stream* s) {
+    if (!s) return JIFFY_E_INVALID;
+    s->has_prev = 0;
+    return JIFFY_OK;
+}
+
+void jiffy_stream_destroy(jiffy_stream* s) {
+    if (!s) return;
+    for (int k = 0; k < 2; ++k)
+        for (uint32_t a = 0; a < JIFFY_MAX_ATTRS; ++a) {
+            if (s->q[k][a]) (void)hipFree(s->q[k][a]);
+            if (s->v[k][a]) (void)hipFree(s->v[k][a]);
+        }
+    delete s;
+}
+
+int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
+                            void* const* d_out, const size_t* caps, size_t* h_lens, uint8_t* h_modes,
+                            hipStream_t stream) {
+    if (n == 0) return JIFFY_OK;
+    if (!streams || !d_planes || !d_out || !caps || !h_lens) return JIFFY_E_INVALID;
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    for (uint32_t i = 0; i < n; ++i) {
+        const jiffy_stream* s = streams[i];
+        if (!s || !d_planes[i] || !d_out[i] || (uintptr_t)d_out[i] % 4) return JIFFY_E_INVALID;
+        if (s->device != dev) return JIFFY_E_SHAPE;
+        for (uint32_t a = 0; a < s->layout.n_attrs; ++a)
+            if (!d_planes[i][a] || (uintptr_t)d_planes[i][a] % s->layout.width_bytes[a]) return JIFFY_E_INVALID;
+        for (uint32_t k = 0; k < i; ++k)
+            if (streams[k] == s) return JIFFY_E_INVALID;
+    }
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    std::vector<EncSpec> specs;
+    std::vector<OutSpec> outs(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const jiffy_stream* s = streams[i];
+        const jiffy_layout& L = s->layout;
+        outs[i] = OutSpec{(uint8_t*)d_out[i], caps[i], (uint32_t)specs.size(), L.n_attrs, 0, 1, &s->layout};
+        for (uint32_t a = 0; a < L.n_attrs; ++a) {
+            EncSpec e;
+            e.x = d_planes[i][a];
+            e.xprev = s->has_prev ? s->q[s->cur][a] : nullptr;
+            e.qout = s->q[s->cur ^ 1][a];
+            e.vw_fixed = s->v[s->cur ^ 1][a];
+            e.vwprev_fixed = s->has_prev ? s->v[s->cur][a] : nullptr;
+            e.prev_item = -1;
+            e.H = L.height;
+            e.W = L.width;
+            e.wb = L.width_bytes[a];
+            e.P = L.precision[a];
+            e.attr = a;
+            e.out_id = i;
+            e.has_prev = s->has_prev ? 1u : 0u;
+            e.prev_quantized = 1;
+            e.mode_req = s->opt.mode;
+            e.trial_rows = s->opt.trial_rows;
+            specs.push_back(e);
+        }
+    }
+    EncResult res;
+    int rc = run_encode(ctx, specs, outs, stream, res);
+    if (rc) return rc;
+    int status = JIFFY_OK;
+    for (uint32_t i = 0; i < n; ++i) {
+        h_lens[i] = res.lens[i];
+        if (!res.ok[i]) status = JIFFY_E_CAPACITY;
+    }
+    if (h_modes) memcpy(h_modes, res.modes.data(), res.modes.size());
+    if (status == JIFFY_OK) {
+        for (uint32_t i = 0; i < n; ++i) {
+            streams[i]->cur ^= 1;
+            streams[i]->has_prev = 1;
+        }
+    }
+    return status;
+}
+
+}  // extern "C"

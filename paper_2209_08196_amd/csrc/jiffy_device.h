@@ -1,0 +1,220 @@
+// Device helpers for the Jiffy kernels (gfx950, wave64).
+#pragma once
+
+#include "jiffy_internal.h"
+
+namespace jiffy {
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// number of set bits of m below this lane
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, kWave);
+    return v;
+}
+// inclusive prefix sum over the wave (wrapping u32)
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t t = (uint32_t)__shfl_up((int)v, o, kWave);
+        if (l >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint64_t t = __shfl_up(v, o, kWave);
+        if (l >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over a workgroup of NT threads.  `scratch` holds
+// NT/64 + 1 words of LDS.  Returns the exclusive prefix; *total gets the sum.
+// Every thread of the workgroup must call it.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratch, uint32_t* total) {
+    constexpr int NW = NT / kWave;
+    const uint32_t l = lane_id(), w = threadIdx.x / kWave;
+    uint32_t inc = wave_incl_scan(v);
+    if (l == kWave - 1) scratch[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t s = l < (uint32_t)NW ? scratch[l] : 0u;
+        uint32_t si = wave_incl_scan(s);
+        if (l < (uint32_t)NW) scratch[l] = si - s;
+        if (l == NW - 1) scratch[NW] = si;
+    }
+    __syncthreads();
+    uint32_t r = scratch[w] + inc - v;
+    *total = scratch[NW];
+    __syncthreads();
+    return r;
+}
+
+template <int NT>
+__device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v, uint64_t* scratch, uint64_t* total) {
+    constexpr int NW = NT / kWave;
+    const uint32_t l = lane_id(), w = threadIdx.x / kWave;
+    uint64_t inc = wave_incl_scan64(v);
+    if (l == kWave - 1) scratch[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint64_t s = l < (uint32_t)NW ? scratch[l] : 0ull;
+        uint64_t si = wave_incl_scan64(s);
+        if (l < (uint32_t)NW) scratch[l] = si - s;
+        if (l == NW - 1) scratch[NW] = si;
+    }
+    __syncthreads();
+    uint64_t r = scratch[w] + inc - v;
+    *total = scratch[NW];
+    __syncthreads();
+    return r;
+}
+
+// position of the r-th (0-based) set bit of v; v must have more than r bits set
+__device__ __forceinline__ uint32_t select_bit(uint64_t v, uint32_t r) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        uint64_t lowmask = (width == 64) ? ~0ull : ((1ull << width) - 1);
+        uint32_t c = __popcll(v & lowmask);
+        if (r >= c) {
+            r -= c;
+            v >>= width;
+            pos += width;
+        }
+    }
+    return pos;
+}
+
+__device__ __forceinline__ uint32_t low_mask32(uint32_t bits) { return bits >= 32 ? 0xFFFFFFFFu : ((1u << bits) - 1u); }
+
+// Sec. III-B: nearest multiple of P, halves up; zero stays zero, valid stays >= 1.
+__device__ __forceinline__ uint32_t quantize(uint32_t x, const Divisor& d) {
+    if (d.P == 1) return x;
+    uint32_t t = __umulhi(d.magic, x);
+    uint32_t a = (t + ((x - t) >> d.s1)) >> d.s2;  // x / P
+    uint32_t r = x - a * d.P;
+    uint32_t q = a + (r >= d.half_up ? 1u : 0u);
+    return x == 0 ? 0u : max(q, 1u);
+}
+__device__ __forceinline__ uint32_t dequantize(uint32_t q, uint32_t P, uint32_t bits) {
+    uint64_t v = (uint64_t)q * P;
+    uint64_t top = (bits >= 32) ? 0xFFFFFFFFull : ((1ull << bits) - 1);
+    return (uint32_t)(v > top ? top : v);
+}
+
+// Eq. 1 (standard ZigZag) on w-bit two's-complement values.
+__device__ __forceinline__ uint32_t zigzag(uint32_t d, uint32_t bits) {
+    int32_t s = (int32_t)(d << (32 - bits)) >> (32 - bits);
+    return ((uint32_t)s << 1) ^ (uint32_t)(s >> 31);
+}
+__device__ __forceinline__ uint32_t unzigzag(uint32_t z, uint32_t bits) {
+    return ((z >> 1) ^ (0u - (z & 1u))) & low_mask32(bits);
+}
+
+// Frame-width choice for 128 values held two per lane (Sec. II):
+// B = width of the maximum; n(b) = values >= 2^b;
+// cost(b) = 16 b + [n > 0] (n + ceil(n (B - b) / 8)); ties go to the larger b.
+struct FrameChoice {
+    uint32_t b, n, B, cost;
+};
+__device__ __forceinline__ FrameChoice choose_frame(uint32_t z0, uint32_t z1) {
+    uint32_t mx = wave_max(max(z0, z1));
+    uint32_t B = mx ? 32u - __clz(mx) : 0u;
+    FrameChoice best{0, 0, B, 0xFFFFFFFFu};
+    for (uint32_t b = 0; b <= B; ++b) {
+        uint32_t n = 0;
+        if (b < 32) n = __popcll(ballot((z0 >> b) != 0)) + __popcll(ballot((z1 >> b) != 0));
+        uint32_t cost = 16u * b + (n ? n + (n * (B - b) + 7u) / 8u : 0u);
+        if (cost <= best.cost) best = FrameChoice{b, n, B, cost};
+    }
+    return best;
+}
+
+// ---- 16-sample vector access -------------------------------------------
+template <int WB> struct SampleT;
+template <> struct SampleT<1> { using T = uint8_t; };
+template <> struct SampleT<2> { using T = uint16_t; };
+template <> struct SampleT<4> { using T = uint32_t; };
+
+template <int WB>
+__device__ __forceinline__ uint32_t load1(const void* base, uint32_t p) {
+    return ((const typename SampleT<WB>::T*)base)[p];
+}
+
+// v[i] = sample p0 + i (0 beyond npx).  p0 must be a multiple of 16.
+template <int WB>
+__device__ __forceinline__ void load16(const void* base, uint32_t p0, uint32_t npx, bool aligned, uint32_t v[16]) {
+    using T = typename SampleT<WB>::T;
+    const T* b = (const T*)base;
+    if (aligned && p0 + 16 <= npx) {
+        const uint4* q = (const uint4*)(b + p0);
+        uint32_t w[4 * WB];
+#pragma unroll
+        for (int i = 0; i < WB; ++i) {
+            uint4 t = q[i];
+            w[4 * i + 0] = t.x;
+            w[4 * i + 1] = t.y;
+            w[4 * i + 2] = t.z;
+            w[4 * i + 3] = t.w;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (WB == 4) v[i] = w[i];
+            else if (WB == 2) v[i] = (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+            else v[i] = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = (p0 + i < npx) ? (uint32_t)b[p0 + i] : 0u;
+    }
+}
+
+template <int WB>
+__device__ __forceinline__ void store16(void* base, uint32_t p0, uint32_t npx, bool aligned, const uint32_t v[16]) {
+    using T = typename SampleT<WB>::T;
+    T* b = (T*)base;
+    if (aligned && p0 + 16 <= npx) {
+        uint32_t w[4 * WB];
+#pragma unroll
+        for (int i = 0; i < 4 * WB; ++i) w[i] = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (WB == 4) w[i] = v[i];
+            else if (WB == 2) w[i >> 1] |= (v[i] & 0xFFFFu) << (16 * (i & 1));
+            else w[i >> 2] |= (v[i] & 0xFFu) << (8 * (i & 3));
+        }
+        uint4* q = (uint4*)(b + p0);
+#pragma unroll
+        for (int i = 0; i < WB; ++i) q[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (p0 + i < npx) b[p0 + i] = (T)v[i];
+    }
+}
+
+// valid-bit word mask for the last, partial word
+__device__ __forceinline__ uint64_t tail_mask(uint32_t w, uint32_t nwords, uint32_t npx) {
+    uint32_t r = npx & 63u;
+    return (w == nwords - 1 && r) ? ((1ull << r) - 1ull) : ~0ull;
+}
+
+}  // namespace jiffy

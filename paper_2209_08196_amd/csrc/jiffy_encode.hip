@@ -1,0 +1,635 @@
+// Jiffy encoder kernels for gfx950.
+//
+// One call encodes every (scan, attribute) record of a batch at once: the
+// records of a scan sequence are independent once the previous scan is an
+// input, so each kernel runs over all records together.
+//
+//   k_enc_mask     quantize (Sec. III-B), zero bitmask by wave ballot (Sec. III-C)
+//   k_enc_trial    I/P choice by trial compression of a few scanlines (Sec. III-E)
+//   k_enc_scan     running count of in-range samples; frame start/end pixels
+//   k_enc_frames   zero removal, temporal difference (Sec. III-D), delta,
+//                  ZigZag (Eq. 1), frame width choice and bit packing (Sec. II)
+//   k_enc_mframe   mask (XOR previous for a P-scan, Sec. III-D) as a Raw/RLE
+//                  Zstandard frame (Sec. III-C)
+//   k_enc_sizes    per-record section layout (prefix sums of frame sizes)
+//   k_enc_offsets  record offsets in the output (prefix sum over records)
+//   k_enc_assemble copies everything to its place in the stream
+#include "jiffy_device.h"
+
+namespace jiffy {
+
+// ---------------------------------------------------------------------------
+// quantize + zero bitmask.  One workgroup per 4096-pixel tile; each thread
+// reads 16 consecutive samples; 4 lanes form one 64-bit valid word.
+// ---------------------------------------------------------------------------
+template <int WB>
+__device__ __forceinline__ void enc_mask_body(const EncItem& it, uint32_t lt) {
+    const uint32_t p0 = lt * kTilePx + threadIdx.x * 16;
+    uint32_t v[16];
+    load16<WB>(it.x, p0, it.npx, it.aligned16, v);
+    uint32_t bits16 = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        v[i] = quantize(v[i], it.div);
+        bits16 |= (v[i] != 0 ? 1u : 0u) << i;
+    }
+    if (it.qout && p0 < it.npx) store16<WB>(it.qout, p0, it.npx, it.aligned16, v);
+    uint64_t w = (uint64_t)bits16 << (16 * (threadIdx.x & 3));
+    w |= __shfl_xor(w, 1, kWave);
+    w |= __shfl_xor(w, 2, kWave);
+    const uint32_t word = lt * kTileWords + threadIdx.x / 4;
+    if ((threadIdx.x & 3) == 0 && word < it.nwords) it.vw[word] = w;
+}
+
+__global__ __launch_bounds__(256) void k_enc_mask(EncPlan plan) {
+    const uint32_t tile = blockIdx.x;
+    const uint32_t r = plan.tile_item[tile];
+    const EncItem it = plan.items[r];
+    const uint32_t lt = tile - plan.tile_first[r];
+    switch (it.wb) {
+        case 4: enc_mask_body<4>(it, lt); break;
+        case 2: enc_mask_body<2>(it, lt); break;
+        default: enc_mask_body<1>(it, lt); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Trial compression (Sec. III-E): the band-centre rows floor((2j+1)H/(2K)),
+// compacted, coded both ways; P iff its packed size is strictly smaller.
+// The mask is not part of the trial.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t sample_at(const void* base, uint32_t wb, uint32_t p) {
+    if (wb == 4) return ((const uint32_t*)base)[p];
+    if (wb == 2) return ((const uint16_t*)base)[p];
+    return ((const uint8_t*)base)[p];
+}
+
+// packed size of one frame of values s[0..real) with predecessor `pred`;
+// called by one whole wave
+__device__ __forceinline__ uint32_t frame_cost_lds(const uint32_t* s, uint32_t real, uint32_t pred, uint32_t bits) {
+    const uint32_t l = lane_id();
+    const uint32_t m = low_mask32(bits);
+    uint32_t z0 = 0, z1 = 0;
+    if (l < real) z0 = zigzag((s[l] - (l ? s[l - 1] : pred)) & m, bits);
+    if (l + 64 < real) z1 = zigzag((s[l + 64] - s[l + 63]) & m, bits);
+    return choose_frame(z0, z1).cost;
+}
+
+__global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
+    const uint32_t r = blockIdx.x;
+    const EncItem it = plan.items[r];
+    if (!it.has_prev || it.mode_req != 0) {
+        if (threadIdx.x == 0) plan.res[r].mode = (it.has_prev && it.mode_req == 2) ? 1u : 0u;
+        return;
+    }
+    __shared__ uint32_t su[384], sv[384];
+    __shared__ uint32_t scratch[8];
+    __shared__ uint64_t s_cost[2];
+    __shared__ uint32_t s_pred[2];
+    const uint32_t tid = threadIdx.x, wave = tid / kWave;
+    const uint32_t m = low_mask32(it.bits);
+    if (tid == 0) { s_cost[0] = s_cost[1] = 0; s_pred[0] = s_pred[1] = 0; }
+    __syncthreads();
+    uint32_t cnt = 0;
+    const uint32_t K = it.trial_rows, H = it.height, W = it.width;
+    uint32_t prev_row = 0xFFFFFFFFu;
+    for (uint32_t j = 0; j < K; ++j) {
+        const uint32_t row = (uint32_t)(((uint64_t)(2 * j + 1) * H) / (2ull * K));
+        if (row == prev_row) continue;
+        prev_row = row;
+        for (uint32_t c0 = 0; c0 < W; c0 += 256) {
+            const uint32_t c = c0 + tid;
+            uint32_t u = 0, v = 0, valid = 0;
+            if (c < W) {
+                const uint32_t p = row * W + c;
+                const uint32_t q = quantize(sample_at(it.x, it.wb, p), it.div);
+                uint32_t qp = sample_at(it.xprev, it.wb, p);
+                if (!it.prev_quantized) qp = quantize(qp, it.div);
+                valid = q != 0;
+                u = q;
+                v = (q - qp) & m;
+            }
+            uint32_t total;
+            const uint32_t off = block_excl_scan<256>(valid, scratch, &total);
+            if (valid) { su[cnt + off] = u; sv[cnt + off] = v; }
+            __syncthreads();
+            cnt += total;
+            while (cnt >= 128) {
+                if (wave == 0) {
+                    uint32_t ci = frame_cost_lds(su, 128, s_pred[0], it.bits);
+                    uint32_t cp = frame_cost_lds(sv, 128, s_pred[1], it.bits);
+                    if (lane_id() == 0) { s_cost[0] += ci; s_cost[1] += cp; }
+                }
+                __syncthreads();
+                const uint32_t pu = su[127], pv = sv[127];
+                const uint32_t rest = cnt - 128;
+                uint32_t tu = 0, tv = 0;
+                if (tid < rest) { tu = su[128 + tid]; tv = sv[128 + tid]; }
+                __syncthreads();
+                if (tid < rest) { su[tid] = tu; sv[tid] = tv; }
+                if (tid == 0) { s_pred[0] = pu; s_pred[1] = pv; }
+                __syncthreads();
+                cnt = rest;
+            }
+        }
+    }
+    if (cnt > 0 && wave == 0) {
+        uint32_t ci = frame_cost_lds(su, cnt, s_pred[0], it.bits);
+        uint32_t cp = frame_cost_lds(sv, cnt, s_pred[1], it.bits);
+        if (lane_id() == 0) { s_cost[0] += ci; s_cost[1] += cp; }
+    }
+    __syncthreads();
+    if (tid == 0) plan.res[r].mode = s_cost[1] < s_cost[0] ? 1u : 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Running count of in-range samples over the flattened scan (Sec. III-C zero
+// removal): N, and the pixel of each frame's first and last value.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_enc_scan(EncPlan plan) {
+    const uint32_t r = blockIdx.x;
+    const EncItem it = plan.items[r];
+    __shared__ uint32_t scratch[20];
+    uint32_t carry = 0;
+    for (uint32_t w0 = 0; w0 < it.nwords; w0 += 1024) {
+        const uint32_t w = w0 + threadIdx.x;
+        const uint64_t v = w < it.nwords ? it.vw[w] : 0ull;
+        const uint32_t pc = __popcll(v);
+        uint32_t total;
+        const uint32_t pre = block_excl_scan<1024>(pc, scratch, &total) + carry;
+        if (pc) {
+            uint32_t k = (pre + 127u) & ~127u;  // first frame start at or after pre
+            if (k < pre + pc) it.blkstart[k >> 7] = 64u * w + select_bit(v, k - pre);
+            k = pre + ((127u - pre) & 127u);    // first frame end at or after pre
+            if (k < pre + pc) it.blklast[k >> 7] = 64u * w + select_bit(v, k - pre);
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        plan.res[r].N = carry;
+        plan.res[r].nb = div_up(carry, kFrame);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Residuals and frame packing.  A workgroup takes kGroupFrames consecutive
+// frames of one record: it streams the pixels they cover, keeps the in-range
+// samples (Sec. III-C), subtracts the previous scan for a P-scan (Sec. III-D)
+// and compacts them in LDS; each wave then codes frames: delta to the
+// preceding value, ZigZag (Eq. 1), width choice and packing (Sec. II).
+// A packed frame goes to its slot: payload (16 b bytes), exception
+// positions (n bytes), exception high parts (ceil(n (B-b) / 8) bytes).
+// ---------------------------------------------------------------------------
+template <int WB>
+__device__ __forceinline__ uint32_t residual_at(const EncItem& it, uint32_t mode, uint32_t p, uint32_t m) {
+    const uint32_t q = quantize(load1<WB>(it.x, p), it.div);
+    if (!mode) return q;
+    uint32_t qp = load1<WB>(it.xprev, p);
+    if (!it.prev_quantized) qp = quantize(qp, it.div);
+    return (q - qp) & m;
+}
+
+struct FramesLds {
+    uint32_t sv[kGroupFrames * kFrame + 1];
+    uint32_t scratch[8];
+    uint32_t pw[4][128];
+    uint32_t hw[4][128];
+};
+
+template <int WB>
+__device__ __forceinline__ void enc_frames_body(const EncPlan& plan, const EncItem& it, uint32_t r, FramesLds& L) {
+    uint32_t* sv = L.sv;
+    uint32_t* scratch = L.scratch;
+    auto& pw = L.pw;
+    auto& hw = L.hw;
+    const uint32_t N = plan.res[r].N, nb = plan.res[r].nb, mode = plan.res[r].mode;
+    const uint32_t j0 = blockIdx.x * kGroupFrames;
+    if (j0 >= nb) return;
+    const uint32_t j1 = min(j0 + kGroupFrames, nb);
+    const uint32_t nvals = min(j1 * kFrame, N) - j0 * kFrame;
+    const uint32_t p_lo = it.blkstart[j0];
+    const uint32_t p_hi = (j1 == nb) ? it.npx - 1 : it.blklast[j1 - 1];
+    const uint32_t m = low_mask32(it.bits);
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) sv[0] = j0 ? residual_at<WB>(it, mode, it.blklast[j0 - 1], m) : 0u;
+
+    uint32_t cnt = 0;
+    for (uint32_t c0 = p_lo & ~15u; c0 <= p_hi; c0 += 256 * 16) {
+        const uint32_t p0 = c0 + tid * 16;
+        uint32_t s[16];
+        uint32_t keep = 0;
+        if (p0 <= p_hi && p0 + 15 >= p_lo && p0 < it.npx) {
+            uint32_t x[16];
+            load16<WB>(it.x, p0, it.npx, it.aligned16, x);
+            uint32_t xp[16];
+            if (mode) load16<WB>(it.xprev, p0, it.npx, it.aligned16, xp);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t p = p0 + i;
+                const uint32_t q = quantize(x[i], it.div);
+                uint32_t val = q;
+                if (mode) {
+                    const uint32_t qp = it.prev_quantized ? xp[i] : quantize(xp[i], it.div);
+                    val = (q - qp) & m;
+                }
+                s[i] = val;
+                if (q != 0 && p >= p_lo && p <= p_hi) keep |= 1u << i;
+            }
+        }
+        uint32_t total;
+        uint32_t off = block_excl_scan<256>(__popc(keep), scratch, &total);
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (keep & (1u << i)) sv[1 + cnt + off++] = s[i];
+        cnt += total;
+    }
+    __syncthreads();
+
+    const uint32_t wave = tid / kWave, l = lane_id();
+    for (uint32_t jj = wave; jj < j1 - j0; jj += 4) {
+        const uint32_t k0 = jj * kFrame;
+        const uint32_t real = min(kFrame, nvals - k0);
+        const uint32_t i0 = l, i1 = l + 64;
+        uint32_t z0 = 0, z1 = 0;
+        if (i0 < real) z0 = zigzag((sv[1 + k0 + i0] - sv[k0 + i0]) & m, it.bits);
+        if (i1 < real) z1 = zigzag((sv[1 + k0 + i1] - sv[k0 + i1]) & m, it.bits);
+        const FrameChoice fc = choose_frame(z0, z1);
+        const uint32_t b = fc.b, hwid = fc.B - fc.b;
+        pw[wave][l] = 0; pw[wave][l + 64] = 0;
+        hw[wave][l] = 0; hw[wave][l + 64] = 0;
+        __builtin_amdgcn_wave_barrier();
+        if (b) {
+            const uint32_t lm = low_mask32(b);
+            uint32_t bp = i0 * b;
+            uint64_t t = (uint64_t)(z0 & lm) << (bp & 31);
+            atomicOr(&pw[wave][bp >> 5], (uint32_t)t);
+            if ((uint32_t)(t >> 32)) atomicOr(&pw[wave][(bp >> 5) + 1], (uint32_t)(t >> 32));
+            bp = i1 * b;
+            t = (uint64_t)(z1 & lm) << (bp & 31);
+            atomicOr(&pw[wave][bp >> 5], (uint32_t)t);
+            if ((uint32_t)(t >> 32)) atomicOr(&pw[wave][(bp >> 5) + 1], (uint32_t)(t >> 32));
+        }
+        const bool e0 = b < 32 && (z0 >> b) != 0;
+        const bool e1 = b < 32 && (z1 >> b) != 0;
+        const uint64_t m0 = ballot(e0), m1 = ballot(e1);
+        const uint32_t r0 = rank_below(m0), r1 = __popcll(m0) + rank_below(m1);
+        uint8_t* slot = it.slots + (size_t)(j0 + jj) * kSlotBytes;
+        if (e0) slot[16 * b + r0] = (uint8_t)i0;
+        if (e1) slot[16 * b + r1] = (uint8_t)i1;
+        if (fc.n) {
+            if (e0) {
+                uint32_t bp = r0 * hwid;
+                uint64_t t = (uint64_t)(z0 >> b) << (bp & 31);
+                atomicOr(&hw[wave][bp >> 5], (uint32_t)t);
+                if ((uint32_t)(t >> 32)) atomicOr(&hw[wave][(bp >> 5) + 1], (uint32_t)(t >> 32));
+            }
+            if (e1) {
+                uint32_t bp = r1 * hwid;
+                uint64_t t = (uint64_t)(z1 >> b) << (bp & 31);
+                atomicOr(&hw[wave][bp >> 5], (uint32_t)t);
+                if ((uint32_t)(t >> 32)) atomicOr(&hw[wave][(bp >> 5) + 1], (uint32_t)(t >> 32));
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // payload words
+        uint32_t* sw = (uint32_t*)slot;
+        if (l < 4 * b) sw[l] = pw[wave][l];
+        if (l + 64 < 4 * b) sw[l + 64] = pw[wave][l + 64];
+        // exception high parts, byte by byte
+        const uint32_t hb = (fc.n * hwid + 7) / 8;
+        const uint8_t* hbytes = (const uint8_t*)hw[wave];
+        for (uint32_t k = l; k < hb; k += 64) slot[16 * b + fc.n + k] = hbytes[k];
+        if (l == 0) it.blkinfo[j0 + jj] = b | (fc.n << 8) | (fc.B << 16);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_enc_frames(EncPlan plan) {
+    const uint32_t r = blockIdx.y;
+    const EncItem it = plan.items[r];
+    __shared__ FramesLds lds;
+    switch (it.wb) {
+        case 4: enc_frames_body<4>(plan, it, r, lds); break;
+        case 2: enc_frames_body<2>(plan, it, r, lds); break;
+        default: enc_frames_body<1>(plan, it, r, lds); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Mask frame (Sec. III-C/D): content byte i holds mask bits 8i..8i+7 (bit = 1:
+// zero sample), XORed with the previous mask for a P-scan.  Runs of >= 8
+// equal bytes become RLE blocks, the stretches between them Raw blocks,
+// each split at 128 KiB (RFC 8878 frame, single segment, no checksum).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t content_byte(const EncItem& it, uint32_t mode, uint32_t i) {
+    const uint32_t w = i >> 3;
+    const uint64_t tm = tail_mask(w, it.nwords, it.npx);
+    uint64_t mk = ~it.vw[w] & tm;
+    if (mode) mk ^= ~it.vwprev[w] & tm;
+    return (uint32_t)(mk >> (8 * (i & 7))) & 0xFFu;
+}
+
+struct SegScan {
+    uint32_t is_long[4];
+    uint32_t start[4];
+};
+
+// classifies the 4 content bytes of this thread: long-run membership and
+// segment starts.  `lds` holds content bytes [c0 - 8, c0 + 4096 + 8) (0x100
+// marks a position outside the content).
+__device__ __forceinline__ void classify4(const uint16_t* lds, uint32_t c0, uint32_t nm, SegScan& out) {
+    auto at = [&](int i) -> uint32_t { return lds[i - (int)c0 + 8]; };
+    auto is_long = [&](int i) -> uint32_t {
+        const uint32_t b = at(i);
+        int left = 0, right = 0;
+        for (int k = 1; k <= 7; ++k) { if (at(i - k) == b) left++; else break; }
+        for (int k = 1; k <= 7; ++k) { if (at(i + k) == b) right++; else break; }
+        return (left + right + 1 >= (int)kRleMinRun) ? 1u : 0u;
+    };
+    for (int k = 0; k < 4; ++k) {
+        const int i = (int)c0 + 4 * (int)threadIdx.x + k;
+        out.is_long[k] = 0;
+        out.start[k] = 0;
+        if ((uint32_t)i >= nm) continue;
+        const uint32_t L = is_long(i);
+        out.is_long[k] = L;
+        if (i == 0) { out.start[k] = 1; continue; }
+        const uint32_t Lp = is_long(i - 1);
+        out.start[k] = (L != Lp) || (L && at(i) != at(i - 1));
+    }
+}
+
+__device__ __forceinline__ void stage_content(const EncItem& it, uint32_t mode, uint16_t* lds, uint32_t c0,
+                                              uint32_t nm) {
+    for (uint32_t k = threadIdx.x; k < 4096 + 16; k += 1024) {
+        const int i = (int)c0 - 8 + (int)k;
+        lds[k] = (i >= 0 && (uint32_t)i < nm) ? (uint16_t)content_byte(it, mode, (uint32_t)i) : (uint16_t)0x100;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_enc_mframe(EncPlan plan) {
+    const uint32_t r = blockIdx.x;
+    const EncItem it = plan.items[r];
+    const uint32_t mode = plan.res[r].mode;
+    const uint32_t nm = div_up(it.npx, 8);
+    __shared__ uint16_t lds[4096 + 16];
+    __shared__ uint32_t scratch[20];
+    const uint32_t hdr = nm <= 255 ? 6u : nm <= 65791 ? 7u : 9u;
+
+    // pass 1: segment starts
+    uint32_t nseg = 0;
+    for (uint32_t c0 = 0; c0 < nm; c0 += 4096) {
+        stage_content(it, mode, lds, c0, nm);
+        __syncthreads();
+        SegScan sc;
+        classify4(lds, c0, nm, sc);
+        const uint32_t cnt = sc.start[0] + sc.start[1] + sc.start[2] + sc.start[3];
+        uint32_t total;
+        uint32_t sid = block_excl_scan<1024>(cnt, scratch, &total) + nseg;
+        for (int k = 0; k < 4; ++k)
+            if (sc.start[k]) it.segs[sid++] = (c0 + 4 * threadIdx.x + k) | (sc.is_long[k] << 31);
+        nseg += total;
+        __syncthreads();
+    }
+    __threadfence_block();
+    __syncthreads();
+    // pass 2: encoded sizes and offsets of the segments
+    uint32_t off_carry = hdr;
+    for (uint32_t s0 = 0; s0 < nseg; s0 += 1024) {
+        const uint32_t s = s0 + threadIdx.x;
+        uint32_t size = 0;
+        if (s < nseg) {
+            const uint32_t a = it.segs[s];
+            const uint32_t start = a & 0x7FFFFFFFu;
+            const uint32_t end = (s + 1 < nseg) ? (it.segs[s + 1] & 0x7FFFFFFFu) : nm;
+            const uint32_t len = end - start;
+            const uint32_t nblk = div_up(len, kZstdBlockMax);
+            size = (a >> 31) ? 4u * nblk : 3u * nblk + len;
+        }
+        uint32_t total;
+        const uint32_t off = block_excl_scan<1024>(size, scratch, &total) + off_carry;
+        if (s < nseg) it.segoff[s] = off;
+        off_carry += total;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // pass 3: write the frame
+    uint8_t* f = it.frame;
+    if (threadIdx.x == 0) {
+        f[0] = 0x28; f[1] = 0xB5; f[2] = 0x2F; f[3] = 0xFD;
+        if (nm <= 255) { f[4] = 0x20; f[5] = (uint8_t)nm; }
+        else if (nm <= 65791) { f[4] = 0x60; f[5] = (uint8_t)(nm - 256); f[6] = (uint8_t)((nm - 256) >> 8); }
+        else { f[4] = 0xA0; f[5] = (uint8_t)nm; f[6] = (uint8_t)(nm >> 8); f[7] = (uint8_t)(nm >> 16); f[8] = (uint8_t)(nm >> 24); }
+        plan.res[r].flen = off_carry;
+        plan.res[r].nseg = nseg;
+    }
+    // block headers (and the byte of each RLE block)
+    for (uint32_t s = threadIdx.x; s < nseg; s += 1024) {
+        const uint32_t a = it.segs[s];
+        const uint32_t start = a & 0x7FFFFFFFu;
+        const uint32_t end = (s + 1 < nseg) ? (it.segs[s + 1] & 0x7FFFFFFFu) : nm;
+        const uint32_t len = end - start;
+        const uint32_t nblk = div_up(len, kZstdBlockMax);
+        const uint32_t is_rle = a >> 31;
+        uint32_t o = it.segoff[s];
+        for (uint32_t q = 0; q < nblk; ++q) {
+            const uint32_t blen = min(kZstdBlockMax, len - q * kZstdBlockMax);
+            const uint32_t last = (s + 1 == nseg && q + 1 == nblk) ? 1u : 0u;
+            const uint32_t h = last | (is_rle << 1) | (blen << 3);
+            f[o] = (uint8_t)h; f[o + 1] = (uint8_t)(h >> 8); f[o + 2] = (uint8_t)(h >> 16);
+            if (is_rle) {
+                f[o + 3] = (uint8_t)content_byte(it, mode, start);
+                o += 4;
+            } else {
+                o += 3 + blen;
+            }
+        }
+    }
+    // raw bytes: recompute the segment of every byte
+    uint32_t seg_carry = 0;
+    for (uint32_t c0 = 0; c0 < nm; c0 += 4096) {
+        stage_content(it, mode, lds, c0, nm);
+        __syncthreads();
+        SegScan sc;
+        classify4(lds, c0, nm, sc);
+        const uint32_t cnt = sc.start[0] + sc.start[1] + sc.start[2] + sc.start[3];
+        uint32_t total;
+        uint32_t sid = block_excl_scan<1024>(cnt, scratch, &total) + seg_carry;  // segments started before
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = c0 + 4 * threadIdx.x + k;
+            if (i >= nm) break;
+            if (sc.start[k]) sid++;
+            if (sc.is_long[k]) continue;
+            const uint32_t sg = sid - 1;
+            const uint32_t start = it.segs[sg] & 0x7FFFFFFFu;
+            const uint32_t q = (i - start) / kZstdBlockMax;
+            f[it.segoff[sg] + 3u * (q + 1u) + (i - start)] = (uint8_t)lds[i - c0 + 8];
+        }
+        seg_carry += total;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Section layout of each record: prefix sums of payload, position and high
+// part sizes over its frames; the record length.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_enc_sizes(EncPlan plan) {
+    const uint32_t r = blockIdx.x;
+    const EncItem it = plan.items[r];
+    const uint32_t nb = plan.res[r].nb;
+    __shared__ uint32_t scratch[8];
+    uint32_t cp = 0, cn = 0, ch = 0;
+    for (uint32_t j0 = 0; j0 < nb; j0 += 256) {
+        const uint32_t j = j0 + threadIdx.x;
+        uint32_t pay = 0, pos = 0, high = 0;
+        if (j < nb) {
+            const uint32_t info = it.blkinfo[j];
+            const uint32_t b = info & 0xFF, n = (info >> 8) & 0xFF, B = (info >> 16) & 0xFF;
+            pay = 16 * b;
+            pos = n;
+            high = (n * (B - b) + 7) / 8;
+        }
+        uint32_t tp, tn, th;
+        const uint32_t op = block_excl_scan<256>(pay, scratch, &tp);
+        const uint32_t on = block_excl_scan<256>(pos, scratch, &tn);
+        const uint32_t oh = block_excl_scan<256>(high, scratch, &th);
+        if (j < nb) {
+            it.blkoffs[3 * j] = cp + op;
+            it.blkoffs[3 * j + 1] = cn + on;
+            it.blkoffs[3 * j + 2] = ch + oh;
+        }
+        cp += tp; cn += tn; ch += th;
+    }
+    if (threadIdx.x == 0) {
+        EncRes& rs = plan.res[r];
+        rs.pay = cp;
+        rs.pos = cn;
+        rs.high = ch;
+        rs.rec_len = align4(12 + rs.flen) + align4(4 + 3 * nb) + align4(cp + cn + ch);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Record offsets: one prefix sum over all records, rebased per output.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_enc_offsets(EncPlan plan) {
+    __shared__ uint64_t scratch[20];
+    uint64_t carry = 0;
+    for (uint32_t r0 = 0; r0 < plan.n_items; r0 += 1024) {
+        const uint32_t r = r0 + threadIdx.x;
+        const uint64_t len = r < plan.n_items ? plan.res[r].rec_len : 0;
+        uint64_t total;
+        const uint64_t pre = block_excl_scan64<1024>(len, scratch, &total) + carry;
+        if (r < plan.n_items) plan.res[r].rec_off = pre;
+        carry += total;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < plan.n_outs; k += 1024) {
+        EncOut& o = plan.outs[k];
+        uint64_t body = 0, base = 0;
+        if (o.n_items) {
+            const uint32_t last = o.first_item + o.n_items - 1;
+            base = plan.res[o.first_item].rec_off;
+            body = plan.res[last].rec_off + plan.res[last].rec_len - base;
+        }
+        o.gbase = base;
+        o.len = o.hdr_len + body;
+        o.ok = o.len <= o.cap ? 1u : 0u;
+        if (!o.ok) atomicOr(plan.err, kErrCapacity);
+    }
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < plan.n_items; r += 1024) {
+        const EncOut& o = plan.outs[plan.items[r].out_id];
+        plan.res[r].rec_off = plan.res[r].rec_off - o.gbase + o.hdr_len;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Assembly.  blockIdx.x == 0: record header, mask frame, section header and
+// padding (and the stream header for an output's first record);
+// blockIdx.x >= 1: the packed frames of one group.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
+    const uint32_t r = blockIdx.y;
+    const EncItem it = plan.items[r];
+    const EncOut& o = plan.outs[it.out_id];
+    if (!o.ok) return;
+    const EncRes rs = plan.res[r];
+    uint8_t* rec = o.base + rs.rec_off;
+    const uint32_t sec = align4(12 + rs.flen);
+    const uint32_t hdr4 = align4(4 + 3 * rs.nb);
+    const uint32_t pay0 = sec + hdr4, pos0 = pay0 + rs.pay, high0 = pos0 + rs.pos, end = high0 + rs.high;
+    const uint32_t tid = threadIdx.x;
+    if (blockIdx.x == 0) {
+        if (tid == 0) {
+            uint32_t* h = (uint32_t*)rec;
+            h[0] = rs.rec_len;
+            h[1] = rs.mode | (it.attr << 8);
+            h[2] = rs.flen;
+            *(uint32_t*)(rec + sec) = rs.N;
+        }
+        for (uint32_t k = tid; k < rs.flen; k += 256) rec[12 + k] = it.frame[k];
+        for (uint32_t k = 12 + rs.flen + tid; k < sec; k += 256) rec[k] = 0;
+        for (uint32_t j = tid; j < rs.nb; j += 256) {
+            const uint32_t info = it.blkinfo[j];
+            rec[sec + 4 + j] = (uint8_t)(info & 0xFF);
+            rec[sec + 4 + rs.nb + j] = (uint8_t)((info >> 8) & 0xFF);
+            rec[sec + 4 + 2 * rs.nb + j] = (uint8_t)((info >> 16) & 0xFF);
+        }
+        for (uint32_t k = sec + 4 + 3 * rs.nb + tid; k < pay0; k += 256) rec[k] = 0;
+        for (uint32_t k = end + tid; k < rs.rec_len; k += 256) rec[k] = 0;
+        if (r == o.first_item && o.hdr_len) {
+            uint8_t* s = o.base;
+            if (tid == 0) {
+                s[0] = 'J'; s[1] = 'F'; s[2] = 'Y'; s[3] = '1';
+                *(uint16_t*)(s + 4) = 1;
+                *(uint16_t*)(s + 6) = (uint16_t)o.n_attrs;
+                *(uint32_t*)(s + 8) = o.height;
+                *(uint32_t*)(s + 12) = o.width;
+                *(uint32_t*)(s + 16) = o.n_scans;
+            }
+            if (tid < o.n_attrs) {
+                uint32_t* a = (uint32_t*)(s + 20 + 8 * tid);
+                a[0] = o.attr_wb[tid];
+                a[1] = o.attr_p[tid];
+            }
+            uint32_t* table = (uint32_t*)(s + 20 + 8 * o.n_attrs);
+            for (uint32_t k = tid; k < o.n_items; k += 256) table[k] = plan.res[o.first_item + k].rec_len;
+        }
+        return;
+    }
+    const uint32_t j0 = (blockIdx.x - 1) * kGroupFrames;
+    if (j0 >= rs.nb) return;
+    const uint32_t j1 = min(j0 + kGroupFrames, rs.nb);
+    const uint32_t wave = tid / kWave, l = lane_id();
+    for (uint32_t j = j0 + wave; j < j1; j += 4) {
+        const uint32_t info = it.blkinfo[j];
+        const uint32_t b = info & 0xFF, n = (info >> 8) & 0xFF, B = (info >> 16) & 0xFF;
+        const uint32_t hb = (n * (B - b) + 7) / 8;
+        const uint8_t* slot = it.slots + (size_t)j * kSlotBytes;
+        const uint32_t* sw = (const uint32_t*)slot;
+        uint32_t* dp = (uint32_t*)(rec + pay0 + it.blkoffs[3 * j]);
+        if (l < 4 * b) dp[l] = sw[l];
+        if (l + 64 < 4 * b) dp[l + 64] = sw[l + 64];
+        uint8_t* pp = rec + pos0 + it.blkoffs[3 * j + 1];
+        for (uint32_t k = l; k < n; k += 64) pp[k] = slot[16 * b + k];
+        uint8_t* hp = rec + high0 + it.blkoffs[3 * j + 2];
+        for (uint32_t k = l; k < hb; k += 64) hp[k] = slot[16 * b + n + k];
+    }
+}
+
+hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
+    if (plan.n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_enc_mask, dim3(plan.n_tiles), dim3(256), 0, stream, plan);
+    hipLaunchKernelGGL(k_enc_trial, dim3(plan.n_items), dim3(256), 0, stream, plan);
+    hipLaunchKernelGGL(k_enc_scan, dim3(plan.n_items), dim3(1024), 0, stream, plan);
+    hipLaunchKernelGGL(k_enc_frames, dim3(plan.max_groups, plan.n_items), dim3(256), 0, stream, plan);
+    hipLaunchKernelGGL(k_enc_mframe, dim3(plan.n_items), dim3(1024), 0, stream, plan);
+    hipLaunchKernelGGL(k_enc_sizes, dim3(plan.n_items), dim3(256), 0, stream, plan);
+    hipLaunchKernelGGL(k_enc_offsets, dim3(1), dim3(1024), 0, stream, plan);
+    hipLaunchKernelGGL(k_enc_assemble, dim3(plan.max_groups + 1, plan.n_items), dim3(256), 0, stream, plan);
+    return hipGetLastError();
+}
+
+}  // namespace jiffy

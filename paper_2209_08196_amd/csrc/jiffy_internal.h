@@ -1,0 +1,139 @@
+// Internal declarations shared by the Jiffy HIP kernels and the C-ABI host
+// code.  gfx950 only: wave64, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jiffy {
+
+constexpr int kWave = 64;
+constexpr uint32_t kFrame = 128;            // values per packed frame (Sec. II: frames of 128)
+constexpr uint32_t kSlotBytes = 512;        // largest packed frame: 16 * 32 bytes
+constexpr uint32_t kTilePx = 4096;          // pixels per mask tile (64 words of 64 px)
+constexpr uint32_t kTileWords = kTilePx / 64;
+constexpr uint32_t kGroupFrames = 16;       // frames handled by one encode/decode workgroup
+constexpr uint32_t kZstdBlockMax = 131072;  // largest Zstandard block (RFC 8878)
+constexpr uint32_t kRleMinRun = 8;          // runs this long become RLE blocks
+
+// Error bits raised by kernels (ORed into a device word).
+enum : uint32_t { kErrCorrupt = 1u, kErrCapacity = 2u };
+
+inline __host__ __device__ uint32_t align4(uint32_t x) { return (x + 3u) & ~3u; }
+inline __host__ __device__ uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+// Worst-case size of the mask frame for n content bytes.
+inline __host__ __device__ uint32_t frame_bound(uint32_t n) { return 16u + n + 4u * (n / kZstdBlockMax + 1u); }
+
+// Division by a run-time invariant P (Granlund & Montgomery, "Division by
+// invariant integers using multiplication", 1994): n / P = (t + ((n - t) >> s1)) >> s2,
+// t = mulhi(m, n), exact for every 32-bit n.
+struct Divisor {
+    uint32_t P, magic, s1, s2, half_up;  // half_up = ceil(P / 2)
+};
+
+inline Divisor make_divisor(uint32_t P) {
+    Divisor d;
+    uint32_t l = 0;
+    while ((1ull << l) < P) l++;
+    d.P = P;
+    d.magic = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - P)) / P + 1);
+    d.s1 = l < 1 ? l : 1;
+    d.s2 = l > 1 ? l - 1 : 0;
+    d.half_up = P - P / 2;
+    return d;
+}
+
+// One (scan, attribute) record to encode.
+struct EncItem {
+    const void* x;            // current scan, npx samples
+    const void* xprev;        // previous scan (raw or quantized), or null
+    void* qout;               // if set, the quantized scan is stored here
+    uint64_t* vw;             // valid-sample words of this scan (bit = 1: nonzero)
+    const uint64_t* vwprev;   // valid-sample words of the previous scan
+    uint32_t* blkstart;       // [maxnb] pixel of each frame's first value
+    uint32_t* blklast;        // [maxnb] pixel of each frame's last value
+    uint32_t* blkinfo;        // [maxnb] b | n << 8 | B << 16
+    uint32_t* blkoffs;        // [3 * maxnb] payload / position / high offsets
+    uint8_t* slots;           // [maxnb * kSlotBytes] packed frames
+    uint8_t* frame;           // mask frame staging
+    uint32_t* segs;           // [seg_cap] frame segment starts (bit 31: run)
+    uint32_t* segoff;         // [seg_cap] frame segment output offsets
+    Divisor div;
+    uint32_t npx, nwords, height, width;
+    uint32_t wb, bits, attr, out_id;
+    uint32_t has_prev, prev_quantized, mode_req, trial_rows;
+    uint32_t maxnb, frame_cap, seg_cap, aligned16;
+};
+
+// Per-record results of an encode.
+struct EncRes {
+    uint32_t N, nb, mode, flen;
+    uint32_t pay, pos, high, rec_len;
+    uint32_t nseg, pad0;
+    uint64_t rec_off;
+};
+
+// One output buffer of an encode call (the whole stream, or one stream's
+// records in a batch step).
+struct EncOut {
+    uint8_t* base;
+    uint64_t cap;
+    uint32_t first_item, n_items;
+    uint32_t hdr_len;         // stream header + length table, or 0
+    uint32_t n_scans, n_attrs, height, width;
+    uint32_t ok;
+    uint64_t len;
+    uint64_t gbase;           // global prefix of the first record (scratch)
+    uint8_t attr_wb[8];
+    uint32_t attr_p[8];
+};
+
+// One record to decode.
+struct DecItem {
+    const uint8_t* rec;
+    uint32_t rec_len;
+    void* out;                // [npx] output samples
+    uint64_t* cw;             // unframed mask content (XOR form for a P-scan)
+    uint64_t* vw;             // valid-sample words
+    uint32_t* wpre;           // [nwords] exclusive prefix of valid counts
+    uint32_t* blkinfo;        // [maxnb]
+    uint32_t* blkoffs;        // [3 * maxnb]
+    uint32_t* bsum;           // [maxnb] frame sums, then exclusive prefixes
+    uint32_t* sbuf;           // [npx] running sums inside each frame
+    uint32_t npx, nwords, wb, bits;
+    uint32_t attr, t, P, maxnb;
+    uint32_t aligned16, pad0;
+};
+
+struct DecRes {
+    uint32_t mode, flen, N, nb;
+    uint32_t sec, pay_off, pos_off, high_off;
+    uint32_t err, pad0;
+};
+
+// ---- kernel launchers (defined in the .hip files) -------------------------
+struct EncPlan {
+    const EncItem* items;     // device
+    EncRes* res;              // device
+    EncOut* outs;             // device
+    uint32_t* err;            // device
+    const uint32_t* tile_item;  // device: item of each mask tile
+    const uint32_t* tile_first; // device: first tile of each item
+    uint32_t n_items, n_outs, n_tiles;
+    uint32_t max_groups;      // max over items of ceil(maxnb / kGroupFrames)
+};
+hipError_t launch_encode(const EncPlan& plan, hipStream_t stream);
+
+struct DecPlan {
+    const DecItem* items;
+    DecRes* res;
+    uint32_t* err;
+    uint32_t n_items, n_scans, n_attrs;
+    uint32_t nwords, npx, max_groups;
+    uint32_t n_tiles;
+    uint32_t need_temporal;   // per-pixel pass over time needed
+};
+hipError_t launch_decode(const DecPlan& plan, hipStream_t stream);
+
+}  // namespace jiffy

@@ -1,0 +1,231 @@
+"""Python binding of libjiffy.so (the C ABI of include/jiffy.h).
+
+Argument marshalling only: every step of encoding and decoding runs in the
+library's HIP kernels.  Tensors are PyTorch device tensors (device memory
+and the current HIP stream); results the C ABI returns on the host (lengths,
+modes) come back as Python / numpy values.  There is no fallback: without
+the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjiffy.so")
+MAX_ATTRS = 8
+
+OK, E_INVALID, E_CAPACITY, E_CORRUPT, E_DEVICE, E_SHAPE = 0, -1, -2, -3, -4, -5
+MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY = 0, 1, 2
+
+SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_peek", "jiffy_decode", "jiffy_status_string",
+           "jiffy_stream_create", "jiffy_batch_encode_step", "jiffy_stream_reset", "jiffy_stream_destroy")
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [
+        ("height", ctypes.c_uint32),
+        ("width", ctypes.c_uint32),
+        ("n_attrs", ctypes.c_uint32),
+        ("width_bytes", ctypes.c_uint8 * MAX_ATTRS),
+        ("precision", ctypes.c_uint32 * MAX_ATTRS),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("trial_rows", ctypes.c_uint32)]
+
+
+class JiffyError(RuntimeError):
+    def __init__(self, code, what=""):
+        msg = lib().jiffy_status_string(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads libjiffy.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2209_08196_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, u32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32
+        L.jiffy_encode_bound.restype = sz
+        L.jiffy_encode_bound.argtypes = [ctypes.POINTER(Layout), u32]
+        L.jiffy_encode.restype = ctypes.c_int
+        L.jiffy_encode.argtypes = [ctypes.POINTER(Layout), ctypes.POINTER(Options), u32, vp, vp, sz,
+                                   ctypes.POINTER(sz), vp, vp]
+        L.jiffy_peek.restype = ctypes.c_int
+        L.jiffy_peek.argtypes = [vp, sz, ctypes.POINTER(Layout), ctypes.POINTER(u32)]
+        L.jiffy_decode.restype = ctypes.c_int
+        L.jiffy_decode.argtypes = [vp, sz, vp, vp]
+        L.jiffy_status_string.restype = ctypes.c_char_p
+        L.jiffy_status_string.argtypes = [ctypes.c_int]
+        L.jiffy_stream_create.restype = ctypes.c_int
+        L.jiffy_stream_create.argtypes = [ctypes.POINTER(Layout), ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.jiffy_batch_encode_step.restype = ctypes.c_int
+        L.jiffy_batch_encode_step.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp]
+        L.jiffy_stream_reset.restype = ctypes.c_int
+        L.jiffy_stream_reset.argtypes = [vp]
+        L.jiffy_stream_destroy.restype = None
+        L.jiffy_stream_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_layout(height, width, widths, precisions=None):
+    lay = Layout()
+    lay.height, lay.width, lay.n_attrs = int(height), int(width), len(widths)
+    precisions = precisions if precisions is not None else [1] * len(widths)
+    for i, (w, p) in enumerate(zip(widths, precisions)):
+        lay.width_bytes[i] = int(w)
+        lay.precision[i] = int(p)
+    return lay
+
+
+def encode_bound(layout: Layout, n_scans: int) -> int:
+    return lib().jiffy_encode_bound(ctypes.byref(layout), n_scans)
+
+
+def _check_planes(planes):
+    import torch
+    T, H, W = planes[0].shape
+    for p in planes:
+        if p.device.type != "cuda" or not p.is_contiguous() or tuple(p.shape) != (T, H, W):
+            raise ValueError("planes must be contiguous device tensors of one [T, H, W] shape")
+        if p.dtype not in (torch.uint8, torch.int16, torch.int32, torch.uint16, torch.uint32):
+            raise ValueError(f"unsupported dtype {p.dtype}")
+    return T, H, W
+
+
+def encode(planes, precisions=None, mode=MODE_AUTO, trial_rows=0, out=None, stream=None):
+    """planes: list of contiguous device tensors [T, H, W] (uint8, uint16 /
+    int16 or uint32 / int32 storage).  Returns (stream tensor uint8 [n],
+    modes ndarray [T, A] uint8)."""
+    import torch
+    T, H, W = _check_planes(planes)
+    widths = [p.element_size() for p in planes]
+    lay = make_layout(H, W, widths, precisions)
+    opt = Options(mode, trial_rows)
+    if out is None:
+        out = torch.empty(encode_bound(lay, T), dtype=torch.uint8, device=planes[0].device)
+    arr = (ctypes.c_void_p * len(planes))(*[p.data_ptr() for p in planes])
+    n = ctypes.c_size_t()
+    modes = np.zeros((max(T, 1), len(planes)), np.uint8)
+    rc = lib().jiffy_encode(ctypes.byref(lay), ctypes.byref(opt), T, ctypes.cast(arr, ctypes.c_void_p),
+                            ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(n),
+                            modes.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+    if rc:
+        raise JiffyError(rc, "jiffy_encode")
+    return out[: n.value], modes[:T]
+
+
+def peek(data: bytes):
+    buf = np.frombuffer(bytes(data), np.uint8)
+    lay, T = Layout(), ctypes.c_uint32()
+    rc = lib().jiffy_peek(buf.ctypes.data_as(ctypes.c_void_p), len(data), ctypes.byref(lay), ctypes.byref(T))
+    if rc:
+        raise JiffyError(rc, "jiffy_peek")
+    return lay, T.value
+
+
+_TORCH_DT = {1: "uint8", 2: "int16", 4: "int32"}
+
+
+def decode(stream_bytes, layout: Layout = None, n_scans: int = None, outs=None, stream=None):
+    """stream_bytes: device uint8 tensor holding a whole stream.  layout /
+    n_scans come from jiffy_peek of its header when not given.  Returns the
+    list of decoded [T, H, W] device tensors (int16 / int32 storage for 16 /
+    32-bit attributes)."""
+    import torch
+    if layout is None or n_scans is None:
+        head = stream_bytes.cpu().numpy().tobytes()
+        layout, n_scans = peek(head)
+    dev = stream_bytes.device
+    if outs is None:
+        outs = [torch.empty((n_scans, layout.height, layout.width), dtype=getattr(torch, _TORCH_DT[layout.width_bytes[a]]),
+                            device=dev) for a in range(layout.n_attrs)]
+    arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+    rc = lib().jiffy_decode(ctypes.c_void_p(stream_bytes.data_ptr()), stream_bytes.numel(),
+                            ctypes.cast(arr, ctypes.c_void_p), _stream_handle(stream))
+    if rc:
+        raise JiffyError(rc, "jiffy_decode")
+    return outs
+
+
+class Stream:
+    """A sensor stream whose previous quantized scan stays resident on the
+    device (jiffy_stream)."""
+
+    def __init__(self, height, width, widths, precisions=None, mode=MODE_AUTO, trial_rows=0):
+        self.layout = make_layout(height, width, widths, precisions)
+        self.widths = list(widths)
+        opt = Options(mode, trial_rows)
+        h = ctypes.c_void_p()
+        rc = lib().jiffy_stream_create(ctypes.byref(self.layout), ctypes.byref(opt), ctypes.byref(h))
+        if rc:
+            raise JiffyError(rc, "jiffy_stream_create")
+        self.handle = h
+
+    def record_bound(self):
+        lay = self.layout
+        return encode_bound(lay, 1) - (20 + 8 * lay.n_attrs + 4 * lay.n_attrs)
+
+    def reset(self):
+        rc = lib().jiffy_stream_reset(self.handle)
+        if rc:
+            raise JiffyError(rc, "jiffy_stream_reset")
+
+    def close(self):
+        if self.handle:
+            lib().jiffy_stream_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_encode_step(streams, scans, outs, stream=None):
+    """streams: list of Stream; scans[i]: list of [H, W] device tensors (one
+    per attribute); outs[i]: device uint8 tensors.  Returns (lengths list,
+    modes ndarray [n, A])."""
+    n = len(streams)
+    if n == 0:
+        return [], np.zeros((0, 0), np.uint8)
+    A = streams[0].layout.n_attrs
+    sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
+    inner = [(ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
+    planes = (ctypes.c_void_p * n)(*[ctypes.cast(x, ctypes.c_void_p).value for x in inner])
+    dout = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    caps = (ctypes.c_size_t * n)(*[o.numel() for o in outs])
+    lens = (ctypes.c_size_t * n)()
+    modes = np.zeros((n, max(s.layout.n_attrs for s in streams)), np.uint8)
+    mbuf = np.zeros(sum(s.layout.n_attrs for s in streams), np.uint8)
+    rc = lib().jiffy_batch_encode_step(ctypes.cast(sh, ctypes.c_void_p), n, ctypes.cast(planes, ctypes.c_void_p),
+                                       ctypes.cast(dout, ctypes.c_void_p), ctypes.cast(caps, ctypes.c_void_p),
+                                       ctypes.cast(lens, ctypes.c_void_p), mbuf.ctypes.data_as(ctypes.c_void_p),
+                                       _stream_handle(stream))
+    if rc:
+        raise JiffyError(rc, "jiffy_batch_encode_step")
+    k = 0
+    for i, s in enumerate(streams):
+        a = s.layout.n_attrs
+        modes[i, :a] = mbuf[k:k + a]
+        k += a
+    del A
+    return list(lens), modes

@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every function include/jiffy.h
+declares; its host-only entry points (bound, header parse, status strings)
+agree with the oracle.  CPU only: no device call is made."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_08196_amd import jiffy, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "jiffy.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(jiffy_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(jiffy.LIB_PATH):
+        pytest.fail("libjiffy.so is not built (run __graft_entry__.build())")
+    return jiffy.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert set(names) == set(jiffy.SYMBOLS)
+    for n in names:
+        assert hasattr(lib, n), n
+        assert ctypes.cast(getattr(lib, n), ctypes.c_void_p).value
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        s = lib.jiffy_status_string(code)
+        assert s and s != b"unknown status"
+    assert lib.jiffy_status_string(7) == b"unknown status"
+
+
+def test_encode_bound_matches_oracle_bound(lib):
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        H, W = int(rng.integers(1, 300)), int(rng.integers(1, 5000))
+        widths = list(rng.choice([1, 2, 4], size=int(rng.integers(1, 9))))
+        precs = [int(p) for p in rng.integers(1, 100, len(widths))]
+        T = int(rng.integers(0, 50))
+        lay_g = jiffy.make_layout(H, W, widths, precs)
+        lay_o = oracle.make_layout(H, W, widths, precs)
+        assert jiffy.encode_bound(lay_g, T) == oracle.encode_bound(lay_o, T)
+    bad = jiffy.make_layout(4, 4, [3])
+    assert jiffy.encode_bound(bad, 1) == 0
+
+
+def test_peek_agrees_with_oracle(lib):
+    g = synth.stream(2, 0)
+    planes = [p[:, :16, :64] for p in g.scans(0, 3)]
+    s, _ = oracle.encode(planes)
+    lay, T = jiffy.peek(s)
+    lo, To = oracle.peek(s)
+    assert T == To == 3
+    assert (lay.height, lay.width, lay.n_attrs) == (lo.height, lo.width, lo.n_attrs)
+    assert list(lay.width_bytes[:5]) == list(lo.width_bytes[:5])
+    assert list(lay.precision[:5]) == list(lo.precision[:5])
+    for cut in (0, 10, 27, len(s) - 1):
+        with pytest.raises(jiffy.JiffyError):
+            jiffy.peek(s[:cut])
+    with pytest.raises(jiffy.JiffyError):
+        jiffy.peek(b"XFY1" + s[4:])
