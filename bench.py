@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Encode+decode throughput of the Jiffy codec on one MI355X.
+
+Workload: one sensor stream of 100 scans of 128x2048 with five attributes
+(dual-return range u32, second-return range u32, signal u16, reflectivity u8,
+near-IR u16), precision 1 mm, about 20% zero samples, seeded synthetic data
+standing in for the paper's Ouster driving recordings (the sensor drives,
+stops for 30 scans, drives again).  One step encodes all 100 scans
+(jiffy_encode) and decodes the stream back (jiffy_decode); inputs and
+outputs stay in device memory.  A point is one pixel of one attribute, as in
+the paper's points/s (Sec. IV-F).
+
+Prints one JSON line.  Besides the throughput it carries:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                mean launch time (HIP events on the launch stream) against
+                the 8 TB/s HBM peak; `traffic` is the HBM bytes measured with
+                rocprofv3 counters for the same kernel source (or null).
+  cpu_baseline  the CPU oracle (single thread) on the same workload, and
+                whether its stream is byte-identical to the GPU's.
+"""
+import argparse
+import hashlib
+import json
+import os
+import struct
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "encode+decode points/sec & HBM GB/s fraction at byte-identical output"
+HBM_PEAK_GBS = 8000.0
+CID = 2  # the dual-return 128x2048 five-attribute stream
+N_SCANS = 100
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_08196_amd", "csrc", f)
+                  for f in ("jiffy_encode.hip", "jiffy_decode.hip", "jiffy_device.h", "jiffy_internal.h")]
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stream_stats(s: bytes, widths, npx):
+    """Sizes of the stream's parts, read from its header and record headers."""
+    A, = struct.unpack_from("<H", s, 6)
+    T, = struct.unpack_from("<I", s, 16)
+    p = 20 + 8 * A
+    lens = struct.unpack_from(f"<{T * A}I", s, p)
+    p += 4 * T * A
+    st = dict(mask_bytes=0, frame_bytes=0, n_values=0, p_items=0, p_bytes=0, i_items=0)
+    for r, L in enumerate(lens):
+        a = r % A
+        mode = s[p + 4]
+        flen, = struct.unpack_from("<I", s, p + 8)
+        sec = (12 + flen + 3) & ~3
+        N, = struct.unpack_from("<I", s, p + sec)
+        nb = (N + 127) // 128
+        hdr4 = (4 + 3 * nb + 3) & ~3
+        b = np.frombuffer(s, np.uint8, nb, p + sec + 4).astype(np.int64)
+        n = np.frombuffer(s, np.uint8, nb, p + sec + 4 + nb).astype(np.int64)
+        B = np.frombuffer(s, np.uint8, nb, p + sec + 4 + 2 * nb).astype(np.int64)
+        st["frame_bytes"] += int((16 * b + n + (n * (B - b) + 7) // 8).sum())
+        st["mask_bytes"] += flen
+        st["n_values"] += N
+        if mode == 1:
+            st["p_items"] += 1
+            st["p_bytes"] += widths[a] * npx
+        else:
+            st["i_items"] += 1
+        p += L
+    st["stream_bytes"] = len(s)
+    return st
+
+
+def kernel_alg_bytes(name, st, x_bytes, n_items, nwords):
+    """Bytes each kernel must move for the whole workload (one launch)."""
+    vb = 8 * nwords * n_items          # valid-sample words of every record
+    F, M, S, N = st["frame_bytes"], st["mask_bytes"], st["stream_bytes"], st["n_values"]
+    Xp = st["p_bytes"]
+    table = {
+        "k_enc_mask": x_bytes + vb,
+        "k_enc_frames": x_bytes + Xp + F,
+        "k_enc_mframe": vb + M,
+        "k_enc_assemble": F + M + S,
+        "k_dec_parse": M + vb,
+        "k_dec_mask": 2 * vb,
+        "k_dec_frames": F + 4 * N,
+        "k_dec_scatter": 4 * N + vb + x_bytes,
+        "k_dec_temporal": 2 * Xp + vb,
+    }
+    return table.get(name)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=3, help="steps timed per kernel with HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (streams shard across GPUs "
+              "without exchange, so the one-GPU figure is the per-GPU throughput).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2209_08196_amd import jiffy, synth
+
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    g = synth.stream(CID, 0)
+    planes = g.scans(0, N_SCANS)
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] generated {N_SCANS} scans of {g.H}x{g.W}, {len(planes)} attributes in {t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    store = {1: np.uint8, 2: np.int16, 4: np.int32}
+    dev = [torch.from_numpy(p.view(store[p.dtype.itemsize])).cuda() for p in planes]
+    precs = g.precisions
+    widths = g.widths
+    T, H, W = planes[0].shape
+    npx = H * W
+    A = len(planes)
+    points = T * npx * A
+    x_bytes = sum(p.nbytes for p in planes)
+    lay = jiffy.make_layout(H, W, widths, precs)
+    out = torch.empty(jiffy.encode_bound(lay, T), dtype=torch.uint8, device="cuda")
+    dec = [torch.empty_like(d) for d in dev]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        s, modes = jiffy.encode(dev, precs, out=out)
+        jiffy.decode(s, lay, T, outs=dec)
+        return s, modes
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # correctness of this run: lossless round trip (P = 1 everywhere)
+    s_dev, modes = step()
+    for d, x in zip(dec, dev):
+        if not torch.equal(d, x):
+            raise SystemExit("decode(encode(x)) != x")
+    s_gpu = s_dev.cpu().numpy().tobytes()
+    st = stream_stats(s_gpu, widths, npx)
+    print(f"[bench] stream {len(s_gpu)} bytes, ratio {x_bytes / len(s_gpu):.2f}, P-scans {st['p_items']}",
+          file=sys.stderr, flush=True)
+
+    # timed steps
+    ev_e0, ev_e1, ev_d1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    enc_ms = dec_ms = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ev_e0.record(stream)
+        s, _ = jiffy.encode(dev, precs, out=out)
+        ev_e1.record(stream)
+        jiffy.decode(s, lay, T, outs=dec)
+        ev_d1.record(stream)
+        ev_d1.synchronize()
+        enc_ms += ev_e0.elapsed_time(ev_e1)
+        dec_ms += ev_e1.elapsed_time(ev_d1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = points / (wall / args.steps)
+    print(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # per-kernel times with HIP events on the launch stream
+    jiffy.profile_enable(True)
+    for _ in range(args.profile_steps):
+        step()
+    torch.cuda.synchronize()
+    prof = jiffy.profile_read()
+    jiffy.profile_enable(False)
+    n_items = T * A
+    nwords = (npx + 63) // 64
+    kernels = {k: dict(avg_ms=v[0] / v[1], launches=v[1]) for k, v in prof.items()}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    alg = kernel_alg_bytes(dom, st, x_bytes, n_items, nwords)
+    avg_s = kernels[dom]["avg_ms"] / 1e3
+    achieved = alg / avg_s / 1e9 if alg else None
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        ent = tr.get("kernels", {}).get(dom)
+        if ent and tr.get("source_sha") == source_sha() and tr.get("workload") == g.cfg.name:
+            traffic = ent["fetch_bytes"] + ent["write_bytes"]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "traffic": traffic, "kernel": dom, "alg_bytes_per_launch": alg,
+                "avg_launch_ms": round(kernels[dom]["avg_ms"], 4)}
+    path_alg = 2 * (x_bytes + st["p_bytes"]) + 2 * st["stream_bytes"]
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{g.cfg.name}, {T} scans, encode+decode", "scans": T, "height": H, "width": W,
+                   "attributes": [a.name for a in g.cfg.attrs], "precision_mm": 1},
+        "encode_points_per_s": round(points / (enc_ms / args.steps / 1e3), 1),
+        "decode_points_per_s": round(points / (dec_ms / args.steps / 1e3), 1),
+        "compression_ratio": round(x_bytes / st["stream_bytes"], 3),
+        "p_scans": st["p_items"], "i_scans": st["i_items"],
+        "path_alg_gbps": round(path_alg / (wall / args.steps) / 1e9, 1),
+        "path_hbm_frac": round(path_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+        "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_ms"])},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle  # the CPU-baseline leg: the oracle timed on the host
+
+        planes_np = planes
+        t0 = time.perf_counter()
+        s_ref, m_ref = oracle.encode(planes_np, precs)
+        t1 = time.perf_counter()
+        oracle.decode(s_ref)
+        t2 = time.perf_counter()
+        identical = (s_ref == s_gpu) and bool(np.array_equal(m_ref, modes))
+        result["byte_identical"] = identical
+        result["cpu_baseline"] = {
+            "value": round(points / (t2 - t0), 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole workload ({T} scans x {A} attributes), encode + decode, one thread",
+            "encode_s": round(t1 - t0, 2), "decode_s": round(t2 - t1, 2),
+            "host_cpu": _cpu_model(), "host_cores": os.cpu_count(),
+        }
+        if not identical:
+            print("[bench] GPU stream differs from the oracle", file=sys.stderr)
+    print(json.dumps(result), flush=True)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

@@ -83,9 +83,11 @@ int jiffy_encode(const jiffy_layout* layout, const jiffy_options* options, uint3
                  const void* const* d_planes, void* d_out, size_t out_capacity, size_t* h_out_len,
                  uint8_t* h_modes, hipStream_t stream);
 
-/* Parses a stream header in host memory.  With a record-length table
- * (n_scans > 0 in the header) in_len must be the whole stream; a header
- * without one (records until the end) is walked record by record.
+/* Parses a stream header in host memory.  in_len is the length of the whole
+ * stream.  With a record-length table (n_scans > 0 in the header) only the
+ * header and the table are read (h_in must hold at least those) and the
+ * table must add up to in_len; a header without one (records until the end)
+ * is walked record by record, so h_in must then hold the whole stream.
  * Returns JIFFY_OK or JIFFY_E_CORRUPT. */
 int jiffy_peek(const void* h_in, size_t in_len, jiffy_layout* layout, uint32_t* n_scans);
 
@@ -127,6 +129,15 @@ int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void
 int jiffy_stream_reset(jiffy_stream* s);
 
 void jiffy_stream_destroy(jiffy_stream* s);
+
+/* ---- kernel timing (benchmarks) ----------------------------------------
+ * While enabled, every kernel this library launches is bracketed by HIP
+ * events recorded on the stream it runs on, and the elapsed times add up
+ * per kernel name.  Enabling clears the totals.  jiffy_profile_read copies
+ * up to max_kernels entries: names (32 bytes each, NUL-terminated), total
+ * milliseconds and launch counts; it returns the number of kernels seen. */
+int jiffy_profile_enable(int enable);
+int jiffy_profile_read(uint32_t max_kernels, char* names, double* total_ms, uint32_t* launches);
 
 #ifdef __cplusplus
 }

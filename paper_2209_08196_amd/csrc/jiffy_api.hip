@@ -14,6 +14,8 @@ using namespace jiffy;
 
 namespace {
 
+void prof_collect();
+
 constexpr size_t kAlign = 256;
 size_t al(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -233,6 +235,7 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
     if (hipMemcpyAsync(ctx.down.p, dev, o_items, hipMemcpyDeviceToHost, stream) != hipSuccess)
         return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    prof_collect();
 
     const uint8_t* down = (const uint8_t*)ctx.down.p;
     const EncRes* dres = (const EncRes*)(down + o_res);
@@ -274,12 +277,98 @@ int parse_header(const uint8_t* h, size_t len, jiffy_layout* L, uint32_t* T, siz
     return JIFFY_OK;
 }
 
+// ---------------------------------------------------------------------------
+// kernel timing: events around each launch, read back after the call's sync
+// ---------------------------------------------------------------------------
+struct ProfEntry {
+    const char* name;
+    hipEvent_t start, stop;
+};
+struct ProfTotal {
+    char name[32];
+    double ms;
+    uint32_t launches;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfEntry> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+std::vector<ProfTotal> g_prof_totals;
+
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// called after the stream of the pending launches has been synchronized
+void prof_collect() {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    for (ProfEntry& p : g_prof_pending) {
+        float ms = 0.f;
+        if (p.start && p.stop && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+            ProfTotal* t = nullptr;
+            for (ProfTotal& x : g_prof_totals)
+                if (strncmp(x.name, p.name, sizeof x.name) == 0) t = &x;
+            if (!t) {
+                g_prof_totals.push_back(ProfTotal{});
+                t = &g_prof_totals.back();
+                strncpy(t->name, p.name, sizeof t->name - 1);
+            }
+            t->ms += ms;
+            t->launches++;
+        }
+        if (p.start) g_prof_pool.push_back(p.start);
+        if (p.stop) g_prof_pool.push_back(p.stop);
+    }
+    g_prof_pending.clear();
+}
+
 }  // namespace
+
+namespace jiffy {
+void prof_begin(const char* name, hipStream_t stream) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    if (!g_prof_on) return;
+    ProfEntry e{name, prof_event(), prof_event()};
+    if (e.start) (void)hipEventRecord(e.start, stream);
+    g_prof_pending.push_back(e);
+}
+void prof_end(hipStream_t stream) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    if (!g_prof_on || g_prof_pending.empty()) return;
+    ProfEntry& e = g_prof_pending.back();
+    if (e.stop) (void)hipEventRecord(e.stop, stream);
+}
+}  // namespace jiffy
 
 // ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
+
+int jiffy_profile_enable(int enable) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    g_prof_on = enable != 0;
+    if (g_prof_on) g_prof_totals.clear();
+    return JIFFY_OK;
+}
+
+int jiffy_profile_read(uint32_t max_kernels, char* names, double* total_ms, uint32_t* launches) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    const uint32_t n = (uint32_t)g_prof_totals.size();
+    for (uint32_t k = 0; k < n && k < max_kernels; ++k) {
+        if (names) memcpy(names + 32 * k, g_prof_totals[k].name, 32);
+        if (total_ms) total_ms[k] = g_prof_totals[k].ms;
+        if (launches) launches[k] = g_prof_totals[k].launches;
+    }
+    return (int)n;
+}
 
 const char* jiffy_status_string(int s) {
     switch (s) {
@@ -532,6 +621,7 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipMemcpyAsync(ctx.down.p, dev + o_err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    prof_collect();
     const uint32_t err = *(const uint32_t*)ctx.down.p;
     return err ? JIFFY_E_CORRUPT : JIFFY_OK;
 }

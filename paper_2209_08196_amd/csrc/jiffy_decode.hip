@@ -408,15 +408,15 @@ __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
 
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dec_parse, dim3(plan.n_items), dim3(256), 0, stream, plan);
-    hipLaunchKernelGGL(k_dec_mask, dim3(div_up(plan.nwords, 64), plan.n_attrs), dim3(64), 0, stream, plan);
-    hipLaunchKernelGGL(k_dec_scan, dim3(plan.n_items), dim3(1024), 0, stream, plan);
-    hipLaunchKernelGGL(k_dec_frames, dim3(plan.max_groups, plan.n_items), dim3(256), 0, stream, plan);
-    hipLaunchKernelGGL(k_dec_bscan, dim3(plan.n_items), dim3(1024), 0, stream, plan);
-    hipLaunchKernelGGL(k_dec_scatter, dim3(plan.n_tiles, plan.n_items), dim3(256), 0, stream, plan);
+    JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(plan.nwords, 64), plan.n_attrs), dim3(64), stream, plan);
+    JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
+    JIFFY_LAUNCH("k_dec_frames", k_dec_frames, dim3(plan.max_groups, plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_dec_bscan", k_dec_bscan, dim3(plan.n_items), dim3(1024), stream, plan);
+    JIFFY_LAUNCH("k_dec_scatter", k_dec_scatter, dim3(plan.n_tiles, plan.n_items), dim3(256), stream, plan);
     if (plan.need_temporal)
-        hipLaunchKernelGGL(k_dec_temporal, dim3(div_up(plan.npx, 256 * 16), plan.n_attrs), dim3(256), 0, stream,
-                           plan);
+        JIFFY_LAUNCH("k_dec_temporal", k_dec_temporal, dim3(div_up(plan.npx, 256 * 16), plan.n_attrs), dim3(256),
+                     stream, plan);
     return hipGetLastError();
 }
 

@@ -621,14 +621,14 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
 
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_enc_mask, dim3(plan.n_tiles), dim3(256), 0, stream, plan);
-    hipLaunchKernelGGL(k_enc_trial, dim3(plan.n_items), dim3(256), 0, stream, plan);
-    hipLaunchKernelGGL(k_enc_scan, dim3(plan.n_items), dim3(1024), 0, stream, plan);
-    hipLaunchKernelGGL(k_enc_frames, dim3(plan.max_groups, plan.n_items), dim3(256), 0, stream, plan);
-    hipLaunchKernelGGL(k_enc_mframe, dim3(plan.n_items), dim3(1024), 0, stream, plan);
-    hipLaunchKernelGGL(k_enc_sizes, dim3(plan.n_items), dim3(256), 0, stream, plan);
-    hipLaunchKernelGGL(k_enc_offsets, dim3(1), dim3(1024), 0, stream, plan);
-    hipLaunchKernelGGL(k_enc_assemble, dim3(plan.max_groups + 1, plan.n_items), dim3(256), 0, stream, plan);
+    JIFFY_LAUNCH("k_enc_mask", k_enc_mask, dim3(plan.n_tiles), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_trial", k_enc_trial, dim3(plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_scan", k_enc_scan, dim3(plan.n_items), dim3(1024), stream, plan);
+    JIFFY_LAUNCH("k_enc_frames", k_enc_frames, dim3(plan.max_groups, plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(1024), stream, plan);
+    JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_offsets", k_enc_offsets, dim3(1), dim3(1024), stream, plan);
+    JIFFY_LAUNCH("k_enc_assemble", k_enc_assemble, dim3(plan.max_groups + 1, plan.n_items), dim3(256), stream, plan);
     return hipGetLastError();
 }
 

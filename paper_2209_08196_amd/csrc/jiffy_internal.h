@@ -112,6 +112,17 @@ struct DecRes {
     uint32_t err, pad0;
 };
 
+// ---- kernel timing hooks (jiffy_api.hip) ----------------------------------
+void prof_begin(const char* name, hipStream_t stream);
+void prof_end(hipStream_t stream);
+
+#define JIFFY_LAUNCH(name, kern, grid, block, stream, ...)                 \
+    do {                                                                     \
+        ::jiffy::prof_begin(name, stream);                                   \
+        hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__);       \
+        ::jiffy::prof_end(stream);                                           \
+    } while (0)
+
 // ---- kernel launchers (defined in the .hip files) -------------------------
 struct EncPlan {
     const EncItem* items;     // device

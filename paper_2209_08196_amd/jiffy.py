@@ -21,7 +21,8 @@ OK, E_INVALID, E_CAPACITY, E_CORRUPT, E_DEVICE, E_SHAPE = 0, -1, -2, -3, -4, -5
 MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY = 0, 1, 2
 
 SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_peek", "jiffy_decode", "jiffy_status_string",
-           "jiffy_stream_create", "jiffy_batch_encode_step", "jiffy_stream_reset", "jiffy_stream_destroy")
+           "jiffy_stream_create", "jiffy_batch_encode_step", "jiffy_stream_reset", "jiffy_stream_destroy",
+           "jiffy_profile_enable", "jiffy_profile_read")
 
 
 class Layout(ctypes.Structure):
@@ -75,8 +76,30 @@ def lib():
         L.jiffy_stream_reset.argtypes = [vp]
         L.jiffy_stream_destroy.restype = None
         L.jiffy_stream_destroy.argtypes = [vp]
+        L.jiffy_profile_enable.restype = ctypes.c_int
+        L.jiffy_profile_enable.argtypes = [ctypes.c_int]
+        L.jiffy_profile_read.restype = ctypes.c_int
+        L.jiffy_profile_read.argtypes = [u32, vp, vp, vp]
         _lib = L
     return _lib
+
+
+def profile_enable(on: bool = True):
+    lib().jiffy_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """-> {kernel name: (total ms, launches)} since profile_enable(True)."""
+    n = lib().jiffy_profile_read(0, None, None, None)
+    names = ctypes.create_string_buffer(32 * max(n, 1))
+    ms = (ctypes.c_double * max(n, 1))()
+    cnt = (ctypes.c_uint32 * max(n, 1))()
+    n = lib().jiffy_profile_read(n, names, ms, cnt)
+    out = {}
+    for k in range(n):
+        nm = names.raw[32 * k:32 * k + 32].split(b"\0", 1)[0].decode()
+        out[nm] = (ms[k], cnt[k])
+    return out
 
 
 def _stream_handle(stream=None):
@@ -144,6 +167,28 @@ def peek(data: bytes):
 _TORCH_DT = {1: "uint8", 2: "int16", 4: "int32"}
 
 
+def _peek_device(stream_bytes):
+    """Layout and scan count of a device stream: copies the header and the
+    record-length table (the whole stream only when it has no table)."""
+    n = stream_bytes.numel()
+    head = stream_bytes[: min(n, 20)].cpu().numpy().tobytes()
+    if len(head) < 20:
+        raise JiffyError(E_CORRUPT, "jiffy_peek")
+    A = int.from_bytes(head[6:8], "little")
+    T = int.from_bytes(head[16:20], "little")
+    if T == 0:
+        return peek(stream_bytes.cpu().numpy().tobytes())
+    need = min(n, 20 + 8 * A + 4 * T * A)
+    blob = np.zeros(need, np.uint8)
+    blob[:need] = stream_bytes[:need].cpu().numpy()
+    # jiffy_peek reads only the header and the table when the table is present
+    lay, T2 = Layout(), ctypes.c_uint32()
+    rc = lib().jiffy_peek(blob.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(lay), ctypes.byref(T2))
+    if rc:
+        raise JiffyError(rc, "jiffy_peek")
+    return lay, T2.value
+
+
 def decode(stream_bytes, layout: Layout = None, n_scans: int = None, outs=None, stream=None):
     """stream_bytes: device uint8 tensor holding a whole stream.  layout /
     n_scans come from jiffy_peek of its header when not given.  Returns the
@@ -151,8 +196,7 @@ def decode(stream_bytes, layout: Layout = None, n_scans: int = None, outs=None, 
     32-bit attributes)."""
     import torch
     if layout is None or n_scans is None:
-        head = stream_bytes.cpu().numpy().tobytes()
-        layout, n_scans = peek(head)
+        layout, n_scans = _peek_device(stream_bytes)
     dev = stream_bytes.device
     if outs is None:
         outs = [torch.empty((n_scans, layout.height, layout.width), dtype=getattr(torch, _TORCH_DT[layout.width_bytes[a]]),

@@ -11,8 +11,8 @@ Scene model: H beams over a +-22.5 degree vertical field of view, W columns
 over 360 degrees of azimuth, sensor 1.8 m above a ground plane, 4-8 vertical
 walls enclosing the sensor at 8-60 m and 10-30 boxes at 5-60 m.  A scan is
 the scene's panorama seen at the sensor's yaw (whole-column rotation) with
-a first-order correction for a small translation, iid Gaussian range noise
-(sigma 20 mm) and zero blobs from a smooth random field fixed in world
+a first-order correction for a small translation, Gaussian range noise of
+about 20 mm (10 mm fixed per sensor pixel, 17 mm fresh every scan) and zero blobs from a smooth random field fixed in world
 azimuth, thresholded so that the zero fraction hits the configuration's
 target.  Attributes follow the surface and range:
   signal ~ Poisson(k * albedo / max(r_m, 1)^2), reflectivity = per-surface
@@ -28,7 +28,8 @@ import numpy as np
 MAX_RANGE_MM = 120_000  # OS1-like maximum range (Table I)
 MIN_RANGE_MM = 300
 SENSOR_HEIGHT_M = 1.8
-NOISE_MM = 20.0
+NOISE_STATIC_MM = 10.0   # fixed per sensor pixel (calibration bias)
+NOISE_TEMPORAL_MM = 17.0  # fresh every scan; about 20 mm in total
 
 _DTYPES = {"u8": np.uint8, "u16": np.uint16, "u32": np.uint32}
 
@@ -53,6 +54,7 @@ class Config:
     yaw_per_stream: bool  # draw one yaw step per stream (else per scan)
     cut_every: int  # new scene every n scans (0 = never)
     size_rule: str  # "first" | "mod" | "uniform"
+    stops: tuple = ()  # (first, end) scan ranges with the sensor standing still
 
 
 RANGE_P10 = Attr("range", "u32", 10)
@@ -63,7 +65,7 @@ CONFIGS = {
               "first"),
     2: Config(2, "dual-return-128x2048-5attr-1mm", 1, 100, ((128, 2048),),
               (RANGE_P1, Attr("range2", "u32", 1), Attr("signal", "u16", 1), Attr("reflectivity", "u8", 1),
-               Attr("nearir", "u16", 1)), 0.20, (0.5, 0.5), True, 0, "first"),
+               Attr("nearir", "u16", 1)), 0.20, (0.5, 0.5), True, 0, "first", ((30, 60),)),
     3: Config(3, "batched-64-streams-mixed-range-signal", 64, 50,
               ((16, 1024), (32, 2048), (64, 1024), (128, 2048)), (RANGE_P10, Attr("signal", "u16", 1)), 0.20,
               (0.0, 2.0), True, 0, "mod"),
@@ -191,6 +193,7 @@ class StreamGen:
         lo, hi = cfg.yaw_deg
         self._stream_yaw = float(rng.uniform(lo, hi))
         self._rng_seq = ss
+        self._static_noise = np.random.default_rng(ss.spawn(2)[1]).normal(0.0, NOISE_STATIC_MM, (self.H, self.W))
         self._scene_cache = {}
         self._pose_cache = None
 
@@ -221,11 +224,17 @@ class StreamGen:
             lo, hi = self.cfg.yaw_deg
             steps = np.full(m, self._stream_yaw) if self.cfg.yaw_per_stream else rng.uniform(lo, hi, m)
             steps[0] = 0.0
+            moving = np.ones(m)
+            for a, b in self.cfg.stops:  # stop-and-go: no motion inside a stop
+                moving[a:b] = 0.0
             cut = self.cfg.cut_every
             yaw = np.zeros(m)
+            tx = np.zeros(m)
             for t in range(1, m):
-                yaw[t] = 0.0 if (cut and t % cut == 0) else yaw[t - 1] + steps[t]
-            tx = np.array([0.05 * (t % cut if cut else t) for t in range(m)])
+                if cut and t % cut == 0:
+                    continue
+                yaw[t] = yaw[t - 1] + steps[t] * moving[t]
+                tx[t] = tx[t - 1] + 0.05 * moving[t]
             self._pose_cache = (yaw, tx)
         return self._pose_cache
 
@@ -239,7 +248,7 @@ class StreamGen:
         dx = roll(scene.dirs[0])
         r = roll(scene.range_mm).astype(np.float64)
         valid = (r > 0) & ~roll(scene.blob)
-        r = r - tx[t] * 1000.0 * dx + rng.normal(0.0, NOISE_MM, r.shape)
+        r = r - tx[t] * 1000.0 * dx + self._static_noise + rng.normal(0.0, NOISE_TEMPORAL_MM, r.shape)
         r = np.clip(np.rint(r), 1, MAX_RANGE_MM + 1000)
         rng_u32 = np.where(valid, r, 0).astype(np.uint32)
         sid = roll(scene.surface)
