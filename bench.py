@@ -174,6 +174,9 @@ def main():
     value = points / (wall / args.steps)
     print(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
 
+    if args.profile_steps <= 0:  # counter-collection runs: the kernels only
+        print(json.dumps({"metric": METRIC, "ms_per_step": round(ms_per_step, 3)}), flush=True)
+        return
     # per-kernel times with HIP events on the launch stream
     jiffy.profile_enable(True)
     for _ in range(args.profile_steps):

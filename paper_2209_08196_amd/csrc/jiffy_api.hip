@@ -564,7 +564,8 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     const size_t o_err = off; off = al(off + sizeof(uint32_t));
     const size_t o_items = off; off = al(off + sizeof(DecItem) * n);
     const size_t up_end = off;
-    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * nwords) + al(4ull * maxnb * 5) + al(4ull * npx);
+    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 6);
+    const size_t o_modes = off; off = al(off + n);
     const size_t o_data = off;
     off += per_item * n;
     if (grow(ctx.ws, off) != hipSuccess) return JIFFY_E_DEVICE;
@@ -586,12 +587,10 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
             it.out = (uint8_t*)d_planes_out[a] + t * step;
             it.cw = (uint64_t*)base; base += al(8ull * nwords);
             it.vw = (uint64_t*)base; base += al(8ull * nwords);
-            it.wpre = (uint32_t*)base; base += al(4ull * nwords);
             it.blkinfo = (uint32_t*)base;
             it.blkoffs = it.blkinfo + maxnb;
             it.bsum = it.blkinfo + 4 * maxnb;
-            base += al(4ull * maxnb * 5);
-            it.sbuf = (uint32_t*)base;
+            it.blklast = it.blkinfo + 5 * maxnb;
             it.npx = npx;
             it.nwords = nwords;
             it.wb = L.width_bytes[a];
@@ -617,6 +616,16 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     plan.max_groups = div_up(maxnb, kGroupFrames);
     plan.n_tiles = div_up(npx, kTilePx);
     plan.need_temporal = need_temporal ? 1u : 0u;
+    plan.modes = dev + o_modes;
+    plan.ws = dev + o_data;
+    plan.item_stride = per_item;
+    plan.off_cw = 0;
+    plan.off_vw = (uint32_t)al(8ull * nwords);
+    for (uint32_t a = 0; a < A; ++a) {
+        plan.out_base[a] = d_planes_out[a];
+        plan.attr_wb[a] = L.width_bytes[a];
+        plan.attr_P[a] = L.precision[a];
+    }
     if (launch_decode(plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipMemcpyAsync(ctx.down.p, dev + o_err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;

@@ -132,20 +132,39 @@ __device__ __forceinline__ uint32_t unzigzag(uint32_t z, uint32_t bits) {
 // Frame-width choice for 128 values held two per lane (Sec. II):
 // B = width of the maximum; n(b) = values >= 2^b;
 // cost(b) = 16 b + [n > 0] (n + ceil(n (B - b) / 8)); ties go to the larger b.
+// A histogram of the values' bit widths (in the wave's 40 words of LDS
+// `hist`) gives n(b) for every b at once: lane b evaluates cost(b) and a
+// wave minimum picks the width.  Called by a whole wave.
 struct FrameChoice {
     uint32_t b, n, B, cost;
 };
-__device__ __forceinline__ FrameChoice choose_frame(uint32_t z0, uint32_t z1) {
-    uint32_t mx = wave_max(max(z0, z1));
-    uint32_t B = mx ? 32u - __clz(mx) : 0u;
-    FrameChoice best{0, 0, B, 0xFFFFFFFFu};
-    for (uint32_t b = 0; b <= B; ++b) {
-        uint32_t n = 0;
-        if (b < 32) n = __popcll(ballot((z0 >> b) != 0)) + __popcll(ballot((z1 >> b) != 0));
-        uint32_t cost = 16u * b + (n ? n + (n * (B - b) + 7u) / 8u : 0u);
-        if (cost <= best.cost) best = FrameChoice{b, n, B, cost};
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ FrameChoice choose_frame(uint32_t z0, uint32_t z1, uint32_t* hist) {
+    const uint32_t l = lane_id();
+    if (l < 40) hist[l] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t w0 = z0 ? 32u - __clz(z0) : 0u;
+    const uint32_t w1 = z1 ? 32u - __clz(z1) : 0u;
+    atomicAdd(&hist[w0], 1u);
+    atomicAdd(&hist[w1], 1u);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t h = l <= 32 ? hist[l] : 0u;
+    const uint32_t n = 128u - wave_incl_scan(h);  // values wider than l bits
+    const uint32_t B = wave_max(max(w0, w1));
+    uint32_t key = 0xFFFFFFFFu;
+    if (l <= B) {
+        const uint32_t cost = 16u * l + (n ? n + (n * (B - l) + 7u) / 8u : 0u);
+        key = (cost << 6) | (63u - l);
     }
-    return best;
+    key = wave_min(key);
+    const uint32_t b = 63u - (key & 63u);
+    const uint32_t nb = (uint32_t)__shfl((int)n, (int)b, kWave);
+    __builtin_amdgcn_wave_barrier();
+    return FrameChoice{b, nb, B, key >> 6};
 }
 
 // ---- 16-sample vector access -------------------------------------------

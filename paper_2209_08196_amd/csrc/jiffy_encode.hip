@@ -66,13 +66,14 @@ __device__ __forceinline__ uint32_t sample_at(const void* base, uint32_t wb, uin
 
 // packed size of one frame of values s[0..real) with predecessor `pred`;
 // called by one whole wave
-__device__ __forceinline__ uint32_t frame_cost_lds(const uint32_t* s, uint32_t real, uint32_t pred, uint32_t bits) {
+__device__ __forceinline__ uint32_t frame_cost_lds(const uint32_t* s, uint32_t real, uint32_t pred, uint32_t bits,
+                                                   uint32_t* hist) {
     const uint32_t l = lane_id();
     const uint32_t m = low_mask32(bits);
     uint32_t z0 = 0, z1 = 0;
     if (l < real) z0 = zigzag((s[l] - (l ? s[l - 1] : pred)) & m, bits);
     if (l + 64 < real) z1 = zigzag((s[l + 64] - s[l + 63]) & m, bits);
-    return choose_frame(z0, z1).cost;
+    return choose_frame(z0, z1, hist).cost;
 }
 
 __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
     }
     __shared__ uint32_t su[384], sv[384];
     __shared__ uint32_t scratch[8];
+    __shared__ uint32_t hist[40];
     __shared__ uint64_t s_cost[2];
     __shared__ uint32_t s_pred[2];
     const uint32_t tid = threadIdx.x, wave = tid / kWave;
@@ -116,8 +118,8 @@ __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
             cnt += total;
             while (cnt >= 128) {
                 if (wave == 0) {
-                    uint32_t ci = frame_cost_lds(su, 128, s_pred[0], it.bits);
-                    uint32_t cp = frame_cost_lds(sv, 128, s_pred[1], it.bits);
+                    uint32_t ci = frame_cost_lds(su, 128, s_pred[0], it.bits, hist);
+                    uint32_t cp = frame_cost_lds(sv, 128, s_pred[1], it.bits, hist);
                     if (lane_id() == 0) { s_cost[0] += ci; s_cost[1] += cp; }
                 }
                 __syncthreads();
@@ -134,8 +136,8 @@ __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
         }
     }
     if (cnt > 0 && wave == 0) {
-        uint32_t ci = frame_cost_lds(su, cnt, s_pred[0], it.bits);
-        uint32_t cp = frame_cost_lds(sv, cnt, s_pred[1], it.bits);
+        uint32_t ci = frame_cost_lds(su, cnt, s_pred[0], it.bits, hist);
+        uint32_t cp = frame_cost_lds(sv, cnt, s_pred[1], it.bits, hist);
         if (lane_id() == 0) { s_cost[0] += ci; s_cost[1] += cp; }
     }
     __syncthreads();
@@ -194,6 +196,7 @@ struct FramesLds {
     uint32_t scratch[8];
     uint32_t pw[4][128];
     uint32_t hw[4][128];
+    uint32_t hist[4][40];
 };
 
 template <int WB>
@@ -253,7 +256,7 @@ __device__ __forceinline__ void enc_frames_body(const EncPlan& plan, const EncIt
         uint32_t z0 = 0, z1 = 0;
         if (i0 < real) z0 = zigzag((sv[1 + k0 + i0] - sv[k0 + i0]) & m, it.bits);
         if (i1 < real) z1 = zigzag((sv[1 + k0 + i1] - sv[k0 + i1]) & m, it.bits);
-        const FrameChoice fc = choose_frame(z0, z1);
+        const FrameChoice fc = choose_frame(z0, z1, L.hist[wave]);
         const uint32_t b = fc.b, hwid = fc.B - fc.b;
         pw[wave][l] = 0; pw[wave][l + 64] = 0;
         hw[wave][l] = 0; hw[wave][l + 64] = 0;
@@ -321,101 +324,102 @@ __global__ __launch_bounds__(256) void k_enc_frames(EncPlan plan) {
 // equal bytes become RLE blocks, the stretches between them Raw blocks,
 // each split at 128 KiB (RFC 8878 frame, single segment, no checksum).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t content_byte(const EncItem& it, uint32_t mode, uint32_t i) {
-    const uint32_t w = i >> 3;
+__device__ __forceinline__ uint64_t content_word(const EncItem& it, uint32_t mode, uint32_t w) {
     const uint64_t tm = tail_mask(w, it.nwords, it.npx);
     uint64_t mk = ~it.vw[w] & tm;
     if (mode) mk ^= ~it.vwprev[w] & tm;
-    return (uint32_t)(mk >> (8 * (i & 7))) & 0xFFu;
+    return mk;
+}
+__device__ __forceinline__ uint32_t content_byte(const EncItem& it, uint32_t mode, uint32_t i) {
+    return (uint32_t)(content_word(it, mode, i >> 3) >> (8 * (i & 7))) & 0xFFu;
 }
 
-struct SegScan {
-    uint32_t is_long[4];
-    uint32_t start[4];
+// Run classification of content bytes [b0, b0 + 32): bit k of `lng` is set
+// when byte b0 + k lies in a run of >= kRleMinRun equal bytes; bit k of
+// `start` when a segment (an RLE run or a raw stretch) begins there.
+// Works on a 64-byte window [b0 - 16, b0 + 48) held in eight words.
+struct RunBits {
+    uint32_t lng, start;
+    uint64_t win[8];
 };
-
-// classifies the 4 content bytes of this thread: long-run membership and
-// segment starts.  `lds` holds content bytes [c0 - 8, c0 + 4096 + 8) (0x100
-// marks a position outside the content).
-__device__ __forceinline__ void classify4(const uint16_t* lds, uint32_t c0, uint32_t nm, SegScan& out) {
-    auto at = [&](int i) -> uint32_t { return lds[i - (int)c0 + 8]; };
-    auto is_long = [&](int i) -> uint32_t {
-        const uint32_t b = at(i);
-        int left = 0, right = 0;
-        for (int k = 1; k <= 7; ++k) { if (at(i - k) == b) left++; else break; }
-        for (int k = 1; k <= 7; ++k) { if (at(i + k) == b) right++; else break; }
-        return (left + right + 1 >= (int)kRleMinRun) ? 1u : 0u;
-    };
-    for (int k = 0; k < 4; ++k) {
-        const int i = (int)c0 + 4 * (int)threadIdx.x + k;
-        out.is_long[k] = 0;
-        out.start[k] = 0;
-        if ((uint32_t)i >= nm) continue;
-        const uint32_t L = is_long(i);
-        out.is_long[k] = L;
-        if (i == 0) { out.start[k] = 1; continue; }
-        const uint32_t Lp = is_long(i - 1);
-        out.start[k] = (L != Lp) || (L && at(i) != at(i - 1));
+__device__ __forceinline__ void classify32(const EncItem& it, uint32_t mode, uint32_t nm, uint32_t b0, RunBits& R) {
+    const int w0 = (int)(b0 >> 3) - 2;  // b0 is a multiple of 32
+    for (int k = 0; k < 8; ++k) {
+        const int w = w0 + k;
+        R.win[k] = (w >= 0 && (uint32_t)w < it.nwords && 8u * (uint32_t)w < nm) ? content_word(it, mode, w) : 0ull;
     }
+    // eq bit k: byte (b0 - 16 + k) equals the byte before it (both inside the content)
+    uint64_t eq = 0;
+    uint32_t prev = 0x200u;
+    for (int k = 0; k < 64; ++k) {
+        const int i = (int)b0 - 16 + k;
+        const uint32_t c = (i >= 0 && (uint32_t)i < nm) ? (uint32_t)(R.win[k >> 3] >> (8 * (k & 7))) & 0xFFu
+                                                       : 0x100u + (uint32_t)k;  // never equal to a neighbour
+        eq |= (uint64_t)(c == prev) << k;
+        prev = c;
+    }
+    // e8 bit k: bytes k .. k+7 all equal; lng bit k: some such window covers k
+    uint64_t e8 = ~0ull;
+    for (int d = 1; d < (int)kRleMinRun; ++d) e8 &= eq >> d;
+    e8 &= ~0ull >> (kRleMinRun - 1);  // windows that leave the 64-byte view are unknown: not long
+    uint64_t lng = 0;
+    for (int d = 0; d < (int)kRleMinRun; ++d) lng |= e8 << d;
+    // bytes b0-1 .. b0+31 are window bits 15 .. 47
+    const uint64_t cur = lng >> 16, prv = lng >> 15, neq = ~(eq >> 16);
+    uint64_t st = ((cur ^ prv) | (cur & neq)) & 0xFFFFFFFFull;
+    if (b0 == 0) st |= 1ull;
+    uint32_t valid = nm > b0 ? (nm - b0 >= 32 ? 0xFFFFFFFFu : ((1u << (nm - b0)) - 1u)) : 0u;
+    R.lng = (uint32_t)cur & valid;
+    R.start = (uint32_t)st & valid;
 }
 
-__device__ __forceinline__ void stage_content(const EncItem& it, uint32_t mode, uint16_t* lds, uint32_t c0,
-                                              uint32_t nm) {
-    for (uint32_t k = threadIdx.x; k < 4096 + 16; k += 1024) {
-        const int i = (int)c0 - 8 + (int)k;
-        lds[k] = (i >= 0 && (uint32_t)i < nm) ? (uint16_t)content_byte(it, mode, (uint32_t)i) : (uint16_t)0x100;
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_enc_mframe(EncPlan plan) {
+__global__ __launch_bounds__(256) void k_enc_mframe(EncPlan plan) {
     const uint32_t r = blockIdx.x;
     const EncItem it = plan.items[r];
     const uint32_t mode = plan.res[r].mode;
     const uint32_t nm = div_up(it.npx, 8);
-    __shared__ uint16_t lds[4096 + 16];
-    __shared__ uint32_t scratch[20];
+    __shared__ uint32_t scratch[8];
     const uint32_t hdr = nm <= 255 ? 6u : nm <= 65791 ? 7u : 9u;
+    const uint32_t tid = threadIdx.x;
+    constexpr uint32_t kStep = 256 * 32;
 
     // pass 1: segment starts
     uint32_t nseg = 0;
-    for (uint32_t c0 = 0; c0 < nm; c0 += 4096) {
-        stage_content(it, mode, lds, c0, nm);
-        __syncthreads();
-        SegScan sc;
-        classify4(lds, c0, nm, sc);
-        const uint32_t cnt = sc.start[0] + sc.start[1] + sc.start[2] + sc.start[3];
+    for (uint32_t c0 = 0; c0 < nm; c0 += kStep) {
+        const uint32_t b0 = c0 + 32 * tid;
+        RunBits R;
+        classify32(it, mode, nm, b0, R);
         uint32_t total;
-        uint32_t sid = block_excl_scan<1024>(cnt, scratch, &total) + nseg;
-        for (int k = 0; k < 4; ++k)
-            if (sc.start[k]) it.segs[sid++] = (c0 + 4 * threadIdx.x + k) | (sc.is_long[k] << 31);
+        uint32_t sid = block_excl_scan<256>(__popc(R.start), scratch, &total) + nseg;
+        for (uint32_t m = R.start; m; m &= m - 1) {
+            const uint32_t k = __ffs(m) - 1;
+            it.segs[sid++] = (b0 + k) | (((R.lng >> k) & 1u) << 31);
+        }
         nseg += total;
-        __syncthreads();
     }
-    __threadfence_block();
     __syncthreads();
     // pass 2: encoded sizes and offsets of the segments
     uint32_t off_carry = hdr;
-    for (uint32_t s0 = 0; s0 < nseg; s0 += 1024) {
-        const uint32_t s = s0 + threadIdx.x;
+    for (uint32_t s0 = 0; s0 < nseg; s0 += 256) {
+        const uint32_t sg = s0 + tid;
         uint32_t size = 0;
-        if (s < nseg) {
-            const uint32_t a = it.segs[s];
+        if (sg < nseg) {
+            const uint32_t a = it.segs[sg];
             const uint32_t start = a & 0x7FFFFFFFu;
-            const uint32_t end = (s + 1 < nseg) ? (it.segs[s + 1] & 0x7FFFFFFFu) : nm;
+            const uint32_t end = (sg + 1 < nseg) ? (it.segs[sg + 1] & 0x7FFFFFFFu) : nm;
             const uint32_t len = end - start;
             const uint32_t nblk = div_up(len, kZstdBlockMax);
             size = (a >> 31) ? 4u * nblk : 3u * nblk + len;
         }
         uint32_t total;
-        const uint32_t off = block_excl_scan<1024>(size, scratch, &total) + off_carry;
-        if (s < nseg) it.segoff[s] = off;
+        const uint32_t off = block_excl_scan<256>(size, scratch, &total) + off_carry;
+        if (sg < nseg) it.segoff[sg] = off;
         off_carry += total;
     }
-    __threadfence_block();
     __syncthreads();
     // pass 3: write the frame
     uint8_t* f = it.frame;
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         f[0] = 0x28; f[1] = 0xB5; f[2] = 0x2F; f[3] = 0xFD;
         if (nm <= 255) { f[4] = 0x20; f[5] = (uint8_t)nm; }
         else if (nm <= 65791) { f[4] = 0x60; f[5] = (uint8_t)(nm - 256); f[6] = (uint8_t)((nm - 256) >> 8); }
@@ -424,17 +428,17 @@ __global__ __launch_bounds__(1024) void k_enc_mframe(EncPlan plan) {
         plan.res[r].nseg = nseg;
     }
     // block headers (and the byte of each RLE block)
-    for (uint32_t s = threadIdx.x; s < nseg; s += 1024) {
-        const uint32_t a = it.segs[s];
+    for (uint32_t sg = tid; sg < nseg; sg += 256) {
+        const uint32_t a = it.segs[sg];
         const uint32_t start = a & 0x7FFFFFFFu;
-        const uint32_t end = (s + 1 < nseg) ? (it.segs[s + 1] & 0x7FFFFFFFu) : nm;
+        const uint32_t end = (sg + 1 < nseg) ? (it.segs[sg + 1] & 0x7FFFFFFFu) : nm;
         const uint32_t len = end - start;
         const uint32_t nblk = div_up(len, kZstdBlockMax);
         const uint32_t is_rle = a >> 31;
-        uint32_t o = it.segoff[s];
+        uint32_t o = it.segoff[sg];
         for (uint32_t q = 0; q < nblk; ++q) {
             const uint32_t blen = min(kZstdBlockMax, len - q * kZstdBlockMax);
-            const uint32_t last = (s + 1 == nseg && q + 1 == nblk) ? 1u : 0u;
+            const uint32_t last = (sg + 1 == nseg && q + 1 == nblk) ? 1u : 0u;
             const uint32_t h = last | (is_rle << 1) | (blen << 3);
             f[o] = (uint8_t)h; f[o + 1] = (uint8_t)(h >> 8); f[o + 2] = (uint8_t)(h >> 16);
             if (is_rle) {
@@ -445,28 +449,29 @@ __global__ __launch_bounds__(1024) void k_enc_mframe(EncPlan plan) {
             }
         }
     }
-    // raw bytes: recompute the segment of every byte
+    // raw bytes: the segment of every byte from the same classification
     uint32_t seg_carry = 0;
-    for (uint32_t c0 = 0; c0 < nm; c0 += 4096) {
-        stage_content(it, mode, lds, c0, nm);
-        __syncthreads();
-        SegScan sc;
-        classify4(lds, c0, nm, sc);
-        const uint32_t cnt = sc.start[0] + sc.start[1] + sc.start[2] + sc.start[3];
+    for (uint32_t c0 = 0; c0 < nm; c0 += kStep) {
+        const uint32_t b0 = c0 + 32 * tid;
+        RunBits R;
+        classify32(it, mode, nm, b0, R);
         uint32_t total;
-        uint32_t sid = block_excl_scan<1024>(cnt, scratch, &total) + seg_carry;  // segments started before
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t i = c0 + 4 * threadIdx.x + k;
-            if (i >= nm) break;
-            if (sc.start[k]) sid++;
-            if (sc.is_long[k]) continue;
-            const uint32_t sg = sid - 1;
-            const uint32_t start = it.segs[sg] & 0x7FFFFFFFu;
-            const uint32_t q = (i - start) / kZstdBlockMax;
-            f[it.segoff[sg] + 3u * (q + 1u) + (i - start)] = (uint8_t)lds[i - c0 + 8];
+        uint32_t sid = block_excl_scan<256>(__popc(R.start), scratch, &total) + seg_carry;
+        const uint32_t nvalid = nm > b0 ? min(32u, nm - b0) : 0u;
+        uint32_t sg = sid ? sid - 1 : 0, sstart = 0, soff = 0;
+        if (sid) { sstart = it.segs[sg] & 0x7FFFFFFFu; soff = it.segoff[sg]; }
+        for (uint32_t k = 0; k < nvalid; ++k) {
+            if ((R.start >> k) & 1u) {
+                sg = sid++;
+                sstart = b0 + k;
+                soff = it.segoff[sg];
+            }
+            if ((R.lng >> k) & 1u) continue;
+            const uint32_t i = b0 + k;
+            const uint32_t q = (i - sstart) / kZstdBlockMax;
+            f[soff + 3u * (q + 1u) + (i - sstart)] = (uint8_t)(R.win[2 + (k >> 3)] >> (8 * (k & 7)));
         }
         seg_carry += total;
-        __syncthreads();
     }
 }
 
@@ -569,7 +574,13 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
             h[2] = rs.flen;
             *(uint32_t*)(rec + sec) = rs.N;
         }
-        for (uint32_t k = tid; k < rs.flen; k += 256) rec[12 + k] = it.frame[k];
+        {
+            const uint32_t nw = rs.flen / 4;
+            const uint32_t* fw = (const uint32_t*)it.frame;  // staging and record are word aligned
+            uint32_t* dw = (uint32_t*)(rec + 12);
+            for (uint32_t k = tid; k < nw; k += 256) dw[k] = fw[k];
+            for (uint32_t k = 4 * nw + tid; k < rs.flen; k += 256) rec[12 + k] = it.frame[k];
+        }
         for (uint32_t k = 12 + rs.flen + tid; k < sec; k += 256) rec[k] = 0;
         for (uint32_t j = tid; j < rs.nb; j += 256) {
             const uint32_t info = it.blkinfo[j];
@@ -601,21 +612,61 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
     }
     const uint32_t j0 = (blockIdx.x - 1) * kGroupFrames;
     if (j0 >= rs.nb) return;
-    const uint32_t j1 = min(j0 + kGroupFrames, rs.nb);
-    const uint32_t wave = tid / kWave, l = lane_id();
-    for (uint32_t j = j0 + wave; j < j1; j += 4) {
-        const uint32_t info = it.blkinfo[j];
-        const uint32_t b = info & 0xFF, n = (info >> 8) & 0xFF, B = (info >> 16) & 0xFF;
-        const uint32_t hb = (n * (B - b) + 7) / 8;
-        const uint8_t* slot = it.slots + (size_t)j * kSlotBytes;
-        const uint32_t* sw = (const uint32_t*)slot;
-        uint32_t* dp = (uint32_t*)(rec + pay0 + it.blkoffs[3 * j]);
-        if (l < 4 * b) dp[l] = sw[l];
-        if (l + 64 < 4 * b) dp[l + 64] = sw[l + 64];
-        uint8_t* pp = rec + pos0 + it.blkoffs[3 * j + 1];
-        for (uint32_t k = l; k < n; k += 64) pp[k] = slot[16 * b + k];
-        uint8_t* hp = rec + high0 + it.blkoffs[3 * j + 2];
-        for (uint32_t k = l; k < hb; k += 64) hp[k] = slot[16 * b + n + k];
+    const uint32_t j1 = min(j0 + kGroupFrames, rs.nb), cnt = j1 - j0;
+    // the group's frames land in three contiguous ranges (payloads,
+    // positions, high parts); each thread copies words or bytes of them
+    __shared__ uint32_t offs[3][kGroupFrames + 1];
+    __shared__ uint32_t bwid[kGroupFrames], nexc[kGroupFrames];
+    if (tid <= cnt) {
+        const uint32_t j = j0 + tid;
+        if (j < rs.nb) {
+            offs[0][tid] = it.blkoffs[3 * j];
+            offs[1][tid] = it.blkoffs[3 * j + 1];
+            offs[2][tid] = it.blkoffs[3 * j + 2];
+        } else {
+            offs[0][tid] = rs.pay;
+            offs[1][tid] = rs.pos;
+            offs[2][tid] = rs.high;
+        }
+        if (tid < cnt) {
+            const uint32_t info = it.blkinfo[j];
+            bwid[tid] = info & 0xFF;
+            nexc[tid] = (info >> 8) & 0xFF;
+        }
+    }
+    __syncthreads();
+    auto frame_of = [&](const uint32_t* o, uint32_t x) -> uint32_t {  // last k with o[k] <= x
+        uint32_t lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (o[mid] <= x) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    };
+    {   // payload words (all ranges word aligned)
+        uint32_t* dst = (uint32_t*)(rec + pay0);
+        const uint32_t a = offs[0][0] >> 2, z = offs[0][cnt] >> 2;
+        for (uint32_t w = a + tid; w < z; w += 256) {
+            const uint32_t k = frame_of(offs[0], 4 * w);
+            const uint32_t* sw = (const uint32_t*)(it.slots + (size_t)(j0 + k) * kSlotBytes);
+            dst[w] = sw[w - (offs[0][k] >> 2)];
+        }
+    }
+    {   // exception positions
+        const uint32_t a = offs[1][0], z = offs[1][cnt];
+        for (uint32_t q = a + tid; q < z; q += 256) {
+            const uint32_t k = frame_of(offs[1], q);
+            const uint8_t* slot = it.slots + (size_t)(j0 + k) * kSlotBytes;
+            rec[pos0 + q] = slot[16 * bwid[k] + (q - offs[1][k])];
+        }
+    }
+    {   // exception high parts
+        const uint32_t a = offs[2][0], z = offs[2][cnt];
+        for (uint32_t q = a + tid; q < z; q += 256) {
+            const uint32_t k = frame_of(offs[2], q);
+            const uint8_t* slot = it.slots + (size_t)(j0 + k) * kSlotBytes;
+            rec[high0 + q] = slot[16 * bwid[k] + nexc[k] + (q - offs[2][k])];
+        }
     }
 }
 
@@ -625,7 +676,7 @@ hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_enc_trial", k_enc_trial, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_scan", k_enc_scan, dim3(plan.n_items), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_enc_frames", k_enc_frames, dim3(plan.max_groups, plan.n_items), dim3(256), stream, plan);
-    JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(1024), stream, plan);
+    JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_offsets", k_enc_offsets, dim3(1), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_enc_assemble", k_enc_assemble, dim3(plan.max_groups + 1, plan.n_items), dim3(256), stream, plan);

@@ -96,11 +96,10 @@ struct DecItem {
     void* out;                // [npx] output samples
     uint64_t* cw;             // unframed mask content (XOR form for a P-scan)
     uint64_t* vw;             // valid-sample words
-    uint32_t* wpre;           // [nwords] exclusive prefix of valid counts
     uint32_t* blkinfo;        // [maxnb]
     uint32_t* blkoffs;        // [3 * maxnb]
     uint32_t* bsum;           // [maxnb] frame sums, then exclusive prefixes
-    uint32_t* sbuf;           // [npx] running sums inside each frame
+    uint32_t* blklast;        // [maxnb] pixel of each frame's last value
     uint32_t npx, nwords, wb, bits;
     uint32_t attr, t, P, maxnb;
     uint32_t aligned16, pad0;
@@ -109,7 +108,7 @@ struct DecItem {
 struct DecRes {
     uint32_t mode, flen, N, nb;
     uint32_t sec, pay_off, pos_off, high_off;
-    uint32_t err, pad0;
+    uint32_t high_end, err;
 };
 
 // ---- kernel timing hooks (jiffy_api.hip) ----------------------------------
@@ -140,10 +139,16 @@ struct DecPlan {
     const DecItem* items;
     DecRes* res;
     uint32_t* err;
+    uint8_t* modes;           // [n_items] 0 = I, 1 = P (written by the parse)
+    uint8_t* ws;              // per-record workspace, item_stride bytes each
+    uint64_t item_stride;
+    uint32_t off_cw, off_vw;  // offsets of the mask words inside a record's workspace
     uint32_t n_items, n_scans, n_attrs;
     uint32_t nwords, npx, max_groups;
     uint32_t n_tiles;
     uint32_t need_temporal;   // per-pixel pass over time needed
+    void* out_base[8];        // attribute planes
+    uint32_t attr_wb[8], attr_P[8];
 };
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream);
 
