@@ -113,12 +113,14 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
                EncResult& result) {
     const uint32_t n = (uint32_t)specs.size(), no = (uint32_t)outs.size();
     // layout of the device workspace: [res][err][outs][items][tile_first][tile_item] then per item
-    uint32_t n_tiles = 0, max_groups = 1;
-    std::vector<uint32_t> tile_first(n);
+    uint32_t n_tiles = 0, n_ftiles = 0, max_groups = 1;
+    std::vector<uint32_t> tile_first(n), ftile_first(n);
     for (uint32_t r = 0; r < n; ++r) {
         tile_first[r] = n_tiles;
+        ftile_first[r] = n_ftiles;
         const uint32_t npx = specs[r].H * specs[r].W;
         n_tiles += div_up(npx, kTilePx);
+        n_ftiles += div_up(npx, kFTile);
         const uint32_t groups = div_up(div_up(npx, kFrame), kGroupFrames);
         if (groups > max_groups) max_groups = groups;
     }
@@ -129,13 +131,15 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
     const size_t o_items = off; off = al(off + sizeof(EncItem) * n);
     const size_t o_tfirst = off; off = al(off + sizeof(uint32_t) * n);
     const size_t o_titem = off; off = al(off + sizeof(uint32_t) * n_tiles);
+    const size_t o_ftfirst = off; off = al(off + sizeof(uint32_t) * n);
+    const size_t o_ftitem = off; off = al(off + sizeof(uint32_t) * n_ftiles);
     const size_t up_end = off;
     std::vector<size_t> o_vw(n), o_blk(n), o_slots(n), o_frame(n), o_segs(n);
     for (uint32_t r = 0; r < n; ++r) {
         const uint32_t npx = specs[r].H * specs[r].W;
         const uint32_t nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame), nm = div_up(npx, 8);
         o_vw[r] = off; off = al(off + (specs[r].vw_fixed ? 0 : 8ull * nwords));
-        o_blk[r] = off; off = al(off + 4ull * maxnb * 6);
+        o_blk[r] = off; off = al(off + 4ull * maxnb * 4 + 12ull * div_up(npx, kFTile));
         o_slots[r] = off; off = al(off + (size_t)kSlotBytes * maxnb);
         o_frame[r] = off; off = al(off + frame_bound(nm));
         o_segs[r] = off; off = al(off + 8ull * (nm / 4 + 4));
@@ -182,10 +186,13 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
         else it.vwprev = nullptr;
         const uint32_t maxnb = div_up(npx, kFrame), nm = div_up(npx, 8);
         uint32_t* blk = (uint32_t*)(dev + o_blk[r]);
-        it.blkstart = blk;
-        it.blklast = blk + maxnb;
-        it.blkinfo = blk + 2 * maxnb;
-        it.blkoffs = blk + 3 * maxnb;
+        const uint32_t nft = div_up(npx, kFTile);
+        it.blkinfo = blk;
+        it.blkoffs = blk + maxnb;
+        it.tbase = blk + 4 * maxnb;
+        it.tpred = it.tbase + nft;
+        it.tfix = it.tpred + nft;
+        it.ntiles = nft;
         it.slots = dev + o_slots[r];
         it.frame = dev + o_frame[r];
         it.seg_cap = nm / 4 + 4;
@@ -217,6 +224,13 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
         const uint32_t nt = div_up(specs[r].H * specs[r].W, kTilePx);
         for (uint32_t k = 0; k < nt; ++k) hti[tile_first[r] + k] = r;
     }
+    uint32_t* hftf = (uint32_t*)U(o_ftfirst);
+    uint32_t* hfti = (uint32_t*)U(o_ftitem);
+    for (uint32_t r = 0; r < n; ++r) {
+        hftf[r] = ftile_first[r];
+        const uint32_t nt = div_up(specs[r].H * specs[r].W, kFTile);
+        for (uint32_t k = 0; k < nt; ++k) hfti[ftile_first[r] + k] = r;
+    }
     if (hipMemcpyAsync(dev + o_err, up, up_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
         return JIFFY_E_DEVICE;
 
@@ -227,6 +241,9 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
     plan.err = (uint32_t*)(dev + o_err);
     plan.tile_item = (const uint32_t*)(dev + o_titem);
     plan.tile_first = (const uint32_t*)(dev + o_tfirst);
+    plan.ftile_item = (const uint32_t*)(dev + o_ftitem);
+    plan.ftile_first = (const uint32_t*)(dev + o_ftfirst);
+    plan.n_ftiles = n_ftiles;
     plan.n_items = n;
     plan.n_outs = no;
     plan.n_tiles = n_tiles;

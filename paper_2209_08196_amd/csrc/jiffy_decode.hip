@@ -16,6 +16,7 @@
 //
 // Every offset read from the stream is checked before it is used; a
 // malformed stream raises kErrCorrupt and later kernels do nothing.
+#define JIFFY_KERNEL_TU 1
 #include "jiffy_device.h"
 
 namespace jiffy {

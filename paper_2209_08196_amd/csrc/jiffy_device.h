@@ -14,25 +14,38 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
 }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
-    return v;
+// Cross-lane moves through DPP (no LDS): row_shr:n moves within rows of 16
+// lanes, row_bcast:15 / :31 carry a row's last lane into the next rows.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, false);
 }
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, kWave);
+template <class Op>
+__device__ __forceinline__ uint32_t wave_incl_op(uint32_t v, Op op) {
+    const uint32_t l = lane_id(), rl = l & 15u;
+    uint32_t t;
+    t = dpp_mov<0x111>(v); if (rl >= 1) v = op(v, t);
+    t = dpp_mov<0x112>(v); if (rl >= 2) v = op(v, t);
+    t = dpp_mov<0x114>(v); if (rl >= 4) v = op(v, t);
+    t = dpp_mov<0x118>(v); if (rl >= 8) v = op(v, t);
+    t = dpp_mov<0x142>(v); if ((l & 31u) >= 16) v = op(v, t);
+    t = dpp_mov<0x143>(v); if (l >= 32) v = op(v, t);
     return v;
 }
 // inclusive prefix sum over the wave (wrapping u32)
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const uint32_t l = lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t t = (uint32_t)__shfl_up((int)v, o, kWave);
-        if (l >= (uint32_t)o) v += t;
-    }
-    return v;
+    return wave_incl_op(v, [](uint32_t a, uint32_t b) { return a + b; });
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+    v = wave_incl_op(v, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = wave_incl_op(v, [](uint32_t a, uint32_t b) { return a < b ? a : b; });
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
 }
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
     const uint32_t l = lane_id();
@@ -87,6 +100,32 @@ __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v, uint64_t* scra
     return r;
 }
 
+// Exclusive running maximum over a workgroup (same contract as block_excl_scan).
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* scratch, uint32_t* total) {
+    constexpr int NW = NT / kWave;
+    const uint32_t l = lane_id(), w = threadIdx.x / kWave;
+    auto mx = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+    uint32_t inc = wave_incl_op(v, mx);
+    uint32_t exc = (uint32_t)__shfl_up((int)inc, 1, kWave);
+    if (l == 0) exc = 0;
+    if (l == kWave - 1) scratch[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t s = l < (uint32_t)NW ? scratch[l] : 0u;
+        uint32_t si = wave_incl_op(s, mx);
+        uint32_t se = (uint32_t)__shfl_up((int)si, 1, kWave);
+        if (l == 0) se = 0;
+        if (l < (uint32_t)NW) scratch[l] = se;
+        if (l == NW - 1) scratch[NW] = si;
+    }
+    __syncthreads();
+    uint32_t r = max(scratch[w], exc);
+    *total = scratch[NW];
+    __syncthreads();
+    return r;
+}
+
 // position of the r-th (0-based) set bit of v; v must have more than r bits set
 __device__ __forceinline__ uint32_t select_bit(uint64_t v, uint32_t r) {
     uint32_t pos = 0;
@@ -132,29 +171,29 @@ __device__ __forceinline__ uint32_t unzigzag(uint32_t z, uint32_t bits) {
 // Frame-width choice for 128 values held two per lane (Sec. II):
 // B = width of the maximum; n(b) = values >= 2^b;
 // cost(b) = 16 b + [n > 0] (n + ceil(n (B - b) / 8)); ties go to the larger b.
-// A histogram of the values' bit widths (in the wave's 40 words of LDS
-// `hist`) gives n(b) for every b at once: lane b evaluates cost(b) and a
-// wave minimum picks the width.  Called by a whole wave.
+// The values' bit widths are counted by ballots, one distinct width at a
+// time (lane v ends up holding the count of width v); a prefix sum gives
+// n(b) on lane b, which evaluates cost(b); a wave minimum picks the width.
+// Called by a whole wave.
 struct FrameChoice {
     uint32_t b, n, B, cost;
 };
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, kWave));
-    return v;
-}
-__device__ __forceinline__ FrameChoice choose_frame(uint32_t z0, uint32_t z1, uint32_t* hist) {
+__device__ __forceinline__ FrameChoice choose_frame(uint32_t z0, uint32_t z1) {
     const uint32_t l = lane_id();
-    if (l < 40) hist[l] = 0;
-    __builtin_amdgcn_wave_barrier();
     const uint32_t w0 = z0 ? 32u - __clz(z0) : 0u;
     const uint32_t w1 = z1 ? 32u - __clz(z1) : 0u;
-    atomicAdd(&hist[w0], 1u);
-    atomicAdd(&hist[w1], 1u);
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t h = l <= 32 ? hist[l] : 0u;
-    const uint32_t n = 128u - wave_incl_scan(h);  // values wider than l bits
-    const uint32_t B = wave_max(max(w0, w1));
+    uint64_t rem0 = ~0ull, rem1 = ~0ull;
+    uint32_t hc = 0, B = 0;
+    while (rem0 | rem1) {
+        const uint32_t v = rem0 ? (uint32_t)__builtin_amdgcn_readlane((int)w0, (int)__builtin_ctzll(rem0))
+                                : (uint32_t)__builtin_amdgcn_readlane((int)w1, (int)__builtin_ctzll(rem1));
+        const uint64_t m0 = ballot(w0 == v) & rem0, m1 = ballot(w1 == v) & rem1;
+        if (l == v) hc = (uint32_t)(__popcll(m0) + __popcll(m1));
+        B = v > B ? v : B;
+        rem0 &= ~m0;
+        rem1 &= ~m1;
+    }
+    const uint32_t n = 128u - wave_incl_scan(hc);  // values wider than l bits
     uint32_t key = 0xFFFFFFFFu;
     if (l <= B) {
         const uint32_t cost = 16u * l + (n ? n + (n * (B - l) + 7u) / 8u : 0u);
@@ -162,8 +201,7 @@ __device__ __forceinline__ FrameChoice choose_frame(uint32_t z0, uint32_t z1, ui
     }
     key = wave_min(key);
     const uint32_t b = 63u - (key & 63u);
-    const uint32_t nb = (uint32_t)__shfl((int)n, (int)b, kWave);
-    __builtin_amdgcn_wave_barrier();
+    const uint32_t nb = (uint32_t)__builtin_amdgcn_readlane((int)n, (int)b);
     return FrameChoice{b, nb, B, key >> 6};
 }
 

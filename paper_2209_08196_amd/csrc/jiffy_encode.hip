@@ -6,14 +6,16 @@
 //
 //   k_enc_mask     quantize (Sec. III-B), zero bitmask by wave ballot (Sec. III-C)
 //   k_enc_trial    I/P choice by trial compression of a few scanlines (Sec. III-E)
-//   k_enc_scan     running count of in-range samples; frame start/end pixels
-//   k_enc_frames   zero removal, temporal difference (Sec. III-D), delta,
+//   k_enc_scan     running count of in-range samples; per-tile bases
+//   k_enc_tiles    zero removal, temporal difference (Sec. III-D), delta,
 //                  ZigZag (Eq. 1), frame width choice and bit packing (Sec. II)
+//   k_enc_fixup    the same for frames that cross tile boundaries
 //   k_enc_mframe   mask (XOR previous for a P-scan, Sec. III-D) as a Raw/RLE
 //                  Zstandard frame (Sec. III-C)
 //   k_enc_sizes    per-record section layout (prefix sums of frame sizes)
 //   k_enc_offsets  record offsets in the output (prefix sum over records)
 //   k_enc_assemble copies everything to its place in the stream
+#define JIFFY_KERNEL_TU 1
 #include "jiffy_device.h"
 
 namespace jiffy {
@@ -66,14 +68,13 @@ __device__ __forceinline__ uint32_t sample_at(const void* base, uint32_t wb, uin
 
 // packed size of one frame of values s[0..real) with predecessor `pred`;
 // called by one whole wave
-__device__ __forceinline__ uint32_t frame_cost_lds(const uint32_t* s, uint32_t real, uint32_t pred, uint32_t bits,
-                                                   uint32_t* hist) {
+__device__ __forceinline__ uint32_t frame_cost_lds(const uint32_t* s, uint32_t real, uint32_t pred, uint32_t bits) {
     const uint32_t l = lane_id();
     const uint32_t m = low_mask32(bits);
     uint32_t z0 = 0, z1 = 0;
     if (l < real) z0 = zigzag((s[l] - (l ? s[l - 1] : pred)) & m, bits);
     if (l + 64 < real) z1 = zigzag((s[l + 64] - s[l + 63]) & m, bits);
-    return choose_frame(z0, z1, hist).cost;
+    return choose_frame(z0, z1).cost;
 }
 
 __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
@@ -85,7 +86,6 @@ __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
     }
     __shared__ uint32_t su[384], sv[384];
     __shared__ uint32_t scratch[8];
-    __shared__ uint32_t hist[40];
     __shared__ uint64_t s_cost[2];
     __shared__ uint32_t s_pred[2];
     const uint32_t tid = threadIdx.x, wave = tid / kWave;
@@ -118,8 +118,8 @@ __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
             cnt += total;
             while (cnt >= 128) {
                 if (wave == 0) {
-                    uint32_t ci = frame_cost_lds(su, 128, s_pred[0], it.bits, hist);
-                    uint32_t cp = frame_cost_lds(sv, 128, s_pred[1], it.bits, hist);
+                    uint32_t ci = frame_cost_lds(su, 128, s_pred[0], it.bits);
+                    uint32_t cp = frame_cost_lds(sv, 128, s_pred[1], it.bits);
                     if (lane_id() == 0) { s_cost[0] += ci; s_cost[1] += cp; }
                 }
                 __syncthreads();
@@ -136,8 +136,8 @@ __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
         }
     }
     if (cnt > 0 && wave == 0) {
-        uint32_t ci = frame_cost_lds(su, cnt, s_pred[0], it.bits, hist);
-        uint32_t cp = frame_cost_lds(sv, cnt, s_pred[1], it.bits, hist);
+        uint32_t ci = frame_cost_lds(su, cnt, s_pred[0], it.bits);
+        uint32_t cp = frame_cost_lds(sv, cnt, s_pred[1], it.bits);
         if (lane_id() == 0) { s_cost[0] += ci; s_cost[1] += cp; }
     }
     __syncthreads();
@@ -146,26 +146,29 @@ __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
 
 // ---------------------------------------------------------------------------
 // Running count of in-range samples over the flattened scan (Sec. III-C zero
-// removal): N, and the pixel of each frame's first and last value.
+// removal): N, and for every kFTile-pixel tile the count before it and the
+// last in-range pixel before it.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_enc_scan(EncPlan plan) {
     const uint32_t r = blockIdx.x;
     const EncItem it = plan.items[r];
-    __shared__ uint32_t scratch[20];
-    uint32_t carry = 0;
+    __shared__ uint32_t scratch[20], scratch2[20];
+    constexpr uint32_t kTW = kFTile / 64;  // words per tile
+    uint32_t carry = 0, lastpx = 0;
     for (uint32_t w0 = 0; w0 < it.nwords; w0 += 1024) {
         const uint32_t w = w0 + threadIdx.x;
         const uint64_t v = w < it.nwords ? it.vw[w] : 0ull;
         const uint32_t pc = __popcll(v);
-        uint32_t total;
+        const uint32_t lp = v ? 64u * w + 64u - (uint32_t)__clzll(v) : 0u;  // last in-range pixel + 1
+        uint32_t total, mtot;
         const uint32_t pre = block_excl_scan<1024>(pc, scratch, &total) + carry;
-        if (pc) {
-            uint32_t k = (pre + 127u) & ~127u;  // first frame start at or after pre
-            if (k < pre + pc) it.blkstart[k >> 7] = 64u * w + select_bit(v, k - pre);
-            k = pre + ((127u - pre) & 127u);    // first frame end at or after pre
-            if (k < pre + pc) it.blklast[k >> 7] = 64u * w + select_bit(v, k - pre);
+        const uint32_t exm = max(block_excl_max<1024>(lp, scratch2, &mtot), lastpx);
+        if (w < it.nwords && w % kTW == 0) {
+            it.tbase[w / kTW] = pre;
+            it.tpred[w / kTW] = exm;
         }
         carry += total;
+        lastpx = max(lastpx, mtot);
     }
     if (threadIdx.x == 0) {
         plan.res[r].N = carry;
@@ -174,13 +177,154 @@ __global__ __launch_bounds__(1024) void k_enc_scan(EncPlan plan) {
 }
 
 // ---------------------------------------------------------------------------
-// Residuals and frame packing.  A workgroup takes kGroupFrames consecutive
-// frames of one record: it streams the pixels they cover, keeps the in-range
-// samples (Sec. III-C), subtracts the previous scan for a P-scan (Sec. III-D)
-// and compacts them in LDS; each wave then codes frames: delta to the
-// preceding value, ZigZag (Eq. 1), width choice and packing (Sec. II).
-// A packed frame goes to its slot: payload (16 b bytes), exception
-// positions (n bytes), exception high parts (ceil(n (B-b) / 8) bytes).
+// Frame coding, four lanes per frame (Sec. II).  Lane q of the quad owns
+// values 32q .. 32q+31 of the frame, so its low-b-bit parts fill exactly
+// b words of the packed frame (words qb .. qb+b-1) and no lane waits for
+// another.  Delta (to the preceding value) and ZigZag (Eq. 1) run in
+// registers; the bit widths are counted in LDS; each lane then evaluates
+// cost(b) for eight of the 32 widths and the quad takes the minimum.  The
+// frame is built in an LDS row and copied to its slot with 16-byte stores.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRow = kSlotBytes / 4;  // LDS words per frame row
+static_assert(kRow >= kFrame + 12 && kRow % 4 == 0, "a frame row holds 128 values, padded every 32");
+
+// word of value i in a frame row: four pad words after every 32 values, so
+// that each lane's 32 values start 16-byte aligned in distinct banks
+__device__ __forceinline__ uint32_t row_off(uint32_t i) { return i + ((i >> 5) << 2); }
+
+// DPP quad permutations
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;
+template <int Q> __device__ __forceinline__ uint32_t quad_bcast(uint32_t v) { return dpp_mov<0x55 * Q>(v); }
+
+// vrow: the frame's values (row layout); on return it holds their ZigZag
+// codes.  orow: the quad's output row.  real: number of real values (the
+// rest count as 0); pred: the value before the first.  All four lanes of
+// the quad call it together; q = lane & 3.
+__device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t* orow, uint32_t real, uint32_t pred,
+                                                uint32_t bits, uint32_t q, JG uint8_t* slot, JG uint32_t* info) {
+    const uint32_t m = low_mask32(bits);
+    uint32_t z[32];
+    {
+        const uint4* v4 = (const uint4*)(vrow + 36 * q);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint4 t = v4[c];
+            z[4 * c] = t.x; z[4 * c + 1] = t.y; z[4 * c + 2] = t.z; z[4 * c + 3] = t.w;
+        }
+    }
+    // histogram of widths 1..32 in orow words 0..31; width 0 goes to word 32 + q
+    uint4* o4 = (uint4*)orow;
+    o4[2 * q] = make_uint4(0u, 0u, 0u, 0u);
+    o4[2 * q + 1] = make_uint4(0u, 0u, 0u, 0u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    uint32_t prev = dpp_mov<0x111>(z[31]);  // the previous lane's last value
+    if (q == 0) prev = pred;
+    uint32_t B = 0;
+    const uint32_t i0 = 32u * q;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const uint32_t x = z[i];
+        const uint32_t r = (i0 + i < real) ? zigzag((x - prev) & m, bits) : 0u;
+        prev = x;
+        z[i] = r;
+        const uint32_t w = r ? 32u - __clz(r) : 0u;
+        B = max(B, w);
+        __hip_atomic_fetch_add(orow + (w ? w - 1u : 32u + q), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    {  // the codes replace the values (read again for the exceptions)
+        uint4* v4 = (uint4*)(vrow + 36 * q);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v4[c] = make_uint4(z[4 * c], z[4 * c + 1], z[4 * c + 2], z[4 * c + 3]);
+    }
+    B = max(B, dpp_mov<kQuadXor1>(B));
+    B = max(B, dpp_mov<kQuadXor2>(B));
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // n(b) = values wider than b bits; lane q evaluates b = 8q .. 8q+7
+    const uint4 ha = o4[2 * q], hb = o4[2 * q + 1];
+    const uint32_t h[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};  // widths 8q+1 .. 8q+8
+    uint32_t loc = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) loc += h[k];
+    const uint32_t c1 = quad_bcast<1>(loc), c2 = quad_bcast<2>(loc), c3 = quad_bcast<3>(loc);
+    uint32_t n = (q < 1 ? c1 : 0u) + (q < 2 ? c2 : 0u) + (q < 3 ? c3 : 0u);
+    // key: cost, then the larger b, then n(b); b = B costs 16 B with no exceptions
+    uint32_t key = ((16u * B) << 14) | ((63u - B) << 8);
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+        n += h[k];
+        const uint32_t b = 8u * q + k;
+        if (b < B) {
+            const uint32_t cost = 16u * b + n + (n * (B - b) + 7u) / 8u;
+            key = min(key, (cost << 14) | ((63u - b) << 8) | n);
+        }
+    }
+    key = min(key, dpp_mov<kQuadXor1>(key));
+    key = min(key, dpp_mov<kQuadXor2>(key));
+    const uint32_t b = 63u - ((key >> 8) & 63u), nexc = key & 255u, cost = key >> 14;
+    const uint32_t hw = B - b, lm = low_mask32(b);
+    uint32_t ex = 0;  // this lane's exceptions
+#pragma unroll
+    for (int i = 0; i < 32; ++i) ex |= (z[i] > lm ? 1u : 0u) << i;
+    const uint32_t ne = __popc(ex);
+    const uint32_t e0 = quad_bcast<0>(ne), e1 = quad_bcast<1>(ne), e2 = quad_bcast<2>(ne);
+    const uint32_t E = (q > 0 ? e0 : 0u) + (q > 1 ? e1 : 0u) + (q > 2 ? e2 : 0u);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const uint32_t cw = (cost + 3u) / 4u;  // words of the packed frame
+    // exception area (positions, then high parts) starts zeroed
+    for (uint32_t w = 4u * b + q; w < cw; w += 4) orow[w] = 0u;
+    {  // low b bits of each value: words qb .. qb+b-1
+        // the word being filled is stored after every value (no branches); its
+        // last store is the complete word.  With b = 0 this writes zeros to
+        // word 0, which belongs to the (zeroed) exception area.
+        uint32_t* dst = orow + q * b;
+        uint64_t acc = 0;
+        uint32_t nacc = 0, wi = 0;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            acc |= (uint64_t)(z[i] & lm) << nacc;
+            nacc += b;
+            dst[wi] = (uint32_t)acc;
+            const bool full = nacc >= 32;
+            acc = full ? acc >> 32 : acc;
+            nacc = full ? nacc - 32 : nacc;
+            wi += full ? 1u : 0u;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (ex) {  // positions at byte 16b + rank, high parts from byte 16b + nexc
+        uint8_t* ob = (uint8_t*)orow;
+        const uint32_t hb0 = 8u * (16u * b + nexc);
+        uint32_t r = E;
+        do {
+            const uint32_t i = __builtin_ctz(ex);
+            ex &= ex - 1u;
+            const uint32_t zi = vrow[row_off(i0 + i)];
+            ob[16u * b + r] = (uint8_t)(i0 + i);
+            const uint32_t o = hb0 + r * hw;
+            const uint64_t sh = (uint64_t)(zi >> b) << (o & 31u);
+            __hip_atomic_fetch_or(orow + (o >> 5), (uint32_t)sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            if (sh >> 32)
+                __hip_atomic_fetch_or(orow + (o >> 5) + 1, (uint32_t)(sh >> 32), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
+            ++r;
+        } while (ex);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    JG uint4* s4 = (JG uint4*)slot;
+    for (uint32_t c = q; c < (cost + 15u) / 16u; c += 4) s4[c] = o4[c];
+    if (q == 0) *info = b | (nexc << 8) | (B << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Residuals and frame packing per kFTile-pixel tile.  Each thread reads 32
+// consecutive samples (and the previous scan's for a P-scan); the in-range
+// residuals -- the sample (I) or its difference to the previous scan
+// (P, Sec. III-D) -- are compacted in LDS (zero removal, Sec. III-C), each
+// frame in its own row.  Then one quad of lanes codes each frame that lies
+// wholly inside the tile (at most 64).  A frame that crosses a tile
+// boundary is staged in its slot by each tile it touches (its values, and
+// the value before it by the tile where it starts) and coded by
+// k_enc_fixup.
 // ---------------------------------------------------------------------------
 template <int WB>
 __device__ __forceinline__ uint32_t residual_at(const EncItem& it, uint32_t mode, uint32_t p, uint32_t m) {
@@ -191,131 +335,134 @@ __device__ __forceinline__ uint32_t residual_at(const EncItem& it, uint32_t mode
     return (q - qp) & m;
 }
 
-struct FramesLds {
-    uint32_t sv[kGroupFrames * kFrame + 1];
+constexpr uint32_t kTileFrames = kFTile / kFrame + 1;  // frames a tile can touch
+constexpr uint32_t kTileQuads = kFTile / kFrame;       // frames a tile can hold whole
+
+struct TileLds {
+    uint32_t rows[(kTileFrames + kTileQuads) * kRow];  // frame rows, then the quads' output rows
     uint32_t scratch[8];
-    uint32_t pw[4][128];
-    uint32_t hw[4][128];
-    uint32_t hist[4][40];
+    uint32_t pred;
+    __device__ uint32_t* outs() { return rows + kTileFrames * kRow; }
 };
 
 template <int WB>
-__device__ __forceinline__ void enc_frames_body(const EncPlan& plan, const EncItem& it, uint32_t r, FramesLds& L) {
-    uint32_t* sv = L.sv;
-    uint32_t* scratch = L.scratch;
-    auto& pw = L.pw;
-    auto& hw = L.hw;
-    const uint32_t N = plan.res[r].N, nb = plan.res[r].nb, mode = plan.res[r].mode;
-    const uint32_t j0 = blockIdx.x * kGroupFrames;
-    if (j0 >= nb) return;
-    const uint32_t j1 = min(j0 + kGroupFrames, nb);
-    const uint32_t nvals = min(j1 * kFrame, N) - j0 * kFrame;
-    const uint32_t p_lo = it.blkstart[j0];
-    const uint32_t p_hi = (j1 == nb) ? it.npx - 1 : it.blklast[j1 - 1];
+__device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
+                                              TileLds& L) {
+    const uint32_t N = plan.res[r].N, mode = plan.res[r].mode;
+    const uint32_t kb = it.tbase[lt], tp = it.tpred[lt];
     const uint32_t m = low_mask32(it.bits);
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) sv[0] = j0 ? residual_at<WB>(it, mode, it.blklast[j0 - 1], m) : 0u;
-
-    uint32_t cnt = 0;
-    for (uint32_t c0 = p_lo & ~15u; c0 <= p_hi; c0 += 256 * 16) {
-        const uint32_t p0 = c0 + tid * 16;
-        uint32_t s[16];
-        uint32_t keep = 0;
-        if (p0 <= p_hi && p0 + 15 >= p_lo && p0 < it.npx) {
-            uint32_t x[16];
-            load16<WB>(it.x, p0, it.npx, it.aligned16, x);
-            uint32_t xp[16];
-            if (mode) load16<WB>(it.xprev, p0, it.npx, it.aligned16, xp);
+    const uint32_t p0 = lt * kFTile + tid * 32;
+    uint32_t s[32];
+    uint32_t keep = 0;
+    if (p0 < it.npx) {
+        load16<WB>(it.x, p0, it.npx, it.aligned16, s);
+        load16<WB>(it.x, p0 + 16, it.npx, it.aligned16, s + 16);
+        if (mode) {
+            uint32_t xp[32];
+            load16<WB>(it.xprev, p0, it.npx, it.aligned16, xp);
+            load16<WB>(it.xprev, p0 + 16, it.npx, it.aligned16, xp + 16);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const uint32_t p = p0 + i;
-                const uint32_t q = quantize(x[i], it.div);
-                uint32_t val = q;
-                if (mode) {
-                    const uint32_t qp = it.prev_quantized ? xp[i] : quantize(xp[i], it.div);
-                    val = (q - qp) & m;
-                }
-                s[i] = val;
-                if (q != 0 && p >= p_lo && p <= p_hi) keep |= 1u << i;
+            for (int i = 0; i < 32; ++i) {
+                const uint32_t q = quantize(s[i], it.div);
+                const uint32_t qp = it.prev_quantized ? xp[i] : quantize(xp[i], it.div);
+                keep |= (q != 0 ? 1u : 0u) << i;
+                s[i] = (q - qp) & m;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                s[i] = quantize(s[i], it.div);
+                keep |= (s[i] != 0 ? 1u : 0u) << i;
             }
         }
-        uint32_t total;
-        uint32_t off = block_excl_scan<256>(__popc(keep), scratch, &total);
+    }
+    if (tid == 0) L.pred = tp ? residual_at<WB>(it, mode, tp - 1, m) : 0u;
+    uint32_t nv;
+    const uint32_t off = block_excl_scan<256>(__popc(keep), L.scratch, &nv);
+    const uint32_t jf = kb >> 7;
+    {
+        // kept values go to their row; the others to a word of this thread's
+        // in the (not yet used) output rows
+        uint32_t k = kb + off;  // index of the next kept value
+        const uint32_t dummy = kTileFrames * kRow + tid;
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (keep & (1u << i)) sv[1 + cnt + off++] = s[i];
-        cnt += total;
+        for (int i = 0; i < 32; ++i) {
+            const bool kp = (keep >> i) & 1u;
+            L.rows[kp ? ((k >> 7) - jf) * kRow + row_off(k & 127u) : dummy] = s[i];
+            k += kp ? 1u : 0u;
+        }
     }
     __syncthreads();
+    if (nv == 0) {
+        if (tid == 0) it.tfix[lt] = kNoFix;
+        return;
+    }
+    const uint32_t ke = kb + nv;  // end of the tile's values
+    const uint32_t jl = (ke - 1) >> 7;
+    const uint32_t kl0 = jl << 7, kl1 = min(kl0 + kFrame, N);
+    const bool head_part = (kb & 127u) != 0;               // frame jf began in an earlier tile
+    const bool tail_part = kl1 > ke && !(jl == jf && head_part);  // frame jl starts here, ends later
+    if (tid == 0) it.tfix[lt] = tail_part ? jl : kNoFix;
+    auto value_at = [&](uint32_t k) { return L.rows[((k >> 7) - jf) * kRow + row_off(k & 127u)]; };
+    // stage the crossing frames: thread t < 128 value t of frame jf, t >= 128 value t - 128 of frame jl
+    if (tid < kFrame) {
+        const uint32_t k = (jf << 7) + tid;
+        if (head_part && k >= kb && k < ke) ((JG uint32_t*)(it.slots + (size_t)jf * kSlotBytes))[tid] = value_at(k);
+    } else {
+        const uint32_t i = tid - kFrame, k = kl0 + i;
+        JG uint32_t* sw = (JG uint32_t*)(it.slots + (size_t)jl * kSlotBytes);
+        if (tail_part && k < ke) sw[i] = value_at(k);
+        if (tail_part && i == 0) sw[kFrame] = kl0 > kb ? value_at(kl0 - 1) : L.pred;
+    }
+    // the whole frames: quad g codes frame jc0 + g
+    const uint32_t g = tid >> 2, q = tid & 3u;
+    const uint32_t j = ((kb + 127u) >> 7) + g;
+    const uint32_t k0 = j << 7, kend = min(k0 + kFrame, N);
+    const bool whole = k0 < ke && kend <= ke;
+    uint32_t pred = 0;
+    if (whole) pred = k0 > kb ? value_at(k0 - 1) : L.pred;
+    __syncthreads();  // every row is read before its quad overwrites it
+    if (!whole) return;
+    code_frame_quad(L.rows + (j - jf) * kRow, L.outs() + g * kRow, kend - k0, pred, it.bits, q,
+                    it.slots + (size_t)j * kSlotBytes, it.blkinfo + j);
+}
 
-    const uint32_t wave = tid / kWave, l = lane_id();
-    for (uint32_t jj = wave; jj < j1 - j0; jj += 4) {
-        const uint32_t k0 = jj * kFrame;
-        const uint32_t real = min(kFrame, nvals - k0);
-        const uint32_t i0 = l, i1 = l + 64;
-        uint32_t z0 = 0, z1 = 0;
-        if (i0 < real) z0 = zigzag((sv[1 + k0 + i0] - sv[k0 + i0]) & m, it.bits);
-        if (i1 < real) z1 = zigzag((sv[1 + k0 + i1] - sv[k0 + i1]) & m, it.bits);
-        const FrameChoice fc = choose_frame(z0, z1, L.hist[wave]);
-        const uint32_t b = fc.b, hwid = fc.B - fc.b;
-        pw[wave][l] = 0; pw[wave][l + 64] = 0;
-        hw[wave][l] = 0; hw[wave][l + 64] = 0;
-        __builtin_amdgcn_wave_barrier();
-        if (b) {
-            const uint32_t lm = low_mask32(b);
-            uint32_t bp = i0 * b;
-            uint64_t t = (uint64_t)(z0 & lm) << (bp & 31);
-            atomicOr(&pw[wave][bp >> 5], (uint32_t)t);
-            if ((uint32_t)(t >> 32)) atomicOr(&pw[wave][(bp >> 5) + 1], (uint32_t)(t >> 32));
-            bp = i1 * b;
-            t = (uint64_t)(z1 & lm) << (bp & 31);
-            atomicOr(&pw[wave][bp >> 5], (uint32_t)t);
-            if ((uint32_t)(t >> 32)) atomicOr(&pw[wave][(bp >> 5) + 1], (uint32_t)(t >> 32));
-        }
-        const bool e0 = b < 32 && (z0 >> b) != 0;
-        const bool e1 = b < 32 && (z1 >> b) != 0;
-        const uint64_t m0 = ballot(e0), m1 = ballot(e1);
-        const uint32_t r0 = rank_below(m0), r1 = __popcll(m0) + rank_below(m1);
-        uint8_t* slot = it.slots + (size_t)(j0 + jj) * kSlotBytes;
-        if (e0) slot[16 * b + r0] = (uint8_t)i0;
-        if (e1) slot[16 * b + r1] = (uint8_t)i1;
-        if (fc.n) {
-            if (e0) {
-                uint32_t bp = r0 * hwid;
-                uint64_t t = (uint64_t)(z0 >> b) << (bp & 31);
-                atomicOr(&hw[wave][bp >> 5], (uint32_t)t);
-                if ((uint32_t)(t >> 32)) atomicOr(&hw[wave][(bp >> 5) + 1], (uint32_t)(t >> 32));
-            }
-            if (e1) {
-                uint32_t bp = r1 * hwid;
-                uint64_t t = (uint64_t)(z1 >> b) << (bp & 31);
-                atomicOr(&hw[wave][bp >> 5], (uint32_t)t);
-                if ((uint32_t)(t >> 32)) atomicOr(&hw[wave][(bp >> 5) + 1], (uint32_t)(t >> 32));
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        // payload words
-        uint32_t* sw = (uint32_t*)slot;
-        if (l < 4 * b) sw[l] = pw[wave][l];
-        if (l + 64 < 4 * b) sw[l + 64] = pw[wave][l + 64];
-        // exception high parts, byte by byte
-        const uint32_t hb = (fc.n * hwid + 7) / 8;
-        const uint8_t* hbytes = (const uint8_t*)hw[wave];
-        for (uint32_t k = l; k < hb; k += 64) slot[16 * b + fc.n + k] = hbytes[k];
-        if (l == 0) it.blkinfo[j0 + jj] = b | (fc.n << 8) | (fc.B << 16);
-        __builtin_amdgcn_wave_barrier();
+__global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
+    const uint32_t t = blockIdx.x;
+    const uint32_t r = plan.ftile_item[t];
+    const EncItem it = plan.items[r];
+    const uint32_t lt = t - plan.ftile_first[r];
+    __shared__ TileLds lds;
+    switch (it.wb) {
+        case 4: enc_tile_body<4>(plan, it, r, lt, lds); break;
+        case 2: enc_tile_body<2>(plan, it, r, lt, lds); break;
+        default: enc_tile_body<1>(plan, it, r, lt, lds); break;
     }
 }
 
-__global__ __launch_bounds__(256) void k_enc_frames(EncPlan plan) {
-    const uint32_t r = blockIdx.y;
-    const EncItem it = plan.items[r];
-    __shared__ FramesLds lds;
-    switch (it.wb) {
-        case 4: enc_frames_body<4>(plan, it, r, lds); break;
-        case 2: enc_frames_body<2>(plan, it, r, lds); break;
-        default: enc_frames_body<1>(plan, it, r, lds); break;
-    }
+// The frames that cross tile boundaries: one quad per tile entry (16 per
+// workgroup); the staged values go to the quad's LDS row first.
+__global__ __launch_bounds__(64) void k_enc_fixup(EncPlan plan) {
+    const uint32_t g = threadIdx.x >> 2, q = threadIdx.x & 3u;
+    const uint32_t t = blockIdx.x * 16 + g;
+    __shared__ uint32_t rows[16 * kRow], outs[16 * kRow];
+    if (t >= plan.n_ftiles) return;  // no barrier follows
+    const uint32_t r = plan.ftile_item[t];
+    const uint32_t lt = t - plan.ftile_first[r];
+    const EncItem& it = plan.items[r];
+    const uint32_t j = it.tfix[lt];
+    if (j == kNoFix) return;
+    const uint32_t N = plan.res[r].N;
+    const uint32_t real = min(kFrame, N - j * kFrame);
+    JG uint8_t* slot = it.slots + (size_t)j * kSlotBytes;
+    const JG uint4* s4 = (const JG uint4*)slot;
+    uint4* v4 = (uint4*)(rows + g * kRow + 36 * q);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v4[c] = s4[8 * q + c];
+    const uint32_t pred = ((const JG uint32_t*)slot)[kFrame];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    code_frame_quad(rows + g * kRow, outs + g * kRow, real, pred, it.bits, q, slot, it.blkinfo + j);
 }
 
 // ---------------------------------------------------------------------------
@@ -675,7 +822,8 @@ hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_enc_mask", k_enc_mask, dim3(plan.n_tiles), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_trial", k_enc_trial, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_scan", k_enc_scan, dim3(plan.n_items), dim3(1024), stream, plan);
-    JIFFY_LAUNCH("k_enc_frames", k_enc_frames, dim3(plan.max_groups, plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_tiles", k_enc_tiles, dim3(plan.n_ftiles), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_fixup", k_enc_fixup, dim3(div_up(plan.n_ftiles, 16)), dim3(64), stream, plan);
     JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_offsets", k_enc_offsets, dim3(1), dim3(1024), stream, plan);

@@ -5,11 +5,24 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// In the kernels' device compilation every pointer in the structures below
+// points to global memory: declaring that lets the compiler emit global
+// (not flat) loads and stores, which do not hold up LDS waits.  Host code
+// sees plain pointers; the layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(JIFFY_KERNEL_TU)
+#define JG __attribute__((address_space(1)))
+#else
+#define JG
+#endif
+
 namespace jiffy {
 
 constexpr int kWave = 64;
 constexpr uint32_t kFrame = 128;            // values per packed frame (Sec. II: frames of 128)
-constexpr uint32_t kSlotBytes = 512;        // largest packed frame: 16 * 32 bytes
+constexpr uint32_t kSlotBytes = 576;        // a packed frame (at most 16 * 32 bytes), or a frame that
+                                            // straddles tiles: its 128 residuals and their predecessor
+constexpr uint32_t kFTile = 8192;           // pixels per encode / decode tile
+constexpr uint32_t kNoFix = 0xFFFFFFFFu;    // a tile with no straddling frame to finish
 constexpr uint32_t kTilePx = 4096;          // pixels per mask tile (64 words of 64 px)
 constexpr uint32_t kTileWords = kTilePx / 64;
 constexpr uint32_t kGroupFrames = 16;       // frames handled by one encode/decode workgroup
@@ -46,24 +59,26 @@ inline Divisor make_divisor(uint32_t P) {
 
 // One (scan, attribute) record to encode.
 struct EncItem {
-    const void* x;            // current scan, npx samples
-    const void* xprev;        // previous scan (raw or quantized), or null
-    void* qout;               // if set, the quantized scan is stored here
-    uint64_t* vw;             // valid-sample words of this scan (bit = 1: nonzero)
-    const uint64_t* vwprev;   // valid-sample words of the previous scan
-    uint32_t* blkstart;       // [maxnb] pixel of each frame's first value
-    uint32_t* blklast;        // [maxnb] pixel of each frame's last value
-    uint32_t* blkinfo;        // [maxnb] b | n << 8 | B << 16
-    uint32_t* blkoffs;        // [3 * maxnb] payload / position / high offsets
-    uint8_t* slots;           // [maxnb * kSlotBytes] packed frames
-    uint8_t* frame;           // mask frame staging
-    uint32_t* segs;           // [seg_cap] frame segment starts (bit 31: run)
-    uint32_t* segoff;         // [seg_cap] frame segment output offsets
+    const JG void* x;            // current scan, npx samples
+    const JG void* xprev;        // previous scan (raw or quantized), or null
+    JG void* qout;               // if set, the quantized scan is stored here
+    JG uint64_t* vw;             // valid-sample words of this scan (bit = 1: nonzero)
+    const JG uint64_t* vwprev;   // valid-sample words of the previous scan
+    JG uint32_t* tbase;          // [ntiles] in-range samples before each kFTile tile
+    JG uint32_t* tpred;          // [ntiles] last in-range pixel before each tile, plus 1 (0: none)
+    JG uint32_t* tfix;           // [ntiles] frame that starts in the tile and ends after it, or kNoFix
+    JG uint32_t* blkinfo;        // [maxnb] b | n << 8 | B << 16
+    JG uint32_t* blkoffs;        // [3 * maxnb] payload / position / high offsets
+    JG uint8_t* slots;           // [maxnb * kSlotBytes] packed frames
+    JG uint8_t* frame;           // mask frame staging
+    JG uint32_t* segs;           // [seg_cap] frame segment starts (bit 31: run)
+    JG uint32_t* segoff;         // [seg_cap] frame segment output offsets
     Divisor div;
     uint32_t npx, nwords, height, width;
     uint32_t wb, bits, attr, out_id;
     uint32_t has_prev, prev_quantized, mode_req, trial_rows;
     uint32_t maxnb, frame_cap, seg_cap, aligned16;
+    uint32_t ntiles, pad0;
 };
 
 // Per-record results of an encode.
@@ -77,7 +92,7 @@ struct EncRes {
 // One output buffer of an encode call (the whole stream, or one stream's
 // records in a batch step).
 struct EncOut {
-    uint8_t* base;
+    JG uint8_t* base;
     uint64_t cap;
     uint32_t first_item, n_items;
     uint32_t hdr_len;         // stream header + length table, or 0
@@ -91,15 +106,15 @@ struct EncOut {
 
 // One record to decode.
 struct DecItem {
-    const uint8_t* rec;
+    const JG uint8_t* rec;
     uint32_t rec_len;
-    void* out;                // [npx] output samples
-    uint64_t* cw;             // unframed mask content (XOR form for a P-scan)
-    uint64_t* vw;             // valid-sample words
-    uint32_t* blkinfo;        // [maxnb]
-    uint32_t* blkoffs;        // [3 * maxnb]
-    uint32_t* bsum;           // [maxnb] frame sums, then exclusive prefixes
-    uint32_t* blklast;        // [maxnb] pixel of each frame's last value
+    JG void* out;                // [npx] output samples
+    JG uint64_t* cw;             // unframed mask content (XOR form for a P-scan)
+    JG uint64_t* vw;             // valid-sample words
+    JG uint32_t* blkinfo;        // [maxnb]
+    JG uint32_t* blkoffs;        // [3 * maxnb]
+    JG uint32_t* bsum;           // [maxnb] frame sums, then exclusive prefixes
+    JG uint32_t* blklast;        // [maxnb] pixel of each frame's last value
     uint32_t npx, nwords, wb, bits;
     uint32_t attr, t, P, maxnb;
     uint32_t aligned16, pad0;
@@ -124,30 +139,32 @@ void prof_end(hipStream_t stream);
 
 // ---- kernel launchers (defined in the .hip files) -------------------------
 struct EncPlan {
-    const EncItem* items;     // device
-    EncRes* res;              // device
-    EncOut* outs;             // device
-    uint32_t* err;            // device
-    const uint32_t* tile_item;  // device: item of each mask tile
-    const uint32_t* tile_first; // device: first tile of each item
-    uint32_t n_items, n_outs, n_tiles;
+    const JG EncItem* items;     // device
+    JG EncRes* res;              // device
+    JG EncOut* outs;             // device
+    JG uint32_t* err;            // device
+    const JG uint32_t* tile_item;  // device: item of each mask tile
+    const JG uint32_t* tile_first; // device: first tile of each item
+    const JG uint32_t* ftile_item;  // device: item of each kFTile tile
+    const JG uint32_t* ftile_first; // device: first kFTile tile of each item
+    uint32_t n_items, n_outs, n_tiles, n_ftiles;
     uint32_t max_groups;      // max over items of ceil(maxnb / kGroupFrames)
 };
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream);
 
 struct DecPlan {
-    const DecItem* items;
-    DecRes* res;
-    uint32_t* err;
-    uint8_t* modes;           // [n_items] 0 = I, 1 = P (written by the parse)
-    uint8_t* ws;              // per-record workspace, item_stride bytes each
+    const JG DecItem* items;
+    JG DecRes* res;
+    JG uint32_t* err;
+    JG uint8_t* modes;           // [n_items] 0 = I, 1 = P (written by the parse)
+    JG uint8_t* ws;              // per-record workspace, item_stride bytes each
     uint64_t item_stride;
     uint32_t off_cw, off_vw;  // offsets of the mask words inside a record's workspace
     uint32_t n_items, n_scans, n_attrs;
     uint32_t nwords, npx, max_groups;
     uint32_t n_tiles;
     uint32_t need_temporal;   // per-pixel pass over time needed
-    void* out_base[8];        // attribute planes
+    JG void* out_base[8];        // attribute planes
     uint32_t attr_wb[8], attr_P[8];
 };
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream);
