@@ -80,20 +80,24 @@ def stream_stats(s: bytes, widths, npx):
 
 
 def kernel_alg_bytes(name, st, x_bytes, n_items, nwords):
-    """Bytes each kernel must move for the whole workload (one launch)."""
+    """Bytes each kernel must move for the whole workload (one launch): its
+    inputs read once and its outputs written once, intermediates it cannot
+    avoid included (the valid-sample words, the packed frames)."""
     vb = 8 * nwords * n_items          # valid-sample words of every record
-    F, M, S, N = st["frame_bytes"], st["mask_bytes"], st["stream_bytes"], st["n_values"]
-    Xp = st["p_bytes"]
+    vbp = 8 * nwords * st["p_items"]   # the previous scan's, for P-records
+    F, M, S = st["frame_bytes"], st["mask_bytes"], st["stream_bytes"]
+    Xp = st["p_bytes"]                 # samples of the P-records
     table = {
-        "k_enc_mask": x_bytes + vb,
-        "k_enc_frames": x_bytes + Xp + F,
-        "k_enc_mframe": vb + M,
-        "k_enc_assemble": F + M + S,
-        "k_dec_parse": M + vb,
-        "k_dec_mask": 2 * vb,
-        "k_dec_frames": F + 4 * N,
-        "k_dec_scatter": 4 * N + vb + x_bytes,
-        "k_dec_temporal": 2 * Xp + vb,
+        "k_enc_mask": x_bytes + vb,            # samples in, valid words out
+        "k_enc_tiles": x_bytes + Xp + F,       # samples (+ previous scan) in, packed frames out
+        "k_enc_mframe": vb + vbp + M,          # valid words in, mask frames out
+        "k_enc_assemble": F + M + S,           # frames and masks in, stream out
+        "k_dec_parse": M + vb,                 # mask frames in, valid words out
+        "k_dec_mask": 2 * vb + vbp,            # mask chain over time
+        "k_dec_fsum": F,                       # packed frames in
+        "k_dec_group": F + vb + x_bytes,       # packed frames and valid words in, samples out
+        "k_dec_tiles": F + vb + x_bytes,
+        "k_dec_temporal": 3 * Xp,              # P-scans: read both scans, write one
     }
     return table.get(name)
 

@@ -578,10 +578,11 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     const uint32_t npx = L.height * L.width, nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame);
     size_t off = 0;
     const size_t o_res = off; off = al(off + sizeof(DecRes) * n);
-    const size_t o_err = off; off = al(off + sizeof(uint32_t));
+    const uint32_t nft = div_up(npx, kFTile);
+    const size_t o_err = off; off = al(off + sizeof(uint32_t) * 2);  // err, err2
     const size_t o_items = off; off = al(off + sizeof(DecItem) * n);
     const size_t up_end = off;
-    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 6);
+    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(4ull * (nft + 1)) + al(8ull * nft) + al(sizeof(DecTile) * nft) + al(4);
     const size_t o_modes = off; off = al(off + n);
     const size_t o_data = off;
     off += per_item * n;
@@ -606,8 +607,14 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
             it.vw = (uint64_t*)base; base += al(8ull * nwords);
             it.blkinfo = (uint32_t*)base;
             it.blkoffs = it.blkinfo + maxnb;
-            it.bsum = it.blkinfo + 4 * maxnb;
-            it.blklast = it.blkinfo + 5 * maxnb;
+            base += al(4ull * maxnb * 4);
+            it.tbase = (uint32_t*)base;
+            base += al(4ull * (nft + 1));
+            it.status = (uint64_t*)base;
+            base += al(8ull * nft);
+            it.tdesc = (DecTile*)base;
+            base += al(sizeof(DecTile) * nft);
+            it.tctr = (uint32_t*)base;
             it.npx = npx;
             it.nwords = nwords;
             it.wb = L.width_bytes[a];
@@ -625,6 +632,8 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     plan.items = (const DecItem*)(dev + o_items);
     plan.res = (DecRes*)(dev + o_res);
     plan.err = (uint32_t*)(dev + o_err);
+    plan.err2 = plan.err + 1;
+    plan.nft = nft;
     plan.n_items = n;
     plan.n_scans = T;
     plan.n_attrs = A;
@@ -645,11 +654,11 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     }
     if (launch_decode(plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
-    if (hipMemcpyAsync(ctx.down.p, dev + o_err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipMemcpyAsync(ctx.down.p, dev + o_err, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     prof_collect();
-    const uint32_t err = *(const uint32_t*)ctx.down.p;
-    return err ? JIFFY_E_CORRUPT : JIFFY_OK;
+    const uint32_t* errs = (const uint32_t*)ctx.down.p;
+    return (errs[0] | errs[1]) ? JIFFY_E_CORRUPT : JIFFY_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -5,18 +5,19 @@
 //                  bytes, residual-section header and its frame offsets
 //   k_dec_mask     mask chain over time: a P-scan's mask is its content XOR
 //                  the previous mask (Sec. III-D); valid-sample words
-//   k_dec_scan     running count of valid samples; where each frame ends
-//   k_dec_fsum     bit unpacking, exception patching (Sec. II), inverse
-//                  ZigZag (Eq. 1); the sum of each frame's deltas
-//   k_dec_bscan    running sum over frames (undoes the delta, Sec. III-C)
-//   k_dec_group    unpacks a group of frames again, running sums inside
-//                  them, values back to their pixels, zeros elsewhere
+//   k_dec_scan     running count of valid samples before every tile
+//   k_dec_tiles    bit unpacking, exception patching (Sec. II), inverse
+//                  ZigZag (Eq. 1), running sum (undoes the delta, Sec.
+//                  III-C) chained across tiles, values back to their
+//                  pixels, zeros elsewhere
 //   k_dec_temporal adds the previous scan for P-scans (Sec. III-D) and
 //                  restores the original representation, q * P (Sec. III-A)
 //
 // Every offset read from the stream is checked before it is used; a
 // malformed stream raises kErrCorrupt and later kernels do nothing.
 #define JIFFY_KERNEL_TU 1
+#include <type_traits>
+
 #include "jiffy_device.h"
 
 namespace jiffy {
@@ -346,257 +347,302 @@ __global__ __launch_bounds__(64) void k_dec_mask(DecPlan plan) {
     if (bad) atomicOr(plan.err, kErrCorrupt);
 }
 
+constexpr uint32_t kDecThreads = 320;                 // 80 quads: enough for the 65 frames a tile can touch
+constexpr uint32_t kFrameMaxWords = 160;              // a frame's packed bytes are at most 640
+constexpr uint32_t kStageWords = 3680;                // staged packed words (larger tiles read memory)
+
 // ---------------------------------------------------------------------------
 // Running count of valid samples: N must match the section header; the
-// pixel of every frame's last value (where each frame group ends).
+// count before every kFTile-pixel tile.  Then each tile's descriptor: its
+// values [kb, ke) and the word ranges of the record that hold its frames'
+// payloads, exception positions and exception high parts.  The tiles'
+// look-back states are cleared here, before k_dec_tiles.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
     if (*plan.err) return;
     const uint32_t r = blockIdx.x;
     const DecItem it = plan.items[r];
+    const DecRes rs = plan.res[r];
     __shared__ uint32_t scratch[20];
+    constexpr uint32_t kTW = kFTile / 64;  // words per tile
+    for (uint32_t lt = threadIdx.x; lt < plan.nft; lt += 1024) it.status[lt] = 0ull;
+    if (threadIdx.x == 0) *it.tctr = 0u;
     uint32_t carry = 0;
     for (uint32_t w0 = 0; w0 < it.nwords; w0 += 1024) {
         const uint32_t w = w0 + threadIdx.x;
         const uint64_t v = w < it.nwords ? it.vw[w] : 0ull;
-        const uint32_t pc = __popcll(v);
         uint32_t total;
-        const uint32_t pre = block_excl_scan<1024>(pc, scratch, &total) + carry;
-        if (pc) {
-            const uint32_t k = pre + ((127u - pre) & 127u);  // first frame end at or after pre
-            if (k < pre + pc && (k >> 7) < it.maxnb) it.blklast[k >> 7] = 64u * w + select_bit(v, k - pre);
-        }
+        const uint32_t pre = block_excl_scan<1024>(__popcll(v), scratch, &total) + carry;
+        if (w < it.nwords && w % kTW == 0) it.tbase[w / kTW] = pre;
         carry += total;
     }
-    if (threadIdx.x == 0 && carry != plan.res[r].N) atomicOr(plan.err, kErrCorrupt);
-}
-
-// ---------------------------------------------------------------------------
-// Frame unpacking (Sec. II).  A workgroup stages the packed bytes of a group
-// of frames in LDS first: the group's payloads, exception positions and
-// exception high parts are three contiguous byte ranges of the record, read
-// with coalesced word loads.  One wave then unpacks one frame: the 128
-// slots, the exception high parts patched in, inverse ZigZag (Eq. 1).
-// Lane l gets the deltas of slots l and l + 64 (0 past the real values).
-// ---------------------------------------------------------------------------
-constexpr uint32_t kStageWords = 512;  // valid-sample words staged per group (more are read from memory)
-
-struct GroupStage {
-    uint32_t info[kGroupFrames];
-    uint32_t offs[kGroupFrames + 1][3];  // relative to the group's first frame
-    uint32_t base[3];                    // word-aligned start of each staged range in the record
-    uint32_t fbase[kGroupFrames];        // running sum before each frame (k_dec_group)
-    uint32_t prange[2];                  // first and last pixel of the group (k_dec_group)
-    uint64_t vw[kStageWords];            // valid words of the pixel range (k_dec_group)
-    uint32_t pay[kGroupFrames * 128 + 2];
-    uint32_t pos[kGroupFrames * 32 + 2];
-    uint32_t high[kGroupFrames * 128 + 2];
-    uint32_t zf[4][128];
-};
-
-__device__ __forceinline__ uint32_t bits_at(const uint32_t* w, uint32_t bp, uint32_t width) {
-    if (width == 0) return 0;
-    const uint64_t v = (uint64_t)w[bp >> 5] | ((uint64_t)w[(bp >> 5) + 1] << 32);
-    return (uint32_t)(v >> (bp & 31)) & low_mask32(width);
-}
-
-// all threads: metadata of frames [j0, j1) and their packed bytes into S;
-// with `scatter` also the frames' running-sum bases, the group's pixel
-// range and its valid words.  Independent loads are issued together.
-__device__ __forceinline__ void stage_group(const DecItem& it, const DecRes& rs, uint32_t j0, uint32_t j1,
-                                            GroupStage& S, bool scatter) {
-    const uint32_t tid = threadIdx.x, cnt = j1 - j0;
-    if (scatter) {
-        if (tid < cnt) S.fbase[tid] = it.bsum[j0 + tid];
-        if (tid == 64) S.prange[0] = j0 == 0 ? 0u : it.blklast[j0 - 1] + 1;
-        if (tid == 65) S.prange[1] = (j1 >= rs.nb) ? it.npx - 1 : it.blklast[j1 - 1];
-    }
-    if (tid <= cnt && cnt) {
-        const uint32_t j = j0 + tid;
-        uint32_t o0, o1, o2;
-        if (j < rs.nb) {
-            o0 = it.blkoffs[3 * j];
-            o1 = it.blkoffs[3 * j + 1];
-            o2 = it.blkoffs[3 * j + 2];
-        } else {  // end of the sections
-            o0 = rs.pos_off - rs.pay_off;
-            o1 = rs.high_off - rs.pos_off;
-            o2 = rs.high_end - rs.high_off;
-        }
-        S.offs[tid][0] = o0;
-        S.offs[tid][1] = o1;
-        S.offs[tid][2] = o2;
-        if (tid < cnt) S.info[tid] = it.blkinfo[j];
+    if (threadIdx.x == 0) {
+        it.tbase[plan.nft] = carry;
+        if (carry != rs.N) atomicOr(plan.err, kErrCorrupt);
     }
     __syncthreads();
-    if (scatter) {
-        const uint32_t v0 = S.prange[0] >> 6, v1 = min((S.prange[1] >> 6) + 1, v0 + kStageWords);
-        for (uint32_t w = v0 + tid; w < v1; w += 256) S.vw[w - v0] = it.vw[w];
-    }
-    if (cnt) {
-        const uint32_t starts[3] = {rs.pay_off + S.offs[0][0], rs.pos_off + S.offs[0][1],
-                                    rs.high_off + S.offs[0][2]};
-        const uint32_t ends[3] = {rs.pay_off + S.offs[cnt][0], rs.pos_off + S.offs[cnt][1],
-                                  rs.high_off + S.offs[cnt][2]};
-        uint32_t* dst[3] = {S.pay, S.pos, S.high};
-        const uint32_t cap[3] = {kGroupFrames * 128 + 2, kGroupFrames * 32 + 2, kGroupFrames * 128 + 2};
-        const uint32_t* recw = (const uint32_t*)it.rec;  // records are 4-byte aligned
+    if (carry != rs.N) return;
+    const uint32_t sec[3] = {rs.pay_off, rs.pos_off, rs.high_off};
+    const uint32_t send[3] = {rs.pos_off - rs.pay_off, rs.high_off - rs.pos_off, rs.high_end - rs.high_off};
+    bool bad = false;
+    for (uint32_t lt = threadIdx.x; lt < plan.nft; lt += 1024) {
+        const uint32_t kb = it.tbase[lt], ke = it.tbase[lt + 1];
+        const uint32_t jf = kb >> 7, j1 = ke > kb ? ((ke - 1) >> 7) + 1 : jf;  // frames [jf, j1)
+        DecTile d;
+        d.kb = kb;
+        d.ke = ke;
+        uint32_t words = 0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const uint32_t w0 = starts[q] >> 2, w1 = (ends[q] + 3) >> 2;
-            for (uint32_t w = w0 + tid; w < w1 && w - w0 < cap[q]; w += 256) dst[q][w - w0] = recw[w];
-            if (tid == 0) S.base[q] = w0 * 4;
+            const uint32_t a = jf < rs.nb ? it.blkoffs[3 * jf + q] : send[q];
+            const uint32_t e = j1 < rs.nb ? it.blkoffs[3 * j1 + q] : send[q];
+            d.w0[q] = (sec[q] + a) >> 2;
+            d.nw[q] = j1 > jf ? ((sec[q] + e + 3) >> 2) - d.w0[q] : 0u;
+            words += d.nw[q];
         }
+        bad |= words > (j1 - jf) * kFrameMaxWords + 6;  // more than 640 bytes per frame: not a valid frame set
+        it.tdesc[lt] = d;
     }
-    __syncthreads();
+    if (bad) atomicOr(plan.err, kErrCorrupt);
 }
 
-// one wave: frame k of the staged group
-__device__ __forceinline__ void unpack_staged(const DecPlan& plan, const DecItem& it, const DecRes& rs,
-                                              GroupStage& S, uint32_t j0, uint32_t k, uint32_t wave, uint32_t& d0,
-                                              uint32_t& d1) {
+// ---------------------------------------------------------------------------
+// Frame unpacking and the running sum, per kFTile-pixel tile (Sec. II,
+// Sec. III-C reversed).  One workgroup per tile of one record, in ticket
+// order:
+//   1. the packed bytes of the frames the tile's values fall in (payloads,
+//      exception positions, exception high parts: three contiguous ranges
+//      of the record) are staged in LDS with coalesced word loads;
+//   2. four lanes per frame unpack the low bits (lane q: values 32q..32q+31)
+//      into the frame's LDS row, patch the exceptions' high parts in, and
+//      undo ZigZag (Eq. 1);
+//   3. a workgroup scan sums the deltas of the tile's values; the running
+//      sum before the tile comes from the tiles before it (decoupled
+//      look-back: each tile publishes its own sum, then the running sum
+//      through it);
+//   4. the tile's pixels are written: the k-th valid pixel gets value k,
+//      the others zero.
+// For a P-scan the values are differences to the previous scan (added by
+// k_dec_temporal); for P > 1 they are quantized (restored there too).
+// ---------------------------------------------------------------------------
+constexpr uint64_t kStAgg = 1ull << 32, kStIncl = 2ull << 32;  // look-back status flags
+constexpr uint32_t kSpinMax = 1u << 16;                // look-back polls before giving up
+
+struct DecTileLds {
+    uint32_t rows[kTileFrames * kRow];
+    uint32_t stage[kStageWords + 2];
+    uint32_t info[kTileFrames];
+    uint32_t offs[kTileFrames + 1][3];  // frame offsets in the three sections
+    uint32_t scratch[8];
+    uint32_t ticket, base, bad;
+};
+
+// `width` bits from bit bp of a little-endian word array.  Without kExact
+// it may read the word after the bits (the staged copy has room for it);
+// with kExact (the record itself) it never reads past them.
+template <bool kExact, class W>
+__device__ __forceinline__ uint32_t bits_at(W* w, uint32_t bp, uint32_t width) {
+    const uint32_t sh = bp & 31;
+    uint64_t v = w[bp >> 5];
+    if (!kExact || sh + width > 32) v |= (uint64_t)w[(bp >> 5) + 1] << 32;
+    return (uint32_t)(v >> sh) & low_mask32(width);
+}
+
+// One wave: publishes the tile's sum, then sums the tiles before it from the
+// nearest one whose running sum is known, 64 tiles per round.  Returns the
+// running sum before the tile.
+__device__ uint32_t dec_lookback(JG uint64_t* st, uint32_t lt, uint32_t agg, JG uint32_t* err2) {
     const uint32_t l = lane_id();
-    const uint32_t j = j0 + k;
-    const uint32_t info = S.info[k];
-    const uint32_t b = info & 0xFF, n = (info >> 8) & 0xFF, B = (info >> 16) & 0xFF;
-    const uint32_t hwid = B - b;
-    const uint32_t real = min(kFrame, rs.N - j * kFrame);
-    const uint32_t pw0 = (rs.pay_off + S.offs[k][0] - S.base[0]) >> 2;  // payloads are word aligned
-    const uint8_t* posb = (const uint8_t*)S.pos + (rs.pos_off + S.offs[k][1] - S.base[1]);
-    const uint32_t hbit0 = 8 * (rs.high_off + S.offs[k][2] - S.base[2]);
-    uint32_t* zf = S.zf[wave];
-    zf[l] = bits_at(S.pay + pw0, l * b, b);
-    zf[l + 64] = bits_at(S.pay + pw0, (l + 64) * b, b);
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t e = l; e < n; e += 64) {
-        const uint32_t p = posb[e];
-        const bool ok = p < real && (e == 0 || posb[e - 1] < p);
-        if (!ok) { atomicOr(plan.err, kErrCorrupt); continue; }
-        zf[p] |= bits_at(S.high, hbit0 + e * hwid, hwid) << b;
+    if (l == 0) __hip_atomic_store(st + lt, (lt ? kStAgg : kStIncl) | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lt == 0) return 0;
+    uint32_t excl = 0, end = lt, spins = 0;  // tiles [0, end) not summed yet
+    for (;;) {
+        const int idx = (int)end - 1 - (int)l;  // lane 0: the nearest
+        uint64_t s = kStIncl;                    // before the first tile: running sum 0
+        if (idx >= 0) s = __hip_atomic_load(st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t f = s & ~0xFFFFFFFFull;
+        const uint64_t incl = ballot(f == kStIncl), empty = ballot(f == 0);
+        const uint32_t fi = incl ? (uint32_t)__builtin_ctzll(incl) : 64u;
+        const uint32_t fe = empty ? (uint32_t)__builtin_ctzll(empty) : 64u;
+        if (fe < fi) {  // a nearer tile has not published: take the sums before it, poll again
+            if (fe) {
+                excl += wave_sum(l < fe ? (uint32_t)s : 0u);
+                end -= fe;
+            }
+            if (++spins > kSpinMax) {  // never expected: a tile before this one did not publish
+                if (l == 0) atomicOr(err2, kErrCorrupt);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_sum(l <= fi ? (uint32_t)s : 0u);
+        if (fi < 64) break;
+        end -= 64;
     }
-    __builtin_amdgcn_wave_barrier();
-    d0 = l < real ? unzigzag(zf[l], it.bits) : 0u;
-    d1 = l + 64 < real ? unzigzag(zf[l + 64], it.bits) : 0u;
-    __builtin_amdgcn_wave_barrier();
+    if (l == 0) __hip_atomic_store(st + lt, kStIncl | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
 }
 
-// per-frame sums of the deltas (mod 2^w)
-__global__ __launch_bounds__(256) void k_dec_fsum(DecPlan plan) {
-    if (*plan.err) return;
-    const uint32_t r = blockIdx.y;
-    const DecItem it = plan.items[r];
-    const DecRes rs = plan.res[r];
-    const uint32_t j0 = blockIdx.x * kGroupFrames;
-    if (j0 >= rs.nb) return;
-    const uint32_t j1 = min(j0 + kGroupFrames, rs.nb);
-    __shared__ GroupStage S;
-    stage_group(it, rs, j0, j1, S, false);
-    const uint32_t wave = threadIdx.x / kWave;
-    for (uint32_t k = wave; k < j1 - j0; k += 4) {
-        uint32_t d0, d1;
-        unpack_staged(plan, it, rs, S, j0, k, wave, d0, d1);
-        const uint32_t s = wave_sum(d0 + d1);
-        if (lane_id() == 0) it.bsum[j0 + k] = s & low_mask32(it.bits);
+// Four lanes unpack frame jf + g: W holds the packed bytes (the staged copy
+// or the record), pay_w is the frame's first payload word, pos_b its first
+// exception-position byte, high_bit its first high-part bit.  d gets the
+// lane's running sum of the deltas of the tile's values.
+template <bool kStaged, class W = typename std::conditional<kStaged, const uint32_t, const JG uint32_t>::type>
+__device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, DecTileLds& L, W* words, uint32_t g,
+                                           uint32_t q, uint32_t kb, uint32_t ke, uint32_t jf, uint32_t pay_w,
+                                           uint32_t pos_b, uint32_t high_bit, uint32_t d[32], uint32_t& lane_sum) {
+    const uint32_t j = jf + g;
+    const uint32_t info = L.info[g];
+    const uint32_t b = info & 0xFFu, n = (info >> 8) & 0xFFu, B = (info >> 16) & 0xFFu;
+    const uint32_t hw = B - b, real = min(kFrame, rs.N - j * kFrame);
+    uint32_t* row = L.rows + g * kRow;
+    W* pay = words + pay_w;
+    const uint32_t i0 = 32u * q;
+    uint32_t z[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) z[i] = b ? bits_at<!kStaged>(pay, (i0 + i) * b, b) : 0u;
+    {
+        uint4* r4 = (uint4*)(row + 36 * q);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) r4[c] = make_uint4(z[4 * c], z[4 * c + 1], z[4 * c + 2], z[4 * c + 3]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (n) {
+        using B8 = typename std::conditional<kStaged, const uint8_t, const JG uint8_t>::type;
+        B8* pos = (B8*)words + pos_b;
+        uint32_t bad = 0;
+        for (uint32_t e = q; e < n; e += 4) {
+            const uint32_t p = pos[e];
+            if (p >= real || (e && pos[e - 1] >= p)) { bad = 1; continue; }
+            row[row_off(p)] |= bits_at<!kStaged>(words, high_bit + e * hw, hw) << b;
+        }
+        if (bad) atomicOr(&L.bad, 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    {
+        const uint4* r4 = (const uint4*)(row + 36 * q);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint4 v = r4[c];
+            z[4 * c] = v.x; z[4 * c + 1] = v.y; z[4 * c + 2] = v.z; z[4 * c + 3] = v.w;
+        }
+    }
+    // deltas of the tile's own values, inclusive running sum over the lane
+    const uint32_t k0 = j * kFrame + i0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const uint32_t k = k0 + i;
+        lane_sum += (k >= kb && k < ke) ? unzigzag(z[i], it.bits) : 0u;
+        d[i] = lane_sum;
     }
 }
 
-// exclusive running sum over the frames (mod 2^w): each frame's base value
-__global__ __launch_bounds__(1024) void k_dec_bscan(DecPlan plan) {
-    if (*plan.err) return;
-    const uint32_t r = blockIdx.x;
-    const DecItem it = plan.items[r];
-    const uint32_t nb = plan.res[r].nb;
-    const uint32_t m = low_mask32(it.bits);
-    __shared__ uint32_t scratch[20];
-    uint32_t carry = 0;
-    for (uint32_t j0 = 0; j0 < nb; j0 += 1024) {
-        const uint32_t j = j0 + threadIdx.x;
-        const uint32_t v = j < nb ? it.bsum[j] : 0u;
-        uint32_t total;
-        const uint32_t pre = block_excl_scan<1024>(v, scratch, &total) + carry;
-        if (j < nb) it.bsum[j] = pre & m;
-        carry += total;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// One workgroup per group of kGroupFrames frames: the frames' running sums
-// (undoing the delta, Sec. III-C) go to LDS, then the group's pixel range is
-// written: the k-th valid pixel gets value k, the others zero.  The ranges
-// of consecutive groups tile the scan.  For a P-scan the value is the
-// difference to the previous scan (added by k_dec_temporal); for P > 1 the
-// quantized value (restored there too).
-// ---------------------------------------------------------------------------
 template <int WB>
-__device__ __forceinline__ void dec_group_scatter(const DecItem& it, const GroupStage& S, const uint32_t* sv,
-                                                  uint32_t* scratch) {
-    using T = typename SampleT<WB>::T;
-    T* out = (T*)it.out;
-    const uint32_t p_lo = S.prange[0], p_hi = S.prange[1];
-    const uint32_t v0 = p_lo >> 6;
-    uint32_t cnt = 0;
-    for (uint32_t c0 = p_lo & ~15u; c0 <= p_hi; c0 += 256 * 16) {
-        const uint32_t p0 = c0 + threadIdx.x * 16;
-        uint32_t bits16 = 0, inr = 0;
-        if (p0 <= p_hi && p0 + 15 >= p_lo && p0 < it.npx) {
-            const uint32_t w = p0 >> 6;
-            const uint64_t v = (w - v0 < kStageWords) ? S.vw[w - v0] : it.vw[w];
-            bits16 = (uint32_t)(v >> (16 * ((p0 >> 4) & 3))) & 0xFFFFu;
-            const uint32_t lo = p0 < p_lo ? p_lo - p0 : 0u;
-            const uint32_t hi = p_hi - p0 >= 15 ? 15u : p_hi - p0;
-            inr = ((0xFFFFu >> (15 - hi)) >> lo) << lo;  // pixels p0+lo .. p0+hi
-            bits16 &= inr;
-        }
-        uint32_t total;
-        uint32_t k = block_excl_scan<256>(__popc(bits16), scratch, &total) + cnt;
-        uint32_t vals[16];
+__device__ __forceinline__ void dec_tile_scatter(const DecItem& it, uint32_t p0, uint32_t bits, uint32_t k,
+                                                 uint32_t jf, const DecTileLds& L) {
+    uint32_t v[32];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            uint32_t val = 0;
-            if (bits16 & (1u << i)) val = sv[k++];
-            vals[i] = val;
-        }
-        if (inr == 0xFFFFu && it.aligned16) {
-            store16<WB>(it.out, p0, it.npx, true, vals);
-        } else if (inr) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (inr & (1u << i)) out[p0 + i] = (T)vals[i];
-        }
-        cnt += total;
+    for (int i = 0; i < 32; ++i) {
+        const bool on = (bits >> i) & 1u;
+        v[i] = on ? L.rows[tile_word(k, jf)] : 0u;
+        k += on ? 1u : 0u;
     }
+    store16<WB>(it.out, p0, it.npx, it.aligned16, v);
+    if (p0 + 16 < it.npx) store16<WB>(it.out, p0 + 16, it.npx, it.aligned16, v + 16);
 }
 
-__global__ __launch_bounds__(256) void k_dec_group(DecPlan plan) {
-    if (*plan.err) return;
-    const uint32_t r = blockIdx.y;
+__global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan) {
+    if (*plan.err) return;  // set before this launch; this kernel reports through err2
+    __shared__ DecTileLds L;
+    const uint32_t tid = threadIdx.x;
+    // the record is fixed by the workgroup index; the tile within it is taken
+    // in arrival order, so every tile a workgroup waits for has started
+    const uint32_t r = blockIdx.x / plan.nft;
     const DecItem it = plan.items[r];
-    const DecRes rs = plan.res[r];
-    const uint32_t g = blockIdx.x;
-    const uint32_t j0 = g * kGroupFrames;
-    if (j0 >= rs.nb && !(g == 0 && rs.nb == 0)) return;
-    const uint32_t j1 = min(j0 + kGroupFrames, rs.nb);
-    __shared__ GroupStage S;
-    __shared__ uint32_t sv[kGroupFrames * kFrame];
-    __shared__ uint32_t scratch[8];
-    const uint32_t wave = threadIdx.x / kWave, l = lane_id();
-    const uint32_t m = low_mask32(it.bits);
-    stage_group(it, rs, j0, j1, S, true);
-    for (uint32_t k = wave; k < j1 - j0; k += 4) {
-        uint32_t d0, d1;
-        unpack_staged(plan, it, rs, S, j0, k, wave, d0, d1);
-        const uint32_t a0 = wave_incl_scan(d0) + S.fbase[k];
-        const uint32_t t0 = (uint32_t)__shfl((int)a0, 63, kWave);
-        const uint32_t a1 = wave_incl_scan(d1) + t0;
-        uint32_t* dst = sv + k * kFrame;
-        dst[l] = a0 & m;
-        dst[l + 64] = a1 & m;
+    if (tid == 0) {
+        L.ticket = atomicAdd(it.tctr, 1u);
+        L.bad = 0;
     }
     __syncthreads();
+    const uint32_t lt = L.ticket;
+    const DecRes rs = plan.res[r];
+    const DecTile D = it.tdesc[lt];
+    const uint32_t m = low_mask32(it.bits);
+    const uint32_t kb = D.kb, ke = D.ke;
+    const uint32_t jf = kb >> 7;
+    const uint32_t nf = ke > kb ? ((ke - 1) >> 7) - jf + 1 : 0u;  // frames the tile's values lie in
+    // 1. everything the tile reads, issued together: its pixels' valid bits,
+    // the frames' metadata and packed bytes
+    const uint32_t p0 = lt * kFTile + tid * 32;
+    const bool scat = tid < kFTile / 32 && p0 < it.npx;
+    const uint32_t pbits = scat ? (uint32_t)(it.vw[p0 >> 6] >> (32 * ((p0 >> 5) & 1))) : 0u;
+    if (tid <= nf && nf) {
+        const uint32_t j = jf + tid;
+        if (j < rs.nb) {
+            L.offs[tid][0] = it.blkoffs[3 * j];
+            L.offs[tid][1] = it.blkoffs[3 * j + 1];
+            L.offs[tid][2] = it.blkoffs[3 * j + 2];
+            if (tid < nf) L.info[tid] = it.blkinfo[j];
+        } else {  // the ends of the sections
+            L.offs[tid][0] = rs.pos_off - rs.pay_off;
+            L.offs[tid][1] = rs.high_off - rs.pos_off;
+            L.offs[tid][2] = rs.high_end - rs.high_off;
+        }
+    }
+    const uint32_t n01 = D.nw[0] + D.nw[1], nall = n01 + D.nw[2];
+    const bool staged = nall <= kStageWords;  // else the frames are read from the record
+    if (staged) {
+        const uint32_t* recw = (const uint32_t*)it.rec;  // records are 4-byte aligned
+        for (uint32_t i = tid; i < nall; i += kDecThreads) {
+            const uint32_t src = i < D.nw[0] ? D.w0[0] + i : (i < n01 ? D.w0[1] + (i - D.nw[0]) : D.w0[2] + (i - n01));
+            L.stage[i] = recw[src];
+        }
+    }
+    __syncthreads();
+    // 2. unpack: quad g decodes frame jf + g
+    const uint32_t g = tid >> 2, q = tid & 3u;
+    uint32_t d[32];
+    uint32_t lane_sum = 0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) d[i] = 0;
+    if (g < nf) {
+        if (staged)
+            dec_unpack<true>(it, rs, L, L.stage, g, q, kb, ke, jf,
+                                       ((rs.pay_off + L.offs[g][0]) >> 2) - D.w0[0],
+                                       4 * D.nw[0] + rs.pos_off + L.offs[g][1] - 4 * D.w0[1],
+                                       8 * (4 * (D.nw[0] + D.nw[1]) + rs.high_off + L.offs[g][2] - 4 * D.w0[2]), d,
+                                       lane_sum);
+        else
+            dec_unpack<false>(it, rs, L, (const JG uint32_t*)it.rec, g, q, kb, ke, jf,
+                                          (rs.pay_off + L.offs[g][0]) >> 2, rs.pos_off + L.offs[g][1],
+                                          8 * (rs.high_off + L.offs[g][2]), d, lane_sum);
+    }
+    // 3. running sum: lanes are in value order (quads in frame order)
+    uint32_t agg;
+    const uint32_t excl = block_excl_scan<kDecThreads>(lane_sum, L.scratch, &agg);
+    if (tid < kWave) {
+        const uint32_t base = dec_lookback(it.status, lt, agg, plan.err2);
+        if (tid == 0) L.base = base;
+    }
+    __syncthreads();
+    if (tid == 0 && L.bad) atomicOr(plan.err2, kErrCorrupt);
+    if (g < nf) {
+        const uint32_t v0 = L.base + excl;
+        uint4* r4 = (uint4*)(L.rows + g * kRow + 36 * q);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            r4[c] = make_uint4((v0 + d[4 * c]) & m, (v0 + d[4 * c + 1]) & m, (v0 + d[4 * c + 2]) & m,
+                               (v0 + d[4 * c + 3]) & m);
+    }
+    // 4. the tile's pixels: the k-th valid pixel gets value k
+    uint32_t total;
+    const uint32_t k = kb + block_excl_scan<kDecThreads>(__popc(pbits), L.scratch, &total);  // also a barrier
+    if (!scat) return;
     switch (it.wb) {
-        case 4: dec_group_scatter<4>(it, S, sv, scratch); break;
-        case 2: dec_group_scatter<2>(it, S, sv, scratch); break;
-        default: dec_group_scatter<1>(it, S, sv, scratch); break;
+        case 4: dec_tile_scatter<4>(it, p0, pbits, k, jf, L); break;
+        case 2: dec_tile_scatter<2>(it, p0, pbits, k, jf, L); break;
+        default: dec_tile_scatter<1>(it, p0, pbits, k, jf, L); break;
     }
 }
 
@@ -667,9 +713,7 @@ hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(plan.nwords, 64), plan.n_attrs), dim3(64), stream, plan);
     JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
-    JIFFY_LAUNCH("k_dec_fsum", k_dec_fsum, dim3(plan.max_groups, plan.n_items), dim3(256), stream, plan);
-    JIFFY_LAUNCH("k_dec_bscan", k_dec_bscan, dim3(plan.n_items), dim3(1024), stream, plan);
-    JIFFY_LAUNCH("k_dec_group", k_dec_group, dim3(plan.max_groups, plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_dec_tiles", k_dec_tiles, dim3(plan.n_items * plan.nft), dim3(kDecThreads), stream, plan);
     if (plan.need_temporal)
         JIFFY_LAUNCH("k_dec_temporal", k_dec_temporal, dim3(div_up(plan.npx, 256 * 16), plan.n_attrs), dim3(256),
                      stream, plan);

@@ -205,6 +205,24 @@ __device__ __forceinline__ FrameChoice choose_frame(uint32_t z0, uint32_t z1) {
     return FrameChoice{b, nb, B, key >> 6};
 }
 
+// ---- frame rows (a frame of 128 values in LDS, four lanes per frame) -----
+constexpr uint32_t kRow = kSlotBytes / 4;  // LDS words per frame row
+static_assert(kRow >= kFrame + 12 && kRow % 4 == 0, "a frame row holds 128 values, padded every 32");
+
+// word of value i in a frame row: four pad words after every 32 values, so
+// that each lane's 32 values start 16-byte aligned in distinct banks
+__device__ __forceinline__ uint32_t row_off(uint32_t i) { return i + ((i >> 5) << 2); }
+
+// DPP quad permutations
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;
+template <int Q> __device__ __forceinline__ uint32_t quad_bcast(uint32_t v) { return dpp_mov<0x55 * Q>(v); }
+
+constexpr uint32_t kTileFrames = kFTile / kFrame + 1;  // frames a tile's values can touch
+constexpr uint32_t kTileQuads = kFTile / kFrame;       // frames a tile can hold whole
+
+// value kb.. of a tile: frame (k >> 7) - jf of the tile's rows
+__device__ __forceinline__ uint32_t tile_word(uint32_t k, uint32_t jf) { return ((k >> 7) - jf) * kRow + row_off(k & 127u); }
+
 // ---- 16-sample vector access -------------------------------------------
 template <int WB> struct SampleT;
 template <> struct SampleT<1> { using T = uint8_t; };

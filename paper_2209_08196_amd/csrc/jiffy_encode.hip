@@ -185,16 +185,6 @@ __global__ __launch_bounds__(1024) void k_enc_scan(EncPlan plan) {
 // cost(b) for eight of the 32 widths and the quad takes the minimum.  The
 // frame is built in an LDS row and copied to its slot with 16-byte stores.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kRow = kSlotBytes / 4;  // LDS words per frame row
-static_assert(kRow >= kFrame + 12 && kRow % 4 == 0, "a frame row holds 128 values, padded every 32");
-
-// word of value i in a frame row: four pad words after every 32 values, so
-// that each lane's 32 values start 16-byte aligned in distinct banks
-__device__ __forceinline__ uint32_t row_off(uint32_t i) { return i + ((i >> 5) << 2); }
-
-// DPP quad permutations
-constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;
-template <int Q> __device__ __forceinline__ uint32_t quad_bcast(uint32_t v) { return dpp_mov<0x55 * Q>(v); }
 
 // vrow: the frame's values (row layout); on return it holds their ZigZag
 // codes.  orow: the quad's output row.  real: number of real values (the
@@ -335,8 +325,6 @@ __device__ __forceinline__ uint32_t residual_at(const EncItem& it, uint32_t mode
     return (q - qp) & m;
 }
 
-constexpr uint32_t kTileFrames = kFTile / kFrame + 1;  // frames a tile can touch
-constexpr uint32_t kTileQuads = kFTile / kFrame;       // frames a tile can hold whole
 
 struct TileLds {
     uint32_t rows[(kTileFrames + kTileQuads) * kRow];  // frame rows, then the quads' output rows
@@ -389,7 +377,7 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
             const bool kp = (keep >> i) & 1u;
-            L.rows[kp ? ((k >> 7) - jf) * kRow + row_off(k & 127u) : dummy] = s[i];
+            L.rows[kp ? tile_word(k, jf) : dummy] = s[i];
             k += kp ? 1u : 0u;
         }
     }
@@ -404,7 +392,7 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
     const bool head_part = (kb & 127u) != 0;               // frame jf began in an earlier tile
     const bool tail_part = kl1 > ke && !(jl == jf && head_part);  // frame jl starts here, ends later
     if (tid == 0) it.tfix[lt] = tail_part ? jl : kNoFix;
-    auto value_at = [&](uint32_t k) { return L.rows[((k >> 7) - jf) * kRow + row_off(k & 127u)]; };
+    auto value_at = [&](uint32_t k) { return L.rows[tile_word(k, jf)]; };
     // stage the crossing frames: thread t < 128 value t of frame jf, t >= 128 value t - 128 of frame jl
     if (tid < kFrame) {
         const uint32_t k = (jf << 7) + tid;

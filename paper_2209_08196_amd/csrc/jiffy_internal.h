@@ -104,6 +104,14 @@ struct EncOut {
     uint32_t attr_p[8];
 };
 
+// A decode tile: its values [kb, ke) and, for the payload, exception
+// position and exception high-part sections, the first record word and the
+// number of words that hold the tile's frames.
+struct DecTile {
+    uint32_t kb, ke;
+    uint32_t w0[3], nw[3];
+};
+
 // One record to decode.
 struct DecItem {
     const JG uint8_t* rec;
@@ -113,8 +121,10 @@ struct DecItem {
     JG uint64_t* vw;             // valid-sample words
     JG uint32_t* blkinfo;        // [maxnb]
     JG uint32_t* blkoffs;        // [3 * maxnb]
-    JG uint32_t* bsum;           // [maxnb] frame sums, then exclusive prefixes
-    JG uint32_t* blklast;        // [maxnb] pixel of each frame's last value
+    JG uint32_t* tbase;          // [nft + 1] valid samples before each kFTile tile (and N)
+    JG DecTile* tdesc;           // [nft]
+    JG uint32_t* tctr;           // k_dec_tiles ticket counter of the record
+    JG uint64_t* status;         // [nft] look-back state of each tile
     uint32_t npx, nwords, wb, bits;
     uint32_t attr, t, P, maxnb;
     uint32_t aligned16, pad0;
@@ -156,6 +166,7 @@ struct DecPlan {
     const JG DecItem* items;
     JG DecRes* res;
     JG uint32_t* err;
+    JG uint32_t* err2;           // errors found by k_dec_tiles
     JG uint8_t* modes;           // [n_items] 0 = I, 1 = P (written by the parse)
     JG uint8_t* ws;              // per-record workspace, item_stride bytes each
     uint64_t item_stride;
@@ -163,6 +174,7 @@ struct DecPlan {
     uint32_t n_items, n_scans, n_attrs;
     uint32_t nwords, npx, max_groups;
     uint32_t n_tiles;
+    uint32_t nft;             // kFTile tiles per record
     uint32_t need_temporal;   // per-pixel pass over time needed
     JG void* out_base[8];        // attribute planes
     uint32_t attr_wb[8], attr_P[8];

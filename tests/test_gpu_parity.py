@@ -194,3 +194,21 @@ def test_stress_128x4096_first_scans(J):
     g = synth.stream(5, 0)
     planes = g.scans(18, 22)  # crosses a scene cut at scan 20
     check_case(J, planes, g.precisions, name="c5 scans 18-21")
+
+
+def test_incompressible_tiles(J):
+    """Full-range random samples: frames near 32 bits wide, so a decode tile's
+    packed bytes exceed what the decoder stages in LDS and it reads them
+    from the record instead."""
+    import torch
+    rng = np.random.default_rng(31)
+    x = rng.integers(1, 2**32, size=(3, 64, 1024), dtype=np.uint64).astype(np.uint32)
+    x[1, :, 100:140] = 0
+    y = rng.integers(0, 2**16, size=(3, 64, 1024), dtype=np.uint64).astype(np.uint16)
+    for mode in (0, 2):
+        s_ref = check_case(J, [x, y], [1, 1], mode=mode, name=f"random u32+u16 mode {mode}")
+        ref = oracle.decode(s_ref)
+        banner("decode random, mode", mode)
+        outs = J.decode(torch.from_numpy(np.frombuffer(s_ref, np.uint8).copy()).cuda())
+        for o, r in zip(outs, ref):
+            assert np.array_equal(to_host(o, r.dtype.itemsize), r)
