@@ -102,6 +102,62 @@ def kernel_alg_bytes(name, st, x_bytes, n_items, nwords):
     return table.get(name)
 
 
+def copy_run(nbytes):
+    """A plain device copy of known size, three times: what FETCH_SIZE and
+    WRITE_SIZE read for it calibrates those counters."""
+    import torch
+    torch.cuda.set_device(0)
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}), flush=True)
+
+
+def _counter_means(folder, counter):
+    """Mean per dispatch of one counter, per kernel name, from a rocprofv3
+    --pmc csv folder (values summed over the dispatch's rows)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter csv under {folder}")
+    per = {}
+    for row in csv.DictReader(open(files[0])):
+        if row["Counter_Name"] != counter:
+            continue
+        name = row["Kernel_Name"].split("(")[0].split("::")[-1]
+        key = (name, row["Dispatch_Id"])
+        per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for (name, _), v in per.items():
+        t = out.setdefault(name, [0.0, 0])
+        t[0] += v
+        t[1] += 1
+    return {k: v[0] / v[1] for k, v in out.items()}
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
+    """HBM bytes per launch of every kernel: FETCH_SIZE and WRITE_SIZE (KiB)
+    scaled by what they read for a copy of copy_bytes."""
+    if not copy_bytes:
+        raise SystemExit("--traffic needs --copy-bytes (the calibration copy's size)")
+    f = _counter_means(fetch_dir, "FETCH_SIZE")
+    w = _counter_means(write_dir, "WRITE_SIZE")
+    cf = max(_counter_means(copy_fetch_dir, "FETCH_SIZE").values())
+    cw = max(_counter_means(copy_write_dir, "WRITE_SIZE").values())
+    kf, kw = copy_bytes / cf, copy_bytes / cw  # bytes per counter unit
+    from paper_2209_08196_amd import synth
+    res = {"source_sha": source_sha(), "workload": synth.CONFIGS[CID].name,
+           "calibration": {"copy_bytes": copy_bytes, "fetch_bytes_per_unit": kf, "write_bytes_per_unit": kw},
+           "kernels": {k: {"fetch_bytes": round(f[k] * kf), "write_bytes": round(w.get(k, 0.0) * kw)}
+                       for k in sorted(f) if k.startswith("k_")}}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +165,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3, help="steps timed per kernel with HIP events")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a device-to-device copy of this many bytes (counter calibration)")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="summarize four rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE of a bench "
+                         "run and of a --copy-bytes run) into " + os.path.relpath(TRAFFIC_FILE, ROOT))
     args = ap.parse_args()
+    if args.traffic:
+        summarize_traffic(*args.traffic, copy_bytes=args.copy_bytes)
+        return
+    if args.copy_bytes:
+        copy_run(args.copy_bytes)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (streams shard across GPUs "
               "without exchange, so the one-GPU figure is the per-GPU throughput).", file=sys.stderr)
