@@ -22,7 +22,7 @@
 
 namespace jiffy {
 
-constexpr uint32_t kWin = 16384;            // frame positions per parsing window
+constexpr uint32_t kWin = 8192;             // frame positions per parsing window
 constexpr uint32_t kChunk = 256;            // bytes per chunk of the chain stitching
 constexpr uint32_t kWinChunks = kWin / kChunk;
 constexpr uint32_t kJInvalid = 0xFFFFFFFFu; // no valid block chain continues here
@@ -90,13 +90,18 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
     // from chunk to chunk (at most kWin / kChunk steps); lanes walk the
     // chunks in parallel to build the block table; all lanes expand it.
     __shared__ uint32_t J[kWin];
+    __shared__ uint32_t fwin[kWin / 4 + 2];  // the window's frame bytes (and the two after it)
     __shared__ uint32_t c_entry[kWinChunks], c_cnt[kWinChunks], c_size[kWinChunks];
     __shared__ uint32_t c_boff[kWinChunks + 1], c_coff[kWinChunks + 1];
     __shared__ uint32_t s_changed;
     const uint8_t* f = rec + 12;
+    const uint8_t* fb = (const uint8_t*)fwin;
+    uint32_t wbase = 0, wlen = 0;  // frame offset of fwin's first byte (records are 4-aligned), bytes staged
+    // a block header at frame offset i, read from the staged window
     auto header_next = [&](uint32_t i, uint32_t* size_out, uint32_t* rle_out) -> uint32_t {
         if (i + 3 > flen) return kJInvalid;
-        const uint32_t h = (uint32_t)f[i] | ((uint32_t)f[i + 1] << 8) | ((uint32_t)f[i + 2] << 16);
+        const uint8_t* hp = fb + (i - wbase);
+        const uint32_t h = (uint32_t)hp[0] | ((uint32_t)hp[1] << 8) | ((uint32_t)hp[2] << 16);
         const uint32_t last = h & 1, type = (h >> 1) & 3, size = h >> 3;
         if (type > 1 || size > kZstdBlockMax) return kJInvalid;
         const uint32_t n = i + 3 + (type ? 1u : size);
@@ -115,6 +120,14 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
             __syncthreads();
             break;
         }
+        {  // stage frame bytes [ws, we + 2) with word loads (the record is 4-byte aligned)
+            const uint32_t r0 = (12 + ws) & ~3u, r1 = min(12 + we + 2, L);
+            const uint32_t* rw = (const uint32_t*)rec;
+            for (uint32_t w = r0 / 4 + tid; w * 4 < r1; w += 256) fwin[w - r0 / 4] = rw[w];
+            wbase = r0 - 12;
+            wlen = r1 - r0;
+        }
+        __syncthreads();
         for (uint32_t i = ws + tid; i < we; i += 256) J[i - ws] = header_next(i, nullptr, nullptr);
         __syncthreads();
         // pointer jumping until every position holds its chunk exit
@@ -218,7 +231,8 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
                     if (d < d0 || d >= d1) { full = 0; continue; }
                     while (d >= tdst[k + 1]) k++;
                     const uint32_t src = tsrc[k] & 0x7FFFFFFFu;
-                    const uint32_t v = (tsrc[k] >> 31) ? f[src] : f[src + (d - tdst[k])];
+                    const uint32_t sb = (tsrc[k] >> 31) ? src : src + (d - tdst[k]);  // frame byte
+                    const uint32_t v = sb - wbase < wlen ? fb[sb - wbase] : f[sb];
                     word |= v << (8 * b);
                 }
                 if (full) *(uint32_t*)(cwb + q) = word;

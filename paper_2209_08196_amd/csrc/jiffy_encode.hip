@@ -56,95 +56,6 @@ __global__ __launch_bounds__(256) void k_enc_mask(EncPlan plan) {
 }
 
 // ---------------------------------------------------------------------------
-// Trial compression (Sec. III-E): the band-centre rows floor((2j+1)H/(2K)),
-// compacted, coded both ways; P iff its packed size is strictly smaller.
-// The mask is not part of the trial.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t sample_at(const void* base, uint32_t wb, uint32_t p) {
-    if (wb == 4) return ((const uint32_t*)base)[p];
-    if (wb == 2) return ((const uint16_t*)base)[p];
-    return ((const uint8_t*)base)[p];
-}
-
-// packed size of one frame of values s[0..real) with predecessor `pred`;
-// called by one whole wave
-__device__ __forceinline__ uint32_t frame_cost_lds(const uint32_t* s, uint32_t real, uint32_t pred, uint32_t bits) {
-    const uint32_t l = lane_id();
-    const uint32_t m = low_mask32(bits);
-    uint32_t z0 = 0, z1 = 0;
-    if (l < real) z0 = zigzag((s[l] - (l ? s[l - 1] : pred)) & m, bits);
-    if (l + 64 < real) z1 = zigzag((s[l + 64] - s[l + 63]) & m, bits);
-    return choose_frame(z0, z1).cost;
-}
-
-__global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
-    const uint32_t r = blockIdx.x;
-    const EncItem it = plan.items[r];
-    if (!it.has_prev || it.mode_req != 0) {
-        if (threadIdx.x == 0) plan.res[r].mode = (it.has_prev && it.mode_req == 2) ? 1u : 0u;
-        return;
-    }
-    __shared__ uint32_t su[384], sv[384];
-    __shared__ uint32_t scratch[8];
-    __shared__ uint64_t s_cost[2];
-    __shared__ uint32_t s_pred[2];
-    const uint32_t tid = threadIdx.x, wave = tid / kWave;
-    const uint32_t m = low_mask32(it.bits);
-    if (tid == 0) { s_cost[0] = s_cost[1] = 0; s_pred[0] = s_pred[1] = 0; }
-    __syncthreads();
-    uint32_t cnt = 0;
-    const uint32_t K = it.trial_rows, H = it.height, W = it.width;
-    uint32_t prev_row = 0xFFFFFFFFu;
-    for (uint32_t j = 0; j < K; ++j) {
-        const uint32_t row = (uint32_t)(((uint64_t)(2 * j + 1) * H) / (2ull * K));
-        if (row == prev_row) continue;
-        prev_row = row;
-        for (uint32_t c0 = 0; c0 < W; c0 += 256) {
-            const uint32_t c = c0 + tid;
-            uint32_t u = 0, v = 0, valid = 0;
-            if (c < W) {
-                const uint32_t p = row * W + c;
-                const uint32_t q = quantize(sample_at(it.x, it.wb, p), it.div);
-                uint32_t qp = sample_at(it.xprev, it.wb, p);
-                if (!it.prev_quantized) qp = quantize(qp, it.div);
-                valid = q != 0;
-                u = q;
-                v = (q - qp) & m;
-            }
-            uint32_t total;
-            const uint32_t off = block_excl_scan<256>(valid, scratch, &total);
-            if (valid) { su[cnt + off] = u; sv[cnt + off] = v; }
-            __syncthreads();
-            cnt += total;
-            while (cnt >= 128) {
-                if (wave == 0) {
-                    uint32_t ci = frame_cost_lds(su, 128, s_pred[0], it.bits);
-                    uint32_t cp = frame_cost_lds(sv, 128, s_pred[1], it.bits);
-                    if (lane_id() == 0) { s_cost[0] += ci; s_cost[1] += cp; }
-                }
-                __syncthreads();
-                const uint32_t pu = su[127], pv = sv[127];
-                const uint32_t rest = cnt - 128;
-                uint32_t tu = 0, tv = 0;
-                if (tid < rest) { tu = su[128 + tid]; tv = sv[128 + tid]; }
-                __syncthreads();
-                if (tid < rest) { su[tid] = tu; sv[tid] = tv; }
-                if (tid == 0) { s_pred[0] = pu; s_pred[1] = pv; }
-                __syncthreads();
-                cnt = rest;
-            }
-        }
-    }
-    if (cnt > 0 && wave == 0) {
-        uint32_t ci = frame_cost_lds(su, cnt, s_pred[0], it.bits);
-        uint32_t cp = frame_cost_lds(sv, cnt, s_pred[1], it.bits);
-        if (lane_id() == 0) { s_cost[0] += ci; s_cost[1] += cp; }
-    }
-    __syncthreads();
-    if (tid == 0) plan.res[r].mode = s_cost[1] < s_cost[0] ? 1u : 0u;
-}
-
-// ---------------------------------------------------------------------------
 // Running count of in-range samples over the flattened scan (Sec. III-C zero
 // removal): N, and for every kFTile-pixel tile the count before it and the
 // last in-range pixel before it.
@@ -186,26 +97,20 @@ __global__ __launch_bounds__(1024) void k_enc_scan(EncPlan plan) {
 // frame is built in an LDS row and copied to its slot with 16-byte stores.
 // ---------------------------------------------------------------------------
 
-// vrow: the frame's values (row layout); on return it holds their ZigZag
-// codes.  orow: the quad's output row.  real: number of real values (the
-// rest count as 0); pred: the value before the first.  All four lanes of
-// the quad call it together; q = lane & 3.
-__device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t* orow, uint32_t real, uint32_t pred,
-                                                uint32_t bits, uint32_t q, JG uint8_t* slot, JG uint32_t* info) {
+// The quad's frame: z holds lane q's 32 values (in) and their ZigZag codes
+// (out); real = number of real values (the rest count as 0); pred = the
+// value before the first.  The width histogram goes to `hist` (36 LDS words,
+// cleared here; words 0..31 count widths 1..32, word 32 + q width 0), and
+// with kStash the codes also go back to vrow.  Returns the width key
+// cost << 14 | (63 - b) << 8 | n(b) of the cheapest b (ties: larger b) and
+// the frame's maximum width in B.  All four lanes call it together.
+template <bool kStash>
+__device__ __forceinline__ uint32_t quad_frame_key(uint32_t z[32], uint32_t* vrow, uint32_t* hist, uint32_t real,
+                                                   uint32_t pred, uint32_t bits, uint32_t q, uint32_t& Bout) {
     const uint32_t m = low_mask32(bits);
-    uint32_t z[32];
-    {
-        const uint4* v4 = (const uint4*)(vrow + 36 * q);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const uint4 t = v4[c];
-            z[4 * c] = t.x; z[4 * c + 1] = t.y; z[4 * c + 2] = t.z; z[4 * c + 3] = t.w;
-        }
-    }
-    // histogram of widths 1..32 in orow words 0..31; width 0 goes to word 32 + q
-    uint4* o4 = (uint4*)orow;
-    o4[2 * q] = make_uint4(0u, 0u, 0u, 0u);
-    o4[2 * q + 1] = make_uint4(0u, 0u, 0u, 0u);
+    uint4* h4 = (uint4*)hist;
+    h4[2 * q] = make_uint4(0u, 0u, 0u, 0u);
+    h4[2 * q + 1] = make_uint4(0u, 0u, 0u, 0u);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     uint32_t prev = dpp_mov<0x111>(z[31]);  // the previous lane's last value
     if (q == 0) prev = pred;
@@ -219,9 +124,9 @@ __device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t* orow, 
         z[i] = r;
         const uint32_t w = r ? 32u - __clz(r) : 0u;
         B = max(B, w);
-        __hip_atomic_fetch_add(orow + (w ? w - 1u : 32u + q), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __hip_atomic_fetch_add(hist + (w ? w - 1u : 32u + q), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
-    {  // the codes replace the values (read again for the exceptions)
+    if (kStash) {  // the codes replace the values (read again for the exceptions)
         uint4* v4 = (uint4*)(vrow + 36 * q);
 #pragma unroll
         for (int c = 0; c < 8; ++c) v4[c] = make_uint4(z[4 * c], z[4 * c + 1], z[4 * c + 2], z[4 * c + 3]);
@@ -230,14 +135,14 @@ __device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t* orow, 
     B = max(B, dpp_mov<kQuadXor2>(B));
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     // n(b) = values wider than b bits; lane q evaluates b = 8q .. 8q+7
-    const uint4 ha = o4[2 * q], hb = o4[2 * q + 1];
+    const uint4 ha = h4[2 * q], hb = h4[2 * q + 1];
     const uint32_t h[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};  // widths 8q+1 .. 8q+8
     uint32_t loc = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) loc += h[k];
     const uint32_t c1 = quad_bcast<1>(loc), c2 = quad_bcast<2>(loc), c3 = quad_bcast<3>(loc);
     uint32_t n = (q < 1 ? c1 : 0u) + (q < 2 ? c2 : 0u) + (q < 3 ? c3 : 0u);
-    // key: cost, then the larger b, then n(b); b = B costs 16 B with no exceptions
+    // b = B costs 16 B with no exceptions
     uint32_t key = ((16u * B) << 14) | ((63u - B) << 8);
 #pragma unroll
     for (int k = 7; k >= 0; --k) {
@@ -250,6 +155,39 @@ __device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t* orow, 
     }
     key = min(key, dpp_mov<kQuadXor1>(key));
     key = min(key, dpp_mov<kQuadXor2>(key));
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    Bout = B;
+    return key;
+}
+
+__device__ __forceinline__ void load_quad_values(const uint32_t* vrow, uint32_t q, uint32_t z[32]) {
+    const uint4* v4 = (const uint4*)(vrow + 36 * q);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint4 t = v4[c];
+        z[4 * c] = t.x; z[4 * c + 1] = t.y; z[4 * c + 2] = t.z; z[4 * c + 3] = t.w;
+    }
+}
+
+// packed size of the quad's frame (vrow: its values in row layout, which
+// the histogram then overwrites)
+__device__ __forceinline__ uint32_t frame_cost_quad(uint32_t* vrow, uint32_t real, uint32_t pred, uint32_t bits,
+                                                    uint32_t q) {
+    uint32_t z[32], B;
+    load_quad_values(vrow, q, z);
+    return quad_frame_key<false>(z, vrow, vrow, real, pred, bits, q, B) >> 14;
+}
+
+// vrow: the frame's values (row layout); on return it holds their ZigZag
+// codes.  orow: the quad's output row.  The packed frame goes to `slot`,
+// b | n << 8 | B << 16 to *info.
+__device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t* orow, uint32_t real, uint32_t pred,
+                                                uint32_t bits, uint32_t q, JG uint8_t* slot, JG uint32_t* info) {
+    uint32_t z[32], B;
+    load_quad_values(vrow, q, z);
+    const uint32_t key = quad_frame_key<true>(z, vrow, orow, real, pred, bits, q, B);
+    uint4* o4 = (uint4*)orow;
+    const uint32_t i0 = 32u * q;
     const uint32_t b = 63u - ((key >> 8) & 63u), nexc = key & 255u, cost = key >> 14;
     const uint32_t hw = B - b, lm = low_mask32(b);
     uint32_t ex = 0;  // this lane's exceptions
@@ -303,6 +241,114 @@ __device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t* orow, 
     JG uint4* s4 = (JG uint4*)slot;
     for (uint32_t c = q; c < (cost + 15u) / 16u; c += 4) s4[c] = o4[c];
     if (q == 0) *info = b | (nexc << 8) | (B << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Trial compression (Sec. III-E): the nonzero samples of the band-centre
+// rows floor((2j+1)H/(2K)) (all rows when K >= H), row by row, coded as
+// the I residuals (the samples) and as the P residuals (differences to the
+// previous scan); P iff its packed size is strictly smaller.  The mask is
+// not part of the trial.  One workgroup per record: chunks of 8192 trial
+// pixels are compacted into LDS frame rows (a frame left incomplete carries
+// to the next chunk) and each whole frame is costed by a quad, the I
+// residuals first, then the P residuals in the same rows.
+// ---------------------------------------------------------------------------
+struct TrialLds {
+    uint32_t rows[kTileFrames * kRow];
+    uint32_t carry[2][kFrame];  // the incomplete frame of each residual kind
+    uint32_t scratch[8];
+    unsigned long long cost[2];
+};
+
+template <int WB>
+__device__ __forceinline__ void enc_trial_body(const EncItem& it, TrialLds& L, JG EncRes* res) {
+    const uint32_t tid = threadIdx.x, g = tid >> 2, q = tid & 3u;
+    const uint32_t m = low_mask32(it.bits);
+    const uint32_t H = it.height, W = it.width, K = it.trial_rows;
+    const uint32_t nr = K >= H ? H : K;  // distinct trial rows
+    const uint32_t NT = nr * W;          // trial pixels
+    if (tid < 2) L.cost[tid] = 0;
+    uint32_t carry = 0, pred[2] = {0u, 0u};  // values in the incomplete frame; value before it
+    for (uint32_t cs = 0; cs < NT; cs += kFTile) {
+        // this thread's 32 trial pixels
+        uint32_t val[2][32];
+        uint32_t keep = 0;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            const uint32_t tp = cs + tid * 32 + i;
+            uint32_t u = 0, v = 0;
+            if (tp < NT) {
+                const uint32_t ri = tp / W, c = tp - ri * W;
+                const uint32_t row = K >= H ? ri : (uint32_t)(((uint64_t)(2 * ri + 1) * H) / (2ull * K));
+                const uint32_t p = row * W + c;
+                const uint32_t qv = quantize(load1<WB>(it.x, p), it.div);
+                uint32_t qp = load1<WB>(it.xprev, p);
+                if (!it.prev_quantized) qp = quantize(qp, it.div);
+                keep |= (qv != 0 ? 1u : 0u) << i;
+                u = qv;
+                v = (qv - qp) & m;
+            }
+            val[0][i] = u;
+            val[1][i] = v;
+        }
+        uint32_t nv;
+        const uint32_t off = block_excl_scan<256>(__popc(keep), L.scratch, &nv);
+        const uint32_t total = carry + nv, nfull = total >> 7, rem = total & 127u;
+        const bool last = cs + kFTile >= NT;
+        const uint32_t ncost = nfull + (last && rem ? 1u : 0u);  // frames costed now
+#pragma unroll
+        for (int kind = 0; kind < 2; ++kind) {
+            // the carried frame start, then this chunk's kept values
+            if (tid < carry) L.rows[row_off(tid)] = L.carry[kind][tid];
+            uint32_t k = carry + off;
+#pragma unroll
+            for (int i = 0; i < 32; ++i)
+                if (keep & (1u << i)) {
+                    L.rows[tile_word(k, 0)] = val[kind][i];
+                    ++k;
+                }
+            __syncthreads();
+            // predecessors, and the new incomplete frame, before any row turns into a histogram
+            // (quad g costs frames g and g + 64: a chunk can hold 65)
+            uint32_t pv[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t f = g + 64 * h;
+                pv[h] = (f < ncost && f > 0) ? L.rows[tile_word(128 * f - 1, 0)] : pred[kind];
+            }
+            const uint32_t npred = nfull ? L.rows[tile_word(128 * nfull - 1, 0)] : pred[kind];
+            if (!last && tid < rem) L.carry[kind][tid] = L.rows[tile_word(128 * nfull + tid, 0)];
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t f = g + 64 * h;
+                if (f < ncost) {
+                    const uint32_t real = f < nfull ? kFrame : rem;
+                    const uint32_t c = frame_cost_quad(L.rows + f * kRow, real, pv[h], it.bits, q);
+                    if (q == 0) atomicAdd(&L.cost[kind], (unsigned long long)c);
+                }
+            }
+            pred[kind] = npred;
+            __syncthreads();
+        }
+        carry = rem;
+    }
+    if (tid == 0) res->mode = L.cost[1] < L.cost[0] ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
+    const uint32_t r = blockIdx.x;
+    const EncItem it = plan.items[r];
+    if (!it.has_prev || it.mode_req != 0) {
+        if (threadIdx.x == 0) plan.res[r].mode = (it.has_prev && it.mode_req == 2) ? 1u : 0u;
+        return;
+    }
+    __shared__ TrialLds lds;
+    switch (it.wb) {
+        case 4: enc_trial_body<4>(it, lds, plan.res + r); break;
+        case 2: enc_trial_body<2>(it, lds, plan.res + r); break;
+        default: enc_trial_body<1>(it, lds, plan.res + r); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
