@@ -102,6 +102,51 @@ def kernel_alg_bytes(name, st, x_bytes, n_items, nwords):
     return table.get(name)
 
 
+def batched_leg(steps, warmup):
+    """64 sensor streams of four sizes (16x1024, 32x2048, 64x1024, 128x2048;
+    range u32 at 1 cm and signal u16), one scan of every stream per step:
+    the graph-replayed batch (jiffy_batch_run) against the plain batched
+    call (jiffy_batch_encode_step) on twin streams, with byte-identical
+    records required."""
+    import torch
+
+    from paper_2209_08196_amd import jiffy, synth
+    cfg = synth.CONFIGS[3]
+    T = warmup + steps
+    gens = [synth.stream(3, s) for s in range(cfg.streams)]
+    store = {1: np.uint8, 2: np.int16, 4: np.int32}
+    scans = [[torch.from_numpy(p.view(store[p.dtype.itemsize])).cuda() for p in g.scans(0, T)] for g in gens]
+    points = sum(g.H * g.W * len(g.widths) for g in gens)
+    mk = lambda: [jiffy.Stream(g.H, g.W, g.widths, g.precisions) for g in gens]  # noqa: E731
+    sg, sp = mk(), mk()
+    inputs = [[p[0] for p in sc] for sc in scans]
+    outs_g = [torch.empty(s.record_bound(), dtype=torch.uint8, device="cuda") for s in sg]
+    outs_p = [torch.empty(s.record_bound(), dtype=torch.uint8, device="cuda") for s in sp]
+    batch = jiffy.Batch(sg, inputs, outs_g)
+    identical = True
+    tg = tp = 0.0
+    for t in range(T):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lg, _ = batch.run([[p[t] for p in sc] for sc in scans])
+        t1 = time.perf_counter()
+        lp, _ = jiffy.batch_encode_step(sp, [[p[t] for p in sc] for sc in scans], outs_p)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if t >= warmup:
+            tg += t1 - t0
+            tp += t2 - t1
+        if lg != lp or any(not torch.equal(outs_g[i][: lg[i]], outs_p[i][: lp[i]]) for i in range(len(gens))):
+            identical = False
+    batch.close()
+    for s in sg + sp:
+        s.close()
+    return {"workload": f"{cfg.name}, {steps} steps", "streams": cfg.streams, "points_per_step": points,
+            "graph_points_per_s": round(points * steps / tg, 1), "graph_ms_per_step": round(1e3 * tg / steps, 3),
+            "plain_points_per_s": round(points * steps / tp, 1), "plain_ms_per_step": round(1e3 * tp / steps, 3),
+            "byte_identical": identical}
+
+
 def copy_run(nbytes):
     """A plain device copy of known size, three times: what FETCH_SIZE and
     WRITE_SIZE read for it calibrates those counters."""
@@ -164,6 +209,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
+    ap.add_argument("--only-batched", action="store_true", help="run only the 64-stream batched leg")
     ap.add_argument("--profile-steps", type=int, default=3, help="steps timed per kernel with HIP events")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (counter calibration)")
@@ -176,6 +223,11 @@ def main():
         return
     if args.copy_bytes:
         copy_run(args.copy_bytes)
+        return
+    if args.only_batched:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(batched_leg(steps=args.steps, warmup=args.warmup)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (streams shard across GPUs "
@@ -289,6 +341,10 @@ def main():
         "roofline": roofline,
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_ms"])},
     }
+
+    if not args.no_batched:
+        result["batched"] = batched_leg(steps=8, warmup=2)
+        print(f"[bench] batched: {result['batched']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         import oracle  # the CPU-baseline leg: the oracle timed on the host

@@ -125,6 +125,35 @@ int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void
                             void* const* d_out, const size_t* caps, size_t* h_lens, uint8_t* h_modes,
                             hipStream_t stream);
 
+/* ---- batches (one graph launch per step) --------------------------------
+ * A fixed set of n streams encoded together every step, with the same
+ * records as jiffy_batch_encode_step.  The step's kernels are captured
+ * once in a HIP graph; a step is one upload of the records' descriptors
+ * (input pointers included), one graph launch and one download of the
+ * lengths.  Arguments of create:
+ *   d_planes[i][a]: device pointer to stream i's next scan of attribute a
+ *                   (H*W samples); a run may name other input pointers;
+ *   d_out[i]:       device buffer of caps[i] bytes (4-byte aligned) that
+ *                   receives stream i's records, fixed for the batch's life.
+ * The batch owns its own workspace (device memory and pinned host memory,
+ * freed by jiffy_batch_destroy).  The streams must outlive the batch; each
+ * appears once.  Runs of one batch must not overlap (jiffy_batch_run
+ * synchronizes `stream` before it returns). */
+typedef struct jiffy_batch jiffy_batch;
+
+int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
+                       void* const* d_out, const size_t* caps, jiffy_batch** out);
+
+/* One step: every stream's next scan, read from d_planes[i][a] (same
+ * layout and alignment rules as at create) or, when d_planes is NULL, from
+ * the pointers given last.  h_lens[i] (host) gets stream i's record bytes
+ * (or the bytes needed, with JIFFY_E_CAPACITY; then no stream advances);
+ * h_modes optional [n][n_attrs]. */
+int jiffy_batch_run(jiffy_batch* b, const void* const* const* d_planes, size_t* h_lens, uint8_t* h_modes,
+                    hipStream_t stream);
+
+void jiffy_batch_destroy(jiffy_batch* b);
+
 /* Drops the resident previous scan; the next scan is an I-scan. */
 int jiffy_stream_reset(jiffy_stream* s);
 

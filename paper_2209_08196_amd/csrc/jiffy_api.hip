@@ -109,51 +109,66 @@ struct EncResult {
     std::vector<uint8_t> modes;
 };
 
-int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs, hipStream_t stream,
-               EncResult& result) {
+// Where everything of one encode launch sequence lives in its device
+// workspace: [res][err][outs][items][tile maps] (the part uploaded from the
+// host, from `err` on) then per record its buffers.
+struct EncLayout {
+    uint32_t n = 0, no = 0, n_tiles = 0, n_ftiles = 0, max_groups = 1;
+    std::vector<uint32_t> tile_first, ftile_first;
+    size_t o_res = 0, o_err = 0, o_outs = 0, o_items = 0, o_tfirst = 0, o_titem = 0, o_ftfirst = 0, o_ftitem = 0;
+    size_t up_end = 0, total = 0;
+    std::vector<size_t> o_vw, o_blk, o_slots, o_frame, o_segs;
+    size_t up_bytes() const { return up_end - o_err; }
+};
+
+EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs) {
+    EncLayout Lo;
     const uint32_t n = (uint32_t)specs.size(), no = (uint32_t)outs.size();
-    // layout of the device workspace: [res][err][outs][items][tile_first][tile_item] then per item
-    uint32_t n_tiles = 0, n_ftiles = 0, max_groups = 1;
-    std::vector<uint32_t> tile_first(n), ftile_first(n);
+    Lo.n = n;
+    Lo.no = no;
+    Lo.tile_first.resize(n);
+    Lo.ftile_first.resize(n);
     for (uint32_t r = 0; r < n; ++r) {
-        tile_first[r] = n_tiles;
-        ftile_first[r] = n_ftiles;
+        Lo.tile_first[r] = Lo.n_tiles;
+        Lo.ftile_first[r] = Lo.n_ftiles;
         const uint32_t npx = specs[r].H * specs[r].W;
-        n_tiles += div_up(npx, kTilePx);
-        n_ftiles += div_up(npx, kFTile);
+        Lo.n_tiles += div_up(npx, kTilePx);
+        Lo.n_ftiles += div_up(npx, kFTile);
         const uint32_t groups = div_up(div_up(npx, kFrame), kGroupFrames);
-        if (groups > max_groups) max_groups = groups;
+        if (groups > Lo.max_groups) Lo.max_groups = groups;
     }
     size_t off = 0;
-    const size_t o_res = off; off = al(off + sizeof(EncRes) * n);
-    const size_t o_err = off; off = al(off + sizeof(uint32_t));
-    const size_t o_outs = off; off = al(off + sizeof(EncOut) * no);
-    const size_t o_items = off; off = al(off + sizeof(EncItem) * n);
-    const size_t o_tfirst = off; off = al(off + sizeof(uint32_t) * n);
-    const size_t o_titem = off; off = al(off + sizeof(uint32_t) * n_tiles);
-    const size_t o_ftfirst = off; off = al(off + sizeof(uint32_t) * n);
-    const size_t o_ftitem = off; off = al(off + sizeof(uint32_t) * n_ftiles);
-    const size_t up_end = off;
-    std::vector<size_t> o_vw(n), o_blk(n), o_slots(n), o_frame(n), o_segs(n);
+    Lo.o_res = off; off = al(off + sizeof(EncRes) * n);
+    Lo.o_err = off; off = al(off + sizeof(uint32_t));
+    Lo.o_outs = off; off = al(off + sizeof(EncOut) * no);
+    Lo.o_items = off; off = al(off + sizeof(EncItem) * n);
+    Lo.o_tfirst = off; off = al(off + sizeof(uint32_t) * n);
+    Lo.o_titem = off; off = al(off + sizeof(uint32_t) * Lo.n_tiles);
+    Lo.o_ftfirst = off; off = al(off + sizeof(uint32_t) * n);
+    Lo.o_ftitem = off; off = al(off + sizeof(uint32_t) * Lo.n_ftiles);
+    Lo.up_end = off;
+    Lo.o_vw.resize(n); Lo.o_blk.resize(n); Lo.o_slots.resize(n); Lo.o_frame.resize(n); Lo.o_segs.resize(n);
     for (uint32_t r = 0; r < n; ++r) {
         const uint32_t npx = specs[r].H * specs[r].W;
         const uint32_t nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame), nm = div_up(npx, 8);
-        o_vw[r] = off; off = al(off + (specs[r].vw_fixed ? 0 : 8ull * nwords));
-        o_blk[r] = off; off = al(off + 4ull * maxnb * 4 + 12ull * div_up(npx, kFTile));
-        o_slots[r] = off; off = al(off + (size_t)kSlotBytes * maxnb);
-        o_frame[r] = off; off = al(off + frame_bound(nm));
-        o_segs[r] = off; off = al(off + 8ull * (nm / 4 + 4));
+        Lo.o_vw[r] = off; off = al(off + (specs[r].vw_fixed ? 0 : 8ull * nwords));
+        Lo.o_blk[r] = off; off = al(off + 4ull * maxnb * 4 + 12ull * div_up(npx, kFTile));
+        Lo.o_slots[r] = off; off = al(off + (size_t)kSlotBytes * maxnb);
+        Lo.o_frame[r] = off; off = al(off + frame_bound(nm));
+        Lo.o_segs[r] = off; off = al(off + 8ull * (nm / 4 + 4));
     }
-    if (grow(ctx.ws, off) != hipSuccess) return JIFFY_E_DEVICE;
-    const size_t up_bytes = up_end - o_err;
-    if (grow(ctx.up, up_bytes) != hipSuccess) return JIFFY_E_DEVICE;
-    if (grow(ctx.down, o_items) != hipSuccess) return JIFFY_E_DEVICE;
-    uint8_t* dev = (uint8_t*)ctx.ws.p;
-    uint8_t* up = (uint8_t*)ctx.up.p;
-    memset(up, 0, up_bytes);
-    auto U = [&](size_t o) { return up + (o - o_err); };
+    Lo.total = off;
+    return Lo;
+}
 
-    EncOut* hout = (EncOut*)U(o_outs);
+// The host image of the uploaded part (records, outputs, tile maps, zeroed
+// error word and output states), written into `up` (up_bytes() bytes).
+void enc_fill(const EncLayout& Lo, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs,
+              uint8_t* dev, uint8_t* up) {
+    const uint32_t n = Lo.n, no = Lo.no;
+    memset(up, 0, Lo.up_bytes());
+    auto U = [&](size_t o) { return up + (o - Lo.o_err); };
+    EncOut* hout = (EncOut*)U(Lo.o_outs);
     for (uint32_t k = 0; k < no; ++k) {
         EncOut& o = hout[k];
         o.base = outs[k].base;
@@ -171,7 +186,7 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
             o.attr_p[a] = L->precision[a];
         }
     }
-    EncItem* hit = (EncItem*)U(o_items);
+    EncItem* hit = (EncItem*)U(Lo.o_items);
     for (uint32_t r = 0; r < n; ++r) {
         const EncSpec& s = specs[r];
         EncItem& it = hit[r];
@@ -179,13 +194,13 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
         it.x = s.x;
         it.xprev = s.xprev;
         it.qout = s.qout;
-        it.vw = s.vw_fixed ? s.vw_fixed : (uint64_t*)(dev + o_vw[r]);
+        it.vw = s.vw_fixed ? s.vw_fixed : (uint64_t*)(dev + Lo.o_vw[r]);
         if (s.vwprev_fixed) it.vwprev = s.vwprev_fixed;
         else if (s.prev_item >= 0) it.vwprev = specs[s.prev_item].vw_fixed ? specs[s.prev_item].vw_fixed
-                                                                         : (uint64_t*)(dev + o_vw[s.prev_item]);
+                                                                         : (uint64_t*)(dev + Lo.o_vw[s.prev_item]);
         else it.vwprev = nullptr;
         const uint32_t maxnb = div_up(npx, kFrame), nm = div_up(npx, 8);
-        uint32_t* blk = (uint32_t*)(dev + o_blk[r]);
+        uint32_t* blk = (uint32_t*)(dev + Lo.o_blk[r]);
         const uint32_t nft = div_up(npx, kFTile);
         it.blkinfo = blk;
         it.blkoffs = blk + maxnb;
@@ -193,10 +208,10 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
         it.tpred = it.tbase + nft;
         it.tfix = it.tpred + nft;
         it.ntiles = nft;
-        it.slots = dev + o_slots[r];
-        it.frame = dev + o_frame[r];
+        it.slots = dev + Lo.o_slots[r];
+        it.frame = dev + Lo.o_frame[r];
         it.seg_cap = nm / 4 + 4;
-        it.segs = (uint32_t*)(dev + o_segs[r]);
+        it.segs = (uint32_t*)(dev + Lo.o_segs[r]);
         it.segoff = it.segs + it.seg_cap;
         it.div = make_divisor(s.P);
         it.npx = npx;
@@ -217,54 +232,75 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
                     (!s.qout || (uintptr_t)s.qout % 16 == 0);
         it.aligned16 = al16 ? 1u : 0u;
     }
-    uint32_t* htf = (uint32_t*)U(o_tfirst);
-    uint32_t* hti = (uint32_t*)U(o_titem);
+    uint32_t* htf = (uint32_t*)U(Lo.o_tfirst);
+    uint32_t* hti = (uint32_t*)U(Lo.o_titem);
+    uint32_t* hftf = (uint32_t*)U(Lo.o_ftfirst);
+    uint32_t* hfti = (uint32_t*)U(Lo.o_ftitem);
     for (uint32_t r = 0; r < n; ++r) {
-        htf[r] = tile_first[r];
-        const uint32_t nt = div_up(specs[r].H * specs[r].W, kTilePx);
-        for (uint32_t k = 0; k < nt; ++k) hti[tile_first[r] + k] = r;
+        const uint32_t npx = specs[r].H * specs[r].W;
+        htf[r] = Lo.tile_first[r];
+        for (uint32_t k = 0, nt = div_up(npx, kTilePx); k < nt; ++k) hti[Lo.tile_first[r] + k] = r;
+        hftf[r] = Lo.ftile_first[r];
+        for (uint32_t k = 0, nt = div_up(npx, kFTile); k < nt; ++k) hfti[Lo.ftile_first[r] + k] = r;
     }
-    uint32_t* hftf = (uint32_t*)U(o_ftfirst);
-    uint32_t* hfti = (uint32_t*)U(o_ftitem);
-    for (uint32_t r = 0; r < n; ++r) {
-        hftf[r] = ftile_first[r];
-        const uint32_t nt = div_up(specs[r].H * specs[r].W, kFTile);
-        for (uint32_t k = 0; k < nt; ++k) hfti[ftile_first[r] + k] = r;
-    }
-    if (hipMemcpyAsync(dev + o_err, up, up_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
-        return JIFFY_E_DEVICE;
+}
 
+EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev) {
     EncPlan plan;
-    plan.items = (const EncItem*)(dev + o_items);
-    plan.res = (EncRes*)(dev + o_res);
-    plan.outs = (EncOut*)(dev + o_outs);
-    plan.err = (uint32_t*)(dev + o_err);
-    plan.tile_item = (const uint32_t*)(dev + o_titem);
-    plan.tile_first = (const uint32_t*)(dev + o_tfirst);
-    plan.ftile_item = (const uint32_t*)(dev + o_ftitem);
-    plan.ftile_first = (const uint32_t*)(dev + o_ftfirst);
-    plan.n_ftiles = n_ftiles;
-    plan.n_items = n;
-    plan.n_outs = no;
-    plan.n_tiles = n_tiles;
-    plan.max_groups = max_groups;
-    if (launch_encode(plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
-    if (hipMemcpyAsync(ctx.down.p, dev, o_items, hipMemcpyDeviceToHost, stream) != hipSuccess)
-        return JIFFY_E_DEVICE;
-    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
-    prof_collect();
+    plan.items = (const EncItem*)(dev + Lo.o_items);
+    plan.res = (EncRes*)(dev + Lo.o_res);
+    plan.outs = (EncOut*)(dev + Lo.o_outs);
+    plan.err = (uint32_t*)(dev + Lo.o_err);
+    plan.tile_item = (const uint32_t*)(dev + Lo.o_titem);
+    plan.tile_first = (const uint32_t*)(dev + Lo.o_tfirst);
+    plan.ftile_item = (const uint32_t*)(dev + Lo.o_ftitem);
+    plan.ftile_first = (const uint32_t*)(dev + Lo.o_ftfirst);
+    plan.n_ftiles = Lo.n_ftiles;
+    plan.n_items = Lo.n;
+    plan.n_outs = Lo.no;
+    plan.n_tiles = Lo.n_tiles;
+    plan.max_groups = Lo.max_groups;
+    return plan;
+}
 
-    const uint8_t* down = (const uint8_t*)ctx.down.p;
-    const EncRes* dres = (const EncRes*)(down + o_res);
-    const EncOut* douts = (const EncOut*)(down + o_outs);
-    result.lens.resize(no);
-    result.ok.resize(no);
-    result.modes.resize(n);
-    for (uint32_t k = 0; k < no; ++k) {
+// upload, the kernels, download of [res][err][outs]: everything one step
+// enqueues (also what a batch captures in its graph)
+hipError_t enc_enqueue(const EncLayout& Lo, const EncPlan& plan, uint8_t* dev, const uint8_t* up, uint8_t* down,
+                       hipStream_t stream) {
+    hipError_t e = hipMemcpyAsync(dev + Lo.o_err, up, Lo.up_bytes(), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    e = launch_encode(plan, stream);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(down, dev, Lo.o_items, hipMemcpyDeviceToHost, stream);
+}
+
+void enc_results(const EncLayout& Lo, const uint8_t* down, EncResult& result) {
+    const EncRes* dres = (const EncRes*)(down + Lo.o_res);
+    const EncOut* douts = (const EncOut*)(down + Lo.o_outs);
+    result.lens.resize(Lo.no);
+    result.ok.resize(Lo.no);
+    result.modes.resize(Lo.n);
+    for (uint32_t k = 0; k < Lo.no; ++k) {
         result.lens[k] = douts[k].len;
         result.ok[k] = (uint8_t)douts[k].ok;
     }
-    for (uint32_t r = 0; r < n; ++r) result.modes[r] = (uint8_t)dres[r].mode;
+    for (uint32_t r = 0; r < Lo.n; ++r) result.modes[r] = (uint8_t)dres[r].mode;
+}
+
+int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs, hipStream_t stream,
+               EncResult& result) {
+    const EncLayout Lo = enc_layout(specs, outs);
+    if (grow(ctx.ws, Lo.total) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(ctx.up, Lo.up_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(ctx.down, Lo.o_items) != hipSuccess) return JIFFY_E_DEVICE;
+    uint8_t* dev = (uint8_t*)ctx.ws.p;
+    enc_fill(Lo, specs, outs, dev, (uint8_t*)ctx.up.p);
+    const EncPlan plan = enc_plan(Lo, dev);
+    if (enc_enqueue(Lo, plan, dev, (const uint8_t*)ctx.up.p, (uint8_t*)ctx.down.p, stream) != hipSuccess)
+        return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    prof_collect();
+    enc_results(Lo, (const uint8_t*)ctx.down.p, result);
     return JIFFY_OK;
 }
 
@@ -349,7 +385,10 @@ void prof_collect() {
 }  // namespace
 
 namespace jiffy {
+thread_local bool t_capturing = false;  // launches go into a graph: no timing events
+
 void prof_begin(const char* name, hipStream_t stream) {
+    if (t_capturing) return;
     std::lock_guard<std::mutex> lock(g_prof_mu);
     if (!g_prof_on) return;
     ProfEntry e{name, prof_event(), prof_event()};
@@ -357,6 +396,7 @@ void prof_begin(const char* name, hipStream_t stream) {
     g_prof_pending.push_back(e);
 }
 void prof_end(hipStream_t stream) {
+    if (t_capturing) return;
     std::lock_guard<std::mutex> lock(g_prof_mu);
     if (!g_prof_on || g_prof_pending.empty()) return;
     ProfEntry& e = g_prof_pending.back();
@@ -715,13 +755,13 @@ void jiffy_stream_destroy(jiffy_stream* s) {
     delete s;
 }
 
-int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
-                            void* const* d_out, const size_t* caps, size_t* h_lens, uint8_t* h_modes,
-                            hipStream_t stream) {
-    if (n == 0) return JIFFY_OK;
-    if (!streams || !d_planes || !d_out || !caps || !h_lens) return JIFFY_E_INVALID;
-    int dev;
-    if (current_device(&dev)) return JIFFY_E_DEVICE;
+}  // extern "C"
+
+namespace {
+// Checks a batch's arguments; JIFFY_OK or an error status.
+int check_batch(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes, void* const* d_out,
+                const size_t* caps, int dev) {
+    if (!streams || !d_planes || !d_out || !caps) return JIFFY_E_INVALID;
     for (uint32_t i = 0; i < n; ++i) {
         const jiffy_stream* s = streams[i];
         if (!s || !d_planes[i] || !d_out[i] || (uintptr_t)d_out[i] % 4) return JIFFY_E_INVALID;
@@ -731,10 +771,16 @@ int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void
         for (uint32_t k = 0; k < i; ++k)
             if (streams[k] == s) return JIFFY_E_INVALID;
     }
-    DevCtx& ctx = g_ctx[dev];
-    std::lock_guard<std::mutex> lock(ctx.mu);
-    std::vector<EncSpec> specs;
-    std::vector<OutSpec> outs(n);
+    return JIFFY_OK;
+}
+
+// One record per attribute of each stream's next scan, predicting from the
+// resident previous scan; the new scan's quantized samples and valid words
+// go to the other half of the stream's state.
+void stream_specs(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes, void* const* d_out,
+                  const size_t* caps, std::vector<EncSpec>& specs, std::vector<OutSpec>& outs) {
+    specs.clear();
+    outs.resize(n);
     for (uint32_t i = 0; i < n; ++i) {
         const jiffy_stream* s = streams[i];
         const jiffy_layout& L = s->layout;
@@ -760,9 +806,11 @@ int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void
             specs.push_back(e);
         }
     }
-    EncResult res;
-    int rc = run_encode(ctx, specs, outs, stream, res);
-    if (rc) return rc;
+}
+
+// lengths, modes and status of a finished step; the streams advance only
+// when every output fitted
+int finish_step(jiffy_stream* const* streams, uint32_t n, const EncResult& res, size_t* h_lens, uint8_t* h_modes) {
     int status = JIFFY_OK;
     for (uint32_t i = 0; i < n; ++i) {
         h_lens[i] = res.lens[i];
@@ -776,6 +824,127 @@ int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void
         }
     }
     return status;
+}
+}  // namespace
+
+extern "C" {
+
+int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
+                            void* const* d_out, const size_t* caps, size_t* h_lens, uint8_t* h_modes,
+                            hipStream_t stream) {
+    if (n == 0) return JIFFY_OK;
+    if (!h_lens) return JIFFY_E_INVALID;
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    if (int rc = check_batch(streams, n, d_planes, d_out, caps, dev)) return rc;
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    std::vector<EncSpec> specs;
+    std::vector<OutSpec> outs;
+    stream_specs(streams, n, d_planes, d_out, caps, specs, outs);
+    EncResult res;
+    if (int rc = run_encode(ctx, specs, outs, stream, res)) return rc;
+    return finish_step(streams, n, res, h_lens, h_modes);
+}
+
+// ---------------------------------------------------------------------------
+// batches: a fixed set of streams whose step is one replay of a HIP graph
+// ---------------------------------------------------------------------------
+struct jiffy_batch {
+    int device = 0;
+    std::vector<jiffy_stream*> streams;
+    std::vector<std::vector<const void*>> planes;
+    std::vector<const void* const*> plane_ptrs;
+    std::vector<void*> outs;
+    std::vector<size_t> caps;
+    EncLayout Lo;
+    uint8_t* dev = nullptr;
+    uint8_t* up = nullptr;
+    uint8_t* down = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
+                       void* const* d_out, const size_t* caps, jiffy_batch** out) {
+    if (!out || n == 0) return JIFFY_E_INVALID;
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    if (int rc = check_batch(streams, n, d_planes, d_out, caps, dev)) return rc;
+    jiffy_batch* b = new (std::nothrow) jiffy_batch();
+    if (!b) return JIFFY_E_INVALID;
+    b->device = dev;
+    b->streams.assign(streams, streams + n);
+    b->planes.resize(n);
+    for (uint32_t i = 0; i < n; ++i) b->planes[i].assign(d_planes[i], d_planes[i] + streams[i]->layout.n_attrs);
+    for (uint32_t i = 0; i < n; ++i) b->plane_ptrs.push_back(b->planes[i].data());
+    b->outs.assign(d_out, d_out + n);
+    b->caps.assign(caps, caps + n);
+    std::vector<EncSpec> specs;
+    std::vector<OutSpec> outs;
+    stream_specs(b->streams.data(), n, b->plane_ptrs.data(), b->outs.data(), b->caps.data(), specs, outs);
+    b->Lo = enc_layout(specs, outs);
+    int rc = JIFFY_E_DEVICE;
+    if (hipMalloc((void**)&b->dev, b->Lo.total) == hipSuccess &&
+        hipHostMalloc((void**)&b->up, b->Lo.up_bytes(), hipHostMallocDefault) == hipSuccess &&
+        hipHostMalloc((void**)&b->down, b->Lo.o_items, hipHostMallocDefault) == hipSuccess &&
+        hipStreamCreate(&b->cap_stream) == hipSuccess) {
+        enc_fill(b->Lo, specs, outs, b->dev, b->up);
+        const EncPlan plan = enc_plan(b->Lo, b->dev);
+        if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            t_capturing = true;
+            const hipError_t e = launch_encode(plan, b->cap_stream);
+            t_capturing = false;
+            const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &b->graph);
+            if (e == hipSuccess && e2 == hipSuccess &&
+                hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess)
+                rc = JIFFY_OK;
+        }
+    }
+    if (rc != JIFFY_OK) {
+        jiffy_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return JIFFY_OK;
+}
+
+int jiffy_batch_run(jiffy_batch* b, const void* const* const* d_planes, size_t* h_lens, uint8_t* h_modes,
+                    hipStream_t stream) {
+    if (!b || !h_lens) return JIFFY_E_INVALID;
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    if (dev != b->device) return JIFFY_E_SHAPE;
+    const uint32_t n = (uint32_t)b->streams.size();
+    if (d_planes) {
+        if (int rc = check_batch(b->streams.data(), n, d_planes, b->outs.data(), b->caps.data(), dev)) return rc;
+        for (uint32_t i = 0; i < n; ++i)
+            b->planes[i].assign(d_planes[i], d_planes[i] + b->streams[i]->layout.n_attrs);
+    }
+    std::vector<EncSpec> specs;
+    std::vector<OutSpec> outs;
+    stream_specs(b->streams.data(), n, b->plane_ptrs.data(), b->outs.data(), b->caps.data(), specs, outs);
+    enc_fill(b->Lo, specs, outs, b->dev, b->up);
+    if (hipMemcpyAsync(b->dev + b->Lo.o_err, b->up, b->Lo.up_bytes(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipGraphLaunch(b->exec, stream) != hipSuccess ||
+        hipMemcpyAsync(b->down, b->dev, b->Lo.o_items, hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    EncResult res;
+    enc_results(b->Lo, b->down, res);
+    return finish_step(b->streams.data(), n, res, h_lens, h_modes);
+}
+
+void jiffy_batch_destroy(jiffy_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->up) (void)hipHostFree(b->up);
+    if (b->down) (void)hipHostFree(b->down);
+    delete b;
 }
 
 }  // extern "C"

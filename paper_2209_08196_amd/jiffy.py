@@ -22,6 +22,7 @@ MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY = 0, 1, 2
 
 SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_peek", "jiffy_decode", "jiffy_status_string",
            "jiffy_stream_create", "jiffy_batch_encode_step", "jiffy_stream_reset", "jiffy_stream_destroy",
+           "jiffy_batch_create", "jiffy_batch_run", "jiffy_batch_destroy",
            "jiffy_profile_enable", "jiffy_profile_read")
 
 
@@ -76,6 +77,12 @@ def lib():
         L.jiffy_stream_reset.argtypes = [vp]
         L.jiffy_stream_destroy.restype = None
         L.jiffy_stream_destroy.argtypes = [vp]
+        L.jiffy_batch_create.restype = ctypes.c_int
+        L.jiffy_batch_create.argtypes = [vp, u32, vp, vp, vp, ctypes.POINTER(vp)]
+        L.jiffy_batch_run.restype = ctypes.c_int
+        L.jiffy_batch_run.argtypes = [vp, vp, vp, vp, vp]
+        L.jiffy_batch_destroy.restype = None
+        L.jiffy_batch_destroy.argtypes = [vp]
         L.jiffy_profile_enable.restype = ctypes.c_int
         L.jiffy_profile_enable.argtypes = [ctypes.c_int]
         L.jiffy_profile_read.restype = ctypes.c_int
@@ -244,6 +251,75 @@ class Stream:
             pass
 
 
+def _batch_args(streams, scans, outs):
+    n = len(streams)
+    sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
+    inner = [(ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
+    planes = (ctypes.c_void_p * n)(*[ctypes.cast(x, ctypes.c_void_p).value for x in inner])
+    dout = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    caps = (ctypes.c_size_t * n)(*[o.numel() for o in outs])
+    return sh, inner, planes, dout, caps
+
+
+def _split_modes(streams, mbuf):
+    modes = np.zeros((len(streams), max(s.layout.n_attrs for s in streams)), np.uint8)
+    k = 0
+    for i, s in enumerate(streams):
+        a = s.layout.n_attrs
+        modes[i, :a] = mbuf[k:k + a]
+        k += a
+    return modes
+
+
+class Batch:
+    """A fixed set of streams encoded together, one HIP graph launch per step
+    (jiffy_batch).  inputs[i][a]: the device tensor ([H, W]) holding stream
+    i's next scan of attribute a (run() may name others); outs[i]: the device
+    uint8 tensor receiving stream i's records, fixed for the batch's life.
+    The tensors must stay alive while the batch reads or writes them."""
+
+    def __init__(self, streams, inputs, outs):
+        self.streams, self.inputs, self.outs = list(streams), inputs, outs
+        sh, self._inner, planes, dout, caps = _batch_args(self.streams, inputs, outs)
+        h = ctypes.c_void_p()
+        rc = lib().jiffy_batch_create(ctypes.cast(sh, ctypes.c_void_p), len(self.streams),
+                                      ctypes.cast(planes, ctypes.c_void_p), ctypes.cast(dout, ctypes.c_void_p),
+                                      ctypes.cast(caps, ctypes.c_void_p), ctypes.byref(h))
+        if rc:
+            raise JiffyError(rc, "jiffy_batch_create")
+        self.handle = h
+        self._lens = (ctypes.c_size_t * len(self.streams))()
+        self._mbuf = np.zeros(sum(s.layout.n_attrs for s in self.streams), np.uint8)
+
+    def run(self, scans=None, stream=None):
+        """One step; scans[i][a] (optional) names this step's input tensors,
+        else the inputs given last are read.  Returns (lengths list, modes
+        ndarray [n, A])."""
+        planes = None
+        if scans is not None:
+            self._inner = [(ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
+            planes = (ctypes.c_void_p * len(self.streams))(*[ctypes.cast(x, ctypes.c_void_p).value
+                                                             for x in self._inner])
+            self.inputs = scans
+        rc = lib().jiffy_batch_run(self.handle, ctypes.cast(planes, ctypes.c_void_p) if planes is not None else None,
+                                   ctypes.cast(self._lens, ctypes.c_void_p),
+                                   self._mbuf.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+        if rc:
+            raise JiffyError(rc, "jiffy_batch_run")
+        return list(self._lens), _split_modes(self.streams, self._mbuf)
+
+    def close(self):
+        if self.handle:
+            lib().jiffy_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def batch_encode_step(streams, scans, outs, stream=None):
     """streams: list of Stream; scans[i]: list of [H, W] device tensors (one
     per attribute); outs[i]: device uint8 tensors.  Returns (lengths list,
@@ -251,14 +327,8 @@ def batch_encode_step(streams, scans, outs, stream=None):
     n = len(streams)
     if n == 0:
         return [], np.zeros((0, 0), np.uint8)
-    A = streams[0].layout.n_attrs
-    sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
-    inner = [(ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
-    planes = (ctypes.c_void_p * n)(*[ctypes.cast(x, ctypes.c_void_p).value for x in inner])
-    dout = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
-    caps = (ctypes.c_size_t * n)(*[o.numel() for o in outs])
+    sh, _inner, planes, dout, caps = _batch_args(streams, scans, outs)
     lens = (ctypes.c_size_t * n)()
-    modes = np.zeros((n, max(s.layout.n_attrs for s in streams)), np.uint8)
     mbuf = np.zeros(sum(s.layout.n_attrs for s in streams), np.uint8)
     rc = lib().jiffy_batch_encode_step(ctypes.cast(sh, ctypes.c_void_p), n, ctypes.cast(planes, ctypes.c_void_p),
                                        ctypes.cast(dout, ctypes.c_void_p), ctypes.cast(caps, ctypes.c_void_p),
@@ -266,10 +336,4 @@ def batch_encode_step(streams, scans, outs, stream=None):
                                        _stream_handle(stream))
     if rc:
         raise JiffyError(rc, "jiffy_batch_encode_step")
-    k = 0
-    for i, s in enumerate(streams):
-        a = s.layout.n_attrs
-        modes[i, :a] = mbuf[k:k + a]
-        k += a
-    del A
-    return list(lens), modes
+    return list(lens), _split_modes(streams, mbuf)
