@@ -147,6 +147,60 @@ def batched_leg(steps, warmup):
             "byte_identical": identical}
 
 
+def serving_leg(duration_s, budgets, scans_per_stream=2):
+    """256 sensor streams (32x1024 .. 128x2048, range u32 and three u16
+    attributes at 1 mm; 10 or 20 Hz each with random phase and jitter)
+    served by continuous batching under device-memory budgets.  Each stream
+    cycles through its first `scans_per_stream` synthetic scans (the
+    sequence it is checked against).  Latency = records on the host minus
+    arrival, in virtual time (each step advances the clock by its measured
+    duration)."""
+    import torch
+
+    import oracle  # checks one served stream against its alone-encoding
+    from paper_2209_08196_amd import serve, synth
+    cfg = synth.CONFIGS[4]
+    gens = [synth.stream(4, s) for s in range(cfg.streams)]
+    store = {1: np.uint8, 2: np.int16, 4: np.int32}
+    host = [g.scans(0, scans_per_stream) for g in gens]
+    dev = [[torch.from_numpy(p.view(store[p.dtype.itemsize])).cuda() for p in h] for h in host]
+    specs = {s: serve.StreamSpec(g.H, g.W, tuple(g.widths), tuple(g.precisions)) for s, g in enumerate(gens)}
+    arrivals = synth.serving_arrivals(cfg.streams, duration_s)
+    check = arrivals[0][1]  # the first stream to arrive is admitted under any budget that admits one
+    ks = [k for _, s, k in arrivals if s == check]
+    g = gens[check]
+    seq = [np.stack([host[check][a][k % scans_per_stream] for k in ks]) for a in range(len(g.widths))]
+    want = split_records(oracle.encode(seq, g.precisions)[0])
+    A = len(g.widths)
+    out = {"workload": f"{cfg.name}, {duration_s} s of arrivals", "streams": cfg.streams,
+           "scans_offered": len(arrivals)}
+    for budget in budgets:
+        srv = serve.Server.gpu(specs, budget)
+        st = srv.run(arrivals, lambda sid, k: [p[k % scans_per_stream] for p in dev[sid]], keep_results={check})
+        res = st.summary()
+        got = srv.results[check]
+        res["alone_equal"] = len(got) == len(ks) and all(
+            r == b"".join(want[k * A:(k + 1) * A]) for k, r in enumerate(got))
+        srv.close()
+        out[f"budget_{budget >> 20}MiB"] = res
+        print(f"[bench] serving budget {budget >> 20} MiB: {res}", file=sys.stderr, flush=True)
+    return out
+
+
+def split_records(s: bytes):
+    """The records of a stream with a record-length table (its header)."""
+    A, = struct.unpack_from("<H", s, 6)
+    T, = struct.unpack_from("<I", s, 16)
+    p = 20 + 8 * A
+    lens = struct.unpack_from(f"<{T * A}I", s, p)
+    p += 4 * T * A
+    out = []
+    for L in lens:
+        out.append(s[p:p + L])
+        p += L
+    return out
+
+
 def copy_run(nbytes):
     """A plain device copy of known size, three times: what FETCH_SIZE and
     WRITE_SIZE read for it calibrates those counters."""
@@ -211,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
     ap.add_argument("--only-batched", action="store_true", help="run only the 64-stream batched leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the 256-stream serving leg")
+    ap.add_argument("--only-serving", action="store_true", help="run only the 256-stream serving leg")
     ap.add_argument("--profile-steps", type=int, default=3, help="steps timed per kernel with HIP events")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (counter calibration)")
@@ -223,6 +279,11 @@ def main():
         return
     if args.copy_bytes:
         copy_run(args.copy_bytes)
+        return
+    if args.only_serving:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(serving_leg(1.0, [8 << 30, 64 << 20])), flush=True)
         return
     if args.only_batched:
         import torch
@@ -345,6 +406,8 @@ def main():
     if not args.no_batched:
         result["batched"] = batched_leg(steps=8, warmup=2)
         print(f"[bench] batched: {result['batched']}", file=sys.stderr, flush=True)
+    if not args.no_serving:
+        result["serving"] = serving_leg(1.0, [8 << 30, 64 << 20])
 
     if not args.no_cpu_baseline:
         import oracle  # the CPU-baseline leg: the oracle timed on the host
