@@ -151,14 +151,13 @@ def serving_leg(duration_s, budgets, scans_per_stream=2):
     """256 sensor streams (32x1024 .. 128x2048, range u32 and three u16
     attributes at 1 mm; 10 or 20 Hz each with random phase and jitter)
     served by continuous batching under device-memory budgets.  Each stream
-    cycles through its first `scans_per_stream` synthetic scans (the
-    sequence it is checked against).  Latency = records on the host minus
-    arrival, in virtual time (each step advances the clock by its measured
-    duration)."""
+    cycles through its first `scans_per_stream` synthetic scans.  Latency =
+    records on the host minus arrival, in virtual time (each step advances
+    the clock by its measured duration).  One served stream's records are
+    compared with encoding its whole sequence alone (jiffy_encode)."""
     import torch
 
-    import oracle  # checks one served stream against its alone-encoding
-    from paper_2209_08196_amd import serve, synth
+    from paper_2209_08196_amd import jiffy, serve, synth
     cfg = synth.CONFIGS[4]
     gens = [synth.stream(4, s) for s in range(cfg.streams)]
     store = {1: np.uint8, 2: np.int16, 4: np.int32}
@@ -169,8 +168,10 @@ def serving_leg(duration_s, budgets, scans_per_stream=2):
     check = arrivals[0][1]  # the first stream to arrive is admitted under any budget that admits one
     ks = [k for _, s, k in arrivals if s == check]
     g = gens[check]
-    seq = [np.stack([host[check][a][k % scans_per_stream] for k in ks]) for a in range(len(g.widths))]
-    want = split_records(oracle.encode(seq, g.precisions)[0])
+    # its alone-encoding: the whole sequence in one jiffy_encode call
+    seq = [torch.stack([dev[check][a][k % scans_per_stream] for k in ks]).contiguous() for a in range(len(g.widths))]
+    alone, _ = jiffy.encode(seq, g.precisions)
+    want = split_records(alone.cpu().numpy().tobytes())
     A = len(g.widths)
     out = {"workload": f"{cfg.name}, {duration_s} s of arrivals", "streams": cfg.streams,
            "scans_offered": len(arrivals)}
