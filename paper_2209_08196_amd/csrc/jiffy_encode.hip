@@ -126,16 +126,17 @@ __device__ __forceinline__ uint32_t quad_frame_key(uint32_t z[32], uint32_t* vro
         B = max(B, w);
         __hip_atomic_fetch_add(hist + (w ? w - 1u : 32u + q), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
-    if (kStash) {  // the codes replace the values (read again for the exceptions)
-        uint4* v4 = (uint4*)(vrow + 36 * q);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) v4[c] = make_uint4(z[4 * c], z[4 * c + 1], z[4 * c + 2], z[4 * c + 3]);
-    }
     B = max(B, dpp_mov<kQuadXor1>(B));
     B = max(B, dpp_mov<kQuadXor2>(B));
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     // n(b) = values wider than b bits; lane q evaluates b = 8q .. 8q+7
     const uint4 ha = h4[2 * q], hb = h4[2 * q + 1];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (kStash) {  // the codes replace the values (and the histogram, when it lives there)
+        uint4* v4 = (uint4*)(vrow + 36 * q);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v4[c] = make_uint4(z[4 * c], z[4 * c + 1], z[4 * c + 2], z[4 * c + 3]);
+    }
     const uint32_t h[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};  // widths 8q+1 .. 8q+8
     uint32_t loc = 0;
 #pragma unroll
@@ -178,68 +179,60 @@ __device__ __forceinline__ uint32_t frame_cost_quad(uint32_t* vrow, uint32_t rea
     return quad_frame_key<false>(z, vrow, vrow, real, pred, bits, q, B) >> 14;
 }
 
-// vrow: the frame's values (row layout); on return it holds their ZigZag
-// codes.  orow: the quad's output row.  The packed frame goes to `slot`,
-// b | n << 8 | B << 16 to *info.
-__device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t* orow, uint32_t real, uint32_t pred,
-                                                uint32_t bits, uint32_t q, JG uint8_t* slot, JG uint32_t* info) {
+// vrow: the frame's values (row layout); the width histogram, then the
+// codes replace them.  The packed frame goes straight to its slot: lane q
+// stores its b words of low bits (words qb .. qb+b-1); then lane 0 writes
+// the exception bytes -- the positions, then the high parts -- as one
+// little-endian bit stream from byte 16b, reading the exceptions' codes
+// back from vrow.  b | n << 8 | B << 16 goes to *info.
+__device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t real, uint32_t pred, uint32_t bits,
+                                                uint32_t q, JG uint8_t* slot, JG uint32_t* info) {
     uint32_t z[32], B;
     load_quad_values(vrow, q, z);
-    const uint32_t key = quad_frame_key<true>(z, vrow, orow, real, pred, bits, q, B);
-    uint4* o4 = (uint4*)orow;
-    const uint32_t i0 = 32u * q;
-    const uint32_t b = 63u - ((key >> 8) & 63u), nexc = key & 255u, cost = key >> 14;
+    const uint32_t key = quad_frame_key<true>(z, vrow, vrow, real, pred, bits, q, B);
+    const uint32_t b = 63u - ((key >> 8) & 63u), nexc = key & 255u;
     const uint32_t hw = B - b, lm = low_mask32(b);
-    uint32_t ex = 0;  // this lane's exceptions
-#pragma unroll
-    for (int i = 0; i < 32; ++i) ex |= (z[i] > lm ? 1u : 0u) << i;
-    const uint32_t ne = __popc(ex);
-    const uint32_t e0 = quad_bcast<0>(ne), e1 = quad_bcast<1>(ne), e2 = quad_bcast<2>(ne);
-    const uint32_t E = (q > 0 ? e0 : 0u) + (q > 1 ? e1 : 0u) + (q > 2 ? e2 : 0u);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    const uint32_t cw = (cost + 3u) / 4u;  // words of the packed frame
-    // exception area (positions, then high parts) starts zeroed
-    for (uint32_t w = 4u * b + q; w < cw; w += 4) orow[w] = 0u;
-    {  // low b bits of each value: words qb .. qb+b-1
-        // the word being filled is stored after every value (no branches); its
-        // last store is the complete word.  With b = 0 this writes zeros to
-        // word 0, which belongs to the (zeroed) exception area.
-        uint32_t* dst = orow + q * b;
+    JG uint32_t* sw = (JG uint32_t*)slot;
+    {  // low b bits of each value
+        JG uint32_t* dst = sw + q * b;
         uint64_t acc = 0;
         uint32_t nacc = 0, wi = 0;
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
             acc |= (uint64_t)(z[i] & lm) << nacc;
             nacc += b;
-            dst[wi] = (uint32_t)acc;
-            const bool full = nacc >= 32;
-            acc = full ? acc >> 32 : acc;
-            nacc = full ? nacc - 32 : nacc;
-            wi += full ? 1u : 0u;
+            if (nacc >= 32) {
+                dst[wi++] = (uint32_t)acc;
+                acc >>= 32;
+                nacc -= 32;
+            }
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    if (ex) {  // positions at byte 16b + rank, high parts from byte 16b + nexc
-        uint8_t* ob = (uint8_t*)orow;
-        const uint32_t hb0 = 8u * (16u * b + nexc);
-        uint32_t r = E;
-        do {
-            const uint32_t i = __builtin_ctz(ex);
-            ex &= ex - 1u;
-            const uint32_t zi = vrow[row_off(i0 + i)];
-            ob[16u * b + r] = (uint8_t)(i0 + i);
-            const uint32_t o = hb0 + r * hw;
-            const uint64_t sh = (uint64_t)(zi >> b) << (o & 31u);
-            __hip_atomic_fetch_or(orow + (o >> 5), (uint32_t)sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            if (sh >> 32)
-                __hip_atomic_fetch_or(orow + (o >> 5) + 1, (uint32_t)(sh >> 32), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
-            ++r;
-        } while (ex);
+    uint32_t ex = 0;  // this lane's exceptions
+#pragma unroll
+    for (int i = 0; i < 32; ++i) ex |= (z[i] > lm ? 1u : 0u) << i;
+    const uint32_t x1 = quad_bcast<1>(ex), x2 = quad_bcast<2>(ex), x3 = quad_bcast<3>(ex);
+    if (q == 0 && nexc) {
+        // positions (8 bits each) then high parts (hw bits each), from byte 16b
+        JG uint32_t* dst = sw + 4u * b;
+        uint64_t acc = 0;
+        uint32_t nacc = 0, wi = 0;
+        auto put = [&](uint32_t v, uint32_t nbits) {
+            acc |= (uint64_t)v << nacc;
+            nacc += nbits;
+            if (nacc >= 32) {
+                dst[wi++] = (uint32_t)acc;
+                acc >>= 32;
+                nacc -= 32;
+            }
+        };
+        const uint32_t xs[4] = {ex, x1, x2, x3};
+        for (uint32_t h = 0; h < 4; ++h)
+            for (uint32_t m = xs[h]; m; m &= m - 1u) put(32u * h + __builtin_ctz(m), 8);
+        for (uint32_t h = 0; h < 4; ++h)
+            for (uint32_t m = xs[h]; m; m &= m - 1u) put(vrow[row_off(32u * h + __builtin_ctz(m))] >> b, hw);
+        if (nacc) dst[wi] = (uint32_t)acc;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    JG uint4* s4 = (JG uint4*)slot;
-    for (uint32_t c = q; c < (cost + 15u) / 16u; c += 4) s4[c] = o4[c];
     if (q == 0) *info = b | (nexc << 8) | (B << 16);
 }
 
@@ -373,10 +366,10 @@ __device__ __forceinline__ uint32_t residual_at(const EncItem& it, uint32_t mode
 
 
 struct TileLds {
-    uint32_t rows[(kTileFrames + kTileQuads) * kRow];  // frame rows, then the quads' output rows
+    uint32_t rows[kTileFrames * kRow];  // frame rows
+    uint32_t sink[256];                 // where the compaction's unkept values go
     uint32_t scratch[8];
     uint32_t pred;
-    __device__ uint32_t* outs() { return rows + kTileFrames * kRow; }
 };
 
 template <int WB>
@@ -416,14 +409,13 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
     const uint32_t off = block_excl_scan<256>(__popc(keep), L.scratch, &nv);
     const uint32_t jf = kb >> 7;
     {
-        // kept values go to their row; the others to a word of this thread's
-        // in the (not yet used) output rows
+        // kept values go to their row; the others to this thread's sink word
         uint32_t k = kb + off;  // index of the next kept value
-        const uint32_t dummy = kTileFrames * kRow + tid;
+        uint32_t* const dummy = L.sink + tid;
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
             const bool kp = (keep >> i) & 1u;
-            L.rows[kp ? tile_word(k, jf) : dummy] = s[i];
+            *(kp ? L.rows + tile_word(k, jf) : dummy) = s[i];
             k += kp ? 1u : 0u;
         }
     }
@@ -458,7 +450,7 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
     if (whole) pred = k0 > kb ? value_at(k0 - 1) : L.pred;
     __syncthreads();  // every row is read before its quad overwrites it
     if (!whole) return;
-    code_frame_quad(L.rows + (j - jf) * kRow, L.outs() + g * kRow, kend - k0, pred, it.bits, q,
+    code_frame_quad(L.rows + (j - jf) * kRow, kend - k0, pred, it.bits, q,
                     it.slots + (size_t)j * kSlotBytes, it.blkinfo + j);
 }
 
@@ -480,7 +472,7 @@ __global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
 __global__ __launch_bounds__(64) void k_enc_fixup(EncPlan plan) {
     const uint32_t g = threadIdx.x >> 2, q = threadIdx.x & 3u;
     const uint32_t t = blockIdx.x * 16 + g;
-    __shared__ uint32_t rows[16 * kRow], outs[16 * kRow];
+    __shared__ uint32_t rows[16 * kRow];
     if (t >= plan.n_ftiles) return;  // no barrier follows
     const uint32_t r = plan.ftile_item[t];
     const uint32_t lt = t - plan.ftile_first[r];
@@ -496,7 +488,7 @@ __global__ __launch_bounds__(64) void k_enc_fixup(EncPlan plan) {
     for (int c = 0; c < 8; ++c) v4[c] = s4[8 * q + c];
     const uint32_t pred = ((const JG uint32_t*)slot)[kFrame];
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    code_frame_quad(rows + g * kRow, outs + g * kRow, real, pred, it.bits, q, slot, it.blkinfo + j);
+    code_frame_quad(rows + g * kRow, real, pred, it.bits, q, slot, it.blkinfo + j);
 }
 
 // ---------------------------------------------------------------------------
