@@ -33,16 +33,44 @@ __device__ __forceinline__ uint32_t rd32(const uint8_t* p) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
-    const uint32_t r = blockIdx.x;
+// Record parse.  blockIdx.y = 0: the record header and the mask frame (Raw
+// and RLE blocks) into mask bytes; blockIdx.y = 1: the residual section
+// header into per-frame widths and section offsets.  The two parts of a
+// record are independent (the section starts after the mask frame, whose
+// length is in the record header).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSeg = 32;                      // bytes per thread segment of a window
+constexpr uint32_t kSegs = kWin / kSeg;            // 256: one per thread
+constexpr uint32_t kSegsPerChunk = kChunk / kSeg;  // 8
+constexpr uint16_t kXOut = 0xFFFFu;                // the chain leaves the window (a valid position)
+constexpr uint16_t kXBad = 0xFFFEu;                // no valid block header here
+constexpr uint16_t kXLast = 0xFFFDu;               // the last block; it ends the frame exactly
+static_assert(kWin <= 0xFFF0u && kSegs == 256, "window offsets fit 16 bits; one segment per thread");
+
+struct ParseLds {
+    union {
+        struct {
+            uint16_t X[kWin];  // per position: the first chain position at or after its segment's end
+            uint16_t Y[kWin];  // per position: the first chain position at or after its chunk's end
+        } x;
+        struct {  // a block takes 3 bytes at least
+            uint32_t dst[kWin / 3 + 2];  // block k: content offset of its first byte (and the end)
+            uint32_t src[kWin / 3 + 1];  // block k: frame offset of its content | RLE << 31
+        } t;
+    } u;
+    uint32_t fwin[kWin / 4 + 2];  // the window's frame bytes (and the two after it)
+    uint16_t seg_entry[kSegs];    // first chain position in each segment (window offset), or kXBad
+    uint16_t c_entry[kWinChunks];
+    uint32_t scratch[8];
+    uint32_t s_err, s_done, s_next, s_pos, s_flen, s_nblk;
+};
+
+__device__ void parse_mask(const DecPlan& plan, uint32_t r, ParseLds& P) {
     const DecItem it = plan.items[r];
     const uint8_t* rec = it.rec;
     const uint32_t L = it.rec_len;
     const uint32_t nm = div_up(it.npx, 8);
     const uint32_t tid = threadIdx.x;
-    __shared__ uint32_t s_err, s_pos, s_done, s_flen, s_mode;
-    __shared__ uint32_t scratch[8];
-
     if (tid == 0) {
         uint32_t err = 0;
         const uint32_t mode = rec[4], attr = rec[5];
@@ -73,199 +101,200 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
                 }
             }
         }
-        s_err = err;
-        s_pos = pos;
-        s_done = 0;
-        s_flen = flen;
-        s_mode = mode;
+        P.s_err = err;
+        P.s_pos = pos;
+        P.s_done = 0;
+        P.s_flen = flen;
+        plan.res[r].mode = mode;
+        plan.res[r].flen = flen;
+        plan.modes[r] = (uint8_t)mode;
     }
     __syncthreads();
-    const uint32_t flen = s_flen;
-    uint8_t* cwb = (uint8_t*)it.cw;
-    // The block headers form a chain (each one gives the next one's
-    // position).  The frame is taken in windows of kWin positions: every
-    // position gets the position of the block that would follow a header
-    // there; pointer jumping inside kChunk-byte chunks turns that into each
-    // position's exit from its chunk; one lane then follows the true chain
-    // from chunk to chunk (at most kWin / kChunk steps); lanes walk the
-    // chunks in parallel to build the block table; all lanes expand it.
-    __shared__ uint32_t J[kWin];
-    __shared__ uint32_t fwin[kWin / 4 + 2];  // the window's frame bytes (and the two after it)
-    __shared__ uint32_t c_entry[kWinChunks], c_cnt[kWinChunks], c_size[kWinChunks];
-    __shared__ uint32_t c_boff[kWinChunks + 1], c_coff[kWinChunks + 1];
-    __shared__ uint32_t s_changed;
+    const uint32_t flen = P.s_flen;
     const uint8_t* f = rec + 12;
-    const uint8_t* fb = (const uint8_t*)fwin;
-    uint32_t wbase = 0, wlen = 0;  // frame offset of fwin's first byte (records are 4-aligned), bytes staged
-    // a block header at frame offset i, read from the staged window
-    auto header_next = [&](uint32_t i, uint32_t* size_out, uint32_t* rle_out) -> uint32_t {
-        if (i + 3 > flen) return kJInvalid;
-        const uint8_t* hp = fb + (i - wbase);
-        const uint32_t h = (uint32_t)hp[0] | ((uint32_t)hp[1] << 8) | ((uint32_t)hp[2] << 16);
-        const uint32_t last = h & 1, type = (h >> 1) & 3, size = h >> 3;
-        if (type > 1 || size > kZstdBlockMax) return kJInvalid;
-        const uint32_t n = i + 3 + (type ? 1u : size);
-        if (size_out) *size_out = size;
-        if (rle_out) *rle_out = type;
-        if (last) return n == flen ? kJLast : kJInvalid;
-        return n < flen ? n : kJInvalid;
-    };
-    uint32_t wentry = s_pos, content = 0;
-    bool fin = false;
-    while (!s_err && !fin) {
-        const uint32_t ws = wentry, we = min(ws + kWin, flen);
+    const uint8_t* fb = (const uint8_t*)P.fwin;
+    uint8_t* cwb = (uint8_t*)it.cw;
+    // The block headers form a chain: each one gives the position of the
+    // next.  The frame is taken in windows of kWin positions.  Every thread
+    // owns a 32-byte segment: walking it backwards it finds, for each
+    // position, where a chain through that position leaves the segment; a
+    // few rounds of pointer jumping turn that into where it leaves the
+    // 256-byte chunk.  One lane then follows the true chain from chunk to
+    // chunk, 32 lanes from segment to segment inside their chunk, and every
+    // lane walks its own segment to list the blocks; all lanes expand them.
+    uint32_t ws = P.s_pos, content = 0;
+    while (!P.s_err && !P.s_done) {
+        const uint32_t we = min(ws + kWin, flen);
         if (ws >= flen) {  // a header must start here: the chain ran off the frame
-            __syncthreads();
-            if (tid == 0) s_err = 1;
-            __syncthreads();
-            break;
+            if (tid == 0) P.s_err = 1;
+            break;  // uniform: every thread sees the same ws and flen
         }
+        uint32_t wbase, wlen;
         {  // stage frame bytes [ws, we + 2) with word loads (the record is 4-byte aligned)
             const uint32_t r0 = (12 + ws) & ~3u, r1 = min(12 + we + 2, L);
             const uint32_t* rw = (const uint32_t*)rec;
-            for (uint32_t w = r0 / 4 + tid; w * 4 < r1; w += 256) fwin[w - r0 / 4] = rw[w];
+            for (uint32_t w = r0 / 4 + tid; w * 4 < r1; w += 256) P.fwin[w - r0 / 4] = rw[w];
             wbase = r0 - 12;
             wlen = r1 - r0;
         }
+        // the block that would start at frame offset i: its next position,
+        // and its content size and type
+        auto header = [&](uint32_t i, uint32_t& size, uint32_t& rle) -> uint32_t {
+            if (i + 3 > flen) return kJInvalid;
+            const uint8_t* hp = fb + (i - wbase);
+            const uint32_t h = (uint32_t)hp[0] | ((uint32_t)hp[1] << 8) | ((uint32_t)hp[2] << 16);
+            const uint32_t last = h & 1, type = (h >> 1) & 3;
+            size = h >> 3;
+            rle = type;
+            if (type > 1 || size > kZstdBlockMax) return kJInvalid;
+            const uint32_t n = i + 3 + (type ? 1u : size);
+            if (last) return n == flen ? kJLast : kJInvalid;
+            return n < flen ? n : kJInvalid;
+        };
+        auto code = [&](uint32_t n) -> uint16_t {  // a next position as a window offset or a mark
+            if (n == kJInvalid) return kXBad;
+            if (n == kJLast) return kXLast;
+            return n >= we ? kXOut : (uint16_t)(n - ws);
+        };
         __syncthreads();
-        for (uint32_t i = ws + tid; i < we; i += 256) J[i - ws] = header_next(i, nullptr, nullptr);
+        const uint32_t s0 = ws + tid * kSeg, s1 = min(s0 + kSeg, we);
+        for (uint32_t i = s1; i-- > s0;) {  // backwards over this thread's segment
+            uint32_t size, rle;
+            const uint32_t n = header(i, size, rle);
+            const uint16_t c = code(n);
+            P.u.x.X[i - ws] = (c >= kXLast || n >= s1) ? c : P.u.x.X[n - ws];
+        }
         __syncthreads();
-        // pointer jumping until every position holds its chunk exit
-        for (int round = 0; round < 16; ++round) {
-            if (tid == 0) s_changed = 0;
-            __syncthreads();
-            uint32_t ch = 0;
+        for (uint32_t i = ws + tid; i < we; i += 256) P.u.x.Y[i - ws] = P.u.x.X[i - ws];
+        __syncthreads();
+        // each step spans a segment at least, so three doublings reach the chunk's end
+        for (int round = 0; round < 3; ++round) {
             for (uint32_t i = ws + tid; i < we; i += 256) {
-                const uint32_t j = J[i - ws];
-                if (j < we && (j - ws) / kChunk == (i - ws) / kChunk) {
-                    J[i - ws] = J[j - ws];
-                    ch = 1;
-                }
+                const uint16_t j = P.u.x.Y[i - ws];
+                if (j < kXLast && j / kChunk == (i - ws) / kChunk) P.u.x.Y[i - ws] = P.u.x.Y[j];
             }
-            if (ch) s_changed = 1;
             __syncthreads();
-            if (!s_changed) break;
         }
-        // follow the true chain over the chunks
-        for (uint32_t c = tid; c < kWinChunks; c += 256) c_entry[c] = kJInvalid;
+        // the true chain: chunk entries (one lane), then segment entries (a lane per chunk)
+        if (tid < kWinChunks) P.c_entry[tid] = kXBad;
+        P.seg_entry[tid] = kXBad;
         __syncthreads();
         if (tid == 0) {
-            uint32_t e = ws, err = 0;
-            while (e < we) {
-                c_entry[(e - ws) / kChunk] = e;
-                e = J[e - ws];
+            uint32_t e = 0;
+            while (e < kXLast) {
+                P.c_entry[e / kChunk] = (uint16_t)e;
+                e = P.u.x.Y[e];
             }
-            if (e == kJInvalid) err = 1;
-            else if (e == kJLast) s_done = 1;
-            else wentry = e;  // first header of the next window
-            s_err = err;
-            s_pos = e;
         }
         __syncthreads();
-        if (s_err) break;
-        wentry = s_pos;
-        fin = s_done;
-        // per-chunk block counts and content sizes
-        for (uint32_t c = tid; c < kWinChunks; c += 256) {
-            uint32_t cnt = 0, csz = 0;
-            const uint32_t cend = ws + (c + 1) * kChunk;
-            for (uint32_t pos = c_entry[c]; pos != kJInvalid && pos < cend && pos < we;) {
-                uint32_t size = 0, rle = 0;
-                const uint32_t n = header_next(pos, &size, &rle);
-                cnt++;
-                csz += size;
-                if (n >= kJLast) break;
-                pos = n;
+        if (tid < kWinChunks) {
+            for (uint32_t e = P.c_entry[tid]; e < kXLast && e / kChunk == tid;) {
+                P.seg_entry[e / kSeg] = (uint16_t)e;
+                e = P.u.x.X[e];
             }
-            c_cnt[c] = cnt;
-            c_size[c] = csz;
         }
         __syncthreads();
-        if (tid == 0) {
-            uint32_t b = 0, co = content;
-            for (uint32_t c = 0; c < kWinChunks; ++c) {
-                c_boff[c] = b;
-                c_coff[c] = co;
-                b += c_cnt[c];
-                co += c_size[c];
+        // every lane: the blocks that start in its segment
+        uint32_t cnt = 0, csz = 0, exit_n = 0, has_exit = 0;
+        for (uint32_t e = P.seg_entry[tid]; e < kXLast && e / kSeg == tid;) {
+            uint32_t size, rle;
+            const uint32_t n = header(ws + e, size, rle);
+            cnt++;
+            csz += size;
+            if (n >= we) {  // the chain leaves the window (or the frame ends) after this block
+                exit_n = n;
+                has_exit = 1;
+                break;
             }
-            c_boff[kWinChunks] = b;
-            c_coff[kWinChunks] = co;
-            if (co > nm) s_err = 1;
+            e = n - ws;
         }
-        __syncthreads();
-        if (s_err) break;
-        // block table (reuses J): tdst[k] content offset, tsrc[k] frame offset | RLE << 31
-        uint32_t* tdst = J;
-        uint32_t* tsrc = J + kWin / 2;
-        const uint32_t nblk = c_boff[kWinChunks];
-        for (uint32_t c = tid; c < kWinChunks; c += 256) {
-            uint32_t k = c_boff[c], d = c_coff[c];
-            const uint32_t cend = ws + (c + 1) * kChunk;
-            for (uint32_t pos = c_entry[c]; pos != kJInvalid && pos < cend && pos < we;) {
-                uint32_t size = 0, rle = 0;
-                const uint32_t n = header_next(pos, &size, &rle);
-                tdst[k] = d;
-                tsrc[k] = (pos + 3) | (rle << 31);
+        uint32_t nblk, ctot;
+        const uint32_t boff = block_excl_scan<256>(cnt, P.scratch, &nblk);
+        const uint32_t coff = content + block_excl_scan<256>(csz, P.scratch, &ctot);
+        if (has_exit) {
+            if (exit_n == kJInvalid) P.s_err = 1;
+            else if (exit_n == kJLast) P.s_done = 1;
+            else P.s_next = exit_n;
+        }
+        if (tid == 0 && (nblk == 0 || content + ctot > nm)) P.s_err = 1;
+        // the block table (the jump tables are no longer needed)
+        {
+            uint32_t k = boff, d = coff;
+            for (uint32_t e = P.seg_entry[tid]; e < kXLast && e / kSeg == tid;) {
+                uint32_t size, rle;
+                const uint32_t n = header(ws + e, size, rle);
+                P.u.t.dst[k] = d;
+                P.u.t.src[k] = (ws + e + 3) | (rle << 31);
                 k++;
                 d += size;
-                if (n >= kJLast) break;
-                pos = n;
+                if (n >= we) break;
+                e = n - ws;
             }
         }
-        if (tid == 0) tdst[nblk] = c_coff[kWinChunks];
+        if (tid == 0) P.u.t.dst[nblk] = content + ctot;
         __syncthreads();
-        if (nblk) {
-            const uint32_t d0 = tdst[0], d1 = tdst[nblk];
-            for (uint32_t q = (d0 & ~3u) + 4 * tid; q < d1; q += 4 * 256) {
-                // block holding byte max(q, d0): largest k with tdst[k] <= it
-                const uint32_t first = q < d0 ? d0 : q;
-                uint32_t lo = 0, hi = nblk - 1;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (tdst[mid] <= first) lo = mid; else hi = mid - 1;
-                }
-                uint32_t k = lo, word = 0, full = 1;
-                for (uint32_t b = 0; b < 4; ++b) {
-                    const uint32_t d = q + b;
-                    if (d < d0 || d >= d1) { full = 0; continue; }
-                    while (d >= tdst[k + 1]) k++;
-                    const uint32_t src = tsrc[k] & 0x7FFFFFFFu;
-                    const uint32_t sb = (tsrc[k] >> 31) ? src : src + (d - tdst[k]);  // frame byte
-                    const uint32_t v = sb - wbase < wlen ? fb[sb - wbase] : f[sb];
-                    word |= v << (8 * b);
-                }
-                if (full) *(uint32_t*)(cwb + q) = word;
-                else
-                    for (uint32_t b = 0; b < 4; ++b)
-                        if (q + b >= d0 && q + b < d1) cwb[q + b] = (uint8_t)(word >> (8 * b));
+        if (P.s_err) break;
+        const uint32_t d0 = content, d1 = content + ctot;
+        for (uint32_t q = (d0 & ~3u) + 4 * tid; q < d1; q += 4 * 256) {
+            // block holding byte max(q, d0): the largest k with dst[k] <= it
+            const uint32_t first = q < d0 ? d0 : q;
+            uint32_t lo = 0, hi = nblk - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (P.u.t.dst[mid] <= first) lo = mid; else hi = mid - 1;
             }
+            uint32_t k = lo, word = 0, full = 1;
+            for (uint32_t b = 0; b < 4; ++b) {
+                const uint32_t d = q + b;
+                if (d < d0 || d >= d1) { full = 0; continue; }
+                while (d >= P.u.t.dst[k + 1]) k++;
+                const uint32_t src = P.u.t.src[k] & 0x7FFFFFFFu;
+                const uint32_t sb = (P.u.t.src[k] >> 31) ? src : src + (d - P.u.t.dst[k]);  // frame byte
+                const uint32_t v = sb - wbase < wlen ? fb[sb - wbase] : f[sb];
+                word |= v << (8 * b);
+            }
+            if (full) *(uint32_t*)(cwb + q) = word;
+            else
+                for (uint32_t b = 0; b < 4; ++b)
+                    if (q + b >= d0 && q + b < d1) cwb[q + b] = (uint8_t)(word >> (8 * b));
         }
-        content = c_coff[kWinChunks];
+        content = d1;
+        ws = P.s_next;
         __syncthreads();
     }
-    if (tid == 0 && !s_err && content != nm) s_err = 1;
     __syncthreads();
+    if (tid == 0 && !P.s_err && content != nm) P.s_err = 1;
     // bytes past the mask content in its last word
     for (uint32_t i = nm + tid; i < it.nwords * 8u; i += 256) cwb[i] = 0;
+    __syncthreads();
+    if (tid == 0 && P.s_err) atomicOr(plan.err, kErrCorrupt);
+}
 
-    // residual section header
-    __shared__ uint32_t s_N, s_nb, s_sec;
-    if (tid == 0 && !s_err) {
-        const uint32_t sec = align4(12 + flen);
-        uint32_t err = 0, N = 0, nb = 0;
-        if (sec + 4 > L) err = 1;
+__device__ void parse_sections(const DecPlan& plan, uint32_t r, ParseLds& P) {
+    const DecItem it = plan.items[r];
+    const uint8_t* rec = it.rec;
+    const uint32_t L = it.rec_len;
+    const uint32_t tid = threadIdx.x;
+    __shared__ uint32_t s_N, s_nb, s_sec, s_err;
+    if (tid == 0) {
+        const uint32_t flen = rd32(rec + 8);
+        uint32_t err = 0, N = 0, nb = 0, sec = 0;
+        if (flen > L - 12) err = 1;
         else {
-            N = rd32(rec + sec);
-            if (N > it.npx) err = 1;
-            nb = div_up(N, kFrame);
-            if (!err && sec + align4(4 + 3 * nb) > L) err = 1;
+            sec = align4(12 + flen);
+            if (sec + 4 > L) err = 1;
+            else {
+                N = rd32(rec + sec);
+                if (N > it.npx) err = 1;
+                nb = div_up(N, kFrame);
+                if (!err && sec + align4(4 + 3 * nb) > L) err = 1;
+            }
         }
         s_err = err; s_N = N; s_nb = nb; s_sec = sec;
     }
     __syncthreads();
     if (s_err) {
-        if (tid == 0) { plan.res[r].err = 1; atomicOr(plan.err, kErrCorrupt); }
+        if (tid == 0) atomicOr(plan.err, kErrCorrupt);
         return;
     }
     const uint32_t sec = s_sec, N = s_N, nb = s_nb;
@@ -283,9 +312,9 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
             it.blkinfo[j] = b | (n << 8) | (B << 16);
         }
         uint32_t tp, tn, th;
-        const uint32_t op = block_excl_scan<256>(pay, scratch, &tp);
-        const uint32_t on = block_excl_scan<256>(pos, scratch, &tn);
-        const uint32_t oh = block_excl_scan<256>(high, scratch, &th);
+        const uint32_t op = block_excl_scan<256>(pay, P.scratch, &tp);
+        const uint32_t on = block_excl_scan<256>(pos, P.scratch, &tn);
+        const uint32_t oh = block_excl_scan<256>(high, P.scratch, &th);
         if (j < nb) {
             it.blkoffs[3 * j] = cp + op;
             it.blkoffs[3 * j + 1] = cn + on;
@@ -301,8 +330,6 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
         uint32_t err = s_err;
         if ((uint64_t)pay0 + align4(cp + cn + ch) != L) err = 1;
         DecRes& rs = plan.res[r];
-        rs.mode = s_mode;
-        rs.flen = flen;
         rs.N = N;
         rs.nb = nb;
         rs.sec = sec;
@@ -310,10 +337,14 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
         rs.pos_off = pay0 + cp;
         rs.high_off = pay0 + cp + cn;
         rs.high_end = pay0 + cp + cn + ch;
-        rs.err = err;
-        plan.modes[r] = (uint8_t)s_mode;
         if (err) atomicOr(plan.err, kErrCorrupt);
     }
+}
+
+__global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
+    __shared__ ParseLds P;
+    if (blockIdx.y == 0) parse_mask(plan, blockIdx.x, P);
+    else parse_sections(plan, blockIdx.x, P);
 }
 
 // ---------------------------------------------------------------------------
@@ -724,7 +755,7 @@ __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
 
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
-    JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items, 2), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(plan.nwords, 64), plan.n_attrs), dim3(64), stream, plan);
     JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_dec_tiles", k_dec_tiles, dim3(plan.n_items * plan.nft), dim3(kDecThreads), stream, plan);

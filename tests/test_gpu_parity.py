@@ -212,3 +212,22 @@ def test_incompressible_tiles(J):
         outs = J.decode(torch.from_numpy(np.frombuffer(s_ref, np.uint8).copy()).cuda())
         for o, r in zip(outs, ref):
             assert np.array_equal(to_host(o, r.dtype.itemsize), r)
+
+
+def test_large_masks_split_blocks(J):
+    """Mask content over 128 KiB: RLE runs and Raw stretches split at the
+    block limit, frames spanning many parse windows; encode and decode."""
+    import torch
+    rng = np.random.default_rng(41)
+    H, W = 1024, 1280
+    full = rng.integers(1, 256, size=(2, H, W), dtype=np.uint64).astype(np.uint8)  # no zeros: one long run
+    sparse = full.copy()
+    sparse[:, rng.random((H, W)) < 0.5] = 0  # random mask bytes: Raw blocks
+    blocky = full.copy()
+    blocky[1, 100:700] = 0  # a P-scan whose XOR mask has long runs
+    for name, x in (("full", full), ("sparse", sparse), ("blocky", blocky)):
+        s_ref = check_case(J, [x], [1], name=f"large mask {name}")
+        ref = oracle.decode(s_ref)[0]
+        banner("decode large mask", name)
+        out = J.decode(torch.from_numpy(np.frombuffer(s_ref, np.uint8).copy()).cuda())[0]
+        assert np.array_equal(to_host(out, 1), ref), name
