@@ -113,7 +113,7 @@ struct EncResult {
 // workspace: [res][err][outs][items][tile maps] (the part uploaded from the
 // host, from `err` on) then per record its buffers.
 struct EncLayout {
-    uint32_t n = 0, no = 0, n_tiles = 0, n_ftiles = 0, max_groups = 1;
+    uint32_t n = 0, no = 0, n_tiles = 0, n_ftiles = 0, max_groups = 1, max_asm = 1;
     std::vector<uint32_t> tile_first, ftile_first;
     size_t o_res = 0, o_err = 0, o_outs = 0, o_items = 0, o_tfirst = 0, o_titem = 0, o_ftfirst = 0, o_ftitem = 0;
     size_t up_end = 0, total = 0;
@@ -136,6 +136,8 @@ EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpe
         Lo.n_ftiles += div_up(npx, kFTile);
         const uint32_t groups = div_up(div_up(npx, kFrame), kGroupFrames);
         if (groups > Lo.max_groups) Lo.max_groups = groups;
+        const uint32_t asmg = div_up(div_up(npx, kFrame), kAsmFrames);
+        if (asmg > Lo.max_asm) Lo.max_asm = asmg;
     }
     size_t off = 0;
     Lo.o_res = off; off = al(off + sizeof(EncRes) * n);
@@ -260,6 +262,7 @@ EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev) {
     plan.n_outs = Lo.no;
     plan.n_tiles = Lo.n_tiles;
     plan.max_groups = Lo.max_groups;
+    plan.max_asm = Lo.max_asm;
     return plan;
 }
 

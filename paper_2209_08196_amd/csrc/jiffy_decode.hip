@@ -47,11 +47,13 @@ constexpr uint16_t kXBad = 0xFFFEu;                // no valid block header here
 constexpr uint16_t kXLast = 0xFFFDu;               // the last block; it ends the frame exactly
 static_assert(kWin <= 0xFFF0u && kSegs == 256, "window offsets fit 16 bits; one segment per thread");
 
+__device__ __forceinline__ uint32_t sx(uint32_t i) { return i + ((i >> 5) << 1); }
+
 struct ParseLds {
     union {
-        struct {
-            uint16_t X[kWin];  // per position: the first chain position at or after its segment's end
-            uint16_t Y[kWin];  // per position: the first chain position at or after its chunk's end
+        struct {  // indexed through sx(): one pad entry pair per 32 positions keeps segments in distinct banks
+            uint16_t X[kWin + kWin / 16];  // per position: the first chain position at or after its segment's end
+            uint16_t Y[kWin + kWin / 16];  // per position: the first chain position at or after its chunk's end
         } x;
         struct {  // a block takes 3 bytes at least
             uint32_t dst[kWin / 3 + 2];  // block k: content offset of its first byte (and the end)
@@ -158,21 +160,52 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, ParseLds& P) {
         };
         __syncthreads();
         const uint32_t s0 = ws + tid * kSeg, s1 = min(s0 + kSeg, we);
-        for (uint32_t i = s1; i-- > s0;) {  // backwards over this thread's segment
-            uint32_t size, rle;
-            const uint32_t n = header(i, size, rle);
-            const uint16_t c = code(n);
-            P.u.x.X[i - ws] = (c >= kXLast || n >= s1) ? c : P.u.x.X[n - ws];
+        {
+            // this segment's 32 bytes and the two after it, aligned to the segment start
+            const uint32_t a = ws - wbase;  // 0..3: the window's first byte within fwin's first word
+            uint32_t w[10], u[9];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) w[k] = P.fwin[8 * tid + k];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) u[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], a);
+            // backwards over the segment: where a chain through each position leaves it
+#pragma unroll
+            for (int j = kSeg - 1; j >= 0; --j) {
+                const uint32_t i = s0 + j;
+                if (i < s1) {
+                    const uint32_t h = (uint32_t)(((((uint64_t)u[(j >> 2) + 1]) << 32) | u[j >> 2]) >> (8 * (j & 3))) &
+                                       0xFFFFFFu;
+                    const uint32_t last = h & 1, type = (h >> 1) & 3, size = h >> 3;
+                    uint32_t n = i + 3 + (type ? 1u : size);
+                    if (i + 3 > flen || type > 1 || size > kZstdBlockMax) n = kJInvalid;
+                    else if (last) n = n == flen ? kJLast : kJInvalid;
+                    else if (n >= flen) n = kJInvalid;
+                    const uint16_t c = code(n);
+                    const uint16_t x = (c >= kXLast || n >= s1) ? c : P.u.x.X[sx(n - ws)];
+                    P.u.x.X[sx(i - ws)] = x;
+                    P.u.x.Y[sx(i - ws)] = x;
+                }
+            }
         }
         __syncthreads();
-        for (uint32_t i = ws + tid; i < we; i += 256) P.u.x.Y[i - ws] = P.u.x.X[i - ws];
-        __syncthreads();
-        // each step spans a segment at least, so three doublings reach the chunk's end
+        // each step spans a segment at least, so three doublings reach the chunk's end;
+        // a thread reads all its 32 positions' next steps before it writes (positions
+        // updated by others in between are still on the same path)
         for (int round = 0; round < 3; ++round) {
-            for (uint32_t i = ws + tid; i < we; i += 256) {
-                const uint16_t j = P.u.x.Y[i - ws];
-                if (j < kXLast && j / kChunk == (i - ws) / kChunk) P.u.x.Y[i - ws] = P.u.x.Y[j];
+            uint32_t y[kWin / 256];
+#pragma unroll
+            for (int k = 0; k < (int)(kWin / 256); ++k) {
+                const uint32_t i = tid + 256u * k;
+                y[k] = ws + i < we ? P.u.x.Y[sx(i)] : kXBad;
             }
+#pragma unroll
+            for (int k = 0; k < (int)(kWin / 256); ++k) {
+                const uint32_t i = tid + 256u * k;
+                y[k] = (y[k] < kXLast && y[k] / kChunk == i / kChunk) ? P.u.x.Y[sx(y[k])] : 0x10000u;
+            }
+#pragma unroll
+            for (int k = 0; k < (int)(kWin / 256); ++k)
+                if (y[k] != 0x10000u) P.u.x.Y[sx(tid + 256u * k)] = (uint16_t)y[k];
             __syncthreads();
         }
         // the true chain: chunk entries (one lane), then segment entries (a lane per chunk)
@@ -183,14 +216,14 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, ParseLds& P) {
             uint32_t e = 0;
             while (e < kXLast) {
                 P.c_entry[e / kChunk] = (uint16_t)e;
-                e = P.u.x.Y[e];
+                e = P.u.x.Y[sx(e)];
             }
         }
         __syncthreads();
         if (tid < kWinChunks) {
             for (uint32_t e = P.c_entry[tid]; e < kXLast && e / kChunk == tid;) {
                 P.seg_entry[e / kSeg] = (uint16_t)e;
-                e = P.u.x.X[e];
+                e = P.u.x.X[sx(e)];
             }
         }
         __syncthreads();
@@ -234,29 +267,43 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, ParseLds& P) {
         if (tid == 0) P.u.t.dst[nblk] = content + ctot;
         __syncthreads();
         if (P.s_err) break;
+        // expansion: each thread writes a contiguous run of content words,
+        // finding its first block by binary search and walking on from there
         const uint32_t d0 = content, d1 = content + ctot;
-        for (uint32_t q = (d0 & ~3u) + 4 * tid; q < d1; q += 4 * 256) {
-            // block holding byte max(q, d0): the largest k with dst[k] <= it
-            const uint32_t first = q < d0 ? d0 : q;
-            uint32_t lo = 0, hi = nblk - 1;
+        const uint32_t q0 = d0 & ~3u, nw = (d1 - q0 + 3) / 4, per = (nw + 255) / 256;
+        const uint32_t qa = q0 + 4 * per * tid, qb = min(q0 + 4 * per * (tid + 1), d1);
+        if (qa < qb) {
+            const uint32_t first = qa < d0 ? d0 : qa;
+            uint32_t lo = 0, hi = nblk - 1;  // the largest k with dst[k] <= first
             while (lo < hi) {
                 const uint32_t mid = (lo + hi + 1) >> 1;
                 if (P.u.t.dst[mid] <= first) lo = mid; else hi = mid - 1;
             }
-            uint32_t k = lo, word = 0, full = 1;
-            for (uint32_t b = 0; b < 4; ++b) {
-                const uint32_t d = q + b;
-                if (d < d0 || d >= d1) { full = 0; continue; }
-                while (d >= P.u.t.dst[k + 1]) k++;
-                const uint32_t src = P.u.t.src[k] & 0x7FFFFFFFu;
-                const uint32_t sb = (P.u.t.src[k] >> 31) ? src : src + (d - P.u.t.dst[k]);  // frame byte
-                const uint32_t v = sb - wbase < wlen ? fb[sb - wbase] : f[sb];
-                word |= v << (8 * b);
+            // the current block: content [bstart, bend), frame source, RLE byte
+            uint32_t k = lo, bstart = P.u.t.dst[k], bend = P.u.t.dst[k + 1], bsrc = P.u.t.src[k];
+            auto byte_at = [&](uint32_t sb) -> uint32_t { return sb - wbase < wlen ? fb[sb - wbase] : f[sb]; };
+            uint32_t rv = byte_at(bsrc & 0x7FFFFFFFu);
+            for (uint32_t q = qa; q < qb; q += 4) {
+                uint32_t word = 0, full = 1;
+#pragma unroll
+                for (uint32_t b = 0; b < 4; ++b) {
+                    const uint32_t d = q + b;
+                    if (d < d0 || d >= d1) { full = 0; continue; }
+                    while (d >= bend) {  // the next block
+                        ++k;
+                        bstart = bend;
+                        bend = P.u.t.dst[k + 1];
+                        bsrc = P.u.t.src[k];
+                        rv = byte_at(bsrc & 0x7FFFFFFFu);
+                    }
+                    const uint32_t v = (bsrc >> 31) ? rv : byte_at((bsrc & 0x7FFFFFFFu) + (d - bstart));
+                    word |= v << (8 * b);
+                }
+                if (full) *(uint32_t*)(cwb + q) = word;
+                else
+                    for (uint32_t b = 0; b < 4; ++b)
+                        if (q + b >= d0 && q + b < d1) cwb[q + b] = (uint8_t)(word >> (8 * b));
             }
-            if (full) *(uint32_t*)(cwb + q) = word;
-            else
-                for (uint32_t b = 0; b < 4; ++b)
-                    if (q + b >= d0 && q + b < d1) cwb[q + b] = (uint8_t)(word >> (8 * b));
         }
         content = d1;
         ws = P.s_next;
@@ -698,58 +745,117 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan) {
 // P-scan, precedes one, or has P > 1.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kModeLds = 8192;
+constexpr uint32_t kTempPx = 4;  // pixels per thread
 
+// four samples at p0 (a multiple of 4); 0 beyond npx
 template <int WB>
-__device__ __forceinline__ void dec_temporal_body(const DecPlan& plan, uint32_t a, uint32_t p0, const uint8_t* md) {
-    uint32_t qprev[16];
+__device__ __forceinline__ void load4(const void* base, uint32_t p0, uint32_t npx, bool al, uint32_t v[4]) {
+    using T = typename SampleT<WB>::T;
+    const T* b = (const T*)base + p0;
+    if (al && p0 + 4 <= npx) {
+        if (WB == 4) {
+            const uint4 t = *(const uint4*)b;
+            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+        } else if (WB == 2) {
+            const uint2 t = *(const uint2*)b;
+            v[0] = t.x & 0xFFFFu; v[1] = t.x >> 16; v[2] = t.y & 0xFFFFu; v[3] = t.y >> 16;
+        } else {
+            const uint32_t t = *(const uint32_t*)b;
+            v[0] = t & 0xFFu; v[1] = (t >> 8) & 0xFFu; v[2] = (t >> 16) & 0xFFu; v[3] = t >> 24;
+        }
+    } else {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) qprev[i] = 0;
-    const uint32_t A = plan.n_attrs, T = plan.n_scans;
+        for (int i = 0; i < 4; ++i) v[i] = p0 + i < npx ? (uint32_t)b[i] : 0u;
+    }
+}
+template <int WB>
+__device__ __forceinline__ void store4(void* base, uint32_t p0, uint32_t npx, bool al, const uint32_t v[4]) {
+    using T = typename SampleT<WB>::T;
+    T* b = (T*)base + p0;
+    if (al && p0 + 4 <= npx) {
+        if (WB == 4) *(uint4*)b = make_uint4(v[0], v[1], v[2], v[3]);
+        else if (WB == 2) *(uint2*)b = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+        else *(uint32_t*)b = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (p0 + i < npx) b[i] = (T)v[i];
+    }
+}
+
+// The scans that must be read: P-scans, scans followed by a P-scan, and
+// every scan when P > 1; taken in order, the next one's samples loaded
+// while the current one is finished.
+template <int WB>
+__device__ __forceinline__ void dec_temporal_body(const DecPlan& plan, uint32_t a, uint32_t p0, const uint16_t* list,
+                                                  uint32_t tb, uint32_t nlist, uint32_t qprev[4]) {
+    const uint32_t A = plan.n_attrs;
     const uint32_t P = plan.attr_P[a], bits = 8 * WB, m = low_mask32(bits);
     const uint64_t stride = (uint64_t)plan.npx * WB;
     const bool al = ((uintptr_t)plan.out_base[a] % 16 == 0) && (stride % 16 == 0);
-    auto mode_of = [&](uint32_t t) -> uint32_t { return t < kModeLds ? md[t] : plan.modes[t * A + a]; };
-    for (uint32_t t = 0; t < T; ++t) {
-        const uint32_t mode = mode_of(t);
-        const bool next_p = (t + 1 < T) && mode_of(t + 1) == 1;
-        if (mode == 0 && P == 1 && !next_p) continue;
-        void* out = (uint8_t*)plan.out_base[a] + stride * t;
-        uint32_t v[16];
-        load16<WB>(out, p0, plan.npx, al, v);
-        if (mode == 1) {
-            const uint64_t vw = item_words(plan, t * A + a, plan.off_vw)[p0 >> 6];
-            const uint32_t bits16 = (uint32_t)(vw >> (16 * ((p0 >> 4) & 3))) & 0xFFFFu;
+    auto fetch = [&](uint32_t t, uint32_t v[4], uint32_t& vb) {
+        load4<WB>((const uint8_t*)plan.out_base[a] + stride * t, p0, plan.npx, al, v);
+        vb = plan.modes[t * A + a] ? (uint32_t)(item_words(plan, t * A + a, plan.off_vw)[p0 >> 6] >> (p0 & 63)) & 0xFu
+                                   : 0x10u;  // 0x10: an I-scan
+    };
+    uint32_t cur[4], nxt[4], cb = 0, nb = 0;
+    if (nlist) fetch(tb + list[0], cur, cb);
+    for (uint32_t k = 0; k < nlist; ++k) {
+        const uint32_t t = tb + list[k];
+        if (k + 1 < nlist) fetch(tb + list[k + 1], nxt, nb);
+        uint32_t v[4];
+        if (cb != 0x10u) {  // P-scan: add the previous scan at the valid pixels
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const uint32_t q = (bits16 & (1u << i)) ? ((v[i] + qprev[i]) & m) : 0u;
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t q = (cb >> i) & 1u ? ((cur[i] + qprev[i]) & m) : 0u;
                 qprev[i] = q;
                 v[i] = dequantize(q, P, bits);
             }
-            store16<WB>(out, p0, plan.npx, al, v);
+            store4<WB>((uint8_t*)plan.out_base[a] + stride * t, p0, plan.npx, al, v);
         } else {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                qprev[i] = v[i];
-                v[i] = dequantize(v[i], P, bits);
+            for (int i = 0; i < 4; ++i) {
+                qprev[i] = cur[i];
+                v[i] = dequantize(cur[i], P, bits);
             }
-            if (P > 1) store16<WB>(out, p0, plan.npx, al, v);
+            if (P > 1) store4<WB>((uint8_t*)plan.out_base[a] + stride * t, p0, plan.npx, al, v);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cur[i] = nxt[i];
+        cb = nb;
     }
 }
 
 __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
     if (*plan.err) return;
     const uint32_t a = blockIdx.y;
-    __shared__ uint8_t md[kModeLds];
-    const uint32_t A = plan.n_attrs;
-    for (uint32_t t = threadIdx.x; t < plan.n_scans && t < kModeLds; t += 256) md[t] = plan.modes[t * A + a];
-    __syncthreads();
-    const uint32_t p0 = (blockIdx.x * 256 + threadIdx.x) * 16;
-    if (p0 >= plan.npx) return;
-    switch (plan.attr_wb[a]) {
-        case 4: dec_temporal_body<4>(plan, a, p0, md); break;
-        case 2: dec_temporal_body<2>(plan, a, p0, md); break;
-        default: dec_temporal_body<1>(plan, a, p0, md); break;
+    __shared__ uint16_t list[kModeLds];
+    __shared__ uint32_t scratch[8];
+    const uint32_t A = plan.n_attrs, T = plan.n_scans;
+    const bool all = plan.attr_P[a] > 1;
+    const uint32_t p0 = (blockIdx.x * 256 + threadIdx.x) * kTempPx;
+    uint32_t qprev[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t tb = 0; tb < T; tb += kModeLds) {  // kModeLds scans at a time
+        const uint32_t te = min(T, tb + kModeLds);
+        uint32_t nlist = 0;  // the scans to read, in order
+        for (uint32_t t0 = tb; t0 < te; t0 += 256) {
+            const uint32_t t = t0 + threadIdx.x;
+            uint32_t need = 0;
+            if (t < te) need = all || plan.modes[t * A + a] || (t + 1 < T && plan.modes[(t + 1) * A + a]);
+            uint32_t tot;
+            const uint32_t o = block_excl_scan<256>(need, scratch, &tot);
+            if (need) list[nlist + o] = (uint16_t)(t - tb);
+            nlist += tot;
+        }
+        __syncthreads();
+        if (p0 < plan.npx) {
+            switch (plan.attr_wb[a]) {
+                case 4: dec_temporal_body<4>(plan, a, p0, list, tb, nlist, qprev); break;
+                case 2: dec_temporal_body<2>(plan, a, p0, list, tb, nlist, qprev); break;
+                default: dec_temporal_body<1>(plan, a, p0, list, tb, nlist, qprev); break;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -760,7 +866,7 @@ hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_dec_tiles", k_dec_tiles, dim3(plan.n_items * plan.nft), dim3(kDecThreads), stream, plan);
     if (plan.need_temporal)
-        JIFFY_LAUNCH("k_dec_temporal", k_dec_temporal, dim3(div_up(plan.npx, 256 * 16), plan.n_attrs), dim3(256),
+        JIFFY_LAUNCH("k_dec_temporal", k_dec_temporal, dim3(div_up(plan.npx, 256 * kTempPx), plan.n_attrs), dim3(256),
                      stream, plan);
     return hipGetLastError();
 }

@@ -783,63 +783,23 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
         }
         return;
     }
-    const uint32_t j0 = (blockIdx.x - 1) * kGroupFrames;
+    // 64 frames per workgroup, 16 lanes per frame: each frame's payload,
+    // positions and high parts go from its slot to their three places
+    const uint32_t j0 = (blockIdx.x - 1) * kAsmFrames;
     if (j0 >= rs.nb) return;
-    const uint32_t j1 = min(j0 + kGroupFrames, rs.nb), cnt = j1 - j0;
-    // the group's frames land in three contiguous ranges (payloads,
-    // positions, high parts); each thread copies words or bytes of them
-    __shared__ uint32_t offs[3][kGroupFrames + 1];
-    __shared__ uint32_t bwid[kGroupFrames], nexc[kGroupFrames];
-    if (tid <= cnt) {
-        const uint32_t j = j0 + tid;
-        if (j < rs.nb) {
-            offs[0][tid] = it.blkoffs[3 * j];
-            offs[1][tid] = it.blkoffs[3 * j + 1];
-            offs[2][tid] = it.blkoffs[3 * j + 2];
-        } else {
-            offs[0][tid] = rs.pay;
-            offs[1][tid] = rs.pos;
-            offs[2][tid] = rs.high;
-        }
-        if (tid < cnt) {
-            const uint32_t info = it.blkinfo[j];
-            bwid[tid] = info & 0xFF;
-            nexc[tid] = (info >> 8) & 0xFF;
-        }
-    }
-    __syncthreads();
-    auto frame_of = [&](const uint32_t* o, uint32_t x) -> uint32_t {  // last k with o[k] <= x
-        uint32_t lo = 0, hi = cnt - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (o[mid] <= x) lo = mid; else hi = mid - 1;
-        }
-        return lo;
-    };
-    {   // payload words (all ranges word aligned)
-        uint32_t* dst = (uint32_t*)(rec + pay0);
-        const uint32_t a = offs[0][0] >> 2, z = offs[0][cnt] >> 2;
-        for (uint32_t w = a + tid; w < z; w += 256) {
-            const uint32_t k = frame_of(offs[0], 4 * w);
-            const uint32_t* sw = (const uint32_t*)(it.slots + (size_t)(j0 + k) * kSlotBytes);
-            dst[w] = sw[w - (offs[0][k] >> 2)];
-        }
-    }
-    {   // exception positions
-        const uint32_t a = offs[1][0], z = offs[1][cnt];
-        for (uint32_t q = a + tid; q < z; q += 256) {
-            const uint32_t k = frame_of(offs[1], q);
-            const uint8_t* slot = it.slots + (size_t)(j0 + k) * kSlotBytes;
-            rec[pos0 + q] = slot[16 * bwid[k] + (q - offs[1][k])];
-        }
-    }
-    {   // exception high parts
-        const uint32_t a = offs[2][0], z = offs[2][cnt];
-        for (uint32_t q = a + tid; q < z; q += 256) {
-            const uint32_t k = frame_of(offs[2], q);
-            const uint8_t* slot = it.slots + (size_t)(j0 + k) * kSlotBytes;
-            rec[high0 + q] = slot[16 * bwid[k] + nexc[k] + (q - offs[2][k])];
-        }
+    const uint32_t j1 = min(j0 + kAsmFrames, rs.nb);
+    const uint32_t l = tid & 15u;
+    for (uint32_t j = j0 + (tid >> 4); j < j1; j += 16) {
+        const uint32_t info = it.blkinfo[j];
+        const uint32_t b = info & 0xFFu, n = (info >> 8) & 0xFFu;
+        const uint32_t op = it.blkoffs[3 * j], on = it.blkoffs[3 * j + 1], oh = it.blkoffs[3 * j + 2];
+        const uint32_t oh1 = j + 1 < rs.nb ? it.blkoffs[3 * (j + 1) + 2] : rs.high;
+        const uint8_t* slot = it.slots + (size_t)j * kSlotBytes;
+        const uint32_t* sw = (const uint32_t*)slot;
+        uint32_t* dw = (uint32_t*)(rec + pay0 + op);  // payloads are whole words
+        for (uint32_t w = l; w < 4 * b; w += 16) dw[w] = sw[w];
+        for (uint32_t q = l; q < n; q += 16) rec[pos0 + on + q] = slot[16 * b + q];
+        for (uint32_t q = l; q < oh1 - oh; q += 16) rec[high0 + oh + q] = slot[16 * b + n + q];
     }
 }
 
@@ -853,7 +813,7 @@ hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_offsets", k_enc_offsets, dim3(1), dim3(1024), stream, plan);
-    JIFFY_LAUNCH("k_enc_assemble", k_enc_assemble, dim3(plan.max_groups + 1, plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_assemble", k_enc_assemble, dim3(plan.max_asm + 1, plan.n_items), dim3(256), stream, plan);
     return hipGetLastError();
 }
 

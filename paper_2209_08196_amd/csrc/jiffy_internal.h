@@ -25,7 +25,8 @@ constexpr uint32_t kFTile = 8192;           // pixels per encode / decode tile
 constexpr uint32_t kNoFix = 0xFFFFFFFFu;    // a tile with no straddling frame to finish
 constexpr uint32_t kTilePx = 4096;          // pixels per mask tile (64 words of 64 px)
 constexpr uint32_t kTileWords = kTilePx / 64;
-constexpr uint32_t kGroupFrames = 16;       // frames handled by one encode/decode workgroup
+constexpr uint32_t kGroupFrames = 16;       // frames per group of the per-record size scans
+constexpr uint32_t kAsmFrames = 64;         // frames copied into the stream by one workgroup
 constexpr uint32_t kZstdBlockMax = 131072;  // largest Zstandard block (RFC 8878)
 constexpr uint32_t kRleMinRun = 8;          // runs this long become RLE blocks
 
@@ -159,6 +160,7 @@ struct EncPlan {
     const JG uint32_t* ftile_first; // device: first kFTile tile of each item
     uint32_t n_items, n_outs, n_tiles, n_ftiles;
     uint32_t max_groups;      // max over items of ceil(maxnb / kGroupFrames)
+    uint32_t max_asm;         // max over items of ceil(maxnb / kAsmFrames)
 };
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream);
 
