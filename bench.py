@@ -54,7 +54,8 @@ def stream_stats(s: bytes, widths, npx):
     p = 20 + 8 * A
     lens = struct.unpack_from(f"<{T * A}I", s, p)
     p += 4 * T * A
-    st = dict(mask_bytes=0, frame_bytes=0, n_values=0, p_items=0, p_bytes=0, i_items=0)
+    st = dict(mask_bytes=0, frame_bytes=0, n_values=0, p_items=0, p_bytes=0, i_items=0,
+              frame_bytes_w32=0, items_w32=0, x_bytes_w32=0)
     for r, L in enumerate(lens):
         a = r % A
         mode = s[p + 4]
@@ -66,7 +67,12 @@ def stream_stats(s: bytes, widths, npx):
         b = np.frombuffer(s, np.uint8, nb, p + sec + 4).astype(np.int64)
         n = np.frombuffer(s, np.uint8, nb, p + sec + 4 + nb).astype(np.int64)
         B = np.frombuffer(s, np.uint8, nb, p + sec + 4 + 2 * nb).astype(np.int64)
-        st["frame_bytes"] += int((16 * b + n + (n * (B - b) + 7) // 8).sum())
+        fb = int((16 * b + n + (n * (B - b) + 7) // 8).sum())
+        st["frame_bytes"] += fb
+        if widths[a] == 4:
+            st["frame_bytes_w32"] += fb
+            st["items_w32"] += 1
+            st["x_bytes_w32"] += 4 * npx
         st["mask_bytes"] += flen
         st["n_values"] += N
         if mode == 1:
@@ -96,7 +102,9 @@ def kernel_alg_bytes(name, st, x_bytes, n_items, nwords):
         "k_dec_mask": 2 * vb + vbp,            # mask chain over time
         "k_dec_fsum": F,                       # packed frames in
         "k_dec_group": F + vb + x_bytes,       # packed frames and valid words in, samples out
-        "k_dec_tiles": F + vb + x_bytes,
+        "k_dec_tiles_w32": st["frame_bytes_w32"] + 8 * nwords * st["items_w32"] + st["x_bytes_w32"],
+        "k_dec_tiles_w16": (F - st["frame_bytes_w32"]) + 8 * nwords * (n_items - st["items_w32"])
+                           + (x_bytes - st["x_bytes_w32"]),
         "k_dec_temporal": 3 * Xp,              # P-scans: read both scans, write one
     }
     return table.get(name)

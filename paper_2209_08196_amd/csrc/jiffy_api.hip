@@ -624,6 +624,7 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     const uint32_t nft = div_up(npx, kFTile);
     const size_t o_err = off; off = al(off + sizeof(uint32_t) * 2);  // err, err2
     const size_t o_items = off; off = al(off + sizeof(DecItem) * n);
+    const size_t o_list = off; off = al(off + sizeof(uint32_t) * n);
     const size_t up_end = off;
     const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(4ull * (nft + 1)) + al(8ull * nft) + al(sizeof(DecTile) * nft) + al(4);
     const size_t o_modes = off; off = al(off + n);
@@ -670,6 +671,13 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
             if (it.P > 1) need_temporal = true;
         }
     }
+    // records with 32-bit samples first (their tiles use 32-bit LDS rows), then the rest
+    uint32_t* hlist = (uint32_t*)(up + (o_list - o_err));
+    uint32_t n_wide = 0;
+    for (uint32_t r = 0; r < n; ++r)
+        if (hit[r].wb == 4) hlist[n_wide++] = r;
+    for (uint32_t r = 0, k = n_wide; r < n; ++r)
+        if (hit[r].wb != 4) hlist[k++] = r;
     if (hipMemcpyAsync(dev + o_err, up, up_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return JIFFY_E_DEVICE;
     DecPlan plan;
     plan.items = (const DecItem*)(dev + o_items);
@@ -677,6 +685,8 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     plan.err = (uint32_t*)(dev + o_err);
     plan.err2 = plan.err + 1;
     plan.nft = nft;
+    plan.rec_list = (const uint32_t*)(dev + o_list);
+    plan.n_wide = n_wide;
     plan.n_items = n;
     plan.n_scans = T;
     plan.n_attrs = A;

@@ -520,8 +520,54 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
 constexpr uint64_t kStAgg = 1ull << 32, kStIncl = 2ull << 32;  // look-back status flags
 constexpr uint32_t kSpinMax = 1u << 16;                // look-back polls before giving up
 
+// Frame rows of 32-bit values (32-bit samples) or 16-bit values (8- and
+// 16-bit samples, whose residuals and running sums fit 16 bits): each lane's
+// 32 values start 16-byte aligned.
+template <class R> struct RowT;
+template <> struct RowT<uint32_t> { static constexpr uint32_t kElems = kRow, kLane = 36, kPad = 4; };
+template <> struct RowT<uint16_t> { static constexpr uint32_t kElems = 160, kLane = 40, kPad = 8; };
+template <class R> __device__ __forceinline__ uint32_t roff(uint32_t i) { return i + RowT<R>::kPad * (i >> 5); }
+template <class R> __device__ __forceinline__ uint32_t tword(uint32_t k, uint32_t jf) {
+    return ((k >> 7) - jf) * RowT<R>::kElems + roff<R>(k & 127u);
+}
+// lane q's 32 values of a row, in and out
+template <class R> __device__ __forceinline__ void row_put(R* row, uint32_t q, const uint32_t v[32]) {
+    uint4* r4 = (uint4*)(row + RowT<R>::kLane * q);
+    if (sizeof(R) == 4) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) r4[c] = make_uint4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            r4[c] = make_uint4((v[8 * c] & 0xFFFFu) | (v[8 * c + 1] << 16), (v[8 * c + 2] & 0xFFFFu) | (v[8 * c + 3] << 16),
+                               (v[8 * c + 4] & 0xFFFFu) | (v[8 * c + 5] << 16), (v[8 * c + 6] & 0xFFFFu) | (v[8 * c + 7] << 16));
+    }
+}
+template <class R> __device__ __forceinline__ void row_get(const R* row, uint32_t q, uint32_t v[32]) {
+    const uint4* r4 = (const uint4*)(row + RowT<R>::kLane * q);
+    if (sizeof(R) == 4) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint4 t = r4[c];
+            v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint4 t = r4[c];
+            const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                v[8 * c + 2 * h] = w[h] & 0xFFFFu;
+                v[8 * c + 2 * h + 1] = w[h] >> 16;
+            }
+        }
+    }
+}
+
+template <class R>
 struct DecTileLds {
-    uint32_t rows[kTileFrames * kRow];
+    R rows[kTileFrames * RowT<R>::kElems];
     uint32_t stage[kStageWords + 2];
     uint32_t info[kTileFrames];
     uint32_t offs[kTileFrames + 1][3];  // frame offsets in the three sections
@@ -580,25 +626,21 @@ __device__ uint32_t dec_lookback(JG uint64_t* st, uint32_t lt, uint32_t agg, JG 
 // or the record), pay_w is the frame's first payload word, pos_b its first
 // exception-position byte, high_bit its first high-part bit.  d gets the
 // lane's running sum of the deltas of the tile's values.
-template <bool kStaged, class W = typename std::conditional<kStaged, const uint32_t, const JG uint32_t>::type>
-__device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, DecTileLds& L, W* words, uint32_t g,
+template <bool kStaged, class R, class W = typename std::conditional<kStaged, const uint32_t, const JG uint32_t>::type>
+__device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, DecTileLds<R>& L, W* words, uint32_t g,
                                            uint32_t q, uint32_t kb, uint32_t ke, uint32_t jf, uint32_t pay_w,
                                            uint32_t pos_b, uint32_t high_bit, uint32_t d[32], uint32_t& lane_sum) {
     const uint32_t j = jf + g;
     const uint32_t info = L.info[g];
     const uint32_t b = info & 0xFFu, n = (info >> 8) & 0xFFu, B = (info >> 16) & 0xFFu;
     const uint32_t hw = B - b, real = min(kFrame, rs.N - j * kFrame);
-    uint32_t* row = L.rows + g * kRow;
+    R* row = L.rows + g * RowT<R>::kElems;
     W* pay = words + pay_w;
     const uint32_t i0 = 32u * q;
     uint32_t z[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) z[i] = b ? bits_at<!kStaged>(pay, (i0 + i) * b, b) : 0u;
-    {
-        uint4* r4 = (uint4*)(row + 36 * q);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) r4[c] = make_uint4(z[4 * c], z[4 * c + 1], z[4 * c + 2], z[4 * c + 3]);
-    }
+    row_put<R>(row, q, z);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     if (n) {
         using B8 = typename std::conditional<kStaged, const uint8_t, const JG uint8_t>::type;
@@ -607,19 +649,12 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
         for (uint32_t e = q; e < n; e += 4) {
             const uint32_t p = pos[e];
             if (p >= real || (e && pos[e - 1] >= p)) { bad = 1; continue; }
-            row[row_off(p)] |= bits_at<!kStaged>(words, high_bit + e * hw, hw) << b;
+            row[roff<R>(p)] |= bits_at<!kStaged>(words, high_bit + e * hw, hw) << b;
         }
         if (bad) atomicOr(&L.bad, 1u);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    {
-        const uint4* r4 = (const uint4*)(row + 36 * q);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const uint4 v = r4[c];
-            z[4 * c] = v.x; z[4 * c + 1] = v.y; z[4 * c + 2] = v.z; z[4 * c + 3] = v.w;
-        }
-    }
+    row_get<R>(row, q, z);
     // deltas of the tile's own values, inclusive running sum over the lane
     const uint32_t k0 = j * kFrame + i0;
 #pragma unroll
@@ -630,27 +665,29 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
     }
 }
 
-template <int WB>
+template <int WB, class R>
 __device__ __forceinline__ void dec_tile_scatter(const DecItem& it, uint32_t p0, uint32_t bits, uint32_t k,
-                                                 uint32_t jf, const DecTileLds& L) {
+                                                 uint32_t jf, const DecTileLds<R>& L) {
     uint32_t v[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
         const bool on = (bits >> i) & 1u;
-        v[i] = on ? L.rows[tile_word(k, jf)] : 0u;
+        v[i] = on ? (uint32_t)L.rows[tword<R>(k, jf)] : 0u;
         k += on ? 1u : 0u;
     }
     store16<WB>(it.out, p0, it.npx, it.aligned16, v);
     if (p0 + 16 < it.npx) store16<WB>(it.out, p0 + 16, it.npx, it.aligned16, v + 16);
 }
 
-__global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan) {
+// R: the row element; the workgroups take the records rec_list[first ..]
+template <class R>
+__global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_t first) {
     if (*plan.err) return;  // set before this launch; this kernel reports through err2
-    __shared__ DecTileLds L;
+    __shared__ DecTileLds<R> L;
     const uint32_t tid = threadIdx.x;
     // the record is fixed by the workgroup index; the tile within it is taken
     // in arrival order, so every tile a workgroup waits for has started
-    const uint32_t r = blockIdx.x / plan.nft;
+    const uint32_t r = plan.rec_list[first + blockIdx.x / plan.nft];
     const DecItem it = plan.items[r];
     if (tid == 0) {
         L.ticket = atomicAdd(it.tctr, 1u);
@@ -700,13 +737,13 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan) {
     for (int i = 0; i < 32; ++i) d[i] = 0;
     if (g < nf) {
         if (staged)
-            dec_unpack<true>(it, rs, L, L.stage, g, q, kb, ke, jf,
+            dec_unpack<true, R>(it, rs, L, L.stage, g, q, kb, ke, jf,
                                        ((rs.pay_off + L.offs[g][0]) >> 2) - D.w0[0],
                                        4 * D.nw[0] + rs.pos_off + L.offs[g][1] - 4 * D.w0[1],
                                        8 * (4 * (D.nw[0] + D.nw[1]) + rs.high_off + L.offs[g][2] - 4 * D.w0[2]), d,
                                        lane_sum);
         else
-            dec_unpack<false>(it, rs, L, (const JG uint32_t*)it.rec, g, q, kb, ke, jf,
+            dec_unpack<false, R>(it, rs, L, (const JG uint32_t*)it.rec, g, q, kb, ke, jf,
                                           (rs.pay_off + L.offs[g][0]) >> 2, rs.pos_off + L.offs[g][1],
                                           8 * (rs.high_off + L.offs[g][2]), d, lane_sum);
     }
@@ -721,21 +758,17 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan) {
     if (tid == 0 && L.bad) atomicOr(plan.err2, kErrCorrupt);
     if (g < nf) {
         const uint32_t v0 = L.base + excl;
-        uint4* r4 = (uint4*)(L.rows + g * kRow + 36 * q);
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            r4[c] = make_uint4((v0 + d[4 * c]) & m, (v0 + d[4 * c + 1]) & m, (v0 + d[4 * c + 2]) & m,
-                               (v0 + d[4 * c + 3]) & m);
+        for (int i = 0; i < 32; ++i) d[i] = (v0 + d[i]) & m;
+        row_put<R>(L.rows + g * RowT<R>::kElems, q, d);
     }
     // 4. the tile's pixels: the k-th valid pixel gets value k
     uint32_t total;
     const uint32_t k = kb + block_excl_scan<kDecThreads>(__popc(pbits), L.scratch, &total);  // also a barrier
     if (!scat) return;
-    switch (it.wb) {
-        case 4: dec_tile_scatter<4>(it, p0, pbits, k, jf, L); break;
-        case 2: dec_tile_scatter<2>(it, p0, pbits, k, jf, L); break;
-        default: dec_tile_scatter<1>(it, p0, pbits, k, jf, L); break;
-    }
+    if (sizeof(R) == 4) dec_tile_scatter<4, R>(it, p0, pbits, k, jf, L);
+    else if (it.wb == 2) dec_tile_scatter<2, R>(it, p0, pbits, k, jf, L);
+    else dec_tile_scatter<1, R>(it, p0, pbits, k, jf, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -864,7 +897,12 @@ hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items, 2), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(plan.nwords, 64), plan.n_attrs), dim3(64), stream, plan);
     JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
-    JIFFY_LAUNCH("k_dec_tiles", k_dec_tiles, dim3(plan.n_items * plan.nft), dim3(kDecThreads), stream, plan);
+    if (plan.n_wide)
+        JIFFY_LAUNCH("k_dec_tiles_w32", k_dec_tiles<uint32_t>, dim3(plan.n_wide * plan.nft), dim3(kDecThreads),
+                     stream, plan, 0u);
+    if (plan.n_items > plan.n_wide)
+        JIFFY_LAUNCH("k_dec_tiles_w16", k_dec_tiles<uint16_t>, dim3((plan.n_items - plan.n_wide) * plan.nft),
+                     dim3(kDecThreads), stream, plan, plan.n_wide);
     if (plan.need_temporal)
         JIFFY_LAUNCH("k_dec_temporal", k_dec_temporal, dim3(div_up(plan.npx, 256 * kTempPx), plan.n_attrs), dim3(256),
                      stream, plan);

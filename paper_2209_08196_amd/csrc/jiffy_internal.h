@@ -177,6 +177,8 @@ struct DecPlan {
     uint32_t nwords, npx, max_groups;
     uint32_t n_tiles;
     uint32_t nft;             // kFTile tiles per record
+    const JG uint32_t* rec_list; // the records with 32-bit samples, then the others
+    uint32_t n_wide;          // how many have 32-bit samples
     uint32_t need_temporal;   // per-pixel pass over time needed
     JG void* out_base[8];        // attribute planes
     uint32_t attr_wb[8], attr_P[8];

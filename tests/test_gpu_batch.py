@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from formatcheck import split_stream
-from gpu_util import banner, to_dev
+from gpu_util import banner, to_dev, to_host
 from paper_2209_08196_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -131,3 +131,30 @@ def test_graph_batch_with_inputs_named_per_run(J):
     batch.close()
     for s in streams:
         s.close()
+
+
+def test_open_ended_stream_of_step_records_decodes(J):
+    """Records from batched steps, behind a header with no length table
+    (T = 0: records until the end), decode on the GPU to the oracle's
+    output for the same scans."""
+    import torch
+    g = synth.stream(3, 1, size=(32, 2048))
+    T = 5
+    x = g.scans(0, T)
+    s = J.Stream(g.H, g.W, g.widths, g.precisions)
+    out = torch.empty(s.record_bound(), dtype=torch.uint8, device="cuda")
+    recs = []
+    for t in range(T):
+        lens, _ = J.batch_encode_step([s], [[to_dev(p[t]) for p in x]], [out])
+        recs.append(out[: lens[0]].cpu().numpy().tobytes())
+    s.close()
+    full, _ = oracle.encode(x, g.precisions)
+    A = len(g.widths)
+    head = bytearray(full[:20 + 8 * A])
+    head[16:20] = (0).to_bytes(4, "little")
+    open_s = bytes(head) + b"".join(recs)
+    banner("decode open-ended stream", len(open_s))
+    outs = J.decode(torch.from_numpy(np.frombuffer(open_s, np.uint8).copy()).cuda())
+    ref = oracle.decode(full)
+    for o, r in zip(outs, ref):
+        assert np.array_equal(to_host(o, r.dtype.itemsize), r)
