@@ -55,7 +55,7 @@ def stream_stats(s: bytes, widths, npx):
     lens = struct.unpack_from(f"<{T * A}I", s, p)
     p += 4 * T * A
     st = dict(mask_bytes=0, frame_bytes=0, n_values=0, p_items=0, p_bytes=0, i_items=0,
-              frame_bytes_w32=0, items_w32=0, x_bytes_w32=0)
+              frame_bytes_w32=0, items_w32=0, x_bytes_w32=0, p_bytes_w32=0)
     for r, L in enumerate(lens):
         a = r % A
         mode = s[p + 4]
@@ -78,6 +78,8 @@ def stream_stats(s: bytes, widths, npx):
         if mode == 1:
             st["p_items"] += 1
             st["p_bytes"] += widths[a] * npx
+            if widths[a] == 4:
+                st["p_bytes_w32"] += 4 * npx
         else:
             st["i_items"] += 1
         p += L

@@ -223,6 +223,51 @@ constexpr uint32_t kTileQuads = kFTile / kFrame;       // frames a tile can hold
 // value kb.. of a tile: frame (k >> 7) - jf of the tile's rows
 __device__ __forceinline__ uint32_t tile_word(uint32_t k, uint32_t jf) { return ((k >> 7) - jf) * kRow + row_off(k & 127u); }
 
+// Frame rows of 32-bit values (32-bit samples) or 16-bit values (8- and
+// 16-bit samples, whose residuals and running sums fit 16 bits): each lane's
+// 32 values start 16-byte aligned.
+template <class R> struct RowT;
+template <> struct RowT<uint32_t> { static constexpr uint32_t kElems = kRow, kLane = 36, kPad = 4; };
+template <> struct RowT<uint16_t> { static constexpr uint32_t kElems = 160, kLane = 40, kPad = 8; };
+template <class R> __device__ __forceinline__ uint32_t roff(uint32_t i) { return i + RowT<R>::kPad * (i >> 5); }
+template <class R> __device__ __forceinline__ uint32_t tword(uint32_t k, uint32_t jf) {
+    return ((k >> 7) - jf) * RowT<R>::kElems + roff<R>(k & 127u);
+}
+// lane q's 32 values of a row, in and out
+template <class R> __device__ __forceinline__ void row_put(R* row, uint32_t q, const uint32_t v[32]) {
+    uint4* r4 = (uint4*)(row + RowT<R>::kLane * q);
+    if (sizeof(R) == 4) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) r4[c] = make_uint4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            r4[c] = make_uint4((v[8 * c] & 0xFFFFu) | (v[8 * c + 1] << 16), (v[8 * c + 2] & 0xFFFFu) | (v[8 * c + 3] << 16),
+                               (v[8 * c + 4] & 0xFFFFu) | (v[8 * c + 5] << 16), (v[8 * c + 6] & 0xFFFFu) | (v[8 * c + 7] << 16));
+    }
+}
+template <class R> __device__ __forceinline__ void row_get(const R* row, uint32_t q, uint32_t v[32]) {
+    const uint4* r4 = (const uint4*)(row + RowT<R>::kLane * q);
+    if (sizeof(R) == 4) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint4 t = r4[c];
+            v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint4 t = r4[c];
+            const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                v[8 * c + 2 * h] = w[h] & 0xFFFFu;
+                v[8 * c + 2 * h + 1] = w[h] >> 16;
+            }
+        }
+    }
+}
+
 // ---- 16-sample vector access -------------------------------------------
 template <int WB> struct SampleT;
 template <> struct SampleT<1> { using T = uint8_t; };
