@@ -350,21 +350,19 @@ def main():
           file=sys.stderr, flush=True)
 
     # timed steps
-    ev_e0, ev_e1, ev_d1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    enc_ms = dec_ms = 0.0
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for ev_e0, ev_e1, ev_d1 in evs:
         ev_e0.record(stream)
         s, _ = jiffy.encode(dev, precs, out=out)
         ev_e1.record(stream)
         jiffy.decode(s, lay, T, outs=dec)
         ev_d1.record(stream)
-        ev_d1.synchronize()
-        enc_ms += ev_e0.elapsed_time(ev_e1)
-        dec_ms += ev_e1.elapsed_time(ev_d1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    enc_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in evs)
+    dec_ms = sum(e1.elapsed_time(d1) for _, e1, d1 in evs)
     ms_per_step = 1e3 * wall / args.steps
     value = points / (wall / args.steps)
     print(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)

@@ -99,6 +99,18 @@ int jiffy_peek(const void* h_in, size_t in_len, jiffy_layout* layout, uint32_t* 
  * jiffy_status. */
 int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hipStream_t stream);
 
+/* Decodes a stream whose layout and scan count the caller already knows
+ * (the sensor's configuration), as jiffy_decode, but without reading
+ * anything back to the host before the kernels run: the header is compared
+ * on the device with the one jiffy_encode writes for (layout, n_scans), and
+ * the record offsets come from its length table on the device.  Only a
+ * stream with a length table (n_scans >= 1, as jiffy_encode writes it) is
+ * accepted; a header without one, or any other header, table or length
+ * mismatch returns JIFFY_E_CORRUPT (outputs then undefined).  Arguments as
+ * jiffy_decode; d_planes_out hold n_scans scans. */
+int jiffy_decode_layout(const jiffy_layout* layout, uint32_t n_scans, const void* d_in, size_t in_len,
+                        void* const* d_planes_out, hipStream_t stream);
+
 /* A short English description of a status code (static storage). */
 const char* jiffy_status_string(int status);
 

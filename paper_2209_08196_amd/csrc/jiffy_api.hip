@@ -23,8 +23,12 @@ struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
 };
+// Pinned host memory; d is its device address (kernels read the plan
+// uploads and write the encode results through it, with system-scope
+// accesses).
 struct HostBuf {
     void* p = nullptr;
+    void* d = nullptr;
     size_t cap = 0;
 };
 
@@ -41,16 +45,27 @@ hipError_t grow(DevBuf& b, size_t need) {
     if (e == hipSuccess) b.cap = cap;
     return e;
 }
+hipError_t host_alloc(void** p, void** d, size_t bytes) {
+    *p = *d = nullptr;
+    hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    e = hipHostGetDevicePointer(d, *p, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(*p);
+        *p = *d = nullptr;
+    }
+    return e;
+}
 hipError_t grow(HostBuf& b, size_t need) {
     if (need <= b.cap) return hipSuccess;
     size_t cap = need + need / 4;
     if (b.p) {
         hipError_t e = hipHostFree(b.p);
         if (e != hipSuccess) return e;
-        b.p = nullptr;
+        b.p = b.d = nullptr;
         b.cap = 0;
     }
-    hipError_t e = hipHostMalloc(&b.p, cap, hipHostMallocDefault);
+    hipError_t e = host_alloc(&b.p, &b.d, cap);
     if (e == hipSuccess) b.cap = cap;
     return e;
 }
@@ -60,7 +75,7 @@ hipError_t grow(HostBuf& b, size_t need) {
 struct DevCtx {
     std::mutex mu;
     DevBuf ws;
-    HostBuf up, down;
+    HostBuf up, down, res;
 };
 DevCtx g_ctx[64];
 
@@ -81,6 +96,24 @@ bool layout_ok(const jiffy_layout* L) {
 }
 
 uint32_t header_len(uint32_t A, uint32_t T) { return 20 + 8 * A + 4 * T * A; }
+
+// The stream header without its length table (20 + 8 A bytes): magic,
+// version 1, attribute count, height, width, scan count (0: records follow
+// one another with no table), then per attribute its sample width and P.
+void write_header(uint8_t* h, const jiffy_layout* L, uint32_t T) {
+    const uint32_t A = L->n_attrs;
+    memset(h, 0, 20 + 8 * A);
+    memcpy(h, "JFY1", 4);
+    h[4] = 1;
+    h[6] = (uint8_t)A;
+    memcpy(h + 8, &L->height, 4);
+    memcpy(h + 12, &L->width, 4);
+    memcpy(h + 16, &T, 4);
+    for (uint32_t a = 0; a < A; ++a) {
+        h[20 + 8 * a] = L->width_bytes[a];
+        memcpy(h + 24 + 8 * a, &L->precision[a], 4);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // encode planning
@@ -114,11 +147,13 @@ struct EncResult {
 // host, from `err` on) then per record its buffers.
 struct EncLayout {
     uint32_t n = 0, no = 0, n_tiles = 0, n_ftiles = 0, max_groups = 1, max_asm = 1;
+    uint32_t tpi = 0, ftpi = 0;  // tiles per record when all records have the same size (no tile maps)
     std::vector<uint32_t> tile_first, ftile_first;
     size_t o_res = 0, o_err = 0, o_outs = 0, o_items = 0, o_tfirst = 0, o_titem = 0, o_ftfirst = 0, o_ftitem = 0;
     size_t up_end = 0, total = 0;
     std::vector<size_t> o_vw, o_blk, o_slots, o_frame, o_segs;
     size_t up_bytes() const { return up_end - o_err; }
+    size_t res_bytes() const { return 16ull * no + 4ull * n; }  // host results: per output len/ok, per record mode
 };
 
 EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs) {
@@ -139,15 +174,23 @@ EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpe
         const uint32_t asmg = div_up(div_up(npx, kFrame), kAsmFrames);
         if (asmg > Lo.max_asm) Lo.max_asm = asmg;
     }
+    bool uniform = true;
+    for (uint32_t r = 1; r < n; ++r)
+        if (specs[r].H * specs[r].W != specs[0].H * specs[0].W) uniform = false;
+    if (n && uniform) {
+        Lo.tpi = div_up(specs[0].H * specs[0].W, kTilePx);
+        Lo.ftpi = div_up(specs[0].H * specs[0].W, kFTile);
+    }
+    const uint32_t n_maps = Lo.tpi ? 0u : n, n_tmap = Lo.tpi ? 0u : Lo.n_tiles, n_ftmap = Lo.tpi ? 0u : Lo.n_ftiles;
     size_t off = 0;
     Lo.o_res = off; off = al(off + sizeof(EncRes) * n);
     Lo.o_err = off; off = al(off + sizeof(uint32_t));
     Lo.o_outs = off; off = al(off + sizeof(EncOut) * no);
     Lo.o_items = off; off = al(off + sizeof(EncItem) * n);
-    Lo.o_tfirst = off; off = al(off + sizeof(uint32_t) * n);
-    Lo.o_titem = off; off = al(off + sizeof(uint32_t) * Lo.n_tiles);
-    Lo.o_ftfirst = off; off = al(off + sizeof(uint32_t) * n);
-    Lo.o_ftitem = off; off = al(off + sizeof(uint32_t) * Lo.n_ftiles);
+    Lo.o_tfirst = off; off = al(off + sizeof(uint32_t) * n_maps);
+    Lo.o_titem = off; off = al(off + sizeof(uint32_t) * n_tmap);
+    Lo.o_ftfirst = off; off = al(off + sizeof(uint32_t) * n_maps);
+    Lo.o_ftitem = off; off = al(off + sizeof(uint32_t) * n_ftmap);
     Lo.up_end = off;
     Lo.o_vw.resize(n); Lo.o_blk.resize(n); Lo.o_slots.resize(n); Lo.o_frame.resize(n); Lo.o_segs.resize(n);
     for (uint32_t r = 0; r < n; ++r) {
@@ -234,6 +277,7 @@ void enc_fill(const EncLayout& Lo, const std::vector<EncSpec>& specs, const std:
                     (!s.qout || (uintptr_t)s.qout % 16 == 0);
         it.aligned16 = al16 ? 1u : 0u;
     }
+    if (Lo.tpi) return;  // tiles are found by division
     uint32_t* htf = (uint32_t*)U(Lo.o_tfirst);
     uint32_t* hti = (uint32_t*)U(Lo.o_titem);
     uint32_t* hftf = (uint32_t*)U(Lo.o_ftfirst);
@@ -247,8 +291,11 @@ void enc_fill(const EncLayout& Lo, const std::vector<EncSpec>& specs, const std:
     }
 }
 
-EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev) {
+EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev, uint8_t* host_res) {
     EncPlan plan;
+    plan.host_res = host_res;
+    plan.tpi = Lo.tpi;
+    plan.ftpi = Lo.ftpi;
     plan.items = (const EncItem*)(dev + Lo.o_items);
     plan.res = (EncRes*)(dev + Lo.o_res);
     plan.outs = (EncOut*)(dev + Lo.o_outs);
@@ -266,18 +313,17 @@ EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev) {
     return plan;
 }
 
-// upload, the kernels, download of [res][err][outs]: everything one step
-// enqueues (also what a batch captures in its graph)
-hipError_t enc_enqueue(const EncLayout& Lo, const EncPlan& plan, uint8_t* dev, const uint8_t* up, uint8_t* down,
-                       hipStream_t stream) {
-    hipError_t e = hipMemcpyAsync(dev + Lo.o_err, up, Lo.up_bytes(), hipMemcpyHostToDevice, stream);
+// Everything one call enqueues: the upload of the plan image by a kernel
+// reading `up_dev` (the device address of the host image), then the
+// kernels; k_enc_offsets writes the lengths and modes to the host results.
+hipError_t enc_enqueue(const EncLayout& Lo, const EncPlan& plan, uint8_t* dev, const void* up_dev, hipStream_t stream) {
+    hipError_t e = launch_copy_in(up_dev, dev + Lo.o_err, Lo.up_bytes(), stream);
     if (e != hipSuccess) return e;
-    e = launch_encode(plan, stream);
-    if (e != hipSuccess) return e;
-    return hipMemcpyAsync(down, dev, Lo.o_items, hipMemcpyDeviceToHost, stream);
+    return launch_encode(plan, stream);
 }
 
-void enc_results(const EncLayout& Lo, const uint8_t* down, EncResult& result) {
+// Results from a host copy of the workspace's [res][err][outs].
+void enc_results_image(const EncLayout& Lo, const uint8_t* down, EncResult& result) {
     const EncRes* dres = (const EncRes*)(down + Lo.o_res);
     const EncOut* douts = (const EncOut*)(down + Lo.o_outs);
     result.lens.resize(Lo.no);
@@ -290,20 +336,36 @@ void enc_results(const EncLayout& Lo, const uint8_t* down, EncResult& result) {
     for (uint32_t r = 0; r < Lo.n; ++r) result.modes[r] = (uint8_t)dres[r].mode;
 }
 
+// Results k_enc_offsets wrote to host memory.
+void enc_results(const EncLayout& Lo, const uint8_t* hres, EncResult& result) {
+    result.lens.resize(Lo.no);
+    result.ok.resize(Lo.no);
+    result.modes.resize(Lo.n);
+    for (uint32_t k = 0; k < Lo.no; ++k) {
+        uint64_t len;
+        uint32_t ok;
+        memcpy(&len, hres + 16 * k, 8);
+        memcpy(&ok, hres + 16 * k + 8, 4);
+        result.lens[k] = len;
+        result.ok[k] = (uint8_t)ok;
+    }
+    const uint32_t* m = (const uint32_t*)(hres + 16ull * Lo.no);
+    for (uint32_t r = 0; r < Lo.n; ++r) result.modes[r] = (uint8_t)m[r];
+}
+
 int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs, hipStream_t stream,
                EncResult& result) {
     const EncLayout Lo = enc_layout(specs, outs);
     if (grow(ctx.ws, Lo.total) != hipSuccess) return JIFFY_E_DEVICE;
     if (grow(ctx.up, Lo.up_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
-    if (grow(ctx.down, Lo.o_items) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(ctx.res, Lo.res_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
     uint8_t* dev = (uint8_t*)ctx.ws.p;
     enc_fill(Lo, specs, outs, dev, (uint8_t*)ctx.up.p);
-    const EncPlan plan = enc_plan(Lo, dev);
-    if (enc_enqueue(Lo, plan, dev, (const uint8_t*)ctx.up.p, (uint8_t*)ctx.down.p, stream) != hipSuccess)
-        return JIFFY_E_DEVICE;
+    const EncPlan plan = enc_plan(Lo, dev, (uint8_t*)ctx.res.d);
+    if (enc_enqueue(Lo, plan, dev, ctx.up.d, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     prof_collect();
-    enc_results(Lo, (const uint8_t*)ctx.down.p, result);
+    enc_results(Lo, (const uint8_t*)ctx.res.p, result);
     return JIFFY_OK;
 }
 
@@ -478,16 +540,7 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
         if (cap < hl) return JIFFY_E_CAPACITY;
         if (grow(ctx.up, hl) != hipSuccess) return JIFFY_E_DEVICE;
         uint8_t* h = (uint8_t*)ctx.up.p;
-        memset(h, 0, hl);
-        memcpy(h, "JFY1", 4);
-        h[4] = 1;
-        h[6] = (uint8_t)A;
-        memcpy(h + 8, &L->height, 4);
-        memcpy(h + 12, &L->width, 4);
-        for (uint32_t a = 0; a < A; ++a) {
-            h[20 + 8 * a] = L->width_bytes[a];
-            memcpy(h + 24 + 8 * a, &L->precision[a], 4);
-        }
+        write_header(h, L, 0);
         if (hipMemcpyAsync(d_out, h, hl, hipMemcpyHostToDevice, stream) != hipSuccess) return JIFFY_E_DEVICE;
         if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
         return JIFFY_OK;
@@ -555,63 +608,17 @@ int jiffy_peek(const void* h_in, size_t len, jiffy_layout* L, uint32_t* n_scans)
     return JIFFY_OK;
 }
 
-int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hipStream_t stream) {
-    if (!d_in || (uintptr_t)d_in % 4) return JIFFY_E_INVALID;
-    if (in_len < 20) return JIFFY_E_CORRUPT;
-    int devid;
-    if (current_device(&devid)) return JIFFY_E_DEVICE;
-    DevCtx& ctx = g_ctx[devid];
-    std::lock_guard<std::mutex> lock(ctx.mu);
-    const uint8_t* din = (const uint8_t*)d_in;
-    // header
-    const size_t h0 = in_len < 20 + 8 * JIFFY_MAX_ATTRS ? in_len : 20 + 8 * JIFFY_MAX_ATTRS;
-    if (grow(ctx.down, 4096) != hipSuccess) return JIFFY_E_DEVICE;
-    uint8_t* hb = (uint8_t*)ctx.down.p;
-    if (hipMemcpyAsync(hb, din, h0, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
-    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
-    jiffy_layout L;
-    uint32_t T_hdr;
-    size_t p;
-    int rc = parse_header(hb, h0, &L, &T_hdr, &p);
-    if (rc) return rc;
+}  // extern "C"
+
+namespace {
+// Decodes T scans of layout L from the stream at din (in_len bytes).  Record
+// offsets come from the host (roff / rlen) or, with roff null, from the
+// length table after `p` header bytes, indexed on the device (hdr: the
+// expected header bytes to check there, or null when the host has read it).
+int run_decode(DevCtx& ctx, const jiffy_layout& L, uint32_t T, const uint8_t* din, size_t in_len,
+               const uint64_t* roff, const uint32_t* rlen, size_t p, const uint8_t* hdr,
+               void* const* d_planes_out, hipStream_t stream) {
     const uint32_t A = L.n_attrs;
-    // record offsets: from the length table, or by walking the records
-    std::vector<uint64_t> roff;
-    std::vector<uint32_t> rlen;
-    if (T_hdr) {
-        const size_t nrec = (size_t)T_hdr * A;
-        if ((uint64_t)T_hdr * A > (1u << 24) || in_len < p + 4 * nrec) return JIFFY_E_CORRUPT;
-        if (grow(ctx.down, 4 * nrec + 64) != hipSuccess) return JIFFY_E_DEVICE;
-        uint8_t* tb = (uint8_t*)ctx.down.p;
-        if (hipMemcpyAsync(tb, din + p, 4 * nrec, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
-        if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
-        uint64_t q = p + 4 * nrec;
-        roff.resize(nrec);
-        rlen.resize(nrec);
-        for (size_t r = 0; r < nrec; ++r) {
-            const uint32_t rl = rd32(tb + 4 * r);
-            if (rl < 12 || rl % 4) return JIFFY_E_CORRUPT;
-            roff[r] = q;
-            rlen[r] = rl;
-            q += rl;
-        }
-        if (q != in_len) return JIFFY_E_CORRUPT;
-    } else {
-        uint64_t q = p;
-        uint8_t* tb = (uint8_t*)ctx.down.p;
-        while (q < in_len) {
-            if (q + 4 > in_len) return JIFFY_E_CORRUPT;
-            if (hipMemcpyAsync(tb, din + q, 4, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
-            if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
-            const uint32_t rl = rd32(tb);
-            if (rl < 12 || rl % 4 || rl > in_len - q) return JIFFY_E_CORRUPT;
-            roff.push_back(q);
-            rlen.push_back(rl);
-            q += rl;
-        }
-        if (roff.size() % A) return JIFFY_E_CORRUPT;
-    }
-    const uint32_t T = (uint32_t)(roff.size() / A);
     if (T == 0) return JIFFY_OK;
     if (!d_planes_out) return JIFFY_E_INVALID;
     for (uint32_t a = 0; a < A; ++a)
@@ -619,9 +626,10 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
 
     const uint32_t n = T * A;
     const uint32_t npx = L.height * L.width, nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame);
+    const uint32_t nft = div_up(npx, kFTile);
     size_t off = 0;
     const size_t o_res = off; off = al(off + sizeof(DecRes) * n);
-    const uint32_t nft = div_up(npx, kFTile);
+    const size_t o_roff = off; off = al(off + (roff ? 0 : sizeof(uint64_t) * n));
     const size_t o_err = off; off = al(off + sizeof(uint32_t) * 2);  // err, err2
     const size_t o_items = off; off = al(off + sizeof(DecItem) * n);
     const size_t o_list = off; off = al(off + sizeof(uint32_t) * n);
@@ -633,6 +641,7 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     if (grow(ctx.ws, off) != hipSuccess) return JIFFY_E_DEVICE;
     const size_t up_bytes = up_end - o_err;
     if (grow(ctx.up, up_bytes) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
     uint8_t* dev = (uint8_t*)ctx.ws.p;
     uint8_t* up = (uint8_t*)ctx.up.p;
     memset(up, 0, up_bytes);
@@ -643,8 +652,8 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
             const uint32_t r = t * A + a;
             DecItem& it = hit[r];
             uint8_t* base = dev + o_data + per_item * r;
-            it.rec = din + roff[r];
-            it.rec_len = rlen[r];
+            it.rec = roff ? din + roff[r] : nullptr;
+            it.rec_len = roff ? rlen[r] : 0;
             const size_t step = (size_t)npx * L.width_bytes[a];
             it.out = (uint8_t*)d_planes_out[a] + t * step;
             it.cw = (uint64_t*)base; base += al(8ull * nwords);
@@ -678,9 +687,9 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
         if (hit[r].wb == 4) hlist[n_wide++] = r;
     for (uint32_t r = 0, k = n_wide; r < n; ++r)
         if (hit[r].wb != 4) hlist[k++] = r;
-    if (hipMemcpyAsync(dev + o_err, up, up_bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return JIFFY_E_DEVICE;
     DecPlan plan;
-    plan.items = (const DecItem*)(dev + o_items);
+    memset(&plan, 0, sizeof plan);
+    plan.items = (DecItem*)(dev + o_items);
     plan.res = (DecRes*)(dev + o_res);
     plan.err = (uint32_t*)(dev + o_err);
     plan.err2 = plan.err + 1;
@@ -705,13 +714,87 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
         plan.attr_wb[a] = L.width_bytes[a];
         plan.attr_P[a] = L.precision[a];
     }
+    if (!roff) {
+        plan.roff = (uint64_t*)(dev + o_roff);
+        plan.tab = (const uint32_t*)(din + p);
+        plan.src = din;
+        plan.src_len = in_len;
+        plan.hdr_len = (uint32_t)p;
+        plan.hdr_check = hdr ? 1u : 0u;
+        if (hdr) memcpy(plan.hdr_words, hdr, p);
+    }
+    if (launch_dec_prepare(ctx.up.d, dev + o_err, up_bytes, plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (launch_decode(plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
-    if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipMemcpyAsync(ctx.down.p, dev + o_err, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     prof_collect();
     const uint32_t* errs = (const uint32_t*)ctx.down.p;
     return (errs[0] | errs[1]) ? JIFFY_E_CORRUPT : JIFFY_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hipStream_t stream) {
+    if (!d_in || (uintptr_t)d_in % 4) return JIFFY_E_INVALID;
+    if (in_len < 20) return JIFFY_E_CORRUPT;
+    int devid;
+    if (current_device(&devid)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[devid];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    const uint8_t* din = (const uint8_t*)d_in;
+    // header
+    const size_t h0 = in_len < 20 + 8 * JIFFY_MAX_ATTRS ? in_len : 20 + 8 * JIFFY_MAX_ATTRS;
+    if (grow(ctx.down, 4096) != hipSuccess) return JIFFY_E_DEVICE;
+    uint8_t* hb = (uint8_t*)ctx.down.p;
+    if (hipMemcpyAsync(hb, din, h0, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    jiffy_layout L;
+    uint32_t T_hdr;
+    size_t p;
+    int rc = parse_header(hb, h0, &L, &T_hdr, &p);
+    if (rc) return rc;
+    const uint32_t A = L.n_attrs;
+    if (T_hdr) {  // a length table: the records are indexed on the device
+        if ((uint64_t)T_hdr * A > (1u << 24) || in_len < p + 4ull * T_hdr * A) return JIFFY_E_CORRUPT;
+        return run_decode(ctx, L, T_hdr, din, in_len, nullptr, nullptr, p, nullptr, d_planes_out, stream);
+    }
+    // no table: walk the records
+    std::vector<uint64_t> roff;
+    std::vector<uint32_t> rlen;
+    uint64_t q = p;
+    uint8_t* tb = (uint8_t*)ctx.down.p;
+    while (q < in_len) {
+        if (q + 4 > in_len) return JIFFY_E_CORRUPT;
+        if (hipMemcpyAsync(tb, din + q, 4, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+        if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+        const uint32_t rl = rd32(tb);
+        if (rl < 12 || rl % 4 || rl > in_len - q) return JIFFY_E_CORRUPT;
+        roff.push_back(q);
+        rlen.push_back(rl);
+        q += rl;
+        if (roff.size() > (1u << 24)) return JIFFY_E_CORRUPT;
+    }
+    if (roff.size() % A) return JIFFY_E_CORRUPT;
+    const uint32_t T = (uint32_t)(roff.size() / A);
+    return run_decode(ctx, L, T, din, in_len, roff.data(), rlen.data(), p, nullptr, d_planes_out, stream);
+}
+
+int jiffy_decode_layout(const jiffy_layout* layout, uint32_t n_scans, const void* d_in, size_t in_len,
+                        void* const* d_planes_out, hipStream_t stream) {
+    if (!layout_ok(layout) || !d_in || (uintptr_t)d_in % 4 || n_scans == 0) return JIFFY_E_INVALID;
+    const uint32_t A = layout->n_attrs;
+    if ((uint64_t)n_scans * A > (1u << 24)) return JIFFY_E_INVALID;
+    const size_t p = 20 + 8 * A;
+    if (in_len < p + 4ull * n_scans * A) return JIFFY_E_CORRUPT;
+    int devid;
+    if (current_device(&devid)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[devid];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    uint8_t hdr[20 + 8 * JIFFY_MAX_ATTRS];
+    write_header(hdr, layout, n_scans);
+    return run_decode(ctx, *layout, n_scans, (const uint8_t*)d_in, in_len, nullptr, nullptr, p, hdr, d_planes_out,
+                      stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -872,8 +955,8 @@ struct jiffy_batch {
     std::vector<size_t> caps;
     EncLayout Lo;
     uint8_t* dev = nullptr;
-    uint8_t* up = nullptr;
-    uint8_t* down = nullptr;
+    uint8_t* up = nullptr;    // host image of the plan, copied in before each launch
+    uint8_t* down = nullptr;  // [res][err][outs], copied out after it
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -904,7 +987,7 @@ int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* con
         hipHostMalloc((void**)&b->down, b->Lo.o_items, hipHostMallocDefault) == hipSuccess &&
         hipStreamCreate(&b->cap_stream) == hipSuccess) {
         enc_fill(b->Lo, specs, outs, b->dev, b->up);
-        const EncPlan plan = enc_plan(b->Lo, b->dev);
+        const EncPlan plan = enc_plan(b->Lo, b->dev, nullptr);
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             t_capturing = true;
             const hipError_t e = launch_encode(plan, b->cap_stream);
@@ -945,7 +1028,7 @@ int jiffy_batch_run(jiffy_batch* b, const void* const* const* d_planes, size_t* 
         return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     EncResult res;
-    enc_results(b->Lo, b->down, res);
+    enc_results_image(b->Lo, b->down, res);
     return finish_step(b->streams.data(), n, res, h_lens, h_modes);
 }
 

@@ -67,8 +67,7 @@ struct ParseLds {
     uint32_t s_err, s_done, s_next, s_pos, s_flen, s_nblk;
 };
 
-__device__ void parse_mask(const DecPlan& plan, uint32_t r, ParseLds& P) {
-    const DecItem it = plan.items[r];
+__device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, ParseLds& P) {
     const uint8_t* rec = it.rec;
     const uint32_t L = it.rec_len;
     const uint32_t nm = div_up(it.npx, 8);
@@ -317,8 +316,7 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, ParseLds& P) {
     if (tid == 0 && P.s_err) atomicOr(plan.err, kErrCorrupt);
 }
 
-__device__ void parse_sections(const DecPlan& plan, uint32_t r, ParseLds& P) {
-    const DecItem it = plan.items[r];
+__device__ void parse_sections(const DecPlan& plan, uint32_t r, const DecItem& it, ParseLds& P) {
     const uint8_t* rec = it.rec;
     const uint32_t L = it.rec_len;
     const uint32_t tid = threadIdx.x;
@@ -390,8 +388,68 @@ __device__ void parse_sections(const DecPlan& plan, uint32_t r, ParseLds& P) {
 
 __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
     __shared__ ParseLds P;
-    if (blockIdx.y == 0) parse_mask(plan, blockIdx.x, P);
-    else parse_sections(plan, blockIdx.x, P);
+    const uint32_t r = blockIdx.x;
+    DecItem it = plan.items[r];
+    if (plan.roff) {  // the record from the device-side index; later kernels find it in the item
+        const uint64_t o = plan.roff[r];
+        if (o == ~0ull) {
+            if (threadIdx.x == 0 && blockIdx.y == 0) atomicOr(plan.err, kErrCorrupt);
+            return;
+        }
+        it.rec = plan.src + o;
+        it.rec_len = plan.tab[r];
+        if (threadIdx.x == 0 && blockIdx.y == 0) {
+            plan.items[r].rec = it.rec;
+            plan.items[r].rec_len = it.rec_len;
+        }
+    }
+    if (blockIdx.y == 0) parse_mask(plan, r, it, P);
+    else parse_sections(plan, r, it, P);
+}
+
+// ---------------------------------------------------------------------------
+// Plan upload (blocks before the last, 16 bytes per thread from host-mapped
+// memory) and record index (the last block): the stream header must equal
+// the expected one, every table length must be a multiple of 4 of at least
+// 12 bytes, and the records must end exactly at the end of the stream;
+// otherwise every record offset is ~0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dec_prepare(const uint4* src, uint4* dst, uint32_t n16, DecPlan plan) {
+    const uint32_t tid = threadIdx.x;
+    if (blockIdx.x + 1 < gridDim.x || !plan.roff) {
+        const uint32_t i = blockIdx.x * 256 + tid;
+        if (i < n16) ((JG uint4*)dst)[i] = load_system16((const JG uint4*)src + i);
+        return;
+    }
+    __shared__ uint64_t scratch[8];
+    __shared__ uint32_t s_bad;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    if (plan.hdr_check && tid < plan.hdr_len / 4 && ((const JG uint32_t*)plan.src)[tid] != plan.hdr_words[tid])
+        atomicOr(&s_bad, 1u);
+    const uint32_t n = plan.n_items;
+    uint64_t carry = (uint64_t)plan.hdr_len + 4ull * n;
+    for (uint32_t r0 = 0; r0 < n; r0 += 256) {
+        const uint32_t r = r0 + tid;
+        const uint32_t len = r < n ? plan.tab[r] : 0u;
+        if (r < n && (len < 12 || len % 4)) atomicOr(&s_bad, 1u);
+        uint64_t total;
+        const uint64_t pre = block_excl_scan64<256>((uint64_t)len, scratch, &total) + carry;
+        if (r < n) plan.roff[r] = pre;
+        carry += total;
+    }
+    __syncthreads();
+    if (s_bad || carry != plan.src_len)
+        for (uint32_t r = tid; r < n; r += 256) plan.roff[r] = ~0ull;  // the same thread wrote it above
+}
+
+hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const DecPlan& plan, hipStream_t stream) {
+    const uint32_t n16 = (uint32_t)(bytes / 16);
+    const uint32_t blocks = div_up(n16, 256) + (plan.roff ? 1u : 0u);
+    if (blocks == 0) return hipSuccess;
+    JIFFY_LAUNCH("k_dec_prepare", k_dec_prepare, dim3(blocks), dim3(256), stream, (const uint4*)host, (uint4*)dev,
+                 n16, plan);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

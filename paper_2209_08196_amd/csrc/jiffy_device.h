@@ -57,6 +57,20 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
     return v;
 }
 
+// Accesses to host memory at system scope: they bypass the device's caches,
+// so a load sees what the host wrote before the launch and a store reaches
+// host memory by the time the kernel completes, whatever caching mode the
+// host allocation has.
+__device__ __forceinline__ uint4 load_system16(const JG uint4* p) {
+    const uint64_t* q = (const uint64_t*)p;
+    const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+}
+__device__ __forceinline__ void store_system(JG uint32_t* p, uint32_t v) {
+    __hip_atomic_store((uint32_t*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Exclusive prefix sum over a workgroup of NT threads.  `scratch` holds
 // NT/64 + 1 words of LDS.  Returns the exclusive prefix; *total gets the sum.
 // Every thread of the workgroup must call it.

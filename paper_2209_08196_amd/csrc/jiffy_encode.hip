@@ -20,6 +20,20 @@
 
 namespace jiffy {
 
+// The record of global tile t and the tile's index inside it: by division
+// when every record has `per` tiles, else from the maps.
+__device__ __forceinline__ uint32_t tile_owner(const JG uint32_t* item_of, const JG uint32_t* first_of, uint32_t per,
+                                               uint32_t t, uint32_t& lt) {
+    if (per) {
+        const uint32_t r = t / per;
+        lt = t - r * per;
+        return r;
+    }
+    const uint32_t r = item_of[t];
+    lt = t - first_of[r];
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // quantize + zero bitmask.  One workgroup per 4096-pixel tile; each thread
 // reads 16 consecutive samples; 4 lanes form one 64-bit valid word.
@@ -44,10 +58,9 @@ __device__ __forceinline__ void enc_mask_body(const EncItem& it, uint32_t lt) {
 }
 
 __global__ __launch_bounds__(256) void k_enc_mask(EncPlan plan) {
-    const uint32_t tile = blockIdx.x;
-    const uint32_t r = plan.tile_item[tile];
+    uint32_t lt;
+    const uint32_t r = tile_owner(plan.tile_item, plan.tile_first, plan.tpi, blockIdx.x, lt);
     const EncItem it = plan.items[r];
-    const uint32_t lt = tile - plan.tile_first[r];
     switch (it.wb) {
         case 4: enc_mask_body<4>(it, lt); break;
         case 2: enc_mask_body<2>(it, lt); break;
@@ -455,10 +468,9 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
 }
 
 __global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
-    const uint32_t t = blockIdx.x;
-    const uint32_t r = plan.ftile_item[t];
+    uint32_t lt;
+    const uint32_t r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, blockIdx.x, lt);
     const EncItem it = plan.items[r];
-    const uint32_t lt = t - plan.ftile_first[r];
     __shared__ TileLds lds;
     switch (it.wb) {
         case 4: enc_tile_body<4>(plan, it, r, lt, lds); break;
@@ -474,8 +486,8 @@ __global__ __launch_bounds__(64) void k_enc_fixup(EncPlan plan) {
     const uint32_t t = blockIdx.x * 16 + g;
     __shared__ uint32_t rows[16 * kRow];
     if (t >= plan.n_ftiles) return;  // no barrier follows
-    const uint32_t r = plan.ftile_item[t];
-    const uint32_t lt = t - plan.ftile_first[r];
+    uint32_t lt;
+    const uint32_t r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, t, lt);
     const EncItem& it = plan.items[r];
     const uint32_t j = it.tfix[lt];
     if (j == kNoFix) return;
@@ -715,11 +727,18 @@ __global__ __launch_bounds__(1024) void k_enc_offsets(EncPlan plan) {
         o.len = o.hdr_len + body;
         o.ok = o.len <= o.cap ? 1u : 0u;
         if (!o.ok) atomicOr(plan.err, kErrCapacity);
+        if (plan.host_res) {
+            JG uint32_t* h = (JG uint32_t*)plan.host_res + 4 * k;
+            store_system(h, (uint32_t)o.len);
+            store_system(h + 1, (uint32_t)(o.len >> 32));
+            store_system(h + 2, o.ok);
+        }
     }
     __syncthreads();
     for (uint32_t r = threadIdx.x; r < plan.n_items; r += 1024) {
         const EncOut& o = plan.outs[plan.items[r].out_id];
         plan.res[r].rec_off = plan.res[r].rec_off - o.gbase + o.hdr_len;
+        if (plan.host_res) store_system((JG uint32_t*)(plan.host_res + 16ull * plan.n_outs) + r, plan.res[r].mode);
     }
 }
 
@@ -801,6 +820,24 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
         for (uint32_t q = l; q < n; q += 16) rec[pos0 + on + q] = slot[16 * b + q];
         for (uint32_t q = l; q < oh1 - oh; q += 16) rec[high0 + oh + q] = slot[16 * b + n + q];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Plan upload: 16 bytes per thread from host-mapped memory.
+// ---------------------------------------------------------------------------
+// Kernel parameters are plain pointers: an address-space qualifier in the
+// signature would change the device symbol's name but not the host's.
+__global__ __launch_bounds__(256) void k_copy_in(const uint4* src, uint4* dst, uint32_t n16) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n16) ((JG uint4*)dst)[i] = load_system16((const JG uint4*)src + i);
+}
+
+hipError_t launch_copy_in(const void* host, void* dev, size_t bytes, hipStream_t stream) {
+    const uint32_t n16 = (uint32_t)(bytes / 16);
+    if (n16 == 0) return hipSuccess;
+    JIFFY_LAUNCH("k_copy_in", k_copy_in, dim3(div_up(n16, 256)), dim3(256), stream, (const uint4*)host, (uint4*)dev,
+                 n16);
+    return hipGetLastError();
 }
 
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {

@@ -158,14 +158,22 @@ struct EncPlan {
     const JG uint32_t* tile_first; // device: first tile of each item
     const JG uint32_t* ftile_item;  // device: item of each kFTile tile
     const JG uint32_t* ftile_first; // device: first kFTile tile of each item
+    JG uint8_t* host_res;        // host-mapped results (or null): per output {u64 len, u32 ok, u32 -}, then
+                                 // per record its mode (u32)
+    uint32_t tpi, ftpi;          // mask / kFTile tiles per record when every record has the same size (the
+                                 // maps above are then unused), else 0
     uint32_t n_items, n_outs, n_tiles, n_ftiles;
     uint32_t max_groups;      // max over items of ceil(maxnb / kGroupFrames)
     uint32_t max_asm;         // max over items of ceil(maxnb / kAsmFrames)
 };
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream);
 
+// Copies `bytes` (a multiple of 16) from host-mapped memory into device
+// memory with a kernel on `stream` (no copy engine, so no cross-queue wait).
+hipError_t launch_copy_in(const void* host, void* dev, size_t bytes, hipStream_t stream);
+
 struct DecPlan {
-    const JG DecItem* items;
+    JG DecItem* items;
     JG DecRes* res;
     JG uint32_t* err;
     JG uint32_t* err2;           // errors found by k_dec_tiles
@@ -180,9 +188,23 @@ struct DecPlan {
     const JG uint32_t* rec_list; // the records with 32-bit samples, then the others
     uint32_t n_wide;          // how many have 32-bit samples
     uint32_t need_temporal;   // per-pixel pass over time needed
+    // Record index built on the device (null roff: the host filled rec / rec_len):
+    // the length table at `tab`, records from `tab + n_items`, the stream `src_len`
+    // bytes long; roff[r] = byte offset of record r, or ~0 when the index is bad.
+    const JG uint32_t* tab;
+    JG uint64_t* roff;
+    const JG uint8_t* src;
+    uint64_t src_len;
+    uint32_t hdr_len;         // header bytes before the table
+    uint32_t hdr_check;       // compare them with hdr_words
+    uint32_t hdr_words[(20 + 8 * 8) / 4];  // the expected header
     JG void* out_base[8];        // attribute planes
     uint32_t attr_wb[8], attr_P[8];
 };
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream);
+
+// Upload of the decode plan (as launch_copy_in) and, when plan.roff is set,
+// the device-side record index, in one launch.
+hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const DecPlan& plan, hipStream_t stream);
 
 }  // namespace jiffy

@@ -20,7 +20,8 @@ MAX_ATTRS = 8
 OK, E_INVALID, E_CAPACITY, E_CORRUPT, E_DEVICE, E_SHAPE = 0, -1, -2, -3, -4, -5
 MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY = 0, 1, 2
 
-SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_peek", "jiffy_decode", "jiffy_status_string",
+SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_peek", "jiffy_decode", "jiffy_decode_layout",
+           "jiffy_status_string",
            "jiffy_stream_create", "jiffy_batch_encode_step", "jiffy_stream_reset", "jiffy_stream_destroy",
            "jiffy_batch_create", "jiffy_batch_run", "jiffy_batch_destroy",
            "jiffy_profile_enable", "jiffy_profile_read")
@@ -67,6 +68,8 @@ def lib():
         L.jiffy_peek.argtypes = [vp, sz, ctypes.POINTER(Layout), ctypes.POINTER(u32)]
         L.jiffy_decode.restype = ctypes.c_int
         L.jiffy_decode.argtypes = [vp, sz, vp, vp]
+        L.jiffy_decode_layout.restype = ctypes.c_int
+        L.jiffy_decode_layout.argtypes = [ctypes.POINTER(Layout), u32, vp, sz, vp, vp]
         L.jiffy_status_string.restype = ctypes.c_char_p
         L.jiffy_status_string.argtypes = [ctypes.c_int]
         L.jiffy_stream_create.restype = ctypes.c_int
@@ -198,21 +201,27 @@ def _peek_device(stream_bytes):
 
 def decode(stream_bytes, layout: Layout = None, n_scans: int = None, outs=None, stream=None):
     """stream_bytes: device uint8 tensor holding a whole stream.  layout /
-    n_scans come from jiffy_peek of its header when not given.  Returns the
-    list of decoded [T, H, W] device tensors (int16 / int32 storage for 16 /
-    32-bit attributes)."""
+    n_scans come from jiffy_peek of its header when not given; when given
+    (n_scans >= 1) the stream is decoded by jiffy_decode_layout, which checks
+    them on the device.  Returns the list of decoded [T, H, W] device tensors
+    (int16 / int32 storage for 16 / 32-bit attributes)."""
     import torch
-    if layout is None or n_scans is None:
+    known = layout is not None and n_scans is not None and n_scans >= 1
+    if not known:
         layout, n_scans = _peek_device(stream_bytes)
     dev = stream_bytes.device
     if outs is None:
         outs = [torch.empty((n_scans, layout.height, layout.width), dtype=getattr(torch, _TORCH_DT[layout.width_bytes[a]]),
                             device=dev) for a in range(layout.n_attrs)]
     arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
-    rc = lib().jiffy_decode(ctypes.c_void_p(stream_bytes.data_ptr()), stream_bytes.numel(),
-                            ctypes.cast(arr, ctypes.c_void_p), _stream_handle(stream))
+    if known:
+        rc = lib().jiffy_decode_layout(ctypes.byref(layout), n_scans, ctypes.c_void_p(stream_bytes.data_ptr()),
+                                       stream_bytes.numel(), ctypes.cast(arr, ctypes.c_void_p), _stream_handle(stream))
+    else:
+        rc = lib().jiffy_decode(ctypes.c_void_p(stream_bytes.data_ptr()), stream_bytes.numel(),
+                                ctypes.cast(arr, ctypes.c_void_p), _stream_handle(stream))
     if rc:
-        raise JiffyError(rc, "jiffy_decode")
+        raise JiffyError(rc, "jiffy_decode_layout" if known else "jiffy_decode")
     return outs
 
 

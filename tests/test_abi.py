@@ -36,6 +36,19 @@ def test_every_declared_symbol_is_exported(lib):
         assert ctypes.cast(getattr(lib, n), ctypes.c_void_p).value
 
 
+def test_every_launched_kernel_is_in_the_code_object(lib):
+    """Each kernel name the host side registers has a kernel descriptor
+    (`.kd`) in the gfx950 code object built into the library.  A kernel
+    whose parameters carry an address-space qualifier gets a different
+    mangled name in the device compilation, and launching it aborts."""
+    blob = open(jiffy.LIB_PATH, "rb").read()
+    names = set(re.findall(rb"_ZN5jiffy\d+k_\w+", blob))
+    kds = {n for n in names if (n + b".kd") in blob}
+    assert kds, "no kernel descriptors found"
+    missing = sorted(n.decode() for n in names - kds if not n.endswith(b"_kd"))
+    assert not missing, missing
+
+
 def test_status_strings(lib):
     for code in (0, -1, -2, -3, -4, -5):
         s = lib.jiffy_status_string(code)

@@ -1,0 +1,113 @@
+"""jiffy_decode_layout: decoding with the layout and scan count known to the
+caller (nothing read back before the kernels; the header is checked and the
+records are indexed on the device) restores the oracle's output exactly.  A
+stream that does not match the given layout, or whose length table does not
+add up, is reported as corrupt, and then no record is parsed at all: every
+case below leaves the records themselves intact, so the kernels only ever
+see well-formed records or none."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import banner, to_dev, to_host
+from paper_2209_08196_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def J():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_08196_amd import jiffy
+    jiffy.lib()
+    return jiffy
+
+
+def _dev(b):
+    import torch
+    return torch.from_numpy(np.frombuffer(bytes(b), np.uint8).copy()).cuda()
+
+
+def _layout(J, planes, precs):
+    T, H, W = planes[0].shape
+    return J.make_layout(H, W, [p.dtype.itemsize for p in planes], precs), T
+
+
+def _cases():
+    g = synth.stream(2, 0)
+    yield "dual-return 128x2048 x3", g.scans(0, 3), list(g.precisions), 0
+    g = synth.stream(1, 2)
+    yield "plain 64x1024 P=10 x4 forced P", g.scans(0, 4), list(g.precisions), 2
+    rng = np.random.default_rng(61)
+    yield "ragged 3x17x129 u16+u8", [synth.random_scans(rng, 3, 17, 129, np.uint16, 0.3),
+                                     synth.random_scans(rng, 3, 17, 129, np.uint8, 0.1)], [3, 1], 0
+    yield "one pixel", [synth.random_scans(rng, 2, 1, 1, np.uint32, 0.5)], [1], 0
+
+
+def test_decode_layout_matches_oracle(J):
+    for name, planes, precs, mode in _cases():
+        banner("decode_layout", name)
+        s_ref, _ = oracle.encode(planes, precs, mode=mode)
+        ref = oracle.decode(s_ref)
+        lay, T = _layout(J, planes, precs)
+        outs = J.decode(_dev(s_ref), lay, T)
+        for a, (o, r) in enumerate(zip(outs, ref)):
+            assert np.array_equal(to_host(o, r.dtype.itemsize), r), (name, a)
+
+
+def test_decode_layout_of_device_encoded_stream(J):
+    """The stream jiffy_encode left on the device, decoded in place."""
+    g = synth.stream(2, 3)
+    x = g.scans(0, 4)
+    banner("encode + decode_layout in place, dual-return x4")
+    s, _ = J.encode([to_dev(p) for p in x], g.precisions)
+    lay, T = _layout(J, x, list(g.precisions))
+    outs = J.decode(s, lay, T)
+    for a, (o, p) in enumerate(zip(outs, x)):
+        assert np.array_equal(to_host(o, p.dtype.itemsize), p), a  # P = 1: lossless
+
+
+def _corrupt(J, fn):
+    with pytest.raises(J.JiffyError) as e:
+        fn()
+    assert e.value.code == J.E_CORRUPT, e.value
+
+
+def test_decode_layout_rejects_mismatched_layouts_and_tables(J):
+    g = synth.stream(1, 0)
+    x = g.scans(0, 3)
+    precs = list(g.precisions)
+    s_ref, _ = oracle.encode(x, precs)
+    lay, T = _layout(J, x, precs)
+    A, H, W = 1, x[0].shape[1], x[0].shape[2]
+    p = 20 + 8 * A
+    banner("decode_layout mismatches")
+    _corrupt(J, lambda: J.decode(_dev(s_ref), lay, T - 1))
+    _corrupt(J, lambda: J.decode(_dev(s_ref), lay, T + 1))
+    _corrupt(J, lambda: J.decode(_dev(s_ref), J.make_layout(H, W, [4], [precs[0] + 1]), T))
+    _corrupt(J, lambda: J.decode(_dev(s_ref), J.make_layout(W, H, [4], precs), T))
+    _corrupt(J, lambda: J.decode(_dev(s_ref), J.make_layout(H, W, [2], precs), T))
+    # a record length changed by 4: the table no longer adds up to the stream
+    b = bytearray(s_ref)
+    n0 = int.from_bytes(b[p:p + 4], "little")
+    b[p:p + 4] = (n0 + 4).to_bytes(4, "little")
+    _corrupt(J, lambda: J.decode(_dev(b), lay, T))
+    _corrupt(J, lambda: J.decode(_dev(b)))  # the host-read header path indexes on the device too
+    # lengths that still add up but are not multiples of 4
+    b = bytearray(s_ref)
+    n1 = int.from_bytes(b[p + 4:p + 8], "little")
+    b[p:p + 4] = (n0 + 1).to_bytes(4, "little")
+    b[p + 4:p + 8] = (n1 - 1).to_bytes(4, "little")
+    _corrupt(J, lambda: J.decode(_dev(b), lay, T))
+    _corrupt(J, lambda: J.decode(_dev(b)))
+    # a header without a length table is not accepted here
+    b = bytearray(s_ref[:p]) + bytearray(s_ref[p + 4 * T * A:])
+    b[16:20] = (0).to_bytes(4, "little")
+    _corrupt(J, lambda: J.decode(_dev(b), lay, T))
+    # the open-ended stream itself decodes through jiffy_decode
+    ref = oracle.decode(s_ref)[0]
+    assert np.array_equal(to_host(J.decode(_dev(b))[0], 4), ref)
+    # and the valid stream still decodes after all of the above
+    assert np.array_equal(to_host(J.decode(_dev(s_ref), lay, T)[0], 4), ref)
