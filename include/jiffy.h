@@ -140,9 +140,10 @@ int jiffy_batch_encode_step(jiffy_stream* const* streams, uint32_t n, const void
 /* ---- batches (one graph launch per step) --------------------------------
  * A fixed set of n streams encoded together every step, with the same
  * records as jiffy_batch_encode_step.  The step's kernels are captured
- * once in a HIP graph; a step is one upload of the records' descriptors
- * (input pointers included), one graph launch and one download of the
- * lengths.  Arguments of create:
+ * once in a HIP graph; a step rewrites the records' descriptors (input
+ * pointers included) in pinned host memory and launches the graph, whose
+ * first kernel reads them and whose offsets kernel writes the lengths and
+ * modes back to pinned host memory.  Arguments of create:
  *   d_planes[i][a]: device pointer to stream i's next scan of attribute a
  *                   (H*W samples); a run may name other input pointers;
  *   d_out[i]:       device buffer of caps[i] bytes (4-byte aligned) that

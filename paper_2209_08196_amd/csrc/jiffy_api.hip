@@ -313,27 +313,14 @@ EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev, uint8_t* host_res) {
     return plan;
 }
 
-// Everything one call enqueues: the upload of the plan image by a kernel
-// reading `up_dev` (the device address of the host image), then the
-// kernels; k_enc_offsets writes the lengths and modes to the host results.
+// Everything one call enqueues (also what a batch captures in its graph):
+// the upload of the plan image by a kernel reading `up_dev` (the device
+// address of the host image), then the kernels; k_enc_offsets writes the
+// lengths and modes to the host results.
 hipError_t enc_enqueue(const EncLayout& Lo, const EncPlan& plan, uint8_t* dev, const void* up_dev, hipStream_t stream) {
     hipError_t e = launch_copy_in(up_dev, dev + Lo.o_err, Lo.up_bytes(), stream);
     if (e != hipSuccess) return e;
     return launch_encode(plan, stream);
-}
-
-// Results from a host copy of the workspace's [res][err][outs].
-void enc_results_image(const EncLayout& Lo, const uint8_t* down, EncResult& result) {
-    const EncRes* dres = (const EncRes*)(down + Lo.o_res);
-    const EncOut* douts = (const EncOut*)(down + Lo.o_outs);
-    result.lens.resize(Lo.no);
-    result.ok.resize(Lo.no);
-    result.modes.resize(Lo.n);
-    for (uint32_t k = 0; k < Lo.no; ++k) {
-        result.lens[k] = douts[k].len;
-        result.ok[k] = (uint8_t)douts[k].ok;
-    }
-    for (uint32_t r = 0; r < Lo.n; ++r) result.modes[r] = (uint8_t)dres[r].mode;
 }
 
 // Results k_enc_offsets wrote to host memory.
@@ -955,8 +942,10 @@ struct jiffy_batch {
     std::vector<size_t> caps;
     EncLayout Lo;
     uint8_t* dev = nullptr;
-    uint8_t* up = nullptr;    // host image of the plan, copied in before each launch
-    uint8_t* down = nullptr;  // [res][err][outs], copied out after it
+    uint8_t* up = nullptr;   // host image of the plan, read by the graph's upload kernel
+    void* up_d = nullptr;
+    uint8_t* res = nullptr;  // host results, written by the graph's offsets kernel
+    void* res_d = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -983,14 +972,14 @@ int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* con
     b->Lo = enc_layout(specs, outs);
     int rc = JIFFY_E_DEVICE;
     if (hipMalloc((void**)&b->dev, b->Lo.total) == hipSuccess &&
-        hipHostMalloc((void**)&b->up, b->Lo.up_bytes(), hipHostMallocDefault) == hipSuccess &&
-        hipHostMalloc((void**)&b->down, b->Lo.o_items, hipHostMallocDefault) == hipSuccess &&
+        host_alloc((void**)&b->up, &b->up_d, b->Lo.up_bytes()) == hipSuccess &&
+        host_alloc((void**)&b->res, &b->res_d, b->Lo.res_bytes()) == hipSuccess &&
         hipStreamCreate(&b->cap_stream) == hipSuccess) {
         enc_fill(b->Lo, specs, outs, b->dev, b->up);
-        const EncPlan plan = enc_plan(b->Lo, b->dev, nullptr);
+        const EncPlan plan = enc_plan(b->Lo, b->dev, (uint8_t*)b->res_d);
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             t_capturing = true;
-            const hipError_t e = launch_encode(plan, b->cap_stream);
+            const hipError_t e = enc_enqueue(b->Lo, plan, b->dev, b->up_d, b->cap_stream);
             t_capturing = false;
             const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &b->graph);
             if (e == hipSuccess && e2 == hipSuccess &&
@@ -1022,13 +1011,10 @@ int jiffy_batch_run(jiffy_batch* b, const void* const* const* d_planes, size_t* 
     std::vector<OutSpec> outs;
     stream_specs(b->streams.data(), n, b->plane_ptrs.data(), b->outs.data(), b->caps.data(), specs, outs);
     enc_fill(b->Lo, specs, outs, b->dev, b->up);
-    if (hipMemcpyAsync(b->dev + b->Lo.o_err, b->up, b->Lo.up_bytes(), hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipGraphLaunch(b->exec, stream) != hipSuccess ||
-        hipMemcpyAsync(b->down, b->dev, b->Lo.o_items, hipMemcpyDeviceToHost, stream) != hipSuccess)
-        return JIFFY_E_DEVICE;
+    if (hipGraphLaunch(b->exec, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     EncResult res;
-    enc_results_image(b->Lo, b->down, res);
+    enc_results(b->Lo, b->res, res);
     return finish_step(b->streams.data(), n, res, h_lens, h_modes);
 }
 
@@ -1039,7 +1025,7 @@ void jiffy_batch_destroy(jiffy_batch* b) {
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->dev) (void)hipFree(b->dev);
     if (b->up) (void)hipHostFree(b->up);
-    if (b->down) (void)hipHostFree(b->down);
+    if (b->res) (void)hipHostFree(b->res);
     delete b;
 }
 
