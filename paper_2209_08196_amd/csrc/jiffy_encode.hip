@@ -192,12 +192,37 @@ __device__ __forceinline__ uint32_t frame_cost_quad(uint32_t* vrow, uint32_t rea
     return quad_frame_key<false>(z, vrow, vrow, real, pred, bits, q, B) >> 14;
 }
 
+// Position of the k-th (from 0) set bit of a (k < popcount(a)).
+__device__ __forceinline__ uint32_t select64(uint64_t a, uint32_t k) {
+    uint32_t p = 0;
+#pragma unroll
+    for (uint32_t w = 32; w >= 1; w >>= 1) {
+        const uint32_t c = __popcll(a & ((1ull << w) - 1ull));
+        if (k >= c) {
+            k -= c;
+            a >>= w;
+            p += w;
+        }
+    }
+    return p;
+}
+
+// Bit offset, inside a frame's exception bytes, of item j: the n positions
+// (8 bits each) come first, then the n high parts (hw bits each).
+__device__ __forceinline__ uint32_t exc_bit(uint32_t j, uint32_t n, uint32_t hw) {
+    return j < n ? 8u * j : 8u * n + (j - n) * hw;
+}
+
 // vrow: the frame's values (row layout); the width histogram, then the
 // codes replace them.  The packed frame goes straight to its slot: lane q
-// stores its b words of low bits (words qb .. qb+b-1); then lane 0 writes
-// the exception bytes -- the positions, then the high parts -- as one
-// little-endian bit stream from byte 16b, reading the exceptions' codes
-// back from vrow.  b | n << 8 | B << 16 goes to *info.
+// stores its b words of low bits (words qb .. qb+b-1).  The exception bytes
+// from byte 16b -- the positions, then the high parts, one little-endian
+// bit stream of 8n + n(B - b) bits -- are split between the lanes by whole
+// words: lane q writes the words from the one that holds item q*2n/4 up to
+// the one that holds item (q+1)*2n/4 (exclusive), so no word has two
+// writers; each lane walks the exceptions from its first item on, reading
+// their codes back from vrow four at a time.  b | n << 8 | B << 16 goes to
+// *info.
 __device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t real, uint32_t pred, uint32_t bits,
                                                 uint32_t q, JG uint8_t* slot, JG uint32_t* info) {
     uint32_t z[32], B;
@@ -224,29 +249,78 @@ __device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t real, u
     uint32_t ex = 0;  // this lane's exceptions
 #pragma unroll
     for (int i = 0; i < 32; ++i) ex |= (z[i] > lm ? 1u : 0u) << i;
-    const uint32_t x1 = quad_bcast<1>(ex), x2 = quad_bcast<2>(ex), x3 = quad_bcast<3>(ex);
-    if (q == 0 && nexc) {
-        // positions (8 bits each) then high parts (hw bits each), from byte 16b
-        JG uint32_t* dst = sw + 4u * b;
-        uint64_t acc = 0;
-        uint32_t nacc = 0, wi = 0;
-        auto put = [&](uint32_t v, uint32_t nbits) {
-            acc |= (uint64_t)v << nacc;
-            nacc += nbits;
-            if (nacc >= 32) {
-                dst[wi++] = (uint32_t)acc;
-                acc >>= 32;
-                nacc -= 32;
-            }
-        };
-        const uint32_t xs[4] = {ex, x1, x2, x3};
-        for (uint32_t h = 0; h < 4; ++h)
-            for (uint32_t m = xs[h]; m; m &= m - 1u) put(32u * h + __builtin_ctz(m), 8);
-        for (uint32_t h = 0; h < 4; ++h)
-            for (uint32_t m = xs[h]; m; m &= m - 1u) put(vrow[row_off(32u * h + __builtin_ctz(m))] >> b, hw);
-        if (nacc) dst[wi] = (uint32_t)acc;
-    }
+    const uint64_t elo = (uint64_t)quad_bcast<0>(ex) | ((uint64_t)quad_bcast<1>(ex) << 32);
+    const uint64_t ehi = (uint64_t)quad_bcast<2>(ex) | ((uint64_t)quad_bcast<3>(ex) << 32);
     if (q == 0) *info = b | (nexc << 8) | (B << 16);
+    if (nexc == 0) return;
+    const uint32_t n2 = 2u * nexc, T = exc_bit(n2, nexc, hw);
+    const uint32_t w0 = exc_bit((q * n2) >> 2, nexc, hw) >> 5;
+    const uint32_t w1 = q == 3 ? (T + 31u) >> 5 : exc_bit(((q + 1u) * n2) >> 2, nexc, hw) >> 5;
+    if (w0 >= w1) return;
+    const uint32_t bb = 32u * w0, be = min(32u * w1, T);
+    // the item holding bit bb, and the exception it belongs to
+    uint32_t j = bb < 8u * nexc ? bb / 8u : nexc + (bb - 8u * nexc) / hw;
+    uint64_t ca, cb;  // exceptions from the cursor on: the current half, then the high half (if not in it)
+    uint32_t cbase;
+    {
+        const uint32_t k = j < nexc ? j : j - nexc, c0 = __popcll(elo);
+        if (k < c0) {
+            ca = elo & (~0ull << select64(elo, k));
+            cb = ehi;
+            cbase = 0;
+        } else {
+            ca = ehi & (~0ull << select64(ehi, k - c0));
+            cb = 0;
+            cbase = 64;
+        }
+    }
+    JG uint32_t* sec = sw + 4u * b;
+    uint64_t acc = 0;
+    uint32_t nacc = 0, wi = w0, s = exc_bit(j, nexc, hw);
+    while (s < be) {
+        uint32_t pos[4], code[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (j + t == nexc) {  // the positions are done: the high parts start again from exception 0
+                ca = elo;
+                cb = ehi;
+                cbase = 0;
+            }
+            if (!ca) {
+                ca = cb;
+                cb = 0;
+                cbase = 64;
+            }
+            pos[t] = ca ? cbase + (uint32_t)__builtin_ctzll(ca) : 0u;
+            ca &= ca - 1ull;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) code[t] = vrow[row_off(pos[t])];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (s < be) {
+                const bool is_pos = j < nexc;
+                uint32_t v = is_pos ? pos[t] : code[t] >> b;
+                uint32_t wd = is_pos ? 8u : hw;
+                const uint32_t s_next = s + wd;
+                if (s < bb) {  // the item began in the previous lane's last word
+                    v >>= bb - s;
+                    wd -= bb - s;
+                }
+                acc |= (uint64_t)v << nacc;
+                nacc += wd;
+                if (nacc >= 32) {
+                    if (wi < w1) sec[wi] = (uint32_t)acc;
+                    ++wi;
+                    acc >>= 32;
+                    nacc -= 32;
+                }
+                ++j;
+                s = s_next;
+            }
+        }
+    }
+    if (nacc && wi < w1) sec[wi] = (uint32_t)acc;
 }
 
 // ---------------------------------------------------------------------------
