@@ -734,11 +734,20 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
     }
     const uint32_t n01 = D.nw[0] + D.nw[1], nall = n01 + D.nw[2];
     const bool staged = nall <= kStageWords;  // else the frames are read from the record
-    if (staged) {
-        const uint32_t* recw = (const uint32_t*)it.rec;  // records are 4-byte aligned
-        for (uint32_t i = tid; i < nall; i += kDecThreads) {
+    if (staged) {  // every load issued before the first store, so their latencies overlap
+        constexpr int kIter = (kStageWords + kDecThreads - 1) / kDecThreads;
+        const JG uint32_t* recw = (const JG uint32_t*)it.rec;  // records are 4-byte aligned
+        uint32_t w[kIter];
+#pragma unroll
+        for (int u = 0; u < kIter; ++u) {
+            const uint32_t i = tid + u * kDecThreads;
             const uint32_t src = i < D.nw[0] ? D.w0[0] + i : (i < n01 ? D.w0[1] + (i - D.nw[0]) : D.w0[2] + (i - n01));
-            L.stage[i] = recw[src];
+            w[u] = i < nall ? recw[src] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kIter; ++u) {
+            const uint32_t i = tid + u * kDecThreads;
+            if (i < nall) L.stage[i] = w[u];
         }
     }
     __syncthreads();
