@@ -632,15 +632,17 @@ __device__ __forceinline__ void classify32(const EncItem& it, uint32_t mode, uin
     R.start = (uint32_t)st & valid;
 }
 
-__global__ __launch_bounds__(256) void k_enc_mframe(EncPlan plan) {
+constexpr uint32_t kMfThreads = 1024;  // one workgroup per record covers 32 KiB of mask content per round
+
+__global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
     const uint32_t r = blockIdx.x;
     const EncItem it = plan.items[r];
     const uint32_t mode = plan.res[r].mode;
     const uint32_t nm = div_up(it.npx, 8);
-    __shared__ uint32_t scratch[8];
+    __shared__ uint32_t scratch[kMfThreads / 64 + 1];
     const uint32_t hdr = nm <= 255 ? 6u : nm <= 65791 ? 7u : 9u;
     const uint32_t tid = threadIdx.x;
-    constexpr uint32_t kStep = 256 * 32;
+    constexpr uint32_t kStep = kMfThreads * 32;
 
     // pass 1: segment starts
     uint32_t nseg = 0;
@@ -649,7 +651,7 @@ __global__ __launch_bounds__(256) void k_enc_mframe(EncPlan plan) {
         RunBits R;
         classify32(it, mode, nm, b0, R);
         uint32_t total;
-        uint32_t sid = block_excl_scan<256>(__popc(R.start), scratch, &total) + nseg;
+        uint32_t sid = block_excl_scan<kMfThreads>(__popc(R.start), scratch, &total) + nseg;
         for (uint32_t m = R.start; m; m &= m - 1) {
             const uint32_t k = __ffs(m) - 1;
             it.segs[sid++] = (b0 + k) | (((R.lng >> k) & 1u) << 31);
@@ -659,7 +661,7 @@ __global__ __launch_bounds__(256) void k_enc_mframe(EncPlan plan) {
     __syncthreads();
     // pass 2: encoded sizes and offsets of the segments
     uint32_t off_carry = hdr;
-    for (uint32_t s0 = 0; s0 < nseg; s0 += 256) {
+    for (uint32_t s0 = 0; s0 < nseg; s0 += kMfThreads) {
         const uint32_t sg = s0 + tid;
         uint32_t size = 0;
         if (sg < nseg) {
@@ -671,7 +673,7 @@ __global__ __launch_bounds__(256) void k_enc_mframe(EncPlan plan) {
             size = (a >> 31) ? 4u * nblk : 3u * nblk + len;
         }
         uint32_t total;
-        const uint32_t off = block_excl_scan<256>(size, scratch, &total) + off_carry;
+        const uint32_t off = block_excl_scan<kMfThreads>(size, scratch, &total) + off_carry;
         if (sg < nseg) it.segoff[sg] = off;
         off_carry += total;
     }
@@ -687,7 +689,7 @@ __global__ __launch_bounds__(256) void k_enc_mframe(EncPlan plan) {
         plan.res[r].nseg = nseg;
     }
     // block headers (and the byte of each RLE block)
-    for (uint32_t sg = tid; sg < nseg; sg += 256) {
+    for (uint32_t sg = tid; sg < nseg; sg += kMfThreads) {
         const uint32_t a = it.segs[sg];
         const uint32_t start = a & 0x7FFFFFFFu;
         const uint32_t end = (sg + 1 < nseg) ? (it.segs[sg + 1] & 0x7FFFFFFFu) : nm;
@@ -715,7 +717,7 @@ __global__ __launch_bounds__(256) void k_enc_mframe(EncPlan plan) {
         RunBits R;
         classify32(it, mode, nm, b0, R);
         uint32_t total;
-        uint32_t sid = block_excl_scan<256>(__popc(R.start), scratch, &total) + seg_carry;
+        uint32_t sid = block_excl_scan<kMfThreads>(__popc(R.start), scratch, &total) + seg_carry;
         const uint32_t nvalid = nm > b0 ? min(32u, nm - b0) : 0u;
         uint32_t sg = sid ? sid - 1 : 0, sstart = 0, soff = 0;
         if (sid) { sstart = it.segs[sg] & 0x7FFFFFFFu; soff = it.segoff[sg]; }
@@ -840,19 +842,42 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
             h[2] = rs.flen;
             *(uint32_t*)(rec + sec) = rs.N;
         }
-        {
+        {  // the mask frame, eight words per thread per round (loads first)
             const uint32_t nw = rs.flen / 4;
             const uint32_t* fw = (const uint32_t*)it.frame;  // staging and record are word aligned
             uint32_t* dw = (uint32_t*)(rec + 12);
-            for (uint32_t k = tid; k < nw; k += 256) dw[k] = fw[k];
+            for (uint32_t k0 = 0; k0 < nw; k0 += 8 * 256) {
+                uint32_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t k = k0 + u * 256 + tid;
+                    v[u] = k < nw ? fw[k] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t k = k0 + u * 256 + tid;
+                    if (k < nw) dw[k] = v[u];
+                }
+            }
             for (uint32_t k = 4 * nw + tid; k < rs.flen; k += 256) rec[12 + k] = it.frame[k];
         }
         for (uint32_t k = 12 + rs.flen + tid; k < sec; k += 256) rec[k] = 0;
-        for (uint32_t j = tid; j < rs.nb; j += 256) {
-            const uint32_t info = it.blkinfo[j];
-            rec[sec + 4 + j] = (uint8_t)(info & 0xFF);
-            rec[sec + 4 + rs.nb + j] = (uint8_t)((info >> 8) & 0xFF);
-            rec[sec + 4 + 2 * rs.nb + j] = (uint8_t)((info >> 16) & 0xFF);
+        for (uint32_t j0 = 0; j0 < rs.nb; j0 += 8 * 256) {  // widths, counts and maximum widths
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t j = j0 + u * 256 + tid;
+                v[u] = j < rs.nb ? it.blkinfo[j] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t j = j0 + u * 256 + tid;
+                if (j < rs.nb) {
+                    rec[sec + 4 + j] = (uint8_t)(v[u] & 0xFF);
+                    rec[sec + 4 + rs.nb + j] = (uint8_t)((v[u] >> 8) & 0xFF);
+                    rec[sec + 4 + 2 * rs.nb + j] = (uint8_t)((v[u] >> 16) & 0xFF);
+                }
+            }
         }
         for (uint32_t k = sec + 4 + 3 * rs.nb + tid; k < pay0; k += 256) rec[k] = 0;
         for (uint32_t k = end + tid; k < rs.rec_len; k += 256) rec[k] = 0;
@@ -876,23 +901,47 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
         }
         return;
     }
-    // 64 frames per workgroup, 16 lanes per frame: each frame's payload,
-    // positions and high parts go from its slot to their three places
-    const uint32_t j0 = (blockIdx.x - 1) * kAsmFrames;
-    if (j0 >= rs.nb) return;
-    const uint32_t j1 = min(j0 + kAsmFrames, rs.nb);
+    // 64 frames per workgroup: 16 lanes per frame, each group of 16 lanes
+    // takes four frames; the metadata of the four, then their first 32
+    // payload words, are loaded in one round each.  A frame's payload,
+    // positions and high parts go from its slot to their three places.
+    constexpr int kPer = kAsmFrames / 16;
+    const uint32_t jg = (blockIdx.x - 1) * kAsmFrames + (tid >> 4) * kPer;
+    if (jg >= rs.nb) return;
     const uint32_t l = tid & 15u;
-    for (uint32_t j = j0 + (tid >> 4); j < j1; j += 16) {
-        const uint32_t info = it.blkinfo[j];
-        const uint32_t b = info & 0xFFu, n = (info >> 8) & 0xFFu;
-        const uint32_t op = it.blkoffs[3 * j], on = it.blkoffs[3 * j + 1], oh = it.blkoffs[3 * j + 2];
-        const uint32_t oh1 = j + 1 < rs.nb ? it.blkoffs[3 * (j + 1) + 2] : rs.high;
-        const uint8_t* slot = it.slots + (size_t)j * kSlotBytes;
+    uint32_t info[kPer], op[kPer], on[kPer], oh[kPer], oh1[kPer];
+#pragma unroll
+    for (int f = 0; f < kPer; ++f) {
+        const uint32_t j = jg + f;
+        const bool ok = j < rs.nb;
+        info[f] = ok ? it.blkinfo[j] : 0u;
+        op[f] = ok ? it.blkoffs[3 * j] : 0u;
+        on[f] = ok ? it.blkoffs[3 * j + 1] : 0u;
+        oh[f] = ok ? it.blkoffs[3 * j + 2] : 0u;
+        oh1[f] = j + 1 < rs.nb ? it.blkoffs[3 * (j + 1) + 2] : rs.high;
+    }
+    uint32_t v[kPer][2];
+#pragma unroll
+    for (int f = 0; f < kPer; ++f) {
+        const uint32_t nw = 4u * (info[f] & 0xFFu);
+        const uint32_t* sw = (const uint32_t*)(it.slots + (size_t)(jg + f) * kSlotBytes);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) v[f][u] = l + 16u * u < nw ? sw[l + 16u * u] : 0u;
+    }
+#pragma unroll
+    for (int f = 0; f < kPer; ++f) {
+        if (jg + f >= rs.nb) break;
+        const uint32_t b = info[f] & 0xFFu, n = (info[f] >> 8) & 0xFFu, nw = 4u * b;
+        const uint8_t* slot = it.slots + (size_t)(jg + f) * kSlotBytes;
         const uint32_t* sw = (const uint32_t*)slot;
-        uint32_t* dw = (uint32_t*)(rec + pay0 + op);  // payloads are whole words
-        for (uint32_t w = l; w < 4 * b; w += 16) dw[w] = sw[w];
-        for (uint32_t q = l; q < n; q += 16) rec[pos0 + on + q] = slot[16 * b + q];
-        for (uint32_t q = l; q < oh1 - oh; q += 16) rec[high0 + oh + q] = slot[16 * b + n + q];
+        uint32_t* dw = (uint32_t*)(rec + pay0 + op[f]);  // payloads are whole words
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (l + 16u * u < nw) dw[l + 16u * u] = v[f][u];
+        for (uint32_t w = 32 + l; w < nw; w += 16) dw[w] = sw[w];
+        if (l < n) rec[pos0 + on[f] + l] = slot[16 * b + l];
+        for (uint32_t q = 16 + l; q < n; q += 16) rec[pos0 + on[f] + q] = slot[16 * b + q];
+        for (uint32_t q = l; q < oh1[f] - oh[f]; q += 16) rec[high0 + oh[f] + q] = slot[16 * b + n + q];
     }
 }
 
@@ -921,7 +970,7 @@ hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_enc_scan", k_enc_scan, dim3(plan.n_items), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_enc_tiles", k_enc_tiles, dim3(plan.n_ftiles), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_fixup", k_enc_fixup, dim3(div_up(plan.n_ftiles, 16)), dim3(64), stream, plan);
-    JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(kMfThreads), stream, plan);
     JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_offsets", k_enc_offsets, dim3(1), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_enc_assemble", k_enc_assemble, dim3(plan.max_asm + 1, plan.n_items), dim3(256), stream, plan);
