@@ -131,10 +131,21 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
             break;  // uniform: every thread sees the same ws and flen
         }
         uint32_t wbase, wlen;
-        {  // stage frame bytes [ws, we + 2) with word loads (the record is 4-byte aligned)
+        {  // stage frame bytes [ws, we + 2) with word loads (the record is 4-byte aligned), all issued first
             const uint32_t r0 = (12 + ws) & ~3u, r1 = min(12 + we + 2, L);
             const uint32_t* rw = (const uint32_t*)rec;
-            for (uint32_t w = r0 / 4 + tid; w * 4 < r1; w += 256) P.fwin[w - r0 / 4] = rw[w];
+            constexpr int kIter = (kWin / 4 + 2 + 255) / 256;
+            uint32_t v[kIter];
+#pragma unroll
+            for (int u = 0; u < kIter; ++u) {
+                const uint32_t w = r0 / 4 + tid + 256u * u;
+                v[u] = w * 4 < r1 ? rw[w] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kIter; ++u) {
+                const uint32_t w = r0 / 4 + tid + 256u * u;
+                if (w * 4 < r1) P.fwin[w - r0 / 4] = v[u];
+            }
             wbase = r0 - 12;
             wlen = r1 - r0;
         }
