@@ -340,21 +340,59 @@ void enc_results(const EncLayout& Lo, const uint8_t* hres, EncResult& result) {
     for (uint32_t r = 0; r < Lo.n; ++r) result.modes[r] = (uint8_t)m[r];
 }
 
-int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs, hipStream_t stream,
-               EncResult& result) {
-    const EncLayout Lo = enc_layout(specs, outs);
-    if (grow(ctx.ws, Lo.total) != hipSuccess) return JIFFY_E_DEVICE;
-    if (grow(ctx.up, Lo.up_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
-    if (grow(ctx.res, Lo.res_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
-    uint8_t* dev = (uint8_t*)ctx.ws.p;
-    enc_fill(Lo, specs, outs, dev, (uint8_t*)ctx.up.p);
-    const EncPlan plan = enc_plan(Lo, dev, (uint8_t*)ctx.res.d);
-    if (enc_enqueue(Lo, plan, dev, ctx.up.d, stream) != hipSuccess) return JIFFY_E_DEVICE;
-    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
-    prof_collect();
-    enc_results(Lo, (const uint8_t*)ctx.res.p, result);
+// An encode plan: the layout and the plan image in `up`, valid for the
+// workspace at `ws`.
+struct EncPrepared {
+    bool valid = false;
+    void* ws = nullptr;
+    EncLayout Lo;
+};
+
+int enc_prepare(DevCtx& ctx, HostBuf& up, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs,
+                EncPrepared& P) {
+    P.valid = false;
+    P.Lo = enc_layout(specs, outs);
+    if (grow(ctx.ws, P.Lo.total) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(up, P.Lo.up_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
+    enc_fill(P.Lo, specs, outs, (uint8_t*)ctx.ws.p, (uint8_t*)up.p);
+    P.ws = ctx.ws.p;
+    P.valid = true;
     return JIFFY_OK;
 }
+
+int enc_execute(DevCtx& ctx, const HostBuf& up, const EncPrepared& P, hipStream_t stream, EncResult& result) {
+    if (grow(ctx.res, P.Lo.res_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
+    uint8_t* dev = (uint8_t*)ctx.ws.p;
+    const EncPlan plan = enc_plan(P.Lo, dev, (uint8_t*)ctx.res.d);
+    if (enc_enqueue(P.Lo, plan, dev, up.d, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    prof_collect();
+    enc_results(P.Lo, (const uint8_t*)ctx.res.p, result);
+    return JIFFY_OK;
+}
+
+int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs, hipStream_t stream,
+               EncResult& result) {
+    EncPrepared P;
+    if (int rc = enc_prepare(ctx, ctx.up, specs, outs, P)) return rc;
+    return enc_execute(ctx, ctx.up, P, stream, result);
+}
+
+// The last jiffy_encode's arguments and plan (per device): a call with the
+// same arguments on the same workspace reuses the plan image.
+struct EncKey {
+    jiffy_layout L;
+    uint32_t mode, K, T, pad;
+    const void* planes[JIFFY_MAX_ATTRS];
+    void* out;
+    size_t cap;
+};
+struct EncCache {
+    EncKey key;
+    EncPrepared prep;
+    HostBuf up;
+};
+EncCache g_enc_cache[64];
 
 // ---------------------------------------------------------------------------
 // header parsing (host memory)
@@ -532,6 +570,24 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
         if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
         return JIFFY_OK;
     }
+    EncCache& C = g_enc_cache[dev];
+    EncKey key;
+    memset(&key, 0, sizeof key);
+    key.L = *L;
+    key.mode = mode;
+    key.K = K;
+    key.T = T;
+    for (uint32_t a = 0; a < A; ++a) key.planes[a] = d_planes[a];
+    key.out = d_out;
+    key.cap = cap;
+    EncResult res;
+    if (C.prep.valid && C.prep.ws == ctx.ws.p && memcmp(&key, &C.key, sizeof key) == 0) {
+        if (int rc = enc_execute(ctx, C.up, C.prep, stream, res)) return rc;
+        *h_out_len = res.lens[0];
+        if (!res.ok[0]) return JIFFY_E_CAPACITY;
+        if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
+        return JIFFY_OK;
+    }
     std::vector<EncSpec> specs((size_t)T * A);
     for (uint32_t t = 0; t < T; ++t) {
         for (uint32_t a = 0; a < A; ++a) {
@@ -557,9 +613,9 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
     }
     std::vector<OutSpec> outs(1);
     outs[0] = OutSpec{(uint8_t*)d_out, cap, 0, T * A, header_len(A, T), T, L};
-    EncResult res;
-    int rc = run_encode(ctx, specs, outs, stream, res);
-    if (rc) return rc;
+    if (int rc = enc_prepare(ctx, C.up, specs, outs, C.prep)) return rc;
+    C.key = key;
+    if (int rc = enc_execute(ctx, C.up, C.prep, stream, res)) return rc;
     *h_out_len = res.lens[0];
     if (!res.ok[0]) return JIFFY_E_CAPACITY;
     if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
@@ -602,14 +658,35 @@ namespace {
 // offsets come from the host (roff / rlen) or, with roff null, from the
 // length table after `p` header bytes, indexed on the device (hdr: the
 // expected header bytes to check there, or null when the host has read it).
-int run_decode(DevCtx& ctx, const jiffy_layout& L, uint32_t T, const uint8_t* din, size_t in_len,
-               const uint64_t* roff, const uint32_t* rlen, size_t p, const uint8_t* hdr,
-               void* const* d_planes_out, hipStream_t stream) {
+// A decode plan: the plan image in `up` (uploaded by k_dec_prepare) and the
+// kernels' arguments, valid for the workspace at `ws`.
+struct DecPrepared {
+    bool valid = false;
+    void* ws = nullptr;
+    DecPlan plan;
+    size_t o_err = 0, up_bytes = 0;
+};
+// The last device-indexed decode's arguments and plan (per device): a call
+// with the same arguments on the same workspace reuses the plan image.
+struct DecKey {
+    jiffy_layout L;
+    uint32_t T, hdr_check;
+    const void* din;
+    size_t in_len;
+    void* planes[JIFFY_MAX_ATTRS];
+};
+struct DecCache {
+    DecKey key;
+    DecPrepared prep;
+    HostBuf up;
+};
+DecCache g_dec_cache[64];
+
+int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, const uint8_t* din, size_t in_len,
+                const uint64_t* roff, const uint32_t* rlen, size_t p, const uint8_t* hdr,
+                void* const* d_planes_out, DecPrepared& P) {
+    P.valid = false;
     const uint32_t A = L.n_attrs;
-    if (T == 0) return JIFFY_OK;
-    if (!d_planes_out) return JIFFY_E_INVALID;
-    for (uint32_t a = 0; a < A; ++a)
-        if (!d_planes_out[a] || (uintptr_t)d_planes_out[a] % L.width_bytes[a]) return JIFFY_E_INVALID;
 
     const uint32_t n = T * A;
     const uint32_t npx = L.height * L.width, nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame);
@@ -627,10 +704,9 @@ int run_decode(DevCtx& ctx, const jiffy_layout& L, uint32_t T, const uint8_t* di
     off += per_item * n;
     if (grow(ctx.ws, off) != hipSuccess) return JIFFY_E_DEVICE;
     const size_t up_bytes = up_end - o_err;
-    if (grow(ctx.up, up_bytes) != hipSuccess) return JIFFY_E_DEVICE;
-    if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(upbuf, up_bytes) != hipSuccess) return JIFFY_E_DEVICE;
     uint8_t* dev = (uint8_t*)ctx.ws.p;
-    uint8_t* up = (uint8_t*)ctx.up.p;
+    uint8_t* up = (uint8_t*)upbuf.p;
     memset(up, 0, up_bytes);
     DecItem* hit = (DecItem*)(up + (o_items - o_err));
     bool need_temporal = T > 1;
@@ -710,13 +786,62 @@ int run_decode(DevCtx& ctx, const jiffy_layout& L, uint32_t T, const uint8_t* di
         plan.hdr_check = hdr ? 1u : 0u;
         if (hdr) memcpy(plan.hdr_words, hdr, p);
     }
-    if (launch_dec_prepare(ctx.up.d, dev + o_err, up_bytes, plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
-    if (launch_decode(plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
-    if (hipMemcpyAsync(ctx.down.p, dev + o_err, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    P.plan = plan;
+    P.o_err = o_err;
+    P.up_bytes = up_bytes;
+    P.ws = ctx.ws.p;
+    P.valid = true;
+    return JIFFY_OK;
+}
+
+int dec_execute(DevCtx& ctx, const HostBuf& upbuf, const DecPrepared& P, hipStream_t stream) {
+    uint8_t* dev = (uint8_t*)ctx.ws.p;
+    if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
+    if (launch_dec_prepare(upbuf.d, dev + P.o_err, P.up_bytes, P.plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (launch_decode(P.plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipMemcpyAsync(ctx.down.p, dev + P.o_err, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     prof_collect();
     const uint32_t* errs = (const uint32_t*)ctx.down.p;
     return (errs[0] | errs[1]) ? JIFFY_E_CORRUPT : JIFFY_OK;
+}
+
+// Decodes T scans of layout L from the stream at din (in_len bytes).  Record
+// offsets come from the host (roff / rlen) or, with roff null, from the
+// length table after `p` header bytes, indexed on the device (hdr: the
+// expected header bytes to check there, or null when the host has read it);
+// a device-indexed call with the arguments of the previous one reuses its
+// plan.
+int run_decode(DevCtx& ctx, const jiffy_layout& L, uint32_t T, const uint8_t* din, size_t in_len,
+               const uint64_t* roff, const uint32_t* rlen, size_t p, const uint8_t* hdr,
+               void* const* d_planes_out, hipStream_t stream) {
+    const uint32_t A = L.n_attrs;
+    if (T == 0) return JIFFY_OK;
+    if (!d_planes_out) return JIFFY_E_INVALID;
+    for (uint32_t a = 0; a < A; ++a)
+        if (!d_planes_out[a] || (uintptr_t)d_planes_out[a] % L.width_bytes[a]) return JIFFY_E_INVALID;
+    if (roff) {  // host-walked records: no reuse
+        DecPrepared P;
+        if (int rc = dec_prepare(ctx, ctx.up, L, T, din, in_len, roff, rlen, p, hdr, d_planes_out, P)) return rc;
+        return dec_execute(ctx, ctx.up, P, stream);
+    }
+    DecCache& C = g_dec_cache[&ctx - g_ctx];
+    DecKey key;
+    memset(&key, 0, sizeof key);
+    key.L = L;
+    key.T = T;
+    key.hdr_check = hdr ? 1u : 0u;
+    key.din = din;
+    key.in_len = in_len;
+    for (uint32_t a = 0; a < A; ++a) key.planes[a] = d_planes_out[a];
+    const bool hit = C.prep.valid && C.prep.ws == ctx.ws.p && memcmp(&key, &C.key, sizeof key) == 0 &&
+                     (!hdr || memcmp(C.prep.plan.hdr_words, hdr, p) == 0);
+    if (!hit) {
+        if (int rc = dec_prepare(ctx, C.up, L, T, din, in_len, nullptr, nullptr, p, hdr, d_planes_out, C.prep))
+            return rc;
+        C.key = key;
+    }
+    return dec_execute(ctx, C.up, C.prep, stream);
 }
 }  // namespace
 

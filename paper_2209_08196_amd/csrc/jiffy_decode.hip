@@ -41,7 +41,6 @@ __device__ __forceinline__ uint32_t rd32(const uint8_t* p) {
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSeg = 32;                      // bytes per thread segment of a window
 constexpr uint32_t kSegs = kWin / kSeg;            // 256: one per thread
-constexpr uint32_t kSegsPerChunk = kChunk / kSeg;  // 8
 constexpr uint16_t kXOut = 0xFFFFu;                // the chain leaves the window (a valid position)
 constexpr uint16_t kXBad = 0xFFFEu;                // no valid block header here
 constexpr uint16_t kXLast = 0xFFFDu;               // the last block; it ends the frame exactly

@@ -111,3 +111,34 @@ def test_decode_layout_rejects_mismatched_layouts_and_tables(J):
     assert np.array_equal(to_host(J.decode(_dev(b))[0], 4), ref)
     # and the valid stream still decodes after all of the above
     assert np.array_equal(to_host(J.decode(_dev(s_ref), lay, T)[0], 4), ref)
+
+
+def test_repeated_calls_on_the_same_buffers_see_new_contents(J):
+    """A call with the same arguments as the previous one reuses its plan;
+    the inputs' contents are still read afresh, and a workspace that grew in
+    between (a larger decode) is not reused stale."""
+    import torch
+    g = synth.stream(1, 4)
+    x, y = g.scans(0, 4), g.scans(4, 8)
+    precs = list(g.precisions)
+    lay, T = _layout(J, x, precs)
+    dev = [to_dev(p) for p in x]
+    out = torch.empty(J.encode_bound(lay, T), dtype=torch.uint8, device="cuda")
+    outs = [torch.empty_like(d) for d in dev]
+    big = synth.stream(2, 5).scans(0, 6)
+    s_big, _ = oracle.encode(big, synth.stream(2, 5).precisions)
+    for rnd, data in enumerate((x, y, x, y)):
+        banner("repeat round", rnd)
+        for d, p in zip(dev, data):
+            d.copy_(to_dev(p))
+        s_ref, m_ref = oracle.encode(data, precs)
+        s, m = J.encode(dev, precs, out=out)
+        assert s.cpu().numpy().tobytes() == s_ref, rnd
+        assert np.array_equal(m, m_ref), rnd
+        ref = oracle.decode(s_ref)[0]
+        for _ in range(2):  # the second decode reuses the first one's plan
+            outs[0].zero_()
+            J.decode(s, lay, T, outs=outs)
+            assert np.array_equal(to_host(outs[0], 4), ref), rnd
+        if rnd == 1:  # a larger decode in between grows the workspace
+            J.decode(_dev(s_big))
