@@ -698,7 +698,9 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     const size_t o_items = off; off = al(off + sizeof(DecItem) * n);
     const size_t o_list = off; off = al(off + sizeof(uint32_t) * n);
     const size_t up_end = off;
-    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(4ull * (nft + 1)) + al(8ull * nft) + al(sizeof(DecTile) * nft) + al(4);
+    const uint32_t pwin = div_up(frame_bound(div_up(npx, 8)), kParseWin);
+    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(4ull * (nft + 1)) + al(8ull * nft) +
+                            al(sizeof(DecTile) * nft) + al(4) + al(8ull * (pwin + 1) + 4);
     const size_t o_modes = off; off = al(off + n);
     const size_t o_data = off;
     off += per_item * n;
@@ -731,6 +733,7 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
             it.tdesc = (DecTile*)base;
             base += al(sizeof(DecTile) * nft);
             it.tctr = (uint32_t*)base;
+            base += al(4);
             it.npx = npx;
             it.nwords = nwords;
             it.wb = L.width_bytes[a];
@@ -770,6 +773,9 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     plan.modes = dev + o_modes;
     plan.ws = dev + o_data;
     plan.item_stride = per_item;
+    plan.pwin = pwin;
+    plan.off_pstate = (uint32_t)(al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(4ull * (nft + 1)) + al(8ull * nft) +
+                                 al(sizeof(DecTile) * nft) + al(4));
     plan.off_cw = 0;
     plan.off_vw = (uint32_t)al(8ull * nwords);
     for (uint32_t a = 0; a < A; ++a) {

@@ -27,6 +27,7 @@ constexpr uint32_t kChunk = 256;            // bytes per chunk of the chain stit
 constexpr uint32_t kWinChunks = kWin / kChunk;
 constexpr uint32_t kJInvalid = 0xFFFFFFFFu; // no valid block chain continues here
 constexpr uint32_t kJLast = 0xFFFFFFFEu;    // a last block that ends the frame exactly
+constexpr uint32_t kSpinMax = 1u << 16;     // polls of a workgroup waiting on another before giving up
 
 __device__ __forceinline__ uint32_t rd32(const uint8_t* p) {
     return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
@@ -45,6 +46,7 @@ constexpr uint16_t kXOut = 0xFFFFu;                // the chain leaves the windo
 constexpr uint16_t kXBad = 0xFFFEu;                // no valid block header here
 constexpr uint16_t kXLast = 0xFFFDu;               // the last block; it ends the frame exactly
 static_assert(kWin <= 0xFFF0u && kSegs == 256, "window offsets fit 16 bits; one segment per thread");
+static_assert(kWin == kParseWin, "the host sizes the parse grid with the same window");
 
 __device__ __forceinline__ uint32_t sx(uint32_t i) { return i + ((i >> 5) << 1); }
 
@@ -66,11 +68,35 @@ struct ParseLds {
     uint32_t s_err, s_done, s_next, s_pos, s_flen, s_nblk;
 };
 
+// Window states of a record's mask-frame parse: bit 63 published, bit 62
+// an error before it, bit 61 the frame ended before it; else the first block
+// header at or after the window's start (bits 0..31, a frame offset) and the
+// content bytes before it (bits 32..60).
+constexpr uint64_t kPsPub = 1ull << 63, kPsErr = 1ull << 62, kPsDone = 1ull << 61;
+
+__device__ __forceinline__ JG uint64_t* parse_states(const DecPlan& plan, uint32_t r) {
+    return (JG uint64_t*)(plan.ws + plan.item_stride * r + plan.off_pstate);
+}
+
+// Record header and mask frame.  The frame's blocks start at offset P0 (after
+// the frame header); window w covers frame offsets [P0 + w kWin, P0 + (w+1) kWin)
+// and is parsed by its own workgroup (windows numbered in arrival order, so a
+// window's predecessors have all started).  Each builds its jump tables
+// independently, then waits for the state its predecessor publishes (where
+// the block chain enters the window and how much content came before),
+// follows the chain through the window, publishes the state for the next
+// window, and only then lists and expands its blocks.
 __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, ParseLds& P) {
     const uint8_t* rec = it.rec;
     const uint32_t L = it.rec_len;
     const uint32_t nm = div_up(it.npx, 8);
     const uint32_t tid = threadIdx.x;
+    JG uint64_t* pst = parse_states(plan, r);
+    __shared__ uint32_t s_win;
+    __shared__ uint64_t s_state;
+    if (tid == 0) s_win = atomicAdd((JG uint32_t*)(pst + plan.pwin + 1), 1u);
+    __syncthreads();
+    const uint32_t win = s_win;
     if (tid == 0) {
         uint32_t err = 0;
         const uint32_t mode = rec[4], attr = rec[5];
@@ -101,229 +127,269 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
                 }
             }
         }
+        if (!err && pos + 3 > flen) err = 1;  // no room for a block
         P.s_err = err;
         P.s_pos = pos;
         P.s_done = 0;
         P.s_flen = flen;
-        plan.res[r].mode = mode;
-        plan.res[r].flen = flen;
-        plan.modes[r] = (uint8_t)mode;
+        if (win == 0) {
+            plan.res[r].mode = mode;
+            plan.res[r].flen = flen;
+            plan.modes[r] = (uint8_t)mode;
+        }
     }
     __syncthreads();
     const uint32_t flen = P.s_flen;
     const uint8_t* f = rec + 12;
     const uint8_t* fb = (const uint8_t*)P.fwin;
     uint8_t* cwb = (uint8_t*)it.cw;
+    if (win == 0)  // bytes past the mask content in its last word
+        for (uint32_t i = nm + tid; i < it.nwords * 8u; i += 256) cwb[i] = 0;
+    if (P.s_err) {  // every window sees the header; the first reports it
+        if (win == 0 && tid == 0) atomicOr(plan.err, kErrCorrupt);
+        return;
+    }
+    const uint32_t P0 = P.s_pos;
+    const uint32_t nwin = div_up(flen - P0, kWin);
+    if (nwin > plan.pwin) {  // longer than any frame of this many pixels
+        if (win == 0 && tid == 0) atomicOr(plan.err, kErrCorrupt);
+        return;
+    }
+    if (win >= nwin) return;  // the frame is shorter than the most windows a record can have
+    const uint32_t ws = P0 + win * kWin, we = min(ws + kWin, flen);
+    // publishes the state for the next window (if the frame reaches it)
+    auto publish = [&](uint64_t st) {
+        if (win + 1 < nwin) __hip_atomic_store(pst + win + 1, kPsPub | st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
     // The block headers form a chain: each one gives the position of the
-    // next.  The frame is taken in windows of kWin positions.  Every thread
-    // owns a 32-byte segment: walking it backwards it finds, for each
-    // position, where a chain through that position leaves the segment; a
-    // few rounds of pointer jumping turn that into where it leaves the
-    // 256-byte chunk.  One lane then follows the true chain from chunk to
-    // chunk, 32 lanes from segment to segment inside their chunk, and every
-    // lane walks its own segment to list the blocks; all lanes expand them.
-    uint32_t ws = P.s_pos, content = 0;
-    while (!P.s_err && !P.s_done) {
-        const uint32_t we = min(ws + kWin, flen);
-        if (ws >= flen) {  // a header must start here: the chain ran off the frame
-            if (tid == 0) P.s_err = 1;
-            break;  // uniform: every thread sees the same ws and flen
-        }
-        uint32_t wbase, wlen;
-        {  // stage frame bytes [ws, we + 2) with word loads (the record is 4-byte aligned), all issued first
-            const uint32_t r0 = (12 + ws) & ~3u, r1 = min(12 + we + 2, L);
-            const uint32_t* rw = (const uint32_t*)rec;
-            constexpr int kIter = (kWin / 4 + 2 + 255) / 256;
-            uint32_t v[kIter];
+    // next.  Every thread owns a 32-byte segment of the window: walking it
+    // backwards it finds, for each position, where a chain through that
+    // position leaves the segment; a few rounds of pointer jumping turn that
+    // into where it leaves the 256-byte chunk.  One lane then follows the
+    // true chain from chunk to chunk, 32 lanes from segment to segment inside
+    // their chunk, and every lane walks its own segment to list the blocks;
+    // all lanes expand them.
+    uint32_t wbase, wlen;
+    {  // stage frame bytes [ws, we + 2) with word loads (the record is 4-byte aligned), all issued first
+        const uint32_t r0 = (12 + ws) & ~3u, r1 = min(12 + we + 2, L);
+        const uint32_t* rw = (const uint32_t*)rec;
+        constexpr int kIter = (kWin / 4 + 2 + 255) / 256;
+        uint32_t v[kIter];
 #pragma unroll
-            for (int u = 0; u < kIter; ++u) {
-                const uint32_t w = r0 / 4 + tid + 256u * u;
-                v[u] = w * 4 < r1 ? rw[w] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < kIter; ++u) {
-                const uint32_t w = r0 / 4 + tid + 256u * u;
-                if (w * 4 < r1) P.fwin[w - r0 / 4] = v[u];
-            }
-            wbase = r0 - 12;
-            wlen = r1 - r0;
+        for (int u = 0; u < kIter; ++u) {
+            const uint32_t q = r0 / 4 + tid + 256u * u;
+            v[u] = q * 4 < r1 ? rw[q] : 0u;
         }
-        // the block that would start at frame offset i: its next position,
-        // and its content size and type
-        auto header = [&](uint32_t i, uint32_t& size, uint32_t& rle) -> uint32_t {
-            if (i + 3 > flen) return kJInvalid;
-            const uint8_t* hp = fb + (i - wbase);
-            const uint32_t h = (uint32_t)hp[0] | ((uint32_t)hp[1] << 8) | ((uint32_t)hp[2] << 16);
-            const uint32_t last = h & 1, type = (h >> 1) & 3;
-            size = h >> 3;
-            rle = type;
-            if (type > 1 || size > kZstdBlockMax) return kJInvalid;
-            const uint32_t n = i + 3 + (type ? 1u : size);
-            if (last) return n == flen ? kJLast : kJInvalid;
-            return n < flen ? n : kJInvalid;
-        };
-        auto code = [&](uint32_t n) -> uint16_t {  // a next position as a window offset or a mark
-            if (n == kJInvalid) return kXBad;
-            if (n == kJLast) return kXLast;
-            return n >= we ? kXOut : (uint16_t)(n - ws);
-        };
+#pragma unroll
+        for (int u = 0; u < kIter; ++u) {
+            const uint32_t q = r0 / 4 + tid + 256u * u;
+            if (q * 4 < r1) P.fwin[q - r0 / 4] = v[u];
+        }
+        wbase = r0 - 12;
+        wlen = r1 - r0;
+    }
+    auto header = [&](uint32_t i, uint32_t& size, uint32_t& rle) -> uint32_t {
+        if (i + 3 > flen) return kJInvalid;
+        const uint8_t* hp = fb + (i - wbase);
+        const uint32_t h = (uint32_t)hp[0] | ((uint32_t)hp[1] << 8) | ((uint32_t)hp[2] << 16);
+        const uint32_t last = h & 1, type = (h >> 1) & 3;
+        size = h >> 3;
+        rle = type;
+        if (type > 1 || size > kZstdBlockMax) return kJInvalid;
+        const uint32_t n = i + 3 + (type ? 1u : size);
+        if (last) return n == flen ? kJLast : kJInvalid;
+        return n < flen ? n : kJInvalid;
+    };
+    auto code = [&](uint32_t n) -> uint16_t {  // a next position as a window offset or a mark
+        if (n == kJInvalid) return kXBad;
+        if (n == kJLast) return kXLast;
+        return n >= we ? kXOut : (uint16_t)(n - ws);
+    };
+    __syncthreads();
+    const uint32_t s0 = ws + tid * kSeg, s1 = min(s0 + kSeg, we);
+    {
+        // this segment's 32 bytes and the two after it, aligned to the segment start
+        const uint32_t a = ws - wbase;  // 0..3: the window's first byte within fwin's first word
+        uint32_t w[10], u[9];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) w[k] = P.fwin[8 * tid + k];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) u[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], a);
+        // backwards over the segment: where a chain through each position leaves it
+#pragma unroll
+        for (int j = kSeg - 1; j >= 0; --j) {
+            const uint32_t i = s0 + j;
+            if (i < s1) {
+                const uint32_t h = (uint32_t)(((((uint64_t)u[(j >> 2) + 1]) << 32) | u[j >> 2]) >> (8 * (j & 3))) &
+                                   0xFFFFFFu;
+                const uint32_t last = h & 1, type = (h >> 1) & 3, size = h >> 3;
+                uint32_t n = i + 3 + (type ? 1u : size);
+                if (i + 3 > flen || type > 1 || size > kZstdBlockMax) n = kJInvalid;
+                else if (last) n = n == flen ? kJLast : kJInvalid;
+                else if (n >= flen) n = kJInvalid;
+                const uint16_t c = code(n);
+                const uint16_t x = (c >= kXLast || n >= s1) ? c : P.u.x.X[sx(n - ws)];
+                P.u.x.X[sx(i - ws)] = x;
+                P.u.x.Y[sx(i - ws)] = x;
+            }
+        }
+    }
+    __syncthreads();
+    // each step spans a segment at least, so three doublings reach the chunk's end;
+    // a thread reads all its 32 positions' next steps before it writes (positions
+    // updated by others in between are still on the same path)
+    for (int round = 0; round < 3; ++round) {
+        uint32_t y[kWin / 256];
+#pragma unroll
+        for (int k = 0; k < (int)(kWin / 256); ++k) {
+            const uint32_t i = tid + 256u * k;
+            y[k] = ws + i < we ? P.u.x.Y[sx(i)] : kXBad;
+        }
+#pragma unroll
+        for (int k = 0; k < (int)(kWin / 256); ++k) {
+            const uint32_t i = tid + 256u * k;
+            y[k] = (y[k] < kXLast && y[k] / kChunk == i / kChunk) ? P.u.x.Y[sx(y[k])] : 0x10000u;
+        }
+#pragma unroll
+        for (int k = 0; k < (int)(kWin / 256); ++k)
+            if (y[k] != 0x10000u) P.u.x.Y[sx(tid + 256u * k)] = (uint16_t)y[k];
         __syncthreads();
-        const uint32_t s0 = ws + tid * kSeg, s1 = min(s0 + kSeg, we);
-        {
-            // this segment's 32 bytes and the two after it, aligned to the segment start
-            const uint32_t a = ws - wbase;  // 0..3: the window's first byte within fwin's first word
-            uint32_t w[10], u[9];
-#pragma unroll
-            for (int k = 0; k < 10; ++k) w[k] = P.fwin[8 * tid + k];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) u[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], a);
-            // backwards over the segment: where a chain through each position leaves it
-#pragma unroll
-            for (int j = kSeg - 1; j >= 0; --j) {
-                const uint32_t i = s0 + j;
-                if (i < s1) {
-                    const uint32_t h = (uint32_t)(((((uint64_t)u[(j >> 2) + 1]) << 32) | u[j >> 2]) >> (8 * (j & 3))) &
-                                       0xFFFFFFu;
-                    const uint32_t last = h & 1, type = (h >> 1) & 3, size = h >> 3;
-                    uint32_t n = i + 3 + (type ? 1u : size);
-                    if (i + 3 > flen || type > 1 || size > kZstdBlockMax) n = kJInvalid;
-                    else if (last) n = n == flen ? kJLast : kJInvalid;
-                    else if (n >= flen) n = kJInvalid;
-                    const uint16_t c = code(n);
-                    const uint16_t x = (c >= kXLast || n >= s1) ? c : P.u.x.X[sx(n - ws)];
-                    P.u.x.X[sx(i - ws)] = x;
-                    P.u.x.Y[sx(i - ws)] = x;
+    }
+    // where the chain enters this window, and the content before it
+    if (tid == 0) {
+        uint64_t st = kPsPub | P0;  // window 0: the first block, no content before it
+        if (win > 0) {
+            uint32_t spins = 0;
+            for (;;) {
+                st = __hip_atomic_load(pst + win, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (st & kPsPub) break;
+                if (++spins > kSpinMax) {  // never expected: the previous window did not publish
+                    st = kPsPub | kPsErr;
+                    atomicOr(plan.err, kErrCorrupt);
+                    break;
                 }
+                __builtin_amdgcn_s_sleep(1);
             }
         }
-        __syncthreads();
-        // each step spans a segment at least, so three doublings reach the chunk's end;
-        // a thread reads all its 32 positions' next steps before it writes (positions
-        // updated by others in between are still on the same path)
-        for (int round = 0; round < 3; ++round) {
-            uint32_t y[kWin / 256];
-#pragma unroll
-            for (int k = 0; k < (int)(kWin / 256); ++k) {
-                const uint32_t i = tid + 256u * k;
-                y[k] = ws + i < we ? P.u.x.Y[sx(i)] : kXBad;
-            }
-#pragma unroll
-            for (int k = 0; k < (int)(kWin / 256); ++k) {
-                const uint32_t i = tid + 256u * k;
-                y[k] = (y[k] < kXLast && y[k] / kChunk == i / kChunk) ? P.u.x.Y[sx(y[k])] : 0x10000u;
-            }
-#pragma unroll
-            for (int k = 0; k < (int)(kWin / 256); ++k)
-                if (y[k] != 0x10000u) P.u.x.Y[sx(tid + 256u * k)] = (uint16_t)y[k];
-            __syncthreads();
+        s_state = st;
+    }
+    __syncthreads();
+    const uint64_t st_in = s_state;
+    const uint32_t entry = (uint32_t)st_in, content = (uint32_t)(st_in >> 32) & 0x1FFFFFFFu;
+    if ((st_in & (kPsErr | kPsDone)) || entry >= we) {  // nothing of the chain here: pass the state on
+        if (tid == 0) publish(st_in & ~kPsPub);
+        return;
+    }
+    // the true chain: chunk entries (one lane), then segment entries (a lane per chunk)
+    if (tid < kWinChunks) P.c_entry[tid] = kXBad;
+    P.seg_entry[tid] = kXBad;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t e = entry - ws;
+        while (e < kXLast) {
+            P.c_entry[e / kChunk] = (uint16_t)e;
+            e = P.u.x.Y[sx(e)];
         }
-        // the true chain: chunk entries (one lane), then segment entries (a lane per chunk)
-        if (tid < kWinChunks) P.c_entry[tid] = kXBad;
-        P.seg_entry[tid] = kXBad;
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t e = 0;
-            while (e < kXLast) {
-                P.c_entry[e / kChunk] = (uint16_t)e;
-                e = P.u.x.Y[sx(e)];
-            }
+    }
+    __syncthreads();
+    if (tid < kWinChunks) {
+        for (uint32_t e = P.c_entry[tid]; e < kXLast && e / kChunk == tid;) {
+            P.seg_entry[e / kSeg] = (uint16_t)e;
+            e = P.u.x.X[sx(e)];
         }
-        __syncthreads();
-        if (tid < kWinChunks) {
-            for (uint32_t e = P.c_entry[tid]; e < kXLast && e / kChunk == tid;) {
-                P.seg_entry[e / kSeg] = (uint16_t)e;
-                e = P.u.x.X[sx(e)];
-            }
+    }
+    __syncthreads();
+    // every lane: the blocks that start in its segment
+    uint32_t cnt = 0, csz = 0, exit_n = 0, has_exit = 0;
+    for (uint32_t e = P.seg_entry[tid]; e < kXLast && e / kSeg == tid;) {
+        uint32_t size, rle;
+        const uint32_t n = header(ws + e, size, rle);
+        cnt++;
+        csz += size;
+        if (n >= we) {  // the chain leaves the window (or the frame ends) after this block
+            exit_n = n;
+            has_exit = 1;
+            break;
         }
-        __syncthreads();
-        // every lane: the blocks that start in its segment
-        uint32_t cnt = 0, csz = 0, exit_n = 0, has_exit = 0;
+        e = n - ws;
+    }
+    uint32_t nblk, ctot;
+    const uint32_t boff = block_excl_scan<256>(cnt, P.scratch, &nblk);
+    const uint32_t coff = content + block_excl_scan<256>(csz, P.scratch, &ctot);
+    if (has_exit) {
+        if (exit_n == kJInvalid) P.s_err = 1;
+        else if (exit_n == kJLast) P.s_done = 1;
+        else P.s_next = exit_n;
+    }
+    if (tid == 0 && (nblk == 0 || content + ctot > nm)) P.s_err = 1;
+    // the block table (the jump tables are no longer needed)
+    {
+        uint32_t k = boff, d = coff;
         for (uint32_t e = P.seg_entry[tid]; e < kXLast && e / kSeg == tid;) {
             uint32_t size, rle;
             const uint32_t n = header(ws + e, size, rle);
-            cnt++;
-            csz += size;
-            if (n >= we) {  // the chain leaves the window (or the frame ends) after this block
-                exit_n = n;
-                has_exit = 1;
-                break;
-            }
+            P.u.t.dst[k] = d;
+            P.u.t.src[k] = (ws + e + 3) | (rle << 31);
+            k++;
+            d += size;
+            if (n >= we) break;
             e = n - ws;
         }
-        uint32_t nblk, ctot;
-        const uint32_t boff = block_excl_scan<256>(cnt, P.scratch, &nblk);
-        const uint32_t coff = content + block_excl_scan<256>(csz, P.scratch, &ctot);
-        if (has_exit) {
-            if (exit_n == kJInvalid) P.s_err = 1;
-            else if (exit_n == kJLast) P.s_done = 1;
-            else P.s_next = exit_n;
+    }
+    if (tid == 0) P.u.t.dst[nblk] = content + ctot;
+    __syncthreads();
+    if (tid == 0) {  // the next window's state, before this one's expansion
+        uint64_t st;
+        if (P.s_err) st = kPsErr;
+        else if (P.s_done) st = kPsDone;
+        else st = P.s_next | ((uint64_t)(content + ctot) << 32);
+        if (!P.s_err && P.s_done && content + ctot != nm) {
+            P.s_err = 1;
+            st = kPsErr;
         }
-        if (tid == 0 && (nblk == 0 || content + ctot > nm)) P.s_err = 1;
-        // the block table (the jump tables are no longer needed)
-        {
-            uint32_t k = boff, d = coff;
-            for (uint32_t e = P.seg_entry[tid]; e < kXLast && e / kSeg == tid;) {
-                uint32_t size, rle;
-                const uint32_t n = header(ws + e, size, rle);
-                P.u.t.dst[k] = d;
-                P.u.t.src[k] = (ws + e + 3) | (rle << 31);
-                k++;
-                d += size;
-                if (n >= we) break;
-                e = n - ws;
-            }
-        }
-        if (tid == 0) P.u.t.dst[nblk] = content + ctot;
-        __syncthreads();
-        if (P.s_err) break;
-        // expansion: each thread writes a contiguous run of content words,
-        // finding its first block by binary search and walking on from there
-        const uint32_t d0 = content, d1 = content + ctot;
-        const uint32_t q0 = d0 & ~3u, nw = (d1 - q0 + 3) / 4, per = (nw + 255) / 256;
-        const uint32_t qa = q0 + 4 * per * tid, qb = min(q0 + 4 * per * (tid + 1), d1);
-        if (qa < qb) {
-            const uint32_t first = qa < d0 ? d0 : qa;
-            uint32_t lo = 0, hi = nblk - 1;  // the largest k with dst[k] <= first
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (P.u.t.dst[mid] <= first) lo = mid; else hi = mid - 1;
-            }
-            // the current block: content [bstart, bend), frame source, RLE byte
-            uint32_t k = lo, bstart = P.u.t.dst[k], bend = P.u.t.dst[k + 1], bsrc = P.u.t.src[k];
-            auto byte_at = [&](uint32_t sb) -> uint32_t { return sb - wbase < wlen ? fb[sb - wbase] : f[sb]; };
-            uint32_t rv = byte_at(bsrc & 0x7FFFFFFFu);
-            for (uint32_t q = qa; q < qb; q += 4) {
-                uint32_t word = 0, full = 1;
-#pragma unroll
-                for (uint32_t b = 0; b < 4; ++b) {
-                    const uint32_t d = q + b;
-                    if (d < d0 || d >= d1) { full = 0; continue; }
-                    while (d >= bend) {  // the next block
-                        ++k;
-                        bstart = bend;
-                        bend = P.u.t.dst[k + 1];
-                        bsrc = P.u.t.src[k];
-                        rv = byte_at(bsrc & 0x7FFFFFFFu);
-                    }
-                    const uint32_t v = (bsrc >> 31) ? rv : byte_at((bsrc & 0x7FFFFFFFu) + (d - bstart));
-                    word |= v << (8 * b);
-                }
-                if (full) *(uint32_t*)(cwb + q) = word;
-                else
-                    for (uint32_t b = 0; b < 4; ++b)
-                        if (q + b >= d0 && q + b < d1) cwb[q + b] = (uint8_t)(word >> (8 * b));
-            }
-        }
-        content = d1;
-        ws = P.s_next;
-        __syncthreads();
+        publish(st);
+        if (P.s_err) atomicOr(plan.err, kErrCorrupt);
     }
     __syncthreads();
-    if (tid == 0 && !P.s_err && content != nm) P.s_err = 1;
-    // bytes past the mask content in its last word
-    for (uint32_t i = nm + tid; i < it.nwords * 8u; i += 256) cwb[i] = 0;
-    __syncthreads();
-    if (tid == 0 && P.s_err) atomicOr(plan.err, kErrCorrupt);
+    if (P.s_err) return;
+    // expansion: each thread writes a contiguous run of content words,
+    // finding its first block by binary search and walking on from there
+    const uint32_t d0 = content, d1 = content + ctot;
+    const uint32_t q0 = d0 & ~3u, nw = (d1 - q0 + 3) / 4, per = (nw + 255) / 256;
+    const uint32_t qa = q0 + 4 * per * tid, qb = min(q0 + 4 * per * (tid + 1), d1);
+    if (qa < qb) {
+        const uint32_t first = qa < d0 ? d0 : qa;
+        uint32_t lo = 0, hi = nblk - 1;  // the largest k with dst[k] <= first
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (P.u.t.dst[mid] <= first) lo = mid; else hi = mid - 1;
+        }
+        // the current block: content [bstart, bend), frame source, RLE byte
+        uint32_t k = lo, bstart = P.u.t.dst[k], bend = P.u.t.dst[k + 1], bsrc = P.u.t.src[k];
+        auto byte_at = [&](uint32_t sb) -> uint32_t { return sb - wbase < wlen ? fb[sb - wbase] : f[sb]; };
+        uint32_t rv = byte_at(bsrc & 0x7FFFFFFFu);
+        for (uint32_t q = qa; q < qb; q += 4) {
+            uint32_t word = 0, full = 1;
+#pragma unroll
+            for (uint32_t b = 0; b < 4; ++b) {
+                const uint32_t d = q + b;
+                if (d < d0 || d >= d1) { full = 0; continue; }
+                while (d >= bend) {  // the next block
+                    ++k;
+                    bstart = bend;
+                    bend = P.u.t.dst[k + 1];
+                    bsrc = P.u.t.src[k];
+                    rv = byte_at(bsrc & 0x7FFFFFFFu);
+                }
+                const uint32_t v = (bsrc >> 31) ? rv : byte_at((bsrc & 0x7FFFFFFFu) + (d - bstart));
+                word |= v << (8 * b);
+            }
+            if (full) *(uint32_t*)(cwb + q) = word;
+            else
+                for (uint32_t b = 0; b < 4; ++b)
+                    if (q + b >= d0 && q + b < d1) cwb[q + b] = (uint8_t)(word >> (8 * b));
+        }
+    }
 }
 
 __device__ void parse_sections(const DecPlan& plan, uint32_t r, const DecItem& it, ParseLds& P) {
@@ -403,34 +469,46 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
     if (plan.roff) {  // the record from the device-side index; later kernels find it in the item
         const uint64_t o = plan.roff[r];
         if (o == ~0ull) {
-            if (threadIdx.x == 0 && blockIdx.y == 0) atomicOr(plan.err, kErrCorrupt);
+            if (threadIdx.x == 0 && blockIdx.y == plan.pwin) atomicOr(plan.err, kErrCorrupt);
             return;
         }
         it.rec = plan.src + o;
         it.rec_len = plan.tab[r];
-        if (threadIdx.x == 0 && blockIdx.y == 0) {
+        if (threadIdx.x == 0 && blockIdx.y == plan.pwin) {
             plan.items[r].rec = it.rec;
             plan.items[r].rec_len = it.rec_len;
         }
     }
-    if (blockIdx.y == 0) parse_mask(plan, r, it, P);
+    if (blockIdx.y < plan.pwin) parse_mask(plan, r, it, P);
     else parse_sections(plan, r, it, P);
 }
 
 // ---------------------------------------------------------------------------
 // Plan upload (blocks before the last, 16 bytes per thread from host-mapped
-// memory) and record index (the last block): the stream header must equal
-// the expected one, every table length must be a multiple of 4 of at least
-// 12 bytes, and the records must end exactly at the end of the stream;
+// memory).  The last block clears the records' parse window states and, with
+// a device-side index, indexes the records: the stream header must equal the
+// expected one, every table length must be a multiple of 4 of at least 12
+// bytes, and the records must end exactly at the end of the stream;
 // otherwise every record offset is ~0.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_dec_prepare(const uint4* src, uint4* dst, uint32_t n16, DecPlan plan) {
     const uint32_t tid = threadIdx.x;
-    if (blockIdx.x + 1 < gridDim.x || !plan.roff) {
+    if (blockIdx.x + 1 < gridDim.x) {
         const uint32_t i = blockIdx.x * 256 + tid;
         if (i < n16) ((JG uint4*)dst)[i] = load_system16((const JG uint4*)src + i);
         return;
     }
+    // every record's parse window states and window ticket start at zero
+    {
+        const uint32_t per = plan.pwin + 2;  // pwin + 1 states, then the ticket word
+        for (uint32_t i = tid; i < plan.n_items * per; i += 256) {
+            const uint32_t r = i / per, k = i - r * per;
+            JG uint64_t* st = parse_states(plan, r);
+            if (k <= plan.pwin) st[k] = 0;
+            else *(JG uint32_t*)(st + k) = 0u;
+        }
+    }
+    if (!plan.roff) return;
     __shared__ uint64_t scratch[8];
     __shared__ uint32_t s_bad;
     if (tid == 0) s_bad = 0;
@@ -455,8 +533,7 @@ __global__ __launch_bounds__(256) void k_dec_prepare(const uint4* src, uint4* ds
 
 hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const DecPlan& plan, hipStream_t stream) {
     const uint32_t n16 = (uint32_t)(bytes / 16);
-    const uint32_t blocks = div_up(n16, 256) + (plan.roff ? 1u : 0u);
-    if (blocks == 0) return hipSuccess;
+    const uint32_t blocks = div_up(n16, 256) + 1;  // the last one clears the parse states (and indexes)
     JIFFY_LAUNCH("k_dec_prepare", k_dec_prepare, dim3(blocks), dim3(256), stream, (const uint4*)host, (uint4*)dev,
                  n16, plan);
     return hipGetLastError();
@@ -586,7 +663,6 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
 // k_dec_temporal); for P > 1 they are quantized (restored there too).
 // ---------------------------------------------------------------------------
 constexpr uint64_t kStAgg = 1ull << 32, kStIncl = 2ull << 32;  // look-back status flags
-constexpr uint32_t kSpinMax = 1u << 16;                // look-back polls before giving up
 
 template <class R>
 struct DecTileLds {
@@ -926,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
 
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
-    JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items, 2), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items, plan.pwin + 1), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(plan.nwords, 64), plan.n_attrs), dim3(64), stream, plan);
     JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
     if (plan.n_wide)

@@ -29,6 +29,7 @@ constexpr uint32_t kGroupFrames = 16;       // frames per group of the per-recor
 constexpr uint32_t kAsmFrames = 64;         // frames copied into the stream by one workgroup
 constexpr uint32_t kZstdBlockMax = 131072;  // largest Zstandard block (RFC 8878)
 constexpr uint32_t kRleMinRun = 8;          // runs this long become RLE blocks
+constexpr uint32_t kParseWin = 8192;        // mask-frame bytes per parsing window (one workgroup each)
 
 // Error bits raised by kernels (ORed into a device word).
 enum : uint32_t { kErrCorrupt = 1u, kErrCapacity = 2u };
@@ -188,6 +189,9 @@ struct DecPlan {
     const JG uint32_t* rec_list; // the records with 32-bit samples, then the others
     uint32_t n_wide;          // how many have 32-bit samples
     uint32_t need_temporal;   // per-pixel pass over time needed
+    uint32_t pwin;            // mask-frame windows per record (parse workgroups), at most
+    uint32_t off_pstate;      // offset in a record's workspace of its window states ([pwin + 1] u64,
+                              // then the window ticket counter)
     // Record index built on the device (null roff: the host filled rec / rec_len):
     // the length table at `tab`, records from `tab + n_items`, the stream `src_len`
     // bytes long; roff[r] = byte offset of record r, or ~0 when the index is bad.
@@ -203,8 +207,9 @@ struct DecPlan {
 };
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream);
 
-// Upload of the decode plan (as launch_copy_in) and, when plan.roff is set,
-// the device-side record index, in one launch.
+// Upload of the decode plan (as launch_copy_in), clearing of the parse
+// window states and, when plan.roff is set, the device-side record index, in
+// one launch.
 hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const DecPlan& plan, hipStream_t stream);
 
 }  // namespace jiffy
