@@ -34,11 +34,11 @@ __device__ __forceinline__ uint32_t rd32(const uint8_t* p) {
 }
 
 // ---------------------------------------------------------------------------
-// Record parse.  blockIdx.y = 0: the record header and the mask frame (Raw
-// and RLE blocks) into mask bytes; blockIdx.y = 1: the residual section
-// header into per-frame widths and section offsets.  The two parts of a
-// record are independent (the section starts after the mask frame, whose
-// length is in the record header).
+// Record parse.  blockIdx.y < pwin: the record header and one 8 KiB window
+// of the mask frame (Raw and RLE blocks) into mask bytes; blockIdx.y = pwin:
+// the residual section header into per-frame widths and section offsets.
+// The two parts of a record are independent (the section starts after the
+// mask frame, whose length is in the record header).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSeg = 32;                      // bytes per thread segment of a window
 constexpr uint32_t kSegs = kWin / kSeg;            // 256: one per thread
