@@ -137,6 +137,7 @@ struct OutSpec {
 };
 
 struct EncResult {
+    uint32_t err = 0;
     std::vector<uint64_t> lens;
     std::vector<uint8_t> ok;
     std::vector<uint8_t> modes;
@@ -146,14 +147,14 @@ struct EncResult {
 // workspace: [res][err][outs][items][tile maps] (the part uploaded from the
 // host, from `err` on) then per record its buffers.
 struct EncLayout {
-    uint32_t n = 0, no = 0, n_tiles = 0, n_ftiles = 0, max_groups = 1, max_asm = 1;
-    uint32_t tpi = 0, ftpi = 0;  // tiles per record when all records have the same size (no tile maps)
-    std::vector<uint32_t> tile_first, ftile_first;
-    size_t o_res = 0, o_err = 0, o_outs = 0, o_items = 0, o_tfirst = 0, o_titem = 0, o_ftfirst = 0, o_ftitem = 0;
+    uint32_t n = 0, no = 0, n_ftiles = 0, max_groups = 1, max_asm = 1;
+    uint32_t ftpi = 0;  // tiles per record when all records have the same size (no tile maps)
+    std::vector<uint32_t> ftile_first;
+    size_t o_res = 0, o_err = 0, o_outs = 0, o_items = 0, o_ftfirst = 0, o_ftitem = 0;
     size_t up_end = 0, total = 0;
     std::vector<size_t> o_vw, o_blk, o_slots, o_frame, o_segs;
     size_t up_bytes() const { return up_end - o_err; }
-    size_t res_bytes() const { return 16ull * no + 4ull * n; }  // host results: per output len/ok, per record mode
+    size_t res_bytes() const { return 16ull * no + 4ull * n + 4; }  // host results: per output len/ok, modes, error
 };
 
 EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs) {
@@ -161,13 +162,10 @@ EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpe
     const uint32_t n = (uint32_t)specs.size(), no = (uint32_t)outs.size();
     Lo.n = n;
     Lo.no = no;
-    Lo.tile_first.resize(n);
     Lo.ftile_first.resize(n);
     for (uint32_t r = 0; r < n; ++r) {
-        Lo.tile_first[r] = Lo.n_tiles;
         Lo.ftile_first[r] = Lo.n_ftiles;
         const uint32_t npx = specs[r].H * specs[r].W;
-        Lo.n_tiles += div_up(npx, kTilePx);
         Lo.n_ftiles += div_up(npx, kFTile);
         const uint32_t groups = div_up(div_up(npx, kFrame), kGroupFrames);
         if (groups > Lo.max_groups) Lo.max_groups = groups;
@@ -178,17 +176,14 @@ EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpe
     for (uint32_t r = 1; r < n; ++r)
         if (specs[r].H * specs[r].W != specs[0].H * specs[0].W) uniform = false;
     if (n && uniform) {
-        Lo.tpi = div_up(specs[0].H * specs[0].W, kTilePx);
         Lo.ftpi = div_up(specs[0].H * specs[0].W, kFTile);
     }
-    const uint32_t n_maps = Lo.tpi ? 0u : n, n_tmap = Lo.tpi ? 0u : Lo.n_tiles, n_ftmap = Lo.tpi ? 0u : Lo.n_ftiles;
+    const uint32_t n_maps = Lo.ftpi ? 0u : n, n_ftmap = Lo.ftpi ? 0u : Lo.n_ftiles;
     size_t off = 0;
     Lo.o_res = off; off = al(off + sizeof(EncRes) * n);
     Lo.o_err = off; off = al(off + sizeof(uint32_t));
     Lo.o_outs = off; off = al(off + sizeof(EncOut) * no);
     Lo.o_items = off; off = al(off + sizeof(EncItem) * n);
-    Lo.o_tfirst = off; off = al(off + sizeof(uint32_t) * n_maps);
-    Lo.o_titem = off; off = al(off + sizeof(uint32_t) * n_tmap);
     Lo.o_ftfirst = off; off = al(off + sizeof(uint32_t) * n_maps);
     Lo.o_ftitem = off; off = al(off + sizeof(uint32_t) * n_ftmap);
     Lo.up_end = off;
@@ -197,7 +192,7 @@ EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpe
         const uint32_t npx = specs[r].H * specs[r].W;
         const uint32_t nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame), nm = div_up(npx, 8);
         Lo.o_vw[r] = off; off = al(off + (specs[r].vw_fixed ? 0 : 8ull * nwords));
-        Lo.o_blk[r] = off; off = al(off + 4ull * maxnb * 4 + 12ull * div_up(npx, kFTile));
+        Lo.o_blk[r] = off; off = al(off + 4ull * maxnb * 4 + 4ull * div_up(npx, kFTile)) + al(8ull * div_up(npx, kFTile) + 4);
         Lo.o_slots[r] = off; off = al(off + (size_t)kSlotBytes * maxnb);
         Lo.o_frame[r] = off; off = al(off + frame_bound(nm));
         Lo.o_segs[r] = off; off = al(off + 8ull * (nm / 4 + 4));
@@ -249,9 +244,9 @@ void enc_fill(const EncLayout& Lo, const std::vector<EncSpec>& specs, const std:
         const uint32_t nft = div_up(npx, kFTile);
         it.blkinfo = blk;
         it.blkoffs = blk + maxnb;
-        it.tbase = blk + 4 * maxnb;
-        it.tpred = it.tbase + nft;
-        it.tfix = it.tpred + nft;
+        it.tfix = blk + 4 * maxnb;
+        it.tstat = (uint64_t*)(dev + Lo.o_blk[r] + al(4ull * maxnb * 4 + 4ull * nft));
+        it.tctr = (uint32_t*)(it.tstat + nft);
         it.ntiles = nft;
         it.slots = dev + Lo.o_slots[r];
         it.frame = dev + Lo.o_frame[r];
@@ -277,15 +272,11 @@ void enc_fill(const EncLayout& Lo, const std::vector<EncSpec>& specs, const std:
                     (!s.qout || (uintptr_t)s.qout % 16 == 0);
         it.aligned16 = al16 ? 1u : 0u;
     }
-    if (Lo.tpi) return;  // tiles are found by division
-    uint32_t* htf = (uint32_t*)U(Lo.o_tfirst);
-    uint32_t* hti = (uint32_t*)U(Lo.o_titem);
+    if (Lo.ftpi) return;  // tiles are found by division
     uint32_t* hftf = (uint32_t*)U(Lo.o_ftfirst);
     uint32_t* hfti = (uint32_t*)U(Lo.o_ftitem);
     for (uint32_t r = 0; r < n; ++r) {
         const uint32_t npx = specs[r].H * specs[r].W;
-        htf[r] = Lo.tile_first[r];
-        for (uint32_t k = 0, nt = div_up(npx, kTilePx); k < nt; ++k) hti[Lo.tile_first[r] + k] = r;
         hftf[r] = Lo.ftile_first[r];
         for (uint32_t k = 0, nt = div_up(npx, kFTile); k < nt; ++k) hfti[Lo.ftile_first[r] + k] = r;
     }
@@ -294,20 +285,16 @@ void enc_fill(const EncLayout& Lo, const std::vector<EncSpec>& specs, const std:
 EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev, uint8_t* host_res) {
     EncPlan plan;
     plan.host_res = host_res;
-    plan.tpi = Lo.tpi;
     plan.ftpi = Lo.ftpi;
     plan.items = (const EncItem*)(dev + Lo.o_items);
     plan.res = (EncRes*)(dev + Lo.o_res);
     plan.outs = (EncOut*)(dev + Lo.o_outs);
     plan.err = (uint32_t*)(dev + Lo.o_err);
-    plan.tile_item = (const uint32_t*)(dev + Lo.o_titem);
-    plan.tile_first = (const uint32_t*)(dev + Lo.o_tfirst);
     plan.ftile_item = (const uint32_t*)(dev + Lo.o_ftitem);
     plan.ftile_first = (const uint32_t*)(dev + Lo.o_ftfirst);
     plan.n_ftiles = Lo.n_ftiles;
     plan.n_items = Lo.n;
     plan.n_outs = Lo.no;
-    plan.n_tiles = Lo.n_tiles;
     plan.max_groups = Lo.max_groups;
     plan.max_asm = Lo.max_asm;
     return plan;
@@ -325,6 +312,7 @@ hipError_t enc_enqueue(const EncLayout& Lo, const EncPlan& plan, uint8_t* dev, c
 
 // Results k_enc_offsets wrote to host memory.
 void enc_results(const EncLayout& Lo, const uint8_t* hres, EncResult& result) {
+    memcpy(&result.err, hres + 16ull * Lo.no + 4ull * Lo.n, 4);
     result.lens.resize(Lo.no);
     result.ok.resize(Lo.no);
     result.modes.resize(Lo.n);
@@ -368,7 +356,7 @@ int enc_execute(DevCtx& ctx, const HostBuf& up, const EncPrepared& P, hipStream_
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     prof_collect();
     enc_results(P.Lo, (const uint8_t*)ctx.res.p, result);
-    return JIFFY_OK;
+    return (result.err & kErrStall) ? JIFFY_E_DEVICE : JIFFY_OK;
 }
 
 int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs, hipStream_t stream,
@@ -768,7 +756,6 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     plan.nwords = nwords;
     plan.npx = npx;
     plan.max_groups = div_up(maxnb, kGroupFrames);
-    plan.n_tiles = div_up(npx, kTilePx);
     plan.need_temporal = need_temporal ? 1u : 0u;
     plan.modes = dev + o_modes;
     plan.ws = dev + o_data;
@@ -1146,6 +1133,7 @@ int jiffy_batch_run(jiffy_batch* b, const void* const* const* d_planes, size_t* 
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     EncResult res;
     enc_results(b->Lo, b->res, res);
+    if (res.err & kErrStall) return JIFFY_E_DEVICE;
     return finish_step(b->streams.data(), n, res, h_lens, h_modes);
 }
 

@@ -4,11 +4,12 @@
 // records of a scan sequence are independent once the previous scan is an
 // input, so each kernel runs over all records together.
 //
-//   k_enc_mask     quantize (Sec. III-B), zero bitmask by wave ballot (Sec. III-C)
 //   k_enc_trial    I/P choice by trial compression of a few scanlines (Sec. III-E)
-//   k_enc_scan     running count of in-range samples; per-tile bases
-//   k_enc_tiles    zero removal, temporal difference (Sec. III-D), delta,
-//                  ZigZag (Eq. 1), frame width choice and bit packing (Sec. II)
+//   k_enc_tiles    quantize (Sec. III-B), zero bitmask (Sec. III-C), running
+//                  count of in-range samples (decoupled look-back over the
+//                  record's tiles), zero removal, temporal difference
+//                  (Sec. III-D), delta, ZigZag (Eq. 1), frame width choice and
+//                  bit packing (Sec. II)
 //   k_enc_fixup    the same for frames that cross tile boundaries
 //   k_enc_mframe   mask (XOR previous for a P-scan, Sec. III-D) as a Raw/RLE
 //                  Zstandard frame (Sec. III-C)
@@ -32,72 +33,6 @@ __device__ __forceinline__ uint32_t tile_owner(const JG uint32_t* item_of, const
     const uint32_t r = item_of[t];
     lt = t - first_of[r];
     return r;
-}
-
-// ---------------------------------------------------------------------------
-// quantize + zero bitmask.  One workgroup per 4096-pixel tile; each thread
-// reads 16 consecutive samples; 4 lanes form one 64-bit valid word.
-// ---------------------------------------------------------------------------
-template <int WB>
-__device__ __forceinline__ void enc_mask_body(const EncItem& it, uint32_t lt) {
-    const uint32_t p0 = lt * kTilePx + threadIdx.x * 16;
-    uint32_t v[16];
-    load16<WB>(it.x, p0, it.npx, it.aligned16, v);
-    uint32_t bits16 = 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        v[i] = quantize(v[i], it.div);
-        bits16 |= (v[i] != 0 ? 1u : 0u) << i;
-    }
-    if (it.qout && p0 < it.npx) store16<WB>(it.qout, p0, it.npx, it.aligned16, v);
-    uint64_t w = (uint64_t)bits16 << (16 * (threadIdx.x & 3));
-    w |= __shfl_xor(w, 1, kWave);
-    w |= __shfl_xor(w, 2, kWave);
-    const uint32_t word = lt * kTileWords + threadIdx.x / 4;
-    if ((threadIdx.x & 3) == 0 && word < it.nwords) it.vw[word] = w;
-}
-
-__global__ __launch_bounds__(256) void k_enc_mask(EncPlan plan) {
-    uint32_t lt;
-    const uint32_t r = tile_owner(plan.tile_item, plan.tile_first, plan.tpi, blockIdx.x, lt);
-    const EncItem it = plan.items[r];
-    switch (it.wb) {
-        case 4: enc_mask_body<4>(it, lt); break;
-        case 2: enc_mask_body<2>(it, lt); break;
-        default: enc_mask_body<1>(it, lt); break;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Running count of in-range samples over the flattened scan (Sec. III-C zero
-// removal): N, and for every kFTile-pixel tile the count before it and the
-// last in-range pixel before it.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_enc_scan(EncPlan plan) {
-    const uint32_t r = blockIdx.x;
-    const EncItem it = plan.items[r];
-    __shared__ uint32_t scratch[20], scratch2[20];
-    constexpr uint32_t kTW = kFTile / 64;  // words per tile
-    uint32_t carry = 0, lastpx = 0;
-    for (uint32_t w0 = 0; w0 < it.nwords; w0 += 1024) {
-        const uint32_t w = w0 + threadIdx.x;
-        const uint64_t v = w < it.nwords ? it.vw[w] : 0ull;
-        const uint32_t pc = __popcll(v);
-        const uint32_t lp = v ? 64u * w + 64u - (uint32_t)__clzll(v) : 0u;  // last in-range pixel + 1
-        uint32_t total, mtot;
-        const uint32_t pre = block_excl_scan<1024>(pc, scratch, &total) + carry;
-        const uint32_t exm = max(block_excl_max<1024>(lp, scratch2, &mtot), lastpx);
-        if (w < it.nwords && w % kTW == 0) {
-            it.tbase[w / kTW] = pre;
-            it.tpred[w / kTW] = exm;
-        }
-        carry += total;
-        lastpx = max(lastpx, mtot);
-    }
-    if (threadIdx.x == 0) {
-        plan.res[r].N = carry;
-        plan.res[r].nb = div_up(carry, kFrame);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -419,6 +354,9 @@ __device__ __forceinline__ void enc_trial_body(const EncItem& it, TrialLds& L, J
 __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
     const uint32_t r = blockIdx.x;
     const EncItem it = plan.items[r];
+    // the record's k_enc_tiles tickets and look-back states start at zero
+    for (uint32_t i = threadIdx.x; i < it.ntiles; i += 256) it.tstat[i] = 0;
+    if (threadIdx.x == 0) *it.tctr = 0u;
     if (!it.has_prev || it.mode_req != 0) {
         if (threadIdx.x == 0) plan.res[r].mode = (it.has_prev && it.mode_req == 2) ? 1u : 0u;
         return;
@@ -455,15 +393,67 @@ __device__ __forceinline__ uint32_t residual_at(const EncItem& it, uint32_t mode
 struct TileLds {
     uint32_t rows[kTileFrames * kRow];  // frame rows
     uint32_t sink[256];                 // where the compaction's unkept values go
-    uint32_t scratch[8];
-    uint32_t pred;
+    uint32_t scratch[8], scratch2[8];
+    uint32_t pred, kb, ticket;
 };
+
+// Look-back state of an encoder tile: bit 63 its own count and last pixel
+// are published, bit 62 its running ones are; the in-range count in bits
+// 0..30 and the last in-range pixel plus 1 (0: none) in bits 31..61.
+constexpr uint64_t kEsAgg = 1ull << 63, kEsIncl = 1ull << 62;
+constexpr uint32_t kEncSpinMax = 1u << 16;  // polls before giving up
+__device__ __forceinline__ uint32_t es_cnt(uint64_t s) { return (uint32_t)s & 0x7FFFFFFFu; }
+__device__ __forceinline__ uint32_t es_lp(uint64_t s) { return (uint32_t)(s >> 31) & 0x7FFFFFFFu; }
+
+// One wave: publishes the tile's count and last pixel, then adds up the
+// counts (and takes the largest last pixel) of the tiles before it, from the
+// nearest one whose running values are known, 64 tiles per round.  Returns
+// the running count before the tile in cnt_before and the last in-range
+// pixel plus 1 before it in lp_before.
+__device__ void enc_lookback(JG uint64_t* st, uint32_t lt, uint32_t cnt, uint32_t lp, JG uint32_t* err,
+                             uint32_t& cnt_before, uint32_t& lp_before) {
+    const uint32_t l = lane_id();
+    if (l == 0)
+        __hip_atomic_store(st + lt, (lt ? kEsAgg : kEsIncl) | cnt | ((uint64_t)lp << 31), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t ec = 0, el = 0, end = lt, spins = 0;  // tiles [0, end) not combined yet
+    while (end > 0) {
+        const int idx = (int)end - 1 - (int)l;  // lane 0: the nearest
+        uint64_t s = kEsIncl;                    // before the first tile: nothing
+        if (idx >= 0) s = __hip_atomic_load(st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t f = s & (kEsAgg | kEsIncl);
+        const uint64_t incl = ballot(f == kEsIncl), empty = ballot(f == 0);
+        const uint32_t fi = incl ? (uint32_t)__builtin_ctzll(incl) : 64u;
+        const uint32_t fe = empty ? (uint32_t)__builtin_ctzll(empty) : 64u;
+        if (fe < fi) {  // a nearer tile has not published: take the ones before it, poll again
+            if (fe) {
+                ec += wave_sum(l < fe ? es_cnt(s) : 0u);
+                el = max(el, wave_max(l < fe ? es_lp(s) : 0u));
+                end -= fe;
+            }
+            if (++spins > kEncSpinMax) {  // never expected: a tile before this one did not publish
+                if (l == 0) atomicOr(err, kErrStall);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        ec += wave_sum(l <= fi ? es_cnt(s) : 0u);
+        el = max(el, wave_max(l <= fi ? es_lp(s) : 0u));
+        if (fi < 64) break;
+        end -= 64;
+    }
+    if (l == 0 && lt)
+        __hip_atomic_store(st + lt, kEsIncl | (ec + cnt) | ((uint64_t)max(el, lp) << 31), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    cnt_before = ec;
+    lp_before = el;
+}
 
 template <int WB>
 __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
                                               TileLds& L) {
-    const uint32_t N = plan.res[r].N, mode = plan.res[r].mode;
-    const uint32_t kb = it.tbase[lt], tp = it.tpred[lt];
+    const uint32_t mode = plan.res[r].mode;
     const uint32_t m = low_mask32(it.bits);
     const uint32_t tid = threadIdx.x;
     const uint32_t p0 = lt * kFTile + tid * 32;
@@ -472,28 +462,54 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
     if (p0 < it.npx) {
         load16<WB>(it.x, p0, it.npx, it.aligned16, s);
         load16<WB>(it.x, p0 + 16, it.npx, it.aligned16, s + 16);
+        uint32_t xp[32];
         if (mode) {
-            uint32_t xp[32];
             load16<WB>(it.xprev, p0, it.npx, it.aligned16, xp);
             load16<WB>(it.xprev, p0 + 16, it.npx, it.aligned16, xp + 16);
+        }
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            s[i] = quantize(s[i], it.div);
+            keep |= (s[i] != 0 ? 1u : 0u) << i;
+        }
+        if (it.qout) {  // the quantized scan, kept for the next scan's prediction
+            store16<WB>(it.qout, p0, it.npx, it.aligned16, s);
+            if (p0 + 16 < it.npx) store16<WB>(it.qout, p0 + 16, it.npx, it.aligned16, s + 16);
+        }
+        if (mode) {
 #pragma unroll
             for (int i = 0; i < 32; ++i) {
-                const uint32_t q = quantize(s[i], it.div);
                 const uint32_t qp = it.prev_quantized ? xp[i] : quantize(xp[i], it.div);
-                keep |= (q != 0 ? 1u : 0u) << i;
-                s[i] = (q - qp) & m;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                s[i] = quantize(s[i], it.div);
-                keep |= (s[i] != 0 ? 1u : 0u) << i;
+                s[i] = (s[i] - qp) & m;
             }
         }
     }
-    if (tid == 0) L.pred = tp ? residual_at<WB>(it, mode, tp - 1, m) : 0u;
-    uint32_t nv;
+    {  // the zero bitmask: one 64-pixel word per pair of threads
+        const uint64_t w = (uint64_t)keep | ((uint64_t)__shfl_down(keep, 1, kWave) << 32);
+        if (!(tid & 1u) && p0 < it.npx) it.vw[p0 >> 6] = w;
+    }
+    uint32_t nv, lp_tile;
     const uint32_t off = block_excl_scan<256>(__popc(keep), L.scratch, &nv);
+    (void)block_excl_max<256>(keep ? p0 + 32u - (uint32_t)__clz(keep) : 0u, L.scratch2, &lp_tile);
+    // in-range samples and the last in-range pixel before this tile, from the tiles before it
+    if (tid < kWave) {
+        uint32_t kb_w, tp_w;
+        enc_lookback(it.tstat, lt, nv, lp_tile, plan.err, kb_w, tp_w);
+        if (tid == 0) {
+            L.kb = kb_w;
+            L.pred = tp_w ? residual_at<WB>(it, mode, tp_w - 1, m) : 0u;
+            if (lt + 1 == it.ntiles) {  // the record's last tile knows its count
+                plan.res[r].N = kb_w + nv;
+                plan.res[r].nb = div_up(kb_w + nv, kFrame);
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t kb = L.kb;
+    // the record's size is known in its last tile only: elsewhere a frame that
+    // runs past the tile's values is taken to continue in a later tile (if it
+    // is the record's last, k_enc_fixup codes it)
+    const uint32_t N = lt + 1 == it.ntiles ? kb + nv : 0xFFFFFFFFu;
     const uint32_t jf = kb >> 7;
     {
         // kept values go to their row; the others to this thread's sink word
@@ -542,10 +558,19 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
 }
 
 __global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
-    uint32_t lt;
-    const uint32_t r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, blockIdx.x, lt);
+    // the record is fixed by the workgroup index; the tile within it is taken
+    // in arrival order, so every tile a workgroup waits for has started
+    uint32_t lt_unused;
+    const uint32_t r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, blockIdx.x, lt_unused);
     const EncItem it = plan.items[r];
     __shared__ TileLds lds;
+    if (threadIdx.x == 0) lds.ticket = atomicAdd(it.tctr, 1u);
+    __syncthreads();
+    const uint32_t lt = lds.ticket;
+    if (lt >= it.ntiles) {  // never expected: the record's ticket counter was not cleared
+        if (threadIdx.x == 0) atomicOr(plan.err, kErrStall);
+        return;
+    }
     switch (it.wb) {
         case 4: enc_tile_body<4>(plan, it, r, lt, lds); break;
         case 2: enc_tile_body<2>(plan, it, r, lt, lds); break;
@@ -816,6 +841,8 @@ __global__ __launch_bounds__(1024) void k_enc_offsets(EncPlan plan) {
         plan.res[r].rec_off = plan.res[r].rec_off - o.gbase + o.hdr_len;
         if (plan.host_res) store_system((JG uint32_t*)(plan.host_res + 16ull * plan.n_outs) + r, plan.res[r].mode);
     }
+    if (plan.host_res && threadIdx.x == 0)
+        store_system((JG uint32_t*)(plan.host_res + 16ull * plan.n_outs) + plan.n_items, *plan.err);
 }
 
 // ---------------------------------------------------------------------------
@@ -965,9 +992,7 @@ hipError_t launch_copy_in(const void* host, void* dev, size_t bytes, hipStream_t
 
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
-    JIFFY_LAUNCH("k_enc_mask", k_enc_mask, dim3(plan.n_tiles), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_trial", k_enc_trial, dim3(plan.n_items), dim3(256), stream, plan);
-    JIFFY_LAUNCH("k_enc_scan", k_enc_scan, dim3(plan.n_items), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_enc_tiles", k_enc_tiles, dim3(plan.n_ftiles), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_fixup", k_enc_fixup, dim3(div_up(plan.n_ftiles, 16)), dim3(64), stream, plan);
     JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(kMfThreads), stream, plan);

@@ -23,8 +23,6 @@ constexpr uint32_t kSlotBytes = 576;        // a packed frame (at most 16 * 32 b
                                             // straddles tiles: its 128 residuals and their predecessor
 constexpr uint32_t kFTile = 8192;           // pixels per encode / decode tile
 constexpr uint32_t kNoFix = 0xFFFFFFFFu;    // a tile with no straddling frame to finish
-constexpr uint32_t kTilePx = 4096;          // pixels per mask tile (64 words of 64 px)
-constexpr uint32_t kTileWords = kTilePx / 64;
 constexpr uint32_t kGroupFrames = 16;       // frames per group of the per-record size scans
 constexpr uint32_t kAsmFrames = 64;         // frames copied into the stream by one workgroup
 constexpr uint32_t kZstdBlockMax = 131072;  // largest Zstandard block (RFC 8878)
@@ -32,7 +30,7 @@ constexpr uint32_t kRleMinRun = 8;          // runs this long become RLE blocks
 constexpr uint32_t kParseWin = 8192;        // mask-frame bytes per parsing window (one workgroup each)
 
 // Error bits raised by kernels (ORed into a device word).
-enum : uint32_t { kErrCorrupt = 1u, kErrCapacity = 2u };
+enum : uint32_t { kErrCorrupt = 1u, kErrCapacity = 2u, kErrStall = 4u };  // stall: a bounded wait ran out
 
 inline __host__ __device__ uint32_t align4(uint32_t x) { return (x + 3u) & ~3u; }
 inline __host__ __device__ uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
@@ -66,9 +64,9 @@ struct EncItem {
     JG void* qout;               // if set, the quantized scan is stored here
     JG uint64_t* vw;             // valid-sample words of this scan (bit = 1: nonzero)
     const JG uint64_t* vwprev;   // valid-sample words of the previous scan
-    JG uint32_t* tbase;          // [ntiles] in-range samples before each kFTile tile
-    JG uint32_t* tpred;          // [ntiles] last in-range pixel before each tile, plus 1 (0: none)
     JG uint32_t* tfix;           // [ntiles] frame that starts in the tile and ends after it, or kNoFix
+    JG uint64_t* tstat;          // [ntiles] look-back state of each kFTile tile
+    JG uint32_t* tctr;           // k_enc_tiles ticket counter of the record
     JG uint32_t* blkinfo;        // [maxnb] b | n << 8 | B << 16
     JG uint32_t* blkoffs;        // [3 * maxnb] payload / position / high offsets
     JG uint8_t* slots;           // [maxnb * kSlotBytes] packed frames
@@ -155,15 +153,13 @@ struct EncPlan {
     JG EncRes* res;              // device
     JG EncOut* outs;             // device
     JG uint32_t* err;            // device
-    const JG uint32_t* tile_item;  // device: item of each mask tile
-    const JG uint32_t* tile_first; // device: first tile of each item
     const JG uint32_t* ftile_item;  // device: item of each kFTile tile
     const JG uint32_t* ftile_first; // device: first kFTile tile of each item
     JG uint8_t* host_res;        // host-mapped results (or null): per output {u64 len, u32 ok, u32 -}, then
-                                 // per record its mode (u32)
-    uint32_t tpi, ftpi;          // mask / kFTile tiles per record when every record has the same size (the
+                                 // per record its mode (u32), then the error word
+    uint32_t ftpi;               // kFTile tiles per record when every record has the same size (the
                                  // maps above are then unused), else 0
-    uint32_t n_items, n_outs, n_tiles, n_ftiles;
+    uint32_t n_items, n_outs, n_ftiles;
     uint32_t max_groups;      // max over items of ceil(maxnb / kGroupFrames)
     uint32_t max_asm;         // max over items of ceil(maxnb / kAsmFrames)
 };
@@ -184,7 +180,6 @@ struct DecPlan {
     uint32_t off_cw, off_vw;  // offsets of the mask words inside a record's workspace
     uint32_t n_items, n_scans, n_attrs;
     uint32_t nwords, npx, max_groups;
-    uint32_t n_tiles;
     uint32_t nft;             // kFTile tiles per record
     const JG uint32_t* rec_list; // the records with 32-bit samples, then the others
     uint32_t n_wide;          // how many have 32-bit samples

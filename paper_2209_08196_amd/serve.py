@@ -64,8 +64,8 @@ def workspace_bytes(height, width, widths):
     maxnb = (npx + _FRAME - 1) // _FRAME
     nm = (npx + 7) // 8
     nft = (npx + _FTILE - 1) // _FTILE
-    per_attr = (_al(16 * maxnb + 12 * nft) + _al(_SLOT_BYTES * maxnb) + _al(16 + nm + 4 * (nm // 131072 + 1))
-                + _al(8 * (nm // 4 + 4)) + _al(8 * nwords) + 512 + 8 * ((npx + 4095) // 4096 + nft))
+    per_attr = (_al(16 * maxnb + 4 * nft) + _al(8 * nft + 4) + _al(_SLOT_BYTES * maxnb)
+                + _al(16 + nm + 4 * (nm // 131072 + 1)) + _al(8 * (nm // 4 + 4)) + _al(8 * nwords) + 512 + 8 * (nft + 1))
     return len(widths) * per_attr + 1024
 
 
