@@ -96,14 +96,11 @@ def kernel_alg_bytes(name, st, x_bytes, n_items, nwords):
     F, M, S = st["frame_bytes"], st["mask_bytes"], st["stream_bytes"]
     Xp = st["p_bytes"]                 # samples of the P-records
     table = {
-        "k_enc_mask": x_bytes + vb,            # samples in, valid words out
-        "k_enc_tiles": x_bytes + Xp + F,       # samples (+ previous scan) in, packed frames out
+        "k_enc_tiles": x_bytes + Xp + vb + F,  # samples (+ previous scan) in, valid words and packed frames out
         "k_enc_mframe": vb + vbp + M,          # valid words in, mask frames out
         "k_enc_assemble": F + M + S,           # frames and masks in, stream out
         "k_dec_parse": M + vb,                 # mask frames in, valid words out
         "k_dec_mask": 2 * vb + vbp,            # mask chain over time
-        "k_dec_fsum": F,                       # packed frames in
-        "k_dec_group": F + vb + x_bytes,       # packed frames and valid words in, samples out
         "k_dec_tiles_w32": st["frame_bytes_w32"] + 8 * nwords * st["items_w32"] + st["x_bytes_w32"],
         "k_dec_tiles_w16": (F - st["frame_bytes_w32"]) + 8 * nwords * (n_items - st["items_w32"])
                            + (x_bytes - st["x_bytes_w32"]),
