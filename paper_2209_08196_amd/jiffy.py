@@ -225,6 +225,59 @@ def decode(stream_bytes, layout: Layout = None, n_scans: int = None, outs=None, 
     return outs
 
 
+class Encoder:
+    """jiffy_encode of fixed planes into a fixed output buffer, prepared once:
+    the tensors are checked and the call's arguments built at construction,
+    so a call is one foreign-function call (the library also reuses its plan
+    for repeated arguments).  The tensors must stay alive and keep their
+    storage; their contents are read afresh on every call.  The stream is
+    the one given, else the current stream at construction."""
+
+    def __init__(self, planes, precisions=None, mode=MODE_AUTO, trial_rows=0, out=None, stream=None):
+        import torch
+        T, H, W = _check_planes(planes)
+        self.planes = list(planes)
+        self.layout = make_layout(H, W, [p.element_size() for p in planes], precisions)
+        self._opt = Options(mode, trial_rows)
+        self.T = T
+        if out is None:
+            out = torch.empty(encode_bound(self.layout, T), dtype=torch.uint8, device=planes[0].device)
+        self.out = out
+        self._arr = (ctypes.c_void_p * len(planes))(*[p.data_ptr() for p in planes])
+        self._n = ctypes.c_size_t()
+        self._modes = np.zeros((max(T, 1), len(planes)), np.uint8)
+        self._args = (ctypes.byref(self.layout), ctypes.byref(self._opt), T, ctypes.cast(self._arr, ctypes.c_void_p),
+                      ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(self._n),
+                      self._modes.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+
+    def __call__(self):
+        """Returns (stream tensor uint8 [n], modes ndarray [T, A]), as encode()."""
+        rc = lib().jiffy_encode(*self._args)
+        if rc:
+            raise JiffyError(rc, "jiffy_encode")
+        return self.out[: self._n.value], self._modes[: self.T]
+
+
+class Decoder:
+    """jiffy_decode_layout of streams of one layout and scan count into fixed
+    output planes, prepared once (as Encoder)."""
+
+    def __init__(self, layout: Layout, n_scans: int, outs, stream=None):
+        if n_scans < 1:
+            raise ValueError("n_scans must be at least 1")
+        self.layout, self.T, self.outs = layout, n_scans, list(outs)
+        self._arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        self._stream = _stream_handle(stream)
+
+    def __call__(self, stream_bytes):
+        """Decodes the device stream tensor into the output planes; returns them."""
+        rc = lib().jiffy_decode_layout(ctypes.byref(self.layout), self.T, ctypes.c_void_p(stream_bytes.data_ptr()),
+                                       stream_bytes.numel(), ctypes.cast(self._arr, ctypes.c_void_p), self._stream)
+        if rc:
+            raise JiffyError(rc, "jiffy_decode_layout")
+        return self.outs
+
+
 class Stream:
     """A sensor stream whose previous quantized scan stays resident on the
     device (jiffy_stream)."""

@@ -142,3 +142,30 @@ def test_repeated_calls_on_the_same_buffers_see_new_contents(J):
             assert np.array_equal(to_host(outs[0], 4), ref), rnd
         if rnd == 1:  # a larger decode in between grows the workspace
             J.decode(_dev(s_big))
+
+
+def test_prepared_encoder_and_decoder(J):
+    """Encoder / Decoder (arguments prepared once) give the oracle's stream
+    and samples, and see new input contents on every call."""
+    import torch
+    g = synth.stream(2, 7)
+    x, y = g.scans(0, 3), g.scans(3, 6)
+    precs = list(g.precisions)
+    lay, T = _layout(J, x, precs)
+    dev = [to_dev(p) for p in x]
+    enc = J.Encoder(dev, precs)
+    outs = [torch.empty_like(d) for d in dev]
+    dcd = J.Decoder(lay, T, outs)
+    for rnd, data in enumerate((x, y, x)):
+        banner("prepared round", rnd)
+        for d, p in zip(dev, data):
+            d.copy_(to_dev(p))
+        s_ref, m_ref = oracle.encode(data, precs)
+        s, m = enc()
+        assert s.cpu().numpy().tobytes() == s_ref, rnd
+        assert np.array_equal(m, m_ref), rnd
+        for o in outs:
+            o.zero_()
+        dcd(s)
+        for a, (o, p) in enumerate(zip(outs, data)):
+            assert np.array_equal(to_host(o, p.dtype.itemsize), p), (rnd, a)  # P = 1: lossless
