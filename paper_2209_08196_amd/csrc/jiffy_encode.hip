@@ -657,7 +657,7 @@ __device__ __forceinline__ void classify32(const EncItem& it, uint32_t mode, uin
     R.start = (uint32_t)st & valid;
 }
 
-constexpr uint32_t kMfThreads = 1024;  // one workgroup per record covers 32 KiB of mask content per round
+constexpr uint32_t kMfThreads = 512;  // one workgroup per record covers 16 KiB of mask content per round
 
 __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
     const uint32_t r = blockIdx.x;
