@@ -394,7 +394,7 @@ struct TileLds {
     uint32_t rows[kTileFrames * kRow];  // frame rows
     uint32_t sink[256];                 // where the compaction's unkept values go
     uint32_t scratch[8], scratch2[8];
-    uint32_t pred, kb, ticket;
+    uint32_t pred, kb, tp, ticket;
 };
 
 // Look-back state of an encoder tile: bit 63 its own count and last pixel
@@ -497,7 +497,7 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
         enc_lookback(it.tstat, lt, nv, lp_tile, plan.err, kb_w, tp_w);
         if (tid == 0) {
             L.kb = kb_w;
-            L.pred = tp_w ? residual_at<WB>(it, mode, tp_w - 1, m) : 0u;
+            L.tp = tp_w;  // the pixel after the last in-range one before the tile (0: none)
             if (lt + 1 == it.ntiles) {  // the record's last tile knows its count
                 plan.res[r].N = kb_w + nv;
                 plan.res[r].nb = div_up(kb_w + nv, kFrame);
@@ -506,6 +506,9 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
     }
     __syncthreads();
     const uint32_t kb = L.kb;
+    // the residual before the tile's first value: its load overlaps the compaction
+    const uint32_t tp = L.tp;
+    const uint32_t pred_v = (tid == 0 && tp) ? residual_at<WB>(it, mode, tp - 1, m) : 0u;
     // the record's size is known in its last tile only: elsewhere a frame that
     // runs past the tile's values is taken to continue in a later tile (if it
     // is the record's last, k_enc_fixup codes it)
@@ -522,6 +525,7 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
             k += kp ? 1u : 0u;
         }
     }
+    if (tid == 0) L.pred = pred_v;
     __syncthreads();
     if (nv == 0) {
         if (tid == 0) it.tfix[lt] = kNoFix;
