@@ -586,7 +586,10 @@ __global__ __launch_bounds__(64) void k_dec_mask(DecPlan plan) {
 
 constexpr uint32_t kDecThreads = 320;                 // 80 quads: enough for the 65 frames a tile can touch
 constexpr uint32_t kFrameMaxWords = 160;              // a frame's packed bytes are at most 640
-constexpr uint32_t kStageWords = 3680;                // staged packed words (larger tiles read memory)
+// staged packed words per tile (larger tiles read the record): 32-bit rows
+// leave room for 3680; with 16-bit rows 2560 (the packed frames of 8- and
+// 16-bit samples are shorter) keep five workgroups on a CU
+template <class R> constexpr uint32_t stage_words() { return sizeof(R) == 4 ? 3680u : 2560u; }
 
 // ---------------------------------------------------------------------------
 // Running count of valid samples: N must match the section header; the
@@ -667,7 +670,7 @@ constexpr uint64_t kStAgg = 1ull << 32, kStIncl = 2ull << 32;  // look-back stat
 template <class R>
 struct DecTileLds {
     R rows[kTileFrames * RowT<R>::kElems];
-    uint32_t stage[kStageWords + 2];
+    uint32_t stage[stage_words<R>() + 2];
     uint32_t info[kTileFrames];
     uint32_t offs[kTileFrames + 1][3];  // frame offsets in the three sections
     uint32_t scratch[8];
@@ -819,9 +822,9 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
         }
     }
     const uint32_t n01 = D.nw[0] + D.nw[1], nall = n01 + D.nw[2];
-    const bool staged = nall <= kStageWords;  // else the frames are read from the record
+    const bool staged = nall <= stage_words<R>();  // else the frames are read from the record
     if (staged) {  // every load issued before the first store, so their latencies overlap
-        constexpr int kIter = (kStageWords + kDecThreads - 1) / kDecThreads;
+        constexpr int kIter = (stage_words<R>() + kDecThreads - 1) / kDecThreads;
         const JG uint32_t* recw = (const JG uint32_t*)it.rec;  // records are 4-byte aligned
         uint32_t w[kIter];
 #pragma unroll
