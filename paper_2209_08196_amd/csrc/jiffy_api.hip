@@ -147,7 +147,7 @@ struct EncResult {
 // workspace: [res][err][outs][items][tile maps] (the part uploaded from the
 // host, from `err` on) then per record its buffers.
 struct EncLayout {
-    uint32_t n = 0, no = 0, n_ftiles = 0, max_groups = 1, max_asm = 1;
+    uint32_t n = 0, no = 0, n_ftiles = 0, max_asm = 1;
     uint32_t ftpi = 0;  // tiles per record when all records have the same size (no tile maps)
     std::vector<uint32_t> ftile_first;
     size_t o_res = 0, o_err = 0, o_outs = 0, o_items = 0, o_ftfirst = 0, o_ftitem = 0;
@@ -167,8 +167,6 @@ EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpe
         Lo.ftile_first[r] = Lo.n_ftiles;
         const uint32_t npx = specs[r].H * specs[r].W;
         Lo.n_ftiles += div_up(npx, kFTile);
-        const uint32_t groups = div_up(div_up(npx, kFrame), kGroupFrames);
-        if (groups > Lo.max_groups) Lo.max_groups = groups;
         const uint32_t asmg = div_up(div_up(npx, kFrame), kAsmFrames);
         if (asmg > Lo.max_asm) Lo.max_asm = asmg;
     }
@@ -295,7 +293,6 @@ EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev, uint8_t* host_res) {
     plan.n_ftiles = Lo.n_ftiles;
     plan.n_items = Lo.n;
     plan.n_outs = Lo.no;
-    plan.max_groups = Lo.max_groups;
     plan.max_asm = Lo.max_asm;
     return plan;
 }
@@ -755,7 +752,6 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     plan.n_attrs = A;
     plan.nwords = nwords;
     plan.npx = npx;
-    plan.max_groups = div_up(maxnb, kGroupFrames);
     plan.need_temporal = need_temporal ? 1u : 0u;
     plan.modes = dev + o_modes;
     plan.ws = dev + o_data;

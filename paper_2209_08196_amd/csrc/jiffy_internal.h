@@ -23,7 +23,6 @@ constexpr uint32_t kSlotBytes = 576;        // a packed frame (at most 16 * 32 b
                                             // straddles tiles: its 128 residuals and their predecessor
 constexpr uint32_t kFTile = 8192;           // pixels per encode / decode tile
 constexpr uint32_t kNoFix = 0xFFFFFFFFu;    // a tile with no straddling frame to finish
-constexpr uint32_t kGroupFrames = 16;       // frames per group of the per-record size scans
 constexpr uint32_t kAsmFrames = 64;         // frames copied into the stream by one workgroup
 constexpr uint32_t kZstdBlockMax = 131072;  // largest Zstandard block (RFC 8878)
 constexpr uint32_t kRleMinRun = 8;          // runs this long become RLE blocks
@@ -160,7 +159,6 @@ struct EncPlan {
     uint32_t ftpi;               // kFTile tiles per record when every record has the same size (the
                                  // maps above are then unused), else 0
     uint32_t n_items, n_outs, n_ftiles;
-    uint32_t max_groups;      // max over items of ceil(maxnb / kGroupFrames)
     uint32_t max_asm;         // max over items of ceil(maxnb / kAsmFrames)
 };
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream);
@@ -179,7 +177,7 @@ struct DecPlan {
     uint64_t item_stride;
     uint32_t off_cw, off_vw;  // offsets of the mask words inside a record's workspace
     uint32_t n_items, n_scans, n_attrs;
-    uint32_t nwords, npx, max_groups;
+    uint32_t nwords, npx;
     uint32_t nft;             // kFTile tiles per record
     const JG uint32_t* rec_list; // the records with 32-bit samples, then the others
     uint32_t n_wide;          // how many have 32-bit samples
