@@ -889,7 +889,6 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
 // P-scan, precedes one, or has P > 1.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kModeLds = 8192;
-constexpr uint32_t kTempPx = 4;  // pixels per thread
 
 // four samples at p0 (a multiple of 4); 0 beyond npx
 template <int WB>
@@ -928,72 +927,104 @@ __device__ __forceinline__ void store4(void* base, uint32_t p0, uint32_t npx, bo
 }
 
 // The scans that must be read: P-scans, scans followed by a P-scan, and
-// every scan when P > 1; taken in order, the next one's samples loaded
-// while the current one is finished.
+// every scan when P > 1; taken in order, with the next kTempAhead - 1 scans'
+// samples in flight while the current one is finished (the loads do not
+// depend on each other, only the sums do).  A thread takes one 32-bit word
+// of every scan: 4 / WB pixels.
+constexpr int kTempAhead = 8;
 template <int WB>
 __device__ __forceinline__ void dec_temporal_body(const DecPlan& plan, uint32_t a, uint32_t p0, const uint16_t* list,
-                                                  uint32_t tb, uint32_t nlist, uint32_t qprev[4]) {
+                                                  uint32_t tb, uint32_t nlist, uint32_t qprev[4 / WB]) {
+    constexpr int NP = 4 / WB;
     const uint32_t A = plan.n_attrs;
     const uint32_t P = plan.attr_P[a], bits = 8 * WB, m = low_mask32(bits);
     const uint64_t stride = (uint64_t)plan.npx * WB;
-    const bool al = ((uintptr_t)plan.out_base[a] % 16 == 0) && (stride % 16 == 0);
-    auto fetch = [&](uint32_t t, uint32_t v[4], uint32_t& vb) {
-        load4<WB>((const uint8_t*)plan.out_base[a] + stride * t, p0, plan.npx, al, v);
-        vb = plan.modes[t * A + a] ? (uint32_t)(item_words(plan, t * A + a, plan.off_vw)[p0 >> 6] >> (p0 & 63)) & 0xFu
-                                   : 0x10u;  // 0x10: an I-scan
+    const bool whole = ((uintptr_t)plan.out_base[a] % 4 == 0) && (stride % 4 == 0) && p0 + NP <= plan.npx;
+    using T = typename SampleT<WB>::T;
+    // e: a list entry (the scan, and bit 15 set for a P-scan).  The loads land
+    // in registers that nothing reads before the scan's turn, so the next
+    // scans' loads stay in flight meanwhile.
+    auto fetch = [&](uint32_t e, uint32_t& w, uint64_t& vw) {
+        const uint32_t t = tb + (e & 0x7FFFu);
+        const uint8_t* s = (const uint8_t*)plan.out_base[a] + stride * t + (uint64_t)p0 * WB;
+        if (whole) w = *(const uint32_t*)s;
+        else {
+            w = 0;
+            for (int i = 0; i < NP; ++i)
+                if (p0 + i < plan.npx) w |= (uint32_t)((const T*)s)[i] << (8 * WB * i);
+        }
+        // the valid-sample words exist for every record; an I-scan's is not used
+        vw = item_words(plan, t * A + a, plan.off_vw)[p0 >> 6];
     };
-    uint32_t cur[4], nxt[4], cb = 0, nb = 0;
-    if (nlist) fetch(tb + list[0], cur, cb);
-    for (uint32_t k = 0; k < nlist; ++k) {
-        const uint32_t t = tb + list[k];
-        if (k + 1 < nlist) fetch(tb + list[k + 1], nxt, nb);
-        uint32_t v[4];
-        if (cb != 0x10u) {  // P-scan: add the previous scan at the valid pixels
+    auto put = [&](uint32_t t, const uint32_t v[NP]) {
+        uint8_t* d = (uint8_t*)plan.out_base[a] + stride * t + (uint64_t)p0 * WB;
+        if (whole) {
+            uint32_t w = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t q = (cb >> i) & 1u ? ((cur[i] + qprev[i]) & m) : 0u;
+            for (int i = 0; i < NP; ++i) w |= v[i] << (8 * WB * i);
+            *(uint32_t*)d = w;
+        } else {
+            for (int i = 0; i < NP; ++i)
+                if (p0 + i < plan.npx) ((T*)d)[i] = (T)v[i];
+        }
+    };
+    uint32_t buf[kTempAhead];
+    uint64_t bw[kTempAhead];
+#pragma unroll
+    for (int j = 0; j < kTempAhead; ++j)
+        if ((uint32_t)j < nlist) fetch(list[j], buf[j], bw[j]);
+    for (uint32_t k0 = 0; k0 < nlist; k0 += kTempAhead) {
+#pragma unroll
+        for (int j = 0; j < kTempAhead; ++j) {
+            const uint32_t k = k0 + j;
+            if (k >= nlist) break;
+            const uint32_t e = list[k], t = tb + (e & 0x7FFFu);
+            const bool pscan = e >> 15;
+            const uint32_t cb = (uint32_t)(bw[j] >> (p0 & 63));
+            uint32_t v[NP];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const uint32_t r = (buf[j] >> (8 * WB * i)) & m;
+                // P-scan: the previous scan added at the valid pixels; I-scan: the sample itself
+                const uint32_t q = !pscan ? r : (cb >> i) & 1u ? ((r + qprev[i]) & m) : 0u;
                 qprev[i] = q;
                 v[i] = dequantize(q, P, bits);
             }
-            store4<WB>((uint8_t*)plan.out_base[a] + stride * t, p0, plan.npx, al, v);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                qprev[i] = cur[i];
-                v[i] = dequantize(cur[i], P, bits);
-            }
-            if (P > 1) store4<WB>((uint8_t*)plan.out_base[a] + stride * t, p0, plan.npx, al, v);
+            if (pscan || P > 1) put(t, v);
+            if (k + kTempAhead < nlist) fetch(list[k + kTempAhead], buf[j], bw[j]);
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) cur[i] = nxt[i];
-        cb = nb;
     }
 }
 
 __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
     if (*plan.err) return;
     const uint32_t a = blockIdx.y;
-    __shared__ uint16_t list[kModeLds];
+    __shared__ uint16_t list[kModeLds];  // the scans to read: offset from tb, bit 15 for a P-scan
     __shared__ uint32_t scratch[8];
     const uint32_t A = plan.n_attrs, T = plan.n_scans;
     const bool all = plan.attr_P[a] > 1;
-    const uint32_t p0 = (blockIdx.x * 256 + threadIdx.x) * kTempPx;
+    const uint32_t wb = plan.attr_wb[a];
+    const uint32_t p0 = (blockIdx.x * 256 + threadIdx.x) * (4 / wb);
+    if (blockIdx.x * 256 * (4 / wb) >= plan.npx) return;  // the grid is sized for 32-bit samples
     uint32_t qprev[4] = {0u, 0u, 0u, 0u};
     for (uint32_t tb = 0; tb < T; tb += kModeLds) {  // kModeLds scans at a time
         const uint32_t te = min(T, tb + kModeLds);
         uint32_t nlist = 0;  // the scans to read, in order
         for (uint32_t t0 = tb; t0 < te; t0 += 256) {
             const uint32_t t = t0 + threadIdx.x;
-            uint32_t need = 0;
-            if (t < te) need = all || plan.modes[t * A + a] || (t + 1 < T && plan.modes[(t + 1) * A + a]);
+            uint32_t need = 0, pscan = 0;
+            if (t < te) {
+                pscan = plan.modes[t * A + a];
+                need = all || pscan || (t + 1 < T && plan.modes[(t + 1) * A + a]);
+            }
             uint32_t tot;
             const uint32_t o = block_excl_scan<256>(need, scratch, &tot);
-            if (need) list[nlist + o] = (uint16_t)(t - tb);
+            if (need) list[nlist + o] = (uint16_t)((t - tb) | (pscan ? 0x8000u : 0u));
             nlist += tot;
         }
         __syncthreads();
         if (p0 < plan.npx) {
-            switch (plan.attr_wb[a]) {
+            switch (wb) {
                 case 4: dec_temporal_body<4>(plan, a, p0, list, tb, nlist, qprev); break;
                 case 2: dec_temporal_body<2>(plan, a, p0, list, tb, nlist, qprev); break;
                 default: dec_temporal_body<1>(plan, a, p0, list, tb, nlist, qprev); break;
@@ -1015,7 +1046,7 @@ hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
         JIFFY_LAUNCH("k_dec_tiles_w16", k_dec_tiles<uint16_t>, dim3((plan.n_items - plan.n_wide) * plan.nft),
                      dim3(kDecThreads), stream, plan, plan.n_wide);
     if (plan.need_temporal)
-        JIFFY_LAUNCH("k_dec_temporal", k_dec_temporal, dim3(div_up(plan.npx, 256 * kTempPx), plan.n_attrs), dim3(256),
+        JIFFY_LAUNCH("k_dec_temporal", k_dec_temporal, dim3(div_up(plan.npx, 256), plan.n_attrs), dim3(256),
                      stream, plan);
     return hipGetLastError();
 }
