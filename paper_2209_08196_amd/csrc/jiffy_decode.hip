@@ -885,46 +885,10 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
 // ---------------------------------------------------------------------------
 // Over time, per pixel: a P-scan adds the previous decoded scan at its valid
 // pixels (Sec. III-D); then q * P, saturated to the sample width.  The
-// attribute's modes are staged in LDS; a scan is read only when it is a
-// P-scan, precedes one, or has P > 1.
+// attribute's list of scans to read is built in LDS: a scan is read only
+// when it is a P-scan, precedes one, or has P > 1.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kModeLds = 8192;
-
-// four samples at p0 (a multiple of 4); 0 beyond npx
-template <int WB>
-__device__ __forceinline__ void load4(const void* base, uint32_t p0, uint32_t npx, bool al, uint32_t v[4]) {
-    using T = typename SampleT<WB>::T;
-    const T* b = (const T*)base + p0;
-    if (al && p0 + 4 <= npx) {
-        if (WB == 4) {
-            const uint4 t = *(const uint4*)b;
-            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-        } else if (WB == 2) {
-            const uint2 t = *(const uint2*)b;
-            v[0] = t.x & 0xFFFFu; v[1] = t.x >> 16; v[2] = t.y & 0xFFFFu; v[3] = t.y >> 16;
-        } else {
-            const uint32_t t = *(const uint32_t*)b;
-            v[0] = t & 0xFFu; v[1] = (t >> 8) & 0xFFu; v[2] = (t >> 16) & 0xFFu; v[3] = t >> 24;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = p0 + i < npx ? (uint32_t)b[i] : 0u;
-    }
-}
-template <int WB>
-__device__ __forceinline__ void store4(void* base, uint32_t p0, uint32_t npx, bool al, const uint32_t v[4]) {
-    using T = typename SampleT<WB>::T;
-    T* b = (T*)base + p0;
-    if (al && p0 + 4 <= npx) {
-        if (WB == 4) *(uint4*)b = make_uint4(v[0], v[1], v[2], v[3]);
-        else if (WB == 2) *(uint2*)b = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
-        else *(uint32_t*)b = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (p0 + i < npx) b[i] = (T)v[i];
-    }
-}
 
 // The scans that must be read: P-scans, scans followed by a P-scan, and
 // every scan when P > 1; taken in order, with the next kTempAhead - 1 scans'

@@ -283,28 +283,55 @@ __device__ __forceinline__ void enc_trial_body(const EncItem& it, TrialLds& L, J
     const uint32_t nr = K >= H ? H : K;  // distinct trial rows
     const uint32_t NT = nr * W;          // trial pixels
     if (tid < 2) L.cost[tid] = 0;
+    // rows of a multiple of 32 samples: a thread's 32 trial pixels lie in one row
+    const bool whole = it.aligned16 && W % 32 == 0;
     uint32_t carry = 0, pred[2] = {0u, 0u};  // values in the incomplete frame; value before it
     for (uint32_t cs = 0; cs < NT; cs += kFTile) {
         // this thread's 32 trial pixels
         uint32_t val[2][32];
         uint32_t keep = 0;
-#pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            const uint32_t tp = cs + tid * 32 + i;
-            uint32_t u = 0, v = 0;
-            if (tp < NT) {
-                const uint32_t ri = tp / W, c = tp - ri * W;
+        const uint32_t tp0 = cs + tid * 32;
+        if (whole) {  // one row, 16-sample aligned: vector loads
+            uint32_t xs[32], xp[32];
+            if (tp0 < NT) {
+                const uint32_t ri = tp0 / W, c = tp0 - ri * W;
                 const uint32_t row = K >= H ? ri : (uint32_t)(((uint64_t)(2 * ri + 1) * H) / (2ull * K));
                 const uint32_t p = row * W + c;
-                const uint32_t qv = quantize(load1<WB>(it.x, p), it.div);
-                uint32_t qp = load1<WB>(it.xprev, p);
-                if (!it.prev_quantized) qp = quantize(qp, it.div);
-                keep |= (qv != 0 ? 1u : 0u) << i;
-                u = qv;
-                v = (qv - qp) & m;
+                load16<WB>(it.x, p, it.npx, true, xs);
+                load16<WB>(it.x, p + 16, it.npx, true, xs + 16);
+                load16<WB>(it.xprev, p, it.npx, true, xp);
+                load16<WB>(it.xprev, p + 16, it.npx, true, xp + 16);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 32; ++i) xs[i] = xp[i] = 0;
             }
-            val[0][i] = u;
-            val[1][i] = v;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const uint32_t qv = quantize(xs[i], it.div);
+                const uint32_t qp = it.prev_quantized ? xp[i] : quantize(xp[i], it.div);
+                keep |= (qv != 0 ? 1u : 0u) << i;
+                val[0][i] = qv;
+                val[1][i] = (qv - qp) & m;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const uint32_t tp = tp0 + i;
+                uint32_t u = 0, v = 0;
+                if (tp < NT) {
+                    const uint32_t ri = tp / W, c = tp - ri * W;
+                    const uint32_t row = K >= H ? ri : (uint32_t)(((uint64_t)(2 * ri + 1) * H) / (2ull * K));
+                    const uint32_t p = row * W + c;
+                    const uint32_t qv = quantize(load1<WB>(it.x, p), it.div);
+                    uint32_t qp = load1<WB>(it.xprev, p);
+                    if (!it.prev_quantized) qp = quantize(qp, it.div);
+                    keep |= (qv != 0 ? 1u : 0u) << i;
+                    u = qv;
+                    v = (qv - qp) & m;
+                }
+                val[0][i] = u;
+                val[1][i] = v;
+            }
         }
         uint32_t nv;
         const uint32_t off = block_excl_scan<256>(__popc(keep), L.scratch, &nv);
