@@ -794,34 +794,64 @@ __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
 
 // ---------------------------------------------------------------------------
 // Section layout of each record: prefix sums of payload, position and high
-// part sizes over its frames; the record length.
+// part sizes over its frames (the three in one pass of 1024 frames); the
+// record length.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_enc_sizes(EncPlan plan) {
+constexpr int kSizeThreads = 1024;
+
+// Exclusive prefix sums of three values over the workgroup at once
+// (3 * (NT/64 + 1) words of LDS); tot gets the three sums.
+template <int NT>
+__device__ __forceinline__ void block_excl_scan3(uint32_t v[3], uint32_t* scratch, uint32_t tot[3]) {
+    constexpr int NW = NT / kWave;
+    const uint32_t l = lane_id(), w = threadIdx.x / kWave;
+    uint32_t inc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        inc[c] = wave_incl_scan(v[c]);
+        if (l == kWave - 1) scratch[c * (NW + 1) + w] = inc[c];
+    }
+    __syncthreads();
+    if (w < 3) {  // wave c combines the wave sums of value c
+        uint32_t* sc = scratch + w * (NW + 1);
+        const uint32_t x = l < (uint32_t)NW ? sc[l] : 0u;
+        const uint32_t xi = wave_incl_scan(x);
+        if (l < (uint32_t)NW) sc[l] = xi - x;
+        if (l == NW - 1) sc[NW] = xi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v[c] = scratch[c * (NW + 1) + w] + inc[c] - v[c];
+        tot[c] = scratch[c * (NW + 1) + NW];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kSizeThreads) void k_enc_sizes(EncPlan plan) {
     const uint32_t r = blockIdx.x;
     const EncItem it = plan.items[r];
     const uint32_t nb = plan.res[r].nb;
-    __shared__ uint32_t scratch[8];
+    __shared__ uint32_t scratch[3 * (kSizeThreads / kWave + 1)];
     uint32_t cp = 0, cn = 0, ch = 0;
-    for (uint32_t j0 = 0; j0 < nb; j0 += 256) {
+    for (uint32_t j0 = 0; j0 < nb; j0 += kSizeThreads) {
         const uint32_t j = j0 + threadIdx.x;
-        uint32_t pay = 0, pos = 0, high = 0;
+        uint32_t v[3] = {0u, 0u, 0u};  // payload, position and high part bytes of frame j
         if (j < nb) {
             const uint32_t info = it.blkinfo[j];
             const uint32_t b = info & 0xFF, n = (info >> 8) & 0xFF, B = (info >> 16) & 0xFF;
-            pay = 16 * b;
-            pos = n;
-            high = (n * (B - b) + 7) / 8;
+            v[0] = 16 * b;
+            v[1] = n;
+            v[2] = (n * (B - b) + 7) / 8;
         }
-        uint32_t tp, tn, th;
-        const uint32_t op = block_excl_scan<256>(pay, scratch, &tp);
-        const uint32_t on = block_excl_scan<256>(pos, scratch, &tn);
-        const uint32_t oh = block_excl_scan<256>(high, scratch, &th);
+        uint32_t tot[3];
+        block_excl_scan3<kSizeThreads>(v, scratch, tot);
         if (j < nb) {
-            it.blkoffs[3 * j] = cp + op;
-            it.blkoffs[3 * j + 1] = cn + on;
-            it.blkoffs[3 * j + 2] = ch + oh;
+            it.blkoffs[3 * j] = cp + v[0];
+            it.blkoffs[3 * j + 1] = cn + v[1];
+            it.blkoffs[3 * j + 2] = ch + v[2];
         }
-        cp += tp; cn += tn; ch += th;
+        cp += tot[0]; cn += tot[1]; ch += tot[2];
     }
     if (threadIdx.x == 0) {
         EncRes& rs = plan.res[r];
@@ -1027,7 +1057,7 @@ hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_enc_tiles", k_enc_tiles, dim3(plan.n_ftiles), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_fixup", k_enc_fixup, dim3(div_up(plan.n_ftiles, 16)), dim3(64), stream, plan);
     JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(kMfThreads), stream, plan);
-    JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(256), stream, plan);
+    JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(kSizeThreads), stream, plan);
     JIFFY_LAUNCH("k_enc_offsets", k_enc_offsets, dim3(1), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_enc_assemble", k_enc_assemble, dim3(plan.max_asm + 1, plan.n_items), dim3(256), stream, plan);
     return hipGetLastError();
