@@ -540,43 +540,42 @@ hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const D
 }
 
 // ---------------------------------------------------------------------------
-// Mask chain over time, one thread per mask word of one attribute; scans are
-// taken eight at a time so that their loads overlap.
+// Mask chain over time, one thread per 32-bit half of a mask word of one
+// attribute; scans are taken kMaskAhead at a time so that their loads
+// overlap (the chain is the only serial part).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t* item_words(const DecPlan& plan, uint32_t r, uint32_t off) {
     return (uint64_t*)(plan.ws + plan.item_stride * r + off);
 }
 
+constexpr int kMaskAhead = 32;
+
 __global__ __launch_bounds__(64) void k_dec_mask(DecPlan plan) {
     if (*plan.err) return;
     const uint32_t a = blockIdx.y;
-    const uint32_t w = blockIdx.x * 64 + threadIdx.x;
-    if (w >= plan.nwords) return;
-    const uint64_t tm = tail_mask(w, plan.nwords, plan.npx);
+    const uint32_t h = blockIdx.x * 64 + threadIdx.x;  // half-word index
+    if (h >= 2 * plan.nwords) return;
+    const uint32_t tm = (uint32_t)(tail_mask(h >> 1, plan.nwords, plan.npx) >> (32 * (h & 1)));
     const uint32_t A = plan.n_attrs, T = plan.n_scans;
-    uint64_t mprev = 0;
+    uint32_t mprev = 0;
     bool bad = false;
-    for (uint32_t t0 = 0; t0 < T; t0 += 8) {
-        uint64_t c[8];
-        uint32_t md[8];
+    for (uint32_t t0 = 0; t0 < T; t0 += kMaskAhead) {
+        // the modes are loaded with the words, and every load is issued (past
+        // the last scan it reads the last scan again, unused): nothing waits alone
+        uint32_t c[kMaskAhead], md[kMaskAhead];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t t = t0 + k;
-            c[k] = 0;
-            md[k] = 0;
-            if (t < T) {
-                const uint32_t r = t * A + a;
-                c[k] = item_words(plan, r, plan.off_cw)[w];
-                md[k] = plan.modes[r];
-            }
+        for (int k = 0; k < kMaskAhead; ++k) {
+            const uint32_t t = min(t0 + k, T - 1);
+            c[k] = ((const uint32_t*)item_words(plan, t * A + a, plan.off_cw))[h];
+            md[k] = plan.modes[t * A + a];
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < kMaskAhead; ++k) {
             const uint32_t t = t0 + k;
             if (t < T) {
-                const uint64_t m = md[k] ? (c[k] ^ mprev) : c[k];
+                const uint32_t m = md[k] ? (c[k] ^ mprev) : c[k];
                 bad |= (m & ~tm) != 0;  // mask bits past the scan
-                item_words(plan, t * A + a, plan.off_vw)[w] = ~m & tm;
+                ((uint32_t*)item_words(plan, t * A + a, plan.off_vw))[h] = ~m & tm;
                 mprev = m;
             }
         }
@@ -1001,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
     JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items, plan.pwin + 1), dim3(256), stream, plan);
-    JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(plan.nwords, 64), plan.n_attrs), dim3(64), stream, plan);
+    JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(2 * plan.nwords, 64), plan.n_attrs), dim3(64), stream, plan);
     JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
     if (plan.n_wide)
         JIFFY_LAUNCH("k_dec_tiles_w32", k_dec_tiles<uint32_t>, dim3(plan.n_wide * plan.nft), dim3(kDecThreads),
