@@ -990,46 +990,64 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
         return;
     }
     // 64 frames per workgroup: 16 lanes per frame, each group of 16 lanes
-    // takes four frames; the metadata of the four, then their first 32
-    // payload words, are loaded in one round each.  A frame's payload,
-    // positions and high parts go from its slot to their three places.
+    // takes four frames.  A frame's slot holds its payload words, then its
+    // exception bytes (positions, high parts), at most kSlotBytes in all: the
+    // four frames' metadata is loaded in one round, then every word of the
+    // four slots in another (words past a frame's end read its first word
+    // again: no extra traffic), then the stores.  Payload words go to the
+    // payload section whole; exception bytes to the position and high-part
+    // sections one by one.
     constexpr int kPer = kAsmFrames / 16;
+    constexpr int kSlotRounds = kSlotBytes / 4 / 16;
+    static_assert(kSlotBytes % 64 == 0, "a slot is a whole number of 16-word rounds");
     const uint32_t jg = (blockIdx.x - 1) * kAsmFrames + (tid >> 4) * kPer;
     if (jg >= rs.nb) return;
     const uint32_t l = tid & 15u;
-    uint32_t info[kPer], op[kPer], on[kPer], oh[kPer], oh1[kPer];
+    uint32_t info[kPer], op[kPer], on[kPer], oh[kPer];
 #pragma unroll
     for (int f = 0; f < kPer; ++f) {
-        const uint32_t j = jg + f;
-        const bool ok = j < rs.nb;
-        info[f] = ok ? it.blkinfo[j] : 0u;
-        op[f] = ok ? it.blkoffs[3 * j] : 0u;
-        on[f] = ok ? it.blkoffs[3 * j + 1] : 0u;
-        oh[f] = ok ? it.blkoffs[3 * j + 2] : 0u;
-        oh1[f] = j + 1 < rs.nb ? it.blkoffs[3 * (j + 1) + 2] : rs.high;
+        const uint32_t j = min(jg + f, rs.nb - 1);  // past the record's frames: its last again (unused)
+        info[f] = it.blkinfo[j];
+        op[f] = it.blkoffs[3 * j];
+        on[f] = it.blkoffs[3 * j + 1];
+        oh[f] = it.blkoffs[3 * j + 2];
     }
-    uint32_t v[kPer][2];
+    uint32_t v[kPer][kSlotRounds], nwf[kPer];
 #pragma unroll
     for (int f = 0; f < kPer; ++f) {
-        const uint32_t nw = 4u * (info[f] & 0xFFu);
-        const uint32_t* sw = (const uint32_t*)(it.slots + (size_t)(jg + f) * kSlotBytes);
+        const uint32_t b = info[f] & 0xFFu, n = (info[f] >> 8) & 0xFFu, B = (info[f] >> 16) & 0xFFu;
+        nwf[f] = jg + f < rs.nb ? (16u * b + n + (n * (B - b) + 7u) / 8u + 3u) / 4u : 0u;
+        const uint32_t* sw = (const uint32_t*)(it.slots + (size_t)min(jg + f, rs.nb - 1) * kSlotBytes);
 #pragma unroll
-        for (int u = 0; u < 2; ++u) v[f][u] = l + 16u * u < nw ? sw[l + 16u * u] : 0u;
+        for (int u = 0; u < kSlotRounds; ++u) {
+            const uint32_t i = l + 16u * u;
+            v[f][u] = sw[i < nwf[f] ? i : 0u];
+        }
     }
 #pragma unroll
     for (int f = 0; f < kPer; ++f) {
-        if (jg + f >= rs.nb) break;
-        const uint32_t b = info[f] & 0xFFu, n = (info[f] >> 8) & 0xFFu, nw = 4u * b;
-        const uint8_t* slot = it.slots + (size_t)(jg + f) * kSlotBytes;
-        const uint32_t* sw = (const uint32_t*)slot;
+        const uint32_t b = info[f] & 0xFFu, n = (info[f] >> 8) & 0xFFu, B = (info[f] >> 16) & 0xFFu;
+        const uint32_t ne = n + (n * (B - b) + 7u) / 8u;  // exception bytes
         uint32_t* dw = (uint32_t*)(rec + pay0 + op[f]);  // payloads are whole words
+        uint8_t* dpos = rec + pos0 + on[f];
+        uint8_t* dhigh = rec + high0 + oh[f];
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (l + 16u * u < nw) dw[l + 16u * u] = v[f][u];
-        for (uint32_t w = 32 + l; w < nw; w += 16) dw[w] = sw[w];
-        if (l < n) rec[pos0 + on[f] + l] = slot[16 * b + l];
-        for (uint32_t q = 16 + l; q < n; q += 16) rec[pos0 + on[f] + q] = slot[16 * b + q];
-        for (uint32_t q = l; q < oh1[f] - oh[f]; q += 16) rec[high0 + oh[f] + q] = slot[16 * b + n + q];
+        for (int u = 0; u < kSlotRounds; ++u) {
+            const uint32_t i = l + 16u * u;
+            if (i >= nwf[f]) continue;
+            if (i < 4u * b) {
+                dw[i] = v[f][u];
+                continue;
+            }
+            const uint32_t e0 = 4u * (i - 4u * b);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t e = e0 + k;
+                const uint8_t byte = (uint8_t)(v[f][u] >> (8 * k));
+                if (e < n) dpos[e] = byte;
+                else if (e < ne) dhigh[e - n] = byte;
+            }
+        }
     }
 }
 
