@@ -94,22 +94,32 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
     JG uint64_t* pst = parse_states(plan, r);
     __shared__ uint32_t s_win;
     __shared__ uint64_t s_state;
-    if (tid == 0) s_win = atomicAdd((JG uint32_t*)(pst + plan.pwin + 1), 1u);
-    __syncthreads();
-    const uint32_t win = s_win;
     if (tid == 0) {
+        // the window's ticket, and with it (no wait in between) the record
+        // header and the frame header through its content size,
+        // record bytes 4..27, in one round of word loads (a record is 4-byte
+        // aligned, at least 12 bytes and a whole number of words long; a word
+        // past its end reads its last word again, and every byte taken from
+        // one is ruled out by the length checks first)
+        const uint32_t win = atomicAdd((JG uint32_t*)(pst + plan.pwin + 1), 1u);
+        const uint32_t* rw = (const uint32_t*)rec;
+        const uint32_t lw = L / 4 - 1;
+        uint32_t hw[7];
+#pragma unroll
+        for (int k = 1; k < 7; ++k) hw[k] = rw[min((uint32_t)k, lw)];
+        s_win = win;
+        auto byte = [&](uint32_t i) -> uint32_t { return (hw[i >> 2] >> (8 * (i & 3))) & 0xFFu; };
         uint32_t err = 0;
-        const uint32_t mode = rec[4], attr = rec[5];
-        const uint32_t resv = rec[6] | (rec[7] << 8);
-        const uint32_t flen = rd32(rec + 8);
+        const uint32_t mode = byte(4), attr = byte(5);
+        const uint32_t resv = hw[1] >> 16;
+        const uint32_t flen = hw[2];
         if (mode > 1 || attr != it.attr || resv != 0 || flen > L - 12) err = 1;
         if (mode == 1 && it.t == 0) err = 1;  // nothing to predict from
         uint32_t pos = 0;
-        if (!err) {
-            const uint8_t* f = rec + 12;
-            if (flen < 6 || rd32(f) != 0xFD2FB528u) err = 1;
+        if (!err) {  // the frame starts at record byte 12
+            if (flen < 6 || hw[3] != 0xFD2FB528u) err = 1;
             else {
-                const uint32_t fhd = f[4];
+                const uint32_t fhd = byte(16);
                 const uint32_t fcs_flag = fhd >> 6, single = (fhd >> 5) & 1;
                 const uint32_t reserved = (fhd >> 3) & 1, checksum = (fhd >> 2) & 1, dict = fhd & 3;
                 if (!single || reserved || checksum || dict) err = 1;
@@ -117,11 +127,11 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
                 pos = 5;
                 if (!err && pos + fcs_len > flen) err = 1;
                 if (!err) {
-                    uint64_t fcs;
-                    if (fcs_len == 1) fcs = f[pos];
-                    else if (fcs_len == 2) fcs = (uint64_t)(f[pos] | (f[pos + 1] << 8)) + 256;
-                    else if (fcs_len == 4) fcs = rd32(f + pos);
-                    else fcs = (uint64_t)rd32(f + pos) | ((uint64_t)rd32(f + pos + 4) << 32);
+                    uint64_t fcs = 0;  // little-endian, frame bytes 5 .. 5 + fcs_len (record bytes 17 ..)
+#pragma unroll
+                    for (uint32_t k = 0; k < 8; ++k)
+                        if (k < fcs_len) fcs |= (uint64_t)byte(17 + k) << (8 * k);
+                    if (fcs_len == 2) fcs += 256;
                     if (fcs != nm) err = 1;
                     pos += fcs_len;
                 }
@@ -139,6 +149,7 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
         }
     }
     __syncthreads();
+    const uint32_t win = s_win;
     const uint32_t flen = P.s_flen;
     const uint8_t* f = rec + 12;
     const uint8_t* fb = (const uint8_t*)P.fwin;
@@ -420,28 +431,49 @@ __device__ void parse_sections(const DecPlan& plan, uint32_t r, const DecItem& i
     }
     const uint32_t sec = s_sec, N = s_N, nb = s_nb;
     const uint8_t* hb = rec + sec + 4;
+    // kSecPer consecutive frames per thread: their width, count and maximum
+    // width bytes loaded in one round (past the last frame: the last again,
+    // unused), summed in order, then one three-value scan per pass
+    constexpr uint32_t kSecPer = 8, kSecPass = 256 * kSecPer;
+    __shared__ uint32_t s_scan[3 * (256 / kWave + 1)];
     uint32_t cp = 0, cn = 0, ch = 0, bad = 0;
-    for (uint32_t j0 = 0; j0 < nb; j0 += 256) {
-        const uint32_t j = j0 + tid;
-        uint32_t pay = 0, pos = 0, high = 0;
-        if (j < nb) {
-            const uint32_t b = hb[j], n = hb[nb + j], B = hb[2 * nb + j];
+    for (uint32_t j0 = 0; j0 < nb; j0 += kSecPass) {
+        const uint32_t jb = j0 + tid * kSecPer;
+        uint32_t fb[kSecPer], fn[kSecPer], fB[kSecPer];
+#pragma unroll
+        for (uint32_t u = 0; u < kSecPer; ++u) {
+            const uint32_t j = min(jb + u, nb - 1);
+            fb[u] = hb[j];
+            fn[u] = hb[nb + j];
+            fB[u] = hb[2 * nb + j];
+        }
+        uint32_t v[3] = {0u, 0u, 0u};  // payload, position and high part bytes of the thread's frames
+#pragma unroll
+        for (uint32_t u = 0; u < kSecPer; ++u) {
+            if (jb + u >= nb) break;
+            const uint32_t b = fb[u], n = fn[u], B = fB[u];
             if (B > it.bits || b > B || n > 128 || (n && b == B)) bad = 1;
-            pay = 16 * b;
-            pos = n;
-            high = (n * (B - b) + 7) / 8;
-            it.blkinfo[j] = b | (n << 8) | (B << 16);
+            v[0] += 16 * b;
+            v[1] += n;
+            v[2] += (n * (B - b) + 7) / 8;
+            it.blkinfo[jb + u] = b | (n << 8) | (B << 16);
         }
-        uint32_t tp, tn, th;
-        const uint32_t op = block_excl_scan<256>(pay, P.scratch, &tp);
-        const uint32_t on = block_excl_scan<256>(pos, P.scratch, &tn);
-        const uint32_t oh = block_excl_scan<256>(high, P.scratch, &th);
-        if (j < nb) {
-            it.blkoffs[3 * j] = cp + op;
-            it.blkoffs[3 * j + 1] = cn + on;
-            it.blkoffs[3 * j + 2] = ch + oh;
+        uint32_t tot[3];
+        block_excl_scan3<256>(v, s_scan, tot);
+        uint32_t op = cp + v[0], on = cn + v[1], oh = ch + v[2];
+#pragma unroll
+        for (uint32_t u = 0; u < kSecPer; ++u) {
+            const uint32_t j = jb + u;
+            if (j >= nb) break;
+            const uint32_t b = fb[u], n = fn[u], B = fB[u];
+            it.blkoffs[3 * j] = op;
+            it.blkoffs[3 * j + 1] = on;
+            it.blkoffs[3 * j + 2] = oh;
+            op += 16 * b;
+            on += n;
+            oh += (n * (B - b) + 7) / 8;
         }
-        cp += tp; cn += tn; ch += th;
+        cp += tot[0]; cn += tot[1]; ch += tot[2];
     }
     if (bad) atomicOr(&s_err, 1u);
     __syncthreads();

@@ -94,6 +94,36 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratc
     return r;
 }
 
+// Exclusive prefix sums of three values over the workgroup at once
+// (3 * (NT/64 + 1) words of LDS); tot gets the three sums.
+template <int NT>
+__device__ __forceinline__ void block_excl_scan3(uint32_t v[3], uint32_t* scratch, uint32_t tot[3]) {
+    constexpr int NW = NT / kWave;
+    static_assert(NW >= 3 && NW <= kWave, "one wave per value combines the wave sums");
+    const uint32_t l = lane_id(), w = threadIdx.x / kWave;
+    uint32_t inc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        inc[c] = wave_incl_scan(v[c]);
+        if (l == kWave - 1) scratch[c * (NW + 1) + w] = inc[c];
+    }
+    __syncthreads();
+    if (w < 3) {  // wave c combines the wave sums of value c
+        uint32_t* sc = scratch + w * (NW + 1);
+        const uint32_t x = l < (uint32_t)NW ? sc[l] : 0u;
+        const uint32_t xi = wave_incl_scan(x);
+        if (l < (uint32_t)NW) sc[l] = xi - x;
+        if (l == NW - 1) sc[NW] = xi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v[c] = scratch[c * (NW + 1) + w] + inc[c] - v[c];
+        tot[c] = scratch[c * (NW + 1) + NW];
+    }
+    __syncthreads();
+}
+
 template <int NT>
 __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v, uint64_t* scratch, uint64_t* total) {
     constexpr int NW = NT / kWave;

@@ -799,35 +799,6 @@ __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
 // ---------------------------------------------------------------------------
 constexpr int kSizeThreads = 1024;
 
-// Exclusive prefix sums of three values over the workgroup at once
-// (3 * (NT/64 + 1) words of LDS); tot gets the three sums.
-template <int NT>
-__device__ __forceinline__ void block_excl_scan3(uint32_t v[3], uint32_t* scratch, uint32_t tot[3]) {
-    constexpr int NW = NT / kWave;
-    const uint32_t l = lane_id(), w = threadIdx.x / kWave;
-    uint32_t inc[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        inc[c] = wave_incl_scan(v[c]);
-        if (l == kWave - 1) scratch[c * (NW + 1) + w] = inc[c];
-    }
-    __syncthreads();
-    if (w < 3) {  // wave c combines the wave sums of value c
-        uint32_t* sc = scratch + w * (NW + 1);
-        const uint32_t x = l < (uint32_t)NW ? sc[l] : 0u;
-        const uint32_t xi = wave_incl_scan(x);
-        if (l < (uint32_t)NW) sc[l] = xi - x;
-        if (l == NW - 1) sc[NW] = xi;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        v[c] = scratch[c * (NW + 1) + w] + inc[c] - v[c];
-        tot[c] = scratch[c * (NW + 1) + NW];
-    }
-    __syncthreads();
-}
-
 __global__ __launch_bounds__(kSizeThreads) void k_enc_sizes(EncPlan plan) {
     const uint32_t r = blockIdx.x;
     const EncItem it = plan.items[r];
