@@ -663,15 +663,25 @@ __device__ __forceinline__ void classify32(const EncItem& it, uint32_t mode, uin
         const int w = w0 + k;
         R.win[k] = (w >= 0 && (uint32_t)w < it.nwords && 8u * (uint32_t)w < nm) ? content_word(it, mode, w) : 0ull;
     }
-    // eq bit k: byte (b0 - 16 + k) equals the byte before it (both inside the content)
+    // eq bit k: byte (b0 - 16 + k) equals the byte before it (both inside the
+    // content).  Four bytes at a time: XOR each byte with its predecessor,
+    // flag the zero bytes exactly (no carries between bytes: the low seven
+    // bits are added separately), gather the four flags with a multiply.
     uint64_t eq = 0;
-    uint32_t prev = 0x200u;
-    for (int k = 0; k < 64; ++k) {
-        const int i = (int)b0 - 16 + k;
-        const uint32_t c = (i >= 0 && (uint32_t)i < nm) ? (uint32_t)(R.win[k >> 3] >> (8 * (k & 7))) & 0xFFu
-                                                       : 0x100u + (uint32_t)k;  // never equal to a neighbour
-        eq |= (uint64_t)(c == prev) << k;
-        prev = c;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t w = (uint32_t)(R.win[j >> 1] >> (32 * (j & 1)));
+        const uint32_t pw = j ? (uint32_t)(R.win[(j - 1) >> 1] >> (32 * ((j - 1) & 1))) : 0u;
+        const uint32_t y = w ^ __builtin_amdgcn_alignbyte(w, pw, 3);  // byte t XOR byte t - 1
+        const uint32_t z = ~(((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y | 0x7F7F7F7Fu);  // bit 8t + 7: byte t of y is 0
+        eq |= (uint64_t)((((z >> 7) & 0x01010101u) * 0x10204081u) >> 28) << (4 * j);
+    }
+    {  // pairs inside the content only: byte k - 1 at or after its start, byte k before its end
+        const int lo = b0 == 0 ? 16 : 0;  // b0 is a multiple of 32
+        const int hi = min(64, (int)nm + 16 - (int)b0);
+        uint64_t vm = 0;
+        if (hi > lo + 1) vm = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << (lo + 1)) - 1ull);
+        eq &= vm;
     }
     // e8 bit k: bytes k .. k+7 all equal; lng bit k: some such window covers k
     uint64_t e8 = ~0ull;
@@ -689,48 +699,63 @@ __device__ __forceinline__ void classify32(const EncItem& it, uint32_t mode, uin
 }
 
 constexpr uint32_t kMfThreads = 512;  // one workgroup per record covers 16 KiB of mask content per round
+constexpr uint32_t kMfStep = kMfThreads * 32;
+constexpr uint32_t kMfKeep = 2;        // rounds whose classification stays in registers between passes
+constexpr uint32_t kMfSegLds = 6144;   // segments the LDS table holds (more: the workspace table)
 
-__global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
-    const uint32_t r = blockIdx.x;
-    const EncItem it = plan.items[r];
-    const uint32_t mode = plan.res[r].mode;
-    const uint32_t nm = div_up(it.npx, 8);
-    __shared__ uint32_t scratch[kMfThreads / 64 + 1];
-    const uint32_t hdr = nm <= 255 ? 6u : nm <= 65791 ? 7u : 9u;
-    const uint32_t tid = threadIdx.x;
-    constexpr uint32_t kStep = kMfThreads * 32;
+struct MfLds {
+    uint32_t segs[kMfSegLds];    // segment start | RLE << 31
+    uint32_t segoff[kMfSegLds];  // its offset in the frame
+    uint8_t segb[kMfSegLds];     // an RLE segment's byte
+    uint32_t scratch[kMfThreads / 64 + 1];
+};
 
-    // pass 1: segment starts
-    uint32_t nseg = 0;
-    for (uint32_t c0 = 0; c0 < nm; c0 += kStep) {
-        const uint32_t b0 = c0 + 32 * tid;
-        RunBits R;
-        classify32(it, mode, nm, b0, R);
-        uint32_t total;
-        uint32_t sid = block_excl_scan<kMfThreads>(__popc(R.start), scratch, &total) + nseg;
-        for (uint32_t m = R.start; m; m &= m - 1) {
-            const uint32_t k = __ffs(m) - 1;
-            it.segs[sid++] = (b0 + k) | (((R.lng >> k) & 1u) << 31);
+// Pass 1 of one round: the round's segment starts, numbered from nseg, go
+// to the LDS table (those that fit) or to the workspace table.
+__device__ __forceinline__ void mframe_starts(const EncItem& it, const RunBits& R, uint32_t b0, bool to_ws, MfLds& M,
+                                              uint32_t& nseg) {
+    uint32_t total;
+    uint32_t sid = block_excl_scan<kMfThreads>(__popc(R.start), M.scratch, &total) + nseg;
+    for (uint32_t m = R.start; m; m &= m - 1) {
+        const uint32_t k = __ffs(m) - 1;
+        const uint32_t e = (b0 + k) | (((R.lng >> k) & 1u) << 31);
+        if (to_ws) it.segs[sid] = e;
+        else if (sid < kMfSegLds) {
+            M.segs[sid] = e;
+            M.segb[sid] = (uint8_t)(R.win[2 + (k >> 3)] >> (8 * (k & 7)));
         }
-        nseg += total;
+        ++sid;
     }
-    __syncthreads();
+    nseg += total;
+}
+
+// Passes 2 and 3 over the segment table (in LDS, or in the workspace).
+template <bool kLds>
+__device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, const EncItem& it, uint32_t mode,
+                                             uint32_t nm, uint32_t nseg, uint32_t hdr, MfLds& M,
+                                             RunBits (&Rk)[kMfKeep]) {
+    const uint32_t tid = threadIdx.x;
+    auto seg = [&](uint32_t i) -> uint32_t { return kLds ? M.segs[i] : it.segs[i]; };
+    auto segoff = [&](uint32_t i) -> uint32_t { return kLds ? M.segoff[i] : it.segoff[i]; };
     // pass 2: encoded sizes and offsets of the segments
     uint32_t off_carry = hdr;
     for (uint32_t s0 = 0; s0 < nseg; s0 += kMfThreads) {
         const uint32_t sg = s0 + tid;
         uint32_t size = 0;
         if (sg < nseg) {
-            const uint32_t a = it.segs[sg];
+            const uint32_t a = seg(sg);
             const uint32_t start = a & 0x7FFFFFFFu;
-            const uint32_t end = (sg + 1 < nseg) ? (it.segs[sg + 1] & 0x7FFFFFFFu) : nm;
+            const uint32_t end = (sg + 1 < nseg) ? (seg(sg + 1) & 0x7FFFFFFFu) : nm;
             const uint32_t len = end - start;
             const uint32_t nblk = div_up(len, kZstdBlockMax);
             size = (a >> 31) ? 4u * nblk : 3u * nblk + len;
         }
         uint32_t total;
-        const uint32_t off = block_excl_scan<kMfThreads>(size, scratch, &total) + off_carry;
-        if (sg < nseg) it.segoff[sg] = off;
+        const uint32_t off = block_excl_scan<kMfThreads>(size, M.scratch, &total) + off_carry;
+        if (sg < nseg) {
+            if (kLds) M.segoff[sg] = off;
+            else it.segoff[sg] = off;
+        }
         off_carry += total;
     }
     __syncthreads();
@@ -746,20 +771,21 @@ __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
     }
     // block headers (and the byte of each RLE block)
     for (uint32_t sg = tid; sg < nseg; sg += kMfThreads) {
-        const uint32_t a = it.segs[sg];
+        const uint32_t a = seg(sg);
         const uint32_t start = a & 0x7FFFFFFFu;
-        const uint32_t end = (sg + 1 < nseg) ? (it.segs[sg + 1] & 0x7FFFFFFFu) : nm;
+        const uint32_t end = (sg + 1 < nseg) ? (seg(sg + 1) & 0x7FFFFFFFu) : nm;
         const uint32_t len = end - start;
         const uint32_t nblk = div_up(len, kZstdBlockMax);
         const uint32_t is_rle = a >> 31;
-        uint32_t o = it.segoff[sg];
+        const uint32_t rb = is_rle ? (kLds ? (uint32_t)M.segb[sg] : content_byte(it, mode, start)) : 0u;
+        uint32_t o = segoff(sg);
         for (uint32_t q = 0; q < nblk; ++q) {
             const uint32_t blen = min(kZstdBlockMax, len - q * kZstdBlockMax);
             const uint32_t last = (sg + 1 == nseg && q + 1 == nblk) ? 1u : 0u;
             const uint32_t h = last | (is_rle << 1) | (blen << 3);
             f[o] = (uint8_t)h; f[o + 1] = (uint8_t)(h >> 8); f[o + 2] = (uint8_t)(h >> 16);
             if (is_rle) {
-                f[o + 3] = (uint8_t)content_byte(it, mode, start);
+                f[o + 3] = (uint8_t)rb;
                 o += 4;
             } else {
                 o += 3 + blen;
@@ -768,20 +794,17 @@ __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
     }
     // raw bytes: the segment of every byte from the same classification
     uint32_t seg_carry = 0;
-    for (uint32_t c0 = 0; c0 < nm; c0 += kStep) {
-        const uint32_t b0 = c0 + 32 * tid;
-        RunBits R;
-        classify32(it, mode, nm, b0, R);
+    auto raw_round = [&](const RunBits& R, uint32_t b0) {
         uint32_t total;
-        uint32_t sid = block_excl_scan<kMfThreads>(__popc(R.start), scratch, &total) + seg_carry;
+        uint32_t sid = block_excl_scan<kMfThreads>(__popc(R.start), M.scratch, &total) + seg_carry;
         const uint32_t nvalid = nm > b0 ? min(32u, nm - b0) : 0u;
         uint32_t sg = sid ? sid - 1 : 0, sstart = 0, soff = 0;
-        if (sid) { sstart = it.segs[sg] & 0x7FFFFFFFu; soff = it.segoff[sg]; }
+        if (sid) { sstart = seg(sg) & 0x7FFFFFFFu; soff = segoff(sg); }
         for (uint32_t k = 0; k < nvalid; ++k) {
             if ((R.start >> k) & 1u) {
                 sg = sid++;
                 sstart = b0 + k;
-                soff = it.segoff[sg];
+                soff = segoff(sg);
             }
             if ((R.lng >> k) & 1u) continue;
             const uint32_t i = b0 + k;
@@ -789,7 +812,58 @@ __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
             f[soff + 3u * (q + 1u) + (i - sstart)] = (uint8_t)(R.win[2 + (k >> 3)] >> (8 * (k & 7)));
         }
         seg_carry += total;
+    };
+#pragma unroll
+    for (uint32_t c = 0; c < kMfKeep; ++c)
+        if (c * kMfStep < nm) raw_round(Rk[c], c * kMfStep + 32 * tid);
+    for (uint32_t c0 = kMfKeep * kMfStep; c0 < nm; c0 += kMfStep) {
+        RunBits R;
+        classify32(it, mode, nm, c0 + 32 * tid, R);
+        raw_round(R, c0 + 32 * tid);
     }
+}
+
+// One workgroup per record.  Pass 1 finds the segment starts (the first
+// kMfKeep rounds' classification is kept in registers for the raw bytes);
+// the segment table lives in LDS when it fits, else in the workspace.
+__global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
+    const uint32_t r = blockIdx.x;
+    const EncItem it = plan.items[r];
+    const uint32_t mode = plan.res[r].mode;
+    const uint32_t nm = div_up(it.npx, 8);
+    __shared__ MfLds M;
+    const uint32_t hdr = nm <= 255 ? 6u : nm <= 65791 ? 7u : 9u;
+    const uint32_t tid = threadIdx.x;
+    RunBits Rk[kMfKeep];
+    uint32_t nseg = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kMfKeep; ++c)
+        if (c * kMfStep < nm) {
+            classify32(it, mode, nm, c * kMfStep + 32 * tid, Rk[c]);
+            mframe_starts(it, Rk[c], c * kMfStep + 32 * tid, false, M, nseg);
+        }
+    for (uint32_t c0 = kMfKeep * kMfStep; c0 < nm; c0 += kMfStep) {
+        RunBits R;
+        classify32(it, mode, nm, c0 + 32 * tid, R);
+        mframe_starts(it, R, c0 + 32 * tid, false, M, nseg);
+    }
+    __syncthreads();
+    if (nseg <= kMfSegLds) {
+        mframe_write<true>(plan, r, it, mode, nm, nseg, hdr, M, Rk);
+        return;
+    }
+    // too many segments for LDS: the starts again, into the workspace table
+    nseg = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kMfKeep; ++c)
+        if (c * kMfStep < nm) mframe_starts(it, Rk[c], c * kMfStep + 32 * tid, true, M, nseg);
+    for (uint32_t c0 = kMfKeep * kMfStep; c0 < nm; c0 += kMfStep) {
+        RunBits R;
+        classify32(it, mode, nm, c0 + 32 * tid, R);
+        mframe_starts(it, R, c0 + 32 * tid, true, M, nseg);
+    }
+    __syncthreads();
+    mframe_write<false>(plan, r, it, mode, nm, nseg, hdr, M, Rk);
 }
 
 // ---------------------------------------------------------------------------
