@@ -798,15 +798,23 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
     }
 }
 
+// Value k sits at row element tword(k, jf) = k + kPad (k >> 5) - kElems jf (a
+// row holds 128 values and kPad pad elements per 32).  Every pixel's read is
+// issued, without a branch (a pixel without a value reads the next value's
+// element, clamped to the rows), and its zero selected afterwards.
 template <int WB, class R>
 __device__ __forceinline__ void dec_tile_scatter(const DecItem& it, uint32_t p0, uint32_t bits, uint32_t k,
                                                  uint32_t jf, const DecTileLds<R>& L) {
+    static_assert(RowT<R>::kElems == 128 + 4 * RowT<R>::kPad, "a row is 128 values and four pads");
+    constexpr uint32_t kLast = kTileFrames * RowT<R>::kElems - 1;
+    const uint32_t rbase = RowT<R>::kElems * jf;
     uint32_t v[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
-        const bool on = (bits >> i) & 1u;
-        v[i] = on ? (uint32_t)L.rows[tword<R>(k, jf)] : 0u;
-        k += on ? 1u : 0u;
+        const uint32_t on = (bits >> i) & 1u;
+        const uint32_t x = L.rows[min(k + RowT<R>::kPad * (k >> 5) - rbase, kLast)];
+        v[i] = on ? x : 0u;
+        k += on;
     }
     store16<WB>(it.out, p0, it.npx, it.aligned16, v);
     if (p0 + 16 < it.npx) store16<WB>(it.out, p0 + 16, it.npx, it.aligned16, v + 16);
