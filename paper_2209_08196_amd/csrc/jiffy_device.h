@@ -264,8 +264,11 @@ template <int Q> __device__ __forceinline__ uint32_t quad_bcast(uint32_t v) { re
 constexpr uint32_t kTileFrames = kFTile / kFrame + 1;  // frames a tile's values can touch
 constexpr uint32_t kTileQuads = kFTile / kFrame;       // frames a tile can hold whole
 
-// value kb.. of a tile: frame (k >> 7) - jf of the tile's rows
-__device__ __forceinline__ uint32_t tile_word(uint32_t k, uint32_t jf) { return ((k >> 7) - jf) * kRow + row_off(k & 127u); }
+// value kb.. of a tile: frame (k >> 7) - jf of the tile's rows, element
+// row_off(k & 127).  A row is 128 values and four pads per 32, so this is
+// k + 4 (k >> 5) - kRow jf: two operations and a uniform term per value.
+static_assert(kRow == kFrame + 16, "a row is 128 values and four pads per 32");
+__device__ __forceinline__ uint32_t tile_word(uint32_t k, uint32_t jf) { return k + ((k >> 5) << 2) - kRow * jf; }
 
 // Frame rows of 32-bit values (32-bit samples) or 16-bit values (8- and
 // 16-bit samples, whose residuals and running sums fit 16 bits): each lane's

@@ -55,7 +55,6 @@ __device__ __forceinline__ uint32_t tile_owner(const JG uint32_t* item_of, const
 template <bool kStash>
 __device__ __forceinline__ uint32_t quad_frame_key(uint32_t z[32], uint32_t* vrow, uint32_t* hist, uint32_t real,
                                                    uint32_t pred, uint32_t bits, uint32_t q, uint32_t& Bout) {
-    const uint32_t m = low_mask32(bits);
     uint4* h4 = (uint4*)hist;
     h4[2 * q] = make_uint4(0u, 0u, 0u, 0u);
     h4[2 * q + 1] = make_uint4(0u, 0u, 0u, 0u);
@@ -67,7 +66,7 @@ __device__ __forceinline__ uint32_t quad_frame_key(uint32_t z[32], uint32_t* vro
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
         const uint32_t x = z[i];
-        const uint32_t r = (i0 + i < real) ? zigzag((x - prev) & m, bits) : 0u;
+        const uint32_t r = (i0 + i < real) ? zigzag(x - prev, bits) : 0u;  // zigzag keeps the low `bits` bits only
         prev = x;
         z[i] = r;
         const uint32_t w = r ? 32u - __clz(r) : 0u;
