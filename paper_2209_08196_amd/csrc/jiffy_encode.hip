@@ -61,18 +61,26 @@ __device__ __forceinline__ uint32_t quad_frame_key(uint32_t z[32], uint32_t* vro
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     uint32_t prev = dpp_mov<0x111>(z[31]);  // the previous lane's last value
     if (q == 0) prev = pred;
-    uint32_t B = 0;
-    const uint32_t i0 = 32u * q;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
+    const uint32_t i0 = 32u * q, zslot = 32u + q;
+    uint32_t orv = 0;  // the widest code is the width of their OR
+    // a code of width w >= 1 counts in word w - 1 = 31 - clz, a zero in the lane's own word
+    auto code = [&](int i, bool real_i) {
         const uint32_t x = z[i];
-        const uint32_t r = (i0 + i < real) ? zigzag(x - prev, bits) : 0u;  // zigzag keeps the low `bits` bits only
+        const uint32_t r = real_i ? zigzag(x - prev, bits) : 0u;  // zigzag keeps the low `bits` bits only
         prev = x;
         z[i] = r;
-        const uint32_t w = r ? 32u - __clz(r) : 0u;
-        B = max(B, w);
-        __hip_atomic_fetch_add(hist + (w ? w - 1u : 32u + q), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        orv |= r;
+        __hip_atomic_fetch_add(hist + (r ? 31u - (uint32_t)__builtin_clz(r) : zslot), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+    };
+    if (i0 + 32u <= real) {  // every value of the lane is real (all but a record's last frame)
+#pragma unroll
+        for (int i = 0; i < 32; ++i) code(i, true);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) code(i, i0 + i < real);
     }
+    uint32_t B = orv ? 32u - (uint32_t)__builtin_clz(orv) : 0u;
     B = max(B, dpp_mov<kQuadXor1>(B));
     B = max(B, dpp_mov<kQuadXor2>(B));
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
