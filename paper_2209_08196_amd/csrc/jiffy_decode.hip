@@ -788,13 +788,23 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     row_get<R>(row, q, z);
-    // deltas of the tile's own values, inclusive running sum over the lane
+    // deltas of the tile's own values, inclusive running sum over the lane:
+    // bit i of `in` is set when value k0 + i lies in [kb, ke)
     const uint32_t k0 = j * kFrame + i0;
+    const uint32_t lo = kb > k0 ? min(kb - k0, 32u) : 0u, hi = ke > k0 ? min(ke - k0, 32u) : 0u;
+    const uint32_t in = (hi >= 32 ? ~0u : (1u << hi) - 1u) & ~(lo >= 32 ? ~0u : (1u << lo) - 1u);
+    if (in == ~0u) {
 #pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        const uint32_t k = k0 + i;
-        lane_sum += (k >= kb && k < ke) ? unzigzag(z[i], it.bits) : 0u;
-        d[i] = lane_sum;
+        for (int i = 0; i < 32; ++i) {
+            lane_sum += unzigzag(z[i], it.bits);
+            d[i] = lane_sum;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            lane_sum += ((in >> i) & 1u) ? unzigzag(z[i], it.bits) : 0u;
+            d[i] = lane_sum;
+        }
     }
 }
 
