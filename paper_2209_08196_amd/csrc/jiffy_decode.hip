@@ -231,8 +231,9 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
         for (int j = kSeg - 1; j >= 0; --j) {
             const uint32_t i = s0 + j;
             if (i < s1) {
-                const uint32_t h = (uint32_t)(((((uint64_t)u[(j >> 2) + 1]) << 32) | u[j >> 2]) >> (8 * (j & 3))) &
-                                   0xFFFFFFu;
+                // bytes j .. j+2 of the segment from two whole words (a 64-bit
+                // shift here makes the compiler keep u[] in memory)
+                const uint32_t h = __builtin_amdgcn_alignbyte(u[(j >> 2) + 1], u[j >> 2], j & 3) & 0xFFFFFFu;
                 const uint32_t last = h & 1, type = (h >> 1) & 3, size = h >> 3;
                 uint32_t n = i + 3 + (type ? 1u : size);
                 if (i + 3 > flen || type > 1 || size > kZstdBlockMax) n = kJInvalid;

@@ -666,6 +666,7 @@ struct RunBits {
 };
 __device__ __forceinline__ void classify32(const EncItem& it, uint32_t mode, uint32_t nm, uint32_t b0, RunBits& R) {
     const int w0 = (int)(b0 >> 3) - 2;  // b0 is a multiple of 32
+#pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int w = w0 + k;
         R.win[k] = (w >= 0 && (uint32_t)w < it.nwords && 8u * (uint32_t)w < nm) ? content_word(it, mode, w) : 0ull;
@@ -705,6 +706,17 @@ __device__ __forceinline__ void classify32(const EncItem& it, uint32_t mode, uin
     R.start = (uint32_t)st & valid;
 }
 
+// Content byte b0 + k (k < 32) of a classified window: selects among its four
+// middle words, so that the window stays in registers (an index computed at
+// run time would move it to scratch memory).
+__device__ __forceinline__ uint32_t win_byte(const RunBits& R, uint32_t k) {
+    const uint32_t q = k >> 3;
+    uint64_t w = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) w |= R.win[2 + c] & (q == c ? ~0ull : 0ull);
+    return (uint32_t)(w >> (8 * (k & 7))) & 0xFFu;
+}
+
 constexpr uint32_t kMfThreads = 512;  // one workgroup per record covers 16 KiB of mask content per round
 constexpr uint32_t kMfStep = kMfThreads * 32;
 constexpr uint32_t kMfKeep = 2;        // rounds whose classification stays in registers between passes
@@ -729,7 +741,7 @@ __device__ __forceinline__ void mframe_starts(const EncItem& it, const RunBits& 
         if (to_ws) it.segs[sid] = e;
         else if (sid < kMfSegLds) {
             M.segs[sid] = e;
-            M.segb[sid] = (uint8_t)(R.win[2 + (k >> 3)] >> (8 * (k & 7)));
+            M.segb[sid] = (uint8_t)win_byte(R, k);
         }
         ++sid;
     }
@@ -816,7 +828,7 @@ __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, co
             if ((R.lng >> k) & 1u) continue;
             const uint32_t i = b0 + k;
             const uint32_t q = (i - sstart) / kZstdBlockMax;
-            f[soff + 3u * (q + 1u) + (i - sstart)] = (uint8_t)(R.win[2 + (k >> 3)] >> (8 * (k & 7)));
+            f[soff + 3u * (q + 1u) + (i - sstart)] = (uint8_t)win_byte(R, k);
         }
         seg_carry += total;
     };
