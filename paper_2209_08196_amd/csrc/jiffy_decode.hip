@@ -783,7 +783,15 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
         for (uint32_t e = q; e < n; e += 4) {
             const uint32_t p = pos[e];
             if (p >= real || (e && pos[e - 1] >= p)) { bad = 1; continue; }
-            row[roff<R>(p)] |= bits_at<!kStaged>(words, high_bit + e * hw, hw) << b;
+            // OR the high part in without waiting for the element (positions
+            // increase strictly, so no two lanes touch one element; a 16-bit
+            // element is ORed into its 32-bit word, the other half unchanged)
+            const uint32_t x = bits_at<!kStaged>(words, high_bit + e * hw, hw) << b, idx = roff<R>(p);
+            if (sizeof(R) == 4)
+                __hip_atomic_fetch_or((uint32_t*)row + idx, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            else
+                __hip_atomic_fetch_or((uint32_t*)row + (idx >> 1), x << (16 * (idx & 1)), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
         if (bad) atomicOr(&L.bad, 1u);
     }
