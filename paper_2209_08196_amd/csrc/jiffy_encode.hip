@@ -10,7 +10,7 @@
 //                  record's tiles), zero removal, temporal difference
 //                  (Sec. III-D), delta, ZigZag (Eq. 1), frame width choice and
 //                  bit packing (Sec. II)
-//   k_enc_fixup    the same for frames that cross tile boundaries
+//   (k_enc_mframe's last workgroups: the same for frames that cross tile boundaries)
 //   k_enc_mframe   mask (XOR previous for a P-scan, Sec. III-D) as a Raw/RLE
 //                  Zstandard frame (Sec. III-C)
 //   k_enc_sizes    per-record section layout (prefix sums of frame sizes)
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
 // wholly inside the tile (at most 64).  A frame that crosses a tile
 // boundary is staged in its slot by each tile it touches (its values, and
 // the value before it by the tile where it starts) and coded by
-// k_enc_fixup.
+// k_enc_mframe's fixup workgroups.
 // ---------------------------------------------------------------------------
 template <int WB>
 __device__ __forceinline__ uint32_t residual_at(const EncItem& it, uint32_t mode, uint32_t p, uint32_t m) {
@@ -545,7 +545,7 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
     const uint32_t pred_v = (tid == 0 && tp) ? residual_at<WB>(it, mode, tp - 1, m) : 0u;
     // the record's size is known in its last tile only: elsewhere a frame that
     // runs past the tile's values is taken to continue in a later tile (if it
-    // is the record's last, k_enc_fixup codes it)
+    // is the record's last, the fixup workgroups code it)
     const uint32_t N = lt + 1 == it.ntiles ? kb + nv : 0xFFFFFFFFu;
     const uint32_t jf = kb >> 7;
     {
@@ -616,13 +616,14 @@ __global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
     }
 }
 
-// The frames that cross tile boundaries: one quad per tile entry (16 per
-// workgroup); the staged values go to the quad's LDS row first.
-__global__ __launch_bounds__(64) void k_enc_fixup(EncPlan plan) {
+// The frames that cross tile boundaries: one quad per tile entry, the tile
+// entries [t0, t0 + kFixQuads) per workgroup; the staged values go to the
+// quad's LDS row first.  Runs in workgroups of k_enc_mframe (see there).
+constexpr uint32_t kFixQuads = 64;
+__device__ void enc_fixup_quads(const EncPlan& plan, uint32_t t0, uint32_t* rows) {
     const uint32_t g = threadIdx.x >> 2, q = threadIdx.x & 3u;
-    const uint32_t t = blockIdx.x * 16 + g;
-    __shared__ uint32_t rows[16 * kRow];
-    if (t >= plan.n_ftiles) return;  // no barrier follows
+    const uint32_t t = t0 + g;
+    if (g >= kFixQuads || t >= plan.n_ftiles) return;  // no barrier follows
     uint32_t lt;
     const uint32_t r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, t, lt);
     const EncItem& it = plan.items[r];
@@ -722,12 +723,13 @@ constexpr uint32_t kMfStep = kMfThreads * 32;
 constexpr uint32_t kMfKeep = 2;        // rounds whose classification stays in registers between passes
 constexpr uint32_t kMfSegLds = 6144;   // segments the LDS table holds (more: the workspace table)
 
-struct MfLds {
-    uint32_t segs[kMfSegLds];    // segment start | RLE << 31
+struct alignas(16) MfLds {
+    uint32_t segs[kMfSegLds];    // segment start | RLE << 31 (also the fixup quads' frame rows)
     uint32_t segoff[kMfSegLds];  // its offset in the frame
     uint8_t segb[kMfSegLds];     // an RLE segment's byte
     uint32_t scratch[kMfThreads / 64 + 1];
 };
+static_assert(sizeof(MfLds) >= kFixQuads * kRow * 4, "the fixup quads' frame rows fit in the mask-frame LDS");
 
 // Pass 1 of one round: the round's segment starts, numbered from nseg, go
 // to the LDS table (those that fit) or to the workspace table.
@@ -842,15 +844,20 @@ __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, co
     }
 }
 
-// One workgroup per record.  Pass 1 finds the segment starts (the first
+// One workgroup per record (the workgroups after them code the tile-crossing
+// frames, enc_fixup_quads).  Pass 1 finds the segment starts (the first
 // kMfKeep rounds' classification is kept in registers for the raw bytes);
 // the segment table lives in LDS when it fits, else in the workspace.
 __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
+    __shared__ MfLds M;
+    if (blockIdx.x >= plan.n_items) {  // the tile-crossing frames: independent of the masks, same launch
+        enc_fixup_quads(plan, (blockIdx.x - plan.n_items) * kFixQuads, (uint32_t*)&M);
+        return;
+    }
     const uint32_t r = blockIdx.x;
     const EncItem it = plan.items[r];
     const uint32_t mode = plan.res[r].mode;
     const uint32_t nm = div_up(it.npx, 8);
-    __shared__ MfLds M;
     const uint32_t hdr = nm <= 255 ? 6u : nm <= 65791 ? 7u : 9u;
     const uint32_t tid = threadIdx.x;
     RunBits Rk[kMfKeep];
@@ -1137,8 +1144,8 @@ hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
     JIFFY_LAUNCH("k_enc_trial", k_enc_trial, dim3(plan.n_items), dim3(256), stream, plan);
     JIFFY_LAUNCH("k_enc_tiles", k_enc_tiles, dim3(plan.n_ftiles), dim3(256), stream, plan);
-    JIFFY_LAUNCH("k_enc_fixup", k_enc_fixup, dim3(div_up(plan.n_ftiles, 16)), dim3(64), stream, plan);
-    JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items), dim3(kMfThreads), stream, plan);
+    JIFFY_LAUNCH("k_enc_mframe", k_enc_mframe, dim3(plan.n_items + div_up(plan.n_ftiles, kFixQuads)),
+                 dim3(kMfThreads), stream, plan);
     JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(kSizeThreads), stream, plan);
     JIFFY_LAUNCH("k_enc_offsets", k_enc_offsets, dim3(1), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_enc_assemble", k_enc_assemble, dim3(plan.max_asm + 1, plan.n_items), dim3(256), stream, plan);
