@@ -788,10 +788,10 @@ int dec_execute(DevCtx& ctx, const HostBuf& upbuf, const DecPrepared& P, hipStre
     if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
     if (launch_dec_prepare(upbuf.d, dev + P.o_err, P.up_bytes, P.plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (launch_decode(P.plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
-    if (hipMemcpyAsync(ctx.down.p, dev + P.o_err, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (launch_dec_report(dev + P.o_err, ctx.down.d, 2, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     prof_collect();
-    const uint32_t* errs = (const uint32_t*)ctx.down.p;
+    const volatile uint32_t* errs = (const volatile uint32_t*)ctx.down.p;
     return (errs[0] | errs[1]) ? JIFFY_E_CORRUPT : JIFFY_OK;
 }
 

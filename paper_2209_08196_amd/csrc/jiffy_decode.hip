@@ -1056,6 +1056,19 @@ __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
     }
 }
 
+// A decode's error words to host-mapped memory: the host reads them once the
+// stream has synchronized, with no copy call.  Kernel parameters are plain
+// pointers (an address-space qualifier would change the device symbol).
+__global__ __launch_bounds__(64) void k_dec_report(const uint32_t* err, uint32_t* host, uint32_t n) {
+    const uint32_t i = threadIdx.x;
+    if (i < n) store_system((JG uint32_t*)host + i, ((const JG uint32_t*)err)[i]);
+}
+
+hipError_t launch_dec_report(const void* dev_err, void* host, uint32_t n, hipStream_t stream) {
+    JIFFY_LAUNCH("k_dec_report", k_dec_report, dim3(1), dim3(64), stream, (const uint32_t*)dev_err, (uint32_t*)host, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
     JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items, plan.pwin + 1), dim3(256), stream, plan);

@@ -204,5 +204,7 @@ hipError_t launch_decode(const DecPlan& plan, hipStream_t stream);
 // window states and, when plan.roff is set, the device-side record index, in
 // one launch.
 hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const DecPlan& plan, hipStream_t stream);
+// Copies n error words of a decode to host-mapped memory (system-scope stores).
+hipError_t launch_dec_report(const void* dev_err, void* host, uint32_t n, hipStream_t stream);
 
 }  // namespace jiffy
