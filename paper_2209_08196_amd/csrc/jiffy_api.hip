@@ -72,10 +72,15 @@ hipError_t grow(HostBuf& b, size_t need) {
 
 // Per-device workspace.  Calls on one device are serialized by `mu` and
 // synchronize their stream before returning, so the buffers are free again.
+// Per device: the encoder's and the decoder's workspaces (separate, so that a
+// decode leaves the encoder's plan image in place), the pinned host buffers,
+// and the number of encoder plan uploads so far (a plan reused with no other
+// upload since needs no upload).
 struct DevCtx {
     std::mutex mu;
-    DevBuf ws;
+    DevBuf ws, ws_dec;
     HostBuf up, down, res;
+    uint64_t enc_gen = 0;
 };
 DevCtx g_ctx[64];
 
@@ -301,9 +306,12 @@ EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev, uint8_t* host_res) {
 // the upload of the plan image by a kernel reading `up_dev` (the device
 // address of the host image), then the kernels; k_enc_offsets writes the
 // lengths and modes to the host results.
-hipError_t enc_enqueue(const EncLayout& Lo, const EncPlan& plan, uint8_t* dev, const void* up_dev, hipStream_t stream) {
-    hipError_t e = launch_copy_in(up_dev, dev + Lo.o_err, Lo.up_bytes(), stream);
-    if (e != hipSuccess) return e;
+hipError_t enc_enqueue(const EncLayout& Lo, const EncPlan& plan, uint8_t* dev, const void* up_dev, hipStream_t stream,
+                       bool upload = true) {
+    if (upload) {
+        hipError_t e = launch_copy_in(up_dev, dev + Lo.o_err, Lo.up_bytes(), stream);
+        if (e != hipSuccess) return e;
+    }
     return launch_encode(plan, stream);
 }
 
@@ -330,12 +338,14 @@ void enc_results(const EncLayout& Lo, const uint8_t* hres, EncResult& result) {
 struct EncPrepared {
     bool valid = false;
     void* ws = nullptr;
+    uint64_t gen = 0;  // the device's upload count when this plan's image was last uploaded
     EncLayout Lo;
 };
 
 int enc_prepare(DevCtx& ctx, HostBuf& up, const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs,
                 EncPrepared& P) {
     P.valid = false;
+    ++ctx.enc_gen;  // the workspace may move or be rewritten: no earlier image is known to be there
     P.Lo = enc_layout(specs, outs);
     if (grow(ctx.ws, P.Lo.total) != hipSuccess) return JIFFY_E_DEVICE;
     if (grow(up, P.Lo.up_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
@@ -345,11 +355,15 @@ int enc_prepare(DevCtx& ctx, HostBuf& up, const std::vector<EncSpec>& specs, con
     return JIFFY_OK;
 }
 
-int enc_execute(DevCtx& ctx, const HostBuf& up, const EncPrepared& P, hipStream_t stream, EncResult& result) {
+// upload = false: the plan's image is still in the workspace (nothing was
+// uploaded or prepared on this device since), so the kernels start at once.
+int enc_execute(DevCtx& ctx, const HostBuf& up, const EncPrepared& P, hipStream_t stream, EncResult& result,
+                bool upload = true) {
     if (grow(ctx.res, P.Lo.res_bytes()) != hipSuccess) return JIFFY_E_DEVICE;
     uint8_t* dev = (uint8_t*)ctx.ws.p;
     const EncPlan plan = enc_plan(P.Lo, dev, (uint8_t*)ctx.res.d);
-    if (enc_enqueue(P.Lo, plan, dev, up.d, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (upload) ++ctx.enc_gen;
+    if (enc_enqueue(P.Lo, plan, dev, up.d, stream, upload) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     prof_collect();
     enc_results(P.Lo, (const uint8_t*)ctx.res.p, result);
@@ -567,7 +581,9 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
     key.cap = cap;
     EncResult res;
     if (C.prep.valid && C.prep.ws == ctx.ws.p && memcmp(&key, &C.key, sizeof key) == 0) {
-        if (int rc = enc_execute(ctx, C.up, C.prep, stream, res)) return rc;
+        const bool resident = C.prep.gen == ctx.enc_gen;  // no other upload or plan on this device since
+        if (int rc = enc_execute(ctx, C.up, C.prep, stream, res, !resident)) return rc;
+        C.prep.gen = ctx.enc_gen;
         *h_out_len = res.lens[0];
         if (!res.ok[0]) return JIFFY_E_CAPACITY;
         if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
@@ -601,6 +617,7 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
     if (int rc = enc_prepare(ctx, C.up, specs, outs, C.prep)) return rc;
     C.key = key;
     if (int rc = enc_execute(ctx, C.up, C.prep, stream, res)) return rc;
+    C.prep.gen = ctx.enc_gen;
     *h_out_len = res.lens[0];
     if (!res.ok[0]) return JIFFY_E_CAPACITY;
     if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
@@ -689,10 +706,10 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     const size_t o_modes = off; off = al(off + n);
     const size_t o_data = off;
     off += per_item * n;
-    if (grow(ctx.ws, off) != hipSuccess) return JIFFY_E_DEVICE;
+    if (grow(ctx.ws_dec, off) != hipSuccess) return JIFFY_E_DEVICE;
     const size_t up_bytes = up_end - o_err;
     if (grow(upbuf, up_bytes) != hipSuccess) return JIFFY_E_DEVICE;
-    uint8_t* dev = (uint8_t*)ctx.ws.p;
+    uint8_t* dev = (uint8_t*)ctx.ws_dec.p;
     uint8_t* up = (uint8_t*)upbuf.p;
     memset(up, 0, up_bytes);
     DecItem* hit = (DecItem*)(up + (o_items - o_err));
@@ -778,13 +795,13 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     P.plan = plan;
     P.o_err = o_err;
     P.up_bytes = up_bytes;
-    P.ws = ctx.ws.p;
+    P.ws = ctx.ws_dec.p;
     P.valid = true;
     return JIFFY_OK;
 }
 
 int dec_execute(DevCtx& ctx, const HostBuf& upbuf, const DecPrepared& P, hipStream_t stream) {
-    uint8_t* dev = (uint8_t*)ctx.ws.p;
+    uint8_t* dev = (uint8_t*)ctx.ws_dec.p;
     if (grow(ctx.down, 64) != hipSuccess) return JIFFY_E_DEVICE;
     if (launch_dec_prepare(upbuf.d, dev + P.o_err, P.up_bytes, P.plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (launch_decode(P.plan, stream) != hipSuccess) return JIFFY_E_DEVICE;
@@ -823,7 +840,7 @@ int run_decode(DevCtx& ctx, const jiffy_layout& L, uint32_t T, const uint8_t* di
     key.din = din;
     key.in_len = in_len;
     for (uint32_t a = 0; a < A; ++a) key.planes[a] = d_planes_out[a];
-    const bool hit = C.prep.valid && C.prep.ws == ctx.ws.p && memcmp(&key, &C.key, sizeof key) == 0 &&
+    const bool hit = C.prep.valid && C.prep.ws == ctx.ws_dec.p && memcmp(&key, &C.key, sizeof key) == 0 &&
                      (!hdr || memcmp(C.prep.plan.hdr_words, hdr, p) == 0);
     if (!hit) {
         if (int rc = dec_prepare(ctx, C.up, L, T, din, in_len, nullptr, nullptr, p, hdr, d_planes_out, C.prep))

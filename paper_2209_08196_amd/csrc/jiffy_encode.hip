@@ -387,6 +387,9 @@ __device__ __forceinline__ void enc_trial_body(const EncItem& it, TrialLds& L, J
 
 __global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
     const uint32_t r = blockIdx.x;
+    // the call's error word starts at zero (a plan reused without an upload
+    // keeps the previous call's); no kernel before k_enc_tiles touches it
+    if (r == 0 && threadIdx.x == 0) *plan.err = 0u;
     const EncItem it = plan.items[r];
     // the record's k_enc_tiles tickets and look-back states start at zero
     for (uint32_t i = threadIdx.x; i < it.ntiles; i += 256) it.tstat[i] = 0;

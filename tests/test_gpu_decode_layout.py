@@ -169,3 +169,39 @@ def test_prepared_encoder_and_decoder(J):
         dcd(s)
         for a, (o, p) in enumerate(zip(outs, data)):
             assert np.array_equal(to_host(o, p.dtype.itemsize), p), (rnd, a)  # P = 1: lossless
+
+
+def test_alternating_plans_and_reuse_after_an_error(J):
+    """Two prepared encoders with different arguments in turn, decodes in
+    between: each call's plan either is still in the workspace or is uploaded
+    again, and every stream equals the oracle's.  A plan reused right after
+    a call that ran out of output space starts with a clear error word."""
+    import torch
+    gA, gB = synth.stream(1, 5), synth.stream(2, 6)
+    xA, xB = gA.scans(0, 3), gB.scans(0, 2)
+    pA, pB = list(gA.precisions), list(gB.precisions)
+    encA = J.Encoder([to_dev(p) for p in xA], pA)
+    encB = J.Encoder([to_dev(p) for p in xB], pB)
+    refA, refB = oracle.encode(xA, pA)[0], oracle.encode(xB, pB)[0]
+    for rnd, (enc, ref) in enumerate([(encA, refA), (encA, refA), (encB, refB), (encA, refA), (encB, refB),
+                                      (encB, refB)]):
+        banner("alternating plans, call", rnd)
+        s, _ = enc()
+        assert s.cpu().numpy().tobytes() == ref, rnd
+        if rnd % 2:
+            J.decode(s)  # the decoder's workspace is its own
+    # an output buffer too small for incompressible samples, then compressible ones in the same planes
+    rng = np.random.default_rng(71)
+    hard = rng.integers(1, 2**32, size=(2, 16, 256), dtype=np.uint64).astype(np.uint32)
+    easy = np.full((2, 16, 256), 1234, np.uint32)
+    dev = to_dev(hard)
+    ref_easy = oracle.encode([easy], [1])[0]
+    out = torch.empty(len(ref_easy) + 64, dtype=torch.uint8, device="cuda")
+    enc = J.Encoder([dev], [1], out=out)
+    banner("capacity error, then the same plan with compressible samples")
+    with pytest.raises(J.JiffyError) as e:
+        enc()
+    assert e.value.code == J.E_CAPACITY
+    dev.copy_(to_dev(easy))
+    s, _ = enc()
+    assert s.cpu().numpy().tobytes() == ref_easy
