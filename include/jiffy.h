@@ -15,8 +15,9 @@
  *
  * Memory: every d_* pointer is device memory owned by the caller; h_*
  * pointers are host memory owned by the caller.  The library owns its
- * workspace (grown on demand per device, kept until process exit) and the
- * resident state of each jiffy_stream.  Calls enqueue work on `stream` and
+ * workspaces (one for encoding and one for decoding per device, grown on
+ * demand, kept until process exit) and the resident state of each
+ * jiffy_stream.  Calls enqueue work on `stream` and
  * synchronize with it once before they return (the byte count, the chosen
  * modes and the status are host values).  Calls on one device are
  * serialized by a per-device lock.
