@@ -12,6 +12,7 @@
 //                  pixels, zeros elsewhere
 //   k_dec_temporal adds the previous scan for P-scans (Sec. III-D) and
 //                  restores the original representation, q * P (Sec. III-A)
+//   k_dec_report   the error words to host-mapped memory
 //
 // Every offset read from the stream is checked before it is used; a
 // malformed stream raises kErrCorrupt and later kernels do nothing.
