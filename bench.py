@@ -1,22 +1,35 @@
 #!/usr/bin/env python3
 """Encode+decode throughput of the Jiffy codec on one MI355X.
 
-Workload: one sensor stream of 100 scans of 128x2048 with five attributes
-(dual-return range u32, second-return range u32, signal u16, reflectivity u8,
-near-IR u16), precision 1 mm, about 20% zero samples, seeded synthetic data
-standing in for the paper's Ouster driving recordings (the sensor drives,
-stops for 30 scans, drives again).  One step encodes all 100 scans
-(jiffy_encode) and decodes the stream back (jiffy_decode); inputs and
-outputs stay in device memory.  A point is one pixel of one attribute, as in
-the paper's points/s (Sec. IV-F).
+Headline workload (the largest configuration that fits one GPU): the
+stress set, 32 independent sensor streams of 200 scans of 128x4096 range
+samples (u32, millimetres, precision 1 mm), 60% zero samples in blobs,
+drone-like motion of 5-15 degrees per scan and a scene cut every 20 scans,
+seeded synthetic data standing in for the paper's recordings.  Each
+stream's first 20-scan scene period is generated on the host and replayed
+ten times on the device (scan 20k+i equals scan i; every 20th scan still
+follows a different view, so it is a scene cut).  One step encodes every
+stream's 200 scans (jiffy_encode, one call per stream) and decodes every
+stream back (jiffy_decode_layout); inputs and outputs stay in device
+memory.  A point is one pixel of one attribute, as in the paper's points/s
+(Sec. IV-F).
 
-Prints one JSON line.  Besides the throughput it carries:
-  roofline      the dominant kernel's algorithmic bytes per launch over its
-                mean launch time (HIP events on the launch stream) against
-                the 8 TB/s HBM peak; `traffic` is the HBM bytes measured with
-                rocprofv3 counters for the same kernel source (or null).
-  cpu_baseline  the CPU oracle (single thread) on the same workload, and
-                whether its stream is byte-identical to the GPU's.
+Further legs (each skippable):
+  batched   the 64-stream batched set (16x1024 .. 128x2048, range at 1 cm
+            and signal), one scan of every stream per step: the plain
+            one-scan-per-launch codec, the batched step and the
+            graph-replayed batch, byte-identical records required, with the
+            batched step's own roofline;
+  serving   the 256-stream serving set under device-memory budgets;
+  cpu       the oracle on a bounded sample of the headline workload, one
+            thread and all host cores, its streams compared byte for byte
+            with the ones the timed GPU encoder wrote.
+
+Prints one JSON line.  `roofline`: the dominant kernel's algorithmic bytes
+per launch (input samples, previous scans of P-records, compressed bytes)
+over its mean launch time (HIP events on the launch stream) against the
+8 TB/s HBM peak; `traffic` is the HBM bytes measured with rocprofv3 counters
+for the same kernel source and workload (or null).
 """
 import argparse
 import hashlib
@@ -33,11 +46,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "encode+decode points/sec & HBM GB/s fraction at byte-identical output"
 HBM_PEAK_GBS = 8000.0
-CID = 2  # the dual-return 128x2048 five-attribute stream
-N_SCANS = 100
+HEAD_CID = 5       # the stress set: 32 streams x 200 scans of 128x4096
+SCENE_PERIOD = 20  # scans per scene of the stress set (the part that is generated)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_08196_amd", "csrc", f)
                   for f in ("jiffy_encode.hip", "jiffy_decode.hip", "jiffy_device.h", "jiffy_internal.h")]
+_STORE = {1: np.uint8, 2: np.int16, 4: np.int32}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def source_sha():
@@ -47,15 +65,39 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def stream_stats(s: bytes, widths, npx):
-    """Sizes of the stream's parts, read from its header and record headers."""
+def pool_size():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+# ---------------------------------------------------------------------------
+# synthetic inputs (generated in worker processes before the GPU is touched)
+# ---------------------------------------------------------------------------
+def _gen(job):
+    from paper_2209_08196_amd import synth
+    cid, sid, t0, t1 = job
+    return synth.stream(cid, sid).scans(t0, t1)
+
+
+def generate(jobs):
+    """Scan arrays for (cid, stream, t0, t1) jobs, in a process pool."""
+    import multiprocessing as mp
+    n = pool_size()
+    if n == 1 or len(jobs) == 1:
+        return [_gen(j) for j in jobs]
+    with mp.get_context("fork").Pool(min(n, len(jobs))) as pool:
+        return pool.map(_gen, jobs, chunksize=1)
+
+
+# ---------------------------------------------------------------------------
+# stream statistics (from the stream's own headers)
+# ---------------------------------------------------------------------------
+def stream_stats(s: bytes, widths, npx, precisions):
     A, = struct.unpack_from("<H", s, 6)
     T, = struct.unpack_from("<I", s, 16)
     p = 20 + 8 * A
     lens = struct.unpack_from(f"<{T * A}I", s, p)
     p += 4 * T * A
-    st = dict(mask_bytes=0, frame_bytes=0, n_values=0, p_items=0, p_bytes=0, i_items=0,
-              frame_bytes_w32=0, items_w32=0, x_bytes_w32=0, p_bytes_w32=0)
+    st = dict(mask_bytes=0, frame_bytes=0, n_values=0, p_items=0, p_bytes=0, i_items=0, x_bytes=0)
     for r, L in enumerate(lens):
         a = r % A
         mode = s[p + 4]
@@ -63,23 +105,16 @@ def stream_stats(s: bytes, widths, npx):
         sec = (12 + flen + 3) & ~3
         N, = struct.unpack_from("<I", s, p + sec)
         nb = (N + 127) // 128
-        hdr4 = (4 + 3 * nb + 3) & ~3
         b = np.frombuffer(s, np.uint8, nb, p + sec + 4).astype(np.int64)
         n = np.frombuffer(s, np.uint8, nb, p + sec + 4 + nb).astype(np.int64)
         B = np.frombuffer(s, np.uint8, nb, p + sec + 4 + 2 * nb).astype(np.int64)
-        fb = int((16 * b + n + (n * (B - b) + 7) // 8).sum())
-        st["frame_bytes"] += fb
-        if widths[a] == 4:
-            st["frame_bytes_w32"] += fb
-            st["items_w32"] += 1
-            st["x_bytes_w32"] += 4 * npx
+        st["frame_bytes"] += int((16 * b + n + (n * (B - b) + 7) // 8).sum())
         st["mask_bytes"] += flen
         st["n_values"] += N
+        st["x_bytes"] += widths[a] * npx
         if mode == 1:
             st["p_items"] += 1
             st["p_bytes"] += widths[a] * npx
-            if widths[a] == 4:
-                st["p_bytes_w32"] += 4 * npx
         else:
             st["i_items"] += 1
         p += L
@@ -87,95 +122,302 @@ def stream_stats(s: bytes, widths, npx):
     return st
 
 
-def kernel_alg_bytes(name, st, x_bytes, n_items, nwords):
-    """Bytes each kernel must move for the whole workload (one launch): its
-    inputs read once and its outputs written once, intermediates it cannot
-    avoid included (the valid-sample words, the packed frames)."""
-    vb = 8 * nwords * n_items          # valid-sample words of every record
-    vbp = 8 * nwords * st["p_items"]   # the previous scan's, for P-records
-    F, M, S = st["frame_bytes"], st["mask_bytes"], st["stream_bytes"]
-    Xp = st["p_bytes"]                 # samples of the P-records
-    table = {
-        "k_enc_tiles": x_bytes + Xp + vb + F,  # samples (+ previous scan) in, valid words and packed frames out
-        "k_enc_mframe": vb + vbp + M,          # valid words in, mask frames out
-        "k_enc_assemble": F + M + S,           # frames and masks in, stream out
-        "k_dec_parse": M + vb,                 # mask frames in, valid words out
-        "k_dec_mask": 2 * vb + vbp,            # mask chain over time
-        "k_dec_tiles_w32": st["frame_bytes_w32"] + 8 * nwords * st["items_w32"] + st["x_bytes_w32"],
-        "k_dec_tiles_w16": (F - st["frame_bytes_w32"]) + 8 * nwords * (n_items - st["items_w32"])
-                           + (x_bytes - st["x_bytes_w32"]),
-        "k_dec_temporal": 3 * Xp,              # P-scans: read both scans, write one
+def add_stats(stats):
+    out = {}
+    for st in stats:
+        for k, v in st.items():
+            out[k] = out.get(k, 0) + v
+    return out
+
+
+def split_records(s: bytes):
+    """The records of a stream with a record-length table."""
+    A, = struct.unpack_from("<H", s, 6)
+    T, = struct.unpack_from("<I", s, 16)
+    p = 20 + 8 * A
+    lens = struct.unpack_from(f"<{T * A}I", s, p)
+    p += 4 * T * A
+    out = []
+    for L in lens:
+        out.append(s[p:p + L])
+        p += L
+    return out
+
+
+def record_stats(recs, widths, npx, precisions):
+    """As stream_stats, for a list of records of one scan each (attribute order)."""
+    st = dict(p_items=0, p_bytes=0, i_items=0, x_bytes=0, q_bytes=0, stream_bytes=0)
+    for k, r in enumerate(recs):
+        a = k % len(widths)
+        st["x_bytes"] += widths[a] * npx
+        st["stream_bytes"] += len(r)
+        if precisions[a] > 1:
+            st["q_bytes"] += widths[a] * npx
+        if r[4] == 1:
+            st["p_items"] += 1
+            st["p_bytes"] += widths[a] * npx
+        else:
+            st["i_items"] += 1
+    return st
+
+
+def kernel_profile(run, reps):
+    """Per-kernel mean launch times (HIP events on the launch stream) over
+    `reps` calls of run()."""
+    import torch
+    from paper_2209_08196_amd import jiffy
+    torch.cuda.synchronize()
+    jiffy.profile_enable(True)
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    prof = jiffy.profile_read()
+    jiffy.profile_enable(False)
+    return {k: dict(avg_ms=v[0] / v[1], launches=v[1]) for k, v in prof.items()}
+
+
+def roofline(kernels, alg_per_launch, workload):
+    """The roofline object of the dominant kernel: algorithmic bytes per
+    launch (encode: samples in + previous scans of P-records + compressed
+    bytes out) over its mean launch time."""
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    alg = alg_per_launch(dom)
+    avg_s = kernels[dom]["avg_ms"] / 1e3
+    achieved = alg / avg_s / 1e9 if alg else None
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        ent = tr.get("workloads", {}).get(workload, {}).get("kernels", {}).get(dom)
+        if ent and tr.get("source_sha") == source_sha():
+            traffic = ent["fetch_bytes"] + ent["write_bytes"]
+    return {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": traffic, "kernel": dom, "alg_bytes_per_launch": alg,
+            "avg_launch_ms": round(kernels[dom]["avg_ms"], 4)}
+
+
+# ---------------------------------------------------------------------------
+# headline: the stress set, encode + decode of whole streams
+# ---------------------------------------------------------------------------
+def headline(args, host_period):
+    import torch
+
+    from paper_2209_08196_amd import jiffy, synth
+    cfg = synth.CONFIGS[HEAD_CID]
+    S = len(host_period) if args.streams is None else min(args.streams, len(host_period))
+    T = cfg.scans
+    reps = T // SCENE_PERIOD
+    g0 = synth.stream(HEAD_CID, 0)
+    H, W, widths, precs = g0.H, g0.W, g0.widths, g0.precisions
+    A = len(widths)
+    npx = H * W
+    lay = jiffy.make_layout(H, W, widths, precs)
+    bound = jiffy.encode_bound(lay, T)
+    dev, outs, decs, encs, dcds = [], [], [], [], []
+    stream = torch.cuda.current_stream()
+    for s in range(S):
+        per = [torch.from_numpy(p.view(_STORE[p.dtype.itemsize])).cuda() for p in host_period[s]]
+        dev.append([p.repeat(reps, 1, 1).contiguous() for p in per])
+        outs.append(torch.empty(bound, dtype=torch.uint8, device="cuda"))
+        decs.append([torch.empty_like(d) for d in dev[-1]])
+        encs.append(jiffy.Encoder(dev[-1], precs, out=outs[-1], stream=stream))
+        dcds.append(jiffy.Decoder(lay, T, decs[-1], stream=stream))
+    log(f"headline: {S} streams x {T} scans of {H}x{W} resident ({S * T * npx * 4 / 1e9:.1f} GB of samples)")
+    points = S * T * npx * A
+
+    def step():
+        res = []
+        for s in range(S):
+            b, m = encs[s]()
+            dcds[s](b)
+            res.append((b, m))
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * S + 1)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ev in evs:
+        ev[0].record(stream)
+        for s in range(S):
+            b, _ = encs[s]()
+            ev[2 * s + 1].record(stream)
+            dcds[s](b)
+            ev[2 * s + 2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    enc_ms = sum(ev[2 * s].elapsed_time(ev[2 * s + 1]) for ev in evs for s in range(S))
+    dec_ms = sum(ev[2 * s + 1].elapsed_time(ev[2 * s + 2]) for ev in evs for s in range(S))
+    ms_per_step = 1e3 * wall / args.steps
+    log(f"headline: {args.steps} steps, {ms_per_step:.2f} ms/step")
+
+    # the outputs of the last timed step: lossless round trip (precision 1)
+    streams_host, modes_all = [], []
+    for s in range(S):
+        n = encs[s]._n.value
+        streams_host.append(outs[s][:n].cpu().numpy().tobytes())
+        modes_all.append(encs[s]._modes[:T].copy())
+        for d, x in zip(decs[s], dev[s]):
+            if not torch.equal(d, x):
+                raise SystemExit(f"stream {s}: decode(encode(x)) != x")
+    stats = add_stats(stream_stats(b, widths, npx, precs) for b in streams_host)
+    x_bytes = stats["x_bytes"]
+    log(f"headline: {stats['stream_bytes']} bytes, ratio {x_bytes / stats['stream_bytes']:.2f}, "
+        f"P-records {stats['p_items']} of {stats['p_items'] + stats['i_items']}")
+
+    kernels = {}
+    if args.profile_steps > 0:
+        kernels = kernel_profile(step, args.profile_steps)
+
+    def alg(name):  # per launch: one stream per launch of every kernel
+        if name.startswith("k_enc"):
+            return (stats["x_bytes"] + stats["p_bytes"] + stats["stream_bytes"]) // S
+        if name.startswith("k_dec"):
+            return (stats["stream_bytes"] + stats["x_bytes"] + stats["p_bytes"]) // S
+        return None
+
+    path_alg = 2 * (x_bytes + stats["p_bytes"] + stats["stream_bytes"])
+    result = {
+        "metric": METRIC, "value": round(points / (wall / args.steps), 1), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"stress-128x4096-drone-range-1mm: {S} streams x {T} scans of {H}x{W} range u32, "
+                               f"precision 1 mm, 60% zeros, 5-15 deg/scan, scene cut every {SCENE_PERIOD} scans "
+                               f"(each stream's first {SCENE_PERIOD}-scan period generated and replayed {reps}x); "
+                               "encode+decode of every stream per step",
+                   "streams": S, "scans": T, "height": H, "width": W, "attributes": ["range"], "precision_mm": 1},
+        "encode_points_per_s": round(points / (enc_ms / args.steps / 1e3), 1),
+        "decode_points_per_s": round(points / (dec_ms / args.steps / 1e3), 1),
+        "compression_ratio": round(x_bytes / stats["stream_bytes"], 3),
+        "p_records": stats["p_items"], "i_records": stats["i_items"],
+        "path_alg_gbps": round(path_alg / (wall / args.steps) / 1e9, 1),
+        "path_hbm_frac": round(path_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
     }
-    return table.get(name)
+    if kernels:
+        result["roofline"] = roofline(kernels, alg, "stress")
+        result["kernels_ms"] = {k: round(v["avg_ms"], 4)
+                                for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_ms"])}
+    ctx = dict(streams=streams_host, modes=modes_all, S=S, T=T, precs=precs)
+    # free the device buffers of this leg before the next
+    del dev, outs, decs, encs, dcds
+    torch.cuda.empty_cache()
+    return result, ctx
 
 
-def batched_leg(steps, warmup):
-    """64 sensor streams of four sizes (16x1024, 32x2048, 64x1024, 128x2048;
-    range u32 at 1 cm and signal u16), one scan of every stream per step:
-    the graph-replayed batch (jiffy_batch_run) against the plain batched
-    call (jiffy_batch_encode_step) on twin streams, with byte-identical
-    records required."""
+# ---------------------------------------------------------------------------
+# batched: 64 streams, one scan each per step
+# ---------------------------------------------------------------------------
+def batched_leg(host, steps, warmup):
+    """host[s]: stream s's scans (list per attribute of [T, H, W]).  Every
+    step encodes one scan of every stream three ways on twin streams:
+    one jiffy_batch_encode_step per stream (the plain one-scan-per-launch
+    codec), one jiffy_batch_encode_step over all 64, and one replay of the
+    batch's HIP graph (jiffy_batch_run).  Records must be identical."""
     import torch
 
     from paper_2209_08196_amd import jiffy, synth
     cfg = synth.CONFIGS[3]
+    gens = [synth.stream(3, s) for s in range(len(host))]
     T = warmup + steps
-    gens = [synth.stream(3, s) for s in range(cfg.streams)]
-    store = {1: np.uint8, 2: np.int16, 4: np.int32}
-    scans = [[torch.from_numpy(p.view(store[p.dtype.itemsize])).cuda() for p in g.scans(0, T)] for g in gens]
+    scans = [[torch.from_numpy(p[:T].view(_STORE[p.dtype.itemsize])).cuda() for p in h] for h in host]
     points = sum(g.H * g.W * len(g.widths) for g in gens)
     mk = lambda: [jiffy.Stream(g.H, g.W, g.widths, g.precisions) for g in gens]  # noqa: E731
-    sg, sp = mk(), mk()
-    inputs = [[p[0] for p in sc] for sc in scans]
-    outs_g = [torch.empty(s.record_bound(), dtype=torch.uint8, device="cuda") for s in sg]
-    outs_p = [torch.empty(s.record_bound(), dtype=torch.uint8, device="cuda") for s in sp]
-    batch = jiffy.Batch(sg, inputs, outs_g)
+    s1, sb, sg = mk(), mk(), mk()
+    mko = lambda ss: [torch.empty(s.record_bound(), dtype=torch.uint8, device="cuda") for s in ss]  # noqa: E731
+    o1, ob, og = mko(s1), mko(sb), mko(sg)
+    batch = jiffy.Batch(sg, [[p[0] for p in sc] for sc in scans], og)
     identical = True
-    tg = tp = 0.0
+    t1 = tb = tg = 0.0
     for t in range(T):
+        at = [[p[t] for p in sc] for sc in scans]
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lg, _ = batch.run([[p[t] for p in sc] for sc in scans])
-        t1 = time.perf_counter()
-        lp, _ = jiffy.batch_encode_step(sp, [[p[t] for p in sc] for sc in scans], outs_p)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
+        a = time.perf_counter()
+        l1 = [jiffy.batch_encode_step([s1[i]], [at[i]], [o1[i]])[0][0] for i in range(len(gens))]
+        b = time.perf_counter()
+        lb, _ = jiffy.batch_encode_step(sb, at, ob)
+        c = time.perf_counter()
+        lg, _ = batch.run(at)
+        d = time.perf_counter()
         if t >= warmup:
-            tg += t1 - t0
-            tp += t2 - t1
-        if lg != lp or any(not torch.equal(outs_g[i][: lg[i]], outs_p[i][: lp[i]]) for i in range(len(gens))):
-            identical = False
-    batch.close()
-    for s in sg + sp:
+            t1 += b - a
+            tb += c - b
+            tg += d - c
+        for i in range(len(gens)):
+            if not (l1[i] == lb[i] == lg[i] and torch.equal(o1[i][:l1[i]], ob[i][:lb[i]])
+                    and torch.equal(ob[i][:lb[i]], og[i][:lg[i]])):
+                identical = False
+    log(f"batched: one-scan-per-launch {1e3 * t1 / steps:.3f} ms, batched {1e3 * tb / steps:.3f} ms, "
+        f"graph {1e3 * tg / steps:.3f} ms per step")
+    # per-kernel times of the batched step: the same steps again on fresh twin streams, with HIP
+    # events around every launch from the first timed step on; the algorithmic bytes of those steps
+    # come from their records
+    sp = mk()
+    op = mko(sp)
+    rs = []
+    for t in range(T):
+        if t == warmup:
+            torch.cuda.synchronize()
+            jiffy.profile_enable(True)
+        lp, _ = jiffy.batch_encode_step(sp, [[p[t] for p in sc] for sc in scans], op)
+        if t >= warmup:
+            for i, g in enumerate(gens):
+                buf = op[i][:lp[i]].cpu().numpy().tobytes()
+                recs, p = [], 0
+                for _ in range(len(g.widths)):
+                    L, = struct.unpack_from("<I", buf, p)
+                    recs.append(buf[p:p + L])
+                    p += L
+                rs.append(record_stats(recs, g.widths, g.H * g.W, g.precisions))
+    torch.cuda.synchronize()
+    prof = jiffy.profile_read()
+    jiffy.profile_enable(False)
+    kernels = {k: dict(avg_ms=v[0] / v[1], launches=v[1]) for k, v in prof.items()}
+    st = add_stats(rs)
+    # per step: samples in, previous scans of P-records, quantized state of P > 1 attributes, records out
+    alg_step = (st["x_bytes"] + st["p_bytes"] + st["q_bytes"] + st["stream_bytes"]) // steps
+    rl = roofline(kernels, lambda name: alg_step if name.startswith("k_enc") else None, "batched")
+    for s in sp:
         s.close()
-    return {"workload": f"{cfg.name}, {steps} steps", "streams": cfg.streams, "points_per_step": points,
+    batch.close()
+    for s in s1 + sb + sg:
+        s.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"{cfg.name}: 64 streams (16 each of 16x1024, 32x2048, 64x1024, 128x2048), range u32 "
+                        f"at 1 cm + signal u16, one scan per stream per step, {steps} timed steps",
+            "streams": len(gens), "points_per_step": points,
+            "batched_points_per_s": round(points * steps / tb, 1), "batched_ms_per_step": round(1e3 * tb / steps, 3),
             "graph_points_per_s": round(points * steps / tg, 1), "graph_ms_per_step": round(1e3 * tg / steps, 3),
-            "plain_points_per_s": round(points * steps / tp, 1), "plain_ms_per_step": round(1e3 * tp / steps, 3),
-            "byte_identical": identical}
+            "one_scan_per_launch_points_per_s": round(points * steps / t1, 1),
+            "one_scan_per_launch_ms_per_step": round(1e3 * t1 / steps, 3),
+            "alg_bytes_per_step": alg_step,
+            "path_alg_gbps": round(alg_step * steps / tb / 1e9, 1),
+            "byte_identical": identical, "roofline": rl,
+            "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_ms"])}}
 
 
+# ---------------------------------------------------------------------------
+# serving: 256 streams under device-memory budgets
+# ---------------------------------------------------------------------------
 def serving_leg(duration_s, budgets, scans_per_stream=2):
     """256 sensor streams (32x1024 .. 128x2048, range u32 and three u16
     attributes at 1 mm; 10 or 20 Hz each with random phase and jitter)
     served by continuous batching under device-memory budgets.  Each stream
-    cycles through its first `scans_per_stream` synthetic scans.  Latency =
-    records on the host minus arrival, in virtual time (each step advances
-    the clock by its measured duration).  One served stream's records are
-    compared with encoding its whole sequence alone (jiffy_encode)."""
+    cycles through its first `scans_per_stream` synthetic scans.  One served
+    stream's records are compared with encoding its whole sequence alone."""
     import torch
 
     from paper_2209_08196_amd import jiffy, serve, synth
     cfg = synth.CONFIGS[4]
     gens = [synth.stream(4, s) for s in range(cfg.streams)]
-    store = {1: np.uint8, 2: np.int16, 4: np.int32}
     host = [g.scans(0, scans_per_stream) for g in gens]
-    dev = [[torch.from_numpy(p.view(store[p.dtype.itemsize])).cuda() for p in h] for h in host]
+    dev = [[torch.from_numpy(p.view(_STORE[p.dtype.itemsize])).cuda() for p in h] for h in host]
     specs = {s: serve.StreamSpec(g.H, g.W, tuple(g.widths), tuple(g.precisions)) for s, g in enumerate(gens)}
     arrivals = synth.serving_arrivals(cfg.streams, duration_s)
-    check = arrivals[0][1]  # the first stream to arrive is admitted under any budget that admits one
+    check = arrivals[0][1]
     ks = [k for _, s, k in arrivals if s == check]
     g = gens[check]
-    # its alone-encoding: the whole sequence in one jiffy_encode call
     seq = [torch.stack([dev[check][a][k % scans_per_stream] for k in ks]).contiguous() for a in range(len(g.widths))]
     alone, _ = jiffy.encode(seq, g.precisions)
     want = split_records(alone.cpu().numpy().tobytes())
@@ -191,24 +433,62 @@ def serving_leg(duration_s, budgets, scans_per_stream=2):
             r == b"".join(want[k * A:(k + 1) * A]) for k, r in enumerate(got))
         srv.close()
         out[f"budget_{budget >> 20}MiB"] = res
-        print(f"[bench] serving budget {budget >> 20} MiB: {res}", file=sys.stderr, flush=True)
+        log(f"serving budget {budget >> 20} MiB: {res}")
     return out
 
 
-def split_records(s: bytes):
-    """The records of a stream with a record-length table (its header)."""
-    A, = struct.unpack_from("<H", s, 6)
-    T, = struct.unpack_from("<I", s, 16)
-    p = 20 + 8 * A
-    lens = struct.unpack_from(f"<{T * A}I", s, p)
-    p += 4 * T * A
-    out = []
-    for L in lens:
-        out.append(s[p:p + L])
-        p += L
-    return out
+# ---------------------------------------------------------------------------
+# the oracle on the host (test infrastructure, timed as the CPU baseline)
+# ---------------------------------------------------------------------------
+def cpu_leg(host_period, ctx, n_single, n_all):
+    """The oracle on whole 200-scan streams of the headline workload: one
+    stream on one thread, then one stream per thread on all host cores.
+    Their streams are compared byte for byte with the timed GPU encoder's."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    T, precs = ctx["T"], ctx["precs"]
+    reps = T // SCENE_PERIOD
+
+    def one(s):
+        planes = [np.ascontiguousarray(np.tile(p, (reps, 1, 1))) for p in host_period[s]]
+        t0 = time.perf_counter()
+        ref, modes = oracle.encode(planes, precs)
+        t1 = time.perf_counter()
+        oracle.decode(ref)
+        t2 = time.perf_counter()
+        same = ref == ctx["streams"][s] and bool(np.array_equal(modes, ctx["modes"][s]))
+        return t1 - t0, t2 - t1, same, sum(p.size for p in planes)
+
+    log(f"cpu: oracle on {n_single} stream(s), one thread")
+    t0 = time.perf_counter()
+    single = [one(s) for s in range(n_single)]
+    w1 = time.perf_counter() - t0
+    pts1 = sum(r[3] for r in single)
+    threads = min(n_all, pool_size())
+    log(f"cpu: oracle on {n_all} streams, {threads} threads")
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:  # the oracle releases the GIL inside its C calls
+        multi = list(ex.map(one, range(n_all)))
+    wn = time.perf_counter() - t0
+    ptsn = sum(r[3] for r in multi)
+    identical = all(r[2] for r in single + multi)
+    return {
+        "value": round(ptsn / wn, 1), "unit": "points/s", "cores": threads, "kind": "oracle",
+        "sample": f"{n_all} whole streams of the headline workload ({T} scans of 128x4096 each), encode + decode, "
+                  f"one stream per thread on {threads} threads; {wn:.1f} s wall",
+        "single_thread": {"value": round(pts1 / w1, 1), "cores": 1,
+                          "sample": f"{n_single} whole stream(s), encode + decode, {w1:.1f} s",
+                          "encode_s": round(sum(r[0] for r in single), 2),
+                          "decode_s": round(sum(r[1] for r in single), 2)},
+        "host_cpu": _cpu_model(), "host_cores": os.cpu_count(),
+        "byte_identical_streams": n_all if identical else [i for i, r in enumerate(multi) if not r[2]],
+    }, identical
 
 
+# ---------------------------------------------------------------------------
+# counter runs (rocprofv3) and their summary
+# ---------------------------------------------------------------------------
 def copy_run(nbytes):
     """A plain device copy of known size, three times: what FETCH_SIZE and
     WRITE_SIZE read for it calibrates those counters."""
@@ -235,6 +515,8 @@ def _counter_means(folder, counter):
         if row["Counter_Name"] != counter:
             continue
         name = row["Kernel_Name"].split("(")[0].split("::")[-1]
+        if "<" in name:
+            name = name.split("<")[0]
         key = (name, row["Dispatch_Id"])
         per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
     out = {}
@@ -245,9 +527,9 @@ def _counter_means(folder, counter):
     return {k: v[0] / v[1] for k, v in out.items()}
 
 
-def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
-    """HBM bytes per launch of every kernel: FETCH_SIZE and WRITE_SIZE (KiB)
-    scaled by what they read for a copy of copy_bytes."""
+def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
+    """HBM bytes per launch of every kernel of one workload: FETCH_SIZE and
+    WRITE_SIZE (KiB) scaled by what they read for a copy of copy_bytes."""
     if not copy_bytes:
         raise SystemExit("--traffic needs --copy-bytes (the calibration copy's size)")
     f = _counter_means(fetch_dir, "FETCH_SIZE")
@@ -255,188 +537,16 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
     cf = max(_counter_means(copy_fetch_dir, "FETCH_SIZE").values())
     cw = max(_counter_means(copy_write_dir, "WRITE_SIZE").values())
     kf, kw = copy_bytes / cf, copy_bytes / cw  # bytes per counter unit
-    from paper_2209_08196_amd import synth
-    res = {"source_sha": source_sha(), "workload": synth.CONFIGS[CID].name,
-           "calibration": {"copy_bytes": copy_bytes, "fetch_bytes_per_unit": kf, "write_bytes_per_unit": kw},
-           "kernels": {k: {"fetch_bytes": round(f[k] * kf), "write_bytes": round(w.get(k, 0.0) * kw)}
-                       for k in sorted(f) if k.startswith("k_")}}
+    res = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
+    if res.get("source_sha") != source_sha():
+        res = {"source_sha": source_sha(), "workloads": {}}
+    res["workloads"][workload] = {
+        "calibration": {"copy_bytes": copy_bytes, "fetch_bytes_per_unit": kf, "write_bytes_per_unit": kw},
+        "kernels": {k: {"fetch_bytes": round(f[k] * kf), "write_bytes": round(w.get(k, 0.0) * kw)}
+                    for k in sorted(f) if k.startswith("k_")}}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(res, fh, indent=1)
-    print(json.dumps(res))
-
-
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
-    ap.add_argument("--only-batched", action="store_true", help="run only the 64-stream batched leg")
-    ap.add_argument("--no-serving", action="store_true", help="skip the 256-stream serving leg")
-    ap.add_argument("--only-serving", action="store_true", help="run only the 256-stream serving leg")
-    ap.add_argument("--profile-steps", type=int, default=3, help="steps timed per kernel with HIP events")
-    ap.add_argument("--copy-bytes", type=int, default=0,
-                    help="only run a device-to-device copy of this many bytes (counter calibration)")
-    ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
-                    help="summarize four rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE of a bench "
-                         "run and of a --copy-bytes run) into " + os.path.relpath(TRAFFIC_FILE, ROOT))
-    args = ap.parse_args()
-    if args.traffic:
-        summarize_traffic(*args.traffic, copy_bytes=args.copy_bytes)
-        return
-    if args.copy_bytes:
-        copy_run(args.copy_bytes)
-        return
-    if args.only_serving:
-        import torch
-        torch.cuda.set_device(0)
-        print(json.dumps(serving_leg(1.0, [8 << 30, 64 << 20])), flush=True)
-        return
-    if args.only_batched:
-        import torch
-        torch.cuda.set_device(0)
-        print(json.dumps(batched_leg(steps=args.steps, warmup=args.warmup)), flush=True)
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (streams shard across GPUs "
-              "without exchange, so the one-GPU figure is the per-GPU throughput).", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    from paper_2209_08196_amd import jiffy, synth
-
-    torch.cuda.set_device(0)
-    t_gen = time.perf_counter()
-    g = synth.stream(CID, 0)
-    planes = g.scans(0, N_SCANS)
-    t_gen = time.perf_counter() - t_gen
-    print(f"[bench] generated {N_SCANS} scans of {g.H}x{g.W}, {len(planes)} attributes in {t_gen:.1f}s",
-          file=sys.stderr, flush=True)
-    store = {1: np.uint8, 2: np.int16, 4: np.int32}
-    dev = [torch.from_numpy(p.view(store[p.dtype.itemsize])).cuda() for p in planes]
-    precs = g.precisions
-    widths = g.widths
-    T, H, W = planes[0].shape
-    npx = H * W
-    A = len(planes)
-    points = T * npx * A
-    x_bytes = sum(p.nbytes for p in planes)
-    lay = jiffy.make_layout(H, W, widths, precs)
-    out = torch.empty(jiffy.encode_bound(lay, T), dtype=torch.uint8, device="cuda")
-    dec = [torch.empty_like(d) for d in dev]
-    stream = torch.cuda.current_stream()
-
-    def step():
-        s, modes = jiffy.encode(dev, precs, out=out)
-        jiffy.decode(s, lay, T, outs=dec)
-        return s, modes
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # correctness of this run: lossless round trip (P = 1 everywhere)
-    s_dev, modes = step()
-    for d, x in zip(dec, dev):
-        if not torch.equal(d, x):
-            raise SystemExit("decode(encode(x)) != x")
-    s_gpu = s_dev.cpu().numpy().tobytes()
-    st = stream_stats(s_gpu, widths, npx)
-    print(f"[bench] stream {len(s_gpu)} bytes, ratio {x_bytes / len(s_gpu):.2f}, P-scans {st['p_items']}",
-          file=sys.stderr, flush=True)
-
-    # timed steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    enc = jiffy.Encoder(dev, precs, out=out, stream=stream)  # the same calls, arguments prepared once
-    dcd = jiffy.Decoder(lay, T, dec, stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for ev_e0, ev_e1, ev_d1 in evs:
-        ev_e0.record(stream)
-        s, _ = enc()
-        ev_e1.record(stream)
-        dcd(s)
-        ev_d1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    enc_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in evs)
-    dec_ms = sum(e1.elapsed_time(d1) for _, e1, d1 in evs)
-    ms_per_step = 1e3 * wall / args.steps
-    value = points / (wall / args.steps)
-    print(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
-
-    if args.profile_steps <= 0:  # counter-collection runs: the kernels only
-        print(json.dumps({"metric": METRIC, "ms_per_step": round(ms_per_step, 3)}), flush=True)
-        return
-    # per-kernel times with HIP events on the launch stream
-    jiffy.profile_enable(True)
-    for _ in range(args.profile_steps):
-        step()
-    torch.cuda.synchronize()
-    prof = jiffy.profile_read()
-    jiffy.profile_enable(False)
-    n_items = T * A
-    nwords = (npx + 63) // 64
-    kernels = {k: dict(avg_ms=v[0] / v[1], launches=v[1]) for k, v in prof.items()}
-    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
-    alg = kernel_alg_bytes(dom, st, x_bytes, n_items, nwords)
-    avg_s = kernels[dom]["avg_ms"] / 1e3
-    achieved = alg / avg_s / 1e9 if alg else None
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        ent = tr.get("kernels", {}).get(dom)
-        if ent and tr.get("source_sha") == source_sha() and tr.get("workload") == g.cfg.name:
-            traffic = ent["fetch_bytes"] + ent["write_bytes"]
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                "traffic": traffic, "kernel": dom, "alg_bytes_per_launch": alg,
-                "avg_launch_ms": round(kernels[dom]["avg_ms"], 4)}
-    path_alg = 2 * (x_bytes + st["p_bytes"]) + 2 * st["stream_bytes"]
-
-    result = {
-        "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"{g.cfg.name}, {T} scans, encode+decode", "scans": T, "height": H, "width": W,
-                   "attributes": [a.name for a in g.cfg.attrs], "precision_mm": 1},
-        "encode_points_per_s": round(points / (enc_ms / args.steps / 1e3), 1),
-        "decode_points_per_s": round(points / (dec_ms / args.steps / 1e3), 1),
-        "compression_ratio": round(x_bytes / st["stream_bytes"], 3),
-        "p_scans": st["p_items"], "i_scans": st["i_items"],
-        "path_alg_gbps": round(path_alg / (wall / args.steps) / 1e9, 1),
-        "path_hbm_frac": round(path_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": roofline,
-        "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_ms"])},
-    }
-
-    if not args.no_batched:
-        result["batched"] = batched_leg(steps=8, warmup=2)
-        print(f"[bench] batched: {result['batched']}", file=sys.stderr, flush=True)
-    if not args.no_serving:
-        result["serving"] = serving_leg(1.0, [8 << 30, 64 << 20])
-
-    if not args.no_cpu_baseline:
-        import oracle  # the CPU-baseline leg: the oracle timed on the host
-
-        planes_np = planes
-        t0 = time.perf_counter()
-        s_ref, m_ref = oracle.encode(planes_np, precs)
-        t1 = time.perf_counter()
-        oracle.decode(s_ref)
-        t2 = time.perf_counter()
-        identical = (s_ref == s_gpu) and bool(np.array_equal(m_ref, modes))
-        result["byte_identical"] = identical
-        result["cpu_baseline"] = {
-            "value": round(points / (t2 - t0), 1), "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"the whole workload ({T} scans x {A} attributes), encode + decode, one thread",
-            "encode_s": round(t1 - t0, 2), "decode_s": round(t2 - t1, 2),
-            "host_cpu": _cpu_model(), "host_cores": os.cpu_count(),
-        }
-        if not identical:
-            print("[bench] GPU stream differs from the oracle", file=sys.stderr)
-    print(json.dumps(result), flush=True)
+    print(json.dumps(res["workloads"][workload]))
 
 
 def _cpu_model():
@@ -447,6 +557,75 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--streams", type=int, default=None, help="headline streams (default: all 32)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the 256-stream serving leg")
+    ap.add_argument("--only", choices=["headline", "batched", "serving"], help="run one leg only")
+    ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--serving-seconds", type=float, default=10.0)
+    ap.add_argument("--profile-steps", type=int, default=1, help="steps timed per kernel with HIP events")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a device-to-device copy of this many bytes (counter calibration)")
+    ap.add_argument("--traffic", nargs=5, metavar=("WORKLOAD", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="summarize four rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE of a bench "
+                         "run and of a --copy-bytes run) into " + os.path.relpath(TRAFFIC_FILE, ROOT))
+    args = ap.parse_args()
+    if args.traffic:
+        summarize_traffic(*args.traffic, copy_bytes=args.copy_bytes)
+        return
+    if args.copy_bytes:
+        copy_run(args.copy_bytes)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (streams shard across GPUs "
+              "without exchange, so the one-GPU figure is the per-GPU throughput).", file=sys.stderr)
+        sys.exit(2)
+    from paper_2209_08196_amd import synth
+
+    legs = {args.only} if args.only else {"headline", "batched", "serving"}
+    if args.no_batched:
+        legs.discard("batched")
+    if args.no_serving:
+        legs.discard("serving")
+    # synthetic inputs first, in worker processes (the GPU is not touched yet)
+    t0 = time.perf_counter()
+    jobs = []
+    n_head = synth.CONFIGS[HEAD_CID].streams if args.streams is None else args.streams
+    if "headline" in legs:
+        jobs += [(HEAD_CID, s, 0, SCENE_PERIOD) for s in range(n_head)]
+    nb = args.warmup + args.batched_steps
+    if "batched" in legs:
+        jobs += [(3, s, 0, nb) for s in range(synth.CONFIGS[3].streams)]
+    data = generate(jobs)
+    head_host = data[:n_head] if "headline" in legs else None
+    batched_host = data[n_head if "headline" in legs else 0:] if "batched" in legs else None
+    log(f"generated {len(jobs)} stream segments in {time.perf_counter() - t0:.1f}s on {pool_size()} processes")
+
+    import torch
+    torch.cuda.set_device(0)
+    result = {}
+    if "headline" in legs:
+        result, ctx = headline(args, head_host)
+    if "batched" in legs:
+        result["batched"] = batched_leg(batched_host, args.batched_steps, args.warmup)
+        log(f"batched: {json.dumps(result['batched'])}")
+    if "serving" in legs:
+        result["serving"] = serving_leg(args.serving_seconds, [8 << 30, 64 << 20])
+    if "headline" in legs and not args.no_cpu_baseline:
+        cb, identical = cpu_leg(head_host, ctx, n_single=1, n_all=min(n_head, pool_size()))
+        result["cpu_baseline"] = cb
+        result["byte_identical"] = identical
+        if not identical:
+            log("GPU stream differs from the oracle")
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":

@@ -14,6 +14,7 @@ using namespace jiffy;
 
 namespace {
 
+
 void prof_collect();
 
 constexpr size_t kAlign = 256;
@@ -89,13 +90,24 @@ int current_device(int* dev) {
     return JIFFY_OK;
 }
 
+// Worst-case bytes of one record of npx samples of `bits` bits: header, mask
+// frame, section header and every frame packed at full width, each part
+// padded to 4 bytes.
+uint64_t record_bound(uint64_t npx, uint32_t bits) {
+    const uint64_t nm = (npx + 7) / 8, nb = (npx + kFrame - 1) / kFrame;
+    return 12 + (16 + nm + 4 * (nm / kZstdBlockMax + 1)) + 3 + 4 + 3 * nb + 3 + nb * 16 * bits + 3;
+}
+
 bool layout_ok(const jiffy_layout* L) {
     if (!L || L->n_attrs < 1 || L->n_attrs > JIFFY_MAX_ATTRS || L->height == 0 || L->width == 0) return false;
-    if ((uint64_t)L->height * L->width >= (1ull << 31)) return false;
+    const uint64_t npx = (uint64_t)L->height * L->width;
+    if (npx >= (1ull << 31)) return false;
     for (uint32_t a = 0; a < L->n_attrs; ++a) {
         const uint32_t wb = L->width_bytes[a];
         if (wb != 1 && wb != 2 && wb != 4) return false;
         if (L->precision[a] == 0) return false;
+        // record lengths, section sizes and offsets are 32-bit fields of the stream
+        if (record_bound(npx, 8 * wb) >= (1ull << 32)) return false;
     }
     return true;
 }
@@ -377,6 +389,50 @@ int run_encode(DevCtx& ctx, const std::vector<EncSpec>& specs, const std::vector
     return enc_execute(ctx, ctx.up, P, stream, result);
 }
 
+// The records of one scan sequence (jiffy_encode): scan t of attribute a
+// predicts from scan t-1 of the same plane; one output, the whole stream.
+void sequence_specs(const jiffy_layout* L, uint32_t mode, uint32_t K, uint32_t T, const void* const* d_planes,
+                    void* d_out, size_t cap, std::vector<EncSpec>& specs, std::vector<OutSpec>& outs) {
+    const uint32_t A = L->n_attrs;
+    const size_t npx = (size_t)L->height * L->width;
+    specs.resize((size_t)T * A);
+    for (uint32_t t = 0; t < T; ++t) {
+        for (uint32_t a = 0; a < A; ++a) {
+            EncSpec& s = specs[(size_t)t * A + a];
+            const size_t step = npx * L->width_bytes[a];
+            s.x = (const uint8_t*)d_planes[a] + t * step;
+            s.xprev = t ? (const uint8_t*)d_planes[a] + (t - 1) * step : nullptr;
+            s.qout = nullptr;
+            s.vw_fixed = nullptr;
+            s.vwprev_fixed = nullptr;
+            s.prev_item = t ? (int)((t - 1) * A + a) : -1;
+            s.H = L->height;
+            s.W = L->width;
+            s.wb = L->width_bytes[a];
+            s.P = L->precision[a];
+            s.attr = a;
+            s.out_id = 0;
+            s.has_prev = t ? 1u : 0u;
+            s.prev_quantized = 0;
+            s.mode_req = mode;
+            s.trial_rows = K;
+        }
+    }
+    outs.assign(1, OutSpec{(uint8_t*)d_out, cap, 0, T * A, header_len(A, T), T, L});
+}
+
+// Arguments of jiffy_encode; JIFFY_OK or JIFFY_E_INVALID.
+int check_encode_args(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, const void* const* d_planes,
+                      void* d_out, size_t* h_out_len) {
+    if (!layout_ok(L) || !h_out_len || !d_out || (uintptr_t)d_out % 4) return JIFFY_E_INVALID;
+    if (opt && opt->mode > 2) return JIFFY_E_INVALID;
+    if ((uint64_t)T * L->n_attrs > (1u << 24)) return JIFFY_E_INVALID;
+    if (T && !d_planes) return JIFFY_E_INVALID;
+    for (uint32_t a = 0; T && a < L->n_attrs; ++a)
+        if (!d_planes[a] || (uintptr_t)d_planes[a] % L->width_bytes[a]) return JIFFY_E_INVALID;
+    return JIFFY_OK;
+}
+
 // The last jiffy_encode's arguments and plan (per device): a call with the
 // same arguments on the same workspace reuses the plan image.
 struct EncKey {
@@ -474,10 +530,11 @@ void prof_collect() {
 }  // namespace
 
 namespace jiffy {
-thread_local bool t_capturing = false;  // launches go into a graph: no timing events
+// launches go into a graph, or the call may not create events: no timing events
+thread_local bool t_no_events = false;
 
 void prof_begin(const char* name, hipStream_t stream) {
-    if (t_capturing) return;
+    if (t_no_events) return;
     std::lock_guard<std::mutex> lock(g_prof_mu);
     if (!g_prof_on) return;
     ProfEntry e{name, prof_event(), prof_event()};
@@ -485,7 +542,7 @@ void prof_begin(const char* name, hipStream_t stream) {
     g_prof_pending.push_back(e);
 }
 void prof_end(hipStream_t stream) {
-    if (t_capturing) return;
+    if (t_no_events) return;
     std::lock_guard<std::mutex> lock(g_prof_mu);
     if (!g_prof_on || g_prof_pending.empty()) return;
     ProfEntry& e = g_prof_pending.back();
@@ -531,32 +588,21 @@ const char* jiffy_status_string(int s) {
 size_t jiffy_encode_bound(const jiffy_layout* L, uint32_t n_scans) {
     if (!layout_ok(L)) return 0;
     const size_t npx = (size_t)L->height * L->width;
-    const size_t nm = (npx + 7) / 8, nb = (npx + 127) / 128;
     size_t total = header_len(L->n_attrs, n_scans);
-    for (uint32_t a = 0; a < L->n_attrs; ++a) {
-        const size_t bits = 8u * L->width_bytes[a];
-        const size_t rec = 12 + frame_bound((uint32_t)nm) + 3 + 4 + 3 * nb + 3 + nb * 16 * bits + 3;
-        total += rec * n_scans;
-    }
+    for (uint32_t a = 0; a < L->n_attrs; ++a) total += record_bound(npx, 8u * L->width_bytes[a]) * n_scans;
     return total;
 }
 
 int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, const void* const* d_planes,
                  void* d_out, size_t cap, size_t* h_out_len, uint8_t* h_modes, hipStream_t stream) {
-    if (!layout_ok(L) || !h_out_len || !d_out || (uintptr_t)d_out % 4) return JIFFY_E_INVALID;
+    if (int rc = check_encode_args(L, opt, T, d_planes, d_out, h_out_len)) return rc;
     const uint32_t mode = opt ? opt->mode : 0;
     const uint32_t K = (opt && opt->trial_rows) ? opt->trial_rows : 4;
-    if (mode > 2) return JIFFY_E_INVALID;
     const uint32_t A = L->n_attrs;
-    if ((uint64_t)T * A > (1u << 24)) return JIFFY_E_INVALID;
-    if (T && !d_planes) return JIFFY_E_INVALID;
-    for (uint32_t a = 0; T && a < A; ++a)
-        if (!d_planes[a] || (uintptr_t)d_planes[a] % L->width_bytes[a]) return JIFFY_E_INVALID;
     int dev;
     if (current_device(&dev)) return JIFFY_E_DEVICE;
     DevCtx& ctx = g_ctx[dev];
     std::lock_guard<std::mutex> lock(ctx.mu);
-    const size_t npx = (size_t)L->height * L->width;
     if (T == 0) {
         // a header with no records
         const uint32_t hl = header_len(A, 0);
@@ -589,31 +635,9 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
         if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
         return JIFFY_OK;
     }
-    std::vector<EncSpec> specs((size_t)T * A);
-    for (uint32_t t = 0; t < T; ++t) {
-        for (uint32_t a = 0; a < A; ++a) {
-            EncSpec& s = specs[(size_t)t * A + a];
-            const size_t step = npx * L->width_bytes[a];
-            s.x = (const uint8_t*)d_planes[a] + t * step;
-            s.xprev = t ? (const uint8_t*)d_planes[a] + (t - 1) * step : nullptr;
-            s.qout = nullptr;
-            s.vw_fixed = nullptr;
-            s.vwprev_fixed = nullptr;
-            s.prev_item = t ? (int)((t - 1) * A + a) : -1;
-            s.H = L->height;
-            s.W = L->width;
-            s.wb = L->width_bytes[a];
-            s.P = L->precision[a];
-            s.attr = a;
-            s.out_id = 0;
-            s.has_prev = t ? 1u : 0u;
-            s.prev_quantized = 0;
-            s.mode_req = mode;
-            s.trial_rows = K;
-        }
-    }
-    std::vector<OutSpec> outs(1);
-    outs[0] = OutSpec{(uint8_t*)d_out, cap, 0, T * A, header_len(A, T), T, L};
+    std::vector<EncSpec> specs;
+    std::vector<OutSpec> outs;
+    sequence_specs(L, mode, K, T, d_planes, d_out, cap, specs, outs);
     if (int rc = enc_prepare(ctx, C.up, specs, outs, C.prep)) return rc;
     C.key = key;
     if (int rc = enc_execute(ctx, C.up, C.prep, stream, res)) return rc;
@@ -1088,6 +1112,8 @@ int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* con
     int dev;
     if (current_device(&dev)) return JIFFY_E_DEVICE;
     if (int rc = check_batch(streams, n, d_planes, d_out, caps, dev)) return rc;
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);  // the streams' state is read while the batch is planned
     jiffy_batch* b = new (std::nothrow) jiffy_batch();
     if (!b) return JIFFY_E_INVALID;
     b->device = dev;
@@ -1109,9 +1135,9 @@ int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* con
         enc_fill(b->Lo, specs, outs, b->dev, b->up);
         const EncPlan plan = enc_plan(b->Lo, b->dev, (uint8_t*)b->res_d);
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-            t_capturing = true;
+            t_no_events = true;
             const hipError_t e = enc_enqueue(b->Lo, plan, b->dev, b->up_d, b->cap_stream);
-            t_capturing = false;
+            t_no_events = false;
             const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &b->graph);
             if (e == hipSuccess && e2 == hipSuccess &&
                 hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess)
@@ -1132,6 +1158,8 @@ int jiffy_batch_run(jiffy_batch* b, const void* const* const* d_planes, size_t* 
     int dev;
     if (current_device(&dev)) return JIFFY_E_DEVICE;
     if (dev != b->device) return JIFFY_E_SHAPE;
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);  // the streams' resident state changes with the step
     const uint32_t n = (uint32_t)b->streams.size();
     if (d_planes) {
         if (int rc = check_batch(b->streams.data(), n, d_planes, b->outs.data(), b->caps.data(), dev)) return rc;

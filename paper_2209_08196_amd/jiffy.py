@@ -132,15 +132,74 @@ def encode_bound(layout: Layout, n_scans: int) -> int:
     return lib().jiffy_encode_bound(ctypes.byref(layout), n_scans)
 
 
+_SAMPLE_DTYPES = None
+
+
+def _sample_dtypes():
+    global _SAMPLE_DTYPES
+    if _SAMPLE_DTYPES is None:
+        import torch
+        _SAMPLE_DTYPES = (torch.uint8, torch.int16, torch.int32, torch.uint16, torch.uint32)
+    return _SAMPLE_DTYPES
+
+
+def _check_tensor(t, numel, width_bytes, what):
+    """A contiguous device tensor of `numel` samples of `width_bytes` bytes
+    (the C ABI reads or writes exactly that many bytes through its pointer)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what}: must be a device tensor (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if t.dtype not in _sample_dtypes():
+        raise ValueError(f"{what}: unsupported dtype {t.dtype}")
+    if t.element_size() != width_bytes:
+        raise ValueError(f"{what}: {t.element_size()}-byte samples where the layout has {width_bytes}")
+    if t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} samples where {numel} are needed")
+
+
+def _check_bytes_out(t, what):
+    """A contiguous device uint8 tensor (an output byte buffer)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.uint8 \
+            or not t.is_contiguous() or t.dim() != 1:
+        raise ValueError(f"{what}: must be a contiguous 1-D device uint8 tensor")
+
+
 def _check_planes(planes):
     import torch
+    if not planes or len(planes) > MAX_ATTRS:
+        raise ValueError(f"between 1 and {MAX_ATTRS} attribute planes are needed")
+    if not isinstance(planes[0], torch.Tensor) or planes[0].dim() != 3:
+        raise ValueError("planes must be [T, H, W] tensors")
     T, H, W = planes[0].shape
-    for p in planes:
-        if p.device.type != "cuda" or not p.is_contiguous() or tuple(p.shape) != (T, H, W):
+    for a, p in enumerate(planes):
+        if not isinstance(p, torch.Tensor) or tuple(p.shape) != (T, H, W):
             raise ValueError("planes must be contiguous device tensors of one [T, H, W] shape")
-        if p.dtype not in (torch.uint8, torch.int16, torch.int32, torch.uint16, torch.uint32):
-            raise ValueError(f"unsupported dtype {p.dtype}")
+        _check_tensor(p, T * H * W, p.element_size(), f"plane {a}")
     return T, H, W
+
+
+def _check_outs(layout, T, outs):
+    """Decode outputs: one device tensor per attribute of T*H*W samples of
+    the attribute's width."""
+    if outs is None or len(outs) != layout.n_attrs:
+        raise ValueError(f"{layout.n_attrs} output planes are needed")
+    n = T * layout.height * layout.width
+    for a, o in enumerate(outs):
+        _check_tensor(o, n, layout.width_bytes[a], f"output plane {a}")
+
+
+def _check_scan(stream, tensors, what):
+    """One scan of a stream: a device tensor of H*W samples per attribute."""
+    lay = stream.layout
+    if tensors is None or len(tensors) != lay.n_attrs:
+        raise ValueError(f"{what}: {lay.n_attrs} attribute tensors are needed")
+    for a, t in enumerate(tensors):
+        _check_tensor(t, lay.height * lay.width, lay.width_bytes[a], f"{what}, attribute {a}")
 
 
 def encode(planes, precisions=None, mode=MODE_AUTO, trial_rows=0, out=None, stream=None):
@@ -154,6 +213,7 @@ def encode(planes, precisions=None, mode=MODE_AUTO, trial_rows=0, out=None, stre
     opt = Options(mode, trial_rows)
     if out is None:
         out = torch.empty(encode_bound(lay, T), dtype=torch.uint8, device=planes[0].device)
+    _check_bytes_out(out, "out")
     arr = (ctypes.c_void_p * len(planes))(*[p.data_ptr() for p in planes])
     n = ctypes.c_size_t()
     modes = np.zeros((max(T, 1), len(planes)), np.uint8)
@@ -213,6 +273,8 @@ def decode(stream_bytes, layout: Layout = None, n_scans: int = None, outs=None, 
     if outs is None:
         outs = [torch.empty((n_scans, layout.height, layout.width), dtype=getattr(torch, _TORCH_DT[layout.width_bytes[a]]),
                             device=dev) for a in range(layout.n_attrs)]
+    _check_bytes_out(stream_bytes, "stream_bytes")
+    _check_outs(layout, n_scans, outs)
     arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
     if known:
         rc = lib().jiffy_decode_layout(ctypes.byref(layout), n_scans, ctypes.c_void_p(stream_bytes.data_ptr()),
@@ -242,6 +304,7 @@ class Encoder:
         self.T = T
         if out is None:
             out = torch.empty(encode_bound(self.layout, T), dtype=torch.uint8, device=planes[0].device)
+        _check_bytes_out(out, "out")
         self.out = out
         self._arr = (ctypes.c_void_p * len(planes))(*[p.data_ptr() for p in planes])
         self._n = ctypes.c_size_t()
@@ -265,12 +328,14 @@ class Decoder:
     def __init__(self, layout: Layout, n_scans: int, outs, stream=None):
         if n_scans < 1:
             raise ValueError("n_scans must be at least 1")
+        _check_outs(layout, n_scans, outs)
         self.layout, self.T, self.outs = layout, n_scans, list(outs)
         self._arr = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
         self._stream = _stream_handle(stream)
 
     def __call__(self, stream_bytes):
         """Decodes the device stream tensor into the output planes; returns them."""
+        _check_bytes_out(stream_bytes, "stream_bytes")
         rc = lib().jiffy_decode_layout(ctypes.byref(self.layout), self.T, ctypes.c_void_p(stream_bytes.data_ptr()),
                                        stream_bytes.numel(), ctypes.cast(self._arr, ctypes.c_void_p), self._stream)
         if rc:
@@ -313,7 +378,18 @@ class Stream:
             pass
 
 
+def _check_batch(streams, scans, outs):
+    if len(scans) != len(streams) or len(outs) != len(streams):
+        raise ValueError("one scan and one output buffer per stream are needed")
+    for i, (s, sc, o) in enumerate(zip(streams, scans, outs)):
+        if not getattr(s, "handle", None):
+            raise ValueError(f"stream {i} is closed")
+        _check_scan(s, sc, f"stream {i}")
+        _check_bytes_out(o, f"output of stream {i}")
+
+
 def _batch_args(streams, scans, outs):
+    _check_batch(streams, scans, outs)
     n = len(streams)
     sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
     inner = [(ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
@@ -359,6 +435,10 @@ class Batch:
         ndarray [n, A])."""
         planes = None
         if scans is not None:
+            if len(scans) != len(self.streams):
+                raise ValueError("one scan per stream is needed")
+            for i, (s, sc) in enumerate(zip(self.streams, scans)):
+                _check_scan(s, sc, f"stream {i}")
             self._inner = [(ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
             planes = (ctypes.c_void_p * len(self.streams))(*[ctypes.cast(x, ctypes.c_void_p).value
                                                              for x in self._inner])

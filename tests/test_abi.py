@@ -85,3 +85,41 @@ def test_peek_agrees_with_oracle(lib):
             jiffy.peek(s[:cut])
     with pytest.raises(jiffy.JiffyError):
         jiffy.peek(b"XFY1" + s[4:])
+
+
+def test_oversized_records_are_rejected_on_the_host(lib):
+    """Record lengths, section sizes and offsets are 32-bit stream fields:
+    a layout whose worst-case record reaches 4 GiB is invalid.  Checked
+    before any device call (the pointers are never used)."""
+    big = jiffy.make_layout(16384, 65535, [4])      # 2^30 samples of 4 bytes: a record can pass 4 GiB
+    assert jiffy.encode_bound(big, 1) == 0
+    n = ctypes.c_size_t()
+    arr = (ctypes.c_void_p * 1)(0x1000)
+    rc = lib.jiffy_encode(ctypes.byref(big), None, 1, ctypes.cast(arr, ctypes.c_void_p), ctypes.c_void_p(0x1000),
+                          1 << 40, ctypes.byref(n), None, None)
+    assert rc == jiffy.E_INVALID
+    h = ctypes.c_void_p()
+    assert lib.jiffy_stream_create(ctypes.byref(big), None, ctypes.byref(h)) == jiffy.E_INVALID
+    ok = jiffy.make_layout(32768, 65535, [1])       # 1-byte samples: every record stays below 4 GiB
+    assert 0 < jiffy.encode_bound(ok, 1) < (1 << 32) + 4096
+
+
+def test_binding_rejects_bad_tensors_before_any_call():
+    """The binding checks tensors on the host before it calls the library:
+    host tensors, wrong ranks and mismatched shapes raise ValueError."""
+    import torch
+    cpu = torch.zeros((2, 4, 8), dtype=torch.int32)
+    with pytest.raises(ValueError):
+        jiffy.encode([cpu])
+    with pytest.raises(ValueError):
+        jiffy.Encoder([cpu])
+    with pytest.raises(ValueError):
+        jiffy.encode([])
+    with pytest.raises(ValueError):
+        jiffy.encode([torch.zeros((4, 8), dtype=torch.int32)])
+    lay = jiffy.make_layout(4, 8, [4, 2])
+    with pytest.raises(ValueError):
+        jiffy.Decoder(lay, 2, [cpu])                 # one plane for two attributes
+    with pytest.raises(ValueError):
+        jiffy.Decoder(lay, 2, [cpu, torch.zeros((2, 4, 8), dtype=torch.int16)])  # host tensors
+
