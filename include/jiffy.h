@@ -64,7 +64,8 @@ typedef enum {
     JIFFY_E_CAPACITY = -2,  /* output buffer too small; the size needed is returned */
     JIFFY_E_CORRUPT = -3,   /* malformed stream */
     JIFFY_E_DEVICE = -4,    /* a HIP runtime error */
-    JIFFY_E_SHAPE = -5      /* planes do not match the stream's layout */
+    JIFFY_E_SHAPE = -5,     /* planes do not match the stream's layout */
+    JIFFY_E_SCRATCH = -6    /* jiffy_encode_noalloc: the call needs more than its fixed scratch */
 } jiffy_status;
 
 /* Worst-case size in bytes of the stream jiffy_encode writes for n_scans
@@ -83,6 +84,28 @@ size_t jiffy_encode_bound(const jiffy_layout* layout, uint32_t n_scans);
 int jiffy_encode(const jiffy_layout* layout, const jiffy_options* options, uint32_t n_scans,
                  const void* const* d_planes, void* d_out, size_t out_capacity, size_t* h_out_len,
                  uint8_t* h_modes, hipStream_t stream);
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops and harnesses that forbid device allocation): jiffy_encode
+ * with the same arguments, results and stream bytes, whose encoder
+ * workspace is a fixed device array of 64 MiB in the library (one copy per
+ * device, held until the process ends) instead of memory the library
+ * allocates.  It calls no hipMalloc, hipFree, hipHostMalloc or other device
+ * or pinned-host allocating routine; its plan image and results pass
+ * through a fixed 1 MiB / 256 KiB host staging area by hipMemcpyAsync.
+ * Host-side planning still uses ordinary heap memory.
+ * A call whose workspace would exceed the array (about 5.2 bytes per sample
+ * of all its scans and attributes plus ~200 bytes per record, e.g. 24 scans
+ * of one 128x4096 attribute), or whose plan exceeds the staging area,
+ * returns JIFFY_E_SCRATCH with *h_out_len = 0 before touching the device.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents; each call first writes or clears everything it reads.
+ * Calls on one device are serialized by the per-device lock and complete
+ * before they return; calls that overlapped on one device (for instance
+ * from another library instance in the process) would race on the array. */
+int jiffy_encode_noalloc(const jiffy_layout* layout, const jiffy_options* options, uint32_t n_scans,
+                         const void* const* d_planes, void* d_out, size_t out_capacity, size_t* h_out_len,
+                         uint8_t* h_modes, hipStream_t stream);
 
 /* Parses a stream header in host memory.  in_len is the length of the whole
  * stream.  With a record-length table (n_scans > 0 in the header) only the

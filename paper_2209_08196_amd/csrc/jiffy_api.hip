@@ -12,8 +12,23 @@
 
 using namespace jiffy;
 
+// Device scratch of jiffy_encode_noalloc: that entry point's whole encoder
+// workspace (plan image, results, per-record buffers), of a fixed size, one
+// copy per device, held until the process ends.  Host code uses the address
+// hipGetSymbolAddress returns for it on each device (DevCtx::scratch), never
+// the array's own name.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 namespace {
 
+// Host staging of jiffy_encode_noalloc (ordinary static memory, not pinned):
+// the plan image it copies to the device and the results it copies back.
+constexpr size_t kNoallocUpBytes = 1u << 20;
+constexpr size_t kNoallocResBytes = 256u << 10;
+alignas(256) uint8_t g_noalloc_up[kNoallocUpBytes];
+alignas(256) uint8_t g_noalloc_res[kNoallocResBytes];
+std::mutex g_noalloc_mu;  // guards the two staging buffers (taken after a device's lock)
 
 void prof_collect();
 
@@ -82,6 +97,7 @@ struct DevCtx {
     DevBuf ws, ws_dec;
     HostBuf up, down, res;
     uint64_t enc_gen = 0;
+    uint8_t* scratch = nullptr;  // this device's copy of `scratch` (jiffy_encode_noalloc), once looked up
 };
 DevCtx g_ctx[64];
 
@@ -421,7 +437,7 @@ void sequence_specs(const jiffy_layout* L, uint32_t mode, uint32_t K, uint32_t T
     outs.assign(1, OutSpec{(uint8_t*)d_out, cap, 0, T * A, header_len(A, T), T, L});
 }
 
-// Arguments of jiffy_encode; JIFFY_OK or JIFFY_E_INVALID.
+// Arguments of jiffy_encode / jiffy_encode_noalloc; JIFFY_OK or JIFFY_E_INVALID.
 int check_encode_args(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, const void* const* d_planes,
                       void* d_out, size_t* h_out_len) {
     if (!layout_ok(L) || !h_out_len || !d_out || (uintptr_t)d_out % 4) return JIFFY_E_INVALID;
@@ -581,6 +597,7 @@ const char* jiffy_status_string(int s) {
         case JIFFY_E_CORRUPT: return "corrupt stream";
         case JIFFY_E_DEVICE: return "HIP runtime error";
         case JIFFY_E_SHAPE: return "planes do not match the stream";
+        case JIFFY_E_SCRATCH: return "request exceeds the fixed scratch buffer of jiffy_encode_noalloc";
         default: return "unknown status";
     }
 }
@@ -645,6 +662,76 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
     *h_out_len = res.lens[0];
     if (!res.ok[0]) return JIFFY_E_CAPACITY;
     if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
+    return JIFFY_OK;
+}
+
+int jiffy_encode_noalloc(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, const void* const* d_planes,
+                         void* d_out, size_t cap, size_t* h_out_len, uint8_t* h_modes, hipStream_t stream) {
+    if (int rc = check_encode_args(L, opt, T, d_planes, d_out, h_out_len)) return rc;
+    const uint32_t mode = opt ? opt->mode : 0;
+    const uint32_t K = (opt && opt->trial_rows) ? opt->trial_rows : 4;
+    const uint32_t A = L->n_attrs;
+    const uint32_t hl = header_len(A, T);
+    std::vector<EncSpec> specs;
+    std::vector<OutSpec> outs;
+    EncLayout Lo;
+    if (T) {  // the workspace this call needs must fit the fixed scratch and staging buffers
+        sequence_specs(L, mode, K, T, d_planes, d_out, cap, specs, outs);
+        Lo = enc_layout(specs, outs);
+        if (Lo.total > kScratchBytes || Lo.up_bytes() > kNoallocUpBytes || Lo.o_items - Lo.o_res > kNoallocResBytes) {
+            *h_out_len = 0;
+            return JIFFY_E_SCRATCH;
+        }
+    } else if (hl > kNoallocUpBytes) {
+        return JIFFY_E_SCRATCH;
+    }
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    std::lock_guard<std::mutex> hlock(g_noalloc_mu);
+    if (!ctx.scratch) {  // first call on this device (it is current): where its copy of the array lives
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return JIFFY_E_DEVICE;
+        ctx.scratch = (uint8_t*)p;
+    }
+    if (T == 0) {  // a header with no records
+        *h_out_len = hl;
+        if (cap < hl) return JIFFY_E_CAPACITY;
+        write_header(g_noalloc_up, L, 0);
+        if (hipMemcpyAsync(d_out, g_noalloc_up, hl, hipMemcpyHostToDevice, stream) != hipSuccess) return JIFFY_E_DEVICE;
+        return hipStreamSynchronize(stream) == hipSuccess ? JIFFY_OK : JIFFY_E_DEVICE;
+    }
+    uint8_t* ws = ctx.scratch;
+    // the plan image (records, outputs, tile maps; the error word and the output
+    // states zeroed) is written on the host and copied in; everything else the
+    // kernels read is written or cleared by this call's kernels first
+    enc_fill(Lo, specs, outs, ws, g_noalloc_up);
+    const EncPlan plan = enc_plan(Lo, ws, nullptr);  // no host-mapped results: they are copied back below
+    t_no_events = true;                              // no timing events either
+    hipError_t e = hipMemcpyAsync(ws + Lo.o_err, g_noalloc_up, Lo.up_bytes(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_encode(plan, stream);
+    t_no_events = false;
+    if (e != hipSuccess) return JIFFY_E_DEVICE;
+    // results: per record its mode, the error word, the output's length and fit flag
+    if (hipMemcpyAsync(g_noalloc_res, ws + Lo.o_res, Lo.o_items - Lo.o_res, hipMemcpyDeviceToHost, stream) !=
+        hipSuccess)
+        return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    uint32_t err;
+    memcpy(&err, g_noalloc_res + (Lo.o_err - Lo.o_res), 4);
+    if (err & kErrStall) return JIFFY_E_DEVICE;
+    EncOut o;
+    memcpy(&o, g_noalloc_res + (Lo.o_outs - Lo.o_res), sizeof o);
+    *h_out_len = o.len;
+    if (!o.ok) return JIFFY_E_CAPACITY;
+    if (h_modes) {
+        for (uint32_t r = 0; r < Lo.n; ++r) {
+            EncRes rs;
+            memcpy(&rs, g_noalloc_res + sizeof(EncRes) * r, sizeof rs);
+            h_modes[r] = (uint8_t)rs.mode;
+        }
+    }
     return JIFFY_OK;
 }
 

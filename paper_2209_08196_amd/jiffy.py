@@ -17,10 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjiffy.so")
 MAX_ATTRS = 8
 
-OK, E_INVALID, E_CAPACITY, E_CORRUPT, E_DEVICE, E_SHAPE = 0, -1, -2, -3, -4, -5
+OK, E_INVALID, E_CAPACITY, E_CORRUPT, E_DEVICE, E_SHAPE, E_SCRATCH = 0, -1, -2, -3, -4, -5, -6
 MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY = 0, 1, 2
 
-SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_peek", "jiffy_decode", "jiffy_decode_layout",
+SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_encode_noalloc", "jiffy_peek", "jiffy_decode", "jiffy_decode_layout",
            "jiffy_status_string",
            "jiffy_stream_create", "jiffy_batch_encode_step", "jiffy_stream_reset", "jiffy_stream_destroy",
            "jiffy_batch_create", "jiffy_batch_run", "jiffy_batch_destroy",
@@ -64,6 +64,8 @@ def lib():
         L.jiffy_encode.restype = ctypes.c_int
         L.jiffy_encode.argtypes = [ctypes.POINTER(Layout), ctypes.POINTER(Options), u32, vp, vp, sz,
                                    ctypes.POINTER(sz), vp, vp]
+        L.jiffy_encode_noalloc.restype = ctypes.c_int
+        L.jiffy_encode_noalloc.argtypes = L.jiffy_encode.argtypes
         L.jiffy_peek.restype = ctypes.c_int
         L.jiffy_peek.argtypes = [vp, sz, ctypes.POINTER(Layout), ctypes.POINTER(u32)]
         L.jiffy_decode.restype = ctypes.c_int
@@ -202,11 +204,15 @@ def _check_scan(stream, tensors, what):
         _check_tensor(t, lay.height * lay.width, lay.width_bytes[a], f"{what}, attribute {a}")
 
 
-def encode(planes, precisions=None, mode=MODE_AUTO, trial_rows=0, out=None, stream=None):
+def encode(planes, precisions=None, mode=MODE_AUTO, trial_rows=0, out=None, stream=None, noalloc=False):
     """planes: list of contiguous device tensors [T, H, W] (uint8, uint16 /
     int16 or uint32 / int32 storage).  Returns (stream tensor uint8 [n],
-    modes ndarray [T, A] uint8)."""
+    modes ndarray [T, A] uint8).  noalloc=True calls jiffy_encode_noalloc
+    (the library's fixed scratch instead of its own allocations; `out` must
+    then be given, so that nothing is allocated here either)."""
     import torch
+    if noalloc and out is None:
+        raise ValueError("encode(noalloc=True) needs an output buffer")
     T, H, W = _check_planes(planes)
     widths = [p.element_size() for p in planes]
     lay = make_layout(H, W, widths, precisions)
@@ -217,11 +223,12 @@ def encode(planes, precisions=None, mode=MODE_AUTO, trial_rows=0, out=None, stre
     arr = (ctypes.c_void_p * len(planes))(*[p.data_ptr() for p in planes])
     n = ctypes.c_size_t()
     modes = np.zeros((max(T, 1), len(planes)), np.uint8)
-    rc = lib().jiffy_encode(ctypes.byref(lay), ctypes.byref(opt), T, ctypes.cast(arr, ctypes.c_void_p),
-                            ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(n),
-                            modes.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+    fn = lib().jiffy_encode_noalloc if noalloc else lib().jiffy_encode
+    rc = fn(ctypes.byref(lay), ctypes.byref(opt), T, ctypes.cast(arr, ctypes.c_void_p),
+            ctypes.c_void_p(out.data_ptr()), out.numel(), ctypes.byref(n),
+            modes.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
     if rc:
-        raise JiffyError(rc, "jiffy_encode")
+        raise JiffyError(rc, "jiffy_encode_noalloc" if noalloc else "jiffy_encode")
     return out[: n.value], modes[:T]
 
 

@@ -50,7 +50,7 @@ def test_every_launched_kernel_is_in_the_code_object(lib):
 
 
 def test_status_strings(lib):
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         s = lib.jiffy_status_string(code)
         assert s and s != b"unknown status"
     assert lib.jiffy_status_string(7) == b"unknown status"
@@ -123,3 +123,16 @@ def test_binding_rejects_bad_tensors_before_any_call():
     with pytest.raises(ValueError):
         jiffy.Decoder(lay, 2, [cpu, torch.zeros((2, 4, 8), dtype=torch.int16)])  # host tensors
 
+
+def test_noalloc_refuses_calls_beyond_its_scratch(lib):
+    """jiffy_encode_noalloc works in a fixed 64 MiB device array: a call that
+    needs more (here 32 scans of 128x4096 32-bit samples, about 168 MB of
+    workspace) returns JIFFY_E_SCRATCH with a zero length before any device
+    call (the pointers are never used)."""
+    lay = jiffy.make_layout(128, 4096, [4])
+    n = ctypes.c_size_t(123)
+    arr = (ctypes.c_void_p * 1)(0x1000)
+    rc = lib.jiffy_encode_noalloc(ctypes.byref(lay), None, 32, ctypes.cast(arr, ctypes.c_void_p),
+                                  ctypes.c_void_p(0x1000), 1 << 40, ctypes.byref(n), None, None)
+    assert rc == jiffy.E_SCRATCH and n.value == 0
+    assert lib.jiffy_status_string(rc) != b"unknown status"
