@@ -48,6 +48,7 @@ METRIC = "encode+decode points/sec & HBM GB/s fraction at byte-identical output"
 HBM_PEAK_GBS = 8000.0
 HEAD_CID = 5       # the stress set: 32 streams x 200 scans of 128x4096
 SCENE_PERIOD = 20  # scans per scene of the stress set (the part that is generated)
+SERVING_CYCLE = 4  # distinct synthetic scans per serving stream (cycled)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_08196_amd", "csrc", f)
                   for f in ("jiffy_encode.hip", "jiffy_decode.hip", "jiffy_device.h", "jiffy_internal.h")]
@@ -400,40 +401,57 @@ def batched_leg(host, steps, warmup):
 # ---------------------------------------------------------------------------
 # serving: 256 streams under device-memory budgets
 # ---------------------------------------------------------------------------
-def serving_leg(duration_s, budgets, scans_per_stream=2):
+def serving_leg(host, duration_s, speed_loaded=8.0):
     """256 sensor streams (32x1024 .. 128x2048, range u32 and three u16
-    attributes at 1 mm; 10 or 20 Hz each with random phase and jitter)
-    served by continuous batching under device-memory budgets.  Each stream
-    cycles through its first `scans_per_stream` synthetic scans.  One served
-    stream's records are compared with encoding its whole sequence alone."""
+    attributes at 1 mm; 10 or 20 Hz each with random phase and Poisson
+    jitter), served in real time by continuous batching over two step
+    contexts: under 8 GiB at the sensors' rate, under 8 GiB with arrivals
+    `speed_loaded` times faster (the server saturated), and under 64 MiB
+    with sensors connecting for 1-3 s sessions (admission binds, idle
+    streams' memory is reused).  host[s]: stream s's distinct synthetic
+    scans, cycled.  Stream 0's records from the first run are compared with
+    its sequence encoded alone by jiffy_encode."""
     import torch
 
     from paper_2209_08196_amd import jiffy, serve, synth
     cfg = synth.CONFIGS[4]
-    gens = [synth.stream(4, s) for s in range(cfg.streams)]
-    host = [g.scans(0, scans_per_stream) for g in gens]
+    gens = [synth.stream(4, s) for s in range(len(host))]
+    ncyc = host[0][0].shape[0]
     dev = [[torch.from_numpy(p.view(_STORE[p.dtype.itemsize])).cuda() for p in h] for h in host]
     specs = {s: serve.StreamSpec(g.H, g.W, tuple(g.widths), tuple(g.precisions)) for s, g in enumerate(gens)}
-    arrivals = synth.serving_arrivals(cfg.streams, duration_s)
-    check = arrivals[0][1]
-    ks = [k for _, s, k in arrivals if s == check]
-    g = gens[check]
-    seq = [torch.stack([dev[check][a][k % scans_per_stream] for k in ks]).contiguous() for a in range(len(g.widths))]
-    alone, _ = jiffy.encode(seq, g.precisions)
-    want = split_records(alone.cpu().numpy().tobytes())
-    A = len(g.widths)
-    out = {"workload": f"{cfg.name}, {duration_s} s of arrivals", "streams": cfg.streams,
-           "scans_offered": len(arrivals)}
-    for budget in budgets:
+    # every cycled scan's tensors checked once against its stream's layout
+    prepared = [[jiffy.PreparedScan(g.H, g.W, g.widths, [p[k] for p in dev[s]]) for k in range(ncyc)]
+                for s, g in enumerate(gens)]
+    scan_of = lambda sid, k: prepared[sid][k % ncyc]  # noqa: E731
+    out = {"workload": f"{cfg.name}: {len(host)} streams (sizes 32x1024, 64x1024, 64x2048, 128x2048; range u32 + "
+                       f"3 x u16 at 1 mm), 10/20 Hz with Poisson(2 ms) jitter, {duration_s} s of arrivals, each "
+                       f"stream cycling {ncyc} synthetic scans; real-time serving on two step contexts"}
+    runs = [("nominal_8192MiB", 8 << 30, 1.0, None), ("loaded_x%g_8192MiB" % speed_loaded, 8 << 30, speed_loaded, None),
+            ("sessions_64MiB", 64 << 20, 1.0, (1.0, 3.0))]
+    for name, budget, speed, sess in runs:
+        arrivals = synth.serving_arrivals(len(host), duration_s, session_s=sess)
+        keep = {arrivals[0][1]} if name.startswith("nominal") else False
         srv = serve.Server.gpu(specs, budget)
-        st = srv.run(arrivals, lambda sid, k: [p[k % scans_per_stream] for p in dev[sid]], keep_results={check})
+        st = srv.run(arrivals, scan_of, speed=speed, keep_results=keep)
         res = st.summary()
-        got = srv.results[check]
-        res["alone_equal"] = len(got) == len(ks) and all(
-            r == b"".join(want[k * A:(k + 1) * A]) for k, r in enumerate(got))
+        res["scans_offered"] = len(arrivals)
+        res["speed"] = speed
+        if keep:
+            sid = arrivals[0][1]
+            ks = [k for _, s, k in arrivals if s == sid]
+            g = gens[sid]
+            seq = [torch.stack([dev[sid][a][k % ncyc] for k in ks]).contiguous() for a in range(len(g.widths))]
+            alone, _ = jiffy.encode(seq, g.precisions)
+            want = split_records(alone.cpu().numpy().tobytes())
+            A = len(g.widths)
+            got = srv.results[sid]
+            res["alone_equal_stream"] = sid
+            res["alone_equal"] = len(got) == len(ks) and all(
+                r == b"".join(want[i * A:(i + 1) * A]) for i, (_, _, r) in enumerate(got))
         srv.close()
-        out[f"budget_{budget >> 20}MiB"] = res
-        log(f"serving budget {budget >> 20} MiB: {res}")
+        torch.cuda.synchronize()
+        out[name] = res
+        log(f"serving {name}: {res}")
     return out
 
 
@@ -549,6 +567,44 @@ def summarize_traffic(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write
     print(json.dumps(res["workloads"][workload]))
 
 
+def trace_overlap(path):
+    """From a rocprofv3 --kernel-trace csv: per HIP stream (queue) the
+    library's kernels' busy time, and the time during which kernels of two
+    or more streams ran at once."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    key = "Stream_Id" if rows and "Stream_Id" in rows[0] else "Queue_Id"
+    iv = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "jiffy" not in name:
+            continue
+        iv.setdefault(r[key], []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    events = []
+    for q, lst in iv.items():
+        for a, b in lst:
+            events.append((a, 1, q))
+            events.append((b, -1, q))
+    events.sort()
+    active = {}
+    both = 0
+    last = None
+    busy = {q: 0 for q in iv}
+    for t, d, q in events:
+        if last is not None:
+            live = [x for x, c in active.items() if c > 0]
+            for x in live:
+                busy[x] += t - last
+            if len(live) >= 2:
+                both += t - last
+        active[q] = active.get(q, 0) + d
+        last = t
+    res = {"streams": {str(q): {"kernels": len(iv[q]), "busy_ms": round(busy[q] / 1e6, 3)} for q in iv},
+           "overlap_ms": round(both / 1e6, 3), "key": key}
+    print(json.dumps(res))
+    return res
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -577,7 +633,12 @@ def main():
     ap.add_argument("--traffic", nargs=5, metavar=("WORKLOAD", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="summarize four rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE of a bench "
                          "run and of a --copy-bytes run) into " + os.path.relpath(TRAFFIC_FILE, ROOT))
+    ap.add_argument("--trace-overlap", metavar="KERNEL_TRACE_CSV",
+                    help="summarize per-stream kernel time and cross-stream overlap of a rocprofv3 kernel trace")
     args = ap.parse_args()
+    if args.trace_overlap:
+        trace_overlap(args.trace_overlap)
+        return
     if args.traffic:
         summarize_traffic(*args.traffic, copy_bytes=args.copy_bytes)
         return
@@ -604,9 +665,14 @@ def main():
     nb = args.warmup + args.batched_steps
     if "batched" in legs:
         jobs += [(3, s, 0, nb) for s in range(synth.CONFIGS[3].streams)]
+    if "serving" in legs:
+        jobs += [(4, s, 0, SERVING_CYCLE) for s in range(synth.CONFIGS[4].streams)]
     data = generate(jobs)
     head_host = data[:n_head] if "headline" in legs else None
-    batched_host = data[n_head if "headline" in legs else 0:] if "batched" in legs else None
+    o = n_head if "headline" in legs else 0
+    batched_host = data[o:o + synth.CONFIGS[3].streams] if "batched" in legs else None
+    o += synth.CONFIGS[3].streams if "batched" in legs else 0
+    serving_host = data[o:] if "serving" in legs else None
     log(f"generated {len(jobs)} stream segments in {time.perf_counter() - t0:.1f}s on {pool_size()} processes")
 
     import torch
@@ -618,7 +684,7 @@ def main():
         result["batched"] = batched_leg(batched_host, args.batched_steps, args.warmup)
         log(f"batched: {json.dumps(result['batched'])}")
     if "serving" in legs:
-        result["serving"] = serving_leg(args.serving_seconds, [8 << 30, 64 << 20])
+        result["serving"] = serving_leg(serving_host, args.serving_seconds)
     if "headline" in legs and not args.no_cpu_baseline:
         cb, identical = cpu_leg(head_host, ctx, n_single=1, n_all=min(n_head, pool_size()))
         result["cpu_baseline"] = cb

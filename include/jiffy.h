@@ -147,6 +147,21 @@ typedef struct jiffy_stream jiffy_stream;
 
 int jiffy_stream_create(const jiffy_layout* layout, const jiffy_options* options, jiffy_stream** out);
 
+/* Bytes of device memory a stream's resident state takes (two halves of
+ * quantized samples and of zero-mask words, Sec. III-D); 0 for an invalid
+ * layout. */
+size_t jiffy_stream_state_bytes(const jiffy_layout* layout);
+
+/* As jiffy_stream_create, with the resident state in caller-owned device
+ * memory: d_state (256-byte aligned) holds at least
+ * jiffy_stream_state_bytes(layout) bytes and must outlive the stream; the
+ * library allocates nothing on the device.  A server can so carve many
+ * streams' states out of one budgeted buffer and reuse the memory of
+ * streams it has closed.  JIFFY_E_INVALID on a bad layout, alignment or
+ * size. */
+int jiffy_stream_create_at(const jiffy_layout* layout, const jiffy_options* options, void* d_state,
+                           size_t state_bytes, jiffy_stream** out);
+
 /* Encodes one scan of each of n streams in one batch.
  *   d_planes[i][a]: device pointer to the height*width samples of attribute
  *                   a of stream i's new scan.
@@ -190,6 +205,46 @@ int jiffy_batch_run(jiffy_batch* b, const void* const* const* d_planes, size_t* 
                     hipStream_t stream);
 
 void jiffy_batch_destroy(jiffy_batch* b);
+
+/* ---- asynchronous steps (serving: steps in flight on several HIP streams)
+ * A jiffy_step owns a device workspace and pinned host buffers sized once at
+ * creation for batches of at most max_records records (one per attribute of
+ * each stream) and max_samples samples in all; submitting never allocates.
+ * jiffy_step_submit plans one scan of each of n streams exactly as
+ * jiffy_batch_encode_step does, enqueues the kernels on `stream` and returns
+ * at once; jiffy_step_finish waits for them, returns the lengths and modes
+ * and advances the streams.  Two step contexts can be in flight at once on
+ * different HIP streams (their work overlaps on the device); a jiffy_stream
+ * may be in at most one unfinished step (it is refused elsewhere until
+ * then).  A step context and its streams are used by one thread at a time;
+ * nothing here takes the per-device lock. */
+typedef struct jiffy_step jiffy_step;
+
+/* Device bytes a step context of these limits holds (its workspace). */
+size_t jiffy_step_workspace_bytes(uint32_t max_records, uint64_t max_samples);
+
+int jiffy_step_create(uint32_t max_records, uint64_t max_samples, jiffy_step** out);
+
+/* d_planes[i][a]: stream i's new scan of attribute a (H*W samples).
+ * d_out: device buffer of out_capacity bytes (4-byte aligned) receiving all
+ * records packed: stream 0's n_attrs records, then stream 1's right after,
+ * and so on (each stream's records are those jiffy_encode writes for its
+ * scan sequence).  JIFFY_E_CAPACITY when the batch exceeds the context's
+ * limits (nothing enqueued); JIFFY_E_INVALID for a busy stream, a stream
+ * named twice, or a step still unfinished. */
+int jiffy_step_submit(jiffy_step* step, jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
+                      void* d_out, size_t out_capacity, hipStream_t stream);
+
+/* Waits for the submitted step.  h_lens[i] (host): stream i's record bytes
+ * in the packed output (stream i starts after the lengths before it);
+ * h_modes optional [records] (0 = I, 1 = P).  JIFFY_E_CAPACITY when the
+ * packed output did not fit (nothing written, h_lens hold the sizes needed;
+ * no stream advances). */
+int jiffy_step_finish(jiffy_step* step, size_t* h_lens, uint8_t* h_modes);
+
+/* Waits for an unfinished step (its streams then do not advance) and
+ * frees the context. */
+void jiffy_step_destroy(jiffy_step* step);
 
 /* Drops the resident previous scan; the next scan is an I-scan. */
 int jiffy_stream_reset(jiffy_stream* s);

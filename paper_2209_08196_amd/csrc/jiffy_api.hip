@@ -174,6 +174,7 @@ struct EncResult {
     std::vector<uint64_t> lens;
     std::vector<uint8_t> ok;
     std::vector<uint8_t> modes;
+    std::vector<uint32_t> rec_lens;
 };
 
 // Where everything of one encode launch sequence lives in its device
@@ -187,7 +188,8 @@ struct EncLayout {
     size_t up_end = 0, total = 0;
     std::vector<size_t> o_vw, o_blk, o_slots, o_frame, o_segs;
     size_t up_bytes() const { return up_end - o_err; }
-    size_t res_bytes() const { return 16ull * no + 4ull * n + 4; }  // host results: per output len/ok, modes, error
+    // host results: per output len/ok, per record its mode, the error word, per record its length
+    size_t res_bytes() const { return 16ull * no + 8ull * n + 4; }
 };
 
 EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpec>& outs) {
@@ -358,7 +360,11 @@ void enc_results(const EncLayout& Lo, const uint8_t* hres, EncResult& result) {
         result.ok[k] = (uint8_t)ok;
     }
     const uint32_t* m = (const uint32_t*)(hres + 16ull * Lo.no);
-    for (uint32_t r = 0; r < Lo.n; ++r) result.modes[r] = (uint8_t)m[r];
+    result.rec_lens.resize(Lo.n);
+    for (uint32_t r = 0; r < Lo.n; ++r) {
+        result.modes[r] = (uint8_t)m[r];
+        result.rec_lens[r] = m[Lo.n + 1 + r];
+    }
 }
 
 // An encode plan: the layout and the plan image in `up`, valid for the
@@ -1037,16 +1043,56 @@ struct jiffy_stream {
     uint64_t* v[2][JIFFY_MAX_ATTRS];
     int cur;
     int has_prev;
+    bool owns;  // the state buffers were allocated by the library (else they live in the caller's memory)
+    bool busy;  // in a submitted step that has not finished
 };
+
+}  // extern "C"
+
+namespace {
+// The resident state of a stream, in order: for each half k and attribute a
+// the quantized samples (npx * width + 16 bytes), then the valid-sample words
+// (8 bytes per 64 samples), each part 256-byte aligned.
+size_t state_layout(const jiffy_layout* L, jiffy_stream* s, uint8_t* base) {
+    const size_t npx = (size_t)L->height * L->width, nwords = (npx + 63) / 64;
+    size_t off = 0;
+    for (int k = 0; k < 2; ++k) {
+        for (uint32_t a = 0; a < L->n_attrs; ++a) {
+            if (s) s->q[k][a] = base + off;
+            off = al(off + npx * L->width_bytes[a] + 16);
+            if (s) s->v[k][a] = (uint64_t*)(base + off);
+            off = al(off + 8 * nwords);
+        }
+    }
+    return off;
+}
+
+jiffy_stream* new_stream(const jiffy_layout* L, const jiffy_options* opt) {
+    jiffy_stream* s = new (std::nothrow) jiffy_stream();
+    if (!s) return nullptr;
+    s->layout = *L;
+    s->opt.mode = opt ? opt->mode : 0;
+    s->opt.trial_rows = (opt && opt->trial_rows) ? opt->trial_rows : 4;
+    s->cur = 0;
+    s->has_prev = 0;
+    s->busy = false;
+    return s;
+}
+}  // namespace
+
+extern "C" {
+
+size_t jiffy_stream_state_bytes(const jiffy_layout* L) {
+    if (!layout_ok(L)) return 0;
+    return state_layout(L, nullptr, nullptr);
+}
 
 int jiffy_stream_create(const jiffy_layout* L, const jiffy_options* opt, jiffy_stream** out) {
     if (!layout_ok(L) || !out) return JIFFY_E_INVALID;
     if (opt && opt->mode > 2) return JIFFY_E_INVALID;
-    jiffy_stream* s = new (std::nothrow) jiffy_stream();
+    jiffy_stream* s = new_stream(L, opt);
     if (!s) return JIFFY_E_INVALID;
-    s->layout = *L;
-    s->opt.mode = opt ? opt->mode : 0;
-    s->opt.trial_rows = (opt && opt->trial_rows) ? opt->trial_rows : 4;
+    s->owns = true;
     if (current_device(&s->device)) { delete s; return JIFFY_E_DEVICE; }
     const size_t npx = (size_t)L->height * L->width, nwords = (npx + 63) / 64;
     for (int k = 0; k < 2; ++k) {
@@ -1058,25 +1104,38 @@ int jiffy_stream_create(const jiffy_layout* L, const jiffy_options* opt, jiffy_s
             }
         }
     }
-    s->cur = 0;
-    s->has_prev = 0;
+    *out = s;
+    return JIFFY_OK;
+}
+
+int jiffy_stream_create_at(const jiffy_layout* L, const jiffy_options* opt, void* d_state, size_t state_bytes,
+                           jiffy_stream** out) {
+    if (!layout_ok(L) || !out || !d_state || (uintptr_t)d_state % kAlign) return JIFFY_E_INVALID;
+    if (opt && opt->mode > 2) return JIFFY_E_INVALID;
+    if (state_bytes < state_layout(L, nullptr, nullptr)) return JIFFY_E_INVALID;
+    jiffy_stream* s = new_stream(L, opt);
+    if (!s) return JIFFY_E_INVALID;
+    s->owns = false;
+    if (current_device(&s->device)) { delete s; return JIFFY_E_DEVICE; }
+    state_layout(L, s, (uint8_t*)d_state);
     *out = s;
     return JIFFY_OK;
 }
 
 int jiffy_stream_reset(jiffy_stream* s) {
-    if (!s) return JIFFY_E_INVALID;
+    if (!s || s->busy) return JIFFY_E_INVALID;
     s->has_prev = 0;
     return JIFFY_OK;
 }
 
 void jiffy_stream_destroy(jiffy_stream* s) {
     if (!s) return;
-    for (int k = 0; k < 2; ++k)
-        for (uint32_t a = 0; a < JIFFY_MAX_ATTRS; ++a) {
-            if (s->q[k][a]) (void)hipFree(s->q[k][a]);
-            if (s->v[k][a]) (void)hipFree(s->v[k][a]);
-        }
+    if (s->owns)
+        for (int k = 0; k < 2; ++k)
+            for (uint32_t a = 0; a < JIFFY_MAX_ATTRS; ++a) {
+                if (s->q[k][a]) (void)hipFree(s->q[k][a]);
+                if (s->v[k][a]) (void)hipFree(s->v[k][a]);
+            }
     delete s;
 }
 
@@ -1091,6 +1150,7 @@ int check_batch(jiffy_stream* const* streams, uint32_t n, const void* const* con
         const jiffy_stream* s = streams[i];
         if (!s || !d_planes[i] || !d_out[i] || (uintptr_t)d_out[i] % 4) return JIFFY_E_INVALID;
         if (s->device != dev) return JIFFY_E_SHAPE;
+        if (s->busy) return JIFFY_E_INVALID;  // in a submitted step that has not finished
         for (uint32_t a = 0; a < s->layout.n_attrs; ++a)
             if (!d_planes[i][a] || (uintptr_t)d_planes[i][a] % s->layout.width_bytes[a]) return JIFFY_E_INVALID;
         for (uint32_t k = 0; k < i; ++k)
@@ -1102,14 +1162,19 @@ int check_batch(jiffy_stream* const* streams, uint32_t n, const void* const* con
 // One record per attribute of each stream's next scan, predicting from the
 // resident previous scan; the new scan's quantized samples and valid words
 // go to the other half of the stream's state.
+// With `packed` every record goes to the one output d_out[0] (caps[0] bytes),
+// stream after stream, each right after the one before.
 void stream_specs(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes, void* const* d_out,
-                  const size_t* caps, std::vector<EncSpec>& specs, std::vector<OutSpec>& outs) {
+                  const size_t* caps, std::vector<EncSpec>& specs, std::vector<OutSpec>& outs, bool packed = false) {
     specs.clear();
-    outs.resize(n);
+    outs.resize(packed ? 1 : n);
+    uint32_t total = 0;
+    for (uint32_t i = 0; i < n; ++i) total += streams[i]->layout.n_attrs;
+    if (packed) outs[0] = OutSpec{(uint8_t*)d_out[0], caps[0], 0, total, 0, 1, &streams[0]->layout};
     for (uint32_t i = 0; i < n; ++i) {
         const jiffy_stream* s = streams[i];
         const jiffy_layout& L = s->layout;
-        outs[i] = OutSpec{(uint8_t*)d_out[i], caps[i], (uint32_t)specs.size(), L.n_attrs, 0, 1, &s->layout};
+        if (!packed) outs[i] = OutSpec{(uint8_t*)d_out[i], caps[i], (uint32_t)specs.size(), L.n_attrs, 0, 1, &s->layout};
         for (uint32_t a = 0; a < L.n_attrs; ++a) {
             EncSpec e;
             e.x = d_planes[i][a];
@@ -1123,7 +1188,7 @@ void stream_specs(jiffy_stream* const* streams, uint32_t n, const void* const* c
             e.wb = L.width_bytes[a];
             e.P = L.precision[a];
             e.attr = a;
-            e.out_id = i;
+            e.out_id = packed ? 0u : i;
             e.has_prev = s->has_prev ? 1u : 0u;
             e.prev_quantized = 1;
             e.mode_req = s->opt.mode;
@@ -1274,6 +1339,154 @@ void jiffy_batch_destroy(jiffy_batch* b) {
     if (b->up) (void)hipHostFree(b->up);
     if (b->res) (void)hipHostFree(b->res);
     delete b;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// asynchronous steps: a step context owns a workspace sized once; submit
+// enqueues a batch and returns, finish waits for it and reads the results
+// ---------------------------------------------------------------------------
+namespace {
+// Upper bounds of what enc_layout needs for any batch of at most R records
+// of at most S samples in all, with one (packed) output and resident valid
+// words: every per-record part is at most its linear size plus one alignment
+// unit, and ceil(npx / k) summed over records is at most S / k + R.
+struct StepBound {
+    size_t dev, up, res;
+};
+StepBound step_bound(uint64_t R, uint64_t S) {
+    const uint64_t nb = S / kFrame + R, nft = S / kFTile + R, nm = S / 8 + R;
+    StepBound b;
+    const size_t fixed_up = 4 + sizeof(EncOut) + sizeof(EncItem) * R + 4 * R + 4 * nft + 5 * kAlign;
+    b.up = fixed_up;
+    b.dev = sizeof(EncRes) * R + kAlign + fixed_up                             // results, then the uploaded part
+            + 16 * nb + 4 * nft + 8 * nft + 4 * R + 2 * kAlign * R              // frame info, offsets, tile states
+            + (size_t)kSlotBytes * nb + kAlign * R                              // frame slots
+            + (16 + 4 + 4) * R + nm + 4 * (nm / kZstdBlockMax + R) + kAlign * R  // mask frames
+            + 8 * (nm / 4 + 4 * R + R) + kAlign * R;                            // segment tables
+    b.res = 16 + 8 * R + 4;
+    return b;
+}
+}  // namespace
+
+struct jiffy_step {
+    int device = 0;
+    uint32_t max_records = 0;
+    uint64_t max_samples = 0;
+    DevBuf ws;
+    HostBuf up, res;
+    bool pending = false;
+    hipStream_t stream = nullptr;
+    std::vector<jiffy_stream*> streams;
+    EncLayout Lo;
+};
+
+extern "C" {
+
+size_t jiffy_step_workspace_bytes(uint32_t max_records, uint64_t max_samples) {
+    if (max_records == 0 || max_samples == 0) return 0;
+    return step_bound(max_records, max_samples).dev;
+}
+
+int jiffy_step_create(uint32_t max_records, uint64_t max_samples, jiffy_step** out) {
+    if (!out || max_records == 0 || max_samples == 0 || max_records > (1u << 24)) return JIFFY_E_INVALID;
+    jiffy_step* st = new (std::nothrow) jiffy_step();
+    if (!st) return JIFFY_E_INVALID;
+    if (current_device(&st->device)) { delete st; return JIFFY_E_DEVICE; }
+    st->max_records = max_records;
+    st->max_samples = max_samples;
+    const StepBound b = step_bound(max_records, max_samples);
+    if (hipMalloc(&st->ws.p, b.dev) != hipSuccess) { delete st; return JIFFY_E_DEVICE; }
+    st->ws.cap = b.dev;
+    if (host_alloc(&st->up.p, &st->up.d, b.up) != hipSuccess || host_alloc(&st->res.p, &st->res.d, b.res) != hipSuccess) {
+        jiffy_step_destroy(st);
+        return JIFFY_E_DEVICE;
+    }
+    st->up.cap = b.up;
+    st->res.cap = b.res;
+    *out = st;
+    return JIFFY_OK;
+}
+
+int jiffy_step_submit(jiffy_step* st, jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
+                      void* d_out, size_t out_capacity, hipStream_t stream) {
+    if (!st || st->pending || n == 0 || !d_out) return JIFFY_E_INVALID;
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    if (dev != st->device) return JIFFY_E_SHAPE;
+    void* const outs1[1] = {d_out};
+    const size_t caps1[1] = {out_capacity};
+    if (!streams || !d_planes || (uintptr_t)d_out % 4) return JIFFY_E_INVALID;
+    uint64_t recs = 0, samples = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const jiffy_stream* s = streams[i];
+        if (!s || !d_planes[i]) return JIFFY_E_INVALID;
+        if (s->device != dev) return JIFFY_E_SHAPE;
+        if (s->busy) return JIFFY_E_INVALID;
+        for (uint32_t a = 0; a < s->layout.n_attrs; ++a)
+            if (!d_planes[i][a] || (uintptr_t)d_planes[i][a] % s->layout.width_bytes[a]) return JIFFY_E_INVALID;
+        for (uint32_t k = 0; k < i; ++k)
+            if (streams[k] == s) return JIFFY_E_INVALID;
+        recs += s->layout.n_attrs;
+        samples += (uint64_t)s->layout.n_attrs * s->layout.height * s->layout.width;
+    }
+    if (recs > st->max_records || samples > st->max_samples) return JIFFY_E_CAPACITY;
+    std::vector<EncSpec> specs;
+    std::vector<OutSpec> outs;
+    stream_specs(streams, n, d_planes, outs1, caps1, specs, outs, true);
+    EncLayout Lo = enc_layout(specs, outs);
+    if (Lo.total > st->ws.cap || Lo.up_bytes() > st->up.cap || Lo.res_bytes() > st->res.cap) return JIFFY_E_CAPACITY;
+    enc_fill(Lo, specs, outs, (uint8_t*)st->ws.p, (uint8_t*)st->up.p);
+    const EncPlan plan = enc_plan(Lo, (uint8_t*)st->ws.p, (uint8_t*)st->res.d);
+    t_no_events = true;  // the step completes after this call returns: no timing events
+    const hipError_t e = enc_enqueue(Lo, plan, (uint8_t*)st->ws.p, st->up.d, stream);
+    t_no_events = false;
+    if (e != hipSuccess) return JIFFY_E_DEVICE;
+    st->streams.assign(streams, streams + n);
+    for (jiffy_stream* s : st->streams) s->busy = true;
+    st->Lo = std::move(Lo);
+    st->stream = stream;
+    st->pending = true;
+    return JIFFY_OK;
+}
+
+int jiffy_step_finish(jiffy_step* st, size_t* h_lens, uint8_t* h_modes) {
+    if (!st || !st->pending || !h_lens) return JIFFY_E_INVALID;
+    const hipError_t e = hipStreamSynchronize(st->stream);
+    st->pending = false;
+    for (jiffy_stream* s : st->streams) s->busy = false;
+    if (e != hipSuccess) return JIFFY_E_DEVICE;
+    EncResult res;
+    enc_results(st->Lo, (const uint8_t*)st->res.p, res);
+    if (res.err & kErrStall) return JIFFY_E_DEVICE;
+    const uint32_t n = (uint32_t)st->streams.size();
+    for (uint32_t i = 0, r = 0; i < n; ++i) {
+        size_t len = 0;
+        for (uint32_t a = 0; a < st->streams[i]->layout.n_attrs; ++a, ++r) {
+            len += res.rec_lens[r];
+            if (h_modes) h_modes[r] = res.modes[r];
+        }
+        h_lens[i] = len;
+    }
+    if (!res.ok[0]) return JIFFY_E_CAPACITY;
+    for (jiffy_stream* s : st->streams) {
+        s->cur ^= 1;
+        s->has_prev = 1;
+    }
+    return JIFFY_OK;
+}
+
+void jiffy_step_destroy(jiffy_step* st) {
+    if (!st) return;
+    if (st->pending) {  // an unfinished step: wait for it; its streams do not advance
+        (void)hipStreamSynchronize(st->stream);
+        for (jiffy_stream* s : st->streams) s->busy = false;
+    }
+    if (st->ws.p) (void)hipFree(st->ws.p);
+    if (st->up.p) (void)hipHostFree(st->up.p);
+    if (st->res.p) (void)hipHostFree(st->res.p);
+    delete st;
 }
 
 }  // extern "C"

@@ -974,7 +974,11 @@ __global__ __launch_bounds__(1024) void k_enc_offsets(EncPlan plan) {
     for (uint32_t r = threadIdx.x; r < plan.n_items; r += 1024) {
         const EncOut& o = plan.outs[plan.items[r].out_id];
         plan.res[r].rec_off = plan.res[r].rec_off - o.gbase + o.hdr_len;
-        if (plan.host_res) store_system((JG uint32_t*)(plan.host_res + 16ull * plan.n_outs) + r, plan.res[r].mode);
+        if (plan.host_res) {  // the record's mode, and after the error word its length
+            JG uint32_t* h = (JG uint32_t*)(plan.host_res + 16ull * plan.n_outs);
+            store_system(h + r, plan.res[r].mode);
+            store_system(h + plan.n_items + 1 + r, plan.res[r].rec_len);
+        }
     }
     if (plan.host_res && threadIdx.x == 0)
         store_system((JG uint32_t*)(plan.host_res + 16ull * plan.n_outs) + plan.n_items, *plan.err);

@@ -155,7 +155,8 @@ struct EncPlan {
     const JG uint32_t* ftile_item;  // device: item of each kFTile tile
     const JG uint32_t* ftile_first; // device: first kFTile tile of each item
     JG uint8_t* host_res;        // host-mapped results (or null): per output {u64 len, u32 ok, u32 -}, then
-                                 // per record its mode (u32), then the error word
+                                 // per record its mode (u32), then the error word, then per record its
+                                 // length (u32)
     uint32_t ftpi;               // kFTile tiles per record when every record has the same size (the
                                  // maps above are then unused), else 0
     uint32_t n_items, n_outs, n_ftiles;

@@ -22,7 +22,10 @@ MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY = 0, 1, 2
 
 SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_encode_noalloc", "jiffy_peek", "jiffy_decode", "jiffy_decode_layout",
            "jiffy_status_string",
-           "jiffy_stream_create", "jiffy_batch_encode_step", "jiffy_stream_reset", "jiffy_stream_destroy",
+           "jiffy_stream_create", "jiffy_stream_state_bytes", "jiffy_stream_create_at",
+           "jiffy_batch_encode_step", "jiffy_stream_reset", "jiffy_stream_destroy",
+           "jiffy_step_workspace_bytes", "jiffy_step_create", "jiffy_step_submit", "jiffy_step_finish",
+           "jiffy_step_destroy",
            "jiffy_batch_create", "jiffy_batch_run", "jiffy_batch_destroy",
            "jiffy_profile_enable", "jiffy_profile_read")
 
@@ -76,6 +79,21 @@ def lib():
         L.jiffy_status_string.argtypes = [ctypes.c_int]
         L.jiffy_stream_create.restype = ctypes.c_int
         L.jiffy_stream_create.argtypes = [ctypes.POINTER(Layout), ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.jiffy_stream_state_bytes.restype = sz
+        L.jiffy_stream_state_bytes.argtypes = [ctypes.POINTER(Layout)]
+        L.jiffy_stream_create_at.restype = ctypes.c_int
+        L.jiffy_stream_create_at.argtypes = [ctypes.POINTER(Layout), ctypes.POINTER(Options), vp, sz,
+                                             ctypes.POINTER(vp)]
+        L.jiffy_step_workspace_bytes.restype = sz
+        L.jiffy_step_workspace_bytes.argtypes = [u32, ctypes.c_uint64]
+        L.jiffy_step_create.restype = ctypes.c_int
+        L.jiffy_step_create.argtypes = [u32, ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.jiffy_step_submit.restype = ctypes.c_int
+        L.jiffy_step_submit.argtypes = [vp, vp, u32, vp, vp, sz, vp]
+        L.jiffy_step_finish.restype = ctypes.c_int
+        L.jiffy_step_finish.argtypes = [vp, vp, vp]
+        L.jiffy_step_destroy.restype = None
+        L.jiffy_step_destroy.argtypes = [vp]
         L.jiffy_batch_encode_step.restype = ctypes.c_int
         L.jiffy_batch_encode_step.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp]
         L.jiffy_stream_reset.restype = ctypes.c_int
@@ -350,18 +368,33 @@ class Decoder:
         return self.outs
 
 
+def stream_state_bytes(height, width, widths):
+    """Device bytes of a stream's resident state (jiffy_stream_state_bytes)."""
+    lay = make_layout(height, width, widths)
+    return lib().jiffy_stream_state_bytes(ctypes.byref(lay))
+
+
 class Stream:
     """A sensor stream whose previous quantized scan stays resident on the
-    device (jiffy_stream)."""
+    device (jiffy_stream).  With `state` (a device uint8 tensor of at least
+    stream_state_bytes() bytes, 256-byte aligned) the state lives in that
+    caller-owned memory (jiffy_stream_create_at), which must outlive the
+    stream."""
 
-    def __init__(self, height, width, widths, precisions=None, mode=MODE_AUTO, trial_rows=0):
+    def __init__(self, height, width, widths, precisions=None, mode=MODE_AUTO, trial_rows=0, state=None):
         self.layout = make_layout(height, width, widths, precisions)
         self.widths = list(widths)
         opt = Options(mode, trial_rows)
         h = ctypes.c_void_p()
-        rc = lib().jiffy_stream_create(ctypes.byref(self.layout), ctypes.byref(opt), ctypes.byref(h))
+        if state is None:
+            rc = lib().jiffy_stream_create(ctypes.byref(self.layout), ctypes.byref(opt), ctypes.byref(h))
+        else:
+            _check_bytes_out(state, "state")
+            rc = lib().jiffy_stream_create_at(ctypes.byref(self.layout), ctypes.byref(opt),
+                                              ctypes.c_void_p(state.data_ptr()), state.numel(), ctypes.byref(h))
         if rc:
-            raise JiffyError(rc, "jiffy_stream_create")
+            raise JiffyError(rc, "jiffy_stream_create" if state is None else "jiffy_stream_create_at")
+        self.state = state
         self.handle = h
 
     def record_bound(self):
@@ -486,3 +519,98 @@ def batch_encode_step(streams, scans, outs, stream=None):
     if rc:
         raise JiffyError(rc, "jiffy_batch_encode_step")
     return list(lens), _split_modes(streams, mbuf)
+
+
+class PreparedScan:
+    """One scan's attribute tensors, checked once against a layout (sample
+    count, width, device, contiguity) so that repeated submissions pass
+    their pointers without checking again.  Holds the tensors alive."""
+    __slots__ = ("tensors", "ptrs", "key")
+
+    def __init__(self, height, width, widths, tensors):
+        lay = make_layout(height, width, widths)
+        if tensors is None or len(tensors) != lay.n_attrs:
+            raise ValueError(f"{lay.n_attrs} attribute tensors are needed")
+        for a, t in enumerate(tensors):
+            _check_tensor(t, height * width, widths[a], f"attribute {a}")
+        self.tensors = list(tensors)
+        self.ptrs = tuple(t.data_ptr() for t in tensors)
+        self.key = (int(height), int(width), tuple(int(w) for w in widths))
+
+
+def _stream_key(s):
+    lay = s.layout
+    return (lay.height, lay.width, tuple(lay.width_bytes[a] for a in range(lay.n_attrs)))
+
+
+def step_workspace_bytes(max_records, max_samples):
+    """Device bytes a Step of these limits holds (jiffy_step_workspace_bytes)."""
+    return lib().jiffy_step_workspace_bytes(int(max_records), int(max_samples))
+
+
+class Step:
+    """An asynchronous batch step (jiffy_step): a workspace sized once for
+    batches of at most max_records records and max_samples samples.
+    submit() enqueues one scan of each stream and returns at once; finish()
+    waits and returns (lengths, modes).  The records of all streams land
+    packed in `out`, stream after stream."""
+
+    def __init__(self, max_records, max_samples):
+        h = ctypes.c_void_p()
+        rc = lib().jiffy_step_create(int(max_records), int(max_samples), ctypes.byref(h))
+        if rc:
+            raise JiffyError(rc, "jiffy_step_create")
+        self.handle = h
+        self.max_records = int(max_records)
+        self._lens = (ctypes.c_size_t * 1)()
+        self._modes = np.zeros(1, np.uint8)
+        self._streams = []
+        self._keep = None
+
+    def submit(self, streams, scans, out, stream=None):
+        n = len(streams)
+        if n == 0 or len(scans) != n:
+            raise ValueError("one scan per stream is needed")
+        for i, (s, sc) in enumerate(zip(streams, scans)):
+            if not getattr(s, "handle", None):
+                raise ValueError(f"stream {i} is closed")
+            if isinstance(sc, PreparedScan):
+                if sc.key != _stream_key(s):
+                    raise ValueError(f"stream {i}: the prepared scan was checked for another layout")
+            else:
+                _check_scan(s, sc, f"stream {i}")
+        _check_bytes_out(out, "out")
+        sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
+        inner = [(ctypes.c_void_p * len(sc.ptrs))(*sc.ptrs) if isinstance(sc, PreparedScan)
+                 else (ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
+        planes = (ctypes.c_void_p * n)(*[ctypes.cast(x, ctypes.c_void_p).value for x in inner])
+        rc = lib().jiffy_step_submit(self.handle, ctypes.cast(sh, ctypes.c_void_p), n,
+                                     ctypes.cast(planes, ctypes.c_void_p), ctypes.c_void_p(out.data_ptr()),
+                                     out.numel(), _stream_handle(stream))
+        if rc:
+            raise JiffyError(rc, "jiffy_step_submit")
+        self._streams = list(streams)
+        self._keep = (sh, inner, planes, scans, out)  # alive until the step is finished
+        self._lens = (ctypes.c_size_t * n)()
+        self._modes = np.zeros(sum(s.layout.n_attrs for s in streams), np.uint8)
+
+    def finish(self):
+        """-> (lengths list, modes ndarray [n, A]) of the submitted step."""
+        rc = lib().jiffy_step_finish(self.handle, ctypes.cast(self._lens, ctypes.c_void_p),
+                                     self._modes.ctypes.data_as(ctypes.c_void_p))
+        self._keep = None
+        if rc:
+            raise JiffyError(rc, "jiffy_step_finish")
+        return list(self._lens), _split_modes(self._streams, self._modes)
+
+    def close(self):
+        if self.handle:
+            lib().jiffy_step_destroy(self.handle)
+            self.handle = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

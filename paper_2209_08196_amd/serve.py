@@ -1,93 +1,110 @@
 """Continuous-batching encode server over many sensor streams.
 
-Scans arrive from many sensors at their own rates; every step the server
-encodes the scans that have arrived, at most one per stream, in one batched
-call (jiffy_batch_encode_step), each stream predicting from its own resident
-previous scan (Sec. III-D).  A stream's records are therefore exactly those
-of encoding its scan sequence alone.
+Scans arrive from many sensors at their own rates.  A producer thread
+releases each scan at its arrival time on the wall clock; the serving loop
+admits it, and whenever one of its step contexts is free it submits the
+scans that have arrived -- at most one per stream, oldest first -- as one
+asynchronous batched step (jiffy_step_submit) on that context's own HIP
+stream, then goes on admitting arrivals and submitting to the other context
+while the first runs.  A finished step's records come back to the host in
+one copy; a scan's latency is the time its records are on the host minus its
+arrival time.  Each stream predicts from its own resident previous scan
+(Sec. III-D), so a stream's records are exactly those of encoding its scan
+sequence alone.
 
-Device memory is bounded by a budget: a stream is admitted when its
-resident state (two halves of quantized samples and valid words, and its
-output buffer) fits next to the streams already admitted and the encoder
-workspace reserved for one step; a stream that does not fit is rejected and
-its scans are counted as dropped.  Steps take arrived scans in arrival
-order while their encoder workspace fits the reserve.
-
-Time is virtual: arrivals follow their timestamps, and each step advances
-the clock by its measured duration (submit to records on the host), so the
-reported latency (completion minus arrival) is what a server with this
-throughput would show under that arrival process.
+Device memory is bounded by a budget fixed at start: the step contexts'
+workspaces and packed output buffers are allocated once; the rest is a pool
+from which each admitted stream's resident state is carved
+(jiffy_stream_create_at).  A scan of a stream that is not admitted is
+admitted when its state fits in the pool, else dropped (counted).  A stream
+idle for longer than `idle_s` is closed and its state returned to the pool,
+where later arrivals reuse it; its next scan starts a new session (an
+I-scan).  Nothing is allocated on the device while serving.
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
+import threading
 import time
 
 import numpy as np
 
-_SLOT_BYTES = 576      # device bytes per frame slot of the encoder
-_FRAME = 128
-_FTILE = 8192
 _ALIGN = 256
-_WS_GROWTH = 1.25      # the library grows its workspace by a quarter over the need
 
 
 def _al(x):
     return (x + _ALIGN - 1) // _ALIGN * _ALIGN
 
 
-def state_bytes(height, width, widths):
-    """Device bytes a stream keeps resident: two halves of quantized
-    samples (each padded by 16 bytes) and of 64-pixel valid words."""
-    npx = height * width
-    nwords = (npx + 63) // 64
-    return sum(2 * (npx * w + 16) + 2 * 8 * nwords for w in widths)
-
-
-def record_bound(height, width, widths):
-    """Worst-case bytes of one scan's records (the output buffer)."""
-    npx = height * width
-    nm = (npx + 7) // 8
-    nb = (npx + _FRAME - 1) // _FRAME
-    total = 0
-    for w in widths:
-        frame = 16 + nm + 4 * (nm // 131072 + 1)
-        total += 12 + frame + 3 + 4 + 3 * nb + 3 + nb * 16 * 8 * w + 3
-    return total
-
-
-def workspace_bytes(height, width, widths):
-    """Encoder workspace of one scan (all its attributes) in a batched step."""
-    npx = height * width
-    nwords = (npx + 63) // 64
-    maxnb = (npx + _FRAME - 1) // _FRAME
-    nm = (npx + 7) // 8
-    nft = (npx + _FTILE - 1) // _FTILE
-    per_attr = (_al(16 * maxnb + 4 * nft) + _al(8 * nft + 4) + _al(_SLOT_BYTES * maxnb)
-                + _al(16 + nm + 4 * (nm // 131072 + 1)) + _al(8 * (nm // 4 + 4)) + _al(8 * nwords) + 512 + 8 * (nft + 1))
-    return len(widths) * per_attr + 1024
-
-
-@dataclasses.dataclass
+@dataclasses.dataclass(frozen=True)
 class StreamSpec:
     height: int
     width: int
     widths: tuple
     precisions: tuple
 
+    @property
+    def records(self):
+        return len(self.widths)
+
+    @property
+    def samples(self):
+        return self.height * self.width * len(self.widths)
+
+
+class Pool:
+    """First-fit allocator over [0, capacity) in 256-byte units, with
+    coalescing frees.  Offsets only: the memory itself is the backend's."""
+
+    def __init__(self, capacity):
+        self.capacity = int(capacity) // _ALIGN * _ALIGN
+        self.free = [(0, self.capacity)] if self.capacity > 0 else []  # sorted (offset, size)
+        self.used = 0
+        self.peak = 0
+
+    def alloc(self, nbytes):
+        n = _al(max(int(nbytes), 1))
+        for i, (o, s) in enumerate(self.free):
+            if s >= n:
+                if s == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (o + n, s - n)
+                self.used += n
+                self.peak = max(self.peak, self.used)
+                return o
+        return None
+
+    def release(self, offset, nbytes):
+        n = _al(max(int(nbytes), 1))
+        self.used -= n
+        self.free.append((offset, n))
+        self.free.sort()
+        merged = []
+        for o, s in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + s)
+            else:
+                merged.append((o, s))
+        self.free = merged
+
 
 @dataclasses.dataclass
 class ServeStats:
     scans_done: int = 0
     scans_dropped: int = 0
-    streams_admitted: int = 0
-    streams_rejected: int = 0
+    admissions: int = 0
+    evictions: int = 0
+    streams_seen: int = 0
     steps: int = 0
     points: int = 0
+    wall_s: float = 0.0
     busy_s: float = 0.0
-    sim_end_s: float = 0.0
-    resident_bytes: int = 0
+    overlap_steps: int = 0
+    pool_bytes: int = 0
+    pool_peak_bytes: int = 0
+    fixed_bytes: int = 0
     latencies_s: list = dataclasses.field(default_factory=list)
     batch_sizes: list = dataclasses.field(default_factory=list)
 
@@ -95,135 +112,305 @@ class ServeStats:
         lat = np.asarray(self.latencies_s) if self.latencies_s else np.zeros(1)
         return {
             "scans": self.scans_done, "dropped_scans": self.scans_dropped,
-            "streams_admitted": self.streams_admitted, "streams_rejected": self.streams_rejected,
-            "steps": self.steps, "mean_batch": round(float(np.mean(self.batch_sizes)) if self.batch_sizes else 0, 2),
+            "admissions": self.admissions, "evictions": self.evictions,
+            "steps": self.steps, "steps_submitted_while_another_ran": self.overlap_steps,
+            "mean_batch": round(float(np.mean(self.batch_sizes)) if self.batch_sizes else 0, 2),
+            "max_batch": int(max(self.batch_sizes)) if self.batch_sizes else 0,
             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
             "max_ms": round(1e3 * float(lat.max()), 3),
+            "points_per_s": round(self.points / self.wall_s, 1) if self.wall_s else 0.0,
             "points_per_s_busy": round(self.points / self.busy_s, 1) if self.busy_s else 0.0,
-            "points_per_s_offered": round(self.points / self.sim_end_s, 1) if self.sim_end_s else 0.0,
-            "resident_bytes": self.resident_bytes,
+            "wall_s": round(self.wall_s, 3),
+            "device_bytes_fixed": self.fixed_bytes, "state_pool_bytes": self.pool_bytes,
+            "state_pool_peak_bytes": self.pool_peak_bytes,
         }
 
 
 class Server:
-    """budget_bytes: device bytes the server may use (resident stream
-    states, output buffers, the encoder workspace of one step).
-    encode_step(stream_ids, scans) -> list of bytes objects (one per stream)
-    is the batched encoder; Server.gpu() builds the one over libjiffy."""
+    """budget_bytes: device bytes the server may use in all.  backend: the
+    encoder (GpuBackend over libjiffy, or a stand-in for host-logic tests)
+    exposing state_bytes(spec), record_bound(spec), setup(slots, max_records,
+    max_samples, out_capacity, pool_bytes) -> fixed device bytes,
+    open(sid, spec, offset), close(sid), submit(slot, sids, scans),
+    done(slot) -> bool, finish(slot) -> list of record bytes.
+    Steps hold at most max_records records, max_samples samples and
+    out_capacity bytes of records."""
 
-    def __init__(self, specs: dict, budget_bytes: int, encode_step, max_batch: int = 256, on_admit=None):
+    def __init__(self, specs: dict, budget_bytes: int, backend, slots: int = 2, max_records: int = 256,
+                 max_samples: int = 16 << 20, idle_s: float = 0.5):
         self.specs = specs
-        self.on_admit = on_admit  # called with a stream id when it is admitted (resident state set up)
+        self.backend = backend
+        self.slots = slots
+        self.max_records = max_records
+        self.max_samples = max_samples
+        self.idle_s = idle_s
         self.budget = int(budget_bytes)
-        self.encode_step = encode_step
-        self.max_batch = max_batch
-        self.admitted = set()
-        self.rejected = set()
-        self.resident = 0
-        # the workspace reserve: the largest single scan's need, grown as the library grows
-        self.ws_reserve = int(_WS_GROWTH * max(workspace_bytes(s.height, s.width, s.widths)
-                                              for s in specs.values()))
-        self.results = collections.defaultdict(list)  # stream id -> list of record bytes
+        # the largest single scan must fit a step
+        big = max(specs.values(), key=lambda s: s.samples)
+        self.max_samples = max(self.max_samples, big.samples)
+        self.out_capacity = max(backend.record_bound(s) for s in specs.values())
+        self.out_capacity = max(self.out_capacity, int(self.max_samples * 4.25) + 4096)
+        self.fixed = backend.step_bytes(self.max_records, self.max_samples, self.out_capacity) * slots
+        if self.fixed >= self.budget:
+            # shrink the steps to a quarter of the budget, down to one scan of the largest stream
+            per = self.budget // (4 * slots)
+            s = big.samples
+            while s * 2 <= self.max_samples and backend.step_bytes(
+                    self.max_records, s * 2, int(s * 2 * 4.25) + 4096) <= per:
+                s *= 2
+            self.max_samples = s
+            self.out_capacity = max(max(backend.record_bound(x) for x in specs.values()), int(s * 4.25) + 4096)
+            self.fixed = backend.step_bytes(self.max_records, self.max_samples, self.out_capacity) * slots
+        if self.fixed >= self.budget:
+            raise ValueError(f"a budget of {self.budget} bytes cannot hold {slots} steps of one scan "
+                             f"({self.fixed} bytes)")
+        self.pool = Pool(self.budget - self.fixed)
+        backend.setup(slots, self.max_records, self.max_samples, self.out_capacity, self.pool.capacity)
+        self.open = {}       # sid -> pool offset of its state
+        self.last_use = {}   # sid -> time of its last scan's arrival or completion
+        self.session = collections.defaultdict(int)  # sid -> sessions opened so far
+        self.results = collections.defaultdict(list)  # sid -> [(session, scan index, record bytes), ...]
 
-    def _stream_cost(self, sid):
-        s = self.specs[sid]
-        return state_bytes(s.height, s.width, s.widths) + record_bound(s.height, s.width, s.widths)
-
-    def admit(self, sid):
-        if sid in self.admitted:
+    # -- admission --------------------------------------------------------
+    def _admit(self, sid, st):
+        if sid in self.open:
             return True
-        if sid in self.rejected:
+        spec = self.specs[sid]
+        off = self.pool.alloc(self.backend.state_bytes(spec))
+        if off is None:
             return False
-        need = self._stream_cost(sid)
-        if self.resident + need + self.ws_reserve <= self.budget:
-            self.admitted.add(sid)
-            self.resident += need
-            if self.on_admit:
-                self.on_admit(sid)
-            return True
-        self.rejected.add(sid)
-        return False
+        self.backend.open(sid, spec, off)
+        self.open[sid] = off
+        self.session[sid] += 1
+        st.admissions += 1
+        return True
 
-    def _ws_available(self):
-        return max(0, int((self.budget - self.resident) / _WS_GROWTH))
+    def _evict(self, sid, st):
+        self.backend.close(sid)
+        self.pool.release(self.open.pop(sid), self.backend.state_bytes(self.specs[sid]))
+        st.evictions += 1
 
-    def run(self, arrivals, scan_of, keep_results=False):
-        """arrivals: time-sorted (t, stream id, scan index); scan_of(sid, k)
-        returns the scan's per-attribute device tensors.  keep_results: True,
-        or a set of stream ids whose records are kept in self.results.
-        Returns ServeStats."""
-        st = ServeStats()
-        pending = collections.OrderedDict()  # sid -> deque of (t, k)
-        queue = collections.deque(arrivals)
-        clock = 0.0
-        while queue or any(pending.values()):
-            if not any(pending.values()):
-                clock = max(clock, queue[0][0])
-            while queue and queue[0][0] <= clock:
-                t, sid, k = queue.popleft()
-                if not self.admit(sid):
-                    st.scans_dropped += 1
-                    continue
-                pending.setdefault(sid, collections.deque()).append((t, k))
-            # one scan per stream, oldest arrivals first, while the workspace fits
-            heads = sorted((dq[0][0], sid) for sid, dq in pending.items() if dq)
-            ws_left = self._ws_available()
-            batch = []
-            for t, sid in heads:
-                s = self.specs[sid]
-                w = workspace_bytes(s.height, s.width, s.widths)
-                if batch and (w > ws_left or len(batch) >= self.max_batch):
+    def _choose(self, pending, busy):
+        """Streams for the next step: heads of the pending queues, oldest
+        first, one per stream, within the step limits."""
+        heads = sorted((dq[0][0], sid) for sid, dq in pending.items() if dq and sid not in busy)
+        batch, recs, samples, out = [], 0, 0, 0
+        for _, sid in heads:
+            s = self.specs[sid]
+            rb = self.backend.record_bound(s)
+            if batch and (recs + s.records > self.max_records or samples + s.samples > self.max_samples
+                          or out + rb > self.out_capacity):
+                break
+            batch.append(sid)
+            recs += s.records
+            samples += s.samples
+            out += rb
+        return batch
+
+    def run(self, arrivals, scan_of, speed: float = 1.0, keep_results=False):
+        """arrivals: time-sorted (t, stream id, scan index), t in seconds of
+        the sensors' clock; they are released at t / speed of wall time.
+        scan_of(sid, k) returns the scan's per-attribute tensors (or a
+        jiffy.PreparedScan of them), resident on the device before the run.
+        keep_results: True, or a set of stream ids whose records are kept in
+        self.results.  Returns ServeStats."""
+        st = ServeStats(fixed_bytes=self.fixed, pool_bytes=self.pool.capacity)
+        q = collections.deque()
+        cv = threading.Condition()
+        state = {"done": False}
+        t0 = time.perf_counter() + 0.01
+
+        def producer():
+            for t, sid, k in arrivals:
+                if state.get("stop"):
                     break
-                ws_left -= w
-                batch.append(sid)
-            if not batch:  # every scan that arrived was dropped
-                continue
-            items = [(sid, pending[sid].popleft()) for sid in batch]
-            t0 = time.perf_counter()
-            recs = self.encode_step(batch, [scan_of(sid, k) for sid, (t, k) in items])
-            d = time.perf_counter() - t0
-            clock += d
-            st.busy_s += d
-            st.steps += 1
-            st.batch_sizes.append(len(batch))
-            for (sid, (t, k)), r in zip(items, recs):
-                st.latencies_s.append(clock - t)
-                st.scans_done += 1
-                s = self.specs[sid]
-                st.points += s.height * s.width * len(s.widths)
-                if keep_results is True or (keep_results and sid in keep_results):
-                    self.results[sid].append(r)
-        st.sim_end_s = max(clock, arrivals[-1][0] if arrivals else 0.0)
-        st.streams_admitted = len(self.admitted)
-        st.streams_rejected = len(self.rejected)
-        st.resident_bytes = self.resident
+                due = t0 + t / speed
+                d = due - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                with cv:
+                    q.append((due, sid, k))
+                    cv.notify()
+            with cv:
+                state["done"] = True
+                cv.notify()
+
+        if hasattr(self.backend, "begin"):
+            self.backend.begin()
+        th = threading.Thread(target=producer, daemon=True)
+        th.start()
+        pending = collections.OrderedDict()  # sid -> deque of (due, k)
+        busy = set()
+        inflight = collections.deque()       # (slot, [(sid, due, k, session)], t_submit)
+        free = list(range(self.slots))
+        seen = set()
+        self._busy_until = t0
+        try:
+            while True:
+                with cv:
+                    incoming = list(q)
+                    q.clear()
+                    prod_done = state["done"]
+                now = time.perf_counter()
+                for due, sid, k in incoming:
+                    seen.add(sid)
+                    if not self._admit(sid, st):
+                        st.scans_dropped += 1
+                        continue
+                    pending.setdefault(sid, collections.deque()).append((due, k))
+                    self.last_use[sid] = due
+                # idle streams give their state back
+                for sid in [s for s in self.open if s not in busy and not pending.get(s)
+                            and now - self.last_use.get(s, now) > self.idle_s]:
+                    self._evict(sid, st)
+                # the oldest step in flight, if it is done
+                if inflight and self.backend.done(inflight[0][0]):
+                    self._complete(inflight.popleft(), busy, free, st, keep_results)
+                    continue
+                if free:
+                    batch = self._choose(pending, busy)
+                    if batch:
+                        slot = free.pop()
+                        items = []
+                        for sid in batch:
+                            due, k = pending[sid].popleft()
+                            items.append((sid, due, k, self.session[sid]))
+                        t_sub = time.perf_counter()
+                        if inflight:
+                            st.overlap_steps += 1
+                        self.backend.submit(slot, [i[0] for i in items], [scan_of(i[0], i[2]) for i in items])
+                        busy.update(batch)
+                        inflight.append((slot, items, t_sub))
+                        st.batch_sizes.append(len(batch))
+                        st.steps += 1
+                        continue
+                if inflight:
+                    if not free:  # both contexts busy: wait for the oldest step
+                        self._complete(inflight.popleft(), busy, free, st, keep_results)
+                    else:         # a context is free but nothing can go yet: wait briefly for either
+                        with cv:
+                            if not q:
+                                cv.wait(timeout=0.0002)
+                    continue
+                if prod_done and not any(pending.values()):
+                    with cv:
+                        if not q:
+                            break
+                    continue
+                with cv:
+                    if not q and not state["done"]:
+                        cv.wait(timeout=0.002)
+        finally:
+            state["stop"] = True
+            th.join()
+            for slot, _, _ in inflight:
+                self.backend.finish(slot)
+        st.wall_s = time.perf_counter() - t0
+        st.streams_seen = len(seen)
+        st.pool_peak_bytes = self.pool.peak
         return st
 
+    def _complete(self, entry, busy, free, st, keep_results):
+        slot, items, t_sub = entry
+        recs = self.backend.finish(slot)
+        t_done = time.perf_counter()
+        start = max(t_sub, self._busy_until)  # busy time: the union of the steps' submit-to-done spans
+        if t_done > start:
+            st.busy_s += t_done - start
+        self._busy_until = max(self._busy_until, t_done)
+        free.append(slot)
+        for (sid, due, k, sess), r in zip(items, recs):
+            busy.discard(sid)
+            st.latencies_s.append(t_done - due)
+            st.scans_done += 1
+            st.points += self.specs[sid].samples
+            self.last_use[sid] = t_done
+            if keep_results is True or (keep_results and sid in keep_results):
+                self.results[sid].append((sess, k, r))
+
+    def close(self):
+        for sid in list(self.open):
+            self.backend.close(sid)
+            self.pool.release(self.open.pop(sid), self.backend.state_bytes(self.specs[sid]))
+        self.backend.shutdown()
+
     @staticmethod
-    def gpu(specs: dict, budget_bytes: int, max_batch: int = 256):
-        """A server over libjiffy: one jiffy_stream per admitted stream and a
-        device output buffer each; records are copied to the host."""
+    def gpu(specs: dict, budget_bytes: int, **kw):
+        """A server over libjiffy (GpuBackend)."""
+        return Server(specs, budget_bytes, GpuBackend(), **kw)
+
+
+class GpuBackend:
+    """libjiffy: one jiffy_step per slot on its own HIP stream, a packed
+    output buffer and a pinned host buffer per slot, and one device pool for
+    the streams' resident states -- all allocated in setup()."""
+
+    def state_bytes(self, spec):
+        from . import jiffy
+        return jiffy.stream_state_bytes(spec.height, spec.width, spec.widths)
+
+    def record_bound(self, spec):
+        from . import jiffy
+        lay = jiffy.make_layout(spec.height, spec.width, spec.widths, spec.precisions)
+        return jiffy.encode_bound(lay, 1) - (20 + 8 * lay.n_attrs + 4 * lay.n_attrs)
+
+    def step_bytes(self, max_records, max_samples, out_capacity):
+        from . import jiffy
+        return jiffy.step_workspace_bytes(max_records, max_samples) + _al(out_capacity)
+
+    def setup(self, slots, max_records, max_samples, out_capacity, pool_bytes):
         import torch
 
         from . import jiffy
-        streams, outs = {}, {}
+        self.jiffy = jiffy
+        self.steps = [jiffy.Step(max_records, max_samples) for _ in range(slots)]
+        self.outs = [torch.empty(out_capacity, dtype=torch.uint8, device="cuda") for _ in range(slots)]
+        self.host = [torch.empty(out_capacity, dtype=torch.uint8, pin_memory=True) for _ in range(slots)]
+        self.hip = [torch.cuda.Stream() for _ in range(slots)]
+        self.pool = torch.empty(max(pool_bytes, _ALIGN), dtype=torch.uint8, device="cuda")
+        self.streams = {}
+        self.inflight = {}
 
-        def on_admit(sid):  # the stream's resident state and output buffer
-            s = specs[sid]
-            streams[sid] = jiffy.Stream(s.height, s.width, s.widths, s.precisions)
-            outs[sid] = torch.empty(streams[sid].record_bound(), dtype=torch.uint8, device="cuda")
+    def open(self, sid, spec, offset):
+        n = self.state_bytes(spec)
+        self.streams[sid] = self.jiffy.Stream(spec.height, spec.width, spec.widths, spec.precisions,
+                                              state=self.pool[offset:offset + n])
 
-        def encode_step(sids, scans):
-            lens, _ = jiffy.batch_encode_step([streams[s] for s in sids], scans, [outs[s] for s in sids])
-            host = [outs[s][:n].to("cpu", non_blocking=True) for s, n in zip(sids, lens)]
-            torch.cuda.synchronize()
-            return [h.numpy().tobytes() for h in host]
+    def close(self, sid):
+        self.streams.pop(sid).close()
 
-        srv = Server(specs, budget_bytes, encode_step, max_batch, on_admit)
-        srv._streams = streams
-        return srv
+    def begin(self):
+        # the scans are resident before serving starts (written on other streams): one wait here,
+        # none per step
+        import torch
+        torch.cuda.synchronize()
 
-    def close(self):
-        for s in getattr(self, "_streams", {}).values():
+    def submit(self, slot, sids, scans):
+        self.steps[slot].submit([self.streams[s] for s in sids], scans, self.outs[slot], stream=self.hip[slot])
+        self.inflight[slot] = len(sids)
+
+    def done(self, slot):
+        return self.hip[slot].query()
+
+    def finish(self, slot):
+        lens, _ = self.steps[slot].finish()
+        total = int(sum(lens))
+        host = self.host[slot]
+        with __import__("torch").cuda.stream(self.hip[slot]):
+            host[:total].copy_(self.outs[slot][:total], non_blocking=True)
+        self.hip[slot].synchronize()
+        buf = host[:total].numpy().tobytes()
+        out, p = [], 0
+        for n in lens:
+            out.append(buf[p:p + n])
+            p += n
+        self.inflight.pop(slot, None)
+        return out
+
+    def shutdown(self):
+        for s in self.streams.values():
             s.close()
+        self.streams.clear()
+        for st in getattr(self, "steps", []):
+            st.close()

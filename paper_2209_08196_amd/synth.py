@@ -293,20 +293,31 @@ def random_scans(rng, T, H, W, dtype, zero_frac=0.2, scale=None):
     return np.where(z, 0, v).astype(dt)
 
 
-def serving_arrivals(n_streams: int, duration_s: float, base_seed: int = 0):
+def serving_arrivals(n_streams: int, duration_s: float, base_seed: int = 0, session_s=None):
     """Arrival times (s) of scans for the serving configuration: each stream
     runs at 10 or 20 Hz (fair coin) with a random phase and Poisson(2) ms
-    jitter.  Returns a list of (time, stream_id, scan_index), time-sorted."""
+    jitter.  With session_s = (lo, hi) each stream is connected only for a
+    window of U(lo, hi) seconds starting at a uniform time (sensors that come
+    and go).  Returns a list of (time, stream_id, scan_index), time-sorted;
+    scan indices count each stream's scans from 0."""
     rng = np.random.default_rng(np.random.SeedSequence([4, 999, base_seed]))
     events = []
     for s in range(n_streams):
         period = 0.1 if rng.random() < 0.5 else 0.05
         phase = rng.uniform(0, period)
-        k = 0
+        lo, hi = 0.0, duration_s
+        if session_s is not None:
+            length = min(rng.uniform(*session_s), duration_s)
+            lo = rng.uniform(0, duration_s - length)
+            hi = lo + length
+        k = j = 0
         while True:
-            t = phase + k * period + rng.poisson(2.0) * 1e-3
-            if t >= duration_s:
+            t = phase + j * period + rng.poisson(2.0) * 1e-3
+            j += 1
+            if t >= hi or t >= duration_s:
                 break
+            if t < lo:
+                continue
             events.append((t, s, k))
             k += 1
     events.sort()
