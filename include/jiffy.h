@@ -251,6 +251,23 @@ int jiffy_stream_reset(jiffy_stream* s);
 
 void jiffy_stream_destroy(jiffy_stream* s);
 
+/* ---- launch configuration (the autotuner's knobs) -----------------------
+ * How encodes run, for the whole process, from the next call on (a batch
+ * keeps the configuration in force when it was created): fused = 0 runs
+ * the chain of kernels (decision, tiles, mask frames, sizes, offsets,
+ * assembly); fused = 1 runs the same work as one persistent launch whose
+ * workgroups (wgs_per_cu per compute unit; 0 = as many as one holds) take
+ * the work items from a queue in dependency order.  The output is the same
+ * byte for byte.  jiffy_get_tuning also reports how many workgroups of the
+ * fused kernel one compute unit holds (needs a device). */
+typedef struct {
+    uint32_t fused;
+    uint32_t wgs_per_cu;
+} jiffy_tuning;
+
+int jiffy_set_tuning(const jiffy_tuning* tuning);
+int jiffy_get_tuning(jiffy_tuning* tuning, uint32_t* max_wgs_per_cu);
+
 /* ---- kernel timing (benchmarks) ----------------------------------------
  * While enabled, every kernel this library launches is bracketed by HIP
  * events recorded on the stream it runs on, and the elapsed times add up

@@ -3,6 +3,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -183,8 +184,10 @@ struct EncResult {
 struct EncLayout {
     uint32_t n = 0, no = 0, n_ftiles = 0, max_asm = 1;
     uint32_t ftpi = 0;  // tiles per record when all records have the same size (no tile maps)
-    std::vector<uint32_t> ftile_first;
+    uint32_t n_fix = 0, n_asm = 0;
+    std::vector<uint32_t> ftile_first, asm_first;  // asm_first: empty when every record has max_asm + 1 items
     size_t o_res = 0, o_err = 0, o_outs = 0, o_items = 0, o_ftfirst = 0, o_ftitem = 0;
+    size_t o_fctl = 0, o_fdep = 0, o_fstat = 0, o_ffix = 0, o_fout = 0, o_fasm = 0;
     size_t up_end = 0, total = 0;
     std::vector<size_t> o_vw, o_blk, o_slots, o_frame, o_segs;
     size_t up_bytes() const { return up_end - o_err; }
@@ -212,6 +215,20 @@ EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpe
         Lo.ftpi = div_up(specs[0].H * specs[0].W, kFTile);
     }
     const uint32_t n_maps = Lo.ftpi ? 0u : n, n_ftmap = Lo.ftpi ? 0u : Lo.n_ftiles;
+    // the fused launch's work items: assembly parts per record, tile-crossing frame groups
+    Lo.n_fix = div_up(Lo.n_ftiles, kFixGroup);
+    if (Lo.ftpi) {
+        Lo.n_asm = n * (Lo.max_asm + 1);
+    } else {
+        Lo.asm_first.resize(n + 1);
+        uint32_t a = 0;
+        for (uint32_t r = 0; r < n; ++r) {
+            Lo.asm_first[r] = a;
+            a += 1 + div_up(div_up(specs[r].H * specs[r].W, kFrame), kAsmFrames);
+        }
+        Lo.asm_first[n] = a;
+        Lo.n_asm = a;
+    }
     size_t off = 0;
     Lo.o_res = off; off = al(off + sizeof(EncRes) * n);
     Lo.o_err = off; off = al(off + sizeof(uint32_t));
@@ -219,6 +236,12 @@ EncLayout enc_layout(const std::vector<EncSpec>& specs, const std::vector<OutSpe
     Lo.o_items = off; off = al(off + sizeof(EncItem) * n);
     Lo.o_ftfirst = off; off = al(off + sizeof(uint32_t) * n_maps);
     Lo.o_ftitem = off; off = al(off + sizeof(uint32_t) * n_ftmap);
+    Lo.o_fctl = off; off = al(off + 4 * sizeof(uint32_t));
+    Lo.o_fdep = off; off = al(off + 4 * sizeof(uint32_t) * n);
+    Lo.o_fstat = off; off = al(off + sizeof(uint64_t) * n);
+    Lo.o_ffix = off; off = al(off + sizeof(uint32_t) * Lo.n_fix);
+    Lo.o_fout = off; off = al(off + sizeof(uint32_t) * no);
+    Lo.o_fasm = off; off = al(off + sizeof(uint32_t) * Lo.asm_first.size());
     Lo.up_end = off;
     Lo.o_vw.resize(n); Lo.o_blk.resize(n); Lo.o_slots.resize(n); Lo.o_frame.resize(n); Lo.o_segs.resize(n);
     for (uint32_t r = 0; r < n; ++r) {
@@ -304,7 +327,10 @@ void enc_fill(const EncLayout& Lo, const std::vector<EncSpec>& specs, const std:
         bool al16 = ((uintptr_t)s.x % 16 == 0) && (!s.xprev || (uintptr_t)s.xprev % 16 == 0) &&
                     (!s.qout || (uintptr_t)s.qout % 16 == 0);
         it.aligned16 = al16 ? 1u : 0u;
+        it.prev_item = (!s.vwprev_fixed && s.prev_item >= 0) ? (uint32_t)s.prev_item : kNoFix;
     }
+    if (!Lo.asm_first.empty())
+        memcpy(U(Lo.o_fasm), Lo.asm_first.data(), sizeof(uint32_t) * Lo.asm_first.size());
     if (Lo.ftpi) return;  // tiles are found by division
     uint32_t* hftf = (uint32_t*)U(Lo.o_ftfirst);
     uint32_t* hfti = (uint32_t*)U(Lo.o_ftitem);
@@ -329,6 +355,14 @@ EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev, uint8_t* host_res) {
     plan.n_items = Lo.n;
     plan.n_outs = Lo.no;
     plan.max_asm = Lo.max_asm;
+    plan.fctl = (uint32_t*)(dev + Lo.o_fctl);
+    plan.fdep = (uint32_t*)(dev + Lo.o_fdep);
+    plan.fstat = (uint64_t*)(dev + Lo.o_fstat);
+    plan.ffix = (uint32_t*)(dev + Lo.o_ffix);
+    plan.fout = (uint32_t*)(dev + Lo.o_fout);
+    plan.fasm = Lo.asm_first.empty() ? nullptr : (const uint32_t*)(dev + Lo.o_fasm);
+    plan.n_fix = Lo.n_fix;
+    plan.n_asm = Lo.n_asm;
     return plan;
 }
 
@@ -336,13 +370,47 @@ EncPlan enc_plan(const EncLayout& Lo, uint8_t* dev, uint8_t* host_res) {
 // the upload of the plan image by a kernel reading `up_dev` (the device
 // address of the host image), then the kernels; k_enc_offsets writes the
 // lengths and modes to the host results.
+// The encode's launch configuration (the autotuner's knobs; jiffy_set_tuning):
+// the kernel chain, or one fused persistent launch of wgs_per_cu workgroups
+// per compute unit (0: as many as one holds).
+jiffy_tuning g_tuning = {0u, 0u};
+std::mutex g_tune_mu;
+struct FusedShape {
+    int cus = 0, per_cu = 0;  // looked up once per device
+};
+FusedShape g_fshape[64];
+
+// Workgroups of a fused launch on the current device under tuning t, or 0
+// for the kernel chain (also when the device cannot be queried).
+uint32_t fused_grid(const jiffy_tuning& t) {
+    if (!t.fused) return 0;
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    FusedShape& f = g_fshape[dev];
+    if (!f.cus) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            fused_occupancy(&per) != hipSuccess || cus <= 0 || per <= 0)
+            return 0;
+        f.per_cu = per;
+        f.cus = cus;
+    }
+    const uint32_t per = t.wgs_per_cu ? std::min<uint32_t>(t.wgs_per_cu, (uint32_t)f.per_cu) : (uint32_t)f.per_cu;
+    return per * (uint32_t)f.cus;
+}
+
+jiffy_tuning current_tuning() {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    return g_tuning;
+}
+
 hipError_t enc_enqueue(const EncLayout& Lo, const EncPlan& plan, uint8_t* dev, const void* up_dev, hipStream_t stream,
-                       bool upload = true) {
+                       bool upload = true, uint32_t fgrid = 0) {
     if (upload) {
         hipError_t e = launch_copy_in(up_dev, dev + Lo.o_err, Lo.up_bytes(), stream);
         if (e != hipSuccess) return e;
     }
-    return launch_encode(plan, stream);
+    return fgrid ? launch_encode_fused(plan, fgrid, stream) : launch_encode(plan, stream);
 }
 
 // Results k_enc_offsets wrote to host memory.
@@ -397,7 +465,13 @@ int enc_execute(DevCtx& ctx, const HostBuf& up, const EncPrepared& P, hipStream_
     uint8_t* dev = (uint8_t*)ctx.ws.p;
     const EncPlan plan = enc_plan(P.Lo, dev, (uint8_t*)ctx.res.d);
     if (upload) ++ctx.enc_gen;
-    if (enc_enqueue(P.Lo, plan, dev, up.d, stream, upload) != hipSuccess) return JIFFY_E_DEVICE;
+    // the fused launch needs its control words zeroed by the upload of the plan image
+    const uint32_t fgrid = fused_grid(current_tuning());
+    if (fgrid) {
+        if (!upload) ++ctx.enc_gen;
+        upload = true;
+    }
+    if (enc_enqueue(P.Lo, plan, dev, up.d, stream, upload, fgrid) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
     prof_collect();
     enc_results(P.Lo, (const uint8_t*)ctx.res.p, result);
@@ -593,6 +667,26 @@ int jiffy_profile_read(uint32_t max_kernels, char* names, double* total_ms, uint
         if (launches) launches[k] = g_prof_totals[k].launches;
     }
     return (int)n;
+}
+
+int jiffy_set_tuning(const jiffy_tuning* t) {
+    if (!t || t->fused > 1 || t->wgs_per_cu > 64) return JIFFY_E_INVALID;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuning = *t;
+    return JIFFY_OK;
+}
+
+int jiffy_get_tuning(jiffy_tuning* t, uint32_t* max_wgs_per_cu) {
+    if (t) *t = current_tuning();
+    if (max_wgs_per_cu) {
+        *max_wgs_per_cu = 0;
+        int dev;
+        if (current_device(&dev)) return JIFFY_E_DEVICE;
+        const jiffy_tuning probe = {1u, 0u};
+        if (!fused_grid(probe)) return JIFFY_E_DEVICE;
+        *max_wgs_per_cu = (uint32_t)g_fshape[dev].per_cu;
+    }
+    return JIFFY_OK;
 }
 
 const char* jiffy_status_string(int s) {
@@ -1256,6 +1350,7 @@ struct jiffy_batch {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint32_t fgrid = 0;  // the fused launch's workgroups (the tuning at creation), or 0: the kernel chain
 };
 
 int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* const* const* d_planes,
@@ -1275,6 +1370,7 @@ int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* con
     for (uint32_t i = 0; i < n; ++i) b->plane_ptrs.push_back(b->planes[i].data());
     b->outs.assign(d_out, d_out + n);
     b->caps.assign(caps, caps + n);
+    b->fgrid = fused_grid(current_tuning());
     std::vector<EncSpec> specs;
     std::vector<OutSpec> outs;
     stream_specs(b->streams.data(), n, b->plane_ptrs.data(), b->outs.data(), b->caps.data(), specs, outs);
@@ -1288,7 +1384,7 @@ int jiffy_batch_create(jiffy_stream* const* streams, uint32_t n, const void* con
         const EncPlan plan = enc_plan(b->Lo, b->dev, (uint8_t*)b->res_d);
         if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             t_no_events = true;
-            const hipError_t e = enc_enqueue(b->Lo, plan, b->dev, b->up_d, b->cap_stream);
+            const hipError_t e = enc_enqueue(b->Lo, plan, b->dev, b->up_d, b->cap_stream, true, b->fgrid);
             t_no_events = false;
             const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &b->graph);
             if (e == hipSuccess && e2 == hipSuccess &&
@@ -1440,7 +1536,7 @@ int jiffy_step_submit(jiffy_step* st, jiffy_stream* const* streams, uint32_t n, 
     enc_fill(Lo, specs, outs, (uint8_t*)st->ws.p, (uint8_t*)st->up.p);
     const EncPlan plan = enc_plan(Lo, (uint8_t*)st->ws.p, (uint8_t*)st->res.d);
     t_no_events = true;  // the step completes after this call returns: no timing events
-    const hipError_t e = enc_enqueue(Lo, plan, (uint8_t*)st->ws.p, st->up.d, stream);
+    const hipError_t e = enc_enqueue(Lo, plan, (uint8_t*)st->ws.p, st->up.d, stream, true, fused_grid(current_tuning()));
     t_no_events = false;
     if (e != hipSuccess) return JIFFY_E_DEVICE;
     st->streams.assign(streams, streams + n);

@@ -282,6 +282,128 @@ struct TrialLds {
     unsigned long long cost[2];
 };
 
+// Half h (16 pixels) of a thread's 32 trial pixels from trial pixel tp0 on:
+// v gets the I residuals (the quantized samples) or, with pkind, the P
+// residuals (differences to the previous scan); returns their keep bits.
+// Holding one kind of 16 values at a time keeps the registers low (each
+// kind re-reads the few trial rows, which the cache still holds).
+template <int WB>
+__device__ __forceinline__ uint32_t trial_half(const EncItem& it, uint32_t tp0, uint32_t NT, bool whole, uint32_t h,
+                                               bool pkind, uint32_t v[16]) {
+    const uint32_t H = it.height, W = it.width, K = it.trial_rows, m = low_mask32(it.bits);
+    const uint32_t t0 = tp0 + 16 * h;
+    uint32_t keep = 0;
+    if (whole) {  // the thread's pixels lie in one row, 16-sample aligned: vector loads
+        uint32_t xs[16], xp[16];
+        if (t0 < NT) {
+            const uint32_t ri = t0 / W, c = t0 - ri * W;
+            const uint32_t row = K >= H ? ri : (uint32_t)(((uint64_t)(2 * ri + 1) * H) / (2ull * K));
+            const uint32_t p = row * W + c;
+            load16<WB>(it.x, p, it.npx, true, xs);
+            if (pkind) load16<WB>(it.xprev, p, it.npx, true, xp);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) xs[i] = xp[i] = 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t qv = quantize(xs[i], it.div);
+            keep |= (qv != 0 ? 1u : 0u) << i;
+            if (pkind) {
+                const uint32_t qp = it.prev_quantized ? xp[i] : quantize(xp[i], it.div);
+                v[i] = (qv - qp) & m;
+            } else {
+                v[i] = qv;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t tp = t0 + i;
+            uint32_t u = 0;
+            if (tp < NT) {
+                const uint32_t ri = tp / W, c = tp - ri * W;
+                const uint32_t row = K >= H ? ri : (uint32_t)(((uint64_t)(2 * ri + 1) * H) / (2ull * K));
+                const uint32_t p = row * W + c;
+                const uint32_t qv = quantize(load1<WB>(it.x, p), it.div);
+                keep |= (qv != 0 ? 1u : 0u) << i;
+                u = qv;
+                if (pkind) {
+                    uint32_t qp = load1<WB>(it.xprev, p);
+                    if (!it.prev_quantized) qp = quantize(qp, it.div);
+                    u = (qv - qp) & m;
+                }
+            }
+            v[i] = u;
+        }
+    }
+    return keep;
+}
+
+// The same decision with one residual kind of 16 values in registers at a
+// time (each kind re-reads the trial rows): far fewer registers, for the
+// fused launch, whose register count is that of its largest phase.
+template <int WB>
+__device__ __forceinline__ void enc_trial_body_lowreg(const EncItem& it, TrialLds& L, JG EncRes* res) {
+    const uint32_t tid = threadIdx.x, g = tid >> 2, q = tid & 3u;
+    const uint32_t H = it.height, W = it.width, K = it.trial_rows;
+    const uint32_t nr = K >= H ? H : K;  // distinct trial rows
+    const uint32_t NT = nr * W;          // trial pixels
+    if (tid < 2) L.cost[tid] = 0;
+    // rows of a multiple of 32 samples: a thread's 32 trial pixels lie in one row
+    const bool whole = it.aligned16 && W % 32 == 0;
+    uint32_t carry = 0, pred[2] = {0u, 0u};  // values in the incomplete frame; value before it
+    for (uint32_t cs = 0; cs < NT; cs += kFTile) {
+        const uint32_t tp0 = cs + tid * 32;
+        uint32_t v[16];
+        const uint32_t keep = trial_half<WB>(it, tp0, NT, whole, 0, false, v) |
+                              (trial_half<WB>(it, tp0, NT, whole, 1, false, v) << 16);
+        uint32_t nv;
+        const uint32_t off = block_excl_scan<256>(__popc(keep), L.scratch, &nv);
+        const uint32_t total = carry + nv, nfull = total >> 7, rem = total & 127u;
+        const bool last = cs + kFTile >= NT;
+        const uint32_t ncost = nfull + (last && rem ? 1u : 0u);  // frames costed now
+        for (int kind = 0; kind < 2; ++kind) {
+            // the carried frame start, then this chunk's kept values
+            if (tid < carry) L.rows[row_off(tid)] = L.carry[kind][tid];
+            uint32_t k = carry + off;
+            for (uint32_t h = 0; h < 2; ++h) {
+                trial_half<WB>(it, tp0, NT, whole, h, kind == 1, v);
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (keep & (1u << (16 * h + i))) {
+                        L.rows[tile_word(k, 0)] = v[i];
+                        ++k;
+                    }
+            }
+            __syncthreads();
+            // predecessors, and the new incomplete frame, before any row turns into a histogram
+            // (quad g costs frames g and g + 64: a chunk can hold 65)
+            uint32_t pv[2];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const uint32_t f = g + 64 * hh;
+                pv[hh] = (f < ncost && f > 0) ? L.rows[tile_word(128 * f - 1, 0)] : pred[kind];
+            }
+            const uint32_t npred = nfull ? L.rows[tile_word(128 * nfull - 1, 0)] : pred[kind];
+            if (!last && tid < rem) L.carry[kind][tid] = L.rows[tile_word(128 * nfull + tid, 0)];
+            __syncthreads();
+            for (int hh = 0; hh < 2; ++hh) {  // one frame's 32 values per lane in registers at a time
+                const uint32_t f = g + 64 * hh;
+                if (f < ncost) {
+                    const uint32_t real = f < nfull ? kFrame : rem;
+                    const uint32_t c = frame_cost_quad(L.rows + f * kRow, real, hh ? pv[1] : pv[0], it.bits, q);
+                    if (q == 0) atomicAdd(&L.cost[kind], (unsigned long long)c);
+                }
+            }
+            pred[kind] = npred;
+            __syncthreads();
+        }
+        carry = rem;
+    }
+    if (tid == 0) res->mode = L.cost[1] < L.cost[0] ? 1u : 0u;
+}
+
 template <int WB>
 __device__ __forceinline__ void enc_trial_body(const EncItem& it, TrialLds& L, JG EncRes* res) {
     const uint32_t tid = threadIdx.x, g = tid >> 2, q = tid & 3u;
@@ -385,25 +507,37 @@ __device__ __forceinline__ void enc_trial_body(const EncItem& it, TrialLds& L, J
     if (tid == 0) res->mode = L.cost[1] < L.cost[0] ? 1u : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
-    const uint32_t r = blockIdx.x;
-    // the call's error word starts at zero (a plan reused without an upload
-    // keeps the previous call's); no kernel before k_enc_tiles touches it
-    if (r == 0 && threadIdx.x == 0) *plan.err = 0u;
+// Record r's I/P decision; also clears its tile tickets and look-back states.
+template <bool kLowReg = false>
+__device__ __forceinline__ void enc_trial_item(const EncPlan& plan, uint32_t r, TrialLds& lds) {
     const EncItem it = plan.items[r];
-    // the record's k_enc_tiles tickets and look-back states start at zero
     for (uint32_t i = threadIdx.x; i < it.ntiles; i += 256) it.tstat[i] = 0;
     if (threadIdx.x == 0) *it.tctr = 0u;
     if (!it.has_prev || it.mode_req != 0) {
         if (threadIdx.x == 0) plan.res[r].mode = (it.has_prev && it.mode_req == 2) ? 1u : 0u;
         return;
     }
-    __shared__ TrialLds lds;
+    if (kLowReg) {
+        switch (it.wb) {
+            case 4: enc_trial_body_lowreg<4>(it, lds, plan.res + r); break;
+            case 2: enc_trial_body_lowreg<2>(it, lds, plan.res + r); break;
+            default: enc_trial_body_lowreg<1>(it, lds, plan.res + r); break;
+        }
+        return;
+    }
     switch (it.wb) {
         case 4: enc_trial_body<4>(it, lds, plan.res + r); break;
         case 2: enc_trial_body<2>(it, lds, plan.res + r); break;
         default: enc_trial_body<1>(it, lds, plan.res + r); break;
     }
+}
+
+__global__ __launch_bounds__(256) void k_enc_trial(EncPlan plan) {
+    // the call's error word starts at zero (a plan reused without an upload
+    // keeps the previous call's); no kernel before k_enc_tiles touches it
+    if (blockIdx.x == 0 && threadIdx.x == 0) *plan.err = 0u;
+    __shared__ TrialLds lds;
+    enc_trial_item(plan, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -598,6 +732,15 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
                     it.slots + (size_t)j * kSlotBytes, it.blkinfo + j);
 }
 
+__device__ __forceinline__ void enc_tile_item(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
+                                              TileLds& lds) {
+    switch (it.wb) {
+        case 4: enc_tile_body<4>(plan, it, r, lt, lds); break;
+        case 2: enc_tile_body<2>(plan, it, r, lt, lds); break;
+        default: enc_tile_body<1>(plan, it, r, lt, lds); break;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
     // the record is fixed by the workgroup index; the tile within it is taken
     // in arrival order, so every tile a workgroup waits for has started
@@ -612,18 +755,14 @@ __global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
         if (threadIdx.x == 0) atomicOr(plan.err, kErrStall);
         return;
     }
-    switch (it.wb) {
-        case 4: enc_tile_body<4>(plan, it, r, lt, lds); break;
-        case 2: enc_tile_body<2>(plan, it, r, lt, lds); break;
-        default: enc_tile_body<1>(plan, it, r, lt, lds); break;
-    }
+    enc_tile_item(plan, it, r, lt, lds);
 }
 
 // The frames that cross tile boundaries: one quad per tile entry, the tile
 // entries [t0, t0 + kFixQuads) per workgroup; the staged values go to the
 // quad's LDS row first.  Runs in workgroups of k_enc_mframe (see there).
-constexpr uint32_t kFixQuads = 64;
-__device__ void enc_fixup_quads(const EncPlan& plan, uint32_t t0, uint32_t* rows) {
+constexpr uint32_t kFixQuads = kFixGroup;
+__device__ __forceinline__ void enc_fixup_quads(const EncPlan& plan, uint32_t t0, uint32_t* rows) {
     const uint32_t g = threadIdx.x >> 2, q = threadIdx.x & 3u;
     const uint32_t t = t0 + g;
     if (g >= kFixQuads || t >= plan.n_ftiles) return;  // no barrier follows
@@ -631,7 +770,7 @@ __device__ void enc_fixup_quads(const EncPlan& plan, uint32_t t0, uint32_t* rows
     const uint32_t r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, t, lt);
     const EncItem& it = plan.items[r];
     const uint32_t j = it.tfix[lt];
-    if (j == kNoFix) return;
+    if (j == kNoFix || j >= it.maxnb) return;
     const uint32_t N = plan.res[r].N;
     const uint32_t real = min(kFrame, N - j * kFrame);
     JG uint8_t* slot = it.slots + (size_t)j * kSlotBytes;
@@ -721,30 +860,30 @@ __device__ __forceinline__ uint32_t win_byte(const RunBits& R, uint32_t k) {
     return (uint32_t)(w >> (8 * (k & 7))) & 0xFFu;
 }
 
-constexpr uint32_t kMfThreads = 512;  // one workgroup per record covers 16 KiB of mask content per round
-constexpr uint32_t kMfStep = kMfThreads * 32;
+constexpr uint32_t kMfThreads = 512;   // the mask-frame kernel: one workgroup per record covers 16 KiB per round
 constexpr uint32_t kMfKeep = 2;        // rounds whose classification stays in registers between passes
-constexpr uint32_t kMfSegLds = 6144;   // segments the LDS table holds (more: the workspace table)
+constexpr uint32_t kMfSegLds = 6144;   // segments its LDS table holds (more: the workspace table)
 
+template <int NT, int SEGS>
 struct alignas(16) MfLds {
-    uint32_t segs[kMfSegLds];    // segment start | RLE << 31 (also the fixup quads' frame rows)
-    uint32_t segoff[kMfSegLds];  // its offset in the frame
-    uint8_t segb[kMfSegLds];     // an RLE segment's byte
-    uint32_t scratch[kMfThreads / 64 + 1];
+    uint32_t segs[SEGS];    // segment start | RLE << 31
+    uint32_t segoff[SEGS];  // its offset in the frame
+    uint8_t segb[SEGS];     // an RLE segment's byte
+    uint32_t scratch[NT / 64 + 1];
 };
-static_assert(sizeof(MfLds) >= kFixQuads * kRow * 4, "the fixup quads' frame rows fit in the mask-frame LDS");
 
 // Pass 1 of one round: the round's segment starts, numbered from nseg, go
 // to the LDS table (those that fit) or to the workspace table.
-__device__ __forceinline__ void mframe_starts(const EncItem& it, const RunBits& R, uint32_t b0, bool to_ws, MfLds& M,
-                                              uint32_t& nseg) {
+template <int NT, int SEGS>
+__device__ __forceinline__ void mframe_starts(const EncItem& it, const RunBits& R, uint32_t b0, bool to_ws,
+                                              MfLds<NT, SEGS>& M, uint32_t& nseg) {
     uint32_t total;
-    uint32_t sid = block_excl_scan<kMfThreads>(__popc(R.start), M.scratch, &total) + nseg;
+    uint32_t sid = block_excl_scan<NT>(__popc(R.start), M.scratch, &total) + nseg;
     for (uint32_t m = R.start; m; m &= m - 1) {
         const uint32_t k = __ffs(m) - 1;
         const uint32_t e = (b0 + k) | (((R.lng >> k) & 1u) << 31);
         if (to_ws) it.segs[sid] = e;
-        else if (sid < kMfSegLds) {
+        else if (sid < (uint32_t)SEGS) {
             M.segs[sid] = e;
             M.segb[sid] = (uint8_t)win_byte(R, k);
         }
@@ -754,16 +893,17 @@ __device__ __forceinline__ void mframe_starts(const EncItem& it, const RunBits& 
 }
 
 // Passes 2 and 3 over the segment table (in LDS, or in the workspace).
-template <bool kLds>
+template <bool kLds, int NT, int SEGS>
 __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, const EncItem& it, uint32_t mode,
-                                             uint32_t nm, uint32_t nseg, uint32_t hdr, MfLds& M,
+                                             uint32_t nm, uint32_t nseg, uint32_t hdr, MfLds<NT, SEGS>& M,
                                              RunBits (&Rk)[kMfKeep]) {
+    constexpr uint32_t kStep = NT * 32;
     const uint32_t tid = threadIdx.x;
     auto seg = [&](uint32_t i) -> uint32_t { return kLds ? M.segs[i] : it.segs[i]; };
     auto segoff = [&](uint32_t i) -> uint32_t { return kLds ? M.segoff[i] : it.segoff[i]; };
     // pass 2: encoded sizes and offsets of the segments
     uint32_t off_carry = hdr;
-    for (uint32_t s0 = 0; s0 < nseg; s0 += kMfThreads) {
+    for (uint32_t s0 = 0; s0 < nseg; s0 += NT) {
         const uint32_t sg = s0 + tid;
         uint32_t size = 0;
         if (sg < nseg) {
@@ -775,7 +915,7 @@ __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, co
             size = (a >> 31) ? 4u * nblk : 3u * nblk + len;
         }
         uint32_t total;
-        const uint32_t off = block_excl_scan<kMfThreads>(size, M.scratch, &total) + off_carry;
+        const uint32_t off = block_excl_scan<NT>(size, M.scratch, &total) + off_carry;
         if (sg < nseg) {
             if (kLds) M.segoff[sg] = off;
             else it.segoff[sg] = off;
@@ -794,7 +934,7 @@ __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, co
         plan.res[r].nseg = nseg;
     }
     // block headers (and the byte of each RLE block)
-    for (uint32_t sg = tid; sg < nseg; sg += kMfThreads) {
+    for (uint32_t sg = tid; sg < nseg; sg += NT) {
         const uint32_t a = seg(sg);
         const uint32_t start = a & 0x7FFFFFFFu;
         const uint32_t end = (sg + 1 < nseg) ? (seg(sg + 1) & 0x7FFFFFFFu) : nm;
@@ -820,7 +960,7 @@ __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, co
     uint32_t seg_carry = 0;
     auto raw_round = [&](const RunBits& R, uint32_t b0) {
         uint32_t total;
-        uint32_t sid = block_excl_scan<kMfThreads>(__popc(R.start), M.scratch, &total) + seg_carry;
+        uint32_t sid = block_excl_scan<NT>(__popc(R.start), M.scratch, &total) + seg_carry;
         const uint32_t nvalid = nm > b0 ? min(32u, nm - b0) : 0u;
         uint32_t sg = sid ? sid - 1 : 0, sstart = 0, soff = 0;
         if (sid) { sstart = seg(sg) & 0x7FFFFFFFu; soff = segoff(sg); }
@@ -839,25 +979,21 @@ __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, co
     };
 #pragma unroll
     for (uint32_t c = 0; c < kMfKeep; ++c)
-        if (c * kMfStep < nm) raw_round(Rk[c], c * kMfStep + 32 * tid);
-    for (uint32_t c0 = kMfKeep * kMfStep; c0 < nm; c0 += kMfStep) {
+        if (c * kStep < nm) raw_round(Rk[c], c * kStep + 32 * tid);
+    for (uint32_t c0 = kMfKeep * kStep; c0 < nm; c0 += kStep) {
         RunBits R;
         classify32(it, mode, nm, c0 + 32 * tid, R);
         raw_round(R, c0 + 32 * tid);
     }
 }
 
-// One workgroup per record (the workgroups after them code the tile-crossing
-// frames, enc_fixup_quads).  Pass 1 finds the segment starts (the first
-// kMfKeep rounds' classification is kept in registers for the raw bytes);
-// the segment table lives in LDS when it fits, else in the workspace.
-__global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
-    __shared__ MfLds M;
-    if (blockIdx.x >= plan.n_items) {  // the tile-crossing frames: independent of the masks, same launch
-        enc_fixup_quads(plan, (blockIdx.x - plan.n_items) * kFixQuads, (uint32_t*)&M);
-        return;
-    }
-    const uint32_t r = blockIdx.x;
+// The mask frame of record r, by a workgroup of NT threads.  Pass 1 finds
+// the segment starts (the first kMfKeep rounds' classification is kept in
+// registers for the raw bytes); the segment table lives in LDS when it
+// fits, else in the workspace.
+template <int NT, int SEGS>
+__device__ __forceinline__ void enc_mframe_item(const EncPlan& plan, uint32_t r, MfLds<NT, SEGS>& M) {
+    constexpr uint32_t kStep = NT * 32;
     const EncItem it = plan.items[r];
     const uint32_t mode = plan.res[r].mode;
     const uint32_t nm = div_up(it.npx, 8);
@@ -867,17 +1003,17 @@ __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
     uint32_t nseg = 0;
 #pragma unroll
     for (uint32_t c = 0; c < kMfKeep; ++c)
-        if (c * kMfStep < nm) {
-            classify32(it, mode, nm, c * kMfStep + 32 * tid, Rk[c]);
-            mframe_starts(it, Rk[c], c * kMfStep + 32 * tid, false, M, nseg);
+        if (c * kStep < nm) {
+            classify32(it, mode, nm, c * kStep + 32 * tid, Rk[c]);
+            mframe_starts(it, Rk[c], c * kStep + 32 * tid, false, M, nseg);
         }
-    for (uint32_t c0 = kMfKeep * kMfStep; c0 < nm; c0 += kMfStep) {
+    for (uint32_t c0 = kMfKeep * kStep; c0 < nm; c0 += kStep) {
         RunBits R;
         classify32(it, mode, nm, c0 + 32 * tid, R);
         mframe_starts(it, R, c0 + 32 * tid, false, M, nseg);
     }
     __syncthreads();
-    if (nseg <= kMfSegLds) {
+    if (nseg <= (uint32_t)SEGS) {
         mframe_write<true>(plan, r, it, mode, nm, nseg, hdr, M, Rk);
         return;
     }
@@ -885,14 +1021,29 @@ __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
     nseg = 0;
 #pragma unroll
     for (uint32_t c = 0; c < kMfKeep; ++c)
-        if (c * kMfStep < nm) mframe_starts(it, Rk[c], c * kMfStep + 32 * tid, true, M, nseg);
-    for (uint32_t c0 = kMfKeep * kMfStep; c0 < nm; c0 += kMfStep) {
+        if (c * kStep < nm) mframe_starts(it, Rk[c], c * kStep + 32 * tid, true, M, nseg);
+    for (uint32_t c0 = kMfKeep * kStep; c0 < nm; c0 += kStep) {
         RunBits R;
         classify32(it, mode, nm, c0 + 32 * tid, R);
         mframe_starts(it, R, c0 + 32 * tid, true, M, nseg);
     }
     __syncthreads();
     mframe_write<false>(plan, r, it, mode, nm, nseg, hdr, M, Rk);
+}
+
+// One workgroup per record (the workgroups after them code the tile-crossing
+// frames, enc_fixup_quads, in the same LDS).
+union MfKernelLds {
+    MfLds<kMfThreads, kMfSegLds> mf;
+    uint32_t fix[kFixQuads * kRow];
+};
+__global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
+    __shared__ MfKernelLds M;
+    if (blockIdx.x >= plan.n_items) {  // the tile-crossing frames: independent of the masks, same launch
+        enc_fixup_quads(plan, (blockIdx.x - plan.n_items) * kFixQuads, M.fix);
+        return;
+    }
+    enc_mframe_item(plan, blockIdx.x, M.mf);
 }
 
 // ---------------------------------------------------------------------------
@@ -902,13 +1053,12 @@ __global__ __launch_bounds__(kMfThreads) void k_enc_mframe(EncPlan plan) {
 // ---------------------------------------------------------------------------
 constexpr int kSizeThreads = 1024;
 
-__global__ __launch_bounds__(kSizeThreads) void k_enc_sizes(EncPlan plan) {
-    const uint32_t r = blockIdx.x;
-    const EncItem it = plan.items[r];
-    const uint32_t nb = plan.res[r].nb;
-    __shared__ uint32_t scratch[3 * (kSizeThreads / kWave + 1)];
+template <int NT>
+__device__ __forceinline__ void enc_sizes_item(const EncPlan& plan, uint32_t r, uint32_t* scratch /* 3 * (NT/64 + 1) */) {
+    const EncItem& it = plan.items[r];
+    const uint32_t nb = min(plan.res[r].nb, it.maxnb);  // (never more; kept in bounds whatever a stall left)
     uint32_t cp = 0, cn = 0, ch = 0;
-    for (uint32_t j0 = 0; j0 < nb; j0 += kSizeThreads) {
+    for (uint32_t j0 = 0; j0 < nb; j0 += NT) {
         const uint32_t j = j0 + threadIdx.x;
         uint32_t v[3] = {0u, 0u, 0u};  // payload, position and high part bytes of frame j
         if (j < nb) {
@@ -919,7 +1069,7 @@ __global__ __launch_bounds__(kSizeThreads) void k_enc_sizes(EncPlan plan) {
             v[2] = (n * (B - b) + 7) / 8;
         }
         uint32_t tot[3];
-        block_excl_scan3<kSizeThreads>(v, scratch, tot);
+        block_excl_scan3<NT>(v, scratch, tot);
         if (j < nb) {
             it.blkoffs[3 * j] = cp + v[0];
             it.blkoffs[3 * j + 1] = cn + v[1];
@@ -934,6 +1084,11 @@ __global__ __launch_bounds__(kSizeThreads) void k_enc_sizes(EncPlan plan) {
         rs.high = ch;
         rs.rec_len = align4(12 + rs.flen) + align4(4 + 3 * nb) + align4(cp + cn + ch);
     }
+}
+
+__global__ __launch_bounds__(kSizeThreads) void k_enc_sizes(EncPlan plan) {
+    __shared__ uint32_t scratch[3 * (kSizeThreads / kWave + 1)];
+    enc_sizes_item<kSizeThreads>(plan, blockIdx.x, scratch);
 }
 
 // ---------------------------------------------------------------------------
@@ -985,22 +1140,24 @@ __global__ __launch_bounds__(1024) void k_enc_offsets(EncPlan plan) {
 }
 
 // ---------------------------------------------------------------------------
-// Assembly.  blockIdx.x == 0: record header, mask frame, section header and
-// padding (and the stream header for an output's first record);
-// blockIdx.x >= 1: the packed frames of one group.
+// Assembly.  Part 0 of record r: its header, mask frame, section header and
+// padding (and the stream header and table for an output's first record);
+// part p >= 1: the packed frames of group p - 1.  The kernel runs one
+// workgroup per (part, record).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
-    const uint32_t r = blockIdx.y;
+__device__ __forceinline__ void enc_assemble_item(const EncPlan& plan, uint32_t r, uint32_t part) {
     const EncItem it = plan.items[r];
     const EncOut& o = plan.outs[it.out_id];
     if (!o.ok) return;
-    const EncRes rs = plan.res[r];
+    EncRes rs = plan.res[r];
+    // the record lies inside the output and has at most maxnb frames (always, unless a bounded wait ran out)
+    if (rs.rec_off + rs.rec_len > o.cap || rs.nb > it.maxnb) return;
     uint8_t* rec = o.base + rs.rec_off;
     const uint32_t sec = align4(12 + rs.flen);
     const uint32_t hdr4 = align4(4 + 3 * rs.nb);
     const uint32_t pay0 = sec + hdr4, pos0 = pay0 + rs.pay, high0 = pos0 + rs.pos, end = high0 + rs.high;
     const uint32_t tid = threadIdx.x;
-    if (blockIdx.x == 0) {
+    if (part == 0) {
         if (tid == 0) {
             uint32_t* h = (uint32_t*)rec;
             h[0] = rs.rec_len;
@@ -1078,7 +1235,7 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
     constexpr int kPer = kAsmFrames / 16;
     constexpr int kSlotRounds = kSlotBytes / 4 / 16;
     static_assert(kSlotBytes % 64 == 0, "a slot is a whole number of 16-word rounds");
-    const uint32_t jg = (blockIdx.x - 1) * kAsmFrames + (tid >> 4) * kPer;
+    const uint32_t jg = (part - 1) * kAsmFrames + (tid >> 4) * kPer;
     if (jg >= rs.nb) return;
     const uint32_t l = tid & 15u;
     uint32_t info[kPer], op[kPer], on[kPer], oh[kPer];
@@ -1129,6 +1286,8 @@ __global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) { enc_assemble_item(plan, blockIdx.y, blockIdx.x); }
+
 // ---------------------------------------------------------------------------
 // Plan upload: 16 bytes per thread from host-mapped memory.
 // ---------------------------------------------------------------------------
@@ -1145,6 +1304,246 @@ hipError_t launch_copy_in(const void* host, void* dev, size_t bytes, hipStream_t
     JIFFY_LAUNCH("k_copy_in", k_copy_in, dim3(div_up(n16, 256)), dim3(256), stream, (const uint4*)host, (uint4*)dev,
                  n16);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused persistent encoder: every phase of an encode in one launch.  A grid
+// of workgroups (at most what the device holds at once) takes work items
+// from one queue in order:
+//   trial(r) | tile(t) | mask frame(r) | fixup group(g) | sizes(r) | assembly(r, part)
+// An item waits (bounded polls, then agent-scope acquire) only for items
+// earlier in the queue, each of which a running workgroup has taken, so
+// the lowest unfinished item can always proceed: phases of different
+// records overlap and no grid-wide barrier is needed.  Completion is
+// published with an agent-scope release before the counter update.
+// The record offsets are a decoupled look-back over the sizes items.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFusedThreads = 256;
+constexpr uint32_t kFusedSegs = 4096;               // mask-frame segments kept in LDS
+constexpr uint32_t kFusedSpinMax = 1u << 22;        // polls of a dependency before giving up
+
+union FusedLds {
+    TrialLds trial;
+    TileLds tile;
+    MfLds<kFusedThreads, kFusedSegs> mf;
+    uint32_t fix[kFixQuads * kRow];
+    uint32_t sizes[3 * (kFusedThreads / kWave + 1)];
+};
+// The fused kernel's LDS, at file scope for its phase functions (only
+// k_enc_fused reaches them).
+__shared__ FusedLds fused_lds;
+
+__device__ __forceinline__ void fused_trial(const EncPlan& plan, uint32_t r) {
+    enc_trial_item<true>(plan, r, fused_lds.trial);
+}
+__device__ __forceinline__ void fused_tile(const EncPlan& plan, uint32_t r, uint32_t lt) {
+    const EncItem it = plan.items[r];
+    enc_tile_item(plan, it, r, lt, fused_lds.tile);
+}
+__device__ __forceinline__ void fused_mframe(const EncPlan& plan, uint32_t r) { enc_mframe_item(plan, r, fused_lds.mf); }
+__device__ __forceinline__ void fused_fixup(const EncPlan& plan, uint32_t t0) { enc_fixup_quads(plan, t0, fused_lds.fix); }
+__device__ __forceinline__ void fused_sizes(const EncPlan& plan, uint32_t r) {
+    enc_sizes_item<kFusedThreads>(plan, r, fused_lds.sizes);
+}
+__device__ __forceinline__ void fused_assemble(const EncPlan& plan, uint32_t r, uint32_t part) {
+    enc_assemble_item(plan, r, part);
+}
+
+// Waits until *w >= target (thread 0 polls), then makes what the producers
+// released visible to the workgroup.
+__device__ __forceinline__ void fused_wait(const JG uint32_t* w, uint32_t target, JG uint32_t* err) {
+    if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load((uint32_t*)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kFusedSpinMax) {  // never expected: an earlier item did not finish
+                atomicOr(err, kErrStall);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Publishes the item's writes (every thread's) and adds v to *w.
+__device__ __forceinline__ void fused_signal(JG uint32_t* w, uint32_t v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add((uint32_t*)w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Record look-back state: bit 63 its length is published, bit 62 its
+// inclusive offset is; the value in bits 0..61.
+constexpr uint64_t kRsAgg = 1ull << 63, kRsIncl = 1ull << 62, kRsVal = kRsIncl - 1;
+
+// One wave: publishes record r's length, then adds up the lengths of the
+// records before it in its output (from record `first` on) from the nearest
+// one whose inclusive offset is known.  Returns the bytes of the output's
+// records before r.
+__device__ uint64_t rec_lookback(JG uint64_t* st, uint32_t r, uint32_t first, uint64_t len, JG uint32_t* err) {
+    const uint32_t l = lane_id();
+    if (l == 0)
+        __hip_atomic_store((uint64_t*)st + r, (r > first ? kRsAgg : kRsIncl) | len, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    uint32_t end = r, spins = 0;  // records [first, end) not added yet
+    while (end > first) {
+        const int idx = (int)end - 1 - (int)l;
+        uint64_t v = kRsIncl;  // before the output's first record: nothing
+        if (idx >= (int)first) v = __hip_atomic_load((uint64_t*)st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t f = v & (kRsAgg | kRsIncl);
+        const uint64_t incl = ballot(f == kRsIncl), empty = ballot(f == 0);
+        const uint32_t fi = incl ? (uint32_t)__builtin_ctzll(incl) : 64u;
+        const uint32_t fe = empty ? (uint32_t)__builtin_ctzll(empty) : 64u;
+        auto add = [&](uint32_t upto) {  // the values of lanes [0, upto)
+            uint64_t x = l < upto ? (v & kRsVal) : 0ull;
+            for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+            excl += x;
+        };
+        if (fe < fi) {  // a nearer record has not published: take the ones before it, poll again
+            if (fe) {
+                add(fe);
+                end -= fe;
+            }
+            if (++spins > kFusedSpinMax) {
+                if (l == 0) atomicOr(err, kErrStall);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        add(min(fi + 1, 64u));
+        if (fi < 64) break;
+        end -= 64;
+    }
+    if (l == 0 && r > first)
+        __hip_atomic_store((uint64_t*)st + r, kRsIncl | (excl + len), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+// The record of assembly item a (asm_first: first item of every record, and the total).
+__device__ __forceinline__ uint32_t asm_owner(const JG uint32_t* first, uint32_t n, uint32_t a) {
+    uint32_t lo = 0, hi = n;  // the last r with first[r] <= a
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (first[mid] <= a) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_enc_fused(EncPlan plan) {
+    __shared__ uint32_t s_item;
+    const uint32_t R = plan.n_items, F = plan.n_ftiles, G = plan.n_fix;
+    const uint32_t q_tile = R, q_mf = q_tile + F, q_fix = q_mf + R, q_size = q_fix + G, q_asm = q_size + R;
+    const uint32_t total = q_asm + plan.n_asm;
+    JG uint32_t* dep = plan.fdep;  // per record: trial done, tiles done, mask frame done, -
+    for (;;) {
+        if (threadIdx.x == 0) s_item = __hip_atomic_fetch_add((uint32_t*)plan.fctl, 1u, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t q = s_item;
+        __syncthreads();  // every thread has the item before thread 0 takes the next
+        if (q >= total) break;
+        if (q < q_tile) {  // trial
+            fused_trial(plan, q);
+            fused_signal(dep + 4 * q, 1u);
+        } else if (q < q_mf) {  // tile, after its record's decision
+            uint32_t lt;
+            const uint32_t r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, q - q_tile, lt);
+            fused_wait(dep + 4 * r, 1u, plan.err);
+            fused_tile(plan, r, lt);
+            __syncthreads();
+            fused_signal(dep + 4 * r + 1, 1u);
+        } else if (q < q_fix) {  // mask frame, after the record's (and its predecessor's) zero bitmask
+            const uint32_t r = q - q_mf;
+            const EncItem& it = plan.items[r];
+            fused_wait(dep + 4 * r + 1, it.ntiles, plan.err);
+            if (it.prev_item != kNoFix) fused_wait(dep + 4 * it.prev_item + 1, plan.items[it.prev_item].ntiles, plan.err);
+            fused_mframe(plan, r);
+            fused_signal(dep + 4 * r + 2, 1u);
+        } else if (q < q_size) {  // tile-crossing frames of 64 tiles, after those records' tiles
+            const uint32_t g = q - q_fix, t0 = g * kFixQuads, t1 = min(t0 + kFixQuads, F) - 1;
+            uint32_t lt;
+            const uint32_t r0 = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, t0, lt);
+            const uint32_t r1 = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, t1, lt);
+            for (uint32_t r = r0; r <= r1; ++r) fused_wait(dep + 4 * r + 1, plan.items[r].ntiles, plan.err);
+            fused_fixup(plan, t0);
+            __syncthreads();
+            fused_signal(plan.ffix + g, 1u);
+        } else if (q < q_asm) {  // sizes and the record's offset in its output
+            const uint32_t r = q - q_size;
+            const EncItem& it = plan.items[r];
+            const uint32_t t0 = plan.ftpi ? r * plan.ftpi : plan.ftile_first[r];
+            fused_wait(dep + 4 * r + 1, it.ntiles, plan.err);
+            fused_wait(dep + 4 * r + 2, 1u, plan.err);
+            for (uint32_t g = t0 / kFixQuads; g <= (t0 + it.ntiles - 1) / kFixQuads; ++g)
+                fused_wait(plan.ffix + g, 1u, plan.err);
+            fused_sizes(plan, r);
+            __syncthreads();
+            EncOut& o = plan.outs[it.out_id];
+            const bool last = r + 1 == o.first_item + o.n_items;
+            if (threadIdx.x < kWave) {
+                EncRes& rs = plan.res[r];
+                const uint64_t before = rec_lookback(plan.fstat, r, o.first_item, rs.rec_len, plan.err);
+                if (threadIdx.x == 0) {
+                    rs.rec_off = before + o.hdr_len;
+                    if (plan.host_res) {
+                        JG uint32_t* h = (JG uint32_t*)(plan.host_res + 16ull * plan.n_outs);
+                        store_system(h + r, rs.mode);
+                        store_system(h + plan.n_items + 1 + r, rs.rec_len);
+                    }
+                    if (last) {  // the output's length and whether it fits
+                        o.len = o.hdr_len + before + rs.rec_len;
+                        o.ok = o.len <= o.cap ? 1u : 0u;
+                        if (!o.ok) atomicOr(plan.err, kErrCapacity);
+                        if (plan.host_res) {
+                            JG uint32_t* h = (JG uint32_t*)plan.host_res + 4 * it.out_id;
+                            store_system(h, (uint32_t)o.len);
+                            store_system(h + 1, (uint32_t)(o.len >> 32));
+                            store_system(h + 2, o.ok);
+                        }
+                    }
+                }
+            }
+            fused_signal(dep + 4 * r + 3, 1u);
+            if (last) fused_signal(plan.fout + it.out_id, 1u);
+        } else {  // assembly, once the record's offset and its output's length are known
+            const uint32_t a = q - q_asm;
+            const uint32_t r = plan.fasm ? asm_owner(plan.fasm, R, a) : a / (plan.max_asm + 1);
+            const uint32_t part = a - (plan.fasm ? plan.fasm[r] : r * (plan.max_asm + 1));
+            const EncItem& it = plan.items[r];
+            const EncOut& o = plan.outs[it.out_id];
+            fused_wait(plan.fout + it.out_id, 1u, plan.err);
+            fused_wait(dep + 4 * r + 3, 1u, plan.err);
+            if (part == 0 && r == o.first_item && o.hdr_len)  // the stream's table holds every record's length
+                for (uint32_t k = r; k < r + o.n_items; ++k) fused_wait(dep + 4 * k + 3, 1u, plan.err);
+            fused_assemble(plan, r, part);
+        }
+        __syncthreads();  // the LDS is free for the next item
+    }
+    // the last workgroup out reports the error word
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) {
+        const uint32_t d = __hip_atomic_fetch_add((uint32_t*)plan.fctl + 1, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (d + 1 == gridDim.x && plan.host_res) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            store_system((JG uint32_t*)(plan.host_res + 16ull * plan.n_outs) + plan.n_items,
+                         __hip_atomic_load((uint32_t*)plan.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        }
+    }
+}
+
+hipError_t launch_encode_fused(const EncPlan& plan, uint32_t grid, hipStream_t stream) {
+    if (plan.n_items == 0) return hipSuccess;
+    JIFFY_LAUNCH("k_enc_fused", k_enc_fused, dim3(grid), dim3(kFusedThreads), stream, plan);
+    return hipGetLastError();
+}
+
+hipError_t fused_occupancy(int* per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_enc_fused, kFusedThreads, 0);
 }
 
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {

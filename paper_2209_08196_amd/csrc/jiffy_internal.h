@@ -77,7 +77,8 @@ struct EncItem {
     uint32_t wb, bits, attr, out_id;
     uint32_t has_prev, prev_quantized, mode_req, trial_rows;
     uint32_t maxnb, frame_cap, seg_cap, aligned16;
-    uint32_t ntiles, pad0;
+    uint32_t ntiles;
+    uint32_t prev_item;          // the record in this launch whose valid words are vwprev, or kNoFix
 };
 
 // Per-record results of an encode.
@@ -161,8 +162,21 @@ struct EncPlan {
                                  // maps above are then unused), else 0
     uint32_t n_items, n_outs, n_ftiles;
     uint32_t max_asm;         // max over items of ceil(maxnb / kAsmFrames)
+    // the fused persistent launch (k_enc_fused); all zeroed by the plan upload
+    JG uint32_t* fctl;           // [2] next work item, workgroups finished
+    JG uint32_t* fdep;           // [4 * n_items] per record: decision made, tiles done, mask frame done, sizes done
+    JG uint64_t* fstat;          // [n_items] look-back states of the record offsets
+    JG uint32_t* ffix;           // [n_fix] tile-crossing frame groups done
+    JG uint32_t* fout;           // [n_outs] output length known
+    const JG uint32_t* fasm;     // [n_items + 1] first assembly item of each record (null: max_asm + 1 each)
+    uint32_t n_fix, n_asm;       // tile-crossing frame groups, assembly items
 };
 hipError_t launch_encode(const EncPlan& plan, hipStream_t stream);
+// The same encode as one persistent launch of `grid` workgroups.
+hipError_t launch_encode_fused(const EncPlan& plan, uint32_t grid, hipStream_t stream);
+// Workgroups of the fused launch one compute unit holds at once.
+hipError_t fused_occupancy(int* per_cu);
+constexpr uint32_t kFixGroup = 64;  // tile entries per group of tile-crossing frames
 
 // Copies `bytes` (a multiple of 16) from host-mapped memory into device
 // memory with a kernel on `stream` (no copy engine, so no cross-queue wait).

@@ -27,6 +27,7 @@ SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_encode_noalloc", "jiffy_
            "jiffy_step_workspace_bytes", "jiffy_step_create", "jiffy_step_submit", "jiffy_step_finish",
            "jiffy_step_destroy",
            "jiffy_batch_create", "jiffy_batch_run", "jiffy_batch_destroy",
+           "jiffy_set_tuning", "jiffy_get_tuning",
            "jiffy_profile_enable", "jiffy_profile_read")
 
 
@@ -42,6 +43,10 @@ class Layout(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("trial_rows", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fused", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32)]
 
 
 class JiffyError(RuntimeError):
@@ -106,12 +111,32 @@ def lib():
         L.jiffy_batch_run.argtypes = [vp, vp, vp, vp, vp]
         L.jiffy_batch_destroy.restype = None
         L.jiffy_batch_destroy.argtypes = [vp]
+        L.jiffy_set_tuning.restype = ctypes.c_int
+        L.jiffy_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        L.jiffy_get_tuning.restype = ctypes.c_int
+        L.jiffy_get_tuning.argtypes = [ctypes.POINTER(Tuning), ctypes.POINTER(u32)]
         L.jiffy_profile_enable.restype = ctypes.c_int
         L.jiffy_profile_enable.argtypes = [ctypes.c_int]
         L.jiffy_profile_read.restype = ctypes.c_int
         L.jiffy_profile_read.argtypes = [u32, vp, vp, vp]
         _lib = L
     return _lib
+
+
+def set_tuning(fused=0, wgs_per_cu=0):
+    """The encoders' launch configuration from now on (jiffy_set_tuning)."""
+    rc = lib().jiffy_set_tuning(ctypes.byref(Tuning(int(fused), int(wgs_per_cu))))
+    if rc:
+        raise JiffyError(rc, "jiffy_set_tuning")
+
+
+def get_tuning():
+    """-> (current tuning dict, workgroups of the fused kernel per compute unit)."""
+    t, m = Tuning(), ctypes.c_uint32()
+    rc = lib().jiffy_get_tuning(ctypes.byref(t), ctypes.byref(m))
+    if rc:
+        raise JiffyError(rc, "jiffy_get_tuning")
+    return {"fused": t.fused, "wgs_per_cu": t.wgs_per_cu}, m.value
 
 
 def profile_enable(on: bool = True):
@@ -424,15 +449,30 @@ def _check_batch(streams, scans, outs):
     for i, (s, sc, o) in enumerate(zip(streams, scans, outs)):
         if not getattr(s, "handle", None):
             raise ValueError(f"stream {i} is closed")
-        _check_scan(s, sc, f"stream {i}")
+        _check_any_scan(s, sc, f"stream {i}")
         _check_bytes_out(o, f"output of stream {i}")
+
+
+def _check_any_scan(s, sc, what):
+    """A scan given as tensors (checked now) or as a PreparedScan (checked
+    when it was prepared, for this stream's layout)."""
+    if isinstance(sc, PreparedScan):
+        if sc.key != _stream_key(s):
+            raise ValueError(f"{what}: the prepared scan was checked for another layout")
+    else:
+        _check_scan(s, sc, what)
+
+
+def _scan_ptrs(scans):
+    return [(ctypes.c_void_p * len(sc.ptrs))(*sc.ptrs) if isinstance(sc, PreparedScan)
+            else (ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
 
 
 def _batch_args(streams, scans, outs):
     _check_batch(streams, scans, outs)
     n = len(streams)
     sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
-    inner = [(ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
+    inner = _scan_ptrs(scans)
     planes = (ctypes.c_void_p * n)(*[ctypes.cast(x, ctypes.c_void_p).value for x in inner])
     dout = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
     caps = (ctypes.c_size_t * n)(*[o.numel() for o in outs])
@@ -478,8 +518,8 @@ class Batch:
             if len(scans) != len(self.streams):
                 raise ValueError("one scan per stream is needed")
             for i, (s, sc) in enumerate(zip(self.streams, scans)):
-                _check_scan(s, sc, f"stream {i}")
-            self._inner = [(ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
+                _check_any_scan(s, sc, f"stream {i}")
+            self._inner = _scan_ptrs(scans)
             planes = (ctypes.c_void_p * len(self.streams))(*[ctypes.cast(x, ctypes.c_void_p).value
                                                              for x in self._inner])
             self.inputs = scans
@@ -574,15 +614,10 @@ class Step:
         for i, (s, sc) in enumerate(zip(streams, scans)):
             if not getattr(s, "handle", None):
                 raise ValueError(f"stream {i} is closed")
-            if isinstance(sc, PreparedScan):
-                if sc.key != _stream_key(s):
-                    raise ValueError(f"stream {i}: the prepared scan was checked for another layout")
-            else:
-                _check_scan(s, sc, f"stream {i}")
+            _check_any_scan(s, sc, f"stream {i}")
         _check_bytes_out(out, "out")
         sh = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
-        inner = [(ctypes.c_void_p * len(sc.ptrs))(*sc.ptrs) if isinstance(sc, PreparedScan)
-                 else (ctypes.c_void_p * len(sc))(*[t.data_ptr() for t in sc]) for sc in scans]
+        inner = _scan_ptrs(scans)
         planes = (ctypes.c_void_p * n)(*[ctypes.cast(x, ctypes.c_void_p).value for x in inner])
         rc = lib().jiffy_step_submit(self.handle, ctypes.cast(sh, ctypes.c_void_p), n,
                                      ctypes.cast(planes, ctypes.c_void_p), ctypes.c_void_p(out.data_ptr()),
