@@ -14,7 +14,7 @@ from . import build as _build
 
 MAX_ATTRS = 8
 OK, E_INVALID, E_CAPACITY, E_CORRUPT = 0, -1, -2, -3
-MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY = 0, 1, 2
+MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY, MODE_BRUTE = 0, 1, 2, 3
 
 _DT = {1: np.uint8, 2: np.uint16, 4: np.uint32}
 

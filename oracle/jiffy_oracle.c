@@ -542,13 +542,27 @@ static void encode_record(obuf* ob, unsigned a, const uint64_t* Q, const uint64_
     free(mc);
 }
 
+/* Sec. III-E, the brute-force alternative to the trial: the scan is coded
+ * both ways, mask included, and the smaller record is kept (equal sizes:
+ * the I-scan). */
+static int brute_choose_p(unsigned a, const uint64_t* Q, const uint64_t* Qp, const uint8_t* mb,
+                          const uint8_t* mb_prev, size_t npx, unsigned bits) {
+    obuf bi = {0}, bp = {0};
+    encode_record(&bi, a, Q, Qp, mb, mb_prev, 0, npx, bits);
+    encode_record(&bp, a, Q, Qp, mb, mb_prev, 1, npx, bits);
+    int choose_p = bp.n < bi.n;
+    free(bi.p);
+    free(bp.p);
+    return choose_p;
+}
+
 int orc_encode(const orc_layout* L, const orc_options* opt, uint32_t T, const void* const* planes,
                const void* const* prev_planes, uint8_t* out, size_t cap, size_t* out_len,
                uint8_t* modes) {
     if (!layout_ok(L) || !planes || !out_len) return ORC_E_INVALID;
     uint32_t mode = opt ? opt->mode : 0;
     uint32_t k = (opt && opt->trial_rows) ? opt->trial_rows : 4;
-    if (mode > 2) return ORC_E_INVALID;
+    if (mode > 3) return ORC_E_INVALID;
     unsigned A = L->n_attrs;
     size_t npx = (size_t)L->height * L->width, nm = mask_bytes(npx);
 
@@ -609,6 +623,7 @@ int orc_encode(const orc_layout* L, const orc_options* opt, uint32_t T, const vo
             if (have_prev[a]) {
                 if (mode == 1) pmode = 0;
                 else if (mode == 2) pmode = 1;
+                else if (mode == 3) pmode = brute_choose_p(a, Q, Qps[a], mb, mbps[a], npx, bits);
                 else pmode = trial_choose_p(Q, Qps[a], L, bits, k);
             }
             if (modes) modes[(size_t)t * A + a] = (uint8_t)pmode;

@@ -35,7 +35,7 @@ typedef struct {
 } orc_layout;
 
 typedef struct {
-    uint32_t mode;       /* 0 auto, 1 I only, 2 P only */
+    uint32_t mode;       /* 0 auto (trial), 1 I only, 2 P only, 3 brute force (smaller record) */
     uint32_t trial_rows; /* 0 means the default of 4 */
 } orc_options;
 
