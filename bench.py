@@ -468,6 +468,48 @@ def serving_leg(host, duration_s, speed_loaded=8.0):
     return out
 
 
+def heuristic_leg(cases):
+    """Sec. IV-E's validation of the trial (4 rows) against the brute-force
+    choice, on the GPU: per record whether the trial's choice equals the
+    brute-force one, the split of the disagreements (I chosen where P was
+    smaller, P chosen where I was smaller), the bytes the trial leaves, and
+    the throughput of both."""
+    import torch
+
+    from paper_2209_08196_amd import jiffy
+    out = {}
+    for name, host, precs in cases:
+        dev = [torch.from_numpy(p.view(_STORE[p.dtype.itemsize])).cuda() for p in host]
+        T, H, W = host[0].shape
+        lay = jiffy.make_layout(H, W, [p.dtype.itemsize for p in host], precs)
+        buf = torch.empty(jiffy.encode_bound(lay, T), dtype=torch.uint8, device="cuda")
+        res = {}
+        for mode, key in ((jiffy.MODE_AUTO, "trial"), (jiffy.MODE_BRUTE, "brute")):
+            jiffy.encode(dev, precs, mode=mode, out=buf)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                s, m = jiffy.encode(dev, precs, mode=mode, out=buf)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            res[key] = (s.numel(), m.copy(), dt)
+        mt, mb = res["trial"][1][1:], res["brute"][1][1:]  # scan 0 is an I-scan either way
+        n = mt.size
+        out[name] = {
+            "records_compared": int(n), "agreement": round(float((mt == mb).mean()), 4),
+            "suboptimal_i": round(float(((mt == 0) & (mb == 1)).mean()), 4),
+            "suboptimal_p": round(float(((mt == 1) & (mb == 0)).mean()), 4),
+            "p_fraction_brute": round(float(mb.mean()), 4),
+            "trial_bytes_over_brute": round(res["trial"][0] / res["brute"][0] - 1.0, 5),
+            "encode_points_per_s_trial": round(T * H * W * len(host) / res["trial"][2], 1),
+            "encode_points_per_s_brute": round(T * H * W * len(host) / res["brute"][2], 1)}
+        log(f"heuristic {name}: {out[name]}")
+        del dev, buf
+        torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # the oracle on the host (test infrastructure, timed as the CPU baseline)
 # ---------------------------------------------------------------------------
@@ -637,7 +679,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the 256-stream serving leg")
-    ap.add_argument("--only", choices=["headline", "batched", "serving"], help="run one leg only")
+    ap.add_argument("--only", choices=["headline", "batched", "serving", "heuristic"], help="run one leg only")
+    ap.add_argument("--no-heuristic", action="store_true", help="skip the trial-versus-brute-force leg")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-steps", type=int, default=1, help="steps timed per kernel with HIP events")
@@ -664,7 +707,9 @@ def main():
         sys.exit(2)
     from paper_2209_08196_amd import synth
 
-    legs = {args.only} if args.only else {"headline", "batched", "serving"}
+    legs = {args.only} if args.only else {"headline", "batched", "serving", "heuristic"}
+    if args.no_heuristic:
+        legs.discard("heuristic")
     if args.no_batched:
         legs.discard("batched")
     if args.no_serving:
@@ -680,7 +725,12 @@ def main():
         jobs += [(3, s, 0, nb) for s in range(synth.CONFIGS[3].streams)]
     if "serving" in legs:
         jobs += [(4, s, 0, SERVING_CYCLE) for s in range(synth.CONFIGS[4].streams)]
+    n_before_h = len(jobs)
+    if "heuristic" in legs:  # the plain stream, the dual-return stream, two whole stress streams
+        jobs += [(1, 0, 0, 10), (2, 0, 0, 100), (5, 0, 0, 200), (5, 1, 0, 200)]
     data = generate(jobs)
+    heur_host = data[n_before_h:] if "heuristic" in legs else None
+    data = data[:n_before_h]
     head_host = data[:n_head] if "headline" in legs else None
     o = n_head if "headline" in legs else 0
     batched_host = data[o:o + synth.CONFIGS[3].streams] if "batched" in legs else None
@@ -698,6 +748,13 @@ def main():
         log(f"batched: {json.dumps(result['batched'])}")
     if "serving" in legs:
         result["serving"] = serving_leg(serving_host, args.serving_seconds)
+    if "heuristic" in legs:
+        g1, g2 = synth.stream(1, 0), synth.stream(2, 0)
+        result["heuristic"] = heuristic_leg([
+            ("plain-64x1024-range-1cm x10", heur_host[0], list(g1.precisions)),
+            ("dual-return-128x2048-5attr-1mm x100", heur_host[1], list(g2.precisions)),
+            ("stress-128x4096 stream 0 x200", heur_host[2], [1]),
+            ("stress-128x4096 stream 1 x200", heur_host[3], [1])])
     if "headline" in legs and not args.no_cpu_baseline:
         cb, identical = cpu_leg(head_host, ctx, n_single=1, n_all=min(n_head, pool_size()))
         result["cpu_baseline"] = cb

@@ -50,8 +50,10 @@ typedef struct {
     uint32_t precision[JIFFY_MAX_ATTRS];    /* P >= 1 */
 } jiffy_layout;
 
-/* Sec. III-E: I-only, P-only, or the per-scan automatic choice. */
-typedef enum { JIFFY_MODE_AUTO = 0, JIFFY_MODE_I_ONLY = 1, JIFFY_MODE_P_ONLY = 2 } jiffy_mode;
+/* Sec. III-E: the per-scan choice by trial compression (AUTO), I-only,
+ * P-only, or the brute-force choice (both codings of every record, the
+ * smaller kept; equal sizes: I).  BRUTE is accepted by jiffy_encode only. */
+typedef enum { JIFFY_MODE_AUTO = 0, JIFFY_MODE_I_ONLY = 1, JIFFY_MODE_P_ONLY = 2, JIFFY_MODE_BRUTE = 3 } jiffy_mode;
 
 typedef struct {
     uint32_t mode;        /* a jiffy_mode */

@@ -96,7 +96,9 @@ hipError_t grow(HostBuf& b, size_t need) {
 struct DevCtx {
     std::mutex mu;
     DevBuf ws, ws_dec;
+    DevBuf brute;     // the two staging streams of a brute-force encode
     HostBuf up, down, res;
+    HostBuf jobs;     // its record copy list
     uint64_t enc_gen = 0;
     uint8_t* scratch = nullptr;  // this device's copy of `scratch` (jiffy_encode_noalloc), once looked up
 };
@@ -519,13 +521,68 @@ void sequence_specs(const jiffy_layout* L, uint32_t mode, uint32_t K, uint32_t T
 
 // Arguments of jiffy_encode / jiffy_encode_noalloc; JIFFY_OK or JIFFY_E_INVALID.
 int check_encode_args(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, const void* const* d_planes,
-                      void* d_out, size_t* h_out_len) {
+                      void* d_out, size_t* h_out_len, uint32_t max_mode = JIFFY_MODE_P_ONLY) {
     if (!layout_ok(L) || !h_out_len || !d_out || (uintptr_t)d_out % 4) return JIFFY_E_INVALID;
-    if (opt && opt->mode > 2) return JIFFY_E_INVALID;
+    if (opt && opt->mode > max_mode) return JIFFY_E_INVALID;
     if ((uint64_t)T * L->n_attrs > (1u << 24)) return JIFFY_E_INVALID;
     if (T && !d_planes) return JIFFY_E_INVALID;
     for (uint32_t a = 0; T && a < L->n_attrs; ++a)
         if (!d_planes[a] || (uintptr_t)d_planes[a] % L->width_bytes[a]) return JIFFY_E_INVALID;
+    return JIFFY_OK;
+}
+
+// Sec. III-E, the brute-force choice: every record is coded as an I- and
+// as a P-record in one launch sequence (two staging streams of records),
+// the smaller of each pair is kept (equal sizes: the I-record; the first
+// scan has no P-record), and a copy kernel assembles the stream: header
+// and length table, then the kept records in order.
+int encode_brute(DevCtx& ctx, const jiffy_layout* L, uint32_t K, uint32_t T, const void* const* d_planes,
+                 void* d_out, size_t cap, size_t* h_out_len, uint8_t* h_modes, hipStream_t stream) {
+    const uint32_t A = L->n_attrs, n = T * A;
+    const size_t hl = header_len(A, T);
+    size_t body = 0;
+    for (uint32_t a = 0; a < A; ++a) body += record_bound((uint64_t)L->height * L->width, 8u * L->width_bytes[a]) * T;
+    if (grow(ctx.brute, 2 * al(body)) != hipSuccess) return JIFFY_E_DEVICE;
+    uint8_t* stage[2] = {(uint8_t*)ctx.brute.p, (uint8_t*)ctx.brute.p + al(body)};
+    std::vector<EncSpec> specs, half;
+    std::vector<OutSpec> outs(2), o1;
+    for (uint32_t kind = 0; kind < 2; ++kind) {  // 0: every record an I-record, 1: a P-record where possible
+        sequence_specs(L, kind ? JIFFY_MODE_P_ONLY : JIFFY_MODE_I_ONLY, K, T, d_planes, stage[kind], body, half, o1);
+        for (EncSpec& e : half) {
+            e.out_id = kind;
+            if (e.prev_item >= 0) e.prev_item += (int)(kind * n);
+        }
+        specs.insert(specs.end(), half.begin(), half.end());
+        outs[kind] = OutSpec{stage[kind], body, kind * n, n, 0, T, L};
+    }
+    EncResult res;
+    if (int rc = run_encode(ctx, specs, outs, stream, res)) return rc;
+    if (!res.ok[0] || !res.ok[1]) return JIFFY_E_DEVICE;  // the staging streams hold every record's bound
+    // the kept records and their places
+    if (grow(ctx.jobs, sizeof(CopyJob) * (n + 1) + hl) != hipSuccess) return JIFFY_E_DEVICE;
+    CopyJob* jobs = (CopyJob*)ctx.jobs.p;
+    uint8_t* hdr = (uint8_t*)ctx.jobs.p + sizeof(CopyJob) * (n + 1);
+    write_header(hdr, L, T);
+    uint64_t src[2] = {0, 0}, dst = hl;
+    for (uint32_t r = 0; r < n; ++r) {
+        const uint32_t li = res.rec_lens[r], lp = res.rec_lens[n + r];
+        const bool p = r >= A && lp < li;
+        const uint32_t len = p ? lp : li;
+        memcpy(hdr + 20 + 8 * A + 4 * r, &len, 4);
+        jobs[r] = CopyJob{(uint64_t)(uintptr_t)(stage[p ? 1 : 0] + src[p ? 1 : 0]), (uint64_t)(uintptr_t)d_out + dst,
+                          len, 0, 0};
+        if (h_modes) h_modes[r] = p ? 1 : 0;
+        src[0] += li;
+        src[1] += lp;
+        dst += len;
+    }
+    *h_out_len = dst;
+    if (dst > cap) return JIFFY_E_CAPACITY;
+    ++ctx.enc_gen;  // the encoder workspace now holds this call's plan, not a cached one
+    if (hipMemcpyAsync(d_out, hdr, hl, hipMemcpyHostToDevice, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (launch_copy_records((const CopyJob*)ctx.jobs.d, n, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    prof_collect();
     return JIFFY_OK;
 }
 
@@ -712,7 +769,7 @@ size_t jiffy_encode_bound(const jiffy_layout* L, uint32_t n_scans) {
 
 int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, const void* const* d_planes,
                  void* d_out, size_t cap, size_t* h_out_len, uint8_t* h_modes, hipStream_t stream) {
-    if (int rc = check_encode_args(L, opt, T, d_planes, d_out, h_out_len)) return rc;
+    if (int rc = check_encode_args(L, opt, T, d_planes, d_out, h_out_len, JIFFY_MODE_BRUTE)) return rc;
     const uint32_t mode = opt ? opt->mode : 0;
     const uint32_t K = (opt && opt->trial_rows) ? opt->trial_rows : 4;
     const uint32_t A = L->n_attrs;
@@ -720,6 +777,7 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
     if (current_device(&dev)) return JIFFY_E_DEVICE;
     DevCtx& ctx = g_ctx[dev];
     std::lock_guard<std::mutex> lock(ctx.mu);
+    if (mode == JIFFY_MODE_BRUTE && T) return encode_brute(ctx, L, K, T, d_planes, d_out, cap, h_out_len, h_modes, stream);
     if (T == 0) {
         // a header with no records
         const uint32_t hl = header_len(A, 0);

@@ -1298,6 +1298,38 @@ __global__ __launch_bounds__(256) void k_copy_in(const uint4* src, uint4* dst, u
     if (i < n16) ((JG uint4*)dst)[i] = load_system16((const JG uint4*)src + i);
 }
 
+// Record copies of a brute-force encode: job j (host-mapped, read with
+// system-scope loads) moves len bytes (a multiple of 4) from src to dst,
+// both device memory, word by word with every load of a round issued first.
+__global__ __launch_bounds__(256) void k_copy_records(const CopyJob* jobs, uint32_t n) {
+    const uint32_t j = blockIdx.x;
+    if (j >= n) return;
+    const uint4 a = load_system16((const JG uint4*)(jobs + j));
+    const uint4 b = load_system16((const JG uint4*)(jobs + j) + 1);
+    const JG uint32_t* src = (const JG uint32_t*)((uint64_t)a.x | ((uint64_t)a.y << 32));
+    JG uint32_t* dst = (JG uint32_t*)((uint64_t)a.z | ((uint64_t)a.w << 32));
+    const uint32_t nw = b.x / 4;
+    for (uint32_t k0 = 0; k0 < nw; k0 += 8 * 256) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t k = k0 + u * 256 + threadIdx.x;
+            v[u] = k < nw ? src[k] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t k = k0 + u * 256 + threadIdx.x;
+            if (k < nw) dst[k] = v[u];
+        }
+    }
+}
+
+hipError_t launch_copy_records(const CopyJob* host_jobs, uint32_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    JIFFY_LAUNCH("k_copy_records", k_copy_records, dim3(n), dim3(256), stream, host_jobs, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy_in(const void* host, void* dev, size_t bytes, hipStream_t stream) {
     const uint32_t n16 = (uint32_t)(bytes / 16);
     if (n16 == 0) return hipSuccess;

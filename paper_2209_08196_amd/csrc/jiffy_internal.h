@@ -178,6 +178,16 @@ hipError_t launch_encode_fused(const EncPlan& plan, uint32_t grid, hipStream_t s
 hipError_t fused_occupancy(int* per_cu);
 constexpr uint32_t kFixGroup = 64;  // tile entries per group of tile-crossing frames
 
+// One record copy of a brute-force encode (32 bytes; the job list lives in
+// host-mapped memory).
+struct CopyJob {
+    uint64_t src, dst;
+    uint32_t len, pad0;
+    uint64_t pad1;
+};
+// Copies every job's bytes (device to device) with a kernel on `stream`.
+hipError_t launch_copy_records(const CopyJob* host_jobs, uint32_t n, hipStream_t stream);
+
 // Copies `bytes` (a multiple of 16) from host-mapped memory into device
 // memory with a kernel on `stream` (no copy engine, so no cross-queue wait).
 hipError_t launch_copy_in(const void* host, void* dev, size_t bytes, hipStream_t stream);

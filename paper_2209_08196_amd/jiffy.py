@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libjiffy.so")
 MAX_ATTRS = 8
 
 OK, E_INVALID, E_CAPACITY, E_CORRUPT, E_DEVICE, E_SHAPE, E_SCRATCH = 0, -1, -2, -3, -4, -5, -6
-MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY = 0, 1, 2
+MODE_AUTO, MODE_I_ONLY, MODE_P_ONLY, MODE_BRUTE = 0, 1, 2, 3
 
 SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_encode_noalloc", "jiffy_peek", "jiffy_decode", "jiffy_decode_layout",
            "jiffy_status_string",
