@@ -510,6 +510,57 @@ def heuristic_leg(cases):
     return out
 
 
+def quant_leg(x_host, precisions=(1, 2, 4, 8, 16, 32, 64)):
+    """Sec. IV-G / Fig. 4 on the GPU: the dual-return stream's range scans
+    (mm) at precisions P = 1 .. 64 mm: bits per sample and per in-range
+    sample, the largest reconstruction error (at most floor(P/2)), and
+    encode/decode throughput."""
+    import torch
+
+    from paper_2209_08196_amd import jiffy
+    x = torch.from_numpy(x_host.view(np.int32)).cuda()
+    T, H, W = x_host.shape
+    nz = x != 0
+    n_nz = int(nz.sum())
+    lay = jiffy.make_layout(H, W, [4], [1])
+    buf = torch.empty(jiffy.encode_bound(lay, T), dtype=torch.uint8, device="cuda")
+    dec = torch.empty_like(x)
+    out = {"workload": f"dual-return-128x2048 range u32 (mm), {T} scans of {H}x{W}", "points": T * H * W,
+           "in_range_fraction": round(n_nz / (T * H * W), 4), "sweep": []}
+    prev = None
+    for P in precisions:
+        lay = jiffy.make_layout(H, W, [4], [P])
+        enc = jiffy.Encoder([x], [P], out=buf)
+        dcd = jiffy.Decoder(lay, T, [dec])
+        s, _ = enc()
+        dcd(s)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s, _ = enc()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            dcd(s)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        err = int((dec.to(torch.int64) - x.to(torch.int64)).abs()[nz].max())  # ranges < 2^31: int32 storage
+        bnz = 8.0 * s.numel() / n_nz
+        row = {"P_mm": P, "bits_per_sample": round(8.0 * s.numel() / (T * H * W), 4),
+               "bits_per_in_range_sample": round(bnz, 4),
+               "bits_saved_vs_previous": round(prev - bnz, 4) if prev is not None else None,
+               "max_abs_error_mm": err, "error_bound_mm": P // 2,
+               "encode_points_per_s": round(T * H * W * reps / (t1 - t0), 1),
+               "decode_points_per_s": round(T * H * W * reps / (t2 - t1), 1)}
+        prev = bnz
+        out["sweep"].append(row)
+        log(f"quant P={P}: {row}")
+    del x, buf, dec
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # the oracle on the host (test infrastructure, timed as the CPU baseline)
 # ---------------------------------------------------------------------------
@@ -679,7 +730,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the 256-stream serving leg")
-    ap.add_argument("--only", choices=["headline", "batched", "serving", "heuristic"], help="run one leg only")
+    ap.add_argument("--only", choices=["headline", "batched", "serving", "heuristic", "quant"],
+                    help="run one leg only")
     ap.add_argument("--no-heuristic", action="store_true", help="skip the trial-versus-brute-force leg")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--serving-seconds", type=float, default=10.0)
@@ -707,7 +759,7 @@ def main():
         sys.exit(2)
     from paper_2209_08196_amd import synth
 
-    legs = {args.only} if args.only else {"headline", "batched", "serving", "heuristic"}
+    legs = {args.only} if args.only else {"headline", "batched", "serving", "heuristic", "quant"}
     if args.no_heuristic:
         legs.discard("heuristic")
     if args.no_batched:
@@ -728,8 +780,12 @@ def main():
     n_before_h = len(jobs)
     if "heuristic" in legs:  # the plain stream, the dual-return stream, two whole stress streams
         jobs += [(1, 0, 0, 10), (2, 0, 0, 100), (5, 0, 0, 200), (5, 1, 0, 200)]
+    elif "quant" in legs:
+        jobs += [(2, 0, 0, 100)]
     data = generate(jobs)
-    heur_host = data[n_before_h:] if "heuristic" in legs else None
+    extra = data[n_before_h:]
+    heur_host = extra if "heuristic" in legs else None
+    quant_host = (extra[1] if "heuristic" in legs else extra[0])[0] if "quant" in legs else None
     data = data[:n_before_h]
     head_host = data[:n_head] if "headline" in legs else None
     o = n_head if "headline" in legs else 0
@@ -755,6 +811,8 @@ def main():
             ("dual-return-128x2048-5attr-1mm x100", heur_host[1], list(g2.precisions)),
             ("stress-128x4096 stream 0 x200", heur_host[2], [1]),
             ("stress-128x4096 stream 1 x200", heur_host[3], [1])])
+    if "quant" in legs:
+        result["quant"] = quant_leg(quant_host)
     if "headline" in legs and not args.no_cpu_baseline:
         cb, identical = cpu_leg(head_host, ctx, n_single=1, n_all=min(n_head, pool_size()))
         result["cpu_baseline"] = cb

@@ -421,6 +421,7 @@ class Stream:
             raise JiffyError(rc, "jiffy_stream_create" if state is None else "jiffy_stream_create_at")
         self.state = state
         self.handle = h
+        self.key = (int(height), int(width), tuple(int(w) for w in widths))  # what a PreparedScan must match
 
     def record_bound(self):
         lay = self.layout
@@ -579,8 +580,7 @@ class PreparedScan:
 
 
 def _stream_key(s):
-    lay = s.layout
-    return (lay.height, lay.width, tuple(lay.width_bytes[a] for a in range(lay.n_attrs)))
+    return s.key
 
 
 def step_workspace_bytes(max_records, max_samples):

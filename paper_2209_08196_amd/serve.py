@@ -133,7 +133,8 @@ class Server:
     exposing state_bytes(spec), record_bound(spec), setup(slots, max_records,
     max_samples, out_capacity, pool_bytes) -> fixed device bytes,
     open(sid, spec, offset), close(sid), submit(slot, sids, scans),
-    done(slot) -> bool, finish(slot) -> list of record bytes.
+    done(slot) -> bool, finish(slot) -> one bytes-like object of records per
+    stream (read before the slot's next step).
     Steps hold at most max_records records, max_samples samples and
     out_capacity bytes of records."""
 
@@ -327,7 +328,7 @@ class Server:
             st.points += self.specs[sid].samples
             self.last_use[sid] = t_done
             if keep_results is True or (keep_results and sid in keep_results):
-                self.results[sid].append((sess, k, r))
+                self.results[sid].append((sess, k, bytes(r)))
 
     def close(self):
         for sid in list(self.open):
@@ -394,13 +395,16 @@ class GpuBackend:
         return self.hip[slot].query()
 
     def finish(self, slot):
+        """Waits for the step; its records are then in the slot's pinned host
+        buffer.  Returns one view per stream (valid until the slot's next
+        step; bytes(view) keeps a copy)."""
         lens, _ = self.steps[slot].finish()
         total = int(sum(lens))
         host = self.host[slot]
         with __import__("torch").cuda.stream(self.hip[slot]):
             host[:total].copy_(self.outs[slot][:total], non_blocking=True)
         self.hip[slot].synchronize()
-        buf = host[:total].numpy().tobytes()
+        buf = memoryview(host.numpy())
         out, p = [], 0
         for n in lens:
             out.append(buf[p:p + n])
