@@ -619,10 +619,6 @@ __global__ __launch_bounds__(64) void k_dec_mask(DecPlan plan) {
 
 constexpr uint32_t kDecThreads = 320;                 // 80 quads: enough for the 65 frames a tile can touch
 constexpr uint32_t kFrameMaxWords = 160;              // a frame's packed bytes are at most 640
-// staged packed words per tile (larger tiles read the record): 32-bit rows
-// leave room for 3680; with 16-bit rows 2560 (the packed frames of 8- and
-// 16-bit samples are shorter) keep five workgroups on a CU
-template <class R> constexpr uint32_t stage_words() { return sizeof(R) == 4 ? 3680u : 2560u; }
 
 // ---------------------------------------------------------------------------
 // Running count of valid samples: N must match the section header; the
@@ -683,10 +679,10 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
 // Frame unpacking and the running sum, per kFTile-pixel tile (Sec. II,
 // Sec. III-C reversed).  One workgroup per tile of one record, in ticket
 // order:
-//   1. the packed bytes of the frames the tile's values fall in (payloads,
-//      exception positions, exception high parts: three contiguous ranges
-//      of the record) are staged in LDS with coalesced word loads;
-//   2. four lanes per frame unpack the low bits (lane q: values 32q..32q+31)
+//   1. the tile's pixels' valid bits and the frames' widths and offsets
+//      are loaded;
+//   2. four lanes per frame unpack the low bits (lane q: values 32q..32q+31,
+//      its b payload words loaded straight from the record into registers)
 //      into the frame's LDS row, patch the exceptions' high parts in, and
 //      undo ZigZag (Eq. 1);
 //   3. a workgroup scan sums the deltas of the tile's values; the running
@@ -703,7 +699,6 @@ constexpr uint64_t kStAgg = 1ull << 32, kStIncl = 2ull << 32;  // look-back stat
 template <class R>
 struct DecTileLds {
     R rows[kTileFrames * RowT<R>::kElems];
-    uint32_t stage[stage_words<R>() + 2];
     uint32_t info[kTileFrames];
     uint32_t offs[kTileFrames + 1][3];  // frame offsets in the three sections
     uint32_t scratch[8];
@@ -711,8 +706,8 @@ struct DecTileLds {
 };
 
 // `width` bits from bit bp of a little-endian word array.  Without kExact
-// it may read the word after the bits (the staged copy has room for it);
-// with kExact (the record itself) it never reads past them.
+// it may read the word after the bits; with kExact (the record itself) it
+// never reads past them.
 template <bool kExact, class W>
 __device__ __forceinline__ uint32_t bits_at(W* w, uint32_t bp, uint32_t width) {
     const uint32_t sh = bp & 31;
@@ -757,11 +752,47 @@ __device__ uint32_t dec_lookback(JG uint64_t* st, uint32_t lt, uint32_t agg, JG 
     return excl;
 }
 
-// Four lanes unpack frame jf + g: W holds the packed bytes (the staged copy
-// or the record), pay_w is the frame's first payload word, pos_b its first
-// exception-position byte, high_bit its first high-part bit.  d gets the
-// lane's running sum of the deltas of the tile's values.
-template <bool kStaged, class R, class W = typename std::conditional<kStaged, const uint32_t, const JG uint32_t>::type>
+// The low B bits of a lane's 32 values: its B payload words (from w) are
+// loaded at once, then every value is taken out of them with shifts known
+// at compile time.
+template <int B>
+__device__ __forceinline__ void unpack32(const JG uint32_t* w, uint32_t z[32]) {
+    uint32_t v[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) v[k] = w[k];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        constexpr uint32_t kMask = B == 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
+        const int bit = i * B, lo = bit >> 5, sh = bit & 31;
+        uint32_t x = v[lo] >> sh;
+        if (sh + B > 32) x |= v[lo + 1] << (32 - sh);
+        z[i] = x & kMask;
+    }
+}
+#define JIFFY_UNPACK_CASE(B) \
+    case B: unpack32<B>(w, z); break;
+__device__ __forceinline__ void unpack_lane(const JG uint32_t* w, uint32_t b, uint32_t z[32]) {
+    switch (b) {
+        JIFFY_UNPACK_CASE(1) JIFFY_UNPACK_CASE(2) JIFFY_UNPACK_CASE(3) JIFFY_UNPACK_CASE(4)
+        JIFFY_UNPACK_CASE(5) JIFFY_UNPACK_CASE(6) JIFFY_UNPACK_CASE(7) JIFFY_UNPACK_CASE(8)
+        JIFFY_UNPACK_CASE(9) JIFFY_UNPACK_CASE(10) JIFFY_UNPACK_CASE(11) JIFFY_UNPACK_CASE(12)
+        JIFFY_UNPACK_CASE(13) JIFFY_UNPACK_CASE(14) JIFFY_UNPACK_CASE(15) JIFFY_UNPACK_CASE(16)
+        JIFFY_UNPACK_CASE(17) JIFFY_UNPACK_CASE(18) JIFFY_UNPACK_CASE(19) JIFFY_UNPACK_CASE(20)
+        JIFFY_UNPACK_CASE(21) JIFFY_UNPACK_CASE(22) JIFFY_UNPACK_CASE(23) JIFFY_UNPACK_CASE(24)
+        JIFFY_UNPACK_CASE(25) JIFFY_UNPACK_CASE(26) JIFFY_UNPACK_CASE(27) JIFFY_UNPACK_CASE(28)
+        JIFFY_UNPACK_CASE(29) JIFFY_UNPACK_CASE(30) JIFFY_UNPACK_CASE(31) JIFFY_UNPACK_CASE(32)
+        default:  // b = 0 (a width above 32 is rejected by the section parse)
+#pragma unroll
+            for (int i = 0; i < 32; ++i) z[i] = 0;
+    }
+}
+#undef JIFFY_UNPACK_CASE
+
+// Four lanes unpack frame jf + g from the record's words: pay_w is the
+// frame's first payload word, pos_b its first exception-position byte,
+// high_bit its first high-part bit.  d gets the lane's running sum of the
+// deltas of the tile's values.
+template <class R, class W = const JG uint32_t>
 __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, DecTileLds<R>& L, W* words, uint32_t g,
                                            uint32_t q, uint32_t kb, uint32_t ke, uint32_t jf, uint32_t pay_w,
                                            uint32_t pos_b, uint32_t high_bit, uint32_t d[32], uint32_t& lane_sum) {
@@ -770,16 +801,13 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
     const uint32_t b = info & 0xFFu, n = (info >> 8) & 0xFFu, B = (info >> 16) & 0xFFu;
     const uint32_t hw = B - b, real = min(kFrame, rs.N - j * kFrame);
     R* row = L.rows + g * RowT<R>::kElems;
-    W* pay = words + pay_w;
     const uint32_t i0 = 32u * q;
     uint32_t z[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) z[i] = b ? bits_at<!kStaged>(pay, (i0 + i) * b, b) : 0u;
+    unpack_lane(words + pay_w + q * b, b, z);  // lane q's values fill words q*b .. q*b + b - 1 of the frame
     row_put<R>(row, q, z);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     if (n) {
-        using B8 = typename std::conditional<kStaged, const uint8_t, const JG uint8_t>::type;
-        B8* pos = (B8*)words + pos_b;
+        const JG uint8_t* pos = (const JG uint8_t*)words + pos_b;
         uint32_t bad = 0;
         for (uint32_t e = q; e < n; e += 4) {
             const uint32_t p = pos[e];
@@ -787,7 +815,7 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
             // OR the high part in without waiting for the element (positions
             // increase strictly, so no two lanes touch one element; a 16-bit
             // element is ORed into its 32-bit word, the other half unchanged)
-            const uint32_t x = bits_at<!kStaged>(words, high_bit + e * hw, hw) << b, idx = roff<R>(p);
+            const uint32_t x = bits_at<true>(words, high_bit + e * hw, hw) << b, idx = roff<R>(p);
             if (sizeof(R) == 4)
                 __hip_atomic_fetch_or((uint32_t*)row + idx, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             else
@@ -880,43 +908,16 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
             L.offs[tid][2] = rs.high_end - rs.high_off;
         }
     }
-    const uint32_t n01 = D.nw[0] + D.nw[1], nall = n01 + D.nw[2];
-    const bool staged = nall <= stage_words<R>();  // else the frames are read from the record
-    if (staged) {  // every load issued before the first store, so their latencies overlap
-        constexpr int kIter = (stage_words<R>() + kDecThreads - 1) / kDecThreads;
-        const JG uint32_t* recw = (const JG uint32_t*)it.rec;  // records are 4-byte aligned
-        uint32_t w[kIter];
-#pragma unroll
-        for (int u = 0; u < kIter; ++u) {
-            const uint32_t i = tid + u * kDecThreads;
-            const uint32_t src = i < D.nw[0] ? D.w0[0] + i : (i < n01 ? D.w0[1] + (i - D.nw[0]) : D.w0[2] + (i - n01));
-            w[u] = i < nall ? recw[src] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kIter; ++u) {
-            const uint32_t i = tid + u * kDecThreads;
-            if (i < nall) L.stage[i] = w[u];
-        }
-    }
     __syncthreads();
-    // 2. unpack: quad g decodes frame jf + g
+    // 2. unpack: quad g decodes frame jf + g, straight from the record
     const uint32_t g = tid >> 2, q = tid & 3u;
     uint32_t d[32];
     uint32_t lane_sum = 0;
 #pragma unroll
     for (int i = 0; i < 32; ++i) d[i] = 0;
-    if (g < nf) {
-        if (staged)
-            dec_unpack<true, R>(it, rs, L, L.stage, g, q, kb, ke, jf,
-                                       ((rs.pay_off + L.offs[g][0]) >> 2) - D.w0[0],
-                                       4 * D.nw[0] + rs.pos_off + L.offs[g][1] - 4 * D.w0[1],
-                                       8 * (4 * (D.nw[0] + D.nw[1]) + rs.high_off + L.offs[g][2] - 4 * D.w0[2]), d,
-                                       lane_sum);
-        else
-            dec_unpack<false, R>(it, rs, L, (const JG uint32_t*)it.rec, g, q, kb, ke, jf,
-                                          (rs.pay_off + L.offs[g][0]) >> 2, rs.pos_off + L.offs[g][1],
-                                          8 * (rs.high_off + L.offs[g][2]), d, lane_sum);
-    }
+    if (g < nf)
+        dec_unpack<R>(it, rs, L, (const JG uint32_t*)it.rec, g, q, kb, ke, jf, (rs.pay_off + L.offs[g][0]) >> 2,
+                      rs.pos_off + L.offs[g][1], 8 * (rs.high_off + L.offs[g][2]), d, lane_sum);
     // 3. running sum: lanes are in value order (quads in frame order)
     uint32_t agg;
     const uint32_t excl = block_excl_scan<kDecThreads>(lane_sum, L.scratch, &agg);
