@@ -75,8 +75,8 @@ def pool_size():
 # ---------------------------------------------------------------------------
 def _gen(job):
     from paper_2209_08196_amd import synth
-    cid, sid, t0, t1 = job
-    return synth.stream(cid, sid).scans(t0, t1)
+    cid, sid, t0, t1, *rest = job
+    return synth.stream(cid, sid, standing=bool(rest and rest[0])).scans(t0, t1)
 
 
 def generate(jobs):
@@ -561,6 +561,70 @@ def quant_leg(x_host, precisions=(1, 2, 4, 8, 16, 32, 64)):
     return out
 
 
+def _records(s):
+    """(modes, record lengths, mask-frame lengths) of a stream with a length table."""
+    A, = struct.unpack_from("<H", s, 6)
+    T, = struct.unpack_from("<I", s, 16)
+    p = 20 + 8 * A
+    lens = np.array(struct.unpack_from(f"<{T * A}I", s, p), np.int64)
+    p += 4 * T * A
+    offs = p + np.concatenate([[0], np.cumsum(lens)[:-1]])
+    b = np.frombuffer(s, np.uint8)
+    modes = b[offs + 4].astype(np.int64)
+    mlen = (b[offs + 8].astype(np.int64) | (b[offs + 9].astype(np.int64) << 8) | (b[offs + 10].astype(np.int64) << 16)
+            | (b[offs + 11].astype(np.int64) << 24))
+    return modes.reshape(T, A), lens.reshape(T, A), mlen.reshape(T, A)
+
+
+def ablation_leg(cases):
+    """Sec. IV-H / Table IV on the GPU: compression ratio (sample bytes over
+    record bytes) of PFOR alone, Delta -> PFOR, Delta -> ZigZag -> PFOR (every
+    pixel coded, no mask; jiffy_ablate), Mask -> Delta -> ZigZag -> PFOR (the
+    I-only stream) and the codec (automatic I/P), per attribute and over all;
+    and the mask frames of the codec's stream against the run-length mask
+    codec on the same masks (the I-mask or the XOR mask, as each record
+    chose)."""
+    import torch
+
+    from paper_2209_08196_amd import jiffy
+    out = {}
+    for name, host, precs, attr_names in cases:
+        dev = [torch.from_numpy(p.view(_STORE[p.dtype.itemsize])).cuda() for p in host]
+        T, H, W = host[0].shape
+        raw = np.array([p.nbytes for p in host], np.float64)
+        jiffy.ablate(dev, precs)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sz = jiffy.ablate(dev, precs).astype(np.int64)  # [T, A, 5]
+        dt = time.perf_counter() - t0
+        lay = jiffy.make_layout(H, W, [p.dtype.itemsize for p in host], precs)
+        buf = torch.empty(jiffy.encode_bound(lay, T), dtype=torch.uint8, device="cuda")
+        rec = {}
+        for mode, key in ((jiffy.MODE_I_ONLY, "i_only"), (jiffy.MODE_AUTO, "jiffy")):
+            s, _ = jiffy.encode(dev, precs, mode=mode, out=buf)
+            rec[key] = _records(s.cpu().numpy().tobytes())
+        levels = {"pfor": sz[:, :, 0].sum(0), "delta_pfor": sz[:, :, 1].sum(0),
+                  "delta_zigzag_pfor": sz[:, :, 2].sum(0), "mask_delta_zigzag_pfor": rec["i_only"][1].sum(0),
+                  "jiffy": rec["jiffy"][1].sum(0)}
+        modes, _, mlen = rec["jiffy"]
+        zstd_mask = ((mlen + 3) & ~3).sum(0)
+        rl_mask = np.where(modes == 1, sz[:, :, 4], sz[:, :, 3]).sum(0)
+        i_zstd = ((rec["i_only"][2] + 3) & ~3).sum(0)
+        row = {"points": T * H * W * len(host), "scans": T, "shape": [H, W], "attributes": attr_names,
+               "ablate_points_per_s": round(T * H * W * len(host) / dt, 1),
+               "ratio_total": {k: round(float(raw.sum() / v.sum()), 3) for k, v in levels.items()},
+               "ratio_per_attribute": {k: [round(float(r / b), 3) for r, b in zip(raw, v)] for k, v in levels.items()},
+               "mask_bytes_codec_frame": int(zstd_mask.sum()), "mask_bytes_run_length": int(rl_mask.sum()),
+               "mask_bytes_i_frame": int(i_zstd.sum()), "mask_bytes_i_run_length": int(sz[:, :, 3].sum()),
+               "mask_run_length_over_frame": round(float(rl_mask.sum() / zstd_mask.sum()), 4),
+               "p_records": int(modes.sum())}
+        out[name] = row
+        log(f"ablation {name}: {row}")
+        del dev, buf
+        torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # the oracle on the host (test infrastructure, timed as the CPU baseline)
 # ---------------------------------------------------------------------------
@@ -730,9 +794,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the 256-stream serving leg")
-    ap.add_argument("--only", choices=["headline", "batched", "serving", "heuristic", "quant"],
+    ap.add_argument("--only", choices=["headline", "batched", "serving", "heuristic", "quant", "ablation"],
                     help="run one leg only")
     ap.add_argument("--no-heuristic", action="store_true", help="skip the trial-versus-brute-force leg")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the ablation leg")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-steps", type=int, default=1, help="steps timed per kernel with HIP events")
@@ -759,9 +824,11 @@ def main():
         sys.exit(2)
     from paper_2209_08196_amd import synth
 
-    legs = {args.only} if args.only else {"headline", "batched", "serving", "heuristic", "quant"}
+    legs = {args.only} if args.only else {"headline", "batched", "serving", "heuristic", "quant", "ablation"}
     if args.no_heuristic:
         legs.discard("heuristic")
+    if args.no_ablation:
+        legs.discard("ablation")
     if args.no_batched:
         legs.discard("batched")
     if args.no_serving:
@@ -780,12 +847,18 @@ def main():
     n_before_h = len(jobs)
     if "heuristic" in legs:  # the plain stream, the dual-return stream, two whole stress streams
         jobs += [(1, 0, 0, 10), (2, 0, 0, 100), (5, 0, 0, 200), (5, 1, 0, 200)]
-    elif "quant" in legs:
+    elif "quant" in legs or "ablation" in legs:
         jobs += [(2, 0, 0, 100)]
+    n_before_a = len(jobs)
+    if "ablation" in legs:  # the dual-return stream seen by a sensor that never moves
+        jobs += [(2, 0, 0, 100, True)]
     data = generate(jobs)
+    abl_static = data[n_before_a] if "ablation" in legs else None
+    data = data[:n_before_a]
     extra = data[n_before_h:]
     heur_host = extra if "heuristic" in legs else None
-    quant_host = (extra[1] if "heuristic" in legs else extra[0])[0] if "quant" in legs else None
+    dual_host = (extra[1] if "heuristic" in legs else extra[0]) if ("quant" in legs or "ablation" in legs) else None
+    quant_host = dual_host[0] if "quant" in legs else None
     data = data[:n_before_h]
     head_host = data[:n_head] if "headline" in legs else None
     o = n_head if "headline" in legs else 0
@@ -813,6 +886,12 @@ def main():
             ("stress-128x4096 stream 1 x200", heur_host[3], [1])])
     if "quant" in legs:
         result["quant"] = quant_leg(quant_host)
+    if "ablation" in legs:
+        g2 = synth.stream(2, 0)
+        an = [a.name for a in g2.cfg.attrs]
+        result["ablation"] = ablation_leg([
+            ("dual-return-128x2048-5attr-1mm x100", dual_host, list(g2.precisions), an),
+            ("dual-return-128x2048-5attr-1mm standing sensor x100", abl_static, list(g2.precisions), an)])
     if "headline" in legs and not args.no_cpu_baseline:
         cb, identical = cpu_leg(head_host, ctx, n_single=1, n_all=min(n_head, pool_size()))
         result["cpu_baseline"] = cb

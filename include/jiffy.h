@@ -270,6 +270,36 @@ typedef struct {
 int jiffy_set_tuning(const jiffy_tuning* tuning);
 int jiffy_get_tuning(jiffy_tuning* tuning, uint32_t* max_wgs_per_cu);
 
+/* ---- ablated codecs (Sec. IV-H, Table IV) ------------------------------
+ * Record sizes of every scan of every attribute under codecs with stages
+ * left out, and of the zero bitmask under a run-length alternative to the
+ * mask frame.  Nothing is encoded; the sizes are exact.  Every level
+ * quantizes first (Sec. III-B, the layout's precisions).  Per record
+ * (scan-major, attribute-minor) h_sizes receives JIFFY_ABL_SIZES values:
+ *   [0] PFOR alone: every pixel's quantized sample, zeros included, coded as
+ *       one residual section (Sec. II) in a record with no mask frame
+ *       (12-byte head, section, padding to 4);
+ *   [1] Delta -> PFOR: the differences to the preceding pixel of the
+ *       flattened scan (0 before the first) modulo 2^w, same record;
+ *   [2] Delta -> ZigZag -> PFOR: those differences ZigZag-coded (Eq. 1);
+ *   [3] the run-length mask codec on the scan's zero bitmask (Sec. III-C):
+ *       the bits read as alternating runs, the first of in-range pixels
+ *       (possibly empty), coded as one residual section of the first run's
+ *       length and every later run's length minus one; bytes padded to 4;
+ *   [4] the same for the mask XOR the previous scan's (Sec. III-D); for
+ *       the first scan, value [3].
+ * Levels 4 and 5 of the table (mask, then prediction) are the records of
+ * jiffy_encode in I-only and automatic mode.
+ *   layout, n_scans, d_planes: as jiffy_encode (device, caller-owned);
+ *   h_sizes: host, n_scans * n_attrs * JIFFY_ABL_SIZES values.
+ * Synchronizes `stream`.  JIFFY_E_INVALID on bad arguments or a grid
+ * beyond 2^31 workgroups; JIFFY_E_DEVICE on a runtime error.  The library
+ * keeps a workspace of 64 bytes per record plus 4 bytes per pixel for each
+ * of at most 256 records in flight. */
+#define JIFFY_ABL_SIZES 5
+int jiffy_ablate(const jiffy_layout* layout, uint32_t n_scans, const void* const* d_planes, uint64_t* h_sizes,
+                 hipStream_t stream);
+
 /* ---- kernel timing (benchmarks) ----------------------------------------
  * While enabled, every kernel this library launches is bracketed by HIP
  * events recorded on the stream it runs on, and the elapsed times add up

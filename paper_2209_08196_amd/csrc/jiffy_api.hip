@@ -97,6 +97,7 @@ struct DevCtx {
     std::mutex mu;
     DevBuf ws, ws_dec;
     DevBuf brute;     // the two staging streams of a brute-force encode
+    DevBuf abl;       // jiffy_ablate: per-record sums and run-start lists
     HostBuf up, down, res;
     HostBuf jobs;     // its record copy list
     uint64_t enc_gen = 0;
@@ -820,6 +821,58 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
     *h_out_len = res.lens[0];
     if (!res.ok[0]) return JIFFY_E_CAPACITY;
     if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
+    return JIFFY_OK;
+}
+
+int jiffy_ablate(const jiffy_layout* L, uint32_t T, const void* const* d_planes, uint64_t* h_sizes,
+                 hipStream_t stream) {
+    static_assert(JIFFY_MAX_ATTRS <= 8, "AblArgs holds 8 attributes");
+    if (!layout_ok(L) || !h_sizes || (T && !d_planes)) return JIFFY_E_INVALID;
+    const uint32_t A = L->n_attrs;
+    const uint64_t n = (uint64_t)T * A;
+    if (n > (1u << 24)) return JIFFY_E_INVALID;
+    for (uint32_t a = 0; T && a < A; ++a)
+        if (!d_planes[a] || (uintptr_t)d_planes[a] % L->width_bytes[a]) return JIFFY_E_INVALID;
+    if (n == 0) return JIFFY_OK;
+    const uint32_t npx = L->height * L->width;
+    const uint32_t nb = div_up(npx, kFrame);
+    AblArgs g;
+    memset(&g, 0, sizeof g);
+    g.A = A;
+    g.T = T;
+    g.npx = npx;
+    g.nb = nb;
+    g.chunks = div_up(nb, 64u);
+    if (n * g.chunks >= (1ull << 31)) return JIFFY_E_INVALID;
+    for (uint32_t a = 0; a < A; ++a) {
+        g.attr[a].x = d_planes[a];
+        g.attr[a].wb = L->width_bytes[a];
+        g.attr[a].bits = 8u * L->width_bytes[a];
+        g.attr[a].div = make_divisor(L->precision[a]);
+    }
+    const uint32_t groups = (uint32_t)(n < 256 ? n : 256);
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    const size_t acc_bytes = al(64 * n);
+    if (grow(ctx.abl, acc_bytes + (size_t)groups * npx * 4) != hipSuccess) return JIFFY_E_DEVICE;
+    g.acc = (uint64_t*)ctx.abl.p;
+    g.runs = (uint32_t*)((uint8_t*)ctx.abl.p + acc_bytes);
+    if (launch_ablate(g, groups, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    std::vector<uint64_t> acc(8 * n);
+    if (hipMemcpyAsync(acc.data(), g.acc, 64 * n, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    // section = u32 N, three bytes per frame padded to 4, the frames' packed bytes
+    auto section = [](uint64_t values, uint64_t packed) { return 4 + ((3 * ((values + 127) / 128) + 3) & ~3ull) + packed; };
+    auto pad4 = [](uint64_t x) { return (x + 3) & ~3ull; };
+    for (uint64_t r = 0; r < n; ++r) {
+        const uint64_t* c = &acc[8 * r];
+        uint64_t* o = h_sizes + JIFFY_ABL_SIZES * r;
+        for (int k = 0; k < 3; ++k) o[k] = 12 + pad4(section(npx, c[k]));
+        o[3] = pad4(section(c[4], c[3]));
+        o[4] = r >= A ? pad4(section(c[6], c[5])) : o[3];
+    }
     return JIFFY_OK;
 }
 

@@ -52,7 +52,10 @@ __device__ __forceinline__ uint32_t tile_owner(const JG uint32_t* item_of, const
 // with kStash the codes also go back to vrow.  Returns the width key
 // cost << 14 | (63 - b) << 8 | n(b) of the cheapest b (ties: larger b) and
 // the frame's maximum width in B.  All four lanes call it together.
-template <bool kStash>
+// kXf selects what is coded: 2 the ZigZag code of the difference to the
+// preceding value (the codec), 1 that difference modulo 2^bits, 0 the values
+// themselves (pred unused); 0 and 1 serve the ablated codecs only.
+template <bool kStash, int kXf = 2>
 __device__ __forceinline__ uint32_t quad_frame_key(uint32_t z[32], uint32_t* vrow, uint32_t* hist, uint32_t real,
                                                    uint32_t pred, uint32_t bits, uint32_t q, uint32_t& Bout) {
     uint4* h4 = (uint4*)hist;
@@ -66,7 +69,8 @@ __device__ __forceinline__ uint32_t quad_frame_key(uint32_t z[32], uint32_t* vro
     // a code of width w >= 1 counts in word w - 1 = 31 - clz, a zero in the lane's own word
     auto code = [&](int i, bool real_i) {
         const uint32_t x = z[i];
-        const uint32_t r = real_i ? zigzag(x - prev, bits) : 0u;  // zigzag keeps the low `bits` bits only
+        uint32_t r = 0u;  // zigzag keeps the low `bits` bits only
+        if (real_i) r = kXf == 2 ? zigzag(x - prev, bits) : kXf == 1 ? (x - prev) & low_mask32(bits) : x;
         prev = x;
         z[i] = r;
         orv |= r;
@@ -1587,6 +1591,178 @@ hipError_t launch_encode(const EncPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_enc_sizes", k_enc_sizes, dim3(plan.n_items), dim3(kSizeThreads), stream, plan);
     JIFFY_LAUNCH("k_enc_offsets", k_enc_offsets, dim3(1), dim3(1024), stream, plan);
     JIFFY_LAUNCH("k_enc_assemble", k_enc_assemble, dim3(plan.max_asm + 1, plan.n_items), dim3(256), stream, plan);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ablated codecs (Sec. IV-H, Table IV) and the run-length mask codec.  These
+// measure record sizes only; no stream is written.
+//
+// k_abl_levels: levels 1-3 code every pixel of a record, zeros included.
+// Each quad takes one frame of 128 pixels, loads and quantizes its lanes'
+// 32 values once and costs the frame three times with the coder's width
+// choice: the values, their differences to the preceding pixel (modulo
+// 2^bits) and the ZigZag codes of those differences.
+//
+// k_abl_runs: the record's zero bitmask (XOR the previous scan's for the
+// P-mask) as alternating runs, the first of in-range pixels and possibly
+// empty.  A run starts wherever a pixel's bit differs from its
+// predecessor's (the bit before pixel 0 counts as 0), so the run starts are
+// the set bits of m ^ (m << 1): one workgroup per record lists them in
+// order (a workgroup scan of their counts per 64-pixel word, the words
+// built by ballots over 64 consecutive pixels) and then costs the frames of
+// run lengths (the first as is, the others minus one), a quad per frame.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kAblQuads = 64;          // frames per workgroup of k_abl_levels
+constexpr uint32_t kAblRunThreads = 1024;   // one workgroup per record of k_abl_runs
+
+template <int WB>
+__device__ __forceinline__ void abl_levels_frame(const AblArgs& g, const AblAttr& at, uint32_t t, uint32_t f,
+                                                 uint32_t q, uint32_t* hist, uint32_t cost[3]) {
+    const uint8_t* base = (const uint8_t*)at.x + (uint64_t)t * g.npx * WB;
+    const bool aligned = ((uintptr_t)base & 15u) == 0;
+    uint32_t v[32];
+    load16<WB>(base, 128u * f + 32u * q, g.npx, aligned, v);
+    load16<WB>(base, 128u * f + 32u * q + 16u, g.npx, aligned, v + 16);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = quantize(v[i], at.div);
+    const uint32_t pred = (q == 0 && f > 0) ? quantize(load1<WB>(base, 128u * f - 1u), at.div) : 0u;
+    const uint32_t real = min(kFrame, g.npx - 128u * f);
+    uint32_t z[32], B;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) z[i] = v[i];
+    cost[0] = quad_frame_key<false, 0>(z, nullptr, hist, real, pred, at.bits, q, B) >> 14;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) z[i] = v[i];
+    cost[1] = quad_frame_key<false, 1>(z, nullptr, hist, real, pred, at.bits, q, B) >> 14;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) z[i] = v[i];
+    cost[2] = quad_frame_key<false, 2>(z, nullptr, hist, real, pred, at.bits, q, B) >> 14;
+}
+
+__global__ __launch_bounds__(256) void k_abl_levels(AblArgs g) {
+    __shared__ uint32_t hist[kAblQuads * 36];
+    __shared__ uint32_t wsum[3];
+    const uint32_t r = blockIdx.x / g.chunks, c = blockIdx.x - r * g.chunks;
+    const uint32_t t = r / g.A, a = r - t * g.A;
+    const uint32_t quad = threadIdx.x >> 2, q = threadIdx.x & 3u;
+    const uint32_t f = c * kAblQuads + quad;
+    if (threadIdx.x < 3) wsum[threadIdx.x] = 0;
+    __syncthreads();
+    const AblAttr at = g.attr[a];
+    if (f < g.nb) {
+        uint32_t cost[3];
+        uint32_t* h = hist + 36 * quad;
+        if (at.wb == 1) abl_levels_frame<1>(g, at, t, f, q, h, cost);
+        else if (at.wb == 2) abl_levels_frame<2>(g, at, t, f, q, h, cost);
+        else abl_levels_frame<4>(g, at, t, f, q, h, cost);
+        if (q == 0)
+            for (int k = 0; k < 3; ++k) atomicAdd(&wsum[k], cost[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && wsum[threadIdx.x])
+        atomicAdd((unsigned long long*)(g.acc + 8ull * r + threadIdx.x), (unsigned long long)wsum[threadIdx.x]);
+}
+
+// bit p of the mask being coded (pixels from npx on read as 0)
+template <int WB>
+__device__ __forceinline__ bool abl_mask_bit(const uint8_t* base, const uint8_t* prev, uint32_t p, uint32_t npx) {
+    if (p >= npx) return false;
+    bool b = load1<WB>(base, p) == 0u;
+    if (prev) b = b != (load1<WB>(prev, p) == 0u);
+    return b;
+}
+
+template <int WB>
+__device__ void abl_runs_record(const AblArgs& g, const AblAttr& at, uint32_t r, uint32_t t, uint32_t kind,
+                                uint32_t* runs, uint32_t* hist, uint32_t* scan, uint64_t* lsum) {
+    const uint32_t npx = g.npx, l = lane_id(), wv = threadIdx.x / kWave;
+    const uint8_t* base = (const uint8_t*)at.x + (uint64_t)t * npx * WB;
+    const uint8_t* prev = kind ? base - (uint64_t)npx * WB : nullptr;
+    const uint32_t nwords = div_up(npx, 64u);
+    uint32_t K = 0;  // run starts listed so far (pixel 0 counts only when its bit is 1)
+    for (uint32_t w0 = 0; w0 < nwords; w0 += kAblRunThreads) {
+        const uint32_t wbase = w0 + 64u * wv;
+        uint64_t my = 0;  // lane k: mask word wbase + k
+        for (uint32_t k = 0; k < 64u && wbase + k < nwords; ++k) {
+            const uint64_t m = ballot(abl_mask_bit<WB>(base, prev, 64u * (wbase + k) + l, npx));
+            if (l == k) my = m;
+        }
+        const uint32_t wi = wbase + l;
+        uint64_t st = 0;  // run starts in word wi
+        if (wi < nwords) {
+            const uint64_t carry = wi ? (uint64_t)abl_mask_bit<WB>(base, prev, 64u * wi - 1u, npx) : 0ull;
+            st = my ^ ((my << 1) | carry);
+            const uint32_t left = npx - 64u * wi;
+            if (left < 64u) st &= (1ull << left) - 1ull;
+        }
+        uint32_t total;
+        const uint32_t before = block_excl_scan<kAblRunThreads>((uint32_t)__popcll(st), scan, &total);
+        uint32_t* dst = runs + K + before;
+        while (st) {
+            *dst++ = 64u * wi + (uint32_t)__builtin_ctzll(st);
+            st &= st - 1ull;
+        }
+        K += total;
+    }
+    __syncthreads();  // every run start stored
+    // values: run j spans [E(j), E(j+1)) with E(0) = 0, E(j) = runs[j-1], E(K+1) = npx
+    const uint32_t nv = K + 1, nbr = div_up(nv, kFrame);
+    const uint32_t quad = threadIdx.x >> 2, q = threadIdx.x & 3u;
+    uint64_t sum = 0;
+    for (uint32_t fr = quad; fr < nbr; fr += kAblRunThreads / 4) {
+        uint32_t z[32], B;
+        const uint32_t i0 = 128u * fr + 32u * q;
+#pragma unroll
+        for (int e = 0; e < 32; ++e) {
+            const uint32_t i = i0 + e;
+            uint32_t v = 0;
+            if (i < nv) {
+                const uint32_t lo = i ? runs[i - 1] : 0u;
+                const uint32_t hi = i < K ? runs[i] : npx;
+                v = hi - lo - (i ? 1u : 0u);
+            }
+            z[e] = v;
+        }
+        const uint32_t real = min(kFrame, nv - 128u * fr);
+        sum += quad_frame_key<false, 0>(z, nullptr, hist + 36 * quad, real, 0u, 32u, q, B) >> 14;
+    }
+    if (q == 0 && sum) atomicAdd((unsigned long long*)lsum, (unsigned long long)sum);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        g.acc[8ull * r + 3 + 2 * kind] = *lsum;
+        g.acc[8ull * r + 4 + 2 * kind] = nv;
+        *lsum = 0;
+    }
+    __syncthreads();  // runs and lsum are free for the next record
+}
+
+__global__ __launch_bounds__(kAblRunThreads) void k_abl_runs(AblArgs g) {
+    __shared__ uint32_t hist[(kAblRunThreads / 4) * 36];
+    __shared__ uint32_t scan[kAblRunThreads / kWave + 1];
+    __shared__ uint64_t lsum;
+    if (threadIdx.x == 0) lsum = 0;
+    __syncthreads();
+    uint32_t* runs = g.runs + (uint64_t)blockIdx.x * g.npx;
+    const uint32_t n = g.T * g.A;
+    for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const uint32_t t = r / g.A, a = r - t * g.A;
+        const AblAttr at = g.attr[a];
+        for (uint32_t kind = 0; kind < (t ? 2u : 1u); ++kind) {
+            if (at.wb == 1) abl_runs_record<1>(g, at, r, t, kind, runs, hist, scan, &lsum);
+            else if (at.wb == 2) abl_runs_record<2>(g, at, r, t, kind, runs, hist, scan, &lsum);
+            else abl_runs_record<4>(g, at, r, t, kind, runs, hist, scan, &lsum);
+        }
+    }
+}
+
+hipError_t launch_ablate(const AblArgs& a, uint32_t run_groups, hipStream_t stream) {
+    const uint32_t n = a.T * a.A;
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMemsetAsync(a.acc, 0, 8ull * n * sizeof(uint64_t), stream);
+    if (e != hipSuccess) return e;
+    JIFFY_LAUNCH("k_abl_levels", k_abl_levels, dim3(n * a.chunks), dim3(256), stream, a);
+    JIFFY_LAUNCH("k_abl_runs", k_abl_runs, dim3(run_groups), dim3(kAblRunThreads), stream, a);
     return hipGetLastError();
 }
 

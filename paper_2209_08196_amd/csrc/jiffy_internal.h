@@ -188,6 +188,28 @@ struct CopyJob {
 // Copies every job's bytes (device to device) with a kernel on `stream`.
 hipError_t launch_copy_records(const CopyJob* host_jobs, uint32_t n, hipStream_t stream);
 
+// Ablated codecs (Sec. IV-H, Table IV) and the run-length mask codec: byte
+// sums per record r (scan-major, attribute-minor) in acc[8 r + k]: k = 0, 1, 2
+// the packed bytes of every pixel's frames coded as values, differences
+// (modulo 2^bits), ZigZag-coded differences; 3, 4 the packed bytes and the
+// value count of the run-length section of the record's zero bitmask; 5, 6
+// the same for that mask XOR the previous scan's (left 0 for the first scan).
+struct AblAttr {
+    const void* x;  // [T][H][W] samples of wb bytes
+    uint32_t wb, bits;
+    Divisor div;
+};
+struct AblArgs {
+    AblAttr attr[8];
+    uint32_t A, T, npx, nb;  // nb: frames per record
+    uint32_t chunks;         // 64-frame chunks per record (workgroups of the level kernel per record)
+    uint64_t* acc;           // [8 T A], zeroed by launch_ablate
+    uint32_t* runs;          // npx words per workgroup of the run-length kernel
+};
+// Zeroes acc, then launches the level kernel over every chunk of every
+// record and the run-length kernel with `run_groups` workgroups.
+hipError_t launch_ablate(const AblArgs& a, uint32_t run_groups, hipStream_t stream);
+
 // Copies `bytes` (a multiple of 16) from host-mapped memory into device
 // memory with a kernel on `stream` (no copy engine, so no cross-queue wait).
 hipError_t launch_copy_in(const void* host, void* dev, size_t bytes, hipStream_t stream);

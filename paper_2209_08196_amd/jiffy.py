@@ -27,7 +27,7 @@ SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_encode_noalloc", "jiffy_
            "jiffy_step_workspace_bytes", "jiffy_step_create", "jiffy_step_submit", "jiffy_step_finish",
            "jiffy_step_destroy",
            "jiffy_batch_create", "jiffy_batch_run", "jiffy_batch_destroy",
-           "jiffy_set_tuning", "jiffy_get_tuning",
+           "jiffy_set_tuning", "jiffy_get_tuning", "jiffy_ablate",
            "jiffy_profile_enable", "jiffy_profile_read")
 
 
@@ -115,6 +115,8 @@ def lib():
         L.jiffy_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.jiffy_get_tuning.restype = ctypes.c_int
         L.jiffy_get_tuning.argtypes = [ctypes.POINTER(Tuning), ctypes.POINTER(u32)]
+        L.jiffy_ablate.restype = ctypes.c_int
+        L.jiffy_ablate.argtypes = [ctypes.POINTER(Layout), u32, vp, vp, vp]
         L.jiffy_profile_enable.restype = ctypes.c_int
         L.jiffy_profile_enable.argtypes = [ctypes.c_int]
         L.jiffy_profile_read.restype = ctypes.c_int
@@ -273,6 +275,26 @@ def encode(planes, precisions=None, mode=MODE_AUTO, trial_rows=0, out=None, stre
     if rc:
         raise JiffyError(rc, "jiffy_encode_noalloc" if noalloc else "jiffy_encode")
     return out[: n.value], modes[:T]
+
+
+ABL_SIZES = 5
+ABL_NAMES = ("pfor", "delta_pfor", "delta_zigzag_pfor", "rl_mask_i", "rl_mask_p")
+
+
+def ablate(planes, precisions=None, stream=None):
+    """Record sizes under the ablated codecs and the run-length mask codec
+    (jiffy_ablate).  planes: as encode.  Returns uint64 [T, A, 5] in the
+    order of ABL_NAMES."""
+    T, H, W = _check_planes(planes)
+    widths = [p.element_size() for p in planes]
+    lay = make_layout(H, W, widths, precisions)
+    arr = (ctypes.c_void_p * len(planes))(*[p.data_ptr() for p in planes])
+    out = np.zeros((max(T, 1), len(planes), ABL_SIZES), np.uint64)
+    rc = lib().jiffy_ablate(ctypes.byref(lay), T, ctypes.cast(arr, ctypes.c_void_p),
+                            out.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+    if rc:
+        raise JiffyError(rc, "jiffy_ablate")
+    return out[:T]
 
 
 def peek(data: bytes):
