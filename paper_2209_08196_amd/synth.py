@@ -176,7 +176,9 @@ class StreamGen:
     """One sensor stream of a configuration.  scans(t0, t1) returns a list of
     [t1-t0, H, W] arrays, one per attribute, in the configuration's order."""
 
-    def __init__(self, cfg: Config, stream_id: int = 0, base_seed: int = 0, size=None):
+    def __init__(self, cfg: Config, stream_id: int = 0, base_seed: int = 0, size=None, standing=False):
+        if standing:  # the same scene seen by a sensor that never moves (a fixed monitoring sensor)
+            cfg = dataclasses.replace(cfg, stops=((0, 1 << 30),))
         self.cfg = cfg
         self.stream_id = stream_id
         ss = np.random.SeedSequence([cfg.cid, stream_id, base_seed])
@@ -279,8 +281,8 @@ class StreamGen:
         return [np.stack([p[a] for p in per]) for a in range(len(self.cfg.attrs))]
 
 
-def stream(cid: int, stream_id: int = 0, base_seed: int = 0, size=None) -> StreamGen:
-    return StreamGen(CONFIGS[cid], stream_id, base_seed, size)
+def stream(cid: int, stream_id: int = 0, base_seed: int = 0, size=None, standing=False) -> StreamGen:
+    return StreamGen(CONFIGS[cid], stream_id, base_seed, size, standing)
 
 
 def random_scans(rng, T, H, W, dtype, zero_frac=0.2, scale=None):
@@ -291,6 +293,58 @@ def random_scans(rng, T, H, W, dtype, zero_frac=0.2, scale=None):
     v = rng.integers(1, int(top) + 1, size=(T, H, W), dtype=np.uint64)
     z = rng.random((T, H, W)) < zero_frac
     return np.where(z, 0, v).astype(dt)
+
+
+FOV_ELEV_RAD = (-np.pi / 8, np.pi / 8)  # the +-22.5 degree vertical field of view
+
+
+def cartesian_scan(rng, range_mm, attr_imgs=(), e_lo=FOV_ELEV_RAD[0], e_hi=FOV_ELEV_RAD[1], jitter=0.3,
+                   invalid_frac=0.02, dup_frac=0.02, tie_frac=0.005):
+    """The raw output of a sensor that reports Cartesian points (Sec. III-A):
+    every nonzero pixel of a range image (mm) becomes a float32 point in
+    metres at its row's elevation and its column's azimuth (row 0 at the top
+    of the band, column 0 at azimuth 0, counter-clockwise), each moved by a
+    uniform fraction of a bin up to +-jitter, at a range of the pixel's
+    millimetres plus 0.25 mm (float32 rounding stays far below that).  Mixed
+    in, in random order: invalid points (NaN, the origin, above the band),
+    farther duplicates of some pixels, and duplicates at the same
+    millimetre (ties).  Each point carries its pixel's attribute values;
+    duplicates carry other values.
+    Returns (xyz [N, 3] float32, attribute arrays [N], pixel index [N], -1 for invalid points)."""
+    H, W = range_mm.shape
+    rows, cols = np.nonzero(range_mm)
+    pix = rows * W + cols
+    n = pix.size
+    nd, nt = int(dup_frac * n), int(tie_frac * n)
+    di = rng.choice(n, nd + nt, replace=nd + nt > n)
+    pix_all = np.concatenate([pix, pix[di]])
+    rows_all, cols_all = pix_all // W, pix_all % W
+    mm = range_mm.ravel()[pix_all].astype(np.float64)
+    mm[n:n + nd] += rng.uniform(1.0, 5000.0, nd).round()
+    m = pix_all.size
+    r = (mm + 0.25) / 1000.0
+    e = e_hi - (rows_all + 0.5 + rng.uniform(-jitter, jitter, m)) * (e_hi - e_lo) / H
+    a = (cols_all + 0.5 + rng.uniform(-jitter, jitter, m)) * 2.0 * np.pi / W
+    xyz = np.stack([r * np.cos(e) * np.cos(a), r * np.cos(e) * np.sin(a), r * np.sin(e)], 1)
+    attrs = []
+    for img in attr_imgs:
+        v = img.ravel()[pix_all].copy()
+        top = np.iinfo(img.dtype).max
+        v[n:] = rng.integers(0, top, m - n, endpoint=True).astype(img.dtype)
+        attrs.append(v)
+    ni = int(invalid_frac * n)
+    bad = np.zeros((ni, 3))
+    kind = rng.integers(0, 3, ni)
+    bad[kind == 0] = np.nan
+    up = kind == 2  # above the band, 30 m away
+    ang = e_hi + 0.05
+    bad[up] = [30.0 * np.cos(ang), 0.0, 30.0 * np.sin(ang)]
+    xyz = np.concatenate([xyz, bad])
+    attrs = [np.concatenate([v, rng.integers(0, np.iinfo(v.dtype).max, ni, endpoint=True).astype(v.dtype)])
+             for v in attrs]
+    src = np.concatenate([pix_all, np.full(ni, -1)])
+    order = rng.permutation(xyz.shape[0])
+    return xyz[order].astype(np.float32), [v[order] for v in attrs], src[order]
 
 
 def serving_arrivals(n_streams: int, duration_s: float, base_seed: int = 0, session_s=None):
@@ -332,5 +386,5 @@ def config_pixels(cid: int) -> int:
     return cfg.streams * h * w
 
 
-__all__ = ["CONFIGS", "Config", "Attr", "StreamGen", "stream", "random_scans", "serving_arrivals",
+__all__ = ["CONFIGS", "Config", "Attr", "StreamGen", "stream", "random_scans", "serving_arrivals", "cartesian_scan",
            "config_pixels"]
