@@ -51,7 +51,8 @@ SCENE_PERIOD = 20  # scans per scene of the stress set (the part that is generat
 SERVING_CYCLE = 4  # distinct synthetic scans per serving stream (cycled)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_08196_amd", "csrc", f)
-                  for f in ("jiffy_encode.hip", "jiffy_decode.hip", "jiffy_device.h", "jiffy_internal.h")]
+                  for f in ("jiffy_encode.hip", "jiffy_decode.hip", "jiffy_standardize.hip", "jiffy_device.h",
+                            "jiffy_internal.h")]
 _STORE = {1: np.uint8, 2: np.int16, 4: np.int32}
 
 
@@ -87,6 +88,22 @@ def generate(jobs):
         return [_gen(j) for j in jobs]
     with mp.get_context("fork").Pool(min(n, len(jobs))) as pool:
         return pool.map(_gen, jobs, chunksize=1)
+
+
+def _cloud(args):
+    from paper_2209_08196_amd import synth
+    t, rng_img, attr_imgs = args
+    return synth.cartesian_scan(np.random.default_rng([2, t]), rng_img, attr_imgs)[:2]
+
+
+def generate_clouds(dual):
+    """Cartesian clouds of the dual-return stream's range scans, each point
+    carrying signal, reflectivity and near-IR (in a process pool)."""
+    import multiprocessing as mp
+    T = dual[0].shape[0]
+    jobs = [(t, dual[0][t], [dual[2][t], dual[3][t], dual[4][t]]) for t in range(T)]
+    with mp.get_context("fork").Pool(min(pool_size(), T)) as pool:
+        return pool.map(_cloud, jobs, chunksize=4)
 
 
 # ---------------------------------------------------------------------------
@@ -625,6 +642,64 @@ def ablation_leg(cases):
     return out
 
 
+def standardize_leg(clouds, H, W, reps=5):
+    """Sec. III-A on the GPU: Cartesian clouds (float32 xyz plus three
+    attributes per point) of the dual-return stream's range scans binned into
+    range and attribute images, all scans in one call; throughput, the
+    kernels' times (HIP events) and their algorithmic bytes (12 bytes of
+    coordinates and the attributes per point read, the images and one 8-byte
+    key per cell written and read back), and a comparison of sampled scans
+    with the oracle."""
+    import torch
+
+    import oracle.standardize as ost
+    from paper_2209_08196_amd import jiffy, synth
+    S = len(clouds)
+    n = max(len(x) for x, _ in clouds)
+    xyz = np.full((S, n, 3), np.nan, np.float32)
+    A = len(clouds[0][1])
+    attrs = [np.zeros((S, n), clouds[0][1][a].dtype) for a in range(A)]
+    for i, (x, at) in enumerate(clouds):
+        xyz[i, :len(x)] = x
+        for a in range(A):
+            attrs[a][i, :len(x)] = at[a]
+    e_lo, e_hi = synth.FOV_ELEV_RAD
+    dx = torch.from_numpy(xyz).cuda()
+    da = [torch.from_numpy(a.view(_STORE[a.dtype.itemsize])).cuda() for a in attrs]
+    rng = torch.empty((S, H, W), dtype=torch.int32, device="cuda")
+    outs = [torch.empty((S, H, W), dtype=d.dtype, device="cuda") for d in da]
+    jiffy.standardize(dx, H, W, e_lo, e_hi, 0.001, 4, da, outs=(rng, outs))
+    torch.cuda.synchronize()
+    jiffy.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        jiffy.standardize(dx, H, W, e_lo, e_hi, 0.001, 4, da, outs=(rng, outs))
+    dt = (time.perf_counter() - t0) / reps
+    prof = jiffy.profile_read()
+    jiffy.profile_enable(False)
+    ab = sum(a.dtype.itemsize for a in attrs)
+    cells = S * H * W
+    alg = {"k_std_points": S * n * 12 + cells * 8, "k_std_gather": S * n * ab + cells * (8 + 4 + ab),
+           "k_std_clear": cells * 8}
+    kern = {k: round(v[0] / v[1], 4) for k, v in prof.items() if k in alg}
+    got = rng.cpu().numpy().view(np.uint32)
+    got_a = [o.cpu().numpy().view({1: np.uint8, 2: np.uint16, 4: np.uint32}[a.dtype.itemsize])
+             for o, a in zip(outs, attrs)]
+    checked, same = [0, S // 2, S - 1], True
+    for s in checked:
+        w, wa = ost.standardize(xyz[s], H, W, e_lo, e_hi, 0.001, 4, [a[s] for a in attrs])
+        same &= bool(np.array_equal(got[s], w)) and all(np.array_equal(g[s], x) for g, x in zip(got_a, wa))
+    out = {"workload": f"dual-return-128x2048 Cartesian clouds: {S} scans of up to {n} points (float32 xyz, "
+                       f"{A} attributes), binned to {H}x{W}", "points": S * n, "ms_per_call": round(1e3 * dt, 3),
+           "points_per_s": round(S * n / dt, 1), "kernels_ms": kern,
+           "kernel_alg_gbps": {k: round(alg[k] / (kern[k] * 1e-3) / 1e9, 1) for k in kern},
+           "oracle_scans_checked": checked, "identical": same}
+    log(f"standardize: {out}")
+    del dx, da, rng, outs
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # the oracle on the host (test infrastructure, timed as the CPU baseline)
 # ---------------------------------------------------------------------------
@@ -794,10 +869,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the 256-stream serving leg")
-    ap.add_argument("--only", choices=["headline", "batched", "serving", "heuristic", "quant", "ablation"],
+    ap.add_argument("--only", choices=["headline", "batched", "serving", "heuristic", "quant", "ablation",
+                                       "standardize"],
                     help="run one leg only")
     ap.add_argument("--no-heuristic", action="store_true", help="skip the trial-versus-brute-force leg")
     ap.add_argument("--no-ablation", action="store_true", help="skip the ablation leg")
+    ap.add_argument("--no-standardize", action="store_true", help="skip the input standardization leg")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-steps", type=int, default=1, help="steps timed per kernel with HIP events")
@@ -824,11 +901,14 @@ def main():
         sys.exit(2)
     from paper_2209_08196_amd import synth
 
-    legs = {args.only} if args.only else {"headline", "batched", "serving", "heuristic", "quant", "ablation"}
+    legs = {args.only} if args.only else {"headline", "batched", "serving", "heuristic", "quant", "ablation",
+                                          "standardize"}
     if args.no_heuristic:
         legs.discard("heuristic")
     if args.no_ablation:
         legs.discard("ablation")
+    if args.no_standardize:
+        legs.discard("standardize")
     if args.no_batched:
         legs.discard("batched")
     if args.no_serving:
@@ -847,7 +927,7 @@ def main():
     n_before_h = len(jobs)
     if "heuristic" in legs:  # the plain stream, the dual-return stream, two whole stress streams
         jobs += [(1, 0, 0, 10), (2, 0, 0, 100), (5, 0, 0, 200), (5, 1, 0, 200)]
-    elif "quant" in legs or "ablation" in legs:
+    elif "quant" in legs or "ablation" in legs or "standardize" in legs:
         jobs += [(2, 0, 0, 100)]
     n_before_a = len(jobs)
     if "ablation" in legs:  # the dual-return stream seen by a sensor that never moves
@@ -857,7 +937,9 @@ def main():
     data = data[:n_before_a]
     extra = data[n_before_h:]
     heur_host = extra if "heuristic" in legs else None
-    dual_host = (extra[1] if "heuristic" in legs else extra[0]) if ("quant" in legs or "ablation" in legs) else None
+    dual_host = (extra[1] if "heuristic" in legs else extra[0]) \
+        if ("quant" in legs or "ablation" in legs or "standardize" in legs) else None
+    clouds = generate_clouds(dual_host) if "standardize" in legs else None
     quant_host = dual_host[0] if "quant" in legs else None
     data = data[:n_before_h]
     head_host = data[:n_head] if "headline" in legs else None
@@ -886,6 +968,8 @@ def main():
             ("stress-128x4096 stream 1 x200", heur_host[3], [1])])
     if "quant" in legs:
         result["quant"] = quant_leg(quant_host)
+    if "standardize" in legs:
+        result["standardize"] = standardize_leg(clouds, *dual_host[0].shape[1:])
     if "ablation" in legs:
         g2 = synth.stream(2, 0)
         an = [a.name for a in g2.cfg.attrs]

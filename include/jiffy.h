@@ -270,6 +270,45 @@ typedef struct {
 int jiffy_set_tuning(const jiffy_tuning* tuning);
 int jiffy_get_tuning(jiffy_tuning* tuning, uint32_t* max_wgs_per_cu);
 
+/* ---- input standardization (Sec. III-A) --------------------------------
+ * Cartesian points become the canonical range image: per point, in IEEE
+ * double with one rounding per operation (no fused multiply-adds),
+ *   r = sqrt(x*x + y*y + z*z), e = atan2(z, sqrt(x*x + y*y)),
+ *   a = atan2(y, x) (+ 2 pi when negative),
+ *   row = floor(((elev_hi - e) * height) / (elev_hi - elev_lo)),
+ *   col = floor((a * width) / (2 pi)) (width wraps to 0),
+ *   q = floor(r / range_unit + 0.5);
+ * the point is dropped (Sec. III-A: invalid and out-of-range measurements
+ * are zero) when a coordinate is not finite, row is outside [0, height) or
+ * q outside [1, 2^(8 range_bytes) - 1].  Several points in one cell: the
+ * smallest q wins, ties going to the earlier point.  The range image holds
+ * the winner's q (0 for an empty cell), each attribute image the winner's
+ * attribute value (0 for an empty cell).  atan2 is not correctly rounded:
+ * a point within a few units in the last place of a bin edge may land in
+ * either neighbour depending on the math library. */
+typedef struct {
+    uint32_t height, width;                /* rows by elevation (row 0 at elev_hi), columns by azimuth */
+    uint32_t range_bytes;                  /* 1, 2 or 4 */
+    uint32_t n_attrs;                      /* 0 .. JIFFY_MAX_ATTRS */
+    uint8_t attr_bytes[JIFFY_MAX_ATTRS];   /* 1, 2 or 4 each */
+    double elev_lo, elev_hi;               /* radians, elev_lo < elev_hi */
+    double range_unit;                     /* metres per range step (0.001: millimetres), > 0 */
+} jiffy_grid;
+
+/* n_scans scans of n_points points each (pad a shorter scan with NaN).
+ *   d_xyz:        device, [n_scans][n_points][3] float32 metres, 4-byte aligned;
+ *   d_attrs_in:   host array of n_attrs device pointers, [n_scans][n_points]
+ *                 values of attr_bytes[a] bytes each (unused when n_attrs = 0);
+ *   d_range:      device, [n_scans][height][width] of range_bytes, written;
+ *   d_attrs_out:  host array of n_attrs device pointers, [n_scans][height][width]
+ *                 of attr_bytes[a] bytes each, written.
+ * Device buffers are caller-owned and aligned to their element size; the
+ * library keeps a workspace of 8 bytes per cell of the call.  Synchronizes
+ * `stream`.  JIFFY_E_INVALID on a bad grid, pointer, alignment or more
+ * than 2^38 points or cells; JIFFY_E_DEVICE on a runtime error. */
+int jiffy_standardize(const jiffy_grid* grid, uint32_t n_scans, uint32_t n_points, const float* d_xyz,
+                      const void* const* d_attrs_in, void* d_range, void* const* d_attrs_out, hipStream_t stream);
+
 /* ---- ablated codecs (Sec. IV-H, Table IV) ------------------------------
  * Record sizes of every scan of every attribute under codecs with stages
  * left out, and of the zero bitmask under a run-length alternative to the

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjiffy.so")
-SOURCES = ["jiffy_encode.hip", "jiffy_decode.hip", "jiffy_api.hip"]
+SOURCES = ["jiffy_encode.hip", "jiffy_decode.hip", "jiffy_standardize.hip", "jiffy_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -98,6 +98,7 @@ struct DevCtx {
     DevBuf ws, ws_dec;
     DevBuf brute;     // the two staging streams of a brute-force encode
     DevBuf abl;       // jiffy_ablate: per-record sums and run-start lists
+    DevBuf std_keys;  // jiffy_standardize: one 64-bit key per cell
     HostBuf up, down, res;
     HostBuf jobs;     // its record copy list
     uint64_t enc_gen = 0;
@@ -824,6 +825,59 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
     return JIFFY_OK;
 }
 
+int jiffy_standardize(const jiffy_grid* G, uint32_t n_scans, uint32_t n_points, const float* d_xyz,
+                      const void* const* d_attrs_in, void* d_range, void* const* d_attrs_out, hipStream_t stream) {
+    static_assert(JIFFY_MAX_ATTRS <= 8, "StdArgs holds 8 attributes");
+    if (!G || G->height == 0 || G->width == 0 || G->n_attrs > JIFFY_MAX_ATTRS) return JIFFY_E_INVALID;
+    const uint32_t rb = G->range_bytes;
+    if (rb != 1 && rb != 2 && rb != 4) return JIFFY_E_INVALID;
+    if (!(G->elev_lo < G->elev_hi) || !(G->range_unit > 0.0) || !(G->elev_hi - G->elev_lo < 1e300) ||
+        !(G->range_unit < 1e300))
+        return JIFFY_E_INVALID;
+    const uint64_t cells = (uint64_t)G->height * G->width;
+    if (cells >= (1ull << 32)) return JIFFY_E_INVALID;
+    const uint64_t tot_cells = cells * n_scans, tot_pts = (uint64_t)n_points * n_scans;
+    if (tot_cells > (1ull << 38) || tot_pts > (1ull << 38)) return JIFFY_E_INVALID;
+    if (n_scans == 0) return JIFFY_OK;
+    if (!d_range || (uintptr_t)d_range % rb) return JIFFY_E_INVALID;
+    if (n_points && (!d_xyz || (uintptr_t)d_xyz % 4)) return JIFFY_E_INVALID;
+    if (G->n_attrs && (!d_attrs_out || (n_points && !d_attrs_in))) return JIFFY_E_INVALID;
+    StdArgs g;
+    memset(&g, 0, sizeof g);
+    for (uint32_t a = 0; a < G->n_attrs; ++a) {
+        const uint32_t ab = G->attr_bytes[a];
+        if (ab != 1 && ab != 2 && ab != 4) return JIFFY_E_INVALID;
+        if (!d_attrs_out[a] || (uintptr_t)d_attrs_out[a] % ab) return JIFFY_E_INVALID;
+        if (n_points && (!d_attrs_in[a] || (uintptr_t)d_attrs_in[a] % ab)) return JIFFY_E_INVALID;
+        g.attr_in[a] = n_points ? d_attrs_in[a] : nullptr;
+        g.attr_out[a] = d_attrs_out[a];
+        g.attr_bytes[a] = ab;
+    }
+    g.xyz = d_xyz;
+    g.range = d_range;
+    g.n_scans = n_scans;
+    g.n_points = n_points;
+    g.height = G->height;
+    g.width = G->width;
+    g.cells = (uint32_t)cells;
+    g.range_bytes = rb;
+    g.n_attrs = G->n_attrs;
+    g.elev_hi = G->elev_hi;
+    g.span = G->elev_hi - G->elev_lo;
+    g.unit = G->range_unit;
+    g.qmax = (double)((1ull << (8 * rb)) - 1);
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    if (grow(ctx.std_keys, 8 * tot_cells) != hipSuccess) return JIFFY_E_DEVICE;
+    g.keys = (uint64_t*)ctx.std_keys.p;
+    if (launch_standardize(g, stream) != hipSuccess) return JIFFY_E_DEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    prof_collect();
+    return JIFFY_OK;
+}
+
 int jiffy_ablate(const jiffy_layout* L, uint32_t T, const void* const* d_planes, uint64_t* h_sizes,
                  hipStream_t stream) {
     static_assert(JIFFY_MAX_ATTRS <= 8, "AblArgs holds 8 attributes");
@@ -863,6 +917,7 @@ int jiffy_ablate(const jiffy_layout* L, uint32_t T, const void* const* d_planes,
     std::vector<uint64_t> acc(8 * n);
     if (hipMemcpyAsync(acc.data(), g.acc, 64 * n, hipMemcpyDeviceToHost, stream) != hipSuccess) return JIFFY_E_DEVICE;
     if (hipStreamSynchronize(stream) != hipSuccess) return JIFFY_E_DEVICE;
+    prof_collect();
     // section = u32 N, three bytes per frame padded to 4, the frames' packed bytes
     auto section = [](uint64_t values, uint64_t packed) { return 4 + ((3 * ((values + 127) / 128) + 3) & ~3ull) + packed; };
     auto pad4 = [](uint64_t x) { return (x + 3) & ~3ull; };

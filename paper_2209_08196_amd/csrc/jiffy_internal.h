@@ -206,6 +206,21 @@ struct AblArgs {
     uint64_t* acc;           // [8 T A], zeroed by launch_ablate
     uint32_t* runs;          // npx words per workgroup of the run-length kernel
 };
+// Input standardization (Sec. III-A): points of n_scans scans, n_points
+// each, into range and attribute images of height x width cells.
+struct StdArgs {
+    const float* xyz;            // [n_scans][n_points][3]
+    const void* attr_in[8];      // [n_scans][n_points] each
+    void* range;                 // [n_scans][cells] of range_bytes
+    void* attr_out[8];           // [n_scans][cells] each
+    uint64_t* keys;              // [n_scans][cells] workspace
+    uint32_t n_scans, n_points, height, width, cells;
+    uint32_t range_bytes, n_attrs;
+    uint32_t attr_bytes[8];
+    double elev_hi, span, unit, qmax;  // span = elev_hi - elev_lo; qmax = 2^(8 range_bytes) - 1
+};
+hipError_t launch_standardize(const StdArgs& g, hipStream_t stream);
+
 // Zeroes acc, then launches the level kernel over every chunk of every
 // record and the run-length kernel with `run_groups` workgroups.
 hipError_t launch_ablate(const AblArgs& a, uint32_t run_groups, hipStream_t stream);

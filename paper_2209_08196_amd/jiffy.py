@@ -27,7 +27,7 @@ SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_encode_noalloc", "jiffy_
            "jiffy_step_workspace_bytes", "jiffy_step_create", "jiffy_step_submit", "jiffy_step_finish",
            "jiffy_step_destroy",
            "jiffy_batch_create", "jiffy_batch_run", "jiffy_batch_destroy",
-           "jiffy_set_tuning", "jiffy_get_tuning", "jiffy_ablate",
+           "jiffy_set_tuning", "jiffy_get_tuning", "jiffy_ablate", "jiffy_standardize",
            "jiffy_profile_enable", "jiffy_profile_read")
 
 
@@ -47,6 +47,19 @@ class Options(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("fused", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [
+        ("height", ctypes.c_uint32),
+        ("width", ctypes.c_uint32),
+        ("range_bytes", ctypes.c_uint32),
+        ("n_attrs", ctypes.c_uint32),
+        ("attr_bytes", ctypes.c_uint8 * MAX_ATTRS),
+        ("elev_lo", ctypes.c_double),
+        ("elev_hi", ctypes.c_double),
+        ("range_unit", ctypes.c_double),
+    ]
 
 
 class JiffyError(RuntimeError):
@@ -117,6 +130,8 @@ def lib():
         L.jiffy_get_tuning.argtypes = [ctypes.POINTER(Tuning), ctypes.POINTER(u32)]
         L.jiffy_ablate.restype = ctypes.c_int
         L.jiffy_ablate.argtypes = [ctypes.POINTER(Layout), u32, vp, vp, vp]
+        L.jiffy_standardize.restype = ctypes.c_int
+        L.jiffy_standardize.argtypes = [ctypes.POINTER(Grid), u32, u32, vp, vp, vp, vp, vp]
         L.jiffy_profile_enable.restype = ctypes.c_int
         L.jiffy_profile_enable.argtypes = [ctypes.c_int]
         L.jiffy_profile_read.restype = ctypes.c_int
@@ -295,6 +310,59 @@ def ablate(planes, precisions=None, stream=None):
     if rc:
         raise JiffyError(rc, "jiffy_ablate")
     return out[:T]
+
+
+_WIDTH_DTYPE = None
+
+
+def standardize(xyz, height, width, elev_lo, elev_hi, range_unit=0.001, range_bytes=4, attrs=(), outs=None,
+                stream=None):
+    """Cartesian points to range and attribute images (jiffy_standardize).
+    xyz: contiguous device float32 tensor [S, N, 3] (or [N, 3]: one scan);
+    attrs: device tensors [S, N] (or [N]) of 1-, 2- or 4-byte integers.
+    Returns (range tensor [S, H, W], list of attribute tensors [S, H, W]);
+    16- and 32-bit images are int16 / int32 storage of unsigned values."""
+    import torch
+    global _WIDTH_DTYPE
+    if _WIDTH_DTYPE is None:
+        _WIDTH_DTYPE = {1: torch.uint8, 2: torch.int16, 4: torch.int32}
+    if not isinstance(xyz, torch.Tensor) or xyz.device.type != "cuda" or xyz.dtype != torch.float32 \
+            or not xyz.is_contiguous() or xyz.dim() not in (2, 3) or xyz.shape[-1] != 3:
+        raise ValueError("xyz: must be a contiguous device float32 tensor [S, N, 3] or [N, 3]")
+    single = xyz.dim() == 2
+    S, N = (1, xyz.shape[0]) if single else (xyz.shape[0], xyz.shape[1])
+    if len(attrs) > MAX_ATTRS:
+        raise ValueError(f"at most {MAX_ATTRS} attributes")
+    for a, t in enumerate(attrs):
+        _check_tensor(t, S * N, t.element_size() if isinstance(t, torch.Tensor) else 0, f"attribute {a}")
+    if range_bytes not in (1, 2, 4):
+        raise ValueError("range_bytes must be 1, 2 or 4")
+    g = Grid()
+    g.height, g.width, g.range_bytes, g.n_attrs = height, width, range_bytes, len(attrs)
+    for a, t in enumerate(attrs):
+        g.attr_bytes[a] = t.element_size()
+    g.elev_lo, g.elev_hi, g.range_unit = elev_lo, elev_hi, range_unit
+    if outs is None:
+        rng = torch.empty((S, height, width), dtype=_WIDTH_DTYPE[range_bytes], device=xyz.device)
+        aout = [torch.empty((S, height, width), dtype=_WIDTH_DTYPE[t.element_size()], device=xyz.device)
+                for t in attrs]
+    else:
+        rng, aout = outs[0], list(outs[1])
+        _check_tensor(rng, S * height * width, range_bytes, "range image")
+        if len(aout) != len(attrs):
+            raise ValueError("one output image per attribute is needed")
+        for a, (o, t) in enumerate(zip(aout, attrs)):
+            _check_tensor(o, S * height * width, t.element_size(), f"attribute image {a}")
+    ain = (ctypes.c_void_p * max(1, len(attrs)))(*[t.data_ptr() for t in attrs])
+    aon = (ctypes.c_void_p * max(1, len(attrs)))(*[o.data_ptr() for o in aout])
+    rc = lib().jiffy_standardize(ctypes.byref(g), S, N, ctypes.c_void_p(xyz.data_ptr()),
+                                 ctypes.cast(ain, ctypes.c_void_p), ctypes.c_void_p(rng.data_ptr()),
+                                 ctypes.cast(aon, ctypes.c_void_p), _stream_handle(stream))
+    if rc:
+        raise JiffyError(rc, "jiffy_standardize")
+    if single:
+        return rng[0], [o[0] for o in aout]
+    return rng, aout
 
 
 def peek(data: bytes):
