@@ -574,45 +574,73 @@ hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const D
 }
 
 // ---------------------------------------------------------------------------
-// Mask chain over time, one thread per 32-bit half of a mask word of one
-// attribute; scans are taken kMaskAhead at a time so that their loads
-// overlap (the chain is the only serial part).
+// Mask chain over time: a P-scan's mask is its content XOR the previous
+// scan's mask, an I-scan's mask is its content.  A workgroup takes 64
+// 32-bit halves of the mask words of one attribute over every scan; each of
+// its waves takes kMaskAhead consecutive scans (their loads issued together)
+// and runs the chain from a carry of 0, keeping the chunk's last mask and
+// whether the chunk holds an I-scan.  The chain is linear in the carry
+// (XOR), so a chunk without an I-scan ends at its last mask XOR the carry
+// into it, and one with an I-scan does not depend on the carry: each wave
+// folds the summaries of the chunks before it to get its own carry, then
+// writes its scans' valid words.  Rounds of (waves x kMaskAhead) scans
+// follow one another with the carry passed on.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t* item_words(const DecPlan& plan, uint32_t r, uint32_t off) {
     return (uint64_t*)(plan.ws + plan.item_stride * r + off);
 }
 
 constexpr int kMaskAhead = 32;
+constexpr uint32_t kMaskWaves = 16;  // waves per workgroup of k_dec_mask, at most
 
-__global__ __launch_bounds__(64) void k_dec_mask(DecPlan plan) {
+__global__ __launch_bounds__(kMaskWaves * 64) void k_dec_mask(DecPlan plan) {
     if (*plan.err) return;
-    const uint32_t a = blockIdx.y;
-    const uint32_t h = blockIdx.x * 64 + threadIdx.x;  // half-word index
-    if (h >= 2 * plan.nwords) return;
-    const uint32_t tm = (uint32_t)(tail_mask(h >> 1, plan.nwords, plan.npx) >> (32 * (h & 1)));
+    __shared__ uint32_t s_end[kMaskWaves][64], s_reset[kMaskWaves][64];
+    const uint32_t a = blockIdx.y, l = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const uint32_t h = blockIdx.x * 64 + l;  // half-word index
+    const bool live = h < 2 * plan.nwords;
+    const uint32_t tm = live ? (uint32_t)(tail_mask(h >> 1, plan.nwords, plan.npx) >> (32 * (h & 1))) : 0u;
     const uint32_t A = plan.n_attrs, T = plan.n_scans;
-    uint32_t mprev = 0;
+    uint32_t carry = 0;  // the mask of the scan before this round
     bool bad = false;
-    for (uint32_t t0 = 0; t0 < T; t0 += kMaskAhead) {
+    for (uint32_t t_round = 0; t_round < T; t_round += nw * kMaskAhead) {
+        const uint32_t t0 = t_round + w * kMaskAhead;
         // the modes are loaded with the words, and every load is issued (past
         // the last scan it reads the last scan again, unused): nothing waits alone
         uint32_t c[kMaskAhead], md[kMaskAhead];
 #pragma unroll
         for (int k = 0; k < kMaskAhead; ++k) {
             const uint32_t t = min(t0 + k, T - 1);
-            c[k] = ((const uint32_t*)item_words(plan, t * A + a, plan.off_cw))[h];
+            c[k] = live ? ((const uint32_t*)item_words(plan, t * A + a, plan.off_cw))[h] : 0u;
             md[k] = plan.modes[t * A + a];
         }
+        uint32_t loc = 0, reset = 0;
+#pragma unroll
+        for (int k = 0; k < kMaskAhead; ++k) {
+            if (t0 + k < T) {
+                loc = md[k] ? (c[k] ^ loc) : c[k];
+                reset |= md[k] ? 0u : 1u;
+            }
+        }
+        s_end[w][l] = loc;
+        s_reset[w][l] = reset;
+        __syncthreads();
+        uint32_t prev = carry;
+        for (uint32_t v = 0; v < w; ++v) prev = s_reset[v][l] ? s_end[v][l] : (s_end[v][l] ^ prev);
+        uint32_t next = carry;  // the carry into the next round: the last chunk's true end
+        for (uint32_t v = 0; v < nw; ++v) next = s_reset[v][l] ? s_end[v][l] : (s_end[v][l] ^ next);
 #pragma unroll
         for (int k = 0; k < kMaskAhead; ++k) {
             const uint32_t t = t0 + k;
-            if (t < T) {
-                const uint32_t m = md[k] ? (c[k] ^ mprev) : c[k];
+            if (t < T && live) {
+                const uint32_t m = md[k] ? (c[k] ^ prev) : c[k];
                 bad |= (m & ~tm) != 0;  // mask bits past the scan
                 ((uint32_t*)item_words(plan, t * A + a, plan.off_vw))[h] = ~m & tm;
-                mprev = m;
+                prev = m;
             }
         }
+        carry = next;
+        __syncthreads();  // the summaries are free for the next round
     }
     if (bad) atomicOr(plan.err, kErrCorrupt);
 }
@@ -1074,7 +1102,9 @@ hipError_t launch_dec_report(const void* dev_err, void* host, uint32_t n, hipStr
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     if (plan.n_items == 0) return hipSuccess;
     JIFFY_LAUNCH("k_dec_parse", k_dec_parse, dim3(plan.n_items, plan.pwin + 1), dim3(256), stream, plan);
-    JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(2 * plan.nwords, 64), plan.n_attrs), dim3(64), stream, plan);
+    const uint32_t mask_waves = min(kMaskWaves, div_up(plan.n_scans, (uint32_t)kMaskAhead));
+    JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(2 * plan.nwords, 64), plan.n_attrs), dim3(64 * mask_waves),
+                 stream, plan);
     JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
     if (plan.n_wide)
         JIFFY_LAUNCH("k_dec_tiles_w32", k_dec_tiles<uint32_t>, dim3(plan.n_wide * plan.nft), dim3(kDecThreads),

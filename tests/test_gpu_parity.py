@@ -231,3 +231,25 @@ def test_large_masks_split_blocks(J):
         banner("decode large mask", name)
         out = J.decode(torch.from_numpy(np.frombuffer(s_ref, np.uint8).copy()).cuda())[0]
         assert np.array_equal(to_host(out, 1), ref), name
+
+
+@pytest.mark.parametrize("T", [33, 65, 600])
+def test_long_mask_chains(J, T):
+    """P-scan mask chains across many scans (the decoder's mask pass splits
+    time into chunks of 32 scans and rounds of 512): forced P-scans, and a
+    mix where static stretches (P) alternate with fresh noise (I)."""
+    import torch
+    rng = np.random.default_rng(T)
+    base = synth.random_scans(rng, 1, 4, 40, np.uint16, 0.4, scale=500)
+    x = np.repeat(base, T, axis=0)
+    flips = rng.random(x.shape) < 0.05  # zeros appear and disappear: every XOR mask differs
+    x = np.where(flips, np.where(x == 0, 7, 0), x).astype(np.uint16)
+    noisy = rng.random(T) < 0.1
+    x[noisy] = synth.random_scans(rng, int(noisy.sum()), 4, 40, np.uint16, 0.4, scale=500)
+    for mode in (2, 0):
+        banner("long mask chain", T, "mode", mode)
+        s_ref, m = oracle.encode([x], [1], mode=mode)
+        if mode == 2:
+            assert m[1:].all()
+        out = J.decode(torch.from_numpy(np.frombuffer(s_ref, np.uint8).copy()).cuda())[0]
+        assert np.array_equal(to_host(out, 2), x), (T, mode)
