@@ -716,7 +716,8 @@ int orc_decode(const uint8_t* in, size_t len, void* const* planes_out) {
     if (rc) return rc;
     rc = orc_peek(in, len, &L, &T);
     if (rc) return rc;
-    if (T_hdr) p += 4 * (size_t)T_hdr * L.n_attrs; /* skip the length table */
+    const size_t hdr_end = p;
+    if (T_hdr) p += 4 * (size_t)T_hdr * L.n_attrs; /* the length table, checked record by record below */
     unsigned A = L.n_attrs;
     size_t npx = (size_t)L.height * L.width, nm = mask_bytes(npx);
     uint64_t** Qp = (uint64_t**)calloc(A, sizeof(uint64_t*));
@@ -737,6 +738,8 @@ int orc_decode(const uint8_t* in, size_t len, void* const* planes_out) {
             if (avail < 12) { rc = ORC_E_CORRUPT; break; }
             uint32_t rl = rd_u32(r);
             if (rl < 12 || rl % 4 || rl > avail) { rc = ORC_E_CORRUPT; break; }
+            /* the length table repeats every record's own length */
+            if (T_hdr && rd_u32(in + hdr_end + 4 * ((size_t)t * A + a)) != rl) { rc = ORC_E_CORRUPT; break; }
             unsigned pmode = r[4], attr = r[5];
             if (pmode > 1 || attr != a || rd_u16(r + 6) != 0) { rc = ORC_E_CORRUPT; break; }
             if (pmode && t == 0) { rc = ORC_E_CORRUPT; break; } /* nothing to predict from */

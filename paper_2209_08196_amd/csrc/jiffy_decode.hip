@@ -98,7 +98,7 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
     if (tid == 0) {
         // the window's ticket, and with it (no wait in between) the record
         // header and the frame header through its content size,
-        // record bytes 4..27, in one round of word loads (a record is 4-byte
+        // record bytes 0..27, in one round of word loads (a record is 4-byte
         // aligned, at least 12 bytes and a whole number of words long; a word
         // past its end reads its last word again, and every byte taken from
         // one is ruled out by the length checks first)
@@ -107,14 +107,15 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
         const uint32_t lw = L / 4 - 1;
         uint32_t hw[7];
 #pragma unroll
-        for (int k = 1; k < 7; ++k) hw[k] = rw[min((uint32_t)k, lw)];
+        for (int k = 0; k < 7; ++k) hw[k] = rw[min((uint32_t)k, lw)];
         s_win = win;
         auto byte = [&](uint32_t i) -> uint32_t { return (hw[i >> 2] >> (8 * (i & 3))) & 0xFFu; };
         uint32_t err = 0;
         const uint32_t mode = byte(4), attr = byte(5);
         const uint32_t resv = hw[1] >> 16;
         const uint32_t flen = hw[2];
-        if (mode > 1 || attr != it.attr || resv != 0 || flen > L - 12) err = 1;
+        // the record's own length must repeat the length the index gave it
+        if (hw[0] != L || mode > 1 || attr != it.attr || resv != 0 || flen > L - 12) err = 1;
         if (mode == 1 && it.t == 0) err = 1;  // nothing to predict from
         uint32_t pos = 0;
         if (!err) {  // the frame starts at record byte 12
@@ -438,7 +439,10 @@ __device__ void parse_sections(const DecPlan& plan, uint32_t r, const DecItem& i
     // unused), summed in order, then one three-value scan per pass
     constexpr uint32_t kSecPer = 8, kSecPass = 256 * kSecPer;
     __shared__ uint32_t s_scan[3 * (256 / kWave + 1)];
+    // offsets within the record are 32-bit; the total is kept in 64 bits so
+    // that widths and counts claiming more than 4 GiB cannot wrap past the check
     uint32_t cp = 0, cn = 0, ch = 0, bad = 0;
+    uint64_t sum = 0;
     for (uint32_t j0 = 0; j0 < nb; j0 += kSecPass) {
         const uint32_t jb = j0 + tid * kSecPer;
         uint32_t fb[kSecPer], fn[kSecPer], fB[kSecPer];
@@ -476,6 +480,7 @@ __device__ void parse_sections(const DecPlan& plan, uint32_t r, const DecItem& i
             oh += (n * (B - b) + 7) / 8;
         }
         cp += tot[0]; cn += tot[1]; ch += tot[2];
+        sum += (uint64_t)tot[0] + tot[1] + tot[2];
     }
     if (bad) atomicOr(&s_err, 1u);
     __syncthreads();
@@ -483,7 +488,7 @@ __device__ void parse_sections(const DecPlan& plan, uint32_t r, const DecItem& i
         const uint32_t pay0 = sec + align4(4 + 3 * nb);
         // the record must end exactly after the padded sections
         uint32_t err = s_err;
-        if ((uint64_t)pay0 + align4(cp + cn + ch) != L) err = 1;
+        if (pay0 + ((sum + 3) & ~3ull) != L) err = 1;
         DecRes& rs = plan.res[r];
         rs.N = N;
         rs.nb = nb;
