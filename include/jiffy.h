@@ -222,9 +222,11 @@ void jiffy_batch_destroy(jiffy_batch* b);
  * nothing here takes the per-device lock. */
 typedef struct jiffy_step jiffy_step;
 
-/* Device bytes a step context of these limits holds (its workspace). */
+/* Device bytes a step context of these limits holds (its workspace); 0 when
+ * a limit is 0 or above its maximum (2^24 records, 2^40 samples). */
 size_t jiffy_step_workspace_bytes(uint32_t max_records, uint64_t max_samples);
 
+/* JIFFY_E_INVALID for a limit of 0 or above its maximum (as above). */
 int jiffy_step_create(uint32_t max_records, uint64_t max_samples, jiffy_step** out);
 
 /* d_planes[i][a]: stream i's new scan of attribute a (H*W samples).

@@ -1617,6 +1617,9 @@ namespace {
 struct StepBound {
     size_t dev, up, res;
 };
+// Limits of a step context: with them every size below fits in 64 bits.
+constexpr uint64_t kStepMaxRecords = 1ull << 24, kStepMaxSamples = 1ull << 40;
+
 StepBound step_bound(uint64_t R, uint64_t S) {
     const uint64_t nb = S / kFrame + R, nft = S / kFTile + R, nm = S / 8 + R;
     StepBound b;
@@ -1647,12 +1650,15 @@ struct jiffy_step {
 extern "C" {
 
 size_t jiffy_step_workspace_bytes(uint32_t max_records, uint64_t max_samples) {
-    if (max_records == 0 || max_samples == 0) return 0;
+    if (max_records == 0 || max_samples == 0 || max_records > kStepMaxRecords || max_samples > kStepMaxSamples)
+        return 0;
     return step_bound(max_records, max_samples).dev;
 }
 
 int jiffy_step_create(uint32_t max_records, uint64_t max_samples, jiffy_step** out) {
-    if (!out || max_records == 0 || max_samples == 0 || max_records > (1u << 24)) return JIFFY_E_INVALID;
+    if (!out || max_records == 0 || max_samples == 0 || max_records > kStepMaxRecords ||
+        max_samples > kStepMaxSamples)
+        return JIFFY_E_INVALID;
     jiffy_step* st = new (std::nothrow) jiffy_step();
     if (!st) return JIFFY_E_INVALID;
     if (current_device(&st->device)) { delete st; return JIFFY_E_DEVICE; }
