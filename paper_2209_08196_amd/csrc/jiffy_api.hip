@@ -1069,7 +1069,7 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
 
     const uint32_t n = T * A;
     const uint32_t npx = L.height * L.width, nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame);
-    const uint32_t nft = div_up(npx, kFTile);
+    const uint32_t nvt = dec_tile_slots(npx);
     size_t off = 0;
     const size_t o_res = off; off = al(off + sizeof(DecRes) * n);
     const size_t o_roff = off; off = al(off + (roff ? 0 : sizeof(uint64_t) * n));
@@ -1078,8 +1078,8 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     const size_t o_list = off; off = al(off + sizeof(uint32_t) * n);
     const size_t up_end = off;
     const uint32_t pwin = div_up(frame_bound(div_up(npx, 8)), kParseWin);
-    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(4ull * (nft + 1)) + al(8ull * nft) +
-                            al(sizeof(DecTile) * nft) + al(4) + al(8ull * (pwin + 1) + 4);
+    const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(8ull * (nvt + 1)) + al(8ull * nvt) +
+                            al(sizeof(DecTile) * nvt) + al(4) + al(8ull * (pwin + 1) + 4);
     const size_t o_modes = off; off = al(off + n);
     const size_t o_data = off;
     off += per_item * n;
@@ -1105,12 +1105,12 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
             it.blkinfo = (uint32_t*)base;
             it.blkoffs = it.blkinfo + maxnb;
             base += al(4ull * maxnb * 4);
-            it.tbase = (uint32_t*)base;
-            base += al(4ull * (nft + 1));
+            it.tstart = (uint2*)base;
+            base += al(8ull * (nvt + 1));
             it.status = (uint64_t*)base;
-            base += al(8ull * nft);
+            base += al(8ull * nvt);
             it.tdesc = (DecTile*)base;
-            base += al(sizeof(DecTile) * nft);
+            base += al(sizeof(DecTile) * nvt);
             it.tctr = (uint32_t*)base;
             base += al(4);
             it.npx = npx;
@@ -1125,22 +1125,27 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
             if (it.P > 1) need_temporal = true;
         }
     }
-    // records with 32-bit samples first (their tiles use 32-bit LDS rows), then the rest
+    // records with 32-bit samples first (their tiles use 32-bit LDS rows), then 16-bit, then 8-bit ones
     uint32_t* hlist = (uint32_t*)(up + (o_list - o_err));
-    uint32_t n_wide = 0;
-    for (uint32_t r = 0; r < n; ++r)
-        if (hit[r].wb == 4) hlist[n_wide++] = r;
-    for (uint32_t r = 0, k = n_wide; r < n; ++r)
-        if (hit[r].wb != 4) hlist[k++] = r;
+    uint32_t k_list = 0;
+    for (uint32_t w : {4u, 2u, 1u})
+        for (uint32_t r = 0; r < n; ++r)
+            if (hit[r].wb == w) hlist[k_list++] = r;
+    uint32_t n_wide = 0, n_w16 = 0;
+    for (uint32_t r = 0; r < n; ++r) {
+        n_wide += hit[r].wb == 4;
+        n_w16 += hit[r].wb == 2;
+    }
     DecPlan plan;
     memset(&plan, 0, sizeof plan);
     plan.items = (DecItem*)(dev + o_items);
     plan.res = (DecRes*)(dev + o_res);
     plan.err = (uint32_t*)(dev + o_err);
     plan.err2 = plan.err + 1;
-    plan.nft = nft;
+    plan.nvt = nvt;
     plan.rec_list = (const uint32_t*)(dev + o_list);
     plan.n_wide = n_wide;
+    plan.n_w16 = n_w16;
     plan.n_items = n;
     plan.n_scans = T;
     plan.n_attrs = A;
@@ -1151,8 +1156,8 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     plan.ws = dev + o_data;
     plan.item_stride = per_item;
     plan.pwin = pwin;
-    plan.off_pstate = (uint32_t)(al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(4ull * (nft + 1)) + al(8ull * nft) +
-                                 al(sizeof(DecTile) * nft) + al(4));
+    plan.off_pstate = (uint32_t)(al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(8ull * (nvt + 1)) + al(8ull * nvt) +
+                                 al(sizeof(DecTile) * nvt) + al(4));
     plan.off_cw = 0;
     plan.off_vw = (uint32_t)al(8ull * nwords);
     for (uint32_t a = 0; a < A; ++a) {

@@ -654,66 +654,84 @@ constexpr uint32_t kDecThreads = 320;                 // 80 quads: enough for th
 constexpr uint32_t kFrameMaxWords = 160;              // a frame's packed bytes are at most 640
 
 // ---------------------------------------------------------------------------
-// Running count of valid samples: N must match the section header; the
-// count before every kFTile-pixel tile.  Then each tile's descriptor: its
-// values [kb, ke) and the word ranges of the record that hold its frames'
-// payloads, exception positions and exception high parts.  The tiles'
-// look-back states are cleared here, before k_dec_tiles.
+// Running count of valid samples (N must match the section header) and the
+// record's decode tiles.  One round per kDecBlockPx-pixel block (1024 mask
+// words, one per thread): the block's first pixel starts a tile, and so does
+// every valid pixel whose rank is a positive multiple of kDecTileVals inside
+// the block (the word that holds that rank finds its bit); the tiles are
+// numbered in pixel order by counting, per block, one tile plus its rank
+// boundaries.  Then each tile's descriptor (values and pixels), with the
+// check that its frames' packed bytes are plausible.  The tiles' look-back
+// states and the record's ticket are cleared here, before k_dec_tiles.
 // ---------------------------------------------------------------------------
+static_assert(kDecBlockPx == 64 * 1024, "a block is one mask word per thread of k_dec_scan");
+
 __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
     if (*plan.err) return;
     const uint32_t r = blockIdx.x;
     const DecItem it = plan.items[r];
     const DecRes rs = plan.res[r];
     __shared__ uint32_t scratch[20];
-    constexpr uint32_t kTW = kFTile / 64;  // words per tile
-    for (uint32_t lt = threadIdx.x; lt < plan.nft; lt += 1024) it.status[lt] = 0ull;
+    for (uint32_t lt = threadIdx.x; lt < plan.nvt; lt += 1024) it.status[lt] = 0ull;
     if (threadIdx.x == 0) *it.tctr = 0u;
-    uint32_t carry = 0;
+    uint32_t carry = 0, tiles = 0;  // valid samples and tiles before the block
     for (uint32_t w0 = 0; w0 < it.nwords; w0 += 1024) {
         const uint32_t w = w0 + threadIdx.x;
         const uint64_t v = w < it.nwords ? it.vw[w] : 0ull;
+        const uint32_t c = (uint32_t)__popcll(v);
         uint32_t total;
-        const uint32_t pre = block_excl_scan<1024>(__popcll(v), scratch, &total) + carry;
-        if (w < it.nwords && w % kTW == 0) it.tbase[w / kTW] = pre;
+        const uint32_t pre = block_excl_scan<1024>(c, scratch, &total) + carry;
+        const uint32_t k0 = carry / kDecTileVals;
+        if (threadIdx.x == 0) it.tstart[tiles] = make_uint2(64u * w0, carry);
+        if (c) {  // a rank boundary in this word: at most one, a word holds 64 values
+            const uint32_t k = (pre + c - 1) / kDecTileVals, R = k * kDecTileVals;
+            if (k > k0 && R >= pre) it.tstart[tiles + (k - k0)] = make_uint2(64u * w + select_bit(v, R - pre), R);
+        }
+        tiles += 1 + (total ? (carry + total - 1) / kDecTileVals - k0 : 0u);
         carry += total;
     }
     if (threadIdx.x == 0) {
-        it.tbase[plan.nft] = carry;
-        if (carry != rs.N) atomicOr(plan.err, kErrCorrupt);
+        it.tstart[tiles] = make_uint2(it.npx, carry);
+        plan.res[r].ntiles = tiles;
+        if (carry != rs.N || tiles > plan.nvt) atomicOr(plan.err, kErrCorrupt);
     }
-    __syncthreads();
-    if (carry != rs.N) return;
+    __syncthreads();  // every tile start stored
+    if (carry != rs.N || tiles > plan.nvt) return;
     const uint32_t sec[3] = {rs.pay_off, rs.pos_off, rs.high_off};
     const uint32_t send[3] = {rs.pos_off - rs.pay_off, rs.high_off - rs.pos_off, rs.high_end - rs.high_off};
     bool bad = false;
-    for (uint32_t lt = threadIdx.x; lt < plan.nft; lt += 1024) {
-        const uint32_t kb = it.tbase[lt], ke = it.tbase[lt + 1];
-        const uint32_t jf = kb >> 7, j1 = ke > kb ? ((ke - 1) >> 7) + 1 : jf;  // frames [jf, j1)
+    for (uint32_t lt = threadIdx.x; lt < tiles; lt += 1024) {
+        const uint2 a = it.tstart[lt], b = it.tstart[lt + 1];
         DecTile d;
-        d.kb = kb;
-        d.ke = ke;
+        d.ps = a.x;
+        d.kb = a.y;
+        d.pe = b.x;
+        d.ke = b.y;
+        const uint32_t jf = d.kb >> 7, j1 = d.ke > d.kb ? ((d.ke - 1) >> 7) + 1 : jf;  // frames [jf, j1)
         uint32_t words = 0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const uint32_t a = jf < rs.nb ? it.blkoffs[3 * jf + q] : send[q];
-            const uint32_t e = j1 < rs.nb ? it.blkoffs[3 * j1 + q] : send[q];
-            d.w0[q] = (sec[q] + a) >> 2;
-            d.nw[q] = j1 > jf ? ((sec[q] + e + 3) >> 2) - d.w0[q] : 0u;
-            words += d.nw[q];
+            const uint32_t o0 = jf < rs.nb ? it.blkoffs[3 * jf + q] : send[q];
+            const uint32_t o1 = j1 < rs.nb ? it.blkoffs[3 * j1 + q] : send[q];
+            words += j1 > jf ? ((sec[q] + o1 + 3) >> 2) - ((sec[q] + o0) >> 2) : 0u;
         }
-        bad |= words > (j1 - jf) * kFrameMaxWords + 6;  // more than 640 bytes per frame: not a valid frame set
+        // more than 640 bytes per frame, or a tile of no pixels or too many: not a valid tile
+        bad |= words > (j1 - jf) * kFrameMaxWords + 6 || d.pe <= d.ps || d.pe - d.ps > kDecBlockPx ||
+               d.ke - d.kb > kDecTileVals;
         it.tdesc[lt] = d;
     }
     if (bad) atomicOr(plan.err, kErrCorrupt);
 }
 
 // ---------------------------------------------------------------------------
-// Frame unpacking and the running sum, per kFTile-pixel tile (Sec. II,
-// Sec. III-C reversed).  One workgroup per tile of one record, in ticket
-// order:
-//   1. the tile's pixels' valid bits and the frames' widths and offsets
-//      are loaded;
+// Frame unpacking and the running sum, per decode tile (Sec. II, Sec. III-C
+// reversed): at most kDecTileVals values and kDecBlockPx pixels of one
+// record.  Workgroups are laid out tile-major (workgroup i serves record
+// i mod n); the tile within the record is taken in arrival order (a ticket),
+// so every tile a workgroup waits for has started, and workgroups past the
+// record's tile count leave at once.
+//   1. the tile's pixels' valid bits (32 pixels per chunk, a run of chunks
+//      per thread) and the frames' widths and offsets are loaded;
 //   2. four lanes per frame unpack the low bits (lane q: values 32q..32q+31,
 //      its b payload words loaded straight from the record into registers)
 //      into the frame's LDS row, patch the exceptions' high parts in, and
@@ -723,7 +741,8 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
 //      look-back: each tile publishes its own sum, then the running sum
 //      through it);
 //   4. the tile's pixels are written: the k-th valid pixel gets value k,
-//      the others zero.
+//      the others zero; the chunks at the tile's two ends write only the
+//      tile's own pixels.
 // For a P-scan the values are differences to the previous scan (added by
 // k_dec_temporal); for P > 1 they are quantized (restored there too).
 // ---------------------------------------------------------------------------
@@ -882,10 +901,12 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
 // Value k sits at row element tword(k, jf) = k + kPad (k >> 5) - kElems jf (a
 // row holds 128 values and kPad pad elements per 32).  Every pixel's read is
 // issued, without a branch (a pixel without a value reads the next value's
-// element, clamped to the rows), and its zero selected afterwards.
+// element, clamped to the rows), and its zero selected afterwards.  `own`
+// marks the chunk's pixels that belong to the tile: a whole chunk is
+// written with vector stores, a chunk at the tile's ends pixel by pixel.
 template <int WB, class R>
-__device__ __forceinline__ void dec_tile_scatter(const DecItem& it, uint32_t p0, uint32_t bits, uint32_t k,
-                                                 uint32_t jf, const DecTileLds<R>& L) {
+__device__ __forceinline__ void dec_tile_scatter(const DecItem& it, uint32_t p0, uint32_t bits, uint32_t own,
+                                                 uint32_t k, uint32_t jf, const DecTileLds<R>& L) {
     static_assert(RowT<R>::kElems == 128 + 4 * RowT<R>::kPad, "a row is 128 values and four pads");
     constexpr uint32_t kLast = kTileFrames * RowT<R>::kElems - 1;
     const uint32_t rbase = RowT<R>::kElems * jf;
@@ -897,19 +918,27 @@ __device__ __forceinline__ void dec_tile_scatter(const DecItem& it, uint32_t p0,
         v[i] = on ? x : 0u;
         k += on;
     }
-    store16<WB>(it.out, p0, it.npx, it.aligned16, v);
-    if (p0 + 16 < it.npx) store16<WB>(it.out, p0 + 16, it.npx, it.aligned16, v + 16);
+    if (own == ~0u) {
+        store16<WB>(it.out, p0, it.npx, it.aligned16, v);
+        store16<WB>(it.out, p0 + 16, it.npx, it.aligned16, v + 16);
+    } else {
+        using T = typename SampleT<WB>::T;
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if ((own >> i) & 1u) ((T*)it.out)[p0 + i] = (T)v[i];
+    }
 }
 
-// R: the row element; the workgroups take the records rec_list[first ..]
-template <class R>
-__global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_t first) {
+constexpr uint32_t kDecChunks = (kDecBlockPx / 32 + 1 + kDecThreads - 1) / kDecThreads;  // chunks per thread, at most
+
+// R: the row element; the workgroups serve the n records rec_list[first ..]
+// (one instantiation per sample width WB: a single store path each)
+template <class R, int WB>
+__global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_t first, uint32_t n) {
     if (*plan.err) return;  // set before this launch; this kernel reports through err2
     __shared__ DecTileLds<R> L;
     const uint32_t tid = threadIdx.x;
-    // the record is fixed by the workgroup index; the tile within it is taken
-    // in arrival order, so every tile a workgroup waits for has started
-    const uint32_t r = plan.rec_list[first + blockIdx.x / plan.nft];
+    const uint32_t r = plan.rec_list[first + blockIdx.x % n];
     const DecItem it = plan.items[r];
     if (tid == 0) {
         L.ticket = atomicAdd(it.tctr, 1u);
@@ -918,16 +947,33 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
     __syncthreads();
     const uint32_t lt = L.ticket;
     const DecRes rs = plan.res[r];
+    if (lt >= rs.ntiles) return;  // more workgroups than the record has tiles
     const DecTile D = it.tdesc[lt];
     const uint32_t m = low_mask32(it.bits);
     const uint32_t kb = D.kb, ke = D.ke;
     const uint32_t jf = kb >> 7;
     const uint32_t nf = ke > kb ? ((ke - 1) >> 7) - jf + 1 : 0u;  // frames the tile's values lie in
-    // 1. everything the tile reads, issued together: its pixels' valid bits,
-    // the frames' metadata and packed bytes
-    const uint32_t p0 = lt * kFTile + tid * 32;
-    const bool scat = tid < kFTile / 32 && p0 < it.npx;
-    const uint32_t pbits = scat ? (uint32_t)(it.vw[p0 >> 6] >> (32 * ((p0 >> 5) & 1))) : 0u;
+    // 1. everything the tile reads, issued together: its pixels' valid bits
+    // (chunks of 32 pixels from the one holding its first pixel, a run of
+    // consecutive chunks per thread, masked to the tile), the frames' metadata
+    const uint32_t cs = D.ps & ~31u, nch = div_up(D.pe - cs, 32u), per = div_up(nch, kDecThreads);
+    // the tile's own pixels in chunk c
+    auto own_bits = [&](uint32_t p) -> uint32_t {
+        uint32_t own = ~0u;
+        if (p < D.ps) own &= ~0u << (D.ps - p);
+        if (D.pe - p < 32u) own &= (1u << (D.pe - p)) - 1u;
+        return own;
+    };
+    uint32_t pb[kDecChunks];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kDecChunks; ++u) {
+        const uint32_t c = tid * per + u, p = cs + 32u * c;
+        uint32_t bits = 0;
+        if (u < per && c < nch) bits = (uint32_t)(it.vw[p >> 6] >> (32 * ((p >> 5) & 1))) & own_bits(p);
+        pb[u] = bits;
+        cnt += __popc(bits);
+    }
     if (tid <= nf && nf) {
         const uint32_t j = jf + tid;
         if (j < rs.nb) {
@@ -968,11 +1014,15 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
     }
     // 4. the tile's pixels: the k-th valid pixel gets value k
     uint32_t total;
-    const uint32_t k = kb + block_excl_scan<kDecThreads>(__popc(pbits), L.scratch, &total);  // also a barrier
-    if (!scat) return;
-    if (sizeof(R) == 4) dec_tile_scatter<4, R>(it, p0, pbits, k, jf, L);
-    else if (it.wb == 2) dec_tile_scatter<2, R>(it, p0, pbits, k, jf, L);
-    else dec_tile_scatter<1, R>(it, p0, pbits, k, jf, L);
+    uint32_t k = kb + block_excl_scan<kDecThreads>(cnt, L.scratch, &total);  // also a barrier
+#pragma unroll
+    for (uint32_t u = 0; u < kDecChunks; ++u) {
+        const uint32_t c = tid * per + u, p = cs + 32u * c;
+        if (u < per && c < nch) {
+            dec_tile_scatter<WB, R>(it, p, pb[u], own_bits(p), k, jf, L);
+            k += __popc(pb[u]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1111,12 +1161,17 @@ hipError_t launch_decode(const DecPlan& plan, hipStream_t stream) {
     JIFFY_LAUNCH("k_dec_mask", k_dec_mask, dim3(div_up(2 * plan.nwords, 64), plan.n_attrs), dim3(64 * mask_waves),
                  stream, plan);
     JIFFY_LAUNCH("k_dec_scan", k_dec_scan, dim3(plan.n_items), dim3(1024), stream, plan);
+    // records of 32-bit samples (32-bit rows), then 16-bit, then 8-bit ones (16-bit rows)
+    const uint32_t n8 = plan.n_items - plan.n_wide - plan.n_w16;
     if (plan.n_wide)
-        JIFFY_LAUNCH("k_dec_tiles_w32", k_dec_tiles<uint32_t>, dim3(plan.n_wide * plan.nft), dim3(kDecThreads),
-                     stream, plan, 0u);
-    if (plan.n_items > plan.n_wide)
-        JIFFY_LAUNCH("k_dec_tiles_w16", k_dec_tiles<uint16_t>, dim3((plan.n_items - plan.n_wide) * plan.nft),
-                     dim3(kDecThreads), stream, plan, plan.n_wide);
+        JIFFY_LAUNCH("k_dec_tiles_w32", (k_dec_tiles<uint32_t, 4>), dim3(plan.n_wide * plan.nvt), dim3(kDecThreads),
+                     stream, plan, 0u, plan.n_wide);
+    if (plan.n_w16)
+        JIFFY_LAUNCH("k_dec_tiles_w16", (k_dec_tiles<uint16_t, 2>), dim3(plan.n_w16 * plan.nvt), dim3(kDecThreads),
+                     stream, plan, plan.n_wide, plan.n_w16);
+    if (n8)
+        JIFFY_LAUNCH("k_dec_tiles_w8", (k_dec_tiles<uint16_t, 1>), dim3(n8 * plan.nvt), dim3(kDecThreads), stream,
+                     plan, plan.n_wide + plan.n_w16, n8);
     if (plan.need_temporal)
         JIFFY_LAUNCH("k_dec_temporal", k_dec_temporal, dim3(div_up(plan.npx, 256), plan.n_attrs), dim3(256),
                      stream, plan);

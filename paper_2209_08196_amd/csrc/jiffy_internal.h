@@ -107,10 +107,19 @@ struct EncOut {
 // A decode tile: its values [kb, ke) and, for the payload, exception
 // position and exception high-part sections, the first record word and the
 // number of words that hold the tile's frames.
+// A decode tile: values [kb, ke) of its record, pixels [ps, pe).  Tiles are
+// cut at every kDecTileVals-th value and at the start of every
+// kDecBlockPx-pixel block, so a tile holds at most kDecTileVals values (the
+// frame rows of one workgroup) and at most kDecBlockPx pixels.
 struct DecTile {
-    uint32_t kb, ke;
-    uint32_t w0[3], nw[3];
+    uint32_t kb, ke, ps, pe;
 };
+constexpr uint32_t kDecTileVals = 8192;
+constexpr uint32_t kDecBlockPx = 65536;
+// tiles a record of npx pixels can have, at most
+inline __host__ __device__ uint32_t dec_tile_slots(uint32_t npx) {
+    return (npx + kDecBlockPx - 1) / kDecBlockPx + (npx + kDecTileVals - 1) / kDecTileVals;
+}
 
 // One record to decode.
 struct DecItem {
@@ -121,10 +130,10 @@ struct DecItem {
     JG uint64_t* vw;             // valid-sample words
     JG uint32_t* blkinfo;        // [maxnb]
     JG uint32_t* blkoffs;        // [3 * maxnb]
-    JG uint32_t* tbase;          // [nft + 1] valid samples before each kFTile tile (and N)
-    JG DecTile* tdesc;           // [nft]
+    JG uint2* tstart;            // [nvt + 1] each tile's first pixel and first value, then (npx, N)
+    JG DecTile* tdesc;           // [nvt]
     JG uint32_t* tctr;           // k_dec_tiles ticket counter of the record
-    JG uint64_t* status;         // [nft] look-back state of each tile
+    JG uint64_t* status;         // [nvt] look-back state of each tile
     uint32_t npx, nwords, wb, bits;
     uint32_t attr, t, P, maxnb;
     uint32_t aligned16, pad0;
@@ -133,7 +142,7 @@ struct DecItem {
 struct DecRes {
     uint32_t mode, flen, N, nb;
     uint32_t sec, pay_off, pos_off, high_off;
-    uint32_t high_end, err;
+    uint32_t high_end, err, ntiles, pad0;
 };
 
 // ---- kernel timing hooks (jiffy_api.hip) ----------------------------------
@@ -240,9 +249,10 @@ struct DecPlan {
     uint32_t off_cw, off_vw;  // offsets of the mask words inside a record's workspace
     uint32_t n_items, n_scans, n_attrs;
     uint32_t nwords, npx;
-    uint32_t nft;             // kFTile tiles per record
-    const JG uint32_t* rec_list; // the records with 32-bit samples, then the others
+    uint32_t nvt;             // decode tile slots per record (dec_tile_slots)
+    const JG uint32_t* rec_list; // the records with 32-bit samples, then 16-bit, then 8-bit
     uint32_t n_wide;          // how many have 32-bit samples
+    uint32_t n_w16;           // how many have 16-bit samples (they follow the 32-bit ones, the 8-bit ones follow them)
     uint32_t need_temporal;   // per-pixel pass over time needed
     uint32_t pwin;            // mask-frame windows per record (parse workgroups), at most
     uint32_t off_pstate;      // offset in a record's workspace of its window states ([pwin + 1] u64,
