@@ -159,6 +159,42 @@ __device__ __forceinline__ uint32_t exc_bit(uint32_t j, uint32_t n, uint32_t hw)
     return j < n ? 8u * j : 8u * n + (j - n) * hw;
 }
 
+// The low B bits of a lane's 32 codes as its B words of the packed frame
+// (value i at bits [iB, (i+1)B)), built with shifts known at compile time
+// and stored unconditionally.
+template <int B>
+__device__ __forceinline__ void pack32(const uint32_t z[32], JG uint32_t* dst) {
+    constexpr uint32_t kMask = B == 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
+    uint32_t w[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) w[k] = 0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const int bit = i * B, lo = bit >> 5, sh = bit & 31;
+        const uint32_t v = z[i] & kMask;
+        w[lo] |= v << sh;
+        if (sh + B > 32) w[lo + 1] |= v >> (32 - sh);
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) dst[k] = w[k];
+}
+#define JIFFY_PACK_CASE(B) \
+    case B: pack32<B>(z, dst); break;
+__device__ __forceinline__ void pack_lane(const uint32_t z[32], uint32_t b, JG uint32_t* dst) {
+    switch (b) {
+        JIFFY_PACK_CASE(1) JIFFY_PACK_CASE(2) JIFFY_PACK_CASE(3) JIFFY_PACK_CASE(4)
+        JIFFY_PACK_CASE(5) JIFFY_PACK_CASE(6) JIFFY_PACK_CASE(7) JIFFY_PACK_CASE(8)
+        JIFFY_PACK_CASE(9) JIFFY_PACK_CASE(10) JIFFY_PACK_CASE(11) JIFFY_PACK_CASE(12)
+        JIFFY_PACK_CASE(13) JIFFY_PACK_CASE(14) JIFFY_PACK_CASE(15) JIFFY_PACK_CASE(16)
+        JIFFY_PACK_CASE(17) JIFFY_PACK_CASE(18) JIFFY_PACK_CASE(19) JIFFY_PACK_CASE(20)
+        JIFFY_PACK_CASE(21) JIFFY_PACK_CASE(22) JIFFY_PACK_CASE(23) JIFFY_PACK_CASE(24)
+        JIFFY_PACK_CASE(25) JIFFY_PACK_CASE(26) JIFFY_PACK_CASE(27) JIFFY_PACK_CASE(28)
+        JIFFY_PACK_CASE(29) JIFFY_PACK_CASE(30) JIFFY_PACK_CASE(31) JIFFY_PACK_CASE(32)
+        default: break;  // b = 0: no payload
+    }
+}
+#undef JIFFY_PACK_CASE
+
 // vrow: the frame's values (row layout); the width histogram, then the
 // codes replace them.  The packed frame goes straight to its slot: lane q
 // stores its b words of low bits (words qb .. qb+b-1).  The exception bytes
@@ -177,21 +213,7 @@ __device__ __forceinline__ void code_frame_quad(uint32_t* vrow, uint32_t real, u
     const uint32_t b = 63u - ((key >> 8) & 63u), nexc = key & 255u;
     const uint32_t hw = B - b, lm = low_mask32(b);
     JG uint32_t* sw = (JG uint32_t*)slot;
-    {  // low b bits of each value
-        JG uint32_t* dst = sw + q * b;
-        uint64_t acc = 0;
-        uint32_t nacc = 0, wi = 0;
-#pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            acc |= (uint64_t)(z[i] & lm) << nacc;
-            nacc += b;
-            if (nacc >= 32) {
-                dst[wi++] = (uint32_t)acc;
-                acc >>= 32;
-                nacc -= 32;
-            }
-        }
-    }
+    pack_lane(z, b, sw + q * b);  // low b bits of each value
     uint32_t ex = 0;  // this lane's exceptions
 #pragma unroll
     for (int i = 0; i < 32; ++i) ex |= (z[i] > lm ? 1u : 0u) << i;
