@@ -765,6 +765,73 @@ def copy_run(nbytes):
     print(json.dumps({"copy_bytes": nbytes}), flush=True)
 
 
+_DEC_TILE_NAMES = {"4": "k_dec_tiles_w32", "2": "k_dec_tiles_w16", "1": "k_dec_tiles_w8"}
+
+
+def _kernel_key(full):
+    """A profiler's kernel name as the library's timing hooks name it (the
+    decoder tile kernel by sample width, other templates without arguments)."""
+    name = full.split("(")[0].split("::")[-1]
+    if "<" in name:
+        base, args = name.split("<", 1)
+        if base == "k_dec_tiles":
+            return _DEC_TILE_NAMES.get(args.rstrip(">").split(",")[-1].strip(), base)
+        name = base
+    return name
+
+
+def profile_summary(title, stats_csv, workload=None, sq_dirs=()):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run: per kernel
+    its calls, mean duration and share of GPU time; with the workload's
+    calibrated HBM counters (profiles/traffic.json, same kernel source) its
+    bytes read and written per launch; with SQ counter folders the per-wave
+    instruction mix, the share of wave time spent waiting and the VALU and
+    LDS activity."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    traffic = {}
+    if workload and os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("source_sha") == source_sha():
+            traffic = tr.get("workloads", {}).get(workload, {}).get("kernels", {})
+    out = [f"# {title}", "", "| kernel | calls | average us | % of GPU time | HBM read MB | HBM write MB |",
+           "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        key = _kernel_key(r["Name"])
+        t = traffic.get(key, {})
+        name = r["Name"].split("(")[0]
+        if len(name) > 60:
+            name = name[:57] + "..."
+        rd = f"{t['fetch_bytes'] / 1e6:.1f}" if t else ""
+        wr = f"{t['write_bytes'] / 1e6:.1f}" if t else ""
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} | "
+                   f"{rd} | {wr} |")
+    if sq_dirs:
+        c = {}
+        for d in sq_dirs:
+            import glob
+            for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+                for row in csv.DictReader(open(f)):
+                    k = _kernel_key(row["Kernel_Name"])
+                    if not k.startswith("k_"):
+                        continue
+                    c.setdefault(k, {}).setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+        out += ["", "SQ counters per launch (means over dispatches; wave-level counts per wave):", "",
+                "| kernel | waves | VALU instr/wave | LDS instr/wave | SALU instr/wave | VMEM rd/wr per wave | "
+                "wave time waiting | LDS bank-conflict cycles / LDS active cycles |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
+
+        def m(k, n):
+            v = c[k].get(n)
+            return sum(v) / len(v) if v else float("nan")
+        for k in sorted(c, key=lambda k: -m(k, "SQ_BUSY_CYCLES") if "SQ_BUSY_CYCLES" in c[k] else 0):
+            w = m(k, "SQ_WAVES")
+            out.append(f"| `{k}` | {w:.0f} | {m(k, 'SQ_INSTS_VALU') / w:.0f} | {m(k, 'SQ_INSTS_LDS') / w:.0f} | "
+                       f"{m(k, 'SQ_INSTS_SALU') / w:.0f} | {m(k, 'SQ_INSTS_VMEM_RD') / w:.1f} / "
+                       f"{m(k, 'SQ_INSTS_VMEM_WR') / w:.1f} | {m(k, 'SQ_WAIT_ANY') / m(k, 'SQ_WAVE_CYCLES'):.0%} | "
+                       f"{m(k, 'SQ_LDS_BANK_CONFLICT') / max(m(k, 'SQ_ACTIVE_INST_LDS'), 1):.2f} |")
+    print("\n".join(out))
+
+
 def _counter_means(folder, counter):
     """Mean per dispatch of one counter, per kernel name, from a rocprofv3
     --pmc csv folder (values summed over the dispatch's rows)."""
@@ -777,9 +844,7 @@ def _counter_means(folder, counter):
     for row in csv.DictReader(open(files[0])):
         if row["Counter_Name"] != counter:
             continue
-        name = row["Kernel_Name"].split("(")[0].split("::")[-1]
-        if "<" in name:
-            name = name.split("<")[0]
+        name = _kernel_key(row["Kernel_Name"])
         key = (name, row["Dispatch_Id"])
         per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
     out = {}
@@ -883,9 +948,16 @@ def main():
     ap.add_argument("--traffic", nargs=5, metavar=("WORKLOAD", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="summarize four rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE of a bench "
                          "run and of a --copy-bytes run) into " + os.path.relpath(TRAFFIC_FILE, ROOT))
+    ap.add_argument("--profile-summary", nargs=2, metavar=("TITLE", "KERNEL_STATS_CSV"),
+                    help="print a markdown summary of a rocprofv3 --stats run (with --traffic-workload and --sq)")
+    ap.add_argument("--traffic-workload", help="workload key of the HBM counters in " + os.path.relpath(TRAFFIC_FILE, ROOT))
+    ap.add_argument("--sq", nargs="*", default=(), help="rocprofv3 --pmc folders of SQ counters")
     ap.add_argument("--trace-overlap", metavar="KERNEL_TRACE_CSV",
                     help="summarize per-stream kernel time and cross-stream overlap of a rocprofv3 kernel trace")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(*args.profile_summary, workload=args.traffic_workload, sq_dirs=args.sq)
+        return
     if args.trace_overlap:
         trace_overlap(args.trace_overlap)
         return
