@@ -68,7 +68,15 @@ def source_sha():
 
 
 def pool_size():
+    """Host threads for the oracle's all-core leg (the GPU machine's share is 16 cores)."""
     return max(1, min(16, os.cpu_count() or 1))
+
+
+def gen_procs():
+    """Processes that generate inputs: at most 8, so that a run under a
+    profiler (which initializes the GPU in the parent before the fork) stays
+    well below the number of processes that may use one GPU."""
+    return max(1, min(8, os.cpu_count() or 1))
 
 
 # ---------------------------------------------------------------------------
@@ -82,12 +90,24 @@ def _gen(job):
 
 def generate(jobs):
     """Scan arrays for (cid, stream, t0, t1) jobs, in a process pool."""
-    import multiprocessing as mp
-    n = pool_size()
+    n = gen_procs()
     if n == 1 or len(jobs) == 1:
         return [_gen(j) for j in jobs]
-    with mp.get_context("fork").Pool(min(n, len(jobs))) as pool:
-        return pool.map(_gen, jobs, chunksize=1)
+    return _pool_map(_gen, jobs, min(n, len(jobs)), 1)
+
+
+def _pool_map(fn, jobs, procs, chunksize):
+    """map over forked worker processes that finish normally (close and join:
+    a terminated worker would run the signal handlers it inherited, such as
+    a profiler's, in the child)."""
+    import multiprocessing as mp
+    pool = mp.get_context("fork").Pool(procs)
+    try:
+        out = pool.map(fn, jobs, chunksize=chunksize)
+    finally:
+        pool.close()
+        pool.join()
+    return out
 
 
 def _cloud(args):
@@ -99,11 +119,9 @@ def _cloud(args):
 def generate_clouds(dual):
     """Cartesian clouds of the dual-return stream's range scans, each point
     carrying signal, reflectivity and near-IR (in a process pool)."""
-    import multiprocessing as mp
     T = dual[0].shape[0]
     jobs = [(t, dual[0][t], [dual[2][t], dual[3][t], dual[4][t]]) for t in range(T)]
-    with mp.get_context("fork").Pool(min(pool_size(), T)) as pool:
-        return pool.map(_cloud, jobs, chunksize=4)
+    return _pool_map(_cloud, jobs, min(gen_procs(), T), 4)
 
 
 # ---------------------------------------------------------------------------
@@ -1019,7 +1037,7 @@ def main():
     batched_host = data[o:o + synth.CONFIGS[3].streams] if "batched" in legs else None
     o += synth.CONFIGS[3].streams if "batched" in legs else 0
     serving_host = data[o:] if "serving" in legs else None
-    log(f"generated {len(jobs)} stream segments in {time.perf_counter() - t0:.1f}s on {pool_size()} processes")
+    log(f"generated {len(jobs)} stream segments in {time.perf_counter() - t0:.1f}s on {gen_procs()} processes")
 
     import torch
     torch.cuda.set_device(0)

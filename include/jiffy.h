@@ -96,9 +96,9 @@ int jiffy_encode(const jiffy_layout* layout, const jiffy_options* options, uint3
  * or pinned-host allocating routine; its plan image and results pass
  * through a fixed 1 MiB / 256 KiB host staging area by hipMemcpyAsync.
  * Host-side planning still uses ordinary heap memory.
- * A call whose workspace would exceed the array (about 5.2 bytes per sample
- * of all its scans and attributes plus ~200 bytes per record, e.g. 24 scans
- * of one 128x4096 attribute), or whose plan exceeds the staging area,
+ * A call whose workspace would exceed the array (about 5.6 bytes per sample
+ * of all its scans and attributes plus ~200 bytes per record, e.g. more than
+ * 22 scans of one 128x4096 attribute), or whose plan exceeds the staging area,
  * returns JIFFY_E_SCRATCH with *h_out_len = 0 before touching the device.
  * Every call on a device shares that device's array, which keeps the last
  * call's contents; each call first writes or clears everything it reads.

@@ -250,8 +250,8 @@ __device__ __forceinline__ FrameChoice choose_frame(uint32_t z0, uint32_t z1) {
 }
 
 // ---- frame rows (a frame of 128 values in LDS, four lanes per frame) -----
-constexpr uint32_t kRow = kSlotBytes / 4;  // LDS words per frame row
-static_assert(kRow >= kFrame + 12 && kRow % 4 == 0, "a frame row holds 128 values, padded every 32");
+constexpr uint32_t kRow = kFrame + 16;  // LDS words per frame row
+static_assert(kRow % 4 == 0 && 4 * kRow <= kSlotBytes, "a frame row holds 128 values, padded every 32, and fits a slot");
 
 // word of value i in a frame row: four pad words after every 32 values, so
 // that each lane's 32 values start 16-byte aligned in distinct banks

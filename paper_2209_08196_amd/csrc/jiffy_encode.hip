@@ -1252,15 +1252,17 @@ __device__ __forceinline__ void enc_assemble_item(const EncPlan& plan, uint32_t 
     }
     // 64 frames per workgroup: 16 lanes per frame, each group of 16 lanes
     // takes four frames.  A frame's slot holds its payload words, then its
-    // exception bytes (positions, high parts), at most kSlotBytes in all: the
-    // four frames' metadata is loaded in one round, then every word of the
-    // four slots in another (words past a frame's end read its first word
+    // exception bytes (positions, high parts), at most 512 bytes in all (the
+    // width choice never costs more than a frame at full width): the four
+    // frames' metadata is loaded in one round, then every word of the four
+    // coded frames in another (words past a frame's end read its first word
     // again: no extra traffic), then the stores.  Payload words go to the
     // payload section whole; exception bytes to the position and high-part
     // sections one by one.
     constexpr int kPer = kAsmFrames / 16;
-    constexpr int kSlotRounds = kSlotBytes / 4 / 16;
-    static_assert(kSlotBytes % 64 == 0, "a slot is a whole number of 16-word rounds");
+    constexpr uint32_t kCodedMax = 16 * 32;  // bytes of a frame coded at full width
+    constexpr int kSlotRounds = kCodedMax / 4 / 16;
+    static_assert(kCodedMax <= kSlotBytes, "a coded frame fits its slot");
     const uint32_t jg = (part - 1) * kAsmFrames + (tid >> 4) * kPer;
     if (jg >= rs.nb) return;
     const uint32_t l = tid & 15u;

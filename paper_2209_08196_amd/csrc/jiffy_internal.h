@@ -19,8 +19,10 @@ namespace jiffy {
 
 constexpr int kWave = 64;
 constexpr uint32_t kFrame = 128;            // values per packed frame (Sec. II: frames of 128)
-constexpr uint32_t kSlotBytes = 576;        // a packed frame (at most 16 * 32 bytes), or a frame that
-                                            // straddles tiles: its 128 residuals and their predecessor
+constexpr uint32_t kSlotBytes = 640;        // a packed frame (at most 16 * 32 bytes), or a frame that
+                                            // straddles tiles: its 128 residuals and their predecessor;
+                                            // five 128-byte lines, so that a frame of up to 128 bytes
+                                            // (most are) starts and ends in one line
 constexpr uint32_t kFTile = 8192;           // pixels per encode / decode tile
 constexpr uint32_t kNoFix = 0xFFFFFFFFu;    // a tile with no straddling frame to finish
 constexpr uint32_t kAsmFrames = 64;         // frames copied into the stream by one workgroup
