@@ -140,6 +140,32 @@ int jiffy_decode_layout(const jiffy_layout* layout, uint32_t n_scans, const void
 /* A short English description of a status code (static storage). */
 const char* jiffy_status_string(int status);
 
+/* ---- several scan sequences at once ----------------------------------
+ * jiffy_encode_many encodes n_streams sequences of one layout and n_scans
+ * scans each in one launch sequence (every record of every stream shares
+ * each kernel launch); stream s's output is exactly what jiffy_encode writes
+ * for it (Sec. III, Fig. 2).  Modes 0..2 only.
+ *   d_planes[s][a]: device, stream s's attribute a, [n_scans][H][W];
+ *   d_outs[s], caps[s]: device output of stream s (4-byte aligned) and its
+ *       capacity; h_out_lens[s]: host, its length (or the bytes needed);
+ *   h_modes: optional host [n_streams][n_scans][n_attrs] (0 = I, 1 = P).
+ * Returns JIFFY_E_CAPACITY when any output is too small (no output is then
+ * complete), else as jiffy_encode.
+ * jiffy_decode_many decodes n_streams streams written for one layout and
+ * n_scans scans in one launch sequence, each indexed on the device from its
+ * length table and its header checked there (Sec. III-C reversed):
+ *   d_ins[s], in_lens[s]: device stream s (4-byte aligned) and its length;
+ *   d_planes_out[s][a]: device, [n_scans][H][W] of attribute a's width.
+ * Returns JIFFY_E_CORRUPT when any stream is malformed or does not match
+ * the layout (outputs then undefined).  Both take at most 2^24 records
+ * (n_streams * n_scans * n_attrs; JIFFY_E_INVALID beyond), do nothing for
+ * n_streams = 0 and synchronize `stream`. */
+int jiffy_encode_many(const jiffy_layout* layout, const jiffy_options* options, uint32_t n_streams,
+                      uint32_t n_scans, const void* const* const* d_planes, void* const* d_outs, const size_t* caps,
+                      size_t* h_out_lens, uint8_t* h_modes, hipStream_t stream);
+int jiffy_decode_many(const jiffy_layout* layout, uint32_t n_streams, uint32_t n_scans, const void* const* d_ins,
+                      const size_t* in_lens, void* const* const* d_planes_out, hipStream_t stream);
+
 /* ---- stateful streams (many sensors, one scan per step) ---------------
  * A jiffy_stream keeps the previous quantized scan and its zero mask
  * resident in device memory, so that a P-scan (Sec. III-D) can predict from

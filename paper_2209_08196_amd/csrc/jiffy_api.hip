@@ -603,6 +603,13 @@ struct EncCache {
     HostBuf up;
 };
 EncCache g_enc_cache[64];
+// The same for jiffy_encode_many, keyed by every stream's planes and output.
+struct EncManyCache {
+    std::vector<uint64_t> key;
+    EncPrepared prep;
+    HostBuf up;
+};
+EncManyCache g_enc_many_cache[64];
 
 // ---------------------------------------------------------------------------
 // header parsing (host memory)
@@ -823,6 +830,66 @@ int jiffy_encode(const jiffy_layout* L, const jiffy_options* opt, uint32_t T, co
     if (!res.ok[0]) return JIFFY_E_CAPACITY;
     if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)T * A);
     return JIFFY_OK;
+}
+
+int jiffy_encode_many(const jiffy_layout* L, const jiffy_options* opt, uint32_t n_streams, uint32_t T,
+                      const void* const* const* d_planes, void* const* d_outs, const size_t* caps, size_t* h_out_lens,
+                      uint8_t* h_modes, hipStream_t stream) {
+    if (!layout_ok(L) || !h_out_lens || (n_streams && (!d_planes || !d_outs || !caps))) return JIFFY_E_INVALID;
+    if (opt && opt->mode > JIFFY_MODE_P_ONLY) return JIFFY_E_INVALID;
+    if (n_streams == 0) return JIFFY_OK;
+    const uint32_t A = L->n_attrs;
+    if ((uint64_t)T * A * n_streams > (1u << 24) || T == 0) return JIFFY_E_INVALID;
+    for (uint32_t s = 0; s < n_streams; ++s)
+        if (int rc = check_encode_args(L, opt, T, d_planes[s], d_outs[s], h_out_lens)) return rc;
+    const uint32_t mode = opt ? opt->mode : 0;
+    const uint32_t K = (opt && opt->trial_rows) ? opt->trial_rows : 4;
+    int dev;
+    if (current_device(&dev)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[dev];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    // the plan of the last call is reused when the arguments and the workspace are the same
+    std::vector<uint64_t> key(sizeof(jiffy_layout) / 8 + 1, 0);
+    memcpy(key.data(), L, sizeof *L);
+    key.push_back(mode);
+    key.push_back(K);
+    key.push_back(T);
+    for (uint32_t s = 0; s < n_streams; ++s) {
+        for (uint32_t a = 0; a < A; ++a) key.push_back((uint64_t)(uintptr_t)d_planes[s][a]);
+        key.push_back((uint64_t)(uintptr_t)d_outs[s]);
+        key.push_back(caps[s]);
+    }
+    EncManyCache& C = g_enc_many_cache[dev];
+    EncResult res;
+    const bool hit = C.prep.valid && C.prep.ws == ctx.ws.p && key == C.key;
+    if (hit) {
+        if (int rc = enc_execute(ctx, C.up, C.prep, stream, res, C.prep.gen != ctx.enc_gen)) return rc;
+    } else {
+        std::vector<EncSpec> specs, half;
+        std::vector<OutSpec> outs, o1;
+        const uint32_t per = T * A;
+        for (uint32_t s = 0; s < n_streams; ++s) {
+            sequence_specs(L, mode, K, T, d_planes[s], d_outs[s], caps[s], half, o1);
+            for (EncSpec& e : half) {
+                e.out_id = s;
+                if (e.prev_item >= 0) e.prev_item += (int)(s * per);
+            }
+            specs.insert(specs.end(), half.begin(), half.end());
+            o1[0].first_item = s * per;
+            outs.push_back(o1[0]);
+        }
+        if (int rc = enc_prepare(ctx, C.up, specs, outs, C.prep)) return rc;
+        C.key = std::move(key);
+        if (int rc = enc_execute(ctx, C.up, C.prep, stream, res)) return rc;
+    }
+    C.prep.gen = ctx.enc_gen;
+    int rc = JIFFY_OK;
+    for (uint32_t s = 0; s < n_streams; ++s) {
+        h_out_lens[s] = res.lens[s];
+        if (!res.ok[s]) rc = JIFFY_E_CAPACITY;
+    }
+    if (h_modes) memcpy(h_modes, res.modes.data(), (size_t)n_streams * T * A);
+    return rc;
 }
 
 int jiffy_standardize(const jiffy_grid* G, uint32_t n_scans, uint32_t n_points, const float* d_xyz,
@@ -1046,36 +1113,37 @@ struct DecPrepared {
     size_t o_err = 0, up_bytes = 0;
 };
 // The last device-indexed decode's arguments and plan (per device): a call
-// with the same arguments on the same workspace reuses the plan image.
-struct DecKey {
-    jiffy_layout L;
-    uint32_t T, hdr_check;
-    const void* din;
-    size_t in_len;
-    void* planes[JIFFY_MAX_ATTRS];
-};
+// with the same arguments on the same workspace reuses the plan image.  The
+// key lists the layout, the scan and stream counts, whether the header is
+// checked, and every stream's bytes and output planes.
 struct DecCache {
-    DecKey key;
+    std::vector<uint64_t> key;
     DecPrepared prep;
     HostBuf up;
 };
 DecCache g_dec_cache[64];
 
-int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, const uint8_t* din, size_t in_len,
-                const uint64_t* roff, const uint32_t* rlen, size_t p, const uint8_t* hdr,
-                void* const* d_planes_out, DecPrepared& P) {
+// A decode plan for S streams of layout L and T scans each (items scan-major,
+// then stream, then attribute).  With roff (records walked on the host; S =
+// 1) record r is at dins[0] + roff[r]; otherwise the records are indexed on
+// the device from each stream's length table.
+int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t S, uint32_t T,
+                const uint8_t* const* dins, const size_t* in_lens, const uint64_t* roff, const uint32_t* rlen,
+                size_t p, const uint8_t* hdr, void* const* const* planes_out, DecPrepared& P) {
     P.valid = false;
-    const uint32_t A = L.n_attrs;
+    const uint32_t A = L.n_attrs, C = S * A;  // attributes per stream, columns
 
-    const uint32_t n = T * A;
+    const uint32_t n = T * C;
     const uint32_t npx = L.height * L.width, nwords = div_up(npx, 64), maxnb = div_up(npx, kFrame);
     const uint32_t nvt = dec_tile_slots(npx);
     size_t off = 0;
     const size_t o_res = off; off = al(off + sizeof(DecRes) * n);
     const size_t o_roff = off; off = al(off + (roff ? 0 : sizeof(uint64_t) * n));
+    const size_t o_rlen = off; off = al(off + (roff ? 0 : sizeof(uint32_t) * n));
     const size_t o_err = off; off = al(off + sizeof(uint32_t) * 2);  // err, err2
     const size_t o_items = off; off = al(off + sizeof(DecItem) * n);
     const size_t o_list = off; off = al(off + sizeof(uint32_t) * n);
+    const size_t o_srcs = off; off = al(off + sizeof(DecSrc) * S);
     const size_t up_end = off;
     const uint32_t pwin = div_up(frame_bound(div_up(npx, 8)), kParseWin);
     const size_t per_item = al(8ull * nwords) * 2 + al(4ull * maxnb * 4) + al(8ull * (nvt + 1)) + al(8ull * nvt) +
@@ -1092,14 +1160,14 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     DecItem* hit = (DecItem*)(up + (o_items - o_err));
     bool need_temporal = T > 1;
     for (uint32_t t = 0; t < T; ++t) {
-        for (uint32_t a = 0; a < A; ++a) {
-            const uint32_t r = t * A + a;
+        for (uint32_t c = 0; c < C; ++c) {
+            const uint32_t r = t * C + c, st = c / A, a = c - st * A;
             DecItem& it = hit[r];
             uint8_t* base = dev + o_data + per_item * r;
-            it.rec = roff ? din + roff[r] : nullptr;
+            it.rec = roff ? dins[0] + roff[r] : nullptr;
             it.rec_len = roff ? rlen[r] : 0;
             const size_t step = (size_t)npx * L.width_bytes[a];
-            it.out = (uint8_t*)d_planes_out[a] + t * step;
+            it.out = (uint8_t*)planes_out[st][a] + t * step;
             it.cw = (uint64_t*)base; base += al(8ull * nwords);
             it.vw = (uint64_t*)base; base += al(8ull * nwords);
             it.blkinfo = (uint32_t*)base;
@@ -1148,7 +1216,9 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
     plan.n_w16 = n_w16;
     plan.n_items = n;
     plan.n_scans = T;
-    plan.n_attrs = A;
+    plan.n_attrs = C;
+    plan.n_src = S;
+    plan.src_attrs = A;
     plan.nwords = nwords;
     plan.npx = npx;
     plan.need_temporal = need_temporal ? 1u : 0u;
@@ -1160,16 +1230,12 @@ int dec_prepare(DevCtx& ctx, HostBuf& upbuf, const jiffy_layout& L, uint32_t T, 
                                  al(sizeof(DecTile) * nvt) + al(4));
     plan.off_cw = 0;
     plan.off_vw = (uint32_t)al(8ull * nwords);
-    for (uint32_t a = 0; a < A; ++a) {
-        plan.out_base[a] = d_planes_out[a];
-        plan.attr_wb[a] = L.width_bytes[a];
-        plan.attr_P[a] = L.precision[a];
-    }
     if (!roff) {
+        DecSrc* hs = (DecSrc*)(up + (o_srcs - o_err));
+        for (uint32_t st = 0; st < S; ++st) hs[st] = DecSrc{(uint64_t)(uintptr_t)dins[st], (uint64_t)in_lens[st]};
+        plan.srcs = (const DecSrc*)((uint8_t*)upbuf.d + (o_srcs - o_err));  // read from host-mapped memory
         plan.roff = (uint64_t*)(dev + o_roff);
-        plan.tab = (const uint32_t*)(din + p);
-        plan.src = din;
-        plan.src_len = in_len;
+        plan.rlen = (uint32_t*)(dev + o_rlen);
         plan.hdr_len = (uint32_t)p;
         plan.hdr_check = hdr ? 1u : 0u;
         if (hdr) memcpy(plan.hdr_words, hdr, p);
@@ -1200,34 +1266,39 @@ int dec_execute(DevCtx& ctx, const HostBuf& upbuf, const DecPrepared& P, hipStre
 // expected header bytes to check there, or null when the host has read it);
 // a device-indexed call with the arguments of the previous one reuses its
 // plan.
-int run_decode(DevCtx& ctx, const jiffy_layout& L, uint32_t T, const uint8_t* din, size_t in_len,
-               const uint64_t* roff, const uint32_t* rlen, size_t p, const uint8_t* hdr,
-               void* const* d_planes_out, hipStream_t stream) {
+int run_decode(DevCtx& ctx, const jiffy_layout& L, uint32_t S, uint32_t T, const uint8_t* const* dins,
+               const size_t* in_lens, const uint64_t* roff, const uint32_t* rlen, size_t p, const uint8_t* hdr,
+               void* const* const* planes_out, hipStream_t stream) {
     const uint32_t A = L.n_attrs;
-    if (T == 0) return JIFFY_OK;
-    if (!d_planes_out) return JIFFY_E_INVALID;
-    for (uint32_t a = 0; a < A; ++a)
-        if (!d_planes_out[a] || (uintptr_t)d_planes_out[a] % L.width_bytes[a]) return JIFFY_E_INVALID;
+    if (T == 0 || S == 0) return JIFFY_OK;
+    if (!planes_out) return JIFFY_E_INVALID;
+    for (uint32_t st = 0; st < S; ++st) {
+        if (!planes_out[st]) return JIFFY_E_INVALID;
+        for (uint32_t a = 0; a < A; ++a)
+            if (!planes_out[st][a] || (uintptr_t)planes_out[st][a] % L.width_bytes[a]) return JIFFY_E_INVALID;
+    }
     if (roff) {  // host-walked records: no reuse
         DecPrepared P;
-        if (int rc = dec_prepare(ctx, ctx.up, L, T, din, in_len, roff, rlen, p, hdr, d_planes_out, P)) return rc;
+        if (int rc = dec_prepare(ctx, ctx.up, L, S, T, dins, in_lens, roff, rlen, p, hdr, planes_out, P)) return rc;
         return dec_execute(ctx, ctx.up, P, stream);
     }
     DecCache& C = g_dec_cache[&ctx - g_ctx];
-    DecKey key;
-    memset(&key, 0, sizeof key);
-    key.L = L;
-    key.T = T;
-    key.hdr_check = hdr ? 1u : 0u;
-    key.din = din;
-    key.in_len = in_len;
-    for (uint32_t a = 0; a < A; ++a) key.planes[a] = d_planes_out[a];
-    const bool hit = C.prep.valid && C.prep.ws == ctx.ws_dec.p && memcmp(&key, &C.key, sizeof key) == 0 &&
+    std::vector<uint64_t> key(sizeof(jiffy_layout) / 8 + 1, 0);
+    memcpy(key.data(), &L, sizeof L);
+    key.push_back(T);
+    key.push_back(S);
+    key.push_back(hdr ? 1u : 0u);
+    for (uint32_t st = 0; st < S; ++st) {
+        key.push_back((uint64_t)(uintptr_t)dins[st]);
+        key.push_back(in_lens[st]);
+        for (uint32_t a = 0; a < A; ++a) key.push_back((uint64_t)(uintptr_t)planes_out[st][a]);
+    }
+    const bool hit = C.prep.valid && C.prep.ws == ctx.ws_dec.p && key == C.key &&
                      (!hdr || memcmp(C.prep.plan.hdr_words, hdr, p) == 0);
     if (!hit) {
-        if (int rc = dec_prepare(ctx, C.up, L, T, din, in_len, nullptr, nullptr, p, hdr, d_planes_out, C.prep))
+        if (int rc = dec_prepare(ctx, C.up, L, S, T, dins, in_lens, nullptr, nullptr, p, hdr, planes_out, C.prep))
             return rc;
-        C.key = key;
+        C.key = std::move(key);
     }
     return dec_execute(ctx, C.up, C.prep, stream);
 }
@@ -1257,7 +1328,7 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     const uint32_t A = L.n_attrs;
     if (T_hdr) {  // a length table: the records are indexed on the device
         if ((uint64_t)T_hdr * A > (1u << 24) || in_len < p + 4ull * T_hdr * A) return JIFFY_E_CORRUPT;
-        return run_decode(ctx, L, T_hdr, din, in_len, nullptr, nullptr, p, nullptr, d_planes_out, stream);
+        return run_decode(ctx, L, 1, T_hdr, &din, &in_len, nullptr, nullptr, p, nullptr, &d_planes_out, stream);
     }
     // no table: walk the records
     std::vector<uint64_t> roff;
@@ -1277,7 +1348,7 @@ int jiffy_decode(const void* d_in, size_t in_len, void* const* d_planes_out, hip
     }
     if (roff.size() % A) return JIFFY_E_CORRUPT;
     const uint32_t T = (uint32_t)(roff.size() / A);
-    return run_decode(ctx, L, T, din, in_len, roff.data(), rlen.data(), p, nullptr, d_planes_out, stream);
+    return run_decode(ctx, L, 1, T, &din, &in_len, roff.data(), rlen.data(), p, nullptr, &d_planes_out, stream);
 }
 
 int jiffy_decode_layout(const jiffy_layout* layout, uint32_t n_scans, const void* d_in, size_t in_len,
@@ -1293,8 +1364,29 @@ int jiffy_decode_layout(const jiffy_layout* layout, uint32_t n_scans, const void
     std::lock_guard<std::mutex> lock(ctx.mu);
     uint8_t hdr[20 + 8 * JIFFY_MAX_ATTRS];
     write_header(hdr, layout, n_scans);
-    return run_decode(ctx, *layout, n_scans, (const uint8_t*)d_in, in_len, nullptr, nullptr, p, hdr, d_planes_out,
-                      stream);
+    const uint8_t* din = (const uint8_t*)d_in;
+    return run_decode(ctx, *layout, 1, n_scans, &din, &in_len, nullptr, nullptr, p, hdr, &d_planes_out, stream);
+}
+
+int jiffy_decode_many(const jiffy_layout* layout, uint32_t n_streams, uint32_t n_scans, const void* const* d_ins,
+                      const size_t* in_lens, void* const* const* d_planes_out, hipStream_t stream) {
+    if (!layout_ok(layout) || n_scans == 0 || !d_ins || !in_lens) return JIFFY_E_INVALID;
+    if (n_streams == 0) return JIFFY_OK;
+    const uint32_t A = layout->n_attrs;
+    if ((uint64_t)n_scans * A * n_streams > (1u << 24)) return JIFFY_E_INVALID;
+    const size_t p = 20 + 8 * A;
+    for (uint32_t s = 0; s < n_streams; ++s) {
+        if (!d_ins[s] || (uintptr_t)d_ins[s] % 4) return JIFFY_E_INVALID;
+        if (in_lens[s] < p + 4ull * n_scans * A) return JIFFY_E_CORRUPT;
+    }
+    int devid;
+    if (current_device(&devid)) return JIFFY_E_DEVICE;
+    DevCtx& ctx = g_ctx[devid];
+    std::lock_guard<std::mutex> lock(ctx.mu);
+    uint8_t hdr[20 + 8 * JIFFY_MAX_ATTRS];
+    write_header(hdr, layout, n_scans);
+    return run_decode(ctx, *layout, n_streams, n_scans, (const uint8_t* const*)d_ins, in_lens, nullptr, nullptr, p,
+                      hdr, d_planes_out, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -511,8 +511,8 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
             if (threadIdx.x == 0 && blockIdx.y == plan.pwin) atomicOr(plan.err, kErrCorrupt);
             return;
         }
-        it.rec = plan.src + o;
-        it.rec_len = plan.tab[r];
+        it.rec = (const JG uint8_t*)o;
+        it.rec_len = plan.rlen[r];
         if (threadIdx.x == 0 && blockIdx.y == plan.pwin) {
             plan.items[r].rec = it.rec;
             plan.items[r].rec_len = it.rec_len;
@@ -530,51 +530,73 @@ __global__ __launch_bounds__(256) void k_dec_parse(DecPlan plan) {
 // bytes, and the records must end exactly at the end of the stream;
 // otherwise every record offset is ~0.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dec_prepare(const uint4* src, uint4* dst, uint32_t n16, DecPlan plan) {
+__global__ __launch_bounds__(256) void k_dec_prepare(const uint4* src, uint4* dst, uint32_t n16, DecPlan plan,
+                                                     uint32_t up_blocks) {
     const uint32_t tid = threadIdx.x;
-    if (blockIdx.x + 1 < gridDim.x) {
+    if (blockIdx.x < up_blocks) {
         const uint32_t i = blockIdx.x * 256 + tid;
         if (i < n16) ((JG uint4*)dst)[i] = load_system16((const JG uint4*)src + i);
         return;
     }
-    // every record's parse window states and window ticket start at zero
+    // one workgroup per stream (one in all without an index): its records'
+    // parse window states and window tickets start at zero
+    const uint32_t s = blockIdx.x - up_blocks, nsrc = plan.roff ? plan.n_src : 1u;
+    const uint32_t A = plan.roff ? plan.src_attrs : plan.n_attrs, nq = plan.n_scans * A;
+    auto item = [&](uint32_t qi) {  // the item of the stream's record qi = t * A + a
+        const uint32_t t = qi / A, a = qi - t * A;
+        return t * plan.n_attrs + s * A + a;
+    };
     {
         const uint32_t per = plan.pwin + 2;  // pwin + 1 states, then the ticket word
-        for (uint32_t i = tid; i < plan.n_items * per; i += 256) {
-            const uint32_t r = i / per, k = i - r * per;
-            JG uint64_t* st = parse_states(plan, r);
+        for (uint32_t i = tid; i < nq * per; i += 256) {
+            const uint32_t qi = i / per, k = i - qi * per;
+            JG uint64_t* st = parse_states(plan, item(qi));
             if (k <= plan.pwin) st[k] = 0;
             else *(JG uint32_t*)(st + k) = 0u;
         }
     }
-    if (!plan.roff) return;
+    if (!plan.roff || s >= nsrc) return;
     __shared__ uint64_t scratch[8];
     __shared__ uint32_t s_bad;
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
-    if (plan.hdr_check && tid < plan.hdr_len / 4 && ((const JG uint32_t*)plan.src)[tid] != plan.hdr_words[tid])
-        atomicOr(&s_bad, 1u);
-    const uint32_t n = plan.n_items;
-    uint64_t carry = (uint64_t)plan.hdr_len + 4ull * n;
-    for (uint32_t r0 = 0; r0 < n; r0 += 256) {
-        const uint32_t r = r0 + tid;
-        const uint32_t len = r < n ? plan.tab[r] : 0u;
-        if (r < n && (len < 12 || len % 4)) atomicOr(&s_bad, 1u);
-        uint64_t total;
-        const uint64_t pre = block_excl_scan64<256>((uint64_t)len, scratch, &total) + carry;
-        if (r < n) plan.roff[r] = pre;
-        carry += total;
+    __shared__ uint4 s_src;
+    if (tid == 0) {
+        s_bad = 0;
+        s_src = load_system16((const JG uint4*)(plan.srcs + s));
     }
     __syncthreads();
-    if (s_bad || carry != plan.src_len)
-        for (uint32_t r = tid; r < n; r += 256) plan.roff[r] = ~0ull;  // the same thread wrote it above
+    const uint64_t base = (uint64_t)s_src.x | ((uint64_t)s_src.y << 32), len = (uint64_t)s_src.z | ((uint64_t)s_src.w << 32);
+    const JG uint32_t* words = (const JG uint32_t*)base;
+    const JG uint32_t* tab = (const JG uint32_t*)(base + plan.hdr_len);
+    if (len < plan.hdr_len + 4ull * nq) s_bad = 1;  // read before any table word (all threads agree)
+    __syncthreads();
+    if (!s_bad) {
+        if (plan.hdr_check && tid < plan.hdr_len / 4 && words[tid] != plan.hdr_words[tid]) atomicOr(&s_bad, 1u);
+        uint64_t carry = (uint64_t)plan.hdr_len + 4ull * nq;
+        for (uint32_t q0 = 0; q0 < nq; q0 += 256) {
+            const uint32_t qi = q0 + tid;
+            const uint32_t l = qi < nq ? tab[qi] : 0u;
+            if (qi < nq && (l < 12 || l % 4)) atomicOr(&s_bad, 1u);
+            uint64_t total;
+            const uint64_t pre = block_excl_scan64<256>((uint64_t)l, scratch, &total) + carry;
+            if (qi < nq) {
+                plan.roff[item(qi)] = base + pre;
+                plan.rlen[item(qi)] = l;
+            }
+            carry += total;
+        }
+        if (tid == 0 && carry != len) s_bad = 1;
+    }
+    __syncthreads();
+    if (s_bad)
+        for (uint32_t qi = tid; qi < nq; qi += 256) plan.roff[item(qi)] = ~0ull;  // the same thread wrote it above
 }
 
 hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const DecPlan& plan, hipStream_t stream) {
     const uint32_t n16 = (uint32_t)(bytes / 16);
-    const uint32_t blocks = div_up(n16, 256) + 1;  // the last one clears the parse states (and indexes)
+    const uint32_t up = div_up(n16, 256);  // then one workgroup per stream (one without an index)
+    const uint32_t blocks = up + (plan.roff ? plan.n_src : 1u);
     JIFFY_LAUNCH("k_dec_prepare", k_dec_prepare, dim3(blocks), dim3(256), stream, (const uint4*)host, (uint4*)dev,
-                 n16, plan);
+                 n16, plan, up);
     return hipGetLastError();
 }
 
@@ -1040,20 +1062,21 @@ constexpr uint32_t kModeLds = 8192;
 // of every scan: 4 / WB pixels.
 constexpr int kTempAhead = 8;
 template <int WB>
-__device__ __forceinline__ void dec_temporal_body(const DecPlan& plan, uint32_t a, uint32_t p0, const uint16_t* list,
-                                                  uint32_t tb, uint32_t nlist, uint32_t qprev[4 / WB]) {
+__device__ __forceinline__ void dec_temporal_body(const DecPlan& plan, uint32_t a, uint8_t* out, uint32_t P,
+                                                  uint32_t p0, const uint16_t* list, uint32_t tb, uint32_t nlist,
+                                                  uint32_t qprev[4 / WB]) {
     constexpr int NP = 4 / WB;
     const uint32_t A = plan.n_attrs;
-    const uint32_t P = plan.attr_P[a], bits = 8 * WB, m = low_mask32(bits);
+    const uint32_t bits = 8 * WB, m = low_mask32(bits);
     const uint64_t stride = (uint64_t)plan.npx * WB;
-    const bool whole = ((uintptr_t)plan.out_base[a] % 4 == 0) && (stride % 4 == 0) && p0 + NP <= plan.npx;
+    const bool whole = ((uintptr_t)out % 4 == 0) && (stride % 4 == 0) && p0 + NP <= plan.npx;
     using T = typename SampleT<WB>::T;
     // e: a list entry (the scan, and bit 15 set for a P-scan).  The loads land
     // in registers that nothing reads before the scan's turn, so the next
     // scans' loads stay in flight meanwhile.
     auto fetch = [&](uint32_t e, uint32_t& w, uint64_t& vw) {
         const uint32_t t = tb + (e & 0x7FFFu);
-        const uint8_t* s = (const uint8_t*)plan.out_base[a] + stride * t + (uint64_t)p0 * WB;
+        const uint8_t* s = out + stride * t + (uint64_t)p0 * WB;
         if (whole) w = *(const uint32_t*)s;
         else {
             w = 0;
@@ -1064,7 +1087,7 @@ __device__ __forceinline__ void dec_temporal_body(const DecPlan& plan, uint32_t 
         vw = item_words(plan, t * A + a, plan.off_vw)[p0 >> 6];
     };
     auto put = [&](uint32_t t, const uint32_t v[NP]) {
-        uint8_t* d = (uint8_t*)plan.out_base[a] + stride * t + (uint64_t)p0 * WB;
+        uint8_t* d = out + stride * t + (uint64_t)p0 * WB;
         if (whole) {
             uint32_t w = 0;
 #pragma unroll
@@ -1109,8 +1132,10 @@ __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
     __shared__ uint16_t list[kModeLds];  // the scans to read: offset from tb, bit 15 for a P-scan
     __shared__ uint32_t scratch[8];
     const uint32_t A = plan.n_attrs, T = plan.n_scans;
-    const bool all = plan.attr_P[a] > 1;
-    const uint32_t wb = plan.attr_wb[a];
+    // the column's planes, width and precision from its first scan's record
+    uint8_t* const out = (uint8_t*)plan.items[a].out;
+    const uint32_t P = plan.items[a].P, wb = plan.items[a].wb;
+    const bool all = P > 1;
     const uint32_t p0 = (blockIdx.x * 256 + threadIdx.x) * (4 / wb);
     if (blockIdx.x * 256 * (4 / wb) >= plan.npx) return;  // the grid is sized for 32-bit samples
     uint32_t qprev[4] = {0u, 0u, 0u, 0u};
@@ -1132,9 +1157,9 @@ __global__ __launch_bounds__(256) void k_dec_temporal(DecPlan plan) {
         __syncthreads();
         if (p0 < plan.npx) {
             switch (wb) {
-                case 4: dec_temporal_body<4>(plan, a, p0, list, tb, nlist, qprev); break;
-                case 2: dec_temporal_body<2>(plan, a, p0, list, tb, nlist, qprev); break;
-                default: dec_temporal_body<1>(plan, a, p0, list, tb, nlist, qprev); break;
+                case 4: dec_temporal_body<4>(plan, a, out, P, p0, list, tb, nlist, qprev); break;
+                case 2: dec_temporal_body<2>(plan, a, out, P, p0, list, tb, nlist, qprev); break;
+                default: dec_temporal_body<1>(plan, a, out, P, p0, list, tb, nlist, qprev); break;
             }
         }
         __syncthreads();

@@ -240,6 +240,11 @@ hipError_t launch_ablate(const AblArgs& a, uint32_t run_groups, hipStream_t stre
 // memory with a kernel on `stream` (no copy engine, so no cross-queue wait).
 hipError_t launch_copy_in(const void* host, void* dev, size_t bytes, hipStream_t stream);
 
+// One stream of a device-indexed decode (in host-mapped memory).
+struct DecSrc {
+    uint64_t src, len;  // device address and length of the stream
+};
+
 struct DecPlan {
     JG DecItem* items;
     JG DecRes* res;
@@ -259,24 +264,27 @@ struct DecPlan {
     uint32_t pwin;            // mask-frame windows per record (parse workgroups), at most
     uint32_t off_pstate;      // offset in a record's workspace of its window states ([pwin + 1] u64,
                               // then the window ticket counter)
-    // Record index built on the device (null roff: the host filled rec / rec_len):
-    // the length table at `tab`, records from `tab + n_items`, the stream `src_len`
-    // bytes long; roff[r] = byte offset of record r, or ~0 when the index is bad.
-    const JG uint32_t* tab;
+    // Record index built on the device (null roff: the host filled rec /
+    // rec_len).  The plan decodes n_src streams of src_attrs attributes and
+    // n_scans scans each; the record of scan t, attribute a of stream s is
+    // item t * n_attrs + s * src_attrs + a (n_attrs = n_src * src_attrs
+    // columns).  srcs (host-mapped) gives each stream's bytes; its length
+    // table follows a header of hdr_len bytes.  roff[r] = the record's
+    // address, rlen[r] its length, or roff[r] = ~0 when its stream's index is
+    // bad.
+    const DecSrc* srcs;
     JG uint64_t* roff;
-    const JG uint8_t* src;
-    uint64_t src_len;
+    JG uint32_t* rlen;
+    uint32_t n_src, src_attrs;
     uint32_t hdr_len;         // header bytes before the table
     uint32_t hdr_check;       // compare them with hdr_words
     uint32_t hdr_words[(20 + 8 * 8) / 4];  // the expected header
-    JG void* out_base[8];        // attribute planes
-    uint32_t attr_wb[8], attr_P[8];
 };
 hipError_t launch_decode(const DecPlan& plan, hipStream_t stream);
 
 // Upload of the decode plan (as launch_copy_in), clearing of the parse
-// window states and, when plan.roff is set, the device-side record index, in
-// one launch.
+// window states and, when plan.roff is set, the device-side record index of
+// every stream, in one launch.
 hipError_t launch_dec_prepare(const void* host, void* dev, size_t bytes, const DecPlan& plan, hipStream_t stream);
 // Copies n error words of a decode to host-mapped memory (system-scope stores).
 hipError_t launch_dec_report(const void* dev_err, void* host, uint32_t n, hipStream_t stream);

@@ -28,6 +28,7 @@ SYMBOLS = ("jiffy_encode_bound", "jiffy_encode", "jiffy_encode_noalloc", "jiffy_
            "jiffy_step_destroy",
            "jiffy_batch_create", "jiffy_batch_run", "jiffy_batch_destroy",
            "jiffy_set_tuning", "jiffy_get_tuning", "jiffy_ablate", "jiffy_standardize",
+           "jiffy_encode_many", "jiffy_decode_many",
            "jiffy_profile_enable", "jiffy_profile_read")
 
 
@@ -128,6 +129,11 @@ def lib():
         L.jiffy_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
         L.jiffy_get_tuning.restype = ctypes.c_int
         L.jiffy_get_tuning.argtypes = [ctypes.POINTER(Tuning), ctypes.POINTER(u32)]
+        L.jiffy_encode_many.restype = ctypes.c_int
+        L.jiffy_encode_many.argtypes = [ctypes.POINTER(Layout), ctypes.POINTER(Options), u32, u32, vp, vp, vp, vp, vp,
+                                        vp]
+        L.jiffy_decode_many.restype = ctypes.c_int
+        L.jiffy_decode_many.argtypes = [ctypes.POINTER(Layout), u32, u32, vp, vp, vp, vp]
         L.jiffy_ablate.restype = ctypes.c_int
         L.jiffy_ablate.argtypes = [ctypes.POINTER(Layout), u32, vp, vp, vp]
         L.jiffy_standardize.restype = ctypes.c_int
@@ -480,6 +486,95 @@ class Decoder:
                                        stream_bytes.numel(), ctypes.cast(self._arr, ctypes.c_void_p), self._stream)
         if rc:
             raise JiffyError(rc, "jiffy_decode_layout")
+        return self.outs
+
+
+class EncoderMany:
+    """jiffy_encode_many of fixed planes of several streams (one layout, one
+    scan count) into fixed outputs, prepared once (as Encoder): every
+    stream's records share each kernel launch; each output equals that
+    stream's jiffy_encode."""
+
+    def __init__(self, streams, precisions=None, mode=MODE_AUTO, trial_rows=0, outs=None, stream=None):
+        import torch
+        if not streams:
+            raise ValueError("at least one stream is needed")
+        shape = _check_planes(streams[0])
+        widths = [p.element_size() for p in streams[0]]
+        for i, planes in enumerate(streams):
+            if _check_planes(planes) != shape or [p.element_size() for p in planes] != widths:
+                raise ValueError(f"stream {i}: every stream needs the same shape and sample widths")
+        T, H, W = shape
+        self.streams = [list(p) for p in streams]
+        self.layout = make_layout(H, W, widths, precisions)
+        self._opt = Options(mode, trial_rows)
+        self.T, n = T, len(streams)
+        if outs is None:
+            bound = encode_bound(self.layout, T)
+            outs = [torch.empty(bound, dtype=torch.uint8, device=streams[0][0].device) for _ in range(n)]
+        if len(outs) != n:
+            raise ValueError("one output buffer per stream is needed")
+        for i, o in enumerate(outs):
+            _check_bytes_out(o, f"out {i}")
+        self.outs = list(outs)
+        A = len(widths)
+        self._rows = [(ctypes.c_void_p * A)(*[p.data_ptr() for p in planes]) for planes in streams]
+        self._planes = (ctypes.c_void_p * n)(*[ctypes.cast(r, ctypes.c_void_p) for r in self._rows])
+        self._outs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        self._caps = (ctypes.c_size_t * n)(*[o.numel() for o in outs])
+        self._lens = (ctypes.c_size_t * n)()
+        self._modes = np.zeros((n, T, A), np.uint8)
+        self._args = (ctypes.byref(self.layout), ctypes.byref(self._opt), n, T,
+                      ctypes.cast(self._planes, ctypes.c_void_p), ctypes.cast(self._outs, ctypes.c_void_p),
+                      ctypes.cast(self._caps, ctypes.c_void_p), ctypes.cast(self._lens, ctypes.c_void_p),
+                      self._modes.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+
+    def __call__(self):
+        """Returns (list of stream tensors, modes ndarray [n, T, A])."""
+        rc = lib().jiffy_encode_many(*self._args)
+        if rc:
+            raise JiffyError(rc, "jiffy_encode_many")
+        return [o[: self._lens[i]] for i, o in enumerate(self.outs)], self._modes
+
+    @property
+    def lengths(self):
+        return list(self._lens)
+
+
+class DecoderMany:
+    """jiffy_decode_many of streams of one layout and scan count into fixed
+    output planes, prepared once for fixed stream buffers."""
+
+    def __init__(self, layout: Layout, n_scans: int, ins, outs, stream=None):
+        if n_scans < 1:
+            raise ValueError("n_scans must be at least 1")
+        if not ins or len(ins) != len(outs):
+            raise ValueError("one list of output planes per stream is needed")
+        for i, (b, o) in enumerate(zip(ins, outs)):
+            _check_bytes_out(b, f"stream {i}")
+            _check_outs(layout, n_scans, o)
+        n = len(ins)
+        self.layout, self.T, self.ins, self.outs = layout, n_scans, list(ins), [list(o) for o in outs]
+        A = layout.n_attrs
+        self._rows = [(ctypes.c_void_p * A)(*[p.data_ptr() for p in o]) for o in outs]
+        self._planes = (ctypes.c_void_p * n)(*[ctypes.cast(r, ctypes.c_void_p) for r in self._rows])
+        self._ins = (ctypes.c_void_p * n)(*[b.data_ptr() for b in ins])
+        self._lens = (ctypes.c_size_t * n)(*[b.numel() for b in ins])
+        self._stream = _stream_handle(stream)
+
+    def __call__(self, lengths=None):
+        """Decodes every stream (its first lengths[s] bytes, else the whole
+        buffer) into the output planes; returns them."""
+        if lengths is not None:
+            for s, n in enumerate(lengths):
+                if not 0 < n <= self.ins[s].numel():
+                    raise ValueError(f"stream {s}: length {n} outside its buffer")
+                self._lens[s] = n
+        rc = lib().jiffy_decode_many(ctypes.byref(self.layout), len(self.ins), self.T,
+                                     ctypes.cast(self._ins, ctypes.c_void_p), ctypes.cast(self._lens, ctypes.c_void_p),
+                                     ctypes.cast(self._planes, ctypes.c_void_p), self._stream)
+        if rc:
+            raise JiffyError(rc, "jiffy_decode_many")
         return self.outs
 
 

@@ -125,6 +125,23 @@ int main(void) {
                                    NULL);
         expect(status_ok(rc), "standardize status", rc);
     }
+    /* the many-stream calls' argument checks */
+    for (int it = 0; it < 100000; ++it) {
+        jiffy_layout L = random_layout();
+        const uint32_t n = (uint32_t)(next_u64() % 4), T = (uint32_t)(next_u64() % 3 ? next_u64() % 40 : next_u64());
+        const void* pl[JIFFY_MAX_ATTRS] = {0};
+        const void* const* planes[4] = {pl, pl, pl, pl};
+        void* outs[4] = {0};
+        size_t caps[4] = {0}, lens[4] = {0};
+        jiffy_options opt = {(uint32_t)(next_u64() % 4), 0};
+        int rc = jiffy_encode_many(&L, &opt, n, T, it % 3 ? planes : NULL, outs, caps, lens, NULL, NULL);
+        expect(n ? rc == JIFFY_E_INVALID : status_ok(rc), "encode_many without planes", rc);
+        const void* ins[4] = {0};
+        size_t in_lens[4] = {0};
+        void* const* po[4] = {0};
+        rc = jiffy_decode_many(&L, n, T, it % 3 ? ins : NULL, in_lens, po, NULL);
+        expect(n && T ? rc == JIFFY_E_INVALID : status_ok(rc), "decode_many without streams", rc);
+    }
     for (int s = -10; s <= 2; ++s) expect(jiffy_status_string(s) != NULL, "status string", s);
     jiffy_tuning t = {(uint32_t)2, 0};
     expect(jiffy_set_tuning(&t) == JIFFY_E_INVALID, "tuning check", 0);
