@@ -9,9 +9,11 @@ seeded synthetic data standing in for the paper's recordings.  Each
 stream's first 20-scan scene period is generated on the host and replayed
 ten times on the device (scan 20k+i equals scan i; every 20th scan still
 follows a different view, so it is a scene cut).  One step encodes every
-stream's 200 scans (jiffy_encode, one call per stream) and decodes every
-stream back (jiffy_decode_layout); inputs and outputs stay in device
-memory.  A point is one pixel of one attribute, as in the paper's points/s
+stream's 200 scans and decodes every stream back, each in one launch
+sequence over all streams (jiffy_encode_many, jiffy_decode_many); inputs
+and outputs stay in device memory.  The same step is also timed as one
+jiffy_encode and one jiffy_decode_layout call per stream
+(`per_stream_calls`), whose streams must be the same bytes.  A point is one pixel of one attribute, as in the paper's points/s
 (Sec. IV-F).
 
 Further legs (each skippable):
@@ -249,69 +251,103 @@ def headline(args, host_period):
     npx = H * W
     lay = jiffy.make_layout(H, W, widths, precs)
     bound = jiffy.encode_bound(lay, T)
-    dev, outs, decs, encs, dcds = [], [], [], [], []
+    dev, outs, decs = [], [], []
     stream = torch.cuda.current_stream()
     for s in range(S):
         per = [torch.from_numpy(p.view(_STORE[p.dtype.itemsize])).cuda() for p in host_period[s]]
         dev.append([p.repeat(reps, 1, 1).contiguous() for p in per])
         outs.append(torch.empty(bound, dtype=torch.uint8, device="cuda"))
         decs.append([torch.empty_like(d) for d in dev[-1]])
-        encs.append(jiffy.Encoder(dev[-1], precs, out=outs[-1], stream=stream))
-        dcds.append(jiffy.Decoder(lay, T, decs[-1], stream=stream))
     log(f"headline: {S} streams x {T} scans of {H}x{W} resident ({S * T * npx * 4 / 1e9:.1f} GB of samples)")
     points = S * T * npx * A
+    # the step: every stream's records in one encode launch sequence, then one decode launch sequence
+    encm = jiffy.EncoderMany(dev, precs, outs=outs, stream=stream)
+    decm = jiffy.DecoderMany(lay, T, outs, decs, stream=stream)
 
     def step():
-        res = []
-        for s in range(S):
-            b, m = encs[s]()
-            dcds[s](b)
-            res.append((b, m))
-        return res
+        bs, m = encm()
+        decm(encm.lengths)
+        return bs, m
+
+    def timed(run_enc, run_dec, steps):
+        """Wall time of `steps` steps, and encode / decode time from events on the launch stream."""
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for ev in evs:
+            ev[0].record(stream)
+            run_enc()
+            ev[1].record(stream)
+            run_dec()
+            ev[2].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return (wall, sum(ev[0].elapsed_time(ev[1]) for ev in evs), sum(ev[1].elapsed_time(ev[2]) for ev in evs))
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * S + 1)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for ev in evs:
-        ev[0].record(stream)
-        for s in range(S):
-            b, _ = encs[s]()
-            ev[2 * s + 1].record(stream)
-            dcds[s](b)
-            ev[2 * s + 2].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    enc_ms = sum(ev[2 * s].elapsed_time(ev[2 * s + 1]) for ev in evs for s in range(S))
-    dec_ms = sum(ev[2 * s + 1].elapsed_time(ev[2 * s + 2]) for ev in evs for s in range(S))
+    wall, enc_ms, dec_ms = timed(encm, lambda: decm(encm.lengths), args.steps)
     ms_per_step = 1e3 * wall / args.steps
     log(f"headline: {args.steps} steps, {ms_per_step:.2f} ms/step")
 
     # the outputs of the last timed step: lossless round trip (precision 1)
-    streams_host, modes_all = [], []
-    for s in range(S):
-        n = encs[s]._n.value
-        streams_host.append(outs[s][:n].cpu().numpy().tobytes())
-        modes_all.append(encs[s]._modes[:T].copy())
-        for d, x in zip(decs[s], dev[s]):
-            if not torch.equal(d, x):
-                raise SystemExit(f"stream {s}: decode(encode(x)) != x")
+    lens = encm.lengths
+    streams_host = [outs[s][:lens[s]].cpu().numpy().tobytes() for s in range(S)]
+    modes_all = [encm._modes[s].copy() for s in range(S)]
+
+    def check_round_trip(what):
+        for s in range(S):
+            for d, x in zip(decs[s], dev[s]):
+                if not torch.equal(d, x):
+                    raise SystemExit(f"{what}: stream {s}: decode(encode(x)) != x")
+
+    check_round_trip("many-stream calls")
     stats = add_stats(stream_stats(b, widths, npx, precs) for b in streams_host)
     x_bytes = stats["x_bytes"]
     log(f"headline: {stats['stream_bytes']} bytes, ratio {x_bytes / stats['stream_bytes']:.2f}, "
         f"P-records {stats['p_items']} of {stats['p_items'] + stats['i_items']}")
 
+    # the same step as one jiffy_encode and one jiffy_decode_layout call per stream: same bytes
+    per_stream = None
+    if args.per_stream_steps > 0:
+        encs = [jiffy.Encoder(dev[s], precs, out=outs[s], stream=stream) for s in range(S)]
+        dcds = [jiffy.Decoder(lay, T, decs[s], stream=stream) for s in range(S)]
+        res1 = [None] * S
+
+        def enc1():
+            for s in range(S):
+                res1[s] = encs[s]()
+
+        def dec1():
+            for s in range(S):
+                dcds[s](res1[s][0])
+
+        for d in decs:
+            for t in d:
+                t.zero_()
+        enc1()
+        dec1()
+        w1, e1, d1 = timed(enc1, dec1, args.per_stream_steps)
+        for s in range(S):
+            if res1[s][0].cpu().numpy().tobytes() != streams_host[s] or not np.array_equal(res1[s][1], modes_all[s]):
+                raise SystemExit(f"stream {s}: jiffy_encode and jiffy_encode_many wrote different streams")
+        check_round_trip("per-stream calls")
+        n1 = args.per_stream_steps
+        per_stream = {"points_per_s": round(points / (w1 / n1), 1), "ms_per_step": round(1e3 * w1 / n1, 3),
+                      "encode_points_per_s": round(points / (e1 / n1 / 1e3), 1),
+                      "decode_points_per_s": round(points / (d1 / n1 / 1e3), 1), "steps": n1,
+                      "same_bytes": True}
+        log(f"headline per-stream calls: {1e3 * w1 / n1:.2f} ms/step")
+        del encs, dcds, res1
+
     kernels = {}
     if args.profile_steps > 0:
         kernels = kernel_profile(step, args.profile_steps)
 
-    def alg(name):  # per launch: one stream per launch of every kernel
-        if name.startswith("k_enc"):
-            return (stats["x_bytes"] + stats["p_bytes"] + stats["stream_bytes"]) // S
-        if name.startswith("k_dec"):
-            return (stats["stream_bytes"] + stats["x_bytes"] + stats["p_bytes"]) // S
+    def alg(name):  # per launch: every launch covers every stream's records
+        if name.startswith("k_enc") or name.startswith("k_dec"):
+            return stats["x_bytes"] + stats["p_bytes"] + stats["stream_bytes"]
         return None
 
     path_alg = 2 * (x_bytes + stats["p_bytes"] + stats["stream_bytes"])
@@ -322,7 +358,8 @@ def headline(args, host_period):
         "config": {"workload": f"stress-128x4096-drone-range-1mm: {S} streams x {T} scans of {H}x{W} range u32, "
                                f"precision 1 mm, 60% zeros, 5-15 deg/scan, scene cut every {SCENE_PERIOD} scans "
                                f"(each stream's first {SCENE_PERIOD}-scan period generated and replayed {reps}x); "
-                               "encode+decode of every stream per step",
+                               "encode+decode of every stream per step (one jiffy_encode_many and one "
+                               "jiffy_decode_many call)",
                    "streams": S, "scans": T, "height": H, "width": W, "attributes": ["range"], "precision_mm": 1},
         "encode_points_per_s": round(points / (enc_ms / args.steps / 1e3), 1),
         "decode_points_per_s": round(points / (dec_ms / args.steps / 1e3), 1),
@@ -331,13 +368,15 @@ def headline(args, host_period):
         "path_alg_gbps": round(path_alg / (wall / args.steps) / 1e9, 1),
         "path_hbm_frac": round(path_alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
     }
+    if per_stream:
+        result["per_stream_calls"] = per_stream
     if kernels:
         result["roofline"] = roofline(kernels, alg, "stress")
         result["kernels_ms"] = {k: round(v["avg_ms"], 4)
                                 for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_ms"])}
     ctx = dict(streams=streams_host, modes=modes_all, S=S, T=T, precs=precs)
     # free the device buffers of this leg before the next
-    del dev, outs, decs, encs, dcds
+    del dev, outs, decs, encm, decm
     torch.cuda.empty_cache()
     return result, ctx
 
@@ -961,6 +1000,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--profile-steps", type=int, default=1, help="steps timed per kernel with HIP events")
+    ap.add_argument("--per-stream-steps", type=int, default=3,
+                    help="headline steps also timed as one encode and one decode call per stream (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (counter calibration)")
     ap.add_argument("--traffic", nargs=5, metavar=("WORKLOAD", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
