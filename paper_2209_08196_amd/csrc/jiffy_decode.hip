@@ -672,7 +672,8 @@ __global__ __launch_bounds__(kMaskWaves * 64) void k_dec_mask(DecPlan plan) {
     if (bad) atomicOr(plan.err, kErrCorrupt);
 }
 
-constexpr uint32_t kDecThreads = 320;                 // 80 quads: enough for the 65 frames a tile can touch
+constexpr uint32_t kDecTileFrames = kDecTileVals / kFrame + 1;         // frames a tile's values can touch
+constexpr uint32_t kDecThreads = (4 * kDecTileFrames + 63) / 64 * 64;  // a quad per frame, in whole waves
 constexpr uint32_t kFrameMaxWords = 160;              // a frame's packed bytes are at most 640
 
 // ---------------------------------------------------------------------------
@@ -772,9 +773,9 @@ constexpr uint64_t kStAgg = 1ull << 32, kStIncl = 2ull << 32;  // look-back stat
 
 template <class R>
 struct DecTileLds {
-    R rows[kTileFrames * RowT<R>::kElems];
-    uint32_t info[kTileFrames];
-    uint32_t offs[kTileFrames + 1][3];  // frame offsets in the three sections
+    R rows[kDecTileFrames * RowT<R>::kElems];
+    uint32_t info[kDecTileFrames];
+    uint32_t offs[kDecTileFrames + 1][3];  // frame offsets in the three sections
     uint32_t scratch[8];
     uint32_t ticket, base, bad;
 };
@@ -930,7 +931,7 @@ template <int WB, class R>
 __device__ __forceinline__ void dec_tile_scatter(const DecItem& it, uint32_t p0, uint32_t bits, uint32_t own,
                                                  uint32_t k, uint32_t jf, const DecTileLds<R>& L) {
     static_assert(RowT<R>::kElems == 128 + 4 * RowT<R>::kPad, "a row is 128 values and four pads");
-    constexpr uint32_t kLast = kTileFrames * RowT<R>::kElems - 1;
+    constexpr uint32_t kLast = kDecTileFrames * RowT<R>::kElems - 1;
     const uint32_t rbase = RowT<R>::kElems * jf;
     uint32_t v[32];
 #pragma unroll

@@ -649,8 +649,7 @@ __device__ void enc_lookback(JG uint64_t* st, uint32_t lt, uint32_t cnt, uint32_
 
 template <int WB>
 __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
-                                              TileLds& L) {
-    const uint32_t mode = plan.res[r].mode;
+                                              uint32_t mode, TileLds& L) {
     const uint32_t m = low_mask32(it.bits);
     const uint32_t tid = threadIdx.x;
     const uint32_t p0 = lt * kFTile + tid * 32;
@@ -703,9 +702,12 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
     }
     __syncthreads();
     const uint32_t kb = L.kb;
-    // the residual before the tile's first value: its load overlaps the compaction
+    // the residual before the tile's first value, needed only when that value
+    // starts a frame (else the frame's predecessor is a value of this tile, or
+    // the frame crosses into the tile and its start stages the predecessor);
+    // its load overlaps the compaction
     const uint32_t tp = L.tp;
-    const uint32_t pred_v = (tid == 0 && tp) ? residual_at<WB>(it, mode, tp - 1, m) : 0u;
+    const uint32_t pred_v = (tid == 0 && tp && !(kb & 127u)) ? residual_at<WB>(it, mode, tp - 1, m) : 0u;
     // the record's size is known in its last tile only: elsewhere a frame that
     // runs past the tile's values is taken to continue in a later tile (if it
     // is the record's last, the fixup workgroups code it)
@@ -758,12 +760,13 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
                     it.slots + (size_t)j * kSlotBytes, it.blkinfo + j);
 }
 
+// mode: the record's trial result (0 = I, 1 = P)
 __device__ __forceinline__ void enc_tile_item(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
-                                              TileLds& lds) {
+                                              uint32_t mode, TileLds& lds) {
     switch (it.wb) {
-        case 4: enc_tile_body<4>(plan, it, r, lt, lds); break;
-        case 2: enc_tile_body<2>(plan, it, r, lt, lds); break;
-        default: enc_tile_body<1>(plan, it, r, lt, lds); break;
+        case 4: enc_tile_body<4>(plan, it, r, lt, mode, lds); break;
+        case 2: enc_tile_body<2>(plan, it, r, lt, mode, lds); break;
+        default: enc_tile_body<1>(plan, it, r, lt, mode, lds); break;
     }
 }
 
@@ -775,13 +778,14 @@ __global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
     const EncItem it = plan.items[r];
     __shared__ TileLds lds;
     if (threadIdx.x == 0) lds.ticket = atomicAdd(it.tctr, 1u);
+    const uint32_t mode = plan.res[r].mode;  // requested with the ticket
     __syncthreads();
     const uint32_t lt = lds.ticket;
     if (lt >= it.ntiles) {  // never expected: the record's ticket counter was not cleared
         if (threadIdx.x == 0) atomicOr(plan.err, kErrStall);
         return;
     }
-    enc_tile_item(plan, it, r, lt, lds);
+    enc_tile_item(plan, it, r, lt, mode, lds);
 }
 
 // The frames that cross tile boundaries: one quad per tile entry, the tile
@@ -1398,7 +1402,7 @@ __device__ __forceinline__ void fused_trial(const EncPlan& plan, uint32_t r) {
 }
 __device__ __forceinline__ void fused_tile(const EncPlan& plan, uint32_t r, uint32_t lt) {
     const EncItem it = plan.items[r];
-    enc_tile_item(plan, it, r, lt, fused_lds.tile);
+    enc_tile_item(plan, it, r, lt, plan.res[r].mode, fused_lds.tile);
 }
 __device__ __forceinline__ void fused_mframe(const EncPlan& plan, uint32_t r) { enc_mframe_item(plan, r, fused_lds.mf); }
 __device__ __forceinline__ void fused_fixup(const EncPlan& plan, uint32_t t0) { enc_fixup_quads(plan, t0, fused_lds.fix); }
