@@ -672,7 +672,7 @@ __global__ __launch_bounds__(kMaskWaves * 64) void k_dec_mask(DecPlan plan) {
     if (bad) atomicOr(plan.err, kErrCorrupt);
 }
 
-constexpr uint32_t kDecTileFrames = kDecTileVals / kFrame + 1;         // frames a tile's values can touch
+constexpr uint32_t kDecTileFrames = (kDecTileVals + 2 * kFrame - 2) / kFrame;  // frames a tile's values can touch
 constexpr uint32_t kDecThreads = (4 * kDecTileFrames + 63) / 64 * 64;  // a quad per frame, in whole waves
 constexpr uint32_t kFrameMaxWords = 160;              // a frame's packed bytes are at most 640
 
@@ -753,8 +753,8 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
 // i mod n); the tile within the record is taken in arrival order (a ticket),
 // so every tile a workgroup waits for has started, and workgroups past the
 // record's tile count leave at once.
-//   1. the tile's pixels' valid bits (32 pixels per chunk, a run of chunks
-//      per thread) and the frames' widths and offsets are loaded;
+//   1. the tile's valid pixels are counted per segment (a wave's store,
+//      below) and the frames' widths and offsets are loaded;
 //   2. four lanes per frame unpack the low bits (lane q: values 32q..32q+31,
 //      its b payload words loaded straight from the record into registers)
 //      into the frame's LDS row, patch the exceptions' high parts in, and
@@ -764,16 +764,40 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
 //      look-back: each tile publishes its own sum, then the running sum
 //      through it);
 //   4. the tile's pixels are written: the k-th valid pixel gets value k,
-//      the others zero; the chunks at the tile's two ends write only the
-//      tile's own pixels.
+//      the others zero.  A wave writes a segment of contiguous bytes at a
+//      time (lane l its l-th 16 bytes), so each store covers whole cache
+//      lines; the groups at the tile's two ends write only the tile's own
+//      pixels.
 // For a P-scan the values are differences to the previous scan (added by
 // k_dec_temporal); for P > 1 they are quantized (restored there too).
 // ---------------------------------------------------------------------------
 constexpr uint64_t kStAgg = 1ull << 32, kStIncl = 2ull << 32;  // look-back status flags
 
+// The pixels are written by segments of 64 lane groups: a lane group is the
+// 16 bytes of output one lane stores at once (16 / WB pixels), so one wave's
+// store covers a segment's whole contiguous bytes.
+template <int WB> struct SegT {
+    static constexpr uint32_t kGroup = 16 / WB;              // pixels per lane
+    static constexpr uint32_t kPx = kWave * kGroup;          // pixels per segment (a multiple of 64)
+    static constexpr uint32_t kWords = kPx / 64;             // valid-pixel words per segment
+};
+constexpr uint32_t kDecSegs = kDecBlockPx / SegT<4>::kPx + 1;   // segments a tile touches, at most (any WB)
+constexpr uint32_t kSegsPerThread = (kDecSegs + kDecThreads - 1) / kDecThreads;  // counted by one thread
+
+// Valid-pixel word of a tile holding pixel p (a multiple of 64), its bits
+// outside the tile's pixels [ps, pe) cleared; 0 past the tile.
+__device__ __forceinline__ uint64_t tile_word(const DecItem& it, const DecTile& D, uint32_t p) {
+    if (p >= D.pe || p + 64u <= D.ps) return 0;  // (a shift of 64 or more is undefined)
+    uint64_t w = it.vw[p >> 6];
+    if (p < D.ps) w &= ~0ull << (D.ps - p);
+    if (D.pe - p < 64u) w &= (1ull << (D.pe - p)) - 1ull;
+    return w;
+}
+
 template <class R>
 struct DecTileLds {
     R rows[kDecTileFrames * RowT<R>::kElems];
+    uint32_t segbase[kDecSegs];      // value index of each segment's first valid pixel
     uint32_t info[kDecTileFrames];
     uint32_t offs[kDecTileFrames + 1][3];  // frame offsets in the three sections
     uint32_t scratch[8];
@@ -921,38 +945,42 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
     }
 }
 
-// Value k sits at row element tword(k, jf) = k + kPad (k >> 5) - kElems jf (a
-// row holds 128 values and kPad pad elements per 32).  Every pixel's read is
-// issued, without a branch (a pixel without a value reads the next value's
-// element, clamped to the rows), and its zero selected afterwards.  `own`
-// marks the chunk's pixels that belong to the tile: a whole chunk is
-// written with vector stores, a chunk at the tile's ends pixel by pixel.
+// Value k sits at row element k + kPad (k >> 5) - kElems jf (a row holds
+// 128 values and kPad pad elements per 32).  A lane's group of pixels
+// starts at pixel p0; bit i of `bits` marks pixel p0 + i valid (only the
+// tile's own pixels can be), k is the value of its first valid pixel.
+// Every pixel's read is issued, without a branch (a pixel without a value
+// reads the next value's element, clamped to the rows), and its zero
+// selected afterwards.  A group wholly inside the tile is written with one
+// 16-byte store; a group at the tile's ends pixel by pixel, its own pixels
+// only.
 template <int WB, class R>
-__device__ __forceinline__ void dec_tile_scatter(const DecItem& it, uint32_t p0, uint32_t bits, uint32_t own,
-                                                 uint32_t k, uint32_t jf, const DecTileLds<R>& L) {
+__device__ __forceinline__ void dec_group_store(const DecItem& it, const DecTile& D, uint32_t p0, uint32_t bits,
+                                                uint32_t k, uint32_t jf, const DecTileLds<R>& L) {
     static_assert(RowT<R>::kElems == 128 + 4 * RowT<R>::kPad, "a row is 128 values and four pads");
+    constexpr uint32_t G = SegT<WB>::kGroup;
     constexpr uint32_t kLast = kDecTileFrames * RowT<R>::kElems - 1;
+    using T = typename SampleT<WB>::T;
     const uint32_t rbase = RowT<R>::kElems * jf;
-    uint32_t v[32];
+    uint32_t v[G];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) {
+    for (uint32_t i = 0; i < G; ++i) {
         const uint32_t on = (bits >> i) & 1u;
         const uint32_t x = L.rows[min(k + RowT<R>::kPad * (k >> 5) - rbase, kLast)];
         v[i] = on ? x : 0u;
         k += on;
     }
-    if (own == ~0u) {
-        store16<WB>(it.out, p0, it.npx, it.aligned16, v);
-        store16<WB>(it.out, p0 + 16, it.npx, it.aligned16, v + 16);
-    } else {
-        using T = typename SampleT<WB>::T;
+    if (p0 >= D.ps && p0 + G <= D.pe && it.aligned16) {
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int i = 0; i < 32; ++i)
-            if ((own >> i) & 1u) ((T*)it.out)[p0 + i] = (T)v[i];
+        for (uint32_t i = 0; i < G; ++i) w[i * WB / 4] |= (v[i] & low_mask32(8 * WB)) << (8 * ((i * WB) & 3));
+        *(uint4*)((T*)it.out + p0) = make_uint4(w[0], w[1], w[2], w[3]);
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < G; ++i)
+            if (p0 + i >= D.ps && p0 + i < D.pe) ((T*)it.out)[p0 + i] = (T)v[i];
     }
 }
-
-constexpr uint32_t kDecChunks = (kDecBlockPx / 32 + 1 + kDecThreads - 1) / kDecThreads;  // chunks per thread, at most
 
 // R: the row element; the workgroups serve the n records rec_list[first ..]
 // (one instantiation per sample width WB: a single store path each)
@@ -976,26 +1004,20 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
     const uint32_t kb = D.kb, ke = D.ke;
     const uint32_t jf = kb >> 7;
     const uint32_t nf = ke > kb ? ((ke - 1) >> 7) - jf + 1 : 0u;  // frames the tile's values lie in
-    // 1. everything the tile reads, issued together: its pixels' valid bits
-    // (chunks of 32 pixels from the one holding its first pixel, a run of
-    // consecutive chunks per thread, masked to the tile), the frames' metadata
-    const uint32_t cs = D.ps & ~31u, nch = div_up(D.pe - cs, 32u), per = div_up(nch, kDecThreads);
-    // the tile's own pixels in chunk c
-    auto own_bits = [&](uint32_t p) -> uint32_t {
-        uint32_t own = ~0u;
-        if (p < D.ps) own &= ~0u << (D.ps - p);
-        if (D.pe - p < 32u) own &= (1u << (D.pe - p)) - 1u;
-        return own;
-    };
-    uint32_t pb[kDecChunks];
-    uint32_t cnt = 0;
+    // 1. everything the tile reads, issued together: the valid pixels of
+    // one segment per thread (from the segment holding the tile's first
+    // pixel), the frames' metadata
+    constexpr uint32_t S = SegT<WB>::kPx;
+    const uint32_t P0 = D.ps & ~(S - 1u), nseg = div_up(D.pe - P0, S);
+    uint32_t sc[kSegsPerThread];  // thread t counts segments t kSegsPerThread ..
 #pragma unroll
-    for (uint32_t u = 0; u < kDecChunks; ++u) {
-        const uint32_t c = tid * per + u, p = cs + 32u * c;
-        uint32_t bits = 0;
-        if (u < per && c < nch) bits = (uint32_t)(it.vw[p >> 6] >> (32 * ((p >> 5) & 1))) & own_bits(p);
-        pb[u] = bits;
-        cnt += __popc(bits);
+    for (uint32_t u = 0; u < kSegsPerThread; ++u) {
+        const uint32_t sg = tid * kSegsPerThread + u;
+        sc[u] = 0;
+        if (sg < nseg) {
+#pragma unroll
+            for (uint32_t j = 0; j < SegT<WB>::kWords; ++j) sc[u] += __popcll(tile_word(it, D, P0 + sg * S + 64u * j));
+        }
     }
     if (tid <= nf && nf) {
         const uint32_t j = jf + tid;
@@ -1035,16 +1057,32 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
         for (int i = 0; i < 32; ++i) d[i] = (v0 + d[i]) & m;
         row_put<R>(L.rows + g * RowT<R>::kElems, q, d);
     }
-    // 4. the tile's pixels: the k-th valid pixel gets value k
-    uint32_t total;
-    uint32_t k = kb + block_excl_scan<kDecThreads>(cnt, L.scratch, &total);  // also a barrier
+    // 4. the tile's pixels: the k-th valid pixel gets value k.  The value
+    // index of each segment's first valid pixel, then each wave takes
+    // segments in turn, lane l the l-th group of pixels
+    uint32_t total, sc_all = 0;
 #pragma unroll
-    for (uint32_t u = 0; u < kDecChunks; ++u) {
-        const uint32_t c = tid * per + u, p = cs + 32u * c;
-        if (u < per && c < nch) {
-            dec_tile_scatter<WB, R>(it, p, pb[u], own_bits(p), k, jf, L);
-            k += __popc(pb[u]);
-        }
+    for (uint32_t u = 0; u < kSegsPerThread; ++u) sc_all += sc[u];
+    uint32_t sb = kb + block_excl_scan<kDecThreads>(sc_all, L.scratch, &total);
+#pragma unroll
+    for (uint32_t u = 0; u < kSegsPerThread; ++u) {
+        if (tid * kSegsPerThread + u < nseg) L.segbase[tid * kSegsPerThread + u] = sb;
+        sb += sc[u];
+    }
+    __syncthreads();
+    constexpr uint32_t G = SegT<WB>::kGroup, kStep = kDecThreads / kWave;
+    const uint32_t l = tid % kWave;
+    // lane l's word of its next segment is requested while it works on one
+    auto seg_word = [&](uint32_t sg) { return tile_word(it, D, (P0 + sg * S + l * G) & ~63u); };
+    uint64_t next = seg_word(tid / kWave);
+    for (uint32_t sg = tid / kWave; sg < nseg; sg += kStep) {
+        const uint64_t w = next;
+        if (sg + kStep < nseg) next = seg_word(sg + kStep);
+        const uint32_t bits = (uint32_t)(w >> ((l * G) & 63u)) & low_mask32(G);
+        const uint32_t c = __popc(bits);
+        const uint32_t k = L.segbase[sg] + wave_incl_scan(c) - c;
+        const uint32_t p0 = P0 + sg * S + l * G;
+        if (p0 < D.pe) dec_group_store<WB, R>(it, D, p0, bits, k, jf, L);
     }
 }
 

@@ -116,7 +116,7 @@ struct EncOut {
 struct DecTile {
     uint32_t kb, ke, ps, pe;
 };
-constexpr uint32_t kDecTileVals = 8192;
+constexpr uint32_t kDecTileVals = 8064;  // 63 frames: a tile's values touch at most 64 frames, one per quad of 256 threads
 constexpr uint32_t kDecBlockPx = 65536;
 // tiles a record of npx pixels can have, at most
 inline __host__ __device__ uint32_t dec_tile_slots(uint32_t npx) {
