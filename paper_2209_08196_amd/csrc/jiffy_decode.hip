@@ -753,8 +753,7 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
 // i mod n); the tile within the record is taken in arrival order (a ticket),
 // so every tile a workgroup waits for has started, and workgroups past the
 // record's tile count leave at once.
-//   1. the tile's valid pixels are counted per segment (a wave's store,
-//      below) and the frames' widths and offsets are loaded;
+//   1. the frames' widths and offsets are loaded;
 //   2. four lanes per frame unpack the low bits (lane q: values 32q..32q+31,
 //      its b payload words loaded straight from the record into registers)
 //      into the frame's LDS row, patch the exceptions' high parts in, and
@@ -764,10 +763,11 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
 //      look-back: each tile publishes its own sum, then the running sum
 //      through it);
 //   4. the tile's pixels are written: the k-th valid pixel gets value k,
-//      the others zero.  A wave writes a segment of contiguous bytes at a
-//      time (lane l its l-th 16 bytes), so each store covers whole cache
-//      lines; the groups at the tile's two ends write only the tile's own
-//      pixels.
+//      the others zero.  Each wave writes a run of segments of contiguous
+//      bytes (lane l a segment's l-th 16 bytes), so each store covers whole
+//      cache lines; its valid-pixel words are requested before the
+//      look-back and held in registers.  The groups at the tile's two ends
+//      write only the tile's own pixels.
 // For a P-scan the values are differences to the previous scan (added by
 // k_dec_temporal); for P > 1 they are quantized (restored there too).
 // ---------------------------------------------------------------------------
@@ -779,10 +779,13 @@ constexpr uint64_t kStAgg = 1ull << 32, kStIncl = 2ull << 32;  // look-back stat
 template <int WB> struct SegT {
     static constexpr uint32_t kGroup = 16 / WB;              // pixels per lane
     static constexpr uint32_t kPx = kWave * kGroup;          // pixels per segment (a multiple of 64)
-    static constexpr uint32_t kWords = kPx / 64;             // valid-pixel words per segment
+    static constexpr uint32_t kWords = kPx / 64;             // valid-pixel words per segment (divides 64)
+    static constexpr uint32_t kSegs = kDecBlockPx / kPx + 1; // segments a tile touches, at most
+    // a wave's run of segments and its words, at most, and the words each lane holds
+    static constexpr uint32_t kRun = (kSegs + kDecThreads / kWave - 1) / (kDecThreads / kWave);
+    static constexpr uint32_t kSlots = (kRun * kWords + kWave - 1) / kWave;
+    static_assert(kWave % kWords == 0, "a segment's words lie in one slot");
 };
-constexpr uint32_t kDecSegs = kDecBlockPx / SegT<4>::kPx + 1;   // segments a tile touches, at most (any WB)
-constexpr uint32_t kSegsPerThread = (kDecSegs + kDecThreads - 1) / kDecThreads;  // counted by one thread
 
 // Valid-pixel word of a tile holding pixel p (a multiple of 64), its bits
 // outside the tile's pixels [ps, pe) cleared; 0 past the tile.
@@ -797,7 +800,6 @@ __device__ __forceinline__ uint64_t tile_word(const DecItem& it, const DecTile& 
 template <class R>
 struct DecTileLds {
     R rows[kDecTileFrames * RowT<R>::kElems];
-    uint32_t segbase[kDecSegs];      // value index of each segment's first valid pixel
     uint32_t info[kDecTileFrames];
     uint32_t offs[kDecTileFrames + 1][3];  // frame offsets in the three sections
     uint32_t scratch[8];
@@ -1004,21 +1006,7 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
     const uint32_t kb = D.kb, ke = D.ke;
     const uint32_t jf = kb >> 7;
     const uint32_t nf = ke > kb ? ((ke - 1) >> 7) - jf + 1 : 0u;  // frames the tile's values lie in
-    // 1. everything the tile reads, issued together: the valid pixels of
-    // one segment per thread (from the segment holding the tile's first
-    // pixel), the frames' metadata
-    constexpr uint32_t S = SegT<WB>::kPx;
-    const uint32_t P0 = D.ps & ~(S - 1u), nseg = div_up(D.pe - P0, S);
-    uint32_t sc[kSegsPerThread];  // thread t counts segments t kSegsPerThread ..
-#pragma unroll
-    for (uint32_t u = 0; u < kSegsPerThread; ++u) {
-        const uint32_t sg = tid * kSegsPerThread + u;
-        sc[u] = 0;
-        if (sg < nseg) {
-#pragma unroll
-            for (uint32_t j = 0; j < SegT<WB>::kWords; ++j) sc[u] += __popcll(tile_word(it, D, P0 + sg * S + 64u * j));
-        }
-    }
+    // 1. the frames' widths and offsets
     if (tid <= nf && nf) {
         const uint32_t j = jf + tid;
         if (j < rs.nb) {
@@ -1042,6 +1030,20 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
     if (g < nf)
         dec_unpack<R>(it, rs, L, (const JG uint32_t*)it.rec, g, q, kb, ke, jf, (rs.pay_off + L.offs[g][0]) >> 2,
                       rs.pos_off + L.offs[g][1], 8 * (rs.high_off + L.offs[g][2]), d, lane_sum);
+    // the tile's valid-pixel words, requested now and used in step 4: wave
+    // w writes the segments [s0, s1) (from the segment holding the tile's
+    // first pixel), whose words lane l holds from the l-th on, every 64th
+    constexpr uint32_t S = SegT<WB>::kPx, kW = SegT<WB>::kWords, kSlots = SegT<WB>::kSlots;
+    const uint32_t P0 = D.ps & ~(S - 1u), nseg = div_up(D.pe - P0, S);
+    const uint32_t wv = tid / kWave, l = tid % kWave, run = div_up(nseg, kDecThreads / kWave);
+    const uint32_t s0 = min(wv * run, nseg), s1 = min(s0 + run, nseg);
+    uint64_t held[kSlots];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kSlots; ++k) {
+        const uint32_t wi = s0 * kW + l + kWave * k;  // word index from P0
+        held[k] = wi < s1 * kW ? tile_word(it, D, P0 + 64u * wi) : 0ull;
+    }
     // 3. running sum: lanes are in value order (quads in frame order)
     uint32_t agg;
     const uint32_t excl = block_excl_scan<kDecThreads>(lane_sum, L.scratch, &agg);
@@ -1057,32 +1059,30 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
         for (int i = 0; i < 32; ++i) d[i] = (v0 + d[i]) & m;
         row_put<R>(L.rows + g * RowT<R>::kElems, q, d);
     }
-    // 4. the tile's pixels: the k-th valid pixel gets value k.  The value
-    // index of each segment's first valid pixel, then each wave takes
-    // segments in turn, lane l the l-th group of pixels
-    uint32_t total, sc_all = 0;
+    // 4. the tile's pixels: the k-th valid pixel gets value k.  A wave's
+    // first value follows the valid pixels of the waves before it; segment
+    // by segment, lane l takes the l-th group of pixels, its word fetched
+    // from the lane that holds it
 #pragma unroll
-    for (uint32_t u = 0; u < kSegsPerThread; ++u) sc_all += sc[u];
-    uint32_t sb = kb + block_excl_scan<kDecThreads>(sc_all, L.scratch, &total);
+    for (uint32_t k = 0; k < kSlots; ++k) cnt += __popcll(held[k]);
+    uint32_t total;
+    const uint32_t before = block_excl_scan<kDecThreads>(cnt, L.scratch, &total);
+    uint32_t next = kb + (uint32_t)__builtin_amdgcn_readfirstlane((int)before);  // lane 0's: the waves before
+    constexpr uint32_t G = SegT<WB>::kGroup;
+    for (uint32_t i = 0; s0 + i < s1; ++i) {
+        const uint32_t j = i * kW + l * G / 64, slot = i * kW / kWave;  // slot: the same for the whole wave
+        uint64_t h = held[0];
 #pragma unroll
-    for (uint32_t u = 0; u < kSegsPerThread; ++u) {
-        if (tid * kSegsPerThread + u < nseg) L.segbase[tid * kSegsPerThread + u] = sb;
-        sb += sc[u];
-    }
-    __syncthreads();
-    constexpr uint32_t G = SegT<WB>::kGroup, kStep = kDecThreads / kWave;
-    const uint32_t l = tid % kWave;
-    // lane l's word of its next segment is requested while it works on one
-    auto seg_word = [&](uint32_t sg) { return tile_word(it, D, (P0 + sg * S + l * G) & ~63u); };
-    uint64_t next = seg_word(tid / kWave);
-    for (uint32_t sg = tid / kWave; sg < nseg; sg += kStep) {
-        const uint64_t w = next;
-        if (sg + kStep < nseg) next = seg_word(sg + kStep);
+        for (uint32_t k = 1; k < kSlots; ++k)
+            if (slot == k) h = held[k];
+        const uint32_t src = j % kWave;
+        const uint64_t w = (uint64_t)(uint32_t)__shfl((int)(uint32_t)h, (int)src, kWave) |
+                           ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(h >> 32), (int)src, kWave) << 32);
         const uint32_t bits = (uint32_t)(w >> ((l * G) & 63u)) & low_mask32(G);
-        const uint32_t c = __popc(bits);
-        const uint32_t k = L.segbase[sg] + wave_incl_scan(c) - c;
-        const uint32_t p0 = P0 + sg * S + l * G;
-        if (p0 < D.pe) dec_group_store<WB, R>(it, D, p0, bits, k, jf, L);
+        const uint32_t c = __popc(bits), inc = wave_incl_scan(c);
+        const uint32_t p0 = P0 + (s0 + i) * S + l * G;
+        if (p0 < D.pe) dec_group_store<WB, R>(it, D, p0, bits, next + inc - c, jf, L);
+        next += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
     }
 }
 
