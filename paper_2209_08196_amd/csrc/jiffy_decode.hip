@@ -997,23 +997,41 @@ __global__ __launch_bounds__(kDecThreads) void k_dec_tiles(DecPlan plan, uint32_
         L.ticket = atomicAdd(it.tctr, 1u);
         L.bad = 0;
     }
+    // 1. the tile's descriptor and its frames' widths and offsets.  Workgroups
+    // usually arrive in index order, so those of the tile the index names are
+    // requested while the ticket (and the record's results) are on their way,
+    // and requested again only when the ticket names another tile (a guess
+    // past the record's tiles reads in-bounds words that are not used)
+    const DecRes rs = plan.res[r];
+    DecTile D;
+    uint32_t mo[4];  // the thread's frame: its three section offsets and its widths
+    auto tile_meta = [&](uint32_t t) {
+        D = it.tdesc[t];
+        const uint32_t j = (D.kb >> 7) + tid;
+        if (tid <= kDecTileFrames && j < it.maxnb) {
+            mo[0] = it.blkoffs[3 * j];
+            mo[1] = it.blkoffs[3 * j + 1];
+            mo[2] = it.blkoffs[3 * j + 2];
+            mo[3] = it.blkinfo[j];
+        }
+    };
+    const uint32_t guess = blockIdx.x / n;
+    tile_meta(min(guess, plan.nvt - 1u));
     __syncthreads();
     const uint32_t lt = L.ticket;
-    const DecRes rs = plan.res[r];
     if (lt >= rs.ntiles) return;  // more workgroups than the record has tiles
-    const DecTile D = it.tdesc[lt];
+    if (lt != guess) tile_meta(lt);
     const uint32_t m = low_mask32(it.bits);
     const uint32_t kb = D.kb, ke = D.ke;
     const uint32_t jf = kb >> 7;
     const uint32_t nf = ke > kb ? ((ke - 1) >> 7) - jf + 1 : 0u;  // frames the tile's values lie in
-    // 1. the frames' widths and offsets
     if (tid <= nf && nf) {
         const uint32_t j = jf + tid;
         if (j < rs.nb) {
-            L.offs[tid][0] = it.blkoffs[3 * j];
-            L.offs[tid][1] = it.blkoffs[3 * j + 1];
-            L.offs[tid][2] = it.blkoffs[3 * j + 2];
-            if (tid < nf) L.info[tid] = it.blkinfo[j];
+            L.offs[tid][0] = mo[0];
+            L.offs[tid][1] = mo[1];
+            L.offs[tid][2] = mo[2];
+            if (tid < nf) L.info[tid] = mo[3];
         } else {  // the ends of the sections
             L.offs[tid][0] = rs.pos_off - rs.pay_off;
             L.offs[tid][1] = rs.high_off - rs.pos_off;

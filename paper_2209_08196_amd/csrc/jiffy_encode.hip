@@ -647,17 +647,25 @@ __device__ void enc_lookback(JG uint64_t* st, uint32_t lt, uint32_t cnt, uint32_
     lp_before = el;
 }
 
+// A thread's 32 samples of tile lt.
 template <int WB>
-__device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
-                                              uint32_t mode, TileLds& L) {
-    const uint32_t m = low_mask32(it.bits);
-    const uint32_t tid = threadIdx.x;
-    const uint32_t p0 = lt * kFTile + tid * 32;
-    uint32_t s[32];
-    uint32_t keep = 0;
+__device__ __forceinline__ void enc_tile_load(const EncItem& it, uint32_t lt, uint32_t s[32]) {
+    const uint32_t p0 = lt * kFTile + threadIdx.x * 32;
     if (p0 < it.npx) {
         load16<WB>(it.x, p0, it.npx, it.aligned16, s);
         load16<WB>(it.x, p0 + 16, it.npx, it.aligned16, s + 16);
+    }
+}
+
+// s: the thread's samples, as enc_tile_load gives them
+template <int WB>
+__device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
+                                              uint32_t mode, TileLds& L, uint32_t s[32]) {
+    const uint32_t m = low_mask32(it.bits);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t p0 = lt * kFTile + tid * 32;
+    uint32_t keep = 0;
+    if (p0 < it.npx) {
         uint32_t xp[32];
         if (mode) {
             load16<WB>(it.xprev, p0, it.npx, it.aligned16, xp);
@@ -760,32 +768,63 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
                     it.slots + (size_t)j * kSlotBytes, it.blkinfo + j);
 }
 
+template <int WB>
+__device__ __forceinline__ void enc_tile_run(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
+                                             uint32_t mode, TileLds& lds) {
+    uint32_t s[32];
+    enc_tile_load<WB>(it, lt, s);
+    enc_tile_body<WB>(plan, it, r, lt, mode, lds, s);
+}
+
 // mode: the record's trial result (0 = I, 1 = P)
 __device__ __forceinline__ void enc_tile_item(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
                                               uint32_t mode, TileLds& lds) {
     switch (it.wb) {
-        case 4: enc_tile_body<4>(plan, it, r, lt, mode, lds); break;
-        case 2: enc_tile_body<2>(plan, it, r, lt, mode, lds); break;
-        default: enc_tile_body<1>(plan, it, r, lt, mode, lds); break;
+        case 4: enc_tile_run<4>(plan, it, r, lt, mode, lds); break;
+        case 2: enc_tile_run<2>(plan, it, r, lt, mode, lds); break;
+        default: enc_tile_run<1>(plan, it, r, lt, mode, lds); break;
     }
 }
 
-__global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
-    // the record is fixed by the workgroup index; the tile within it is taken
-    // in arrival order, so every tile a workgroup waits for has started
-    uint32_t lt_unused;
-    const uint32_t r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, blockIdx.x, lt_unused);
-    const EncItem it = plan.items[r];
-    __shared__ TileLds lds;
-    if (threadIdx.x == 0) lds.ticket = atomicAdd(it.tctr, 1u);
-    const uint32_t mode = plan.res[r].mode;  // requested with the ticket
+// The record is fixed by the workgroup index; the tile within it is taken
+// in arrival order (a ticket), so every tile a workgroup waits for has
+// started.  With records of one size the workgroups are laid out tile-major
+// (workgroup i serves record i mod n), so a record's tiles arrive far apart
+// and, as workgroups usually arrive in index order, in order: the samples
+// of the tile the index names are requested while the ticket is on its way,
+// and requested again only when the ticket names another tile.
+template <int WB>
+__device__ __forceinline__ void enc_tile_ticketed(const EncPlan& plan, const EncItem& it, uint32_t r,
+                                                  uint32_t lt_guess, uint32_t mode, TileLds& lds) {
+    uint32_t s[32];
+    if (lt_guess < it.ntiles) enc_tile_load<WB>(it, lt_guess, s);
     __syncthreads();
     const uint32_t lt = lds.ticket;
     if (lt >= it.ntiles) {  // never expected: the record's ticket counter was not cleared
         if (threadIdx.x == 0) atomicOr(plan.err, kErrStall);
         return;
     }
-    enc_tile_item(plan, it, r, lt, mode, lds);
+    if (lt != lt_guess) enc_tile_load<WB>(it, lt, s);
+    enc_tile_body<WB>(plan, it, r, lt, mode, lds, s);
+}
+
+__global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
+    uint32_t lt_guess, r;
+    if (plan.ftpi) {
+        r = blockIdx.x % plan.n_items;
+        lt_guess = blockIdx.x / plan.n_items;
+    } else {
+        r = tile_owner(plan.ftile_item, plan.ftile_first, plan.ftpi, blockIdx.x, lt_guess);
+    }
+    const EncItem it = plan.items[r];
+    __shared__ TileLds lds;
+    if (threadIdx.x == 0) lds.ticket = atomicAdd(it.tctr, 1u);
+    const uint32_t mode = plan.res[r].mode;  // requested with the ticket
+    switch (it.wb) {
+        case 4: enc_tile_ticketed<4>(plan, it, r, lt_guess, mode, lds); break;
+        case 2: enc_tile_ticketed<2>(plan, it, r, lt_guess, mode, lds); break;
+        default: enc_tile_ticketed<1>(plan, it, r, lt_guess, mode, lds); break;
+    }
 }
 
 // The frames that cross tile boundaries: one quad per tile entry, the tile
