@@ -891,21 +891,30 @@ def profile_summary(title, stats_csv, workload=None, sq_dirs=()):
 
 def _counter_means(folder, counter):
     """Mean per dispatch of one counter, per kernel name, from a rocprofv3
-    --pmc csv folder (values summed over the dispatch's rows)."""
+    --pmc csv folder (values summed over the dispatch's rows), over the
+    kernel's dispatches of its largest grid: the launch shape of the timed
+    step (a leg's smaller launches, such as one scan per launch, are left
+    out)."""
     import csv
     import glob
     files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise SystemExit(f"no counter csv under {folder}")
-    per = {}
+    per, grid = {}, {}
     for row in csv.DictReader(open(files[0])):
         if row["Counter_Name"] != counter:
             continue
         name = _kernel_key(row["Kernel_Name"])
         key = (name, row["Dispatch_Id"])
         per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+        grid[key] = int(row["Grid_Size"])
+    top = {}
+    for (name, d), g in grid.items():
+        top[name] = max(top.get(name, 0), g)
     out = {}
-    for (name, _), v in per.items():
+    for (name, d), v in per.items():
+        if grid[(name, d)] != top[name]:
+            continue
         t = out.setdefault(name, [0.0, 0])
         t[0] += v
         t[1] += 1
