@@ -607,17 +607,25 @@ __device__ __forceinline__ uint32_t es_lp(uint64_t s) { return (uint32_t)(s >> 3
 // nearest one whose running values are known, 64 tiles per round.  Returns
 // the running count before the tile in cnt_before and the last in-range
 // pixel plus 1 before it in lp_before.
+// Lane l: the state of tile end - 1 - l (before the first tile: nothing).
+__device__ __forceinline__ uint64_t enc_lookback_poll(const JG uint64_t* st, uint32_t end) {
+    const int idx = (int)end - 1 - (int)lane_id();
+    return idx >= 0 ? __hip_atomic_load(st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kEsIncl;
+}
+
+// first: the first round's states when polled earlier (a state only moves
+// from empty to aggregate to inclusive, so an early read is as valid as a
+// late one), has_first whether it was
 __device__ void enc_lookback(JG uint64_t* st, uint32_t lt, uint32_t cnt, uint32_t lp, JG uint32_t* err,
-                             uint32_t& cnt_before, uint32_t& lp_before) {
+                             uint32_t& cnt_before, uint32_t& lp_before, uint64_t first, bool has_first) {
     const uint32_t l = lane_id();
     if (l == 0)
         __hip_atomic_store(st + lt, (lt ? kEsAgg : kEsIncl) | cnt | ((uint64_t)lp << 31), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     uint32_t ec = 0, el = 0, end = lt, spins = 0;  // tiles [0, end) not combined yet
     while (end > 0) {
-        const int idx = (int)end - 1 - (int)l;  // lane 0: the nearest
-        uint64_t s = kEsIncl;                    // before the first tile: nothing
-        if (idx >= 0) s = __hip_atomic_load(st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t s = has_first ? first : enc_lookback_poll(st, end);
+        has_first = false;
         const uint64_t f = s & (kEsAgg | kEsIncl);
         const uint64_t incl = ballot(f == kEsIncl), empty = ballot(f == 0);
         const uint32_t fi = incl ? (uint32_t)__builtin_ctzll(incl) : 64u;
@@ -658,9 +666,11 @@ __device__ __forceinline__ void enc_tile_load(const EncItem& it, uint32_t lt, ui
 }
 
 // s: the thread's samples, as enc_tile_load gives them
+// first_poll: wave 0's first look-back round when has_poll (see enc_lookback)
 template <int WB>
 __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem& it, uint32_t r, uint32_t lt,
-                                              uint32_t mode, TileLds& L, uint32_t s[32]) {
+                                              uint32_t mode, TileLds& L, uint32_t s[32], uint64_t first_poll = 0,
+                                              bool has_poll = false) {
     const uint32_t m = low_mask32(it.bits);
     const uint32_t tid = threadIdx.x;
     const uint32_t p0 = lt * kFTile + tid * 32;
@@ -698,7 +708,7 @@ __device__ __forceinline__ void enc_tile_body(const EncPlan& plan, const EncItem
     // in-range samples and the last in-range pixel before this tile, from the tiles before it
     if (tid < kWave) {
         uint32_t kb_w, tp_w;
-        enc_lookback(it.tstat, lt, nv, lp_tile, plan.err, kb_w, tp_w);
+        enc_lookback(it.tstat, lt, nv, lp_tile, plan.err, kb_w, tp_w, first_poll, has_poll);
         if (tid == 0) {
             L.kb = kb_w;
             L.tp = tp_w;  // the pixel after the last in-range one before the tile (0: none)
@@ -805,7 +815,11 @@ __device__ __forceinline__ void enc_tile_ticketed(const EncPlan& plan, const Enc
         return;
     }
     if (lt != lt_guess) enc_tile_load<WB>(it, lt, s);
-    enc_tile_body<WB>(plan, it, r, lt, mode, lds, s);
+    // the tiles before this one were dispatched long before (tile-major), so
+    // one early read of their states usually settles the look-back
+    uint64_t poll = 0;
+    if (threadIdx.x < kWave) poll = enc_lookback_poll(it.tstat, lt);
+    enc_tile_body<WB>(plan, it, r, lt, mode, lds, s, poll, true);
 }
 
 __global__ __launch_bounds__(256) void k_enc_tiles(EncPlan plan) {
