@@ -1229,10 +1229,14 @@ __global__ __launch_bounds__(1024) void k_enc_offsets(EncPlan plan) {
 // workgroup per (part, record).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void enc_assemble_item(const EncPlan& plan, uint32_t r, uint32_t part) {
+    // the record's results are requested with its item, so that a part past
+    // the record's frames (most of the grid for a sparse record) leaves after
+    // one round trip
+    const EncRes rs = plan.res[r];
     const EncItem it = plan.items[r];
+    if (part > 0 && (part - 1) * kAsmFrames >= rs.nb) return;
     const EncOut& o = plan.outs[it.out_id];
     if (!o.ok) return;
-    EncRes rs = plan.res[r];
     // the record lies inside the output and has at most maxnb frames (always, unless a bounded wait ran out)
     if (rs.rec_off + rs.rec_len > o.cap || rs.nb > it.maxnb) return;
     uint8_t* rec = o.base + rs.rec_off;
