@@ -889,6 +889,8 @@ __device__ __forceinline__ void unpack_lane(const JG uint32_t* w, uint32_t b, ui
 }
 #undef JIFFY_UNPACK_CASE
 
+constexpr uint32_t kExPre = 4;  // exceptions per lane requested with the frame's payload
+
 // Four lanes unpack frame jf + g from the record's words: pay_w is the
 // frame's first payload word, pos_b its first exception-position byte,
 // high_bit its first high-part bit.  d gets the lane's running sum of the
@@ -903,26 +905,47 @@ __device__ __forceinline__ void dec_unpack(const DecItem& it, const DecRes& rs, 
     const uint32_t hw = B - b, real = min(kFrame, rs.N - j * kFrame);
     R* row = L.rows + g * RowT<R>::kElems;
     const uint32_t i0 = 32u * q;
+    // the lane's first kExPre exceptions (e = q, q + 4, ...) are requested
+    // with the payload
+    constexpr uint32_t kPre = kExPre;
+    const JG uint8_t* pos = (const JG uint8_t*)words + pos_b;
+    uint32_t ep[kExPre], eq[kExPre], eh[kExPre];
+#pragma unroll
+    for (uint32_t i = 0; i < kPre; ++i) {
+        const uint32_t e = q + 4 * i;
+        ep[i] = eq[i] = eh[i] = 0;
+        if (e < n) {
+            ep[i] = pos[e];
+            eq[i] = e ? pos[e - 1] : 0u;
+            eh[i] = bits_at<true>(words, high_bit + e * hw, hw);
+        }
+    }
     uint32_t z[32];
     unpack_lane(words + pay_w + q * b, b, z);  // lane q's values fill words q*b .. q*b + b - 1 of the frame
     row_put<R>(row, q, z);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     if (n) {
-        const JG uint8_t* pos = (const JG uint8_t*)words + pos_b;
+        // OR each high part in without waiting for the element (positions
+        // increase strictly, so no two lanes touch one element; a 16-bit
+        // element is ORed into its 32-bit word, the other half unchanged)
         uint32_t bad = 0;
-        for (uint32_t e = q; e < n; e += 4) {
-            const uint32_t p = pos[e];
-            if (p >= real || (e && pos[e - 1] >= p)) { bad = 1; continue; }
-            // OR the high part in without waiting for the element (positions
-            // increase strictly, so no two lanes touch one element; a 16-bit
-            // element is ORed into its 32-bit word, the other half unchanged)
-            const uint32_t x = bits_at<true>(words, high_bit + e * hw, hw) << b, idx = roff<R>(p);
+        auto patch = [&](uint32_t e, uint32_t p, uint32_t p_before, uint32_t high) {
+            if (p >= real || (e && p_before >= p)) {
+                bad = 1;
+                return;
+            }
+            const uint32_t x = high << b, idx = roff<R>(p);
             if (sizeof(R) == 4)
                 __hip_atomic_fetch_or((uint32_t*)row + idx, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             else
                 __hip_atomic_fetch_or((uint32_t*)row + (idx >> 1), x << (16 * (idx & 1)), __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
-        }
+        };
+#pragma unroll
+        for (uint32_t i = 0; i < kPre; ++i)
+            if (q + 4 * i < n) patch(q + 4 * i, ep[i], eq[i], eh[i]);
+        for (uint32_t e = q + 4 * kPre; e < n; e += 4)  // (e - 1 only for e > 0: it would wrap)
+            patch(e, pos[e], e ? pos[e - 1] : 0u, bits_at<true>(words, high_bit + e * hw, hw));
         if (bad) atomicOr(&L.bad, 1u);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
