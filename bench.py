@@ -493,9 +493,11 @@ def serving_leg(host, duration_s, speed_loaded=8.0):
     attributes at 1 mm; 10 or 20 Hz each with random phase and Poisson
     jitter), served in real time by continuous batching over two step
     contexts: under 8 GiB at the sensors' rate, under 8 GiB with arrivals
-    `speed_loaded` times faster (the server saturated), and under 64 MiB
-    with sensors connecting for 1-3 s sessions (admission binds, idle
-    streams' memory is reused).  host[s]: stream s's distinct synthetic
+    `speed_loaded` times faster (the server saturated), under 8 GiB with
+    every arrival released at once (a burst: full steps back to back, the
+    two contexts' steps overlapping on the device), and under 64 MiB with
+    sensors connecting for 1-3 s sessions (admission binds, idle streams'
+    memory is reused).  host[s]: stream s's distinct synthetic
     scans, cycled.  Stream 0's records from the first run are compared with
     its sequence encoded alone by jiffy_encode."""
     import torch
@@ -514,7 +516,7 @@ def serving_leg(host, duration_s, speed_loaded=8.0):
                        f"3 x u16 at 1 mm), 10/20 Hz with Poisson(2 ms) jitter, {duration_s} s of arrivals, each "
                        f"stream cycling {ncyc} synthetic scans; real-time serving on two step contexts"}
     runs = [("nominal_8192MiB", 8 << 30, 1.0, None), ("loaded_x%g_8192MiB" % speed_loaded, 8 << 30, speed_loaded, None),
-            ("sessions_64MiB", 64 << 20, 1.0, (1.0, 3.0))]
+            ("burst_8192MiB", 8 << 30, 1e6, None), ("sessions_64MiB", 64 << 20, 1.0, (1.0, 3.0))]
     for name, budget, speed, sess in runs:
         arrivals = synth.serving_arrivals(len(host), duration_s, session_s=sess)
         keep = {arrivals[0][1]} if name.startswith("nominal") else False
