@@ -48,18 +48,20 @@ constexpr uint16_t kXBad = 0xFFFEu;                // no valid block header here
 constexpr uint16_t kXLast = 0xFFFDu;               // the last block; it ends the frame exactly
 static_assert(kWin <= 0xFFF0u && kSegs == 256, "window offsets fit 16 bits; one segment per thread");
 static_assert(kWin == kParseWin, "the host sizes the parse grid with the same window");
+static_assert(kChunk % kSeg == 0 && kWinChunks <= kSegs, "a chunk is whole segments; a lane per chunk");
 
 __device__ __forceinline__ uint32_t sx(uint32_t i) { return i + ((i >> 5) << 1); }
 
 struct ParseLds {
     union {
-        struct {  // indexed through sx(): one pad entry pair per 32 positions keeps segments in distinct banks
-            uint16_t X[kWin + kWin / 16];  // per position: the first chain position at or after its segment's end
-            uint16_t Y[kWin + kWin / 16];  // per position: the first chain position at or after its chunk's end
-        } x;
+        // per position, indexed through sx() (one pad entry pair per 32
+        // positions keeps segments in distinct banks): first the chain
+        // position at or after its segment's end, after the jumping rounds
+        // the one at or after its chunk's end
+        uint16_t Y[kWin + kWin / 16];
         struct {  // a block takes 3 bytes at least
             uint32_t dst[kWin / 3 + 2];  // block k: content offset of its first byte (and the end)
-            uint32_t src[kWin / 3 + 1];  // block k: frame offset of its content | RLE << 31
+            uint16_t src[kWin / 3 + 1];  // block k: window offset of its content | RLE << 15
         } t;
     } u;
     uint32_t fwin[kWin / 4 + 2];  // the window's frame bytes (and the two after it)
@@ -242,31 +244,29 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
                 else if (last) n = n == flen ? kJLast : kJInvalid;
                 else if (n >= flen) n = kJInvalid;
                 const uint16_t c = code(n);
-                const uint16_t x = (c >= kXLast || n >= s1) ? c : P.u.x.X[sx(n - ws)];
-                P.u.x.X[sx(i - ws)] = x;
-                P.u.x.Y[sx(i - ws)] = x;
+                P.u.Y[sx(i - ws)] = (c >= kXLast || n >= s1) ? c : P.u.Y[sx(n - ws)];
             }
         }
     }
     __syncthreads();
-    // each step spans a segment at least, so three doublings reach the chunk's end;
-    // a thread reads all its 32 positions' next steps before it writes (positions
-    // updated by others in between are still on the same path)
-    for (int round = 0; round < 3; ++round) {
+    // each step spans a segment at least, so log2(kChunk / kSeg) doublings reach
+    // the chunk's end; a thread reads all its 32 positions' next steps before it
+    // writes (positions updated by others in between are still on the same path)
+    for (uint32_t span = kSeg; span < kChunk; span *= 2) {
         uint32_t y[kWin / 256];
 #pragma unroll
         for (int k = 0; k < (int)(kWin / 256); ++k) {
             const uint32_t i = tid + 256u * k;
-            y[k] = ws + i < we ? P.u.x.Y[sx(i)] : kXBad;
+            y[k] = ws + i < we ? P.u.Y[sx(i)] : kXBad;
         }
 #pragma unroll
         for (int k = 0; k < (int)(kWin / 256); ++k) {
             const uint32_t i = tid + 256u * k;
-            y[k] = (y[k] < kXLast && y[k] / kChunk == i / kChunk) ? P.u.x.Y[sx(y[k])] : 0x10000u;
+            y[k] = (y[k] < kXLast && y[k] / kChunk == i / kChunk) ? P.u.Y[sx(y[k])] : 0x10000u;
         }
 #pragma unroll
         for (int k = 0; k < (int)(kWin / 256); ++k)
-            if (y[k] != 0x10000u) P.u.x.Y[sx(tid + 256u * k)] = (uint16_t)y[k];
+            if (y[k] != 0x10000u) P.u.Y[sx(tid + 256u * k)] = (uint16_t)y[k];
         __syncthreads();
     }
     // where the chain enters this window, and the content before it
@@ -302,14 +302,21 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
         uint32_t e = entry - ws;
         while (e < kXLast) {
             P.c_entry[e / kChunk] = (uint16_t)e;
-            e = P.u.x.Y[sx(e)];
+            e = P.u.Y[sx(e)];
         }
     }
     __syncthreads();
-    if (tid < kWinChunks) {
+    if (tid < kWinChunks) {  // block by block through the chunk, noting each segment's first
+        uint32_t seg = kSegs;
         for (uint32_t e = P.c_entry[tid]; e < kXLast && e / kChunk == tid;) {
-            P.seg_entry[e / kSeg] = (uint16_t)e;
-            e = P.u.x.X[sx(e)];
+            if (e / kSeg != seg) {
+                seg = e / kSeg;
+                P.seg_entry[seg] = (uint16_t)e;
+            }
+            uint32_t size, rle;
+            const uint32_t n = header(ws + e, size, rle);
+            if (n >= we) break;  // leaves the window, ends the frame, or is no block
+            e = n - ws;
         }
     }
     __syncthreads();
@@ -343,7 +350,7 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
             uint32_t size, rle;
             const uint32_t n = header(ws + e, size, rle);
             P.u.t.dst[k] = d;
-            P.u.t.src[k] = (ws + e + 3) | (rle << 31);
+            P.u.t.src[k] = (uint16_t)((e + 3) | (rle << 15));
             k++;
             d += size;
             if (n >= we) break;
@@ -366,11 +373,13 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
     }
     __syncthreads();
     if (P.s_err) return;
-    // expansion: each thread writes a contiguous run of content words,
-    // finding its first block by binary search and walking on from there
+    // expansion: each thread writes a contiguous run of 16-byte groups of
+    // content, finding its first block by binary search and walking on from
+    // there; a word inside one block is one LDS word pair (raw) or the
+    // repeated byte (RLE), a word across blocks is built byte by byte
     const uint32_t d0 = content, d1 = content + ctot;
-    const uint32_t q0 = d0 & ~3u, nw = (d1 - q0 + 3) / 4, per = (nw + 255) / 256;
-    const uint32_t qa = q0 + 4 * per * tid, qb = min(q0 + 4 * per * (tid + 1), d1);
+    const uint32_t q0 = d0 & ~15u, ng = (d1 - q0 + 15) / 16, per = (ng + 255) / 256;
+    const uint32_t qa = q0 + 16 * per * tid, qb = min(qa + 16 * per, d1);
     if (qa < qb) {
         const uint32_t first = qa < d0 ? d0 : qa;
         uint32_t lo = 0, hi = nblk - 1;  // the largest k with dst[k] <= first
@@ -378,30 +387,50 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
             const uint32_t mid = (lo + hi + 1) >> 1;
             if (P.u.t.dst[mid] <= first) lo = mid; else hi = mid - 1;
         }
-        // the current block: content [bstart, bend), frame source, RLE byte
-        uint32_t k = lo, bstart = P.u.t.dst[k], bend = P.u.t.dst[k + 1], bsrc = P.u.t.src[k];
+        // the current block: content [bstart, bend), frame source | RLE << 31, RLE byte
+        auto src_of = [&](uint32_t k) -> uint32_t {
+            const uint32_t sv = P.u.t.src[k];
+            return (ws + (sv & 0x7FFFu)) | ((sv >> 15) << 31);
+        };
         auto byte_at = [&](uint32_t sb) -> uint32_t { return sb - wbase < wlen ? fb[sb - wbase] : f[sb]; };
+        uint32_t k = lo, bstart = P.u.t.dst[k], bend = P.u.t.dst[k + 1], bsrc = src_of(k);
         uint32_t rv = byte_at(bsrc & 0x7FFFFFFFu);
-        for (uint32_t q = qa; q < qb; q += 4) {
-            uint32_t word = 0, full = 1;
+        auto next_block = [&]() {
+            ++k;
+            bstart = bend;
+            bend = P.u.t.dst[k + 1];
+            bsrc = src_of(k);
+            rv = byte_at(bsrc & 0x7FFFFFFFu);
+        };
+        for (uint32_t q = qa; q < qb; q += 16) {
+            uint32_t wd[4];
 #pragma unroll
-            for (uint32_t b = 0; b < 4; ++b) {
-                const uint32_t d = q + b;
-                if (d < d0 || d >= d1) { full = 0; continue; }
-                while (d >= bend) {  // the next block
-                    ++k;
-                    bstart = bend;
-                    bend = P.u.t.dst[k + 1];
-                    bsrc = P.u.t.src[k];
-                    rv = byte_at(bsrc & 0x7FFFFFFFu);
+            for (uint32_t g = 0; g < 4; ++g) {
+                const uint32_t qw = q + 4 * g;
+                if (qw < d1)
+                    while (qw >= bend) next_block();
+                // the word's source in the staged window (raw blocks)
+                const uint32_t so = (bsrc & 0x7FFFFFFFu) + (qw - bstart) - wbase;
+                uint32_t word = 0;
+                if (qw >= bstart && qw + 4 <= bend && ((bsrc >> 31) || so + 4 <= wlen)) {
+                    word = (bsrc >> 31) ? rv * 0x01010101u
+                                        : __builtin_amdgcn_alignbyte(P.fwin[(so >> 2) + 1], P.fwin[so >> 2], so & 3);
+                } else {
+#pragma unroll
+                    for (uint32_t b = 0; b < 4; ++b) {
+                        const uint32_t d = qw + b;
+                        if (d < d0 || d >= d1) continue;
+                        while (d >= bend) next_block();
+                        const uint32_t v = (bsrc >> 31) ? rv : byte_at((bsrc & 0x7FFFFFFFu) + (d - bstart));
+                        word |= v << (8 * b);
+                    }
                 }
-                const uint32_t v = (bsrc >> 31) ? rv : byte_at((bsrc & 0x7FFFFFFFu) + (d - bstart));
-                word |= v << (8 * b);
+                wd[g] = word;
             }
-            if (full) *(uint32_t*)(cwb + q) = word;
+            if (q >= d0 && q + 16 <= d1) *(uint4*)(cwb + q) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
             else
-                for (uint32_t b = 0; b < 4; ++b)
-                    if (q + b >= d0 && q + b < d1) cwb[q + b] = (uint8_t)(word >> (8 * b));
+                for (uint32_t b = 0; b < 16; ++b)
+                    if (q + b >= d0 && q + b < d1) cwb[q + b] = (uint8_t)(wd[b >> 2] >> (8 * (b & 3)));
         }
     }
 }
