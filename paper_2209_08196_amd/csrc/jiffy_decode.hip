@@ -26,8 +26,8 @@ namespace jiffy {
 constexpr uint32_t kWin = 8192;             // frame positions per parsing window
 constexpr uint32_t kChunk = 256;            // bytes per chunk of the chain stitching
 constexpr uint32_t kWinChunks = kWin / kChunk;
-constexpr uint32_t kJInvalid = 0xFFFFFFFFu; // no valid block chain continues here
-constexpr uint32_t kJLast = 0xFFFFFFFEu;    // a last block that ends the frame exactly
+constexpr uint32_t kJInvalid = 0xFFFFFFFEu; // no valid block chain continues here
+constexpr uint32_t kJLast = 0xFFFFFFFDu;    // a last block that ends the frame exactly
 constexpr uint32_t kSpinMax = 1u << 16;     // polls of a workgroup waiting on another before giving up
 
 __device__ __forceinline__ uint32_t rd32(const uint8_t* p) {
@@ -46,11 +46,28 @@ constexpr uint32_t kSegs = kWin / kSeg;            // 256: one per thread
 constexpr uint16_t kXOut = 0xFFFFu;                // the chain leaves the window (a valid position)
 constexpr uint16_t kXBad = 0xFFFEu;                // no valid block header here
 constexpr uint16_t kXLast = 0xFFFDu;               // the last block; it ends the frame exactly
+static_assert((kJInvalid & 0xFFFFu) == kXBad && (kJLast & 0xFFFFu) == kXLast && kJLast < kJInvalid,
+              "a step's mark keeps its low half as the window mark");
 static_assert(kWin <= 0xFFF0u && kSegs == 256, "window offsets fit 16 bits; one segment per thread");
 static_assert(kWin == kParseWin, "the host sizes the parse grid with the same window");
-static_assert(kChunk % kSeg == 0 && kWinChunks <= kSegs, "a chunk is whole segments; a lane per chunk");
+static_assert(kChunk % kSeg == 0 && kWinChunks <= kSegs && (kChunk & (kChunk - 1)) == 0,
+              "a chunk is a power of two of whole segments; a lane per chunk");
 
 __device__ __forceinline__ uint32_t sx(uint32_t i) { return i + ((i >> 5) << 1); }
+
+// The step a block header h (its three bytes, little-endian) at frame offset
+// i takes: the next header's offset; kJLast for a last block that ends the
+// frame exactly; kJInvalid for no block (type 2 or 3, a size above the
+// format's maximum, no room for the header, or a block that runs past the
+// frame or, being last, stops short of its end).  Type 1 (RLE) takes one
+// content byte.  No branches: every byte of a window is tried.
+constexpr uint32_t kHdrLim = (kZstdBlockMax + 1) << 3;  // headers with a size in range lie below
+__device__ __forceinline__ uint32_t block_next(uint32_t h, uint32_t i, uint32_t flen) {
+    const uint32_t last = h & 1u;
+    const uint32_t n = i + 3 + ((h & 2u) ? 1u : (h >> 3));
+    const bool ok = ((h & 4u) == 0) & (h < kHdrLim) & (i + 3 <= flen) & (last ? n == flen : n < flen);
+    return !ok ? kJInvalid : last ? kJLast : n;
+}
 
 struct ParseLds {
     union {
@@ -203,22 +220,13 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
         wbase = r0 - 12;
         wlen = r1 - r0;
     }
+    // a header at frame offset i (ws <= i < we: its bytes are staged)
     auto header = [&](uint32_t i, uint32_t& size, uint32_t& rle) -> uint32_t {
-        if (i + 3 > flen) return kJInvalid;
         const uint8_t* hp = fb + (i - wbase);
         const uint32_t h = (uint32_t)hp[0] | ((uint32_t)hp[1] << 8) | ((uint32_t)hp[2] << 16);
-        const uint32_t last = h & 1, type = (h >> 1) & 3;
         size = h >> 3;
-        rle = type;
-        if (type > 1 || size > kZstdBlockMax) return kJInvalid;
-        const uint32_t n = i + 3 + (type ? 1u : size);
-        if (last) return n == flen ? kJLast : kJInvalid;
-        return n < flen ? n : kJInvalid;
-    };
-    auto code = [&](uint32_t n) -> uint16_t {  // a next position as a window offset or a mark
-        if (n == kJInvalid) return kXBad;
-        if (n == kJLast) return kXLast;
-        return n >= we ? kXOut : (uint16_t)(n - ws);
+        rle = (h >> 1) & 1u;
+        return block_next(h, i, flen);
     };
     __syncthreads();
     const uint32_t s0 = ws + tid * kSeg, s1 = min(s0 + kSeg, we);
@@ -230,43 +238,51 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
         for (int k = 0; k < 10; ++k) w[k] = P.fwin[8 * tid + k];
 #pragma unroll
         for (int k = 0; k < 9; ++k) u[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], a);
-        // backwards over the segment: where a chain through each position leaves it
+        // backwards over the segment: where a chain through each position
+        // leaves it.  Without branches: every position reads one entry (its
+        // own when the step leaves the segment or the header is no block) and
+        // writes its own; positions past the window's end get values nothing
+        // reads (a valid step from inside the window past its end is kXOut).
+        uint16_t* ys = P.u.Y + sx(tid * kSeg);  // the segment's entries (no pad inside a segment)
 #pragma unroll
         for (int j = kSeg - 1; j >= 0; --j) {
             const uint32_t i = s0 + j;
-            if (i < s1) {
-                // bytes j .. j+2 of the segment from two whole words (a 64-bit
-                // shift here makes the compiler keep u[] in memory)
-                const uint32_t h = __builtin_amdgcn_alignbyte(u[(j >> 2) + 1], u[j >> 2], j & 3) & 0xFFFFFFu;
-                const uint32_t last = h & 1, type = (h >> 1) & 3, size = h >> 3;
-                uint32_t n = i + 3 + (type ? 1u : size);
-                if (i + 3 > flen || type > 1 || size > kZstdBlockMax) n = kJInvalid;
-                else if (last) n = n == flen ? kJLast : kJInvalid;
-                else if (n >= flen) n = kJInvalid;
-                const uint16_t c = code(n);
-                P.u.Y[sx(i - ws)] = (c >= kXLast || n >= s1) ? c : P.u.Y[sx(n - ws)];
-            }
+            // bytes j .. j+2 of the segment from two whole words (a 64-bit
+            // shift here makes the compiler keep u[] in memory)
+            const uint32_t h = __builtin_amdgcn_alignbyte(u[(j >> 2) + 1], u[j >> 2], j & 3) & 0xFFFFFFu;
+            const uint32_t n = block_next(h, i, flen);
+            // the marks lie above every offset and keep their window mark in the low half
+            const uint32_t c = n < we ? n - ws : n >= kJLast ? n & 0xFFFFu : kXOut;
+            const bool in = n < s1;
+            const uint32_t v = ys[in ? n - s0 : (uint32_t)j];
+            ys[j] = (uint16_t)(in ? v : c);
         }
     }
     __syncthreads();
     // each step spans a segment at least, so log2(kChunk / kSeg) doublings reach
-    // the chunk's end; a thread reads all its 32 positions' next steps before it
-    // writes (positions updated by others in between are still on the same path)
+    // the chunk's end.  Entries only ever move forward along their chain and
+    // never past the chunk's exit, so reads and writes of one round may
+    // interleave freely; a thread takes its positions eight at a time, every
+    // one read and rewritten (unchanged when its step leaves the chunk).  A
+    // step stays in the chunk exactly when its offset agrees with the
+    // position's above the chunk bits (marks never do).
     for (uint32_t span = kSeg; span < kChunk; span *= 2) {
-        uint32_t y[kWin / 256];
+        constexpr int kPer = kWin / 256, kGrp = 8;
 #pragma unroll
-        for (int k = 0; k < (int)(kWin / 256); ++k) {
-            const uint32_t i = tid + 256u * k;
-            y[k] = ws + i < we ? P.u.Y[sx(i)] : kXBad;
+        for (int g = 0; g < kPer; g += kGrp) {
+            uint32_t y[kGrp];
+#pragma unroll
+            for (int k = 0; k < kGrp; ++k) y[k] = P.u.Y[sx(tid + 256u * (g + k))];
+#pragma unroll
+            for (int k = 0; k < kGrp; ++k) {
+                const uint32_t i = tid + 256u * (g + k);
+                const bool f = (y[k] ^ i) < kChunk;
+                const uint32_t z = P.u.Y[sx(f ? y[k] : i)];
+                y[k] = f ? z : y[k];
+            }
+#pragma unroll
+            for (int k = 0; k < kGrp; ++k) P.u.Y[sx(tid + 256u * (g + k))] = (uint16_t)y[k];
         }
-#pragma unroll
-        for (int k = 0; k < (int)(kWin / 256); ++k) {
-            const uint32_t i = tid + 256u * k;
-            y[k] = (y[k] < kXLast && y[k] / kChunk == i / kChunk) ? P.u.Y[sx(y[k])] : 0x10000u;
-        }
-#pragma unroll
-        for (int k = 0; k < (int)(kWin / 256); ++k)
-            if (y[k] != 0x10000u) P.u.Y[sx(tid + 256u * k)] = (uint16_t)y[k];
         __syncthreads();
     }
     // where the chain enters this window, and the content before it
@@ -406,24 +422,28 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
             uint32_t wd[4];
 #pragma unroll
             for (uint32_t g = 0; g < 4; ++g) {
-                const uint32_t qw = q + 4 * g;
-                if (qw < d1)
-                    while (qw >= bend) next_block();
-                // the word's source in the staged window (raw blocks)
-                const uint32_t so = (bsrc & 0x7FFFFFFFu) + (qw - bstart) - wbase;
+                // the word's bytes [lo, hi) of the content, one block's part per pass
+                const uint32_t qw = q + 4 * g, hi = min(qw + 4, d1);
                 uint32_t word = 0;
-                if (qw >= bstart && qw + 4 <= bend && ((bsrc >> 31) || so + 4 <= wlen)) {
-                    word = (bsrc >> 31) ? rv * 0x01010101u
-                                        : __builtin_amdgcn_alignbyte(P.fwin[(so >> 2) + 1], P.fwin[so >> 2], so & 3);
-                } else {
-#pragma unroll
-                    for (uint32_t b = 0; b < 4; ++b) {
-                        const uint32_t d = qw + b;
-                        if (d < d0 || d >= d1) continue;
-                        while (d >= bend) next_block();
-                        const uint32_t v = (bsrc >> 31) ? rv : byte_at((bsrc & 0x7FFFFFFFu) + (d - bstart));
-                        word |= v << (8 * b);
+                for (uint32_t d = max(qw, d0); d < hi;) {
+                    while (d >= bend) next_block();  // blocks without content are passed over
+                    const uint32_t e = min(hi, bend);
+                    uint32_t v;
+                    if (bsrc >> 31) v = rv * 0x01010101u;
+                    else {
+                        const uint32_t sb = (bsrc & 0x7FFFFFFFu) + (d - bstart);  // frame offset of byte d
+                        const uint32_t so = sb - wbase;
+                        if (so + 4 <= wlen)
+                            v = __builtin_amdgcn_alignbyte(P.fwin[(so >> 2) + 1], P.fwin[so >> 2], so & 3);
+                        else {  // past the staged bytes (a block running on beyond the window)
+                            v = 0;
+                            for (uint32_t b = 0; b < e - d; ++b) v |= byte_at(sb + b) << (8 * b);
+                        }
                     }
+                    const uint32_t nb = e - d;  // 1 .. 4 bytes, placed at byte d - qw of the word
+                    const uint32_t m = nb >= 4 ? 0xFFFFFFFFu : (1u << (8 * nb)) - 1;
+                    word |= (v & m) << (8 * (d - qw));
+                    d = e;
                 }
                 wd[g] = word;
             }
