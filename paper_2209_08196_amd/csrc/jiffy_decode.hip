@@ -24,7 +24,7 @@
 namespace jiffy {
 
 constexpr uint32_t kWin = 8192;             // frame positions per parsing window
-constexpr uint32_t kChunk = 256;            // bytes per chunk of the chain stitching
+constexpr uint32_t kChunk = 128;            // bytes per chunk of the chain stitching
 constexpr uint32_t kWinChunks = kWin / kChunk;
 constexpr uint32_t kJInvalid = 0xFFFFFFFEu; // no valid block chain continues here
 constexpr uint32_t kJLast = 0xFFFFFFFDu;    // a last block that ends the frame exactly
@@ -197,10 +197,11 @@ __device__ void parse_mask(const DecPlan& plan, uint32_t r, const DecItem& it, P
     // next.  Every thread owns a 32-byte segment of the window: walking it
     // backwards it finds, for each position, where a chain through that
     // position leaves the segment; a few rounds of pointer jumping turn that
-    // into where it leaves the 256-byte chunk.  One lane then follows the
-    // true chain from chunk to chunk, 32 lanes from segment to segment inside
-    // their chunk, and every lane walks its own segment to list the blocks;
-    // all lanes expand them.
+    // into where it leaves the chunk (kChunk bytes).  One lane then follows
+    // the true chain from chunk to chunk, a lane per chunk block by block
+    // through its chunk (noting where the chain enters each segment), and
+    // every lane walks its own segment to list the blocks; all lanes expand
+    // them.
     uint32_t wbase, wlen;
     {  // stage frame bytes [ws, we + 2) with word loads (the record is 4-byte aligned), all issued first
         const uint32_t r0 = (12 + ws) & ~3u, r1 = min(12 + we + 2, L);
