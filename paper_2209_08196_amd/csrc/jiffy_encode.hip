@@ -1047,7 +1047,13 @@ __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, co
         const uint32_t nvalid = nm > b0 ? min(32u, nm - b0) : 0u;
         uint32_t sg = sid ? sid - 1 : 0, sstart = 0, soff = 0;
         if (sid) { sstart = seg(sg) & 0x7FFFFFFFu; soff = segoff(sg); }
-        for (uint32_t k = 0; k < nvalid; ++k) {
+        // unrolled, so that each byte's place in the window is fixed (the
+        // words named one by one: an array indexed in the loop would go to
+        // scratch memory before the unrolling)
+        const uint64_t w0 = R.win[2], w1 = R.win[3], w2 = R.win[4], w3 = R.win[5];
+#pragma unroll
+        for (uint32_t k = 0; k < 32; ++k) {
+            if (k >= nvalid) break;
             if ((R.start >> k) & 1u) {
                 sg = sid++;
                 sstart = b0 + k;
@@ -1056,7 +1062,8 @@ __device__ __forceinline__ void mframe_write(const EncPlan& plan, uint32_t r, co
             if ((R.lng >> k) & 1u) continue;
             const uint32_t i = b0 + k;
             const uint32_t q = (i - sstart) / kZstdBlockMax;
-            f[soff + 3u * (q + 1u) + (i - sstart)] = (uint8_t)win_byte(R, k);
+            const uint64_t wk = k < 8 ? w0 : k < 16 ? w1 : k < 24 ? w2 : w3;
+            f[soff + 3u * (q + 1u) + (i - sstart)] = (uint8_t)(wk >> (8 * (k & 7)));
         }
         seg_carry += total;
     };
