@@ -748,20 +748,34 @@ __global__ __launch_bounds__(1024) void k_dec_scan(DecPlan plan) {
     for (uint32_t lt = threadIdx.x; lt < plan.nvt; lt += 1024) it.status[lt] = 0ull;
     if (threadIdx.x == 0) *it.tctr = 0u;
     uint32_t carry = 0, tiles = 0;  // valid samples and tiles before the block
-    for (uint32_t w0 = 0; w0 < it.nwords; w0 += 1024) {
-        const uint32_t w = w0 + threadIdx.x;
-        const uint64_t v = w < it.nwords ? it.vw[w] : 0ull;
-        const uint32_t c = (uint32_t)__popcll(v);
-        uint32_t total;
-        const uint32_t pre = block_excl_scan<1024>(c, scratch, &total) + carry;
-        const uint32_t k0 = carry / kDecTileVals;
-        if (threadIdx.x == 0) it.tstart[tiles] = make_uint2(64u * w0, carry);
-        if (c) {  // a rank boundary in this word: at most one, a word holds 64 values
-            const uint32_t k = (pre + c - 1) / kDecTileVals, R = k * kDecTileVals;
-            if (k > k0 && R >= pre) it.tstart[tiles + (k - k0)] = make_uint2(64u * w + select_bit(v, R - pre), R);
+    // the words of kScanAhead blocks are requested together, then the blocks
+    // are counted one after another
+    constexpr uint32_t kScanAhead = 8;
+    for (uint32_t wa = 0; wa < it.nwords; wa += 1024 * kScanAhead) {
+        uint64_t vv[kScanAhead];
+#pragma unroll
+        for (uint32_t u = 0; u < kScanAhead; ++u) {
+            const uint32_t w = wa + 1024 * u + threadIdx.x;
+            vv[u] = w < it.nwords ? it.vw[w] : 0ull;
         }
-        tiles += 1 + (total ? (carry + total - 1) / kDecTileVals - k0 : 0u);
-        carry += total;
+#pragma unroll
+        for (uint32_t u = 0; u < kScanAhead; ++u) {
+            const uint32_t w0 = wa + 1024 * u;
+            if (w0 >= it.nwords) break;
+            const uint32_t w = w0 + threadIdx.x;
+            const uint64_t v = vv[u];
+            const uint32_t c = (uint32_t)__popcll(v);
+            uint32_t total;
+            const uint32_t pre = block_excl_scan<1024>(c, scratch, &total) + carry;
+            const uint32_t k0 = carry / kDecTileVals;
+            if (threadIdx.x == 0) it.tstart[tiles] = make_uint2(64u * w0, carry);
+            if (c) {  // a rank boundary in this word: at most one, a word holds 64 values
+                const uint32_t k = (pre + c - 1) / kDecTileVals, R = k * kDecTileVals;
+                if (k > k0 && R >= pre) it.tstart[tiles + (k - k0)] = make_uint2(64u * w + select_bit(v, R - pre), R);
+            }
+            tiles += 1 + (total ? (carry + total - 1) / kDecTileVals - k0 : 0u);
+            carry += total;
+        }
     }
     if (threadIdx.x == 0) {
         it.tstart[tiles] = make_uint2(it.npx, carry);
