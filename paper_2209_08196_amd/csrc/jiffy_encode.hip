@@ -1148,24 +1148,36 @@ __device__ __forceinline__ void enc_sizes_item(const EncPlan& plan, uint32_t r, 
     const EncItem& it = plan.items[r];
     const uint32_t nb = min(plan.res[r].nb, it.maxnb);  // (never more; kept in bounds whatever a stall left)
     uint32_t cp = 0, cn = 0, ch = 0;
-    for (uint32_t j0 = 0; j0 < nb; j0 += NT) {
-        const uint32_t j = j0 + threadIdx.x;
-        uint32_t v[3] = {0u, 0u, 0u};  // payload, position and high part bytes of frame j
-        if (j < nb) {
-            const uint32_t info = it.blkinfo[j];
-            const uint32_t b = info & 0xFF, n = (info >> 8) & 0xFF, B = (info >> 16) & 0xFF;
-            v[0] = 16 * b;
-            v[1] = n;
-            v[2] = (n * (B - b) + 7) / 8;
+    // the widths of kAhead passes are requested together, then scanned pass by pass
+    constexpr uint32_t kAhead = 4;
+    for (uint32_t ja = 0; ja < nb; ja += NT * kAhead) {
+        uint32_t infos[kAhead];
+#pragma unroll
+        for (uint32_t u = 0; u < kAhead; ++u) {
+            const uint32_t j = ja + NT * u + threadIdx.x;
+            infos[u] = j < nb ? it.blkinfo[j] : 0u;
         }
-        uint32_t tot[3];
-        block_excl_scan3<NT>(v, scratch, tot);
-        if (j < nb) {
-            it.blkoffs[3 * j] = cp + v[0];
-            it.blkoffs[3 * j + 1] = cn + v[1];
-            it.blkoffs[3 * j + 2] = ch + v[2];
+#pragma unroll
+        for (uint32_t u = 0; u < kAhead; ++u) {
+            if (ja + NT * u >= nb) break;
+            const uint32_t j = ja + NT * u + threadIdx.x;
+            uint32_t v[3] = {0u, 0u, 0u};  // payload, position and high part bytes of frame j
+            if (j < nb) {
+                const uint32_t info = infos[u];
+                const uint32_t b = info & 0xFF, n = (info >> 8) & 0xFF, B = (info >> 16) & 0xFF;
+                v[0] = 16 * b;
+                v[1] = n;
+                v[2] = (n * (B - b) + 7) / 8;
+            }
+            uint32_t tot[3];
+            block_excl_scan3<NT>(v, scratch, tot);
+            if (j < nb) {
+                it.blkoffs[3 * j] = cp + v[0];
+                it.blkoffs[3 * j + 1] = cn + v[1];
+                it.blkoffs[3 * j + 2] = ch + v[2];
+            }
+            cp += tot[0]; cn += tot[1]; ch += tot[2];
         }
-        cp += tot[0]; cn += tot[1]; ch += tot[2];
     }
     if (threadIdx.x == 0) {
         EncRes& rs = plan.res[r];
@@ -1186,14 +1198,25 @@ __global__ __launch_bounds__(kSizeThreads) void k_enc_sizes(EncPlan plan) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_enc_offsets(EncPlan plan) {
     __shared__ uint64_t scratch[20];
+    // record lengths of kAhead rounds are requested together, then scanned round by round
+    constexpr uint32_t kAhead = 8;
     uint64_t carry = 0;
-    for (uint32_t r0 = 0; r0 < plan.n_items; r0 += 1024) {
-        const uint32_t r = r0 + threadIdx.x;
-        const uint64_t len = r < plan.n_items ? plan.res[r].rec_len : 0;
-        uint64_t total;
-        const uint64_t pre = block_excl_scan64<1024>(len, scratch, &total) + carry;
-        if (r < plan.n_items) plan.res[r].rec_off = pre;
-        carry += total;
+    for (uint32_t ra = 0; ra < plan.n_items; ra += 1024 * kAhead) {
+        uint32_t lens[kAhead];
+#pragma unroll
+        for (uint32_t u = 0; u < kAhead; ++u) {
+            const uint32_t r = ra + 1024 * u + threadIdx.x;
+            lens[u] = r < plan.n_items ? plan.res[r].rec_len : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kAhead; ++u) {
+            if (ra + 1024 * u >= plan.n_items) break;
+            const uint32_t r = ra + 1024 * u + threadIdx.x;
+            uint64_t total;
+            const uint64_t pre = block_excl_scan64<1024>((uint64_t)lens[u], scratch, &total) + carry;
+            if (r < plan.n_items) plan.res[r].rec_off = pre;
+            carry += total;
+        }
     }
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < plan.n_outs; k += 1024) {
@@ -1216,13 +1239,29 @@ __global__ __launch_bounds__(1024) void k_enc_offsets(EncPlan plan) {
         }
     }
     __syncthreads();
-    for (uint32_t r = threadIdx.x; r < plan.n_items; r += 1024) {
-        const EncOut& o = plan.outs[plan.items[r].out_id];
-        plan.res[r].rec_off = plan.res[r].rec_off - o.gbase + o.hdr_len;
-        if (plan.host_res) {  // the record's mode, and after the error word its length
-            JG uint32_t* h = (JG uint32_t*)(plan.host_res + 16ull * plan.n_outs);
-            store_system(h + r, plan.res[r].mode);
-            store_system(h + plan.n_items + 1 + r, plan.res[r].rec_len);
+    // every record rebased to its output (the reads of kAhead rounds requested together)
+    for (uint32_t ra = 0; ra < plan.n_items; ra += 1024 * kAhead) {
+        uint32_t oid[kAhead], md[kAhead], ln[kAhead];
+        uint64_t off[kAhead];
+#pragma unroll
+        for (uint32_t u = 0; u < kAhead; ++u) {
+            const uint32_t r = min(ra + 1024 * u + threadIdx.x, plan.n_items - 1);  // past the end: the last (unused)
+            oid[u] = plan.items[r].out_id;
+            off[u] = plan.res[r].rec_off;
+            md[u] = plan.res[r].mode;
+            ln[u] = plan.res[r].rec_len;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kAhead; ++u) {
+            const uint32_t r = ra + 1024 * u + threadIdx.x;
+            if (r >= plan.n_items) break;
+            const EncOut& o = plan.outs[oid[u]];
+            plan.res[r].rec_off = off[u] - o.gbase + o.hdr_len;
+            if (plan.host_res) {  // the record's mode, and after the error word its length
+                JG uint32_t* h = (JG uint32_t*)(plan.host_res + 16ull * plan.n_outs);
+                store_system(h + r, md[u]);
+                store_system(h + plan.n_items + 1 + r, ln[u]);
+            }
         }
     }
     if (plan.host_res && threadIdx.x == 0)
