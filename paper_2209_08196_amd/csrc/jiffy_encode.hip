@@ -944,7 +944,7 @@ __device__ __forceinline__ uint32_t win_byte(const RunBits& R, uint32_t k) {
 }
 
 constexpr uint32_t kMfThreads = 512;   // the mask-frame kernel: one workgroup per record covers 16 KiB per round
-constexpr uint32_t kMfKeep = 2;        // rounds whose classification stays in registers between passes
+constexpr uint32_t kMfKeep = 4;        // rounds whose classification stays in registers between passes
 constexpr uint32_t kMfSegLds = 6144;   // segments its LDS table holds (more: the workspace table)
 
 template <int NT, int SEGS>
@@ -1091,12 +1091,14 @@ __device__ __forceinline__ void enc_mframe_item(const EncPlan& plan, uint32_t r,
     const uint32_t tid = threadIdx.x;
     RunBits Rk[kMfKeep];
     uint32_t nseg = 0;
+    // the kept rounds classified first (no barrier between them, so their
+    // loads are in flight together), then their segment starts numbered
 #pragma unroll
     for (uint32_t c = 0; c < kMfKeep; ++c)
-        if (c * kStep < nm) {
-            classify32(it, mode, nm, c * kStep + 32 * tid, Rk[c]);
-            mframe_starts(it, Rk[c], c * kStep + 32 * tid, false, M, nseg);
-        }
+        if (c * kStep < nm) classify32(it, mode, nm, c * kStep + 32 * tid, Rk[c]);
+#pragma unroll
+    for (uint32_t c = 0; c < kMfKeep; ++c)
+        if (c * kStep < nm) mframe_starts(it, Rk[c], c * kStep + 32 * tid, false, M, nseg);
     for (uint32_t c0 = kMfKeep * kStep; c0 < nm; c0 += kStep) {
         RunBits R;
         classify32(it, mode, nm, c0 + 32 * tid, R);
