@@ -1426,7 +1426,10 @@ __device__ __forceinline__ void enc_assemble_item(const EncPlan& plan, uint32_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_enc_assemble(EncPlan plan) { enc_assemble_item(plan, blockIdx.y, blockIdx.x); }
+// Held to six waves per SIMD (80 registers instead of 86, nothing spilled):
+// its workgroups are short chains of loads and stores, so more of them in
+// flight pay (3% less time; at eight waves the spills cost 56% more).
+__global__ __launch_bounds__(256, 6) void k_enc_assemble(EncPlan plan) { enc_assemble_item(plan, blockIdx.y, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // Plan upload: 16 bytes per thread from host-mapped memory.
